@@ -1,0 +1,105 @@
+"""Seeded synthetic workloads for the mapped structured multigrid solve.
+
+Shared by the HIP library's tests/benchmarks and by the oracle: this package produces plain
+input data only (map Jacobians at quadrature points, per-cell coefficients, right-hand sides,
+targets, meshes) and contains none of the solver's arithmetic.
+
+Workloads (every random draw comes from numpy.random.SeedSequence(root).spawn(...)):
+  quarter_annulus(n, seed)   : n x n grid, K = 1, b ~ U(-1,1)         (root 0)
+  star(n, seed)              : star domain, log-normal K, b ~ U(-1,1)  (roots 1, 2, 4)
+  batch(count, sizes, seed)  : independent star instances of mixed sizes (root 3)
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .fields import (GAUSS_OFFSETS, grid_coords, lognormal_K, sample_jacobian, smooth_target,
+                     uniform_rhs)
+from .maps import Affine, Identity, QuarterAnnulus, Star, conformal_square_to_disk
+from .mesh import Mesh, lattice_mesh, mesh_points_for_grid
+
+__all__ = ["Problem", "quarter_annulus", "star", "identity", "batch", "Affine", "Identity",
+           "QuarterAnnulus", "Star", "conformal_square_to_disk", "sample_jacobian", "lognormal_K",
+           "uniform_rhs", "smooth_target", "grid_coords", "GAUSS_OFFSETS", "Mesh", "lattice_mesh",
+           "mesh_points_for_grid", "streams"]
+
+
+@dataclass
+class Problem:
+    name: str
+    nx: int
+    ny: int
+    map: object
+    jac: np.ndarray          # [16][ny-1][nx-1]
+    K: np.ndarray            # [ny-1][nx-1]
+    b: np.ndarray            # [ny][nx], zero boundary ring
+    target: np.ndarray = None
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def dof(self) -> int:
+        return (self.nx - 2) * (self.ny - 2)
+
+
+def streams(root: int, n: int = 5):
+    """Independent generators for (map, K, rhs, target, directions, ...)."""
+    return [np.random.Generator(np.random.PCG64(s)) for s in np.random.SeedSequence(root).spawn(n)]
+
+
+def quarter_annulus(n: int, seed: int = 0, ny: int | None = None) -> Problem:
+    ny = ny or n
+    g_map, g_k, g_b, g_t, _ = streams(seed)
+    mp = QuarterAnnulus()
+    return Problem("quarter_annulus", n, ny, mp, sample_jacobian(mp, n, ny),
+                   np.ones((ny - 1, n - 1)), uniform_rhs(n, ny, g_b), smooth_target(n, ny, g_t))
+
+
+def identity(n: int, seed: int = 0, K: np.ndarray | None = None, ny: int | None = None) -> Problem:
+    ny = ny or n
+    _, _, g_b, g_t, _ = streams(seed)
+    mp = Identity()
+    K = np.ones((ny - 1, n - 1)) if K is None else K
+    return Problem("identity", n, ny, mp, sample_jacobian(mp, n, ny), K, uniform_rhs(n, ny, g_b),
+                   smooth_target(n, ny, g_t))
+
+
+def star(n: int, seed: int = 1, ny: int | None = None, lognormal: bool = True,
+         device: str | None = None) -> Problem:
+    ny = ny or n
+    g_map, g_k, g_b, g_t, _ = streams(seed)
+    mp = Star.random(g_map)
+    K = lognormal_K(mp, n, ny, g_k, device=device) if lognormal else np.ones((ny - 1, n - 1))
+    return Problem("star", n, ny, mp, sample_jacobian(mp, n, ny), K, uniform_rhs(n, ny, g_b),
+                   smooth_target(n, ny, g_t))
+
+
+def directions(seed: int, count: int, n_cells: tuple, n_vert: tuple):
+    """Finite-difference directions: z_K ~ N(0,1) per cell, z_b ~ N(0,1) per interior vertex."""
+    g = streams(seed)[4]
+    zK = g.normal(size=(count,) + tuple(n_cells))
+    zb = g.normal(size=(count,) + tuple(n_vert))
+    zb[:, 0, :] = zb[:, -1, :] = 0.0
+    zb[:, :, 0] = zb[:, :, -1] = 0.0
+    return zK, zb
+
+
+def batch_sizes(count: int, choices=(129, 257, 513, 1025), seed: int = 3):
+    g = np.random.Generator(np.random.PCG64(np.random.SeedSequence(seed).spawn(count + 1)[-1]))
+    return [int(c) for c in g.choice(np.asarray(choices), size=count)]
+
+
+def batch(count: int, choices=(129, 257, 513, 1025), seed: int = 3, lognormal: bool = True,
+          device: str | None = None):
+    """``count`` independent star instances; instance k uses child seed k of the root."""
+    sizes = batch_sizes(count, choices, seed)
+    kids = np.random.SeedSequence(seed).spawn(count + 1)
+    out = []
+    for k, n in enumerate(sizes):
+        g_map, g_k, g_b, g_t, _ = [np.random.Generator(np.random.PCG64(s)) for s in kids[k].spawn(5)]
+        mp = Star.random(g_map)
+        K = lognormal_K(mp, n, n, g_k, device=device) if lognormal else np.ones((n - 1, n - 1))
+        out.append(Problem(f"star[{k}]", n, n, mp, sample_jacobian(mp, n, n), K,
+                           uniform_rhs(n, n, g_b), None))
+    return out
