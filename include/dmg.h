@@ -1,0 +1,188 @@
+/*
+ * dmg.h -- C ABI of the MI355X (gfx950) structured multigrid library for remapped elliptic
+ * problems.
+ *
+ * Method: Nytko, MacLachlan, Moulton, Olson, Reisner, West, "Unstructured to structured:
+ * geometric multigrid on complex geometries via domain remapping" (arXiv 2509.08109).
+ * A physical domain is pulled back through a diffeomorphism onto the logical square
+ * (-1,1)^2 (Sec. 2, eq. weak_computational); there -div(K grad u) becomes a 9-point Q1 stencil
+ * whose coefficients come from the map's metric det(J) J^{-1} J^{-T} (Sec. 2.1, effective
+ * tensor D_c).  The structured system is solved by black-box multigrid V-cycles (Sec. 2.2):
+ * factor-two coarsening, operator-induced interpolation, Galerkin coarse operators P^T A P.
+ * Vectors move between a P1 mesh and the grid with the L2 projection P = M_p^{-1} C and its
+ * transpose (Sec. 2.3).
+ *
+ * Conventions (all entry points):
+ *  - Every array pointer is a DEVICE pointer owned by the caller unless stated otherwise.
+ *    Arrays are dense, row-major, i (the xi index) fastest:
+ *      vertex arrays [ny][nx] (boundary ring included), cell arrays [ny-1][nx-1].
+ *  - Stencils use symmetric 5-value storage (Sec. 4.1, closing remark on storage):
+ *      S[0]=C (diagonal), S[1]=W (coupling to (i-1,j)), S[2]=S (to (i,j-1)),
+ *      S[3]=SW (to (i-1,j-1)), S[4]=SE (to (i+1,j-1)); each plane [ny][nx].
+ *    The E, N, NE, NW couplings of (i,j) are W(i+1,j), S(i,j+1), SW(i+1,j+1), SE(i-1,j+1).
+ *    Values are the matrix entries themselves (off-diagonals <= 0 for M-matrices).
+ *    Dirichlet rows and all couplings into the boundary ring are zero.
+ *  - Boundary entries of right-hand sides are ignored; boundary entries of solutions are
+ *    written as 0 (homogeneous Dirichlet; inhomogeneous data is lifted by the caller).
+ *  - Work is enqueued on the given hipStream_t (NULL = default stream) and is asynchronous,
+ *    except for functions that return host scalars (they synchronise that stream).
+ *  - Every function returns dmg_status; on failure dmg_last_error() (thread-local) holds a
+ *    message.  Argument validation happens on the host before anything is enqueued, so a
+ *    rejected call has no device side effects.  No C++ exception crosses this boundary.
+ *  - Grid dimensions must be 2^k + 1 (k >= 1) in each direction for the solver.
+ */
+#ifndef DMG_H
+#define DMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum dmg_status {
+  DMG_OK = 0,
+  DMG_ERR_INVALID_ARG = 1,    /* null pointer, negative size, bad option value          */
+  DMG_ERR_DIMS = 2,           /* grid dims not 2^k+1, or inconsistent sizes               */
+  DMG_ERR_WORKSPACE = 3,      /* workspace missing, misaligned (256 B) or too small        */
+  DMG_ERR_NOT_SPD = 4,        /* coarsest-level Cholesky met a non-positive pivot          */
+  DMG_ERR_NONFINITE = 5,      /* NaN/Inf in a residual norm                               */
+  DMG_ERR_NO_CONVERGENCE = 6, /* max_iters reached before the tolerance                   */
+  DMG_ERR_HIP = 7,            /* a HIP runtime call failed                                */
+  DMG_ERR_UNSUPPORTED = 8
+} dmg_status;
+
+enum { DMG_FP64 = 0, DMG_FP32_IR = 1 };
+
+/* Solver options.  Fill with dmg_default_options() and change what is needed. */
+typedef struct dmg_options {
+  int32_t nu_pre;        /* pre-smoothing sweeps per level (default 1)                    */
+  int32_t nu_post;       /* post-smoothing sweeps per level (default 1)                   */
+  int32_t pre_order[4];  /* colour order of a pre-smoothing sweep (default 0,1,2,3);
+                            colour(i,j) = (i mod 2) + 2 (j mod 2); must be a permutation   */
+  int32_t post_order[4]; /* colour order of a post sweep (default 3,2,1,0: the reverse,
+                            which keeps the V-cycle symmetric)                             */
+  int32_t coarsest_n;    /* stop coarsening when min(nx,ny) <= coarsest_n (default 3);
+                            the coarsest interior system is solved by dense Cholesky       */
+  int32_t precision;     /* DMG_FP64 (default) or DMG_FP32_IR                              */
+  int32_t inner_cycles;  /* FP32 V-cycles per refinement step for DMG_FP32_IR (default 1) */
+  int32_t use_graph;     /* capture one cycle in a hipGraph and replay it (default 1)      */
+  int32_t tile_rows;     /* launch-shape knob of the fused sweep kernels; 0 = built-in
+                            table.  Numerically neutral.                                   */
+  int32_t reserved[7];
+} dmg_options;
+
+typedef struct dmg_hier dmg_hier;
+typedef struct dmg_transfer dmg_transfer;
+typedef struct dmg_batch dmg_batch;
+
+void dmg_default_options(dmg_options* opts);
+const char* dmg_last_error(void);
+const char* dmg_version(void);
+
+/* ---- a1: stencil assembly (Sec. 2, eq. weak_computational; Sec. 2.1 D_c) --------------------
+ * jac : [16][ny-1][nx-1] float64.  Plane 4*q+e is entry e of J = dX/d(xi,eta) of the inverse
+ *       map X = T^{-1} (e = 0: dx/dxi, 1: dx/deta, 2: dy/dxi, 3: dy/deta) at the 2x2 Gauss point
+ *       q = qx + 2 qy of each cell, local offsets 1/2 -+ 1/(2 sqrt 3) of the cell width.
+ *       det J must be > 0.
+ * K   : [ny-1][nx-1] float64 scalar diffusion coefficient per cell (D = K I).
+ * S   : [5][ny][nx] float64 output: A = sum_cells K_e int grad phi_a . M grad phi_b,
+ *       M = det(J) J^{-1} J^{-T}, with the 2x2 Gauss rule; Dirichlet rows/couplings zero.
+ * nx, ny >= 3 (any size).  Errors: DMG_ERR_INVALID_ARG, DMG_ERR_DIMS, DMG_ERR_HIP. */
+dmg_status dmg_assemble_stencil(const double* jac, const double* K, int32_t nx, int32_t ny,
+                                double* S, hipStream_t stream);
+
+/* ---- a2-a4: hierarchy setup (Sec. 2.2; coarsening by two, operator-induced interpolation,
+ * Galerkin P^T A P, dense Cholesky of the coarsest interior system) --------------------------
+ * The hierarchy lives entirely in a caller-provided device workspace (>= *bytes, 256-byte
+ * aligned) which must outlive the handle; the library does not allocate device memory for it.
+ * The fine stencil S is copied into the workspace (the caller may free it after setup).
+ * Setup synchronises `stream` once to read the coarsest pivot check.
+ * Errors: DMG_ERR_DIMS (not 2^k+1), DMG_ERR_WORKSPACE, DMG_ERR_NOT_SPD, DMG_ERR_HIP. */
+dmg_status dmg_workspace_bytes(int32_t nx, int32_t ny, const dmg_options* opts, size_t* bytes);
+dmg_status dmg_setup(const double* S, int32_t nx, int32_t ny, const dmg_options* opts,
+                     void* workspace, size_t ws_bytes, hipStream_t stream, dmg_hier** out);
+void dmg_destroy(dmg_hier* h);
+
+/* Inspection of level l (0 = finest): dims and device pointers to its float64 stencil
+ * [5][ny][nx] and (l < levels-1) interpolation weights [8][ny_c][nx_c] where entry (I,J) of
+ * plane p holds: 0 w_W and 1 w_E of fine (2I+1,2J); 2 w_S and 3 w_N of fine (2I,2J+1);
+ * 4..7 the weights of the centre fine point (2I+1,2J+1) to coarse (I,J),(I+1,J),(I,J+1),
+ * (I+1,J+1).  Unused entries are 0. */
+dmg_status dmg_hier_level(const dmg_hier* h, int32_t level, int32_t* nx, int32_t* ny,
+                          const double** S, const double** P);
+/* Levels, grid complexity sum N_l/N_1 and operator complexity sum nnz_l/nnz_1 (Sec. 4,
+ * definitions of GC and OC; interior unknowns, stored 9-point nonzeros). Host-only. */
+dmg_status dmg_stats(const dmg_hier* h, int32_t* levels, double* grid_complexity,
+                     double* op_complexity);
+
+/* ---- a5-a8: one V(nu_pre, nu_post) cycle on A u = b, in place on u (Sec. 2.2) -------------
+ * Four-colour Gauss-Seidel smoothing, r = b - A u, b_H = P^T r, zero coarse initial guess,
+ * recursion, coarsest Cholesky solve, u += P e_H, post-smoothing.  float64 only. */
+dmg_status dmg_vcycle(dmg_hier* h, double* u, const double* b, hipStream_t stream);
+/* ||b - A u||_2 over interior vertices (deterministic fixed-order reduction).  Synchronous. */
+dmg_status dmg_residual_norm(dmg_hier* h, const double* u, const double* b, double* norm,
+                             hipStream_t stream);
+
+/* ---- a9: solve (Sec. 4 stopping rule: ||b - A u||_2 <= rtol ||b||_2) ------------------------
+ * u in: initial guess, out: solution.  precision DMG_FP64: repeated V-cycles.  DMG_FP32_IR:
+ * r = b - A x (fp64); s = ||r||; r32 = fl32(r/s); inner_cycles fp32 V-cycles from e = 0 with
+ * fp32-rounded copies of the fp64 Galerkin stencils/weights (coarsest solve in fp64);
+ * x += s e.  iters / relres (host, nullable) return the count of cycles or refinement steps
+ * and the final relative residual; history (host, nullable, >= max_iters doubles) receives the
+ * relative residual after each step.  Returns DMG_ERR_NO_CONVERGENCE (u holds the last
+ * iterate) or DMG_ERR_NONFINITE.  Synchronises `stream` once per step. */
+dmg_status dmg_solve(dmg_hier* h, double* u, const double* b, double rtol, int32_t max_iters,
+                     int32_t* iters, double* relres, double* history, hipStream_t stream);
+
+/* ---- a11: per-cell gradient of J through the solve ---------------------------------------
+ * dK[e] = -lambda_e^T G_e u_e, G_e the cell's Q1 element matrix (recomputed from jac as in
+ * dmg_assemble_stencil), lambda and u vertex arrays with zero boundary ring.  With lambda
+ * solving A lambda = dJ/du this is dJ/dK_e (discrete adjoint; A is symmetric). */
+dmg_status dmg_grad_K(const double* jac, const double* lambda, const double* u, int32_t nx,
+                      int32_t ny, double* dK, hipStream_t stream);
+
+/* ---- a12: grid <-> mesh transfers (Sec. 2.3; Sec. 2.3.1 coupled mass) -----------------------
+ * Create from a P1 mesh given as HOST arrays: xy_c [nv][2] the images T(x_v) in (-1,1)^2,
+ * xy_p [nv][2] physical coordinates, tris [nt][3] (int32, any orientation), dof [nv] (uint8,
+ * 0 = Dirichlet vertex).  C is assembled by rasterising each mapped triangle over the grid
+ * cells it overlaps with an nq x nq Gauss rule per cell (points outside the triangle count as
+ * zero; |J_T^{-1}| taken as area(tau_p)/area(mapped tau)); M_p is the P1 mass matrix.  The
+ * handle owns device memory allocated here (freed by dmg_transfer_destroy); the apply calls
+ * allocate nothing.
+ * from_grid: u_p = CG2(M_p, C u_c)      u_c [ny][nx] -> u_p [nv]
+ * to_grid:   r_c = C^T CG2(M_p, r_p)    r_p [nv]     -> r_c [ny][nx]
+ * CG2 = two iterations of unpreconditioned CG from 0.  Dirichlet entries are ignored/zero. */
+dmg_status dmg_transfer_create(int32_t nv, int32_t nt, const double* xy_c, const double* xy_p,
+                               const int32_t* tris, const uint8_t* dof, int32_t nx, int32_t ny,
+                               int32_t nq, hipStream_t stream, dmg_transfer** out);
+dmg_status dmg_transfer_info(const dmg_transfer* t, int64_t* nnz_C, int64_t* nnz_M);
+dmg_status dmg_transfer_from_grid(dmg_transfer* t, const double* u_c, double* u_p,
+                                  hipStream_t stream);
+dmg_status dmg_transfer_to_grid(dmg_transfer* t, const double* r_p, double* r_c,
+                                hipStream_t stream);
+void dmg_transfer_destroy(dmg_transfer* t);
+
+/* ---- a10: batched solve of independent instances ----------------------------------------
+ * count instances with dims nx[k], ny[k] (host arrays) and fine stencils S[k] (host array of
+ * device pointers).  One workspace holds every hierarchy.  dmg_batch_solve runs all instances'
+ * V-cycles level by level in shared launches (one kernel per step over every instance's tiles)
+ * until each instance meets rtol; iters (host, [count], nullable) receives per-instance
+ * counts, relres (host, [count], nullable) final relative residuals. */
+dmg_status dmg_batch_workspace_bytes(int32_t count, const int32_t* nx, const int32_t* ny,
+                                     const dmg_options* opts, size_t* bytes);
+dmg_status dmg_batch_setup(int32_t count, const int32_t* nx, const int32_t* ny,
+                           const double* const* S, const dmg_options* opts, void* workspace,
+                           size_t ws_bytes, hipStream_t stream, dmg_batch** out);
+dmg_status dmg_batch_solve(dmg_batch* bt, double* const* u, const double* const* b,
+                           double rtol, int32_t max_iters, int32_t* iters, double* relres,
+                           hipStream_t stream);
+void dmg_batch_destroy(dmg_batch* bt);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DMG_H */

@@ -1,0 +1,300 @@
+"""MI355X (gfx950) structured multigrid for remapped elliptic problems.
+
+Python binding over the C ABI of libdmg.so (include/dmg.h).  Every numerical step runs in the
+library's HIP kernels; this module only checks tensor shapes/dtypes/devices, allocates device
+memory through PyTorch and passes pointers and the current HIP stream.
+
+    S = assemble_stencil(jac, K)              # [5][ny][nx] mapped Q1 stencil
+    h = Hierarchy(S)                          # operator-induced interpolation + Galerkin levels
+    u, iters, relres, hist = h.solve(b, rtol=1e-10)
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import DMG_FP32_IR, DMG_FP64, DmgError, Options, default_options
+
+__all__ = ["Hierarchy", "assemble_stencil", "grad_K", "Transfer", "BatchSolver", "DiffSolve",
+           "default_options", "Options", "DmgError", "DMG_FP64", "DMG_FP32_IR", "lib", "version"]
+
+
+def lib():
+    return _lib.load()
+
+
+def version() -> str:
+    return lib().dmg_version().decode()
+
+
+def _stream(device) -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dev(t: torch.Tensor, shape, name: str, dtype=torch.float64) -> int:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on a GPU device (got {t.device})")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype} (got {t.dtype})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t.data_ptr()
+
+
+def assemble_stencil(jac: torch.Tensor, K: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Mapped Q1 stencil from map Jacobians at the 2x2 Gauss points ([16][ny-1][nx-1]) and a
+    per-cell coefficient ([ny-1][nx-1]); returns [5][ny][nx] float64."""
+    ny, nx = K.shape[0] + 1, K.shape[1] + 1
+    pj = _dev(jac, (16, ny - 1, nx - 1), "jac")
+    pk = _dev(K, (ny - 1, nx - 1), "K")
+    if out is None:
+        out = torch.empty((5, ny, nx), dtype=torch.float64, device=K.device)
+    ps = _dev(out, (5, ny, nx), "out")
+    _lib.check(lib().dmg_assemble_stencil(pj, pk, nx, ny, ps, _stream(K.device)))
+    return out
+
+
+def grad_K(jac: torch.Tensor, lam: torch.Tensor, u: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+    """dK_e = -lam_e^T G_e u_e per cell ([ny-1][nx-1])."""
+    ny, nx = u.shape
+    pj = _dev(jac, (16, ny - 1, nx - 1), "jac")
+    pl = _dev(lam, (ny, nx), "lam")
+    pu = _dev(u, (ny, nx), "u")
+    if out is None:
+        out = torch.empty((ny - 1, nx - 1), dtype=torch.float64, device=u.device)
+    po = _dev(out, (ny - 1, nx - 1), "out")
+    _lib.check(lib().dmg_grad_K(pj, pl, pu, nx, ny, po, _stream(u.device)))
+    return out
+
+
+class Hierarchy:
+    """BoxMG hierarchy of a fine stencil S [5][ny][nx] (float64, on a GPU)."""
+
+    def __init__(self, S: torch.Tensor, opts: Options | None = None, **kw):
+        _, ny, nx = S.shape
+        self.nx, self.ny, self.device = nx, ny, S.device
+        self.opts = opts if opts is not None else default_options(**kw)
+        nbytes = C.c_size_t()
+        _lib.check(lib().dmg_workspace_bytes(nx, ny, C.byref(self.opts), C.byref(nbytes)))
+        self.workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=S.device)
+        base = self.workspace.data_ptr()
+        self._off = (-base) % 256
+        self._ws_ptr = base + self._off
+        h = C.c_void_p()
+        _lib.check(lib().dmg_setup(_dev(S, (5, ny, nx), "S"), nx, ny, C.byref(self.opts),
+                                   self._ws_ptr, int(nbytes.value), _stream(S.device), C.byref(h)))
+        self._h = h
+
+    # -- inspection --------------------------------------------------------------------
+    def _view(self, ptr: int, count: int) -> torch.Tensor:
+        off = ptr - self.workspace.data_ptr()
+        if off % 8 or off < 0 or off + 8 * count > self.workspace.numel():
+            raise RuntimeError("pointer outside the workspace")
+        return self.workspace[off:off + 8 * count].view(torch.float64)
+
+    def stats(self):
+        lv, gc, oc = C.c_int32(), C.c_double(), C.c_double()
+        _lib.check(lib().dmg_stats(self._h, C.byref(lv), C.byref(gc), C.byref(oc)))
+        return int(lv.value), float(gc.value), float(oc.value)
+
+    @property
+    def num_levels(self) -> int:
+        return self.stats()[0]
+
+    def level(self, l: int):
+        """(S_l [5][ny][nx], P_l [8][nyc][nxc] or None) as views into the workspace."""
+        nx, ny, ps, pp = C.c_int32(), C.c_int32(), C.c_void_p(), C.c_void_p()
+        _lib.check(lib().dmg_hier_level(self._h, l, C.byref(nx), C.byref(ny), C.byref(ps), C.byref(pp)))
+        nx, ny = nx.value, ny.value
+        S = self._view(ps.value, 5 * nx * ny).view(5, ny, nx)
+        P = None
+        if pp.value:
+            ncx, ncy = (nx + 1) // 2, (ny + 1) // 2
+            P = self._view(pp.value, 8 * ncx * ncy).view(8, ncy, ncx)
+        return S, P
+
+    # -- cycles and solves ---------------------------------------------------------------
+    def vcycle(self, u: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
+        shp = (self.ny, self.nx)
+        _lib.check(lib().dmg_vcycle(self._h, _dev(u, shp, "u"), _dev(b, shp, "b"), _stream(self.device)))
+        return u
+
+    def residual_norm(self, u: torch.Tensor, b: torch.Tensor) -> float:
+        shp = (self.ny, self.nx)
+        out = C.c_double()
+        _lib.check(lib().dmg_residual_norm(self._h, _dev(u, shp, "u"), _dev(b, shp, "b"), C.byref(out),
+                                           _stream(self.device)))
+        return float(out.value)
+
+    def solve(self, b: torch.Tensor, u: torch.Tensor | None = None, rtol: float = 1e-10,
+              max_iters: int = 200, raise_on_fail: bool = True):
+        """Solve A u = b from u (default zeros); returns (u, iterations, relres, history)."""
+        shp = (self.ny, self.nx)
+        if u is None:
+            u = torch.zeros(shp, dtype=torch.float64, device=self.device)
+        hist = (C.c_double * max(1, max_iters))()
+        it, rr = C.c_int32(), C.c_double()
+        st = lib().dmg_solve(self._h, _dev(u, shp, "u"), _dev(b, shp, "b"), float(rtol), int(max_iters),
+                             C.byref(it), C.byref(rr), hist, _stream(self.device))
+        if st != 0 and (raise_on_fail or st != 6):
+            _lib.check(st)
+        k = int(it.value)
+        return u, k, float(rr.value), [hist[i] for i in range(k)]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().dmg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Transfer:
+    """L2-projection transfers between a P1 mesh and the grid (host mesh arrays)."""
+
+    def __init__(self, xy_c, xy_p, tris, dof, nx: int, ny: int, nq: int = 4, device="cuda"):
+        self.xy_c = np.ascontiguousarray(xy_c, dtype=np.float64)
+        self.xy_p = np.ascontiguousarray(xy_p, dtype=np.float64)
+        self.tris = np.ascontiguousarray(tris, dtype=np.int32)
+        self.dof = np.ascontiguousarray(dof, dtype=np.uint8)
+        self.nv, self.nt = self.xy_c.shape[0], self.tris.shape[0]
+        if self.xy_c.shape != (self.nv, 2) or self.xy_p.shape != (self.nv, 2) or self.tris.shape != (self.nt, 3) \
+                or self.dof.shape != (self.nv,):
+            raise ValueError("mesh arrays have inconsistent shapes")
+        self.nx, self.ny = nx, ny
+        self.device = torch.device(device)
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _lib.check(lib().dmg_transfer_create(self.nv, self.nt, self.xy_c.ctypes.data, self.xy_p.ctypes.data,
+                                                 self.tris.ctypes.data, self.dof.ctypes.data, nx, ny, nq,
+                                                 _stream(self.device), C.byref(h)))
+        self._h = h
+
+    def nnz(self):
+        a, b = C.c_int64(), C.c_int64()
+        _lib.check(lib().dmg_transfer_info(self._h, C.byref(a), C.byref(b)))
+        return int(a.value), int(b.value)
+
+    def from_grid(self, u_c: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(self.nv, dtype=torch.float64, device=self.device)
+        _lib.check(lib().dmg_transfer_from_grid(self._h, _dev(u_c, (self.ny, self.nx), "u_c"),
+                                                _dev(out, (self.nv,), "out"), _stream(self.device)))
+        return out
+
+    def to_grid(self, r_p: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device)
+        _lib.check(lib().dmg_transfer_to_grid(self._h, _dev(r_p, (self.nv,), "r_p"),
+                                              _dev(out, (self.ny, self.nx), "out"), _stream(self.device)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().dmg_transfer_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class BatchSolver:
+    """Independent instances (stencils S_k [5][ny_k][nx_k]) solved together."""
+
+    def __init__(self, stencils, opts: Options | None = None, **kw):
+        self.count = len(stencils)
+        self.dims = [(int(S.shape[2]), int(S.shape[1])) for S in stencils]
+        self.device = stencils[0].device
+        self.opts = opts if opts is not None else default_options(**kw)
+        self._nx = (C.c_int32 * self.count)(*[d[0] for d in self.dims])
+        self._ny = (C.c_int32 * self.count)(*[d[1] for d in self.dims])
+        nbytes = C.c_size_t()
+        _lib.check(lib().dmg_batch_workspace_bytes(self.count, self._nx, self._ny, C.byref(self.opts),
+                                                   C.byref(nbytes)))
+        self.workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.device)
+        ws = self.workspace.data_ptr()
+        ws += (-ws) % 256
+        ptrs = (C.c_void_p * self.count)(*[_dev(S, (5, ny, nx), f"S[{k}]")
+                                           for k, (S, (nx, ny)) in enumerate(zip(stencils, self.dims))])
+        h = C.c_void_p()
+        _lib.check(lib().dmg_batch_setup(self.count, self._nx, self._ny, ptrs, C.byref(self.opts), ws,
+                                         int(nbytes.value), _stream(self.device), C.byref(h)))
+        self._h = h
+
+    def solve(self, bs, us=None, rtol: float = 1e-10, max_iters: int = 200, raise_on_fail: bool = True):
+        if us is None:
+            us = [torch.zeros((ny, nx), dtype=torch.float64, device=self.device) for nx, ny in self.dims]
+        up = (C.c_void_p * self.count)(*[_dev(u, (ny, nx), "u") for u, (nx, ny) in zip(us, self.dims)])
+        bp = (C.c_void_p * self.count)(*[_dev(b, (ny, nx), "b") for b, (nx, ny) in zip(bs, self.dims)])
+        it = (C.c_int32 * self.count)()
+        rr = (C.c_double * self.count)()
+        st = lib().dmg_batch_solve(self._h, up, bp, float(rtol), int(max_iters), it, rr, _stream(self.device))
+        if st != 0 and (raise_on_fail or st != 6):
+            _lib.check(st)
+        return us, list(it), list(rr)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().dmg_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _interior(x: torch.Tensor) -> torch.Tensor:
+    y = x.clone()
+    y[0, :] = 0
+    y[-1, :] = 0
+    y[:, 0] = 0
+    y[:, -1] = 0
+    return y
+
+
+class DiffSolve(torch.autograd.Function):
+    """u = A(K)^{-1} b with A the mapped Q1 operator; gradients w.r.t. K (per cell) and b.
+
+    Forward saves only (K, b, u); backward recomputes the stencil and hierarchy, solves the
+    adjoint system A lam = du (A is symmetric, so the same V-cycle serves), and returns
+    dK = -lam_e^T G_e u_e and db = lam.
+    """
+
+    @staticmethod
+    def forward(ctx, K, b, jac, rtol=1e-12, max_iters=200, opts=None):
+        S = assemble_stencil(jac, K.detach().contiguous())
+        h = Hierarchy(S, opts)
+        u, its, rr, _ = h.solve(b.detach().contiguous(), rtol=rtol, max_iters=max_iters, raise_on_fail=False)
+        h.close()
+        ctx.save_for_backward(K, b, u)
+        ctx.jac, ctx.rtol, ctx.max_iters, ctx.opts = jac, rtol, max_iters, opts
+        ctx.iters, ctx.relres = its, rr
+        return u
+
+    @staticmethod
+    def backward(ctx, gu):
+        K, b, u = ctx.saved_tensors
+        S = assemble_stencil(ctx.jac, K.detach().contiguous())
+        h = Hierarchy(S, ctx.opts)
+        lam, _, _, _ = h.solve(_interior(gu.contiguous().to(torch.float64)), rtol=ctx.rtol,
+                               max_iters=ctx.max_iters, raise_on_fail=False)
+        h.close()
+        dK = grad_K(ctx.jac, lam, u) if ctx.needs_input_grad[0] else None
+        db = lam if ctx.needs_input_grad[1] else None
+        return dK, db, None, None, None, None

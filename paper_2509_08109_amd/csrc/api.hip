@@ -1,0 +1,472 @@
+// C-ABI entry points: validation, workspace carving, hierarchy setup, V-cycles and solve
+// drivers (float64 and float32-in-float64 refinement), adjoint gradient, batched solves.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+
+#include "dmg_internal.h"
+
+namespace dmg {
+
+namespace {
+thread_local char g_err[1024] = "";
+}
+
+dmg_status fail(dmg_status code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+void clear_error() { g_err[0] = 0; }
+
+namespace {
+
+bool pow2p1(int n) {
+  if (n < 3) return false;
+  const int m = n - 1;
+  return (m & (m - 1)) == 0;
+}
+
+dmg_status check_options(const dmg_options* o) {
+  if (!o) return fail(DMG_ERR_INVALID_ARG, "options pointer is null");
+  if (o->nu_pre < 0 || o->nu_post < 0 || o->nu_pre + o->nu_post == 0 || o->nu_pre > 8 ||
+      o->nu_post > 8)
+    return fail(DMG_ERR_INVALID_ARG, "nu_pre/nu_post must be in [0,8] and not both 0");
+  for (const int32_t* ord : {o->pre_order, o->post_order}) {
+    int seen = 0;
+    for (int k = 0; k < 4; ++k) {
+      if (ord[k] < 0 || ord[k] > 3 || (seen >> ord[k]) & 1)
+        return fail(DMG_ERR_INVALID_ARG, "colour orders must be permutations of 0..3");
+      seen |= 1 << ord[k];
+    }
+  }
+  if (o->coarsest_n < 3) return fail(DMG_ERR_INVALID_ARG, "coarsest_n must be >= 3");
+  if (o->precision != DMG_FP64 && o->precision != DMG_FP32_IR)
+    return fail(DMG_ERR_INVALID_ARG, "unknown precision %d", o->precision);
+  if (o->inner_cycles < 1 || o->inner_cycles > 16)
+    return fail(DMG_ERR_INVALID_ARG, "inner_cycles must be in [1,16]");
+  return DMG_OK;
+}
+
+dmg_status level_dims(int nx, int ny, int coarsest_n, std::vector<std::pair<int, int>>& dims) {
+  if (!pow2p1(nx) || !pow2p1(ny))
+    return fail(DMG_ERR_DIMS, "grid dims %d x %d: each must be 2^k+1 with k >= 1", nx, ny);
+  dims.clear();
+  dims.emplace_back(nx, ny);
+  while (std::min(dims.back().first, dims.back().second) > coarsest_n)
+    dims.emplace_back((dims.back().first + 1) / 2, (dims.back().second + 1) / 2);
+  const auto& c = dims.back();
+  const long m = long(c.first - 2) * long(c.second - 2);
+  if (m > 4096)
+    return fail(DMG_ERR_DIMS, "coarsest system has %ld unknowns (max 4096); lower coarsest_n", m);
+  return DMG_OK;
+}
+
+// Lays out a hierarchy in the arena (sizing pass when a.base is null).
+void carve(dmg_hier& h, Arena& a, const std::vector<std::pair<int, int>>& dims,
+           const dmg_options& o) {
+  const bool fp32 = o.precision == DMG_FP32_IR;
+  h.L.assign(dims.size(), Level{});
+  for (size_t l = 0; l < dims.size(); ++l) {
+    Level& L = h.L[l];
+    L.nx = dims[l].first;
+    L.ny = dims[l].second;
+    const size_t n = L.n();
+    L.S = a.take<double>(5 * n);
+    if (l + 1 < dims.size()) {
+      const size_t nc = size_t(dims[l + 1].first) * dims[l + 1].second;
+      L.P = a.take<double>(8 * nc);
+      L.r = a.take<double>(n);
+      if (fp32) {
+        L.P32 = a.take<float>(8 * nc);
+        L.r32 = a.take<float>(n);
+      }
+    }
+    if (l > 0) {
+      L.u = a.take<double>(n);
+      L.b = a.take<double>(n);
+    }
+    if (fp32) {
+      L.S32 = a.take<float>(5 * n);
+      L.u32 = a.take<float>(n);
+      L.b32 = a.take<float>(n);
+    }
+  }
+  const auto& c = dims.back();
+  h.m_coarse = (c.first - 2) * (c.second - 2);
+  h.coarse_idx = a.take<int>(size_t(h.m_coarse));
+  h.chol = a.take<double>(size_t(h.m_coarse) * h.m_coarse);
+  h.partials = a.take<double>(kReduceBlocks);
+  h.scalars = a.take<double>(16);
+  h.flag = a.take<int>(16);
+  if (fp32) h.r64 = a.take<double>(size_t(dims[0].first) * dims[0].second);
+}
+
+template <class T>
+struct Prec;
+template <>
+struct Prec<double> {
+  static const double* S(const Level& L) { return L.S; }
+  static const double* P(const Level& L) { return L.P; }
+  static double* u(const Level& L) { return L.u; }
+  static double* b(const Level& L) { return L.b; }
+  static double* r(const Level& L) { return L.r; }
+};
+template <>
+struct Prec<float> {
+  static const float* S(const Level& L) { return L.S32; }
+  static const float* P(const Level& L) { return L.P32; }
+  static float* u(const Level& L) { return L.u32; }
+  static float* b(const Level& L) { return L.b32; }
+  static float* r(const Level& L) { return L.r32; }
+};
+
+template <class T>
+dmg_status smooth_sweeps(const Level& L, const T* S, T* u, const T* b, int nu,
+                         const int32_t* order, hipStream_t s) {
+  for (int k = 0; k < nu; ++k)
+    for (int c = 0; c < 4; ++c) DMG_CHECK(launch_smooth<T>(S, u, b, L.nx, L.ny, order[c], s));
+  return DMG_OK;
+}
+
+// One V-cycle in precision T on level-0 arrays (u0, b0); coarse levels use hierarchy arrays.
+template <class T>
+dmg_status vcycle_impl(dmg_hier* h, T* u0, const T* b0, hipStream_t s) {
+  using Pr = Prec<T>;
+  const int nl = int(h->L.size());
+  const dmg_options& o = h->opts;
+  for (int l = 0; l < nl - 1; ++l) {
+    const Level& L = h->L[l];
+    T* u = l == 0 ? u0 : Pr::u(L);
+    const T* b = l == 0 ? b0 : Pr::b(L);
+    if (l > 0) DMG_CHECK(launch_fill<T>(u, T(0), L.n(), s));
+    DMG_CHECK(smooth_sweeps<T>(L, Pr::S(L), u, b, o.nu_pre, o.pre_order, s));
+    DMG_CHECK(launch_residual<T>(Pr::S(L), u, b, Pr::r(L), L.nx, L.ny, s));
+    DMG_CHECK(launch_restrict<T>(Pr::P(L), Pr::r(L), Pr::b(h->L[l + 1]), L.nx, L.ny, s));
+  }
+  {
+    const Level& C = h->L[nl - 1];
+    T* u = nl == 1 ? u0 : Pr::u(C);
+    const T* b = nl == 1 ? b0 : Pr::b(C);
+    DMG_CHECK(launch_coarse_solve<T>(b, u, h->m_coarse, h->coarse_idx, h->chol, C.n(), s));
+  }
+  for (int l = nl - 2; l >= 0; --l) {
+    const Level& L = h->L[l];
+    T* u = l == 0 ? u0 : Pr::u(L);
+    const T* b = l == 0 ? b0 : Pr::b(L);
+    DMG_CHECK(launch_prolong_add<T>(Pr::P(L), Pr::u(h->L[l + 1]), u, L.nx, L.ny, s));
+    DMG_CHECK(smooth_sweeps<T>(L, Pr::S(L), u, b, o.nu_post, o.post_order, s));
+  }
+  return DMG_OK;
+}
+
+dmg_status read_scalar(dmg_hier* h, int slot, double* out, hipStream_t s) {
+  DMG_HIP(hipMemcpyAsync(h->host + slot, h->scalars + slot, sizeof(double),
+                         hipMemcpyDeviceToHost, s));
+  DMG_HIP(hipStreamSynchronize(s));
+  *out = h->host[slot];
+  return DMG_OK;
+}
+
+// ||b||_2 over interior vertices into scalars[0..1]
+dmg_status norm_b(dmg_hier* h, const double* b, hipStream_t s) {
+  const Level& L = h->L[0];
+  DMG_CHECK(launch_sq_partials(b, L.n(), L.nx, L.ny, h->partials, s));
+  return launch_finalize(h->partials, h->scalars + 0, s);
+}
+
+// ||b - A u||_2 into scalars[slot..slot+1]
+dmg_status norm_r(dmg_hier* h, const double* u, const double* b, int slot, hipStream_t s) {
+  const Level& L = h->L[0];
+  DMG_CHECK(launch_resid_sq_partials(L.S, u, b, L.nx, L.ny, h->partials, s));
+  return launch_finalize(h->partials, h->scalars + slot, s);
+}
+
+// The repeated step of a float64 solve: one V-cycle and the new residual norm (slot 2).
+dmg_status step_fp64(dmg_hier* h, double* u, const double* b, hipStream_t s) {
+  DMG_CHECK(vcycle_impl<double>(h, u, b, s));
+  return norm_r(h, u, b, 2, s);
+}
+
+// The repeated step of float32 refinement: r32 = r/s, e = 0, inner fp32 cycles, x += s e,
+// r = b - A x and its norm (slot 4).
+dmg_status step_ir(dmg_hier* h, double* x, const double* b, hipStream_t s) {
+  const Level& L = h->L[0];
+  DMG_CHECK(launch_ir_scale(h->r64, h->scalars + 4, L.b32, L.n(), s));
+  DMG_CHECK(launch_fill<float>(L.u32, 0.0f, L.n(), s));
+  for (int k = 0; k < h->opts.inner_cycles; ++k)
+    DMG_CHECK(vcycle_impl<float>(h, L.u32, L.b32, s));
+  DMG_CHECK(launch_ir_update(x, L.u32, h->scalars + 4, L.n(), s));
+  DMG_CHECK(launch_ir_residual(L.S, x, b, h->r64, L.nx, L.ny, h->partials, s));
+  return launch_finalize(h->partials, h->scalars + 4, s);
+}
+
+void graph_reset(Graph& g) {
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (g.graph) (void)hipGraphDestroy(g.graph);
+  g = Graph{};
+}
+
+// Runs the solve step for (u, b) on stream s, through a captured graph when enabled.  The
+// graph is re-captured when the arrays or the stream change.
+dmg_status run_step(dmg_hier* h, int kind, double* u, const double* b, hipStream_t s) {
+  auto step = [&]() { return kind == 0 ? step_fp64(h, u, b, s) : step_ir(h, u, b, s); };
+  // the legacy default stream cannot be captured: run eagerly there
+  if (!h->opts.use_graph || s == nullptr) return step();
+  Graph& g = h->graph;
+  if (!(g.exec && g.key_u == u && g.key_b == b && g.stream == s && g.kind == kind)) {
+    graph_reset(g);
+    DMG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    dmg_status st = step();
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &graph);
+    if (st != DMG_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    if (e != hipSuccess) return fail(DMG_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
+    g.graph = graph;
+    e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      graph_reset(g);
+      return fail(DMG_ERR_HIP, "graph instantiate failed: %s", hipGetErrorString(e));
+    }
+    g.key_u = u;
+    g.key_b = b;
+    g.stream = s;
+    g.kind = kind;
+  }
+  DMG_HIP(hipGraphLaunch(g.exec, s));
+  return DMG_OK;
+}
+
+dmg_status setup_impl(dmg_hier* h, const double* S, hipStream_t s) {
+  const size_t n0 = h->L[0].n();
+  DMG_HIP(hipMemcpyAsync(h->L[0].S, S, 5 * n0 * sizeof(double), hipMemcpyDeviceToDevice, s));
+  for (size_t l = 0; l + 1 < h->L.size(); ++l) {
+    const Level& L = h->L[l];
+    DMG_CHECK(launch_interp_weights(L.S, L.nx, L.ny, L.P, s));
+    DMG_CHECK(launch_rap(L.S, L.P, L.nx, L.ny, h->L[l + 1].S, s));
+  }
+  const Level& C = h->L.back();
+  DMG_CHECK(launch_coarse_factor(C.S, C.nx, C.ny, h->m_coarse, h->coarse_idx, h->chol, h->flag, s));
+  if (h->opts.precision == DMG_FP32_IR) {
+    for (size_t l = 0; l < h->L.size(); ++l) {
+      const Level& L = h->L[l];
+      DMG_CHECK(launch_cast(L.S, L.S32, 5 * L.n(), s));
+      if (L.P) {
+        const Level& Cn = h->L[l + 1];
+        DMG_CHECK(launch_cast(L.P, L.P32, 8 * Cn.n(), s));
+      }
+    }
+  }
+  int flag = 0;
+  DMG_HIP(hipMemcpyAsync(&flag, h->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  DMG_HIP(hipStreamSynchronize(s));
+  if (flag) return fail(DMG_ERR_NOT_SPD, "coarsest-level Cholesky met a non-positive pivot");
+  return DMG_OK;
+}
+
+}  // namespace
+}  // namespace dmg
+
+dmg_hier::~dmg_hier() {
+  dmg::graph_reset(graph);
+  if (host) (void)hipHostFree(host);
+}
+
+using namespace dmg;
+
+extern "C" {
+
+void dmg_default_options(dmg_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->nu_pre = 1;
+  o->nu_post = 1;
+  for (int k = 0; k < 4; ++k) {
+    o->pre_order[k] = k;
+    o->post_order[k] = 3 - k;
+  }
+  o->coarsest_n = 3;
+  o->precision = DMG_FP64;
+  o->inner_cycles = 1;
+  o->use_graph = 1;
+  o->tile_rows = 0;
+}
+
+const char* dmg_last_error(void) { return g_err; }
+
+const char* dmg_version(void) { return "dmg 0.1 (gfx950)"; }
+
+dmg_status dmg_assemble_stencil(const double* jac, const double* K, int32_t nx, int32_t ny,
+                                double* S, hipStream_t stream) {
+  clear_error();
+  if (!jac || !K || !S) return fail(DMG_ERR_INVALID_ARG, "null pointer argument");
+  if (nx < 3 || ny < 3) return fail(DMG_ERR_DIMS, "grid dims must be >= 3 (got %d x %d)", nx, ny);
+  if (long(nx) * long(ny) > (1L << 31))
+    return fail(DMG_ERR_DIMS, "grid too large (%d x %d)", nx, ny);
+  return launch_assemble(jac, K, nx, ny, S, stream);
+}
+
+dmg_status dmg_grad_K(const double* jac, const double* lambda, const double* u, int32_t nx,
+                      int32_t ny, double* dK, hipStream_t stream) {
+  clear_error();
+  if (!jac || !lambda || !u || !dK) return fail(DMG_ERR_INVALID_ARG, "null pointer argument");
+  if (nx < 3 || ny < 3) return fail(DMG_ERR_DIMS, "grid dims must be >= 3 (got %d x %d)", nx, ny);
+  return launch_grad_K(jac, lambda, u, nx, ny, dK, stream);
+}
+
+dmg_status dmg_workspace_bytes(int32_t nx, int32_t ny, const dmg_options* opts, size_t* bytes) {
+  clear_error();
+  if (!bytes) return fail(DMG_ERR_INVALID_ARG, "bytes pointer is null");
+  dmg_options def;
+  dmg_default_options(&def);
+  const dmg_options& o = opts ? *opts : def;
+  DMG_CHECK(check_options(&o));
+  std::vector<std::pair<int, int>> dims;
+  DMG_CHECK(level_dims(nx, ny, o.coarsest_n, dims));
+  dmg_hier tmp;
+  Arena a;
+  carve(tmp, a, dims, o);
+  *bytes = a.used;
+  return DMG_OK;
+}
+
+dmg_status dmg_setup(const double* S, int32_t nx, int32_t ny, const dmg_options* opts,
+                     void* workspace, size_t ws_bytes, hipStream_t stream, dmg_hier** out) {
+  clear_error();
+  if (!S || !out) return fail(DMG_ERR_INVALID_ARG, "null pointer argument");
+  *out = nullptr;
+  dmg_options def;
+  dmg_default_options(&def);
+  const dmg_options& o = opts ? *opts : def;
+  DMG_CHECK(check_options(&o));
+  std::vector<std::pair<int, int>> dims;
+  DMG_CHECK(level_dims(nx, ny, o.coarsest_n, dims));
+  if (!workspace) return fail(DMG_ERR_WORKSPACE, "workspace pointer is null");
+  if (reinterpret_cast<uintptr_t>(workspace) & 255)
+    return fail(DMG_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  std::unique_ptr<dmg_hier> h(new (std::nothrow) dmg_hier);
+  if (!h) return fail(DMG_ERR_INVALID_ARG, "out of host memory");
+  h->opts = o;
+  Arena sizing;
+  carve(*h, sizing, dims, o);
+  if (ws_bytes < sizing.used)
+    return fail(DMG_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, sizing.used);
+  Arena a;
+  a.base = static_cast<char*>(workspace);
+  a.cap = ws_bytes;
+  carve(*h, a, dims, o);
+  DMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->host), 16 * sizeof(double),
+                        hipHostMallocDefault));
+  DMG_CHECK(setup_impl(h.get(), S, stream));
+  *out = h.release();
+  return DMG_OK;
+}
+
+void dmg_destroy(dmg_hier* h) { delete h; }
+
+dmg_status dmg_hier_level(const dmg_hier* h, int32_t level, int32_t* nx, int32_t* ny,
+                          const double** S, const double** P) {
+  clear_error();
+  if (!h) return fail(DMG_ERR_INVALID_ARG, "null hierarchy");
+  if (level < 0 || level >= int(h->L.size()))
+    return fail(DMG_ERR_INVALID_ARG, "level %d out of range [0,%zu)", level, h->L.size());
+  const Level& L = h->L[level];
+  if (nx) *nx = L.nx;
+  if (ny) *ny = L.ny;
+  if (S) *S = L.S;
+  if (P) *P = L.P;
+  return DMG_OK;
+}
+
+dmg_status dmg_stats(const dmg_hier* h, int32_t* levels, double* gc, double* oc) {
+  clear_error();
+  if (!h) return fail(DMG_ERR_INVALID_ARG, "null hierarchy");
+  double N = 0, N0 = 0, Z = 0, Z0 = 0;
+  for (size_t l = 0; l < h->L.size(); ++l) {
+    const double m = double(h->L[l].nx - 2) * double(h->L[l].ny - 2);
+    const double mx = h->L[l].nx - 2, my = h->L[l].ny - 2;
+    // nonzeros of a 9-point operator on an mx x my interior grid
+    const double z = 9 * m - 6 * (mx + my) + 4;
+    N += m;
+    Z += z > 0 ? z : m;
+    if (l == 0) {
+      N0 = m;
+      Z0 = z > 0 ? z : m;
+    }
+  }
+  if (levels) *levels = int32_t(h->L.size());
+  if (gc) *gc = N / N0;
+  if (oc) *oc = Z / Z0;
+  return DMG_OK;
+}
+
+dmg_status dmg_vcycle(dmg_hier* h, double* u, const double* b, hipStream_t stream) {
+  clear_error();
+  if (!h || !u || !b) return fail(DMG_ERR_INVALID_ARG, "null pointer argument");
+  return vcycle_impl<double>(h, u, b, stream);
+}
+
+dmg_status dmg_residual_norm(dmg_hier* h, const double* u, const double* b, double* norm,
+                             hipStream_t stream) {
+  clear_error();
+  if (!h || !u || !b || !norm) return fail(DMG_ERR_INVALID_ARG, "null pointer argument");
+  DMG_CHECK(norm_r(h, u, b, 2, stream));
+  return read_scalar(h, 3, norm, stream);
+}
+
+dmg_status dmg_solve(dmg_hier* h, double* u, const double* b, double rtol, int32_t max_iters,
+                     int32_t* iters, double* relres, double* history, hipStream_t stream) {
+  clear_error();
+  if (!h || !u || !b) return fail(DMG_ERR_INVALID_ARG, "null pointer argument");
+  if (!(rtol >= 0.0) || max_iters < 0) return fail(DMG_ERR_INVALID_ARG, "bad rtol/max_iters");
+  if (iters) *iters = 0;
+  double bn = 0.0, rn = 0.0;
+  DMG_CHECK(norm_b(h, b, stream));
+  DMG_CHECK(read_scalar(h, 1, &bn, stream));
+  if (!std::isfinite(bn)) return fail(DMG_ERR_NONFINITE, "right-hand side norm is not finite");
+  if (bn == 0.0) {  // the solution of A u = 0 is u = 0
+    DMG_CHECK(launch_fill<double>(u, 0.0, h->L[0].n(), stream));
+    if (relres) *relres = 0.0;
+    return DMG_OK;
+  }
+  const bool ir = h->opts.precision == DMG_FP32_IR;
+  const int slot = ir ? 4 : 2;
+  if (ir) {
+    const Level& L = h->L[0];
+    DMG_CHECK(launch_ir_residual(L.S, u, b, h->r64, L.nx, L.ny, h->partials, stream));
+    DMG_CHECK(launch_finalize(h->partials, h->scalars + 4, stream));
+  } else {
+    DMG_CHECK(norm_r(h, u, b, 2, stream));
+  }
+  DMG_CHECK(read_scalar(h, slot + 1, &rn, stream));
+  if (!std::isfinite(rn)) return fail(DMG_ERR_NONFINITE, "initial residual norm is not finite");
+  const double target = rtol * bn;
+  int k = 0;
+  while (rn > target && k < max_iters) {
+    DMG_CHECK(run_step(h, ir ? 1 : 0, u, b, stream));
+    DMG_CHECK(read_scalar(h, slot + 1, &rn, stream));
+    ++k;
+    if (history) history[k - 1] = bn > 0 ? rn / bn : rn;
+    if (!std::isfinite(rn)) {
+      if (iters) *iters = k;
+      return fail(DMG_ERR_NONFINITE, "residual norm became non-finite at step %d", k);
+    }
+  }
+  if (iters) *iters = k;
+  if (relres) *relres = bn > 0 ? rn / bn : rn;
+  if (rn > target)
+    return fail(DMG_ERR_NO_CONVERGENCE, "no convergence in %d steps (rel. residual %.3e)", k,
+                bn > 0 ? rn / bn : rn);
+  return DMG_OK;
+}
+
+}  // extern "C"

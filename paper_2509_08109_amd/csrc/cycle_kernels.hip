@@ -1,0 +1,304 @@
+// Cycle-phase kernels: four-colour Gauss-Seidel colour sweep, residual, restriction P^T r,
+// interpolation-correction u += P e, deterministic norms, and the float32-in-float64
+// iterative-refinement helpers.  Templated on the working precision T (double or float).
+#include "dmg_internal.h"
+
+namespace dmg {
+namespace {
+
+constexpr int kBX = 64, kBY = 4;
+
+dim3 grid2(int nx, int ny) { return dim3((nx + kBX - 1) / kBX, (ny + kBY - 1) / kBY); }
+
+// Off-diagonal part of row (i,j) applied to u, summed in ascending neighbour index order.
+template <class T>
+__device__ __forceinline__ T offdiag(const T* __restrict__ S, const T* __restrict__ u, size_t N,
+                                     int nx, size_t v) {
+  const T sw = S[3 * N + v] * u[v - nx - 1];
+  const T s = S[2 * N + v] * u[v - nx];
+  const T se = S[4 * N + v] * u[v - nx + 1];
+  const T w = S[N + v] * u[v - 1];
+  const T e = S[N + v + 1] * u[v + 1];
+  const T nw = S[4 * N + v + nx - 1] * u[v + nx - 1];
+  const T n = S[2 * N + v + nx] * u[v + nx];
+  const T ne = S[3 * N + v + nx + 1] * u[v + nx + 1];
+  return ((((((sw + s) + se) + w) + e) + nw) + n) + ne;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_smooth(const T* __restrict__ S, T* __restrict__ u,
+                                                const T* __restrict__ b, int nx, int ny, int ci,
+                                                int cj) {
+  const int i = ci + 2 * int(blockIdx.x * kBX + threadIdx.x);
+  const int j = cj + 2 * int(blockIdx.y * kBY + threadIdx.y);
+  if (i <= 0 || i >= nx - 1 || j <= 0 || j >= ny - 1) return;
+  const size_t N = size_t(nx) * ny;
+  const size_t v = size_t(j) * nx + i;
+  u[v] = (b[v] - offdiag(S, u, N, nx, v)) / S[v];
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_residual(const T* __restrict__ S, const T* __restrict__ u,
+                                                  const T* __restrict__ b, T* __restrict__ r,
+                                                  int nx, int ny) {
+  const int i = blockIdx.x * kBX + threadIdx.x;
+  const int j = blockIdx.y * kBY + threadIdx.y;
+  if (i >= nx || j >= ny) return;
+  const size_t N = size_t(nx) * ny;
+  const size_t v = size_t(j) * nx + i;
+  if (i == 0 || i == nx - 1 || j == 0 || j == ny - 1) {
+    r[v] = T(0);
+    return;
+  }
+  r[v] = b[v] - (offdiag(S, u, N, nx, v) + S[v] * u[v]);
+}
+
+// b_H(I,J) = sum over the fine 3x3 block around (2I,2J) of P[f,(I,J)] r_f.
+template <class T>
+__global__ __launch_bounds__(256) void k_restrict(const T* __restrict__ P, const T* __restrict__ r,
+                                                  T* __restrict__ bH, int nx, int ny) {
+  const int ncx = (nx + 1) / 2, ncy = (ny + 1) / 2;
+  const int I = blockIdx.x * kBX + threadIdx.x;
+  const int J = blockIdx.y * kBY + threadIdx.y;
+  if (I >= ncx || J >= ncy) return;
+  const size_t c = size_t(J) * ncx + I;
+  if (I == 0 || I == ncx - 1 || J == 0 || J == ncy - 1) {
+    bH[c] = T(0);
+    return;
+  }
+  const size_t NC = size_t(ncx) * ncy;
+  const size_t f = size_t(2 * J) * nx + 2 * I;
+  // rows j-1, j, j+1 in ascending fine index order
+  T acc = P[7 * NC + c - ncx - 1] * r[f - nx - 1];      // centre (2I-1,2J-1) -> NE weight
+  acc += P[3 * NC + c - ncx] * r[f - nx];                // y-line (2I,2J-1)   -> N weight
+  acc += P[6 * NC + c - ncx] * r[f - nx + 1];            // centre (2I+1,2J-1) -> NW weight
+  acc += P[1 * NC + c - 1] * r[f - 1];                   // x-line (2I-1,2J)   -> E weight
+  acc += r[f];                                           // coarse point: injection
+  acc += P[0 * NC + c] * r[f + 1];                       // x-line (2I+1,2J)   -> W weight
+  acc += P[5 * NC + c - 1] * r[f + nx - 1];              // centre (2I-1,2J+1) -> SE weight
+  acc += P[2 * NC + c] * r[f + nx];                      // y-line (2I,2J+1)   -> S weight
+  acc += P[4 * NC + c] * r[f + nx + 1];                  // centre (2I+1,2J+1) -> SW weight
+  bH[c] = acc;
+}
+
+// u_f += (P e)_f on interior fine points.
+template <class T>
+__global__ __launch_bounds__(256) void k_prolong_add(const T* __restrict__ P,
+                                                     const T* __restrict__ e, T* __restrict__ u,
+                                                     int nx, int ny) {
+  const int i = blockIdx.x * kBX + threadIdx.x;
+  const int j = blockIdx.y * kBY + threadIdx.y;
+  if (i <= 0 || i >= nx - 1 || j <= 0 || j >= ny - 1) return;
+  const int ncx = (nx + 1) / 2, ncy = (ny + 1) / 2;
+  const size_t NC = size_t(ncx) * ncy;
+  const int I = i >> 1, J = j >> 1;
+  const size_t c = size_t(J) * ncx + I;
+  T corr;
+  if (!(i & 1) && !(j & 1)) {
+    corr = e[c];
+  } else if ((i & 1) && !(j & 1)) {
+    corr = P[c] * e[c] + P[NC + c] * e[c + 1];
+  } else if (!(i & 1) && (j & 1)) {
+    corr = P[2 * NC + c] * e[c] + P[3 * NC + c] * e[c + ncx];
+  } else {
+    corr = ((P[4 * NC + c] * e[c] + P[5 * NC + c] * e[c + 1]) + P[6 * NC + c] * e[c + ncx]) +
+           P[7 * NC + c] * e[c + ncx + 1];
+  }
+  const size_t v = size_t(j) * nx + i;
+  u[v] = u[v] + corr;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_fill(T* __restrict__ x, T val, size_t n) {
+  for (size_t k = blockIdx.x * size_t(blockDim.x) + threadIdx.x; k < n;
+       k += size_t(gridDim.x) * blockDim.x)
+    x[k] = val;
+}
+
+// ---- deterministic reductions ---------------------------------------------------------
+__device__ __forceinline__ double block_sum(double v) {
+  // 64-lane wavefront tree, then the 4 wavefront sums in order.
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  __shared__ double ws[4];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) ws[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) t = ((ws[0] + ws[1]) + ws[2]) + ws[3];
+  return t;
+}
+
+// partials[blk] = sum over interior rows assigned to blk of (b - A u)^2
+__global__ __launch_bounds__(256) void k_resid_sq(const double* __restrict__ S,
+                                                  const double* __restrict__ u,
+                                                  const double* __restrict__ b, int nx, int ny,
+                                                  double* __restrict__ partials) {
+  const size_t N = size_t(nx) * ny;
+  const size_t m = size_t(nx - 2) * (ny - 2);
+  double acc = 0.0;
+  for (size_t k = blockIdx.x * size_t(blockDim.x) + threadIdx.x; k < m;
+       k += size_t(gridDim.x) * blockDim.x) {
+    const size_t jj = k / (nx - 2), ii = k % (nx - 2);
+    const size_t v = (jj + 1) * nx + ii + 1;
+    const double r = b[v] - (offdiag(S, u, N, nx, v) + S[v] * u[v]);
+    acc += r * r;
+  }
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(256) void k_sq(const double* __restrict__ x, int nx, int ny,
+                                            double* __restrict__ partials) {
+  const size_t m = size_t(nx - 2) * (ny - 2);
+  double acc = 0.0;
+  for (size_t k = blockIdx.x * size_t(blockDim.x) + threadIdx.x; k < m;
+       k += size_t(gridDim.x) * blockDim.x) {
+    const size_t jj = k / (nx - 2), ii = k % (nx - 2);
+    const double v = x[(jj + 1) * nx + ii + 1];
+    acc += v * v;
+  }
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+// out[0] = sum of the partials (fixed order), out[1] = sqrt(out[0])
+__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ partials,
+                                                  double* __restrict__ out) {
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < kReduceBlocks; k += 256) acc += partials[k];
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) {
+    out[0] = t;
+    out[1] = sqrt(t);
+  }
+}
+
+// ---- iterative refinement --------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_ir_update(double* __restrict__ x,
+                                                   const float* __restrict__ e,
+                                                   const double* __restrict__ s, size_t n) {
+  const double sc = s[1];
+  for (size_t k = blockIdx.x * size_t(blockDim.x) + threadIdx.x; k < n;
+       k += size_t(gridDim.x) * blockDim.x)
+    x[k] = x[k] + sc * double(e[k]);
+}
+
+__global__ __launch_bounds__(256) void k_ir_residual(const double* __restrict__ S,
+                                                     const double* __restrict__ x,
+                                                     const double* __restrict__ b,
+                                                     double* __restrict__ r, int nx, int ny,
+                                                     double* __restrict__ partials) {
+  const size_t N = size_t(nx) * ny;
+  double acc = 0.0;
+  for (size_t v = blockIdx.x * size_t(blockDim.x) + threadIdx.x; v < N;
+       v += size_t(gridDim.x) * blockDim.x) {
+    const int j = int(v / nx), i = int(v % nx);
+    double rv = 0.0;
+    if (i > 0 && i < nx - 1 && j > 0 && j < ny - 1) {
+      rv = b[v] - (offdiag(S, x, N, nx, v) + S[v] * x[v]);
+      acc += rv * rv;
+    }
+    r[v] = rv;
+  }
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(256) void k_ir_scale(const double* __restrict__ r,
+                                                  const double* __restrict__ s,
+                                                  float* __restrict__ r32, size_t n) {
+  const double sc = s[1];
+  for (size_t k = blockIdx.x * size_t(blockDim.x) + threadIdx.x; k < n;
+       k += size_t(gridDim.x) * blockDim.x)
+    r32[k] = float(r[k] / sc);
+}
+
+unsigned stride_blocks(size_t n) {
+  const size_t b = (n + 255) / 256;
+  return unsigned(b < 4096 ? (b ? b : 1) : 4096);
+}
+
+}  // namespace
+
+template <class T>
+dmg_status launch_smooth(const T* S, T* u, const T* b, int nx, int ny, int colour,
+                         hipStream_t s) {
+  const int ci = colour & 1, cj = colour >> 1;
+  const int px = (nx - ci + 1) / 2, py = (ny - cj + 1) / 2;
+  k_smooth<T><<<grid2(px, py), dim3(kBX, kBY), 0, s>>>(S, u, b, nx, ny, ci, cj);
+  return launch_check("smooth");
+}
+
+template <class T>
+dmg_status launch_residual(const T* S, const T* u, const T* b, T* r, int nx, int ny,
+                           hipStream_t s) {
+  k_residual<T><<<grid2(nx, ny), dim3(kBX, kBY), 0, s>>>(S, u, b, r, nx, ny);
+  return launch_check("residual");
+}
+
+template <class T>
+dmg_status launch_restrict(const T* P, const T* r, T* bH, int nx, int ny, hipStream_t s) {
+  k_restrict<T><<<grid2((nx + 1) / 2, (ny + 1) / 2), dim3(kBX, kBY), 0, s>>>(P, r, bH, nx, ny);
+  return launch_check("restrict");
+}
+
+template <class T>
+dmg_status launch_prolong_add(const T* P, const T* eH, T* u, int nx, int ny, hipStream_t s) {
+  k_prolong_add<T><<<grid2(nx, ny), dim3(kBX, kBY), 0, s>>>(P, eH, u, nx, ny);
+  return launch_check("prolong_add");
+}
+
+template <class T>
+dmg_status launch_fill(T* x, T v, size_t n, hipStream_t s) {
+  k_fill<T><<<stride_blocks(n), 256, 0, s>>>(x, v, n);
+  return launch_check("fill");
+}
+
+#define DMG_INST(T)                                                                          \
+  template dmg_status launch_smooth<T>(const T*, T*, const T*, int, int, int, hipStream_t);  \
+  template dmg_status launch_residual<T>(const T*, const T*, const T*, T*, int, int,         \
+                                         hipStream_t);                                       \
+  template dmg_status launch_restrict<T>(const T*, const T*, T*, int, int, hipStream_t);     \
+  template dmg_status launch_prolong_add<T>(const T*, const T*, T*, int, int, hipStream_t);  \
+  template dmg_status launch_fill<T>(T*, T, size_t, hipStream_t);
+DMG_INST(double)
+DMG_INST(float)
+#undef DMG_INST
+
+dmg_status launch_resid_sq_partials(const double* S, const double* u, const double* b, int nx,
+                                    int ny, double* partials, hipStream_t s) {
+  k_resid_sq<<<kReduceBlocks, 256, 0, s>>>(S, u, b, nx, ny, partials);
+  return launch_check("resid_sq");
+}
+
+dmg_status launch_sq_partials(const double* x, size_t, int nx, int ny, double* partials,
+                              hipStream_t s) {
+  k_sq<<<kReduceBlocks, 256, 0, s>>>(x, nx, ny, partials);
+  return launch_check("sq");
+}
+
+dmg_status launch_finalize(const double* partials, double* out, hipStream_t s) {
+  k_finalize<<<1, 256, 0, s>>>(partials, out);
+  return launch_check("finalize");
+}
+
+dmg_status launch_ir_update(double* x, const float* e, const double* s_dev, size_t n,
+                            hipStream_t s) {
+  k_ir_update<<<stride_blocks(n), 256, 0, s>>>(x, e, s_dev, n);
+  return launch_check("ir_update");
+}
+
+dmg_status launch_ir_residual(const double* S, const double* x, const double* b, double* r,
+                              int nx, int ny, double* partials, hipStream_t s) {
+  k_ir_residual<<<kReduceBlocks, 256, 0, s>>>(S, x, b, r, nx, ny, partials);
+  return launch_check("ir_residual");
+}
+
+dmg_status launch_ir_scale(const double* r, const double* s_dev, float* r32, size_t n,
+                           hipStream_t s) {
+  k_ir_scale<<<stride_blocks(n), 256, 0, s>>>(r, s_dev, r32, n);
+  return launch_check("ir_scale");
+}
+
+}  // namespace dmg

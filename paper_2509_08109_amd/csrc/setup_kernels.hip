@@ -1,0 +1,423 @@
+// Setup-phase kernels: Q1 stencil assembly from map Jacobians, operator-induced interpolation
+// weights, Galerkin coarse stencils, dense Cholesky of the coarsest interior system, fp32
+// casts, and the per-cell adjoint gradient (which reuses the element-matrix code).
+//
+// Stencil storage: planes C, W, S, SW, SE of [ny][nx]; see include/dmg.h.
+#include "dmg_internal.h"
+
+namespace dmg {
+namespace {
+
+constexpr int kBX = 64, kBY = 4;
+
+// ---------------------------------------------------------------------------------------
+// Element matrices.  On cell e with widths hx, hy and reference coordinates (s,t) in [0,1]^2
+// the bilinear basis has reference gradients (d_s, d_t); in (xi, eta) they are
+// (d_s/hx, d_t/hy) and dxi = hx hy ds dt.  With the metric M = det J J^{-1} J^{-T} at the
+// 2x2 Gauss points (weights 1/4):
+//   G[a][b] = sum_q 1/4 [ M11 ds_a ds_b hy/hx + M12 (ds_a dt_b + dt_a ds_b) + M22 dt_a dt_b hx/hy ].
+// Local nodes: 0 = SW (0,0), 1 = SE (1,0), 2 = NW (0,1), 3 = NE (1,1).
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ void ref_grad(int a, double s, double t, double& ds, double& dt) {
+  switch (a) {
+    case 0: ds = -(1.0 - t); dt = -(1.0 - s); break;
+    case 1: ds = (1.0 - t);  dt = -s;         break;
+    case 2: ds = -t;         dt = (1.0 - s);  break;
+    default: ds = t;         dt = s;          break;
+  }
+}
+
+// Row a of the element matrix of cell c (4 entries).
+__device__ void element_row(const double* __restrict__ jac, size_t ncell, size_t c, int a,
+                            double rx, double ry, double* row) {
+  const double g0 = 0.5 - 0.28867513459481287;  // 1/2 - 1/(2 sqrt 3)
+  const double g1 = 0.5 + 0.28867513459481287;
+  row[0] = row[1] = row[2] = row[3] = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const double s = (q & 1) ? g1 : g0;
+    const double t = (q & 2) ? g1 : g0;
+    const double J11 = jac[(4 * q + 0) * ncell + c];
+    const double J12 = jac[(4 * q + 1) * ncell + c];
+    const double J21 = jac[(4 * q + 2) * ncell + c];
+    const double J22 = jac[(4 * q + 3) * ncell + c];
+    const double inv = 1.0 / (J11 * J22 - J12 * J21);
+    const double M11 = (J22 * J22 + J12 * J12) * inv;
+    const double M12 = -(J22 * J21 + J12 * J11) * inv;
+    const double M22 = (J21 * J21 + J11 * J11) * inv;
+    double das, dat;
+    ref_grad(a, s, t, das, dat);
+    // M applied to the scaled gradient of phi_a: (M11 das*ry + M12 dat, M12 das + M22 dat*rx)
+    const double va = 0.25 * (M11 * das * ry + M12 * dat);
+    const double vb = 0.25 * (M12 * das + M22 * dat * rx);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      double dbs, dbt;
+      ref_grad(b, s, t, dbs, dbt);
+      row[b] += va * dbs + vb * dbt;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_assemble(const double* __restrict__ jac,
+                                                  const double* __restrict__ K, int nx, int ny,
+                                                  double* __restrict__ S) {
+  const int i = blockIdx.x * kBX + threadIdx.x;
+  const int j = blockIdx.y * kBY + threadIdx.y;
+  if (i >= nx || j >= ny) return;
+  const size_t N = size_t(nx) * ny;
+  const size_t v = size_t(j) * nx + i;
+  double C = 0, W = 0, So = 0, SW = 0, SE = 0;
+  if (i > 0 && i < nx - 1 && j > 0 && j < ny - 1) {
+    const size_t ncell = size_t(nx - 1) * (ny - 1);
+    const double rx = double(ny - 1) / double(nx - 1);  // hx/hy with hx = 2/(nx-1), hy = 2/(ny-1)
+    const double ry = double(nx - 1) / double(ny - 1);  // hy/hx
+    double row[4];
+    // cell (i-1, j-1): v is its NE node (3)
+    {
+      const size_t c = size_t(j - 1) * (nx - 1) + (i - 1);
+      element_row(jac, ncell, c, 3, rx, ry, row);
+      const double k = K[c];
+      C += k * row[3];
+      if (i - 1 > 0) W += k * row[2];
+      if (j - 1 > 0) So += k * row[1];
+      if (i - 1 > 0 && j - 1 > 0) SW += k * row[0];
+    }
+    // cell (i, j-1): v is its NW node (2)
+    {
+      const size_t c = size_t(j - 1) * (nx - 1) + i;
+      element_row(jac, ncell, c, 2, rx, ry, row);
+      const double k = K[c];
+      C += k * row[2];
+      if (j - 1 > 0) So += k * row[0];
+      if (j - 1 > 0 && i + 1 < nx - 1) SE += k * row[1];
+    }
+    // cell (i-1, j): v is its SE node (1)
+    {
+      const size_t c = size_t(j) * (nx - 1) + (i - 1);
+      element_row(jac, ncell, c, 1, rx, ry, row);
+      const double k = K[c];
+      C += k * row[1];
+      if (i - 1 > 0) W += k * row[0];
+    }
+    // cell (i, j): v is its SW node (0)
+    {
+      const size_t c = size_t(j) * (nx - 1) + i;
+      element_row(jac, ncell, c, 0, rx, ry, row);
+      C += K[c] * row[0];
+    }
+  }
+  S[0 * N + v] = C;
+  S[1 * N + v] = W;
+  S[2 * N + v] = So;
+  S[3 * N + v] = SW;
+  S[4 * N + v] = SE;
+}
+
+// dK_e = -lam_e^T G_e u_e
+__global__ __launch_bounds__(256) void k_grad_K(const double* __restrict__ jac,
+                                                const double* __restrict__ lam,
+                                                const double* __restrict__ u, int nx, int ny,
+                                                double* __restrict__ dK) {
+  const int i = blockIdx.x * kBX + threadIdx.x;
+  const int j = blockIdx.y * kBY + threadIdx.y;
+  if (i >= nx - 1 || j >= ny - 1) return;
+  const size_t ncell = size_t(nx - 1) * (ny - 1);
+  const size_t c = size_t(j) * (nx - 1) + i;
+  const double rx = double(ny - 1) / double(nx - 1);
+  const double ry = double(nx - 1) / double(ny - 1);
+  const size_t v0 = size_t(j) * nx + i;
+  const double uv[4] = {u[v0], u[v0 + 1], u[v0 + nx], u[v0 + nx + 1]};
+  const double lv[4] = {lam[v0], lam[v0 + 1], lam[v0 + nx], lam[v0 + nx + 1]};
+  double acc = 0.0;
+  double row[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    element_row(jac, ncell, c, a, rx, ry, row);
+    acc += lv[a] * (row[0] * uv[0] + row[1] * uv[1] + row[2] * uv[2] + row[3] * uv[3]);
+  }
+  dK[c] = -acc;
+}
+
+// ---------------------------------------------------------------------------------------
+// Operator-induced interpolation.  Full 9-point couplings of fine point (i,j) read from the
+// symmetric storage: E = W(i+1,j), N = S(i,j+1), NE = SW(i+1,j+1), NW = SE(i-1,j+1).
+// ---------------------------------------------------------------------------------------
+struct Nine {
+  double C, W, E, S, N, SW, SE, NW, NE;
+};
+
+__device__ __forceinline__ Nine load9(const double* __restrict__ S, size_t N, int nx, int i,
+                                      int j) {
+  // only called for interior (i,j): all neighbours exist
+  const size_t v = size_t(j) * nx + i;
+  Nine a;
+  a.C = S[v];
+  a.W = S[N + v];
+  a.E = S[N + v + 1];
+  a.S = S[2 * N + v];
+  a.N = S[2 * N + v + nx];
+  a.SW = S[3 * N + v];
+  a.NE = S[3 * N + v + nx + 1];
+  a.SE = S[4 * N + v];
+  a.NW = S[4 * N + v + nx - 1];
+  return a;
+}
+
+// x-line fine point (i,j) (odd i, even j): weights to (i-1,j) and (i+1,j); 0 on the boundary.
+__device__ __forceinline__ void xline_w(const double* S, size_t N, int nx, int ny, int i, int j,
+                                        double& wW, double& wE) {
+  if (j <= 0 || j >= ny - 1) { wW = wE = 0.0; return; }
+  const Nine a = load9(S, N, nx, i, j);
+  const double d = a.C + a.N + a.S;
+  wW = -(a.W + a.NW + a.SW) / d;
+  wE = -(a.E + a.NE + a.SE) / d;
+}
+
+// y-line fine point (i,j) (even i, odd j): weights to (i,j-1) and (i,j+1).
+__device__ __forceinline__ void yline_w(const double* S, size_t N, int nx, int ny, int i, int j,
+                                        double& wS, double& wN) {
+  if (i <= 0 || i >= nx - 1) { wS = wN = 0.0; return; }
+  const Nine a = load9(S, N, nx, i, j);
+  const double d = a.C + a.W + a.E;
+  wS = -(a.S + a.SW + a.SE) / d;
+  wN = -(a.N + a.NW + a.NE) / d;
+}
+
+__global__ __launch_bounds__(256) void k_interp(const double* __restrict__ S, int nx, int ny,
+                                                double* __restrict__ P) {
+  const int ncx = (nx + 1) / 2, ncy = (ny + 1) / 2;
+  const int I = blockIdx.x * kBX + threadIdx.x;
+  const int J = blockIdx.y * kBY + threadIdx.y;
+  if (I >= ncx || J >= ncy) return;
+  const size_t N = size_t(nx) * ny;
+  const size_t NC = size_t(ncx) * ncy;
+  const size_t c = size_t(J) * ncx + I;
+  double w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (I < ncx - 1) xline_w(S, N, nx, ny, 2 * I + 1, 2 * J, w[0], w[1]);
+  if (J < ncy - 1) yline_w(S, N, nx, ny, 2 * I, 2 * J + 1, w[2], w[3]);
+  if (I < ncx - 1 && J < ncy - 1) {
+    const int i = 2 * I + 1, j = 2 * J + 1;
+    const Nine a = load9(S, N, nx, i, j);
+    double wSw, wNw, wSe, wNe, wWs, wEs, wWn, wEn;
+    yline_w(S, N, nx, ny, i - 1, j, wSw, wNw);   // W neighbour
+    yline_w(S, N, nx, ny, i + 1, j, wSe, wNe);   // E neighbour
+    xline_w(S, N, nx, ny, i, j - 1, wWs, wEs);   // S neighbour
+    xline_w(S, N, nx, ny, i, j + 1, wWn, wEn);   // N neighbour
+    w[4] = -(a.SW + a.W * wSw + a.S * wWs) / a.C;
+    w[5] = -(a.SE + a.E * wSe + a.S * wEs) / a.C;
+    w[6] = -(a.NW + a.W * wNw + a.N * wWn) / a.C;
+    w[7] = -(a.NE + a.E * wNe + a.N * wEn) / a.C;
+  }
+#pragma unroll
+  for (int p = 0; p < 8; ++p) P[p * NC + c] = w[p];
+}
+
+// ---------------------------------------------------------------------------------------
+// Galerkin coarse stencil A_H = P^T A P.  Coarse column (I,J) of P is supported on the fine
+// 3x3 block around (2I,2J); pw() returns its weight at fine offset (a,b) in {-1,0,1}^2.
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ double pw(const double* __restrict__ P, size_t NC, int ncx, int I,
+                                     int J, int a, int b) {
+  const size_t c = size_t(J) * ncx + I;
+  if (a == 0 && b == 0) return 1.0;
+  if (b == 0) return a > 0 ? P[0 * NC + c] : P[1 * NC + c - 1];
+  if (a == 0) return b > 0 ? P[2 * NC + c] : P[3 * NC + c - ncx];
+  if (a > 0 && b > 0) return P[4 * NC + c];
+  if (a < 0 && b > 0) return P[5 * NC + c - 1];
+  if (a > 0 && b < 0) return P[6 * NC + c - ncx];
+  return P[7 * NC + c - ncx - 1];
+}
+
+// fine matrix entry A[(i,j), (i+da, j+db)]
+__device__ __forceinline__ double aentry(const double* __restrict__ S, size_t N, int nx, int i,
+                                         int j, int da, int db) {
+  const size_t v = size_t(j) * nx + i;
+  if (db == 0) {
+    if (da == 0) return S[v];
+    return da < 0 ? S[N + v] : S[N + v + 1];
+  }
+  if (da == 0) return db < 0 ? S[2 * N + v] : S[2 * N + v + nx];
+  if (da < 0 && db < 0) return S[3 * N + v];
+  if (da > 0 && db > 0) return S[3 * N + v + nx + 1];
+  if (da > 0 && db < 0) return S[4 * N + v];
+  return S[4 * N + v + nx - 1];  // da < 0, db > 0
+}
+
+__global__ __launch_bounds__(256) void k_rap(const double* __restrict__ S,
+                                             const double* __restrict__ P, int nx, int ny,
+                                             double* __restrict__ SH) {
+  const int ncx = (nx + 1) / 2, ncy = (ny + 1) / 2;
+  const int I = blockIdx.x * kBX + threadIdx.x;
+  const int J = blockIdx.y * kBY + threadIdx.y;
+  if (I >= ncx || J >= ncy) return;
+  const size_t N = size_t(nx) * ny;
+  const size_t NC = size_t(ncx) * ncy;
+  const size_t c = size_t(J) * ncx + I;
+  // targets: C (0,0), W (-1,0), S (0,-1), SW (-1,-1), SE (1,-1)
+  const int tI[5] = {0, -1, 0, -1, 1};
+  const int tJ[5] = {0, 0, -1, -1, -1};
+  double acc[5] = {0, 0, 0, 0, 0};
+  const bool interior = I > 0 && I < ncx - 1 && J > 0 && J < ncy - 1;
+  if (interior) {
+    bool live[5];
+#pragma unroll
+    for (int t = 0; t < 5; ++t) {
+      const int I2 = I + tI[t], J2 = J + tJ[t];
+      live[t] = I2 > 0 && I2 < ncx - 1 && J2 > 0 && J2 < ncy - 1;
+    }
+    for (int b1 = -1; b1 <= 1; ++b1) {
+      for (int a1 = -1; a1 <= 1; ++a1) {
+        const int fi = 2 * I + a1, fj = 2 * J + b1;
+        const double w1 = pw(P, NC, ncx, I, J, a1, b1);
+        if (w1 == 0.0) continue;
+        for (int db = -1; db <= 1; ++db) {
+          for (int da = -1; da <= 1; ++da) {
+            const double av = aentry(S, N, nx, fi, fj, da, db);
+            if (av == 0.0) continue;
+            const double wa = w1 * av;
+#pragma unroll
+            for (int t = 0; t < 5; ++t) {
+              if (!live[t]) continue;
+              // offset of the fine neighbour from the target coarse point's fine position
+              const int oa = a1 + da - 2 * tI[t];
+              const int ob = b1 + db - 2 * tJ[t];
+              if (oa < -1 || oa > 1 || ob < -1 || ob > 1) continue;
+              acc[t] += wa * pw(P, NC, ncx, I + tI[t], J + tJ[t], oa, ob);
+            }
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 5; ++t) SH[t * NC + c] = acc[t];
+}
+
+// ---------------------------------------------------------------------------------------
+// Coarsest level: gather the m interior unknowns into a dense matrix and factor it in place
+// (lower Cholesky) with one workgroup.  flag[0] = 1 on a non-positive pivot.
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_coarse_factor(const double* __restrict__ S, int nx,
+                                                       int ny, int m, int* __restrict__ idx,
+                                                       double* __restrict__ L,
+                                                       int* __restrict__ flag) {
+  const size_t N = size_t(nx) * ny;
+  const int mx = nx - 2;
+  for (int k = threadIdx.x; k < m; k += blockDim.x) idx[k] = (k / mx + 1) * nx + (k % mx + 1);
+  // dense symmetric matrix over interior unknowns r = (j-1)*mx + (i-1)
+  for (int e = threadIdx.x; e < m * m; e += blockDim.x) {
+    const int r = e / m, c = e % m;
+    const int ir = r % mx + 1, jr = r / mx + 1;
+    const int ic = c % mx + 1, jc = c / mx + 1;
+    const int da = ic - ir, db = jc - jr;
+    double v = 0.0;
+    if (da >= -1 && da <= 1 && db >= -1 && db <= 1) v = aentry(S, N, nx, ir, jr, da, db);
+    L[e] = v;
+  }
+  if (threadIdx.x == 0) flag[0] = 0;
+  __syncthreads();
+  __shared__ double piv;
+  for (int k = 0; k < m; ++k) {
+    if (threadIdx.x == 0) {
+      const double d = L[k * m + k];
+      if (!(d > 0.0)) flag[0] = 1;
+      piv = d > 0.0 ? sqrt(d) : 1.0;
+      L[k * m + k] = piv;
+    }
+    __syncthreads();
+    for (int r = k + 1 + threadIdx.x; r < m; r += blockDim.x) L[r * m + k] /= piv;
+    __syncthreads();
+    const int rem = m - k - 1;
+    for (int e = threadIdx.x; e < rem * rem; e += blockDim.x) {
+      const int r = k + 1 + e / rem, c = k + 1 + e % rem;
+      if (c <= r) L[r * m + c] -= L[r * m + k] * L[c * m + k];
+    }
+    __syncthreads();
+  }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_coarse_solve(const T* __restrict__ b, T* __restrict__ u,
+                                                      int m, const int* __restrict__ idx,
+                                                      const double* __restrict__ L, size_t n) {
+  extern __shared__ double y[];
+  // zero the whole coarsest vector first (boundary ring included)
+  for (size_t v = threadIdx.x; v < n; v += blockDim.x) u[v] = T(0);
+  for (int k = threadIdx.x; k < m; k += blockDim.x) y[k] = double(b[idx[k]]);
+  __syncthreads();
+  // forward: L y = b (column-oriented so that each step is a parallel update)
+  for (int k = 0; k < m; ++k) {
+    if (threadIdx.x == 0) y[k] /= L[k * m + k];
+    __syncthreads();
+    for (int r = k + 1 + threadIdx.x; r < m; r += blockDim.x) y[r] -= L[r * m + k] * y[k];
+    __syncthreads();
+  }
+  // backward: L^T x = y
+  for (int k = m - 1; k >= 0; --k) {
+    if (threadIdx.x == 0) y[k] /= L[k * m + k];
+    __syncthreads();
+    for (int r = threadIdx.x; r < k; r += blockDim.x) y[r] -= L[k * m + r] * y[k];
+    __syncthreads();
+  }
+  for (int k = threadIdx.x; k < m; k += blockDim.x) u[idx[k]] = T(y[k]);
+}
+
+__global__ __launch_bounds__(256) void k_cast(const double* __restrict__ in, float* __restrict__ out,
+                                              size_t n) {
+  for (size_t k = blockIdx.x * size_t(blockDim.x) + threadIdx.x; k < n;
+       k += size_t(gridDim.x) * blockDim.x)
+    out[k] = float(in[k]);
+}
+
+dim3 grid2(int nx, int ny) { return dim3((nx + kBX - 1) / kBX, (ny + kBY - 1) / kBY); }
+
+}  // namespace
+
+dmg_status launch_assemble(const double* jac, const double* K, int nx, int ny, double* S,
+                           hipStream_t s) {
+  k_assemble<<<grid2(nx, ny), dim3(kBX, kBY), 0, s>>>(jac, K, nx, ny, S);
+  return launch_check("assemble");
+}
+
+dmg_status launch_grad_K(const double* jac, const double* lam, const double* u, int nx, int ny,
+                         double* dK, hipStream_t s) {
+  k_grad_K<<<grid2(nx - 1, ny - 1), dim3(kBX, kBY), 0, s>>>(jac, lam, u, nx, ny, dK);
+  return launch_check("grad_K");
+}
+
+dmg_status launch_interp_weights(const double* S, int nx, int ny, double* P, hipStream_t s) {
+  k_interp<<<grid2((nx + 1) / 2, (ny + 1) / 2), dim3(kBX, kBY), 0, s>>>(S, nx, ny, P);
+  return launch_check("interp_weights");
+}
+
+dmg_status launch_rap(const double* S, const double* P, int nx, int ny, double* SH,
+                      hipStream_t s) {
+  k_rap<<<grid2((nx + 1) / 2, (ny + 1) / 2), dim3(kBX, kBY), 0, s>>>(S, P, nx, ny, SH);
+  return launch_check("rap");
+}
+
+dmg_status launch_coarse_factor(const double* S, int nx, int ny, int m, int* idx, double* chol,
+                                int* flag, hipStream_t s) {
+  k_coarse_factor<<<1, 256, 0, s>>>(S, nx, ny, m, idx, chol, flag);
+  return launch_check("coarse_factor");
+}
+
+template <class T>
+dmg_status launch_coarse_solve(const T* b, T* u, int m, const int* idx, const double* chol,
+                               size_t n, hipStream_t s) {
+  k_coarse_solve<T><<<1, 256, sizeof(double) * size_t(m), s>>>(b, u, m, idx, chol, n);
+  return launch_check("coarse_solve");
+}
+template dmg_status launch_coarse_solve<double>(const double*, double*, int, const int*,
+                                                const double*, size_t, hipStream_t);
+template dmg_status launch_coarse_solve<float>(const float*, float*, int, const int*,
+                                               const double*, size_t, hipStream_t);
+
+dmg_status launch_cast(const double* in, float* out, size_t n, hipStream_t s) {
+  const size_t blocks = (n + 255) / 256;
+  k_cast<<<dim3(unsigned(blocks < 65535 ? blocks : 65535)), 256, 0, s>>>(in, out, n);
+  return launch_check("cast");
+}
+
+}  // namespace dmg

@@ -1,0 +1,289 @@
+"""Parity of the HIP library (called through the C ABI) with the float64 CPU oracle.
+
+Tolerances: float64 paths agree with the oracle to 1e-12 relative (per entry for setup data,
+per iterate for V-cycles); float32 refinement reaches the same float64 residual tolerance and
+its distance to the float64 oracle solution is reported and bounded."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import problems as pb
+from oracle import adjoint, boxmg, cycle, fem, transfer
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def dmg():
+    import paper_2509_08109_amd as m
+    m.lib()
+    return m
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def relerr(a, b):
+    den = np.max(np.abs(b))
+    return np.max(np.abs(a - b)) / (den if den > 0 else 1.0)
+
+
+PROBLEMS = {
+    "identity33": lambda: pb.identity(33),
+    "annulus65": lambda: pb.quarter_annulus(65),
+    "star129": lambda: pb.star(129, seed=1),
+    "star65x129": lambda: pb.star(65, seed=1, ny=129),
+}
+
+
+@pytest.fixture(scope="module", params=list(PROBLEMS))
+def case(request, dmg):
+    prob = PROBLEMS[request.param]()
+    S_or = fem.assemble_stencil(prob.jac, prob.K, prob.nx, prob.ny)
+    levels = boxmg.build_hierarchy(S_or)
+    return prob, S_or, levels
+
+
+def oracle_P_planes(P, nx, ny):
+    """The oracle's sparse P in the library's 8-plane layout."""
+    ncx, ncy = (nx + 1) // 2, (ny + 1) // 2
+    out = np.zeros((8, ncy, ncx))
+    P = P.tocsr()
+    for J in range(ncy):
+        for I in range(ncx):
+            c = J * ncx + I
+
+            def get(i, j, cc):
+                if 0 <= i < nx and 0 <= j < ny:
+                    return P[j * nx + i, cc]
+                return 0.0
+            if I < ncx - 1:
+                out[0, J, I] = get(2 * I + 1, 2 * J, c)
+                out[1, J, I] = get(2 * I + 1, 2 * J, c + 1)
+            if J < ncy - 1:
+                out[2, J, I] = get(2 * I, 2 * J + 1, c)
+                out[3, J, I] = get(2 * I, 2 * J + 1, c + ncx)
+            if I < ncx - 1 and J < ncy - 1:
+                out[4, J, I] = get(2 * I + 1, 2 * J + 1, c)
+                out[5, J, I] = get(2 * I + 1, 2 * J + 1, c + 1)
+                out[6, J, I] = get(2 * I + 1, 2 * J + 1, c + ncx)
+                out[7, J, I] = get(2 * I + 1, 2 * J + 1, c + ncx + 1)
+    return out
+
+
+def test_assembly_matches_oracle(dmg, case):
+    prob, S_or, _ = case
+    S = dmg.assemble_stencil(dev(prob.jac), dev(prob.K))
+    assert relerr(host(S), S_or) <= TOL
+
+
+def test_hierarchy_matches_oracle(dmg, case):
+    prob, S_or, levels = case
+    h = dmg.Hierarchy(dev(S_or))
+    assert h.num_levels == len(levels)
+    for l, L in enumerate(levels):
+        S, P = h.level(l)
+        assert relerr(host(S), L.S) <= TOL, f"stencil level {l}"
+        if L.P is not None:
+            assert relerr(host(P), oracle_P_planes(L.P, L.nx, L.ny)) <= TOL, f"P level {l}"
+    h.close()
+
+
+def test_vcycle_iterates_match_oracle(dmg, case):
+    prob, S_or, levels = case
+    h = dmg.Hierarchy(dev(S_or))
+    orc = cycle.Oracle(levels)
+    b = dev(prob.b)
+    u = torch.zeros_like(b)
+    uo = np.zeros(prob.nx * prob.ny)
+    bo = prob.b.ravel().copy()
+    for k in range(8):
+        h.vcycle(u, b)
+        orc.vcycle(uo, bo)
+        err = np.linalg.norm(host(u).ravel() - uo) / np.linalg.norm(uo)
+        assert err <= TOL, f"iterate {k + 1}: {err:.3e}"
+    h.close()
+
+
+def test_solve_matches_oracle(dmg, case):
+    prob, S_or, levels = case
+    h = dmg.Hierarchy(dev(S_or))
+    u, k, rel, hist = h.solve(dev(prob.b), rtol=1e-10)
+    uo, ko, histo, _ = cycle.solve(cycle.Oracle(levels), prob.b, rtol=1e-10)
+    assert rel <= 1e-10 and k == ko
+    # late relative residuals (~1e-10) carry rounding noise of order eps * cond-free 1e-15
+    assert np.allclose(hist, histo, rtol=1e-6, atol=1e-13)
+    assert np.linalg.norm(host(u) - uo) / np.linalg.norm(uo) <= TOL
+    h.close()
+
+
+def test_graph_and_eager_solves_are_identical(dmg):
+    prob = pb.star(129, seed=1)
+    S = dmg.assemble_stencil(dev(prob.jac), dev(prob.K))
+    b = dev(prob.b)
+    out = []
+    for g in (0, 1):
+        h = dmg.Hierarchy(S, use_graph=g)
+        u, k, rel, _ = h.solve(b, rtol=1e-10)
+        # a second solve on the same arrays replays the captured graph
+        u2, k2, rel2, _ = h.solve(b, rtol=1e-10)
+        assert k == k2 and torch.equal(u, u2)
+        out.append((host(u), k))
+        h.close()
+    assert out[0][1] == out[1][1] and np.array_equal(out[0][0], out[1][0])
+
+
+@pytest.mark.parametrize("inner", [1, 2])
+def test_fp32_refinement(dmg, inner):
+    prob = pb.star(257, seed=2)
+    S_or = fem.assemble_stencil(prob.jac, prob.K, prob.nx, prob.ny)
+    levels = boxmg.build_hierarchy(S_or)
+    h = dmg.Hierarchy(dev(S_or), precision=dmg.DMG_FP32_IR, inner_cycles=inner)
+    x, k, rel, hist = h.solve(dev(prob.b), rtol=1e-10)
+    assert rel <= 1e-10
+    xo, ko, histo, _ = cycle.solve_ir(cycle.Oracle(levels), cycle.Oracle(levels, np.float32), prob.b,
+                                      1e-10, inner=inner)
+    assert abs(k - ko) <= 1
+    u64, _, _, _ = cycle.solve(cycle.Oracle(levels), prob.b, 1e-10)
+    err = np.linalg.norm(host(x) - u64) / np.linalg.norm(u64)
+    # both are 1e-10-residual solutions of one system; their distance is bounded by cond * 1e-10
+    assert err < 1e-7, err
+    h.close()
+
+
+def test_grad_K_matches_oracle(dmg):
+    prob = pb.star(65, seed=4)
+    rng = np.random.default_rng(0)
+    lam = np.zeros((65, 65)); lam[1:-1, 1:-1] = rng.normal(size=(63, 63))
+    u = np.zeros((65, 65)); u[1:-1, 1:-1] = rng.normal(size=(63, 63))
+    g = dmg.grad_K(dev(prob.jac), dev(lam), dev(u))
+    go = adjoint.grad_K(prob.jac, lam, u, 65, 65)
+    assert relerr(host(g), go) <= TOL
+
+
+def test_diffsolve_gradients(dmg):
+    n = 33
+    prob = pb.star(n, seed=4)
+    jac = dev(prob.jac)
+    K = dev(prob.K).requires_grad_(True)
+    b = dev(prob.b).requires_grad_(True)
+    t = dev(prob.target)
+
+    def J_of(Kv, bv):
+        u = dmg.DiffSolve.apply(Kv, bv, jac, 1e-13)
+        d = (u - t)[1:-1, 1:-1]
+        return 0.5 * (d * d).sum()
+
+    J = J_of(K, b)
+    J.backward()
+    # oracle adjoint gradient
+    S_or = fem.assemble_stencil(prob.jac, prob.K, n, n)
+    orc = cycle.Oracle(boxmg.build_hierarchy(S_or))
+    uo, _, _, _ = cycle.solve(orc, prob.b, 1e-13)
+    lo, _, _, _ = cycle.solve(orc, adjoint.objective_grad_u(uo, prob.target), 1e-13)
+    gKo = adjoint.grad_K(prob.jac, lo, uo, n, n)
+    assert np.linalg.norm(host(K.grad) - gKo) / np.linalg.norm(gKo) <= 1e-6
+    assert np.linalg.norm(host(b.grad) - lo) / np.linalg.norm(lo) <= 1e-6
+    # central differences along random directions
+    zK, zb = pb.directions(4, 4, (n - 1, n - 1), (n, n))
+    with torch.no_grad():
+        for d in range(4):
+            dK = dev(zK[d] * prob.K)
+            db = dev(zb[d])
+            eps = 1e-5
+            fdK = (J_of(K + eps * dK, b) - J_of(K - eps * dK, b)).item() / (2 * eps)
+            fdb = (J_of(K, b + eps * db) - J_of(K, b - eps * db)).item() / (2 * eps)
+            adK = float((K.grad * dK).sum())
+            adb = float((b.grad * db).sum())
+            assert abs(fdK - adK) <= 1e-6 * max(abs(adK), 1e-12)
+            assert abs(fdb - adb) <= 1e-6 * max(abs(adb), 1e-12)
+
+
+def test_transfer_matches_oracle(dmg):
+    mp = pb.Star.random(pb.streams(1)[0])
+    n = 33
+    mesh = pb.lattice_mesh(mp, 45, np.random.default_rng(7))
+    T = dmg.Transfer(mesh.xy_c, mesh.xy_p, mesh.tris, mesh.dof, n, n, nq=4)
+    M = transfer.p1_mass(mesh.xy_p, mesh.tris, mesh.dof)
+    Co = transfer.coupled_mass(mesh.xy_c, mesh.xy_p, mesh.tris, mesh.dof, n, n, nq=4)
+    nnzC, nnzM = T.nnz()
+    assert nnzC == Co.nnz and nnzM == M.nnz
+    rng = np.random.default_rng(3)
+    uc = np.zeros((n, n)); uc[1:-1, 1:-1] = rng.normal(size=(n - 2, n - 2))
+    rp = rng.normal(size=mesh.nv)
+    up = T.from_grid(dev(uc))
+    rc = T.to_grid(dev(rp))
+    assert relerr(host(up), transfer.from_grid(M, Co, uc)) <= TOL
+    assert relerr(host(rc), transfer.to_grid(M, Co, rp * mesh.dof, n, n)) <= TOL
+    T.close()
+
+
+def test_batch_matches_single_solves(dmg):
+    probs = [pb.star(n, seed=10 + k) for k, n in enumerate((33, 65, 129, 65))]
+    Ss = [dmg.assemble_stencil(dev(p.jac), dev(p.K)) for p in probs]
+    bs = [dev(p.b) for p in probs]
+    bt = dmg.BatchSolver(Ss)
+    us, its, rels = bt.solve(bs, rtol=1e-10)
+    for S, b, u, k, r in zip(Ss, bs, us, its, rels):
+        h = dmg.Hierarchy(S)
+        u1, k1, r1, _ = h.solve(b, rtol=1e-10)
+        assert k == k1 and r <= 1e-10
+        assert torch.equal(u, u1)
+        h.close()
+    bt.close()
+
+
+# ---- edge cases -------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [3, 5, 9])
+def test_tiny_grids(dmg, n):
+    prob = pb.star(n, seed=1)
+    S_or = fem.assemble_stencil(prob.jac, prob.K, n, n)
+    levels = boxmg.build_hierarchy(S_or)
+    h = dmg.Hierarchy(dev(S_or))
+    u, k, rel, _ = h.solve(dev(prob.b), rtol=1e-10)
+    uo, ko, _, _ = cycle.solve(cycle.Oracle(levels), prob.b, 1e-10)
+    assert k == ko and np.linalg.norm(host(u) - uo) <= TOL * max(np.linalg.norm(uo), 1e-300)
+    h.close()
+
+
+def test_coarsest_dense_cholesky_larger(dmg):
+    prob = pb.star(65, seed=1, ny=129)
+    S_or = fem.assemble_stencil(prob.jac, prob.K, 65, 129)
+    levels = boxmg.build_hierarchy(S_or, coarsest_n=9)
+    h = dmg.Hierarchy(dev(S_or), coarsest_n=9)
+    assert h.num_levels == len(levels)
+    u, k, rel, _ = h.solve(dev(prob.b), rtol=1e-10)
+    uo, ko, _, _ = cycle.solve(cycle.Oracle(levels), prob.b, 1e-10)
+    assert k == ko and np.linalg.norm(host(u) - uo) / np.linalg.norm(uo) <= TOL
+    h.close()
+
+
+def test_zero_rhs_and_failures(dmg):
+    prob = pb.star(33, seed=1)
+    S = dmg.assemble_stencil(dev(prob.jac), dev(prob.K))
+    h = dmg.Hierarchy(S)
+    u = torch.ones((33, 33), dtype=torch.float64, device="cuda")
+    u, k, rel, _ = h.solve(torch.zeros_like(u), u=u)
+    assert k == 0 and torch.count_nonzero(u) == 0
+    with pytest.raises(dmg.DmgError) as ei:
+        h.solve(dev(prob.b), rtol=1e-10, max_iters=2)
+    assert ei.value.code == 6
+    bad = dev(prob.b)
+    bad[5, 5] = float("nan")
+    with pytest.raises(dmg.DmgError) as ei:
+        h.solve(bad)
+    assert ei.value.code == 5
+    h.close()
+    Sneg = -S
+    with pytest.raises(dmg.DmgError) as ei:
+        dmg.Hierarchy(Sneg)
+    assert ei.value.code == 4
