@@ -1,0 +1,251 @@
+#!/usr/bin/env python3
+"""Throughput of the mapped structured multigrid solve on one MI355X.
+
+Workload (default): a 1025 x 1025 logical grid of a star-shaped domain (conformal square->disk
+map composed with a radial star deformation, boundary radius 1 + sum_{k<=8} a_k cos(k theta +
+phi_k)), log-normal K (sigma 1, correlation length 0.1), b ~ U(-1,1), homogeneous Dirichlet,
+float64 V(1,1) cycles from u = 0 to ||b - A u|| <= 1e-10 ||b||.  All inputs are synthetic and
+seeded; they are generated and copied to the GPU before timing.
+
+One step = the whole hot path on that input: stencil assembly from the map Jacobians,
+hierarchy setup (operator-induced interpolation, Galerkin levels, coarsest factor), and the
+solve.  value = interior DoF x steps / wall time.
+
+Extra legs (same JSON line): the float32-refined solve at the same size, the 4097 x 4097 size
+in float64 and float32-refined form, the roofline of the dominant kernel (timed with HIP events
+on its own stream), and the float64 CPU oracle timed on the host (cpu_baseline).
+
+    python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--n 1025] [--no-c3] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DoF/s solved to 1e-10 rel. residual (FP64 vs FP32-refined) + % HBM peak"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_inputs(n: int, seed: int, device):
+    import torch
+
+    import problems as pb
+    prob = pb.star(n, seed=seed, device="cuda" if device.type == "cuda" else None)
+    as_dev = lambda x: torch.as_tensor(x, dtype=torch.float64, device=device).contiguous()
+    return prob, as_dev(prob.jac), as_dev(prob.K), as_dev(prob.b)
+
+
+def run_leg(dmg, jac, K, b, steps: int, warmup: int, precision: int, inner: int = 1):
+    """Times `steps` whole steps (assemble + refresh + solve) after `warmup` untimed ones."""
+    import torch
+    n_y, n_x = b.shape
+    S = torch.empty((5, n_y, n_x), dtype=torch.float64, device=b.device)
+    dmg.assemble_stencil(jac, K, out=S)
+    h = dmg.Hierarchy(S, precision=precision, inner_cycles=inner)
+    u = torch.zeros_like(b)
+    info = {}
+
+    def step():
+        dmg.assemble_stencil(jac, K, out=S)
+        h.refresh(S)
+        u.zero_()
+        _, k, rel, _ = h.solve(b, u=u, rtol=1e-10)
+        info["iters"], info["relres"] = k, rel
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    info["wall_s"] = wall
+    info["gpu_ms"] = ev0.elapsed_time(ev1)
+    # solve-only rate on the prepared hierarchy (same u, b, stream: graph replay)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        u.zero_()
+        h.solve(b, u=u, rtol=1e-10)
+    torch.cuda.synchronize()
+    info["solve_wall_s"] = time.perf_counter() - t0
+    return h, u, info
+
+
+def kernel_roofline(dmg, h, b, reps: int = 20):
+    """Average duration of the level-0 fused pre and post kernels (HIP events on the stream the
+    library launches on) and their algorithmic HBM bytes."""
+    import torch
+    n_y, n_x = b.shape
+    nc = ((n_x + 1) // 2) * ((n_y + 1) // 2)
+    # algorithmic bytes per launch: read S(5) u b, P(8 per coarse point), e or write b_H
+    # (1 per coarse point); write u.  = 8 (8 N + 9 N_c)
+    bytes_per_launch = 8.0 * (8 * n_x * n_y + 9 * nc)
+    u = torch.zeros_like(b)
+    out = {}
+    for kind, name in ((0, "strip_pre"), (1, "strip_post")):
+        for _ in range(3):
+            h.sweep(0, kind, u, b)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            h.sweep(0, kind, u, b)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = dict(avg_us=1e3 * ms, gbs=bytes_per_launch / (ms * 1e-3) / 1e9)
+    dom = max(out, key=lambda k: out[k]["avg_us"])
+    achieved = out[dom]["gbs"]
+    return dict(bound="hbm", kernel=f"k_strip<double,{dom.split('_')[1]}> level 0", achieved=round(achieved, 1),
+                peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                bytes_per_launch=bytes_per_launch, avg_us=round(out[dom]["avg_us"], 2),
+                kernels={k: {kk: round(vv, 2) for kk, vv in v.items()} for k, v in out.items()})
+
+
+CPU_SNIPPET = r"""
+import json, sys, time
+sys.path.insert(0, {root!r})
+import numpy as np
+import problems as pb
+from oracle import boxmg, cycle, fem
+prob = pb.star({n}, seed={seed})
+reps, t_total, iters = 0, 0.0, 0
+while reps < {max_reps} and (reps == 0 or t_total < {budget}):
+    t0 = time.perf_counter()
+    S = fem.assemble_stencil(prob.jac, prob.K, prob.nx, prob.ny)
+    orc = cycle.Oracle(boxmg.build_hierarchy(S))
+    u, k, hist, _ = cycle.solve(orc, prob.b, 1e-10)
+    t_total += time.perf_counter() - t0
+    reps += 1
+    iters = k
+print(json.dumps(dict(reps=reps, seconds=t_total, iters=iters, relres=hist[-1],
+                      dof=(prob.nx - 2) * (prob.ny - 2))))
+"""
+
+
+def cpu_baseline(n: int, seed: int, budget: float = 15.0):
+    """The float64 oracle, single-threaded, on the same workload (whole steps until ~budget s)."""
+    env = dict(os.environ)
+    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
+        env[k] = "1"
+    env["CUDA_VISIBLE_DEVICES"] = ""
+    env["HIP_VISIBLE_DEVICES"] = ""
+    code = CPU_SNIPPET.format(root=ROOT, n=n, seed=seed, max_reps=5, budget=budget)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
+    if r.returncode != 0:
+        raise RuntimeError(r.stderr[-2000:])
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    return dict(value=d["dof"] * d["reps"] / d["seconds"], unit="DoF/s", cores=1, kind="oracle",
+                sample=f"{d['reps']} whole step(s) (assemble + setup + solve to 1e-10, {d['iters']} V-cycles) "
+                       f"of the {n}x{n} workload, float64 NumPy/SciPy, one thread",
+                seconds=round(d["seconds"], 2), host_cpus=os.cpu_count())
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1025)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--no-c3", action="store_true", help="skip the 4097 x 4097 legs")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2509_08109_amd as dmg
+    dmg.lib()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(dev)
+    torch.cuda.set_stream(stream)   # graph capture needs a non-default stream
+
+    log(f"generating the {args.n}x{args.n} star workload")
+    prob, jac, K, b = make_inputs(args.n, args.seed, dev)
+    dof = (args.n - 2) ** 2
+    log("fp64 leg")
+    h, u, i64 = run_leg(dmg, jac, K, b, args.steps, args.warmup, dmg.DMG_FP64)
+    levels, gc, oc = h.stats()
+    log(f"fp64: {i64['iters']} cycles, {1e3 * i64['wall_s'] / args.steps:.2f} ms/step")
+    roof = kernel_roofline(dmg, h, b)
+    log(f"roofline: {roof['kernel']} {roof['avg_us']} us, {roof['achieved']} GB/s")
+    u64 = u.clone()
+    h.close()
+    log("fp32-refined leg")
+    h32, x32, i32 = run_leg(dmg, jac, K, b, args.steps, args.warmup, dmg.DMG_FP32_IR)
+    err32 = float(torch.linalg.norm(x32 - u64) / torch.linalg.norm(u64))
+    h32.close()
+    value = dof * args.steps / i64["wall_s"]
+    res = {
+        "metric": METRIC, "value": round(value, 1), "unit": "DoF/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * i64["wall_s"] / args.steps, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded star-domain map Jacobians, log-normal K, uniform RHS)",
+        "config": {"workload": f"{args.n}x{args.n} star domain, log-normal K, FP64 V(1,1) to 1e-10 rel. residual; "
+                               "step = assemble + setup + solve", "grid": [args.n, args.n],
+                   "dof": dof, "levels": levels, "grid_complexity": round(gc, 4),
+                   "operator_complexity": round(oc, 4), "seed": args.seed},
+        "iters": i64["iters"], "relres": i64["relres"],
+        "solve_only_dof_per_s": round(dof * args.steps / i64["solve_wall_s"], 1),
+        "fp32_refined": {"value": round(dof * args.steps / i32["wall_s"], 1), "unit": "DoF/s",
+                         "outer_steps": i32["iters"], "relres": i32["relres"],
+                         "solve_only_dof_per_s": round(dof * args.steps / i32["solve_wall_s"], 1),
+                         "rel_err_vs_fp64_solution": err32,
+                         "speedup_vs_fp64": round(i64["wall_s"] / i32["wall_s"], 3)},
+        "roofline": roof,
+    }
+    del jac, K, b, u, u64, x32
+    torch.cuda.empty_cache()
+    if not args.no_c3:
+        n3 = 4097
+        log(f"generating the {n3}x{n3} star workload")
+        prob3, jac3, K3, b3 = make_inputs(n3, 2, dev)
+        dof3 = (n3 - 2) ** 2
+        st3 = max(2, args.steps // 2)
+        h3, u3, j64 = run_leg(dmg, jac3, K3, b3, st3, 1, dmg.DMG_FP64)
+        roof3 = kernel_roofline(dmg, h3, b3, reps=10)
+        u3_64 = u3.clone()
+        h3.close()
+        h3b, x3, j32 = run_leg(dmg, jac3, K3, b3, st3, 1, dmg.DMG_FP32_IR)
+        h3b.close()
+        res["c3_4097"] = {
+            "fp64": {"value": round(dof3 * st3 / j64["wall_s"], 1), "solve_only_dof_per_s":
+                     round(dof3 * st3 / j64["solve_wall_s"], 1), "iters": j64["iters"], "relres": j64["relres"]},
+            "fp32_refined": {"value": round(dof3 * st3 / j32["wall_s"], 1), "solve_only_dof_per_s":
+                             round(dof3 * st3 / j32["solve_wall_s"], 1), "outer_steps": j32["iters"],
+                             "relres": j32["relres"],
+                             "rel_err_vs_fp64_solution": float(torch.linalg.norm(x3 - u3_64) / torch.linalg.norm(u3_64))},
+            "solve_speedup_fp32_refined": round(j64["solve_wall_s"] / j32["solve_wall_s"], 3),
+            "roofline": roof3, "steps": st3,
+        }
+        del jac3, K3, b3, u3, x3, u3_64
+    if not args.no_cpu:
+        log("cpu baseline (oracle)")
+        res["cpu_baseline"] = cpu_baseline(args.n, args.seed)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

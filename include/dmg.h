@@ -106,6 +106,10 @@ dmg_status dmg_workspace_bytes(int32_t nx, int32_t ny, const dmg_options* opts, 
 dmg_status dmg_setup(const double* S, int32_t nx, int32_t ny, const dmg_options* opts,
                      void* workspace, size_t ws_bytes, hipStream_t stream, dmg_hier** out);
 void dmg_destroy(dmg_hier* h);
+/* Recompute the whole hierarchy of h from a new fine stencil S of the same dims, in place (same
+ * workspace, options and launch shapes).  Used when coefficients change (time stepping,
+ * gradient steps: the hierarchy is recomputed rather than stored).  Synchronises `stream`. */
+dmg_status dmg_refresh(dmg_hier* h, const double* S, hipStream_t stream);
 
 /* Inspection of level l (0 = finest): dims and device pointers to its float64 stencil
  * [5][ny][nx] and (l < levels-1) interpolation weights [8][ny_c][nx_c] where entry (I,J) of
@@ -123,6 +127,16 @@ dmg_status dmg_stats(const dmg_hier* h, int32_t* levels, double* grid_complexity
  * Four-colour Gauss-Seidel smoothing, r = b - A u, b_H = P^T r, zero coarse initial guess,
  * recursion, coarsest Cholesky solve, u += P e_H, post-smoothing.  float64 only. */
 dmg_status dmg_vcycle(dmg_hier* h, double* u, const double* b, hipStream_t stream);
+/* One fused sweep kernel on `level` (float64), in the launch shape dmg_vcycle uses:
+ * kind 0 = pre-smoothing sweep starting from u, followed by the restriction P^T (b - A u') into
+ *          the next level's right-hand side;
+ * kind 1 = post-smoothing sweep starting from u + P e (e = the next level's current
+ *          correction).
+ * The kernels work out of place: u is only read and the swept iterate u' goes to the level's
+ * second iterate buffer inside the workspace.  u, b: [ny_l][nx_l] device arrays of that level.
+ * level must be above the coarse tail (max(nx,ny) > 65); DMG_ERR_INVALID_ARG otherwise. */
+dmg_status dmg_sweep(dmg_hier* h, int32_t level, int32_t kind, double* u, const double* b,
+                     hipStream_t stream);
 /* ||b - A u||_2 over interior vertices (deterministic fixed-order reduction).  Synchronous. */
 dmg_status dmg_residual_norm(dmg_hier* h, const double* u, const double* b, double* norm,
                              hipStream_t stream);

@@ -47,10 +47,14 @@ class OracleLevel:
 
 class Oracle:
     """A hierarchy prepared for cycling in ``dtype``; the coarsest interior system is factored
-    once by dense Cholesky in float64."""
+    once by dense Cholesky in float64.  ``pre``/``post`` are the colour orders of one pre/post
+    sweep and ``nu_pre``/``nu_post`` the sweep counts of a V(nu_pre, nu_post) cycle."""
 
-    def __init__(self, levels, dtype=np.float64):
+    def __init__(self, levels, dtype=np.float64, pre=None, post=None, nu_pre=1, nu_post=1):
         self.dtype = np.dtype(dtype)
+        self.pre = tuple(PRE_ORDER if pre is None else pre)
+        self.post = tuple(POST_ORDER if post is None else post)
+        self.nu_pre, self.nu_post = nu_pre, nu_post
         self.levels = [OracleLevel(L, self.dtype) for L in levels]
         last = levels[-1]
         inner = colour_masks(last.nx, last.ny)
@@ -93,13 +97,15 @@ class Oracle:
         if l == len(self.levels) - 1:
             u[:] = self.coarse_solve(b)
             return u
-        self.smooth(l, u, b, PRE_ORDER)
+        for _ in range(self.nu_pre):
+            self.smooth(l, u, b, self.pre)
         r = self.residual(l, u, b)
         bc = self.restrict(l, r)
         ec = np.zeros_like(bc)
         self.vcycle(ec, bc, l + 1)
         u += self.prolong(l, ec)
-        self.smooth(l, u, b, POST_ORDER)
+        for _ in range(self.nu_post):
+            self.smooth(l, u, b, self.post)
         return u
 
 

@@ -120,6 +120,27 @@ class Hierarchy:
             P = self._view(pp.value, 8 * ncx * ncy).view(8, ncy, ncx)
         return S, P
 
+    def refresh(self, S: torch.Tensor) -> None:
+        """Recompute the hierarchy in place from a new fine stencil of the same dims."""
+        _lib.check(lib().dmg_refresh(self._h, _dev(S, (5, self.ny, self.nx), "S"), _stream(self.device)))
+
+    @property
+    def strip_levels(self) -> int:
+        """Levels handled by the fused strip kernels (the rest run in the coarse-tail kernel)."""
+        n = 0
+        for l in range(self.num_levels):
+            S, _ = self.level(l)
+            if max(S.shape[1], S.shape[2]) > 65:
+                n += 1
+        return n
+
+    def sweep(self, level: int, kind: int, u: torch.Tensor, b: torch.Tensor) -> None:
+        """One fused sweep kernel on a level (kind 0: pre + restriction, 1: prolongation + post)."""
+        S, _ = self.level(level)
+        shp = (S.shape[1], S.shape[2])
+        _lib.check(lib().dmg_sweep(self._h, level, kind, _dev(u, shp, "u"), _dev(b, shp, "b"),
+                                   _stream(self.device)))
+
     # -- cycles and solves ---------------------------------------------------------------
     def vcycle(self, u: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
         shp = (self.ny, self.nx)

@@ -46,6 +46,11 @@ dmg_status check_options(const dmg_options* o) {
       seen |= 1 << ord[k];
     }
   }
+  for (const int32_t* ord : {o->pre_order, o->post_order})
+    if ((ord[0] >> 1) != (ord[1] >> 1))
+      return fail(DMG_ERR_UNSUPPORTED,
+                  "colour orders must visit both colours of one row parity first "
+                  "(e.g. 0,1,2,3 or 3,2,1,0)");
   if (o->coarsest_n < 3) return fail(DMG_ERR_INVALID_ARG, "coarsest_n must be >= 3");
   if (o->precision != DMG_FP64 && o->precision != DMG_FP32_IR)
     return fail(DMG_ERR_INVALID_ARG, "unknown precision %d", o->precision);
@@ -68,17 +73,43 @@ dmg_status level_dims(int nx, int ny, int coarsest_n, std::vector<std::pair<int,
   return DMG_OK;
 }
 
+// Launch shape of the strip kernels on an nx x ny level: enough workgroups to fill the chip
+// with as few recomputed halo rows/columns as possible.  tile_rows overrides the segment height.
+StripConfig default_strip_config(int nx, int ny, const dmg_options& o) {
+  StripConfig c;
+  c.bw = nx >= 257 ? 128 : 64;
+  int ns = 0, nseg = 0;
+  c.seg_h = 16;
+  for (int h = 128; h >= 16; h >>= 1) {
+    strip_blocks(nx, ny, c.bw, h, &ns, &nseg);
+    if (ns * nseg >= 1024) {
+      c.seg_h = h;
+      break;
+    }
+  }
+  if (o.tile_rows >= 2) c.seg_h = o.tile_rows & ~1;
+  while (strip_blocks(nx, ny, c.bw, c.seg_h, &ns, &nseg) > kMaxPartials) c.seg_h *= 2;
+  return c;
+}
+
 // Lays out a hierarchy in the arena (sizing pass when a.base is null).
 void carve(dmg_hier& h, Arena& a, const std::vector<std::pair<int, int>>& dims,
            const dmg_options& o) {
   const bool fp32 = o.precision == DMG_FP32_IR;
   h.L.assign(dims.size(), Level{});
+  h.tail = int(dims.size()) - 1;
+  while (h.tail > 0 && std::max(dims[h.tail - 1].first, dims[h.tail - 1].second) <= kTailMaxN)
+    --h.tail;
   for (size_t l = 0; l < dims.size(); ++l) {
     Level& L = h.L[l];
     L.nx = dims[l].first;
     L.ny = dims[l].second;
     const size_t n = L.n();
     L.S = a.take<double>(5 * n);
+    if (int(l) < h.tail) {
+      L.t = a.take<double>(n);
+      if (fp32) L.t32 = a.take<float>(n);
+    }
     if (l + 1 < dims.size()) {
       const size_t nc = size_t(dims[l + 1].first) * dims[l + 1].second;
       L.P = a.take<double>(8 * nc);
@@ -102,7 +133,8 @@ void carve(dmg_hier& h, Arena& a, const std::vector<std::pair<int, int>>& dims,
   h.m_coarse = (c.first - 2) * (c.second - 2);
   h.coarse_idx = a.take<int>(size_t(h.m_coarse));
   h.chol = a.take<double>(size_t(h.m_coarse) * h.m_coarse);
-  h.partials = a.take<double>(kReduceBlocks);
+  h.partials = a.take<double>(kMaxPartials);
+  for (size_t l = 0; l < dims.size(); ++l) h.L[l].cfg = default_strip_config(dims[l].first, dims[l].second, o);
   h.scalars = a.take<double>(16);
   h.flag = a.take<int>(16);
   if (fp32) h.r64 = a.take<double>(size_t(dims[0].first) * dims[0].second);
@@ -112,6 +144,7 @@ template <class T>
 struct Prec;
 template <>
 struct Prec<double> {
+  static double* t(const Level& L) { return L.t; }
   static const double* S(const Level& L) { return L.S; }
   static const double* P(const Level& L) { return L.P; }
   static double* u(const Level& L) { return L.u; }
@@ -120,6 +153,7 @@ struct Prec<double> {
 };
 template <>
 struct Prec<float> {
+  static float* t(const Level& L) { return L.t32; }
   static const float* S(const Level& L) { return L.S32; }
   static const float* P(const Level& L) { return L.P32; }
   static float* u(const Level& L) { return L.u32; }
@@ -127,43 +161,101 @@ struct Prec<float> {
   static float* r(const Level& L) { return L.r32; }
 };
 
+// Strip-kernel colour-order parameters: row parity smoothed first and the column parity
+// smoothed first on each row parity.
+struct OrderParams {
+  int pf, cA, cB;
+};
+OrderParams order_params(const int32_t* ord) {
+  return OrderParams{ord[0] >> 1, ord[0] & 1, ord[2] & 1};
+}
+
 template <class T>
-dmg_status smooth_sweeps(const Level& L, const T* S, T* u, const T* b, int nu,
-                         const int32_t* order, hipStream_t s) {
-  for (int k = 0; k < nu; ++k)
-    for (int c = 0; c < 4; ++c) DMG_CHECK(launch_smooth<T>(S, u, b, L.nx, L.ny, order[c], s));
-  return DMG_OK;
+dmg_status tail_launch(dmg_hier* h, T* u_top, const T* b_top, hipStream_t s, bool u0_zero) {
+  using Pr = Prec<T>;
+  TailSpec<T> sp;
+  const int nl = int(h->L.size());
+  sp.nlev = nl - h->tail;
+  for (int l = h->tail; l < nl; ++l) {
+    const Level& L = h->L[l];
+    const int k = l - h->tail;
+    sp.S[k] = Pr::S(L);
+    sp.u[k] = l == 0 ? u_top : Pr::u(L);
+    sp.b[k] = l == 0 ? const_cast<T*>(b_top) : Pr::b(L);
+    sp.r[k] = Pr::r(L);
+    sp.P[k] = Pr::P(L);
+    sp.nx[k] = L.nx;
+    sp.ny[k] = L.ny;
+  }
+  sp.zero_top = h->tail > 0 || u0_zero;
+  sp.m = h->m_coarse;
+  sp.idx = h->coarse_idx;
+  sp.chol = h->chol;
+  for (int k = 0; k < 4; ++k) {
+    sp.pre[k] = h->opts.pre_order[k];
+    sp.post[k] = h->opts.post_order[k];
+  }
+  sp.nu_pre = h->opts.nu_pre;
+  sp.nu_post = h->opts.nu_post;
+  return launch_tail<T>(sp, s);
 }
 
 // One V-cycle in precision T on level-0 arrays (u0, b0); coarse levels use hierarchy arrays.
+// Levels above the tail: fused pre kernels on the way down (the first sweep of a coarse level
+// starts from u = 0; u0_zero says the same of level 0), fused post kernels on the way up.  The
+// strip kernels are out of place: each level alternates between its two iterate buffers and
+// the cycle ends with the level-0 iterate back in u0.  partials (optional) receives the
+// squared-residual partials of the final level-0 iterate.
 template <class T>
-dmg_status vcycle_impl(dmg_hier* h, T* u0, const T* b0, hipStream_t s) {
+dmg_status vcycle_impl(dmg_hier* h, T* u0, const T* b0, hipStream_t s, double* partials = nullptr,
+                       bool u0_zero = false) {
   using Pr = Prec<T>;
-  const int nl = int(h->L.size());
   const dmg_options& o = h->opts;
-  for (int l = 0; l < nl - 1; ++l) {
+  const OrderParams pre = order_params(o.pre_order), post = order_params(o.post_order);
+  T* cur[kMaxLevels];
+  auto other = [&](int l, const T* x) -> T* {
+    T* a = l == 0 ? u0 : Pr::u(h->L[l]);
+    return x == a ? Pr::t(h->L[l]) : a;
+  };
+  for (int l = 0; l < h->tail; ++l) {
     const Level& L = h->L[l];
-    T* u = l == 0 ? u0 : Pr::u(L);
     const T* b = l == 0 ? b0 : Pr::b(L);
-    if (l > 0) DMG_CHECK(launch_fill<T>(u, T(0), L.n(), s));
-    DMG_CHECK(smooth_sweeps<T>(L, Pr::S(L), u, b, o.nu_pre, o.pre_order, s));
-    DMG_CHECK(launch_residual<T>(Pr::S(L), u, b, Pr::r(L), L.nx, L.ny, s));
-    DMG_CHECK(launch_restrict<T>(Pr::P(L), Pr::r(L), Pr::b(h->L[l + 1]), L.nx, L.ny, s));
+    const T* src = (l == 0 && !u0_zero) ? u0 : nullptr;
+    // every sweep writes the restriction of its residual; the last sweep's is the one used
+    for (int k = 0; k < o.nu_pre; ++k) {
+      T* dst = src ? other(l, src) : Pr::t(L);
+      DMG_CHECK(launch_pre<T>(L.cfg, Pr::S(L), src, dst, b, Pr::P(L), Pr::b(h->L[l + 1]), L.nx,
+                              L.ny, pre.pf, pre.cA, pre.cB, s));
+      src = dst;
+    }
+    cur[l] = const_cast<T*>(src);
   }
-  {
-    const Level& C = h->L[nl - 1];
-    T* u = nl == 1 ? u0 : Pr::u(C);
-    const T* b = nl == 1 ? b0 : Pr::b(C);
-    DMG_CHECK(launch_coarse_solve<T>(b, u, h->m_coarse, h->coarse_idx, h->chol, C.n(), s));
-  }
-  for (int l = nl - 2; l >= 0; --l) {
+  T* ut = h->tail == 0 ? u0 : Pr::u(h->L[h->tail]);
+  const T* bt = h->tail == 0 ? b0 : Pr::b(h->L[h->tail]);
+  DMG_CHECK(tail_launch<T>(h, ut, bt, s, u0_zero));
+  const T* e = ut;
+  for (int l = h->tail - 1; l >= 0; --l) {
     const Level& L = h->L[l];
-    T* u = l == 0 ? u0 : Pr::u(L);
     const T* b = l == 0 ? b0 : Pr::b(L);
-    DMG_CHECK(launch_prolong_add<T>(Pr::P(L), Pr::u(h->L[l + 1]), u, L.nx, L.ny, s));
-    DMG_CHECK(smooth_sweeps<T>(L, Pr::S(L), u, b, o.nu_post, o.post_order, s));
+    for (int k = 0; k < o.nu_post; ++k) {
+      const bool first = k == 0, last = k + 1 == o.nu_post;  // prolongate once, norm once
+      T* dst = other(l, cur[l]);
+      DMG_CHECK(launch_post<T>(L.cfg, Pr::S(L), cur[l], dst, b, Pr::P(L), first ? e : nullptr,
+                               (l == 0 && last) ? partials : nullptr, L.nx, L.ny, post.pf, post.cA,
+                               post.cB, s));
+      cur[l] = dst;
+    }
+    e = cur[l];
   }
+  if (h->tail > 0 && cur[0] != u0)
+    DMG_HIP(hipMemcpyAsync(u0, cur[0], h->L[0].n() * sizeof(T), hipMemcpyDeviceToDevice, s));
   return DMG_OK;
+}
+
+int post_partials_count(const dmg_hier* h) {
+  const Level& L = h->L[0];
+  int ns = 0, nseg = 0;
+  return strip_blocks(L.nx, L.ny, L.cfg.bw, L.cfg.seg_h, &ns, &nseg);
 }
 
 dmg_status read_scalar(dmg_hier* h, int slot, double* out, hipStream_t s) {
@@ -188,10 +280,15 @@ dmg_status norm_r(dmg_hier* h, const double* u, const double* b, int slot, hipSt
   return launch_finalize(h->partials, h->scalars + slot, s);
 }
 
-// The repeated step of a float64 solve: one V-cycle and the new residual norm (slot 2).
+// The repeated step of a float64 solve: one V-cycle and the new residual norm (slot 2).  When
+// the finest level runs in the strip kernels, the norm comes from the last post kernel.
 dmg_status step_fp64(dmg_hier* h, double* u, const double* b, hipStream_t s) {
-  DMG_CHECK(vcycle_impl<double>(h, u, b, s));
-  return norm_r(h, u, b, 2, s);
+  if (h->tail == 0) {
+    DMG_CHECK(vcycle_impl<double>(h, u, b, s));
+    return norm_r(h, u, b, 2, s);
+  }
+  DMG_CHECK(vcycle_impl<double>(h, u, b, s, h->partials));
+  return launch_finalize(h->partials, h->scalars + 2, s, post_partials_count(h));
 }
 
 // The repeated step of float32 refinement: r32 = r/s, e = 0, inner fp32 cycles, x += s e,
@@ -199,9 +296,8 @@ dmg_status step_fp64(dmg_hier* h, double* u, const double* b, hipStream_t s) {
 dmg_status step_ir(dmg_hier* h, double* x, const double* b, hipStream_t s) {
   const Level& L = h->L[0];
   DMG_CHECK(launch_ir_scale(h->r64, h->scalars + 4, L.b32, L.n(), s));
-  DMG_CHECK(launch_fill<float>(L.u32, 0.0f, L.n(), s));
   for (int k = 0; k < h->opts.inner_cycles; ++k)
-    DMG_CHECK(vcycle_impl<float>(h, L.u32, L.b32, s));
+    DMG_CHECK(vcycle_impl<float>(h, L.u32, L.b32, s, nullptr, k == 0));
   DMG_CHECK(launch_ir_update(x, L.u32, h->scalars + 4, L.n(), s));
   DMG_CHECK(launch_ir_residual(L.S, x, b, h->r64, L.nx, L.ny, h->partials, s));
   return launch_finalize(h->partials, h->scalars + 4, s);
@@ -372,6 +468,29 @@ dmg_status dmg_setup(const double* S, int32_t nx, int32_t ny, const dmg_options*
 }
 
 void dmg_destroy(dmg_hier* h) { delete h; }
+
+dmg_status dmg_refresh(dmg_hier* h, const double* S, hipStream_t stream) {
+  clear_error();
+  if (!h || !S) return fail(DMG_ERR_INVALID_ARG, "null pointer argument");
+  return setup_impl(h, S, stream);
+}
+
+dmg_status dmg_sweep(dmg_hier* h, int32_t level, int32_t kind, double* u, const double* b,
+                     hipStream_t stream) {
+  clear_error();
+  if (!h || !u || !b) return fail(DMG_ERR_INVALID_ARG, "null pointer argument");
+  if (level < 0 || level >= h->tail)
+    return fail(DMG_ERR_INVALID_ARG, "level %d is not a strip-kernel level (0..%d)", level,
+                h->tail - 1);
+  if (kind != 0 && kind != 1) return fail(DMG_ERR_INVALID_ARG, "kind must be 0 or 1");
+  const Level& L = h->L[level];
+  const OrderParams pre = order_params(h->opts.pre_order), post = order_params(h->opts.post_order);
+  if (kind == 0)
+    return launch_pre<double>(L.cfg, L.S, u, L.t, b, L.P, h->L[level + 1].b, L.nx, L.ny, pre.pf,
+                              pre.cA, pre.cB, stream);
+  return launch_post<double>(L.cfg, L.S, u, L.t, b, L.P, h->L[level + 1].u, nullptr, L.nx, L.ny,
+                             post.pf, post.cA, post.cB, stream);
+}
 
 dmg_status dmg_hier_level(const dmg_hier* h, int32_t level, int32_t* nx, int32_t* ny,
                           const double** S, const double** P) {

@@ -164,9 +164,9 @@ __global__ __launch_bounds__(256) void k_sq(const double* __restrict__ x, int nx
 
 // out[0] = sum of the partials (fixed order), out[1] = sqrt(out[0])
 __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ partials,
-                                                  double* __restrict__ out) {
+                                                  double* __restrict__ out, int count) {
   double acc = 0.0;
-  for (int k = threadIdx.x; k < kReduceBlocks; k += 256) acc += partials[k];
+  for (int k = threadIdx.x; k < count; k += 256) acc += partials[k];
   const double t = block_sum(acc);
   if (threadIdx.x == 0) {
     out[0] = t;
@@ -278,8 +278,8 @@ dmg_status launch_sq_partials(const double* x, size_t, int nx, int ny, double* p
   return launch_check("sq");
 }
 
-dmg_status launch_finalize(const double* partials, double* out, hipStream_t s) {
-  k_finalize<<<1, 256, 0, s>>>(partials, out);
+dmg_status launch_finalize(const double* partials, double* out, hipStream_t s, int count) {
+  k_finalize<<<1, 256, 0, s>>>(partials, out, count);
   return launch_check("finalize");
 }
 

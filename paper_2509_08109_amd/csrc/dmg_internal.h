@@ -49,23 +49,35 @@ struct Arena {
   }
 };
 
+// Launch shape of the fused strip kernels on one level (numerically neutral).
+struct StripConfig {
+  int bw = 128;     // columns (threads) per workgroup: 64, 128 or 256
+  int seg_h = 32;   // rows per segment (even)
+};
+
 // ---- hierarchy ---------------------------------------------------------------------------
 struct Level {
+  StripConfig cfg;        // fused-kernel launch shape (levels above the tail)
   int nx = 0, ny = 0;
   double* S = nullptr;    // [5][ny][nx]
   double* P = nullptr;    // [8][nyc][nxc] weights to the next coarser level (null at coarsest)
   double* u = nullptr;    // correction on coarse levels (level 0 uses the caller's array)
+  double* t = nullptr;    // second iterate buffer for the out-of-place strip sweeps
   double* b = nullptr;    // right-hand side on coarse levels
   double* r = nullptr;    // residual scratch
   float* S32 = nullptr;   // fp32 copies for DMG_FP32_IR
   float* P32 = nullptr;
   float* u32 = nullptr;
+  float* t32 = nullptr;
   float* b32 = nullptr;
   float* r32 = nullptr;
   size_t n() const { return size_t(nx) * size_t(ny); }
 };
 
 constexpr int kReduceBlocks = 1024;  // fixed partial count: reductions are order-deterministic
+constexpr int kMaxPartials = 16384;  // capacity of the partials buffer
+constexpr int kTailMaxN = 65;
+constexpr int kMaxLevels = 32;        // levels with max(nx,ny) <= this run in the one-workgroup tail
 
 struct Graph {
   hipGraphExec_t exec = nullptr;
@@ -81,6 +93,7 @@ struct Graph {
 struct dmg_hier {
   dmg_options opts;
   std::vector<dmg::Level> L;
+  int tail = 0;               // first level handled by the coarse-tail kernel
   int m_coarse = 0;           // unknowns of the coarsest interior system
   int* coarse_idx = nullptr;  // [m] vertex index of each coarsest unknown
   double* chol = nullptr;     // [m][m] Cholesky factor (lower), float64
@@ -129,7 +142,37 @@ dmg_status launch_resid_sq_partials(const double* S, const double* u, const doub
                                     int ny, double* partials, hipStream_t s);
 dmg_status launch_sq_partials(const double* x, size_t n, int nx, int ny, double* partials,
                               hipStream_t s);
-dmg_status launch_finalize(const double* partials, double* out, hipStream_t s);
+dmg_status launch_finalize(const double* partials, double* out, hipStream_t s,
+                           int count = kReduceBlocks);
+
+// fused strip kernels (fused_kernels.hip)
+int strip_blocks(int nx, int ny, int bw, int seg_h, int* nstrips, int* nsegs);
+// Out-of-place: u_in (pre: nullptr = zero) -> u_out, u_in != u_out.
+template <class T>
+dmg_status launch_pre(const StripConfig& cfg, const T* S, const T* uin, T* u, const T* b,
+                      const T* P, T* bH, int nx, int ny, int pf, int cA, int cB, hipStream_t s);
+template <class T>
+dmg_status launch_post(const StripConfig& cfg, const T* S, const T* uin, T* u, const T* b,
+                       const T* P, const T* e, double* partials, int nx, int ny, int pf, int cA,
+                       int cB, hipStream_t s);
+template <class T>
+struct TailSpec {
+  const T* S[12];
+  T* u[12];
+  T* b[12];
+  T* r[12];
+  const T* P[12];
+  int nx[12], ny[12];
+  int nlev = 0;
+  int zero_top = 1;
+  int m = 0;
+  const int* idx = nullptr;
+  const double* chol = nullptr;
+  int pre[4], post[4];
+  int nu_pre = 1, nu_post = 1;
+};
+template <class T>
+dmg_status launch_tail(const TailSpec<T>& spec, hipStream_t s);
 
 // iterative refinement helpers
 dmg_status launch_ir_update(double* x, const float* e, const double* s_dev, size_t n,

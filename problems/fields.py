@@ -24,12 +24,17 @@ def grid_coords(nx: int, ny: int):
     return np.linspace(-1.0, 1.0, nx), np.linspace(-1.0, 1.0, ny)
 
 
-def sample_jacobian(mp, nx: int, ny: int, row_block: int = 256) -> np.ndarray:
-    """dX/d(xi,eta) of the map at the 2x2 Gauss points of every cell: [16][ny-1][nx-1]."""
+def sample_jacobian(mp, nx: int, ny: int, row_block: int = 128) -> np.ndarray:
+    """dX/d(xi,eta) of the map at the 2x2 Gauss points of every cell: [16][ny-1][nx-1].
+    Row blocks are evaluated on a thread pool (NumPy/SciPy ufuncs release the GIL)."""
+    import concurrent.futures as cf
+    import os
+
     xi, eta = grid_coords(nx, ny)
     hx, hy = xi[1] - xi[0], eta[1] - eta[0]
     out = np.empty((16, ny - 1, nx - 1))
-    for j0 in range(0, ny - 1, row_block):
+
+    def block(j0):
         j1 = min(ny - 1, j0 + row_block)
         for q in range(4):
             qx, qy = q & 1, q >> 1
@@ -39,6 +44,10 @@ def sample_jacobian(mp, nx: int, ny: int, row_block: int = 256) -> np.ndarray:
             J = mp.jacobian(XX, YY)
             for e in range(4):
                 out[4 * q + e, j0:j1] = J[e]
+
+    workers = min(16, os.cpu_count() or 1)
+    with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+        list(ex.map(block, range(0, ny - 1, row_block)))
     return out
 
 

@@ -126,6 +126,40 @@ def test_solve_matches_oracle(dmg, case):
     h.close()
 
 
+@pytest.mark.parametrize("pre,post,nu", [((1, 0, 3, 2), (2, 3, 0, 1), (1, 1)),
+                                         ((2, 3, 0, 1), (1, 0, 3, 2), (1, 1)),
+                                         ((0, 1, 2, 3), (3, 2, 1, 0), (2, 2)),
+                                         ((3, 2, 0, 1), (0, 1, 3, 2), (1, 2))])
+def test_colour_orders_and_sweep_counts(dmg, pre, post, nu):
+    prob = pb.star(257, seed=5)
+    S_or = fem.assemble_stencil(prob.jac, prob.K, prob.nx, prob.ny)
+    levels = boxmg.build_hierarchy(S_or)
+    h = dmg.Hierarchy(dev(S_or), pre_order=pre, post_order=post, nu_pre=nu[0], nu_post=nu[1])
+    orc = cycle.Oracle(levels, pre=pre, post=post, nu_pre=nu[0], nu_post=nu[1])
+    b = dev(prob.b)
+    u = torch.zeros_like(b)
+    uo = np.zeros(prob.nx * prob.ny)
+    for k in range(4):
+        h.vcycle(u, b)
+        orc.vcycle(uo, prob.b.ravel().copy())
+        assert np.linalg.norm(host(u).ravel() - uo) / np.linalg.norm(uo) <= TOL, k
+    h.close()
+
+
+@pytest.mark.parametrize("tile_rows", [2, 6, 64])
+def test_launch_shape_is_numerically_neutral(dmg, tile_rows):
+    prob = pb.star(513, seed=6)
+    S = dmg.assemble_stencil(dev(prob.jac), dev(prob.K))
+    b = dev(prob.b)
+    ref = dmg.Hierarchy(S)
+    u0, k0, _, _ = ref.solve(b, rtol=1e-10)
+    h = dmg.Hierarchy(S, tile_rows=tile_rows)
+    u1, k1, _, _ = h.solve(b, rtol=1e-10)
+    assert k0 == k1 and torch.equal(u0, u1)
+    h.close()
+    ref.close()
+
+
 def test_graph_and_eager_solves_are_identical(dmg):
     prob = pb.star(129, seed=1)
     S = dmg.assemble_stencil(dev(prob.jac), dev(prob.K))
