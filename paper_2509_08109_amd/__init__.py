@@ -141,6 +141,25 @@ class Hierarchy:
         _lib.check(lib().dmg_sweep(self._h, level, kind, _dev(u, shp, "u"), _dev(b, shp, "b"),
                                    _stream(self.device)))
 
+    def autotune(self, b: torch.Tensor, tiles: bool = True, colour_order: bool = False, reps: int = 10):
+        """Pick launch shapes per level (and optionally the colour order) by timing on this
+        hierarchy; returns config()."""
+        u = torch.zeros((self.ny, self.nx), dtype=torch.float64, device=self.device)
+        flags = (1 if tiles else 0) | (2 if colour_order else 0)
+        _lib.check(lib().dmg_autotune(self._h, _dev(u, (self.ny, self.nx), "u"),
+                                      _dev(b, (self.ny, self.nx), "b"), flags, reps, _stream(self.device)))
+        return self.config()
+
+    def config(self):
+        """{'levels': [(bw, seg_h) per level], 'pre_order': [...], 'post_order': [...]}"""
+        out = []
+        pre, post = (C.c_int32 * 4)(), (C.c_int32 * 4)()
+        for l in range(self.num_levels):
+            bw, sh = C.c_int32(), C.c_int32()
+            _lib.check(lib().dmg_hier_config(self._h, l, C.byref(bw), C.byref(sh), pre, post))
+            out.append((int(bw.value), int(sh.value)))
+        return {"levels": out, "pre_order": list(pre), "post_order": list(post)}
+
     # -- cycles and solves ---------------------------------------------------------------
     def vcycle(self, u: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
         shp = (self.ny, self.nx)

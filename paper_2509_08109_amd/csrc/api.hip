@@ -134,9 +134,13 @@ void carve(dmg_hier& h, Arena& a, const std::vector<std::pair<int, int>>& dims,
   h.coarse_idx = a.take<int>(size_t(h.m_coarse));
   h.chol = a.take<double>(size_t(h.m_coarse) * h.m_coarse);
   h.partials = a.take<double>(kMaxPartials);
-  for (size_t l = 0; l < dims.size(); ++l) h.L[l].cfg = default_strip_config(dims[l].first, dims[l].second, o);
+  for (size_t l = 0; l < dims.size(); ++l) {
+    h.L[l].cfg = default_strip_config(dims[l].first, dims[l].second, o);
+    h.L[l].cfg32 = h.L[l].cfg;
+  }
   h.scalars = a.take<double>(16);
   h.flag = a.take<int>(16);
+  h.hist = a.take<double>(kMaxHistory);
   if (fp32) h.r64 = a.take<double>(size_t(dims[0].first) * dims[0].second);
 }
 
@@ -144,6 +148,7 @@ template <class T>
 struct Prec;
 template <>
 struct Prec<double> {
+  static const StripConfig& cfg(const Level& L) { return L.cfg; }
   static double* t(const Level& L) { return L.t; }
   static const double* S(const Level& L) { return L.S; }
   static const double* P(const Level& L) { return L.P; }
@@ -153,6 +158,7 @@ struct Prec<double> {
 };
 template <>
 struct Prec<float> {
+  static const StripConfig& cfg(const Level& L) { return L.cfg32; }
   static float* t(const Level& L) { return L.t32; }
   static const float* S(const Level& L) { return L.S32; }
   static const float* P(const Level& L) { return L.P32; }
@@ -171,7 +177,8 @@ OrderParams order_params(const int32_t* ord) {
 }
 
 template <class T>
-dmg_status tail_launch(dmg_hier* h, T* u_top, const T* b_top, hipStream_t s, bool u0_zero) {
+dmg_status tail_launch(dmg_hier* h, T* u_top, const T* b_top, hipStream_t s, bool u0_zero,
+                       const int* stop) {
   using Pr = Prec<T>;
   TailSpec<T> sp;
   const int nl = int(h->L.size());
@@ -197,6 +204,7 @@ dmg_status tail_launch(dmg_hier* h, T* u_top, const T* b_top, hipStream_t s, boo
   }
   sp.nu_pre = h->opts.nu_pre;
   sp.nu_post = h->opts.nu_post;
+  sp.stop = stop;
   return launch_tail<T>(sp, s);
 }
 
@@ -208,7 +216,7 @@ dmg_status tail_launch(dmg_hier* h, T* u_top, const T* b_top, hipStream_t s, boo
 // squared-residual partials of the final level-0 iterate.
 template <class T>
 dmg_status vcycle_impl(dmg_hier* h, T* u0, const T* b0, hipStream_t s, double* partials = nullptr,
-                       bool u0_zero = false) {
+                       bool u0_zero = false, const int* stop = nullptr) {
   using Pr = Prec<T>;
   const dmg_options& o = h->opts;
   const OrderParams pre = order_params(o.pre_order), post = order_params(o.post_order);
@@ -224,15 +232,15 @@ dmg_status vcycle_impl(dmg_hier* h, T* u0, const T* b0, hipStream_t s, double* p
     // every sweep writes the restriction of its residual; the last sweep's is the one used
     for (int k = 0; k < o.nu_pre; ++k) {
       T* dst = src ? other(l, src) : Pr::t(L);
-      DMG_CHECK(launch_pre<T>(L.cfg, Pr::S(L), src, dst, b, Pr::P(L), Pr::b(h->L[l + 1]), L.nx,
-                              L.ny, pre.pf, pre.cA, pre.cB, s));
+      DMG_CHECK(launch_pre<T>(Pr::cfg(L), Pr::S(L), src, dst, b, Pr::P(L), Pr::b(h->L[l + 1]), L.nx,
+                              L.ny, pre.pf, pre.cA, pre.cB, stop, s));
       src = dst;
     }
     cur[l] = const_cast<T*>(src);
   }
   T* ut = h->tail == 0 ? u0 : Pr::u(h->L[h->tail]);
   const T* bt = h->tail == 0 ? b0 : Pr::b(h->L[h->tail]);
-  DMG_CHECK(tail_launch<T>(h, ut, bt, s, u0_zero));
+  DMG_CHECK(tail_launch<T>(h, ut, bt, s, u0_zero, stop));
   const T* e = ut;
   for (int l = h->tail - 1; l >= 0; --l) {
     const Level& L = h->L[l];
@@ -240,15 +248,15 @@ dmg_status vcycle_impl(dmg_hier* h, T* u0, const T* b0, hipStream_t s, double* p
     for (int k = 0; k < o.nu_post; ++k) {
       const bool first = k == 0, last = k + 1 == o.nu_post;  // prolongate once, norm once
       T* dst = other(l, cur[l]);
-      DMG_CHECK(launch_post<T>(L.cfg, Pr::S(L), cur[l], dst, b, Pr::P(L), first ? e : nullptr,
+      DMG_CHECK(launch_post<T>(Pr::cfg(L), Pr::S(L), cur[l], dst, b, Pr::P(L), first ? e : nullptr,
                                (l == 0 && last) ? partials : nullptr, L.nx, L.ny, post.pf, post.cA,
-                               post.cB, s));
+                               post.cB, stop, s));
       cur[l] = dst;
     }
     e = cur[l];
   }
-  if (h->tail > 0 && cur[0] != u0)
-    DMG_HIP(hipMemcpyAsync(u0, cur[0], h->L[0].n() * sizeof(T), hipMemcpyDeviceToDevice, s));
+  if (h->tail > 0 && cur[0] != u0)  // odd total sweep count: the iterate ends in the buffer
+    DMG_CHECK(launch_copy<T>(cur[0], u0, h->L[0].n(), stop, s));
   return DMG_OK;
 }
 
@@ -280,27 +288,40 @@ dmg_status norm_r(dmg_hier* h, const double* u, const double* b, int slot, hipSt
   return launch_finalize(h->partials, h->scalars + slot, s);
 }
 
-// The repeated step of a float64 solve: one V-cycle and the new residual norm (slot 2).  When
-// the finest level runs in the strip kernels, the norm comes from the last post kernel.
+// Device solve state: flag[4] = stop, flag[5] = steps done, flag[6] = max steps;
+// scalars[6] = (rtol ||b||)^2.
+int* stop_flag(dmg_hier* h) { return h->flag + 4; }
+
+// The repeated step of a float64 solve: one V-cycle, then the residual norm of the new iterate
+// (slot 2) and the convergence check.  When the finest level runs in the strip kernels, the
+// norm partials come from the last post kernel.  Every kernel is a no-op once stop is set.
 dmg_status step_fp64(dmg_hier* h, double* u, const double* b, hipStream_t s) {
+  const int* stop = stop_flag(h);
+  int count = kReduceBlocks;
   if (h->tail == 0) {
-    DMG_CHECK(vcycle_impl<double>(h, u, b, s));
-    return norm_r(h, u, b, 2, s);
+    DMG_CHECK(vcycle_impl<double>(h, u, b, s, nullptr, false, stop));
+    const Level& L = h->L[0];
+    DMG_CHECK(launch_resid_sq_partials(L.S, u, b, L.nx, L.ny, h->partials, s, stop));
+  } else {
+    DMG_CHECK(vcycle_impl<double>(h, u, b, s, h->partials, false, stop));
+    count = post_partials_count(h);
   }
-  DMG_CHECK(vcycle_impl<double>(h, u, b, s, h->partials));
-  return launch_finalize(h->partials, h->scalars + 2, s, post_partials_count(h));
+  return launch_check_step(h->partials, count, h->scalars + 2, h->scalars, h->flag + 4, h->hist,
+                           kMaxHistory, s);
 }
 
 // The repeated step of float32 refinement: r32 = r/s, e = 0, inner fp32 cycles, x += s e,
-// r = b - A x and its norm (slot 4).
+// r = b - A x, its norm (slot 4) and the convergence check.
 dmg_status step_ir(dmg_hier* h, double* x, const double* b, hipStream_t s) {
+  const int* stop = stop_flag(h);
   const Level& L = h->L[0];
-  DMG_CHECK(launch_ir_scale(h->r64, h->scalars + 4, L.b32, L.n(), s));
+  DMG_CHECK(launch_ir_scale(h->r64, h->scalars + 4, L.b32, L.n(), s, stop));
   for (int k = 0; k < h->opts.inner_cycles; ++k)
-    DMG_CHECK(vcycle_impl<float>(h, L.u32, L.b32, s, nullptr, k == 0));
-  DMG_CHECK(launch_ir_update(x, L.u32, h->scalars + 4, L.n(), s));
-  DMG_CHECK(launch_ir_residual(L.S, x, b, h->r64, L.nx, L.ny, h->partials, s));
-  return launch_finalize(h->partials, h->scalars + 4, s);
+    DMG_CHECK(vcycle_impl<float>(h, L.u32, L.b32, s, nullptr, k == 0, stop));
+  DMG_CHECK(launch_ir_update(x, L.u32, h->scalars + 4, L.n(), s, stop));
+  DMG_CHECK(launch_ir_residual(L.S, x, b, h->r64, L.nx, L.ny, h->partials, s, stop));
+  return launch_check_step(h->partials, kReduceBlocks, h->scalars + 4, h->scalars, h->flag + 4,
+                           h->hist, kMaxHistory, s);
 }
 
 void graph_reset(Graph& g) {
@@ -309,10 +330,14 @@ void graph_reset(Graph& g) {
   g = Graph{};
 }
 
-// Runs the solve step for (u, b) on stream s, through a captured graph when enabled.  The
-// graph is re-captured when the arrays or the stream change.
+// Runs kChunk solve steps for (u, b) on stream s, through one captured graph when enabled.
+// The graph is re-captured when the arrays or the stream change.
 dmg_status run_step(dmg_hier* h, int kind, double* u, const double* b, hipStream_t s) {
-  auto step = [&]() { return kind == 0 ? step_fp64(h, u, b, s) : step_ir(h, u, b, s); };
+  auto step = [&]() -> dmg_status {
+    for (int k = 0; k < kChunk; ++k)
+      DMG_CHECK(kind == 0 ? step_fp64(h, u, b, s) : step_ir(h, u, b, s));
+    return DMG_OK;
+  };
   // the legacy default stream cannot be captured: run eagerly there
   if (!h->opts.use_graph || s == nullptr) return step();
   Graph& g = h->graph;
@@ -340,6 +365,69 @@ dmg_status run_step(dmg_hier* h, int kind, double* u, const double* b, hipStream
   }
   DMG_HIP(hipGraphLaunch(g.exec, s));
   return DMG_OK;
+}
+
+// Mean duration (ms) of `reps` pre + post launches of level l in precision T with shape c.
+template <class T>
+dmg_status time_level(dmg_hier* h, int l, const StripConfig& c, int reps, hipStream_t s,
+                      hipEvent_t e0, hipEvent_t e1, float* ms) {
+  using Pr = Prec<T>;
+  const Level& L = h->L[l];
+  const OrderParams pre = order_params(h->opts.pre_order), post = order_params(h->opts.post_order);
+  // level-shaped arrays whose contents do not matter; u, t (written) and b (read) distinct.
+  // Level 0 has no u/b of its own: use the residual scratch and the stencil's first plane.
+  T* u = l == 0 ? Pr::r(L) : Pr::u(L);
+  T* t = Pr::t(L);
+  const T* b = l == 0 ? Pr::S(L) : Pr::b(L);
+  auto run = [&]() -> dmg_status {
+    DMG_CHECK(launch_pre<T>(c, Pr::S(L), u, t, b, Pr::P(L), Pr::b(h->L[l + 1]), L.nx, L.ny, pre.pf,
+                            pre.cA, pre.cB, nullptr, s));
+    return launch_post<T>(c, Pr::S(L), t, u, b, Pr::P(L), Pr::u(h->L[l + 1]), nullptr, L.nx, L.ny,
+                          post.pf, post.cA, post.cB, nullptr, s);
+  };
+  DMG_CHECK(run());  // warm-up
+  DMG_HIP(hipEventRecord(e0, s));
+  for (int k = 0; k < reps; ++k) DMG_CHECK(run());
+  DMG_HIP(hipEventRecord(e1, s));
+  DMG_HIP(hipEventSynchronize(e1));
+  float t_ms = 0.f;
+  DMG_HIP(hipEventElapsedTime(&t_ms, e0, e1));
+  *ms = t_ms / float(reps);
+  return DMG_OK;
+}
+
+template <class T>
+dmg_status tune_levels(dmg_hier* h, int reps, hipStream_t s) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  DMG_HIP(hipEventCreate(&e0));
+  DMG_HIP(hipEventCreate(&e1));
+  dmg_status st = DMG_OK;
+  for (int l = 0; l < h->tail && st == DMG_OK; ++l) {
+    Level& L = h->L[l];
+    StripConfig best = Prec<T>::cfg(L);
+    float best_ms = 1e30f;
+    for (int bw : {64, 128}) {
+      for (int sh = 2; sh <= 128 && st == DMG_OK; sh *= 2) {
+        int ns = 0, nseg = 0;
+        if (strip_blocks(L.nx, L.ny, bw, sh, &ns, &nseg) > kMaxPartials) continue;
+        StripConfig c;
+        c.bw = bw;
+        c.seg_h = sh;
+        float ms = 0.f;
+        st = time_level<T>(h, l, c, reps, s, e0, e1, &ms);
+        if (st == DMG_OK && ms < best_ms) {
+          best_ms = ms;
+          best = c;
+        }
+        if (sh * 2 > L.ny + 1) break;
+      }
+    }
+    if (sizeof(T) == 8) L.cfg = best;
+    else L.cfg32 = best;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
 }
 
 dmg_status setup_impl(dmg_hier* h, const double* S, hipStream_t s) {
@@ -487,9 +575,9 @@ dmg_status dmg_sweep(dmg_hier* h, int32_t level, int32_t kind, double* u, const 
   const OrderParams pre = order_params(h->opts.pre_order), post = order_params(h->opts.post_order);
   if (kind == 0)
     return launch_pre<double>(L.cfg, L.S, u, L.t, b, L.P, h->L[level + 1].b, L.nx, L.ny, pre.pf,
-                              pre.cA, pre.cB, stream);
+                              pre.cA, pre.cB, nullptr, stream);
   return launch_post<double>(L.cfg, L.S, u, L.t, b, L.P, h->L[level + 1].u, nullptr, L.nx, L.ny,
-                             post.pf, post.cA, post.cB, stream);
+                             post.pf, post.cA, post.cB, nullptr, stream);
 }
 
 dmg_status dmg_hier_level(const dmg_hier* h, int32_t level, int32_t* nx, int32_t* ny,
@@ -534,6 +622,78 @@ dmg_status dmg_vcycle(dmg_hier* h, double* u, const double* b, hipStream_t strea
   return vcycle_impl<double>(h, u, b, stream);
 }
 
+dmg_status dmg_hier_config(const dmg_hier* h, int32_t level, int32_t* bw, int32_t* seg_h,
+                           int32_t* pre_order, int32_t* post_order) {
+  clear_error();
+  if (!h) return fail(DMG_ERR_INVALID_ARG, "null hierarchy");
+  if (level < 0 || level >= int(h->L.size()))
+    return fail(DMG_ERR_INVALID_ARG, "level %d out of range", level);
+  const bool strip = level < h->tail;
+  if (bw) *bw = strip ? h->L[level].cfg.bw : 0;
+  if (seg_h) *seg_h = strip ? h->L[level].cfg.seg_h : 0;
+  for (int k = 0; k < 4; ++k) {
+    if (pre_order) pre_order[k] = h->opts.pre_order[k];
+    if (post_order) post_order[k] = h->opts.post_order[k];
+  }
+  return DMG_OK;
+}
+
+dmg_status dmg_autotune(dmg_hier* h, double* u, const double* b, int32_t flags, int32_t reps,
+                        hipStream_t stream) {
+  clear_error();
+  if (!h || !u || !b) return fail(DMG_ERR_INVALID_ARG, "null pointer argument");
+  if (reps < 1 || reps > 1000) return fail(DMG_ERR_INVALID_ARG, "reps must be in [1,1000]");
+  graph_reset(h->graph);
+  if (flags & 1) {
+    DMG_CHECK(tune_levels<double>(h, reps, stream));
+    if (h->opts.precision == DMG_FP32_IR) DMG_CHECK(tune_levels<float>(h, reps, stream));
+  }
+  if (flags & 2) {
+    static const int32_t cand[4][4] = {{0, 1, 2, 3}, {1, 0, 3, 2}, {2, 3, 0, 1}, {3, 2, 1, 0}};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    DMG_HIP(hipEventCreate(&e0));
+    DMG_HIP(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    int best = -1;
+    const dmg_options saved = h->opts;
+    for (int c = 0; c < 4; ++c) {
+      for (int k = 0; k < 4; ++k) {
+        h->opts.pre_order[k] = cand[c][k];
+        h->opts.post_order[k] = cand[c][3 - k];
+      }
+      graph_reset(h->graph);
+      float total = 0.f;
+      dmg_status st = DMG_OK;
+      for (int r = 0; r < std::max(1, reps / 4) && st == DMG_OK; ++r) {
+        DMG_CHECK(launch_fill<double>(u, 0.0, h->L[0].n(), stream));
+        DMG_HIP(hipEventRecord(e0, stream));
+        int32_t it = 0;
+        st = dmg_solve(h, u, b, 1e-10, 500, &it, nullptr, nullptr, stream);
+        DMG_HIP(hipEventRecord(e1, stream));
+        DMG_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        DMG_HIP(hipEventElapsedTime(&ms, e0, e1));
+        total += ms;
+      }
+      if (st == DMG_OK && total < best_ms) {
+        best_ms = total;
+        best = c;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h->opts = saved;
+    if (best >= 0)
+      for (int k = 0; k < 4; ++k) {
+        h->opts.pre_order[k] = cand[best][k];
+        h->opts.post_order[k] = cand[best][3 - k];
+      }
+    graph_reset(h->graph);
+    clear_error();
+  }
+  return DMG_OK;
+}
+
 dmg_status dmg_residual_norm(dmg_hier* h, const double* u, const double* b, double* norm,
                              hipStream_t stream) {
   clear_error();
@@ -570,18 +730,31 @@ dmg_status dmg_solve(dmg_hier* h, double* u, const double* b, double rtol, int32
   if (!std::isfinite(rn)) return fail(DMG_ERR_NONFINITE, "initial residual norm is not finite");
   const double target = rtol * bn;
   int k = 0;
-  while (rn > target && k < max_iters) {
-    DMG_CHECK(run_step(h, ir ? 1 : 0, u, b, stream));
-    DMG_CHECK(read_scalar(h, slot + 1, &rn, stream));
-    ++k;
-    if (history) history[k - 1] = bn > 0 ? rn / bn : rn;
-    if (!std::isfinite(rn)) {
-      if (iters) *iters = k;
-      return fail(DMG_ERR_NONFINITE, "residual norm became non-finite at step %d", k);
+  if (rn > target && max_iters > 0) {
+    // device solve state: stop = 0, steps = 0, max = max_iters, target^2
+    int* hs = reinterpret_cast<int*>(h->host + 8);
+    hs[0] = 0;
+    hs[1] = 0;
+    hs[2] = max_iters;
+    h->host[12] = target * target;
+    DMG_HIP(hipMemcpyAsync(h->flag + 4, hs, 3 * sizeof(int), hipMemcpyHostToDevice, stream));
+    DMG_HIP(hipMemcpyAsync(h->scalars + 6, h->host + 12, sizeof(double), hipMemcpyHostToDevice,
+                           stream));
+    for (;;) {
+      DMG_CHECK(run_step(h, ir ? 1 : 0, u, b, stream));
+      DMG_HIP(hipMemcpyAsync(hs, h->flag + 4, 2 * sizeof(int), hipMemcpyDeviceToHost, stream));
+      DMG_HIP(hipStreamSynchronize(stream));
+      if (hs[0]) break;
     }
+    k = hs[1];
+    DMG_CHECK(read_scalar(h, slot + 1, &rn, stream));
+    if (history && k > 0)
+      DMG_HIP(hipMemcpy(history, h->hist, size_t(std::min(k, kMaxHistory)) * sizeof(double),
+                        hipMemcpyDeviceToHost));
   }
   if (iters) *iters = k;
   if (relres) *relres = bn > 0 ? rn / bn : rn;
+  if (!std::isfinite(rn)) return fail(DMG_ERR_NONFINITE, "residual norm became non-finite at step %d", k);
   if (rn > target)
     return fail(DMG_ERR_NO_CONVERGENCE, "no convergence in %d steps (rel. residual %.3e)", k,
                 bn > 0 ? rn / bn : rn);

@@ -109,6 +109,15 @@ __global__ __launch_bounds__(256) void k_prolong_add(const T* __restrict__ P,
 }
 
 template <class T>
+__global__ __launch_bounds__(256) void k_copy(const T* __restrict__ x, T* __restrict__ y, size_t n,
+                                              const int* __restrict__ stop) {
+  if (stop && *stop) return;
+  for (size_t k = blockIdx.x * size_t(blockDim.x) + threadIdx.x; k < n;
+       k += size_t(gridDim.x) * blockDim.x)
+    y[k] = x[k];
+}
+
+template <class T>
 __global__ __launch_bounds__(256) void k_fill(T* __restrict__ x, T val, size_t n) {
   for (size_t k = blockIdx.x * size_t(blockDim.x) + threadIdx.x; k < n;
        k += size_t(gridDim.x) * blockDim.x)
@@ -133,7 +142,9 @@ __device__ __forceinline__ double block_sum(double v) {
 __global__ __launch_bounds__(256) void k_resid_sq(const double* __restrict__ S,
                                                   const double* __restrict__ u,
                                                   const double* __restrict__ b, int nx, int ny,
-                                                  double* __restrict__ partials) {
+                                                  double* __restrict__ partials,
+                                                  const int* __restrict__ stop) {
+  if (stop && *stop) return;
   const size_t N = size_t(nx) * ny;
   const size_t m = size_t(nx - 2) * (ny - 2);
   double acc = 0.0;
@@ -174,10 +185,35 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ par
   }
 }
 
+// Convergence bookkeeping of a solve step, on the device: sums the partials into out[0..1]
+// (||r||^2, ||r||), appends ||r||/||b|| to the history and raises *stop when
+// ||r||^2 <= target^2, the step budget is spent, or the norm is not finite.
+// st[0] = stop flag, st[1] = steps done, st[2] = max steps; sc[1] = ||b||, sc[6] = target^2.
+__global__ __launch_bounds__(256) void k_check(const double* __restrict__ partials, int count,
+                                               double* __restrict__ out,
+                                               const double* __restrict__ sc,
+                                               int* __restrict__ st, double* __restrict__ hist,
+                                               int hist_cap) {
+  if (st[0]) return;
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < count; k += 256) acc += partials[k];
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) {
+    out[0] = t;
+    out[1] = sqrt(t);
+    const int k = st[1] + 1;
+    st[1] = k;
+    if (k <= hist_cap) hist[k - 1] = sc[1] > 0.0 ? sqrt(t) / sc[1] : sqrt(t);
+    if (!(t > sc[6]) || k >= st[2] || !isfinite(t)) st[0] = 1;
+  }
+}
+
 // ---- iterative refinement --------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_ir_update(double* __restrict__ x,
                                                    const float* __restrict__ e,
-                                                   const double* __restrict__ s, size_t n) {
+                                                   const double* __restrict__ s, size_t n,
+                                                   const int* __restrict__ stop) {
+  if (stop && *stop) return;
   const double sc = s[1];
   for (size_t k = blockIdx.x * size_t(blockDim.x) + threadIdx.x; k < n;
        k += size_t(gridDim.x) * blockDim.x)
@@ -188,7 +224,9 @@ __global__ __launch_bounds__(256) void k_ir_residual(const double* __restrict__ 
                                                      const double* __restrict__ x,
                                                      const double* __restrict__ b,
                                                      double* __restrict__ r, int nx, int ny,
-                                                     double* __restrict__ partials) {
+                                                     double* __restrict__ partials,
+                                                     const int* __restrict__ stop) {
+  if (stop && *stop) return;
   const size_t N = size_t(nx) * ny;
   double acc = 0.0;
   for (size_t v = blockIdx.x * size_t(blockDim.x) + threadIdx.x; v < N;
@@ -207,7 +245,9 @@ __global__ __launch_bounds__(256) void k_ir_residual(const double* __restrict__ 
 
 __global__ __launch_bounds__(256) void k_ir_scale(const double* __restrict__ r,
                                                   const double* __restrict__ s,
-                                                  float* __restrict__ r32, size_t n) {
+                                                  float* __restrict__ r32, size_t n,
+                                                  const int* __restrict__ stop) {
+  if (stop && *stop) return;
   const double sc = s[1];
   for (size_t k = blockIdx.x * size_t(blockDim.x) + threadIdx.x; k < n;
        k += size_t(gridDim.x) * blockDim.x)
@@ -250,6 +290,12 @@ dmg_status launch_prolong_add(const T* P, const T* eH, T* u, int nx, int ny, hip
 }
 
 template <class T>
+dmg_status launch_copy(const T* x, T* y, size_t n, const int* stop, hipStream_t s) {
+  k_copy<T><<<stride_blocks(n), 256, 0, s>>>(x, y, n, stop);
+  return launch_check("copy");
+}
+
+template <class T>
 dmg_status launch_fill(T* x, T v, size_t n, hipStream_t s) {
   k_fill<T><<<stride_blocks(n), 256, 0, s>>>(x, v, n);
   return launch_check("fill");
@@ -261,14 +307,15 @@ dmg_status launch_fill(T* x, T v, size_t n, hipStream_t s) {
                                          hipStream_t);                                       \
   template dmg_status launch_restrict<T>(const T*, const T*, T*, int, int, hipStream_t);     \
   template dmg_status launch_prolong_add<T>(const T*, const T*, T*, int, int, hipStream_t);  \
-  template dmg_status launch_fill<T>(T*, T, size_t, hipStream_t);
+  template dmg_status launch_fill<T>(T*, T, size_t, hipStream_t);                            \
+  template dmg_status launch_copy<T>(const T*, T*, size_t, const int*, hipStream_t);
 DMG_INST(double)
 DMG_INST(float)
 #undef DMG_INST
 
 dmg_status launch_resid_sq_partials(const double* S, const double* u, const double* b, int nx,
-                                    int ny, double* partials, hipStream_t s) {
-  k_resid_sq<<<kReduceBlocks, 256, 0, s>>>(S, u, b, nx, ny, partials);
+                                    int ny, double* partials, hipStream_t s, const int* stop) {
+  k_resid_sq<<<kReduceBlocks, 256, 0, s>>>(S, u, b, nx, ny, partials, stop);
   return launch_check("resid_sq");
 }
 
@@ -284,21 +331,27 @@ dmg_status launch_finalize(const double* partials, double* out, hipStream_t s, i
 }
 
 dmg_status launch_ir_update(double* x, const float* e, const double* s_dev, size_t n,
-                            hipStream_t s) {
-  k_ir_update<<<stride_blocks(n), 256, 0, s>>>(x, e, s_dev, n);
+                            hipStream_t s, const int* stop) {
+  k_ir_update<<<stride_blocks(n), 256, 0, s>>>(x, e, s_dev, n, stop);
   return launch_check("ir_update");
 }
 
 dmg_status launch_ir_residual(const double* S, const double* x, const double* b, double* r,
-                              int nx, int ny, double* partials, hipStream_t s) {
-  k_ir_residual<<<kReduceBlocks, 256, 0, s>>>(S, x, b, r, nx, ny, partials);
+                              int nx, int ny, double* partials, hipStream_t s, const int* stop) {
+  k_ir_residual<<<kReduceBlocks, 256, 0, s>>>(S, x, b, r, nx, ny, partials, stop);
   return launch_check("ir_residual");
 }
 
 dmg_status launch_ir_scale(const double* r, const double* s_dev, float* r32, size_t n,
-                           hipStream_t s) {
-  k_ir_scale<<<stride_blocks(n), 256, 0, s>>>(r, s_dev, r32, n);
+                           hipStream_t s, const int* stop) {
+  k_ir_scale<<<stride_blocks(n), 256, 0, s>>>(r, s_dev, r32, n, stop);
   return launch_check("ir_scale");
+}
+
+dmg_status launch_check_step(const double* partials, int count, double* out, const double* sc,
+                             int* st, double* hist, int hist_cap, hipStream_t s) {
+  k_check<<<1, 256, 0, s>>>(partials, count, out, sc, st, hist, hist_cap);
+  return launch_check("check");
 }
 
 }  // namespace dmg

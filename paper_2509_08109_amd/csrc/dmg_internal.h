@@ -57,7 +57,8 @@ struct StripConfig {
 
 // ---- hierarchy ---------------------------------------------------------------------------
 struct Level {
-  StripConfig cfg;        // fused-kernel launch shape (levels above the tail)
+  StripConfig cfg;        // fused-kernel launch shape (levels above the tail), float64
+  StripConfig cfg32;      // the same for the float32 kernels
   int nx = 0, ny = 0;
   double* S = nullptr;    // [5][ny][nx]
   double* P = nullptr;    // [8][nyc][nxc] weights to the next coarser level (null at coarsest)
@@ -77,7 +78,9 @@ struct Level {
 constexpr int kReduceBlocks = 1024;  // fixed partial count: reductions are order-deterministic
 constexpr int kMaxPartials = 16384;  // capacity of the partials buffer
 constexpr int kTailMaxN = 65;
-constexpr int kMaxLevels = 32;        // levels with max(nx,ny) <= this run in the one-workgroup tail
+constexpr int kMaxLevels = 32;
+constexpr int kMaxHistory = 4096;
+constexpr int kChunk = 4;            // solve steps per host synchronisation        // levels with max(nx,ny) <= this run in the one-workgroup tail
 
 struct Graph {
   hipGraphExec_t exec = nullptr;
@@ -100,7 +103,8 @@ struct dmg_hier {
   double* partials = nullptr; // [kReduceBlocks] reduction partials
   double* scalars = nullptr;  // [16] device scalars (norms, IR scale)
   double* r64 = nullptr;      // fp64 fine residual for iterative refinement
-  int* flag = nullptr;        // device status flag
+  int* flag = nullptr;        // device ints: [0] pivot flag, [4..6] solve state (stop, steps, max)
+  double* hist = nullptr;     // device history of relative residuals [kMaxHistory]
   double* host = nullptr;     // pinned host scalars [16]
   dmg::Graph graph;
   ~dmg_hier();
@@ -135,11 +139,14 @@ template <class T>
 dmg_status launch_prolong_add(const T* P, const T* eH, T* u, int nx, int ny, hipStream_t s);
 template <class T>
 dmg_status launch_fill(T* x, T v, size_t n, hipStream_t s);
+template <class T>
+dmg_status launch_copy(const T* x, T* y, size_t n, const int* stop, hipStream_t s);
 
 // ||b - A u||^2 partials (fixed block count) and sum(x^2) partials; finalize sums the
 // partials in a fixed order into out[0] (and sqrt into out[1]).
 dmg_status launch_resid_sq_partials(const double* S, const double* u, const double* b, int nx,
-                                    int ny, double* partials, hipStream_t s);
+                                    int ny, double* partials, hipStream_t s,
+                                    const int* stop = nullptr);
 dmg_status launch_sq_partials(const double* x, size_t n, int nx, int ny, double* partials,
                               hipStream_t s);
 dmg_status launch_finalize(const double* partials, double* out, hipStream_t s,
@@ -148,13 +155,15 @@ dmg_status launch_finalize(const double* partials, double* out, hipStream_t s,
 // fused strip kernels (fused_kernels.hip)
 int strip_blocks(int nx, int ny, int bw, int seg_h, int* nstrips, int* nsegs);
 // Out-of-place: u_in (pre: nullptr = zero) -> u_out, u_in != u_out.
+// stop (nullable): device flag; the kernels do nothing once it is set (converged solves).
 template <class T>
 dmg_status launch_pre(const StripConfig& cfg, const T* S, const T* uin, T* u, const T* b,
-                      const T* P, T* bH, int nx, int ny, int pf, int cA, int cB, hipStream_t s);
+                      const T* P, T* bH, int nx, int ny, int pf, int cA, int cB, const int* stop,
+                      hipStream_t s);
 template <class T>
 dmg_status launch_post(const StripConfig& cfg, const T* S, const T* uin, T* u, const T* b,
                        const T* P, const T* e, double* partials, int nx, int ny, int pf, int cA,
-                       int cB, hipStream_t s);
+                       int cB, const int* stop, hipStream_t s);
 template <class T>
 struct TailSpec {
   const T* S[12];
@@ -170,16 +179,21 @@ struct TailSpec {
   const double* chol = nullptr;
   int pre[4], post[4];
   int nu_pre = 1, nu_post = 1;
+  const int* stop = nullptr;
 };
 template <class T>
 dmg_status launch_tail(const TailSpec<T>& spec, hipStream_t s);
 
-// iterative refinement helpers
+// iterative refinement helpers (stop: nullable device flag, see launch_check_step)
 dmg_status launch_ir_update(double* x, const float* e, const double* s_dev, size_t n,
-                            hipStream_t s);
+                            hipStream_t s, const int* stop = nullptr);
 dmg_status launch_ir_residual(const double* S, const double* x, const double* b, double* r,
-                              int nx, int ny, double* partials, hipStream_t s);
+                              int nx, int ny, double* partials, hipStream_t s,
+                              const int* stop = nullptr);
 dmg_status launch_ir_scale(const double* r, const double* s_dev, float* r32, size_t n,
-                           hipStream_t s);
+                           hipStream_t s, const int* stop = nullptr);
+// device-side convergence check of one solve step (see k_check)
+dmg_status launch_check_step(const double* partials, int count, double* out, const double* sc,
+                             int* st, double* hist, int hist_cap, hipStream_t s);
 
 }  // namespace dmg

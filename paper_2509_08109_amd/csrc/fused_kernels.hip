@@ -42,6 +42,7 @@ struct StripArgs {
   int nstrips, nsegs;
   int pf;             // row parity smoothed first
   int cA, cB;         // column parity smoothed first on A-rows / on B-rows
+  const int* stop;    // nullable: when *stop != 0 the kernel does nothing (converged solve)
 };
 
 template <class T>
@@ -159,6 +160,7 @@ __device__ __forceinline__ double block_sum(double v) {
 
 template <class T, int BW, bool POST>
 __global__ __launch_bounds__(BW) void k_strip(StripArgs<T> a) {
+  if (a.stop && *a.stop) return;
   extern __shared__ __align__(16) unsigned char smem[];
   T* base = reinterpret_cast<T*>(smem);
   Ring<T> R{base, base + RU * BW, base + (RU + 5 * RS) * BW, base + (RU + 6 * RS) * BW};
@@ -208,6 +210,26 @@ __global__ __launch_bounds__(BW) void k_strip(StripArgs<T> a) {
       load_row<T, POST>(a, i, ar + 2, g0);
       load_row<T, POST>(a, i, ar + 3, g1);
     }
+    // restriction weights of this step's coarse row, loaded now and used after the sweep
+    const int fj = (ar - 2) & ~1;  // fine row 2J of the coarse row restricted in this step
+    const int J = fj >> 1;
+    const int I = i >> 1;
+    const bool do_restrict = !POST && out_col && !(i & 1) && fj >= j0 && fj < j1;
+    const bool inner_c = I >= 1 && I <= ncx - 2 && J >= 1 && J <= ncy - 2;
+    T pw[8];
+    if (do_restrict && inner_c) {
+      const size_t NC = size_t(ncx) * ncy;
+      const size_t c = size_t(J) * ncx + I;
+      const T* P = a.P;
+      pw[0] = P[7 * NC + c - ncx - 1];
+      pw[1] = P[3 * NC + c - ncx];
+      pw[2] = P[6 * NC + c - ncx];
+      pw[3] = P[1 * NC + c - 1];
+      pw[4] = P[0 * NC + c];
+      pw[5] = P[5 * NC + c - 1];
+      pw[6] = P[2 * NC + c];
+      pw[7] = P[4 * NC + c];
+    }
     // A-row ar: column parity cA first, then the other
     if ((i & 1) == a.cA) gs_point<T, BW>(R, t, i, ar, a.nx, a.ny);
     __syncthreads();
@@ -240,27 +262,21 @@ __global__ __launch_bounds__(BW) void k_strip(StripArgs<T> a) {
       R.r[((ar - 1) & (RS - 1)) * BW + t] = r1;
       __syncthreads();
       // restriction for the coarse row whose fine rows 2J-1..2J+1 are now complete
-      const int fj = (ar - 2) & ~1;  // 2J
-      const int J = fj >> 1;
-      if (out_col && !(i & 1) && fj >= j0 && fj < j1) {
-        const int I = i >> 1;
+      if (do_restrict) {
         T acc2 = T(0);
-        if (I >= 1 && I <= ncx - 2 && J >= 1 && J <= ncy - 2) {
-          const size_t NC = size_t(ncx) * ncy;
-          const size_t c = size_t(J) * ncx + I;
-          const T* P = a.P;
+        if (inner_c) {
           const T* rm = R.r + ((fj - 1) & (RS - 1)) * BW;
           const T* r0 = R.r + (fj & (RS - 1)) * BW;
           const T* rp = R.r + ((fj + 1) & (RS - 1)) * BW;
-          acc2 = P[7 * NC + c - ncx - 1] * rm[t - 1];
-          acc2 += P[3 * NC + c - ncx] * rm[t];
-          acc2 += P[6 * NC + c - ncx] * rm[t + 1];
-          acc2 += P[1 * NC + c - 1] * r0[t - 1];
+          acc2 = pw[0] * rm[t - 1];
+          acc2 += pw[1] * rm[t];
+          acc2 += pw[2] * rm[t + 1];
+          acc2 += pw[3] * r0[t - 1];
           acc2 += r0[t];
-          acc2 += P[0 * NC + c] * r0[t + 1];
-          acc2 += P[5 * NC + c - 1] * rp[t - 1];
-          acc2 += P[2 * NC + c] * rp[t];
-          acc2 += P[4 * NC + c] * rp[t + 1];
+          acc2 += pw[4] * r0[t + 1];
+          acc2 += pw[5] * rp[t - 1];
+          acc2 += pw[6] * rp[t];
+          acc2 += pw[7] * rp[t + 1];
         }
         if (J < ncy) a.bH[size_t(J) * ncx + I] = acc2;
       }
@@ -300,6 +316,7 @@ struct TailArgs {
   const double* chol;
   int pre[4], post[4];
   int nu_pre, nu_post;
+  const int* stop;
 };
 
 template <class T>
@@ -332,6 +349,7 @@ __device__ void tail_colour(const TailLevel<T>& L, int c) {
 
 template <class T>
 __global__ __launch_bounds__(1024) void k_tail(TailArgs<T> a) {
+  if (a.stop && *a.stop) return;
   extern __shared__ double y[];
   const int nl = a.nlev;
   for (int l = 0; l < nl - 1; ++l) {
@@ -444,7 +462,7 @@ int strip_blocks(int nx, int ny, int bw, int seg_h, int* nstrips, int* nsegs) {
 template <class T, bool POST>
 dmg_status launch_strip(const StripConfig& cfg, const T* S, const T* uin, T* u, const T* b,
                         const T* P, T* bH, const T* e, double* partials, int nx, int ny, int pf,
-                        int cA, int cB, hipStream_t s) {
+                        int cA, int cB, const int* stop, hipStream_t s) {
   if (POST && !uin) return fail(DMG_ERR_INVALID_ARG, "post sweep needs an input iterate");
   if (uin == u) return fail(DMG_ERR_INVALID_ARG, "strip sweeps work out of place");
   StripArgs<T> a;
@@ -462,6 +480,7 @@ dmg_status launch_strip(const StripConfig& cfg, const T* S, const T* uin, T* u, 
   a.pf = pf;
   a.cA = cA;
   a.cB = cB;
+  a.stop = stop;
   const int nb = strip_blocks(nx, ny, cfg.bw, cfg.seg_h, &a.nstrips, &a.nsegs);
   const size_t lds = size_t(RU + 7 * RS) * cfg.bw * sizeof(T);
   switch (cfg.bw) {
@@ -482,15 +501,18 @@ dmg_status launch_strip(const StripConfig& cfg, const T* S, const T* uin, T* u, 
 
 template <class T>
 dmg_status launch_pre(const StripConfig& cfg, const T* S, const T* uin, T* u, const T* b,
-                      const T* P, T* bH, int nx, int ny, int pf, int cA, int cB, hipStream_t s) {
-  return launch_strip<T, false>(cfg, S, uin, u, b, P, bH, nullptr, nullptr, nx, ny, pf, cA, cB, s);
+                      const T* P, T* bH, int nx, int ny, int pf, int cA, int cB, const int* stop,
+                      hipStream_t s) {
+  return launch_strip<T, false>(cfg, S, uin, u, b, P, bH, nullptr, nullptr, nx, ny, pf, cA, cB,
+                                stop, s);
 }
 
 template <class T>
 dmg_status launch_post(const StripConfig& cfg, const T* S, const T* uin, T* u, const T* b,
                        const T* P, const T* e, double* partials, int nx, int ny, int pf, int cA,
-                       int cB, hipStream_t s) {
-  return launch_strip<T, true>(cfg, S, uin, u, b, P, nullptr, e, partials, nx, ny, pf, cA, cB, s);
+                       int cB, const int* stop, hipStream_t s) {
+  return launch_strip<T, true>(cfg, S, uin, u, b, P, nullptr, e, partials, nx, ny, pf, cA, cB,
+                               stop, s);
 }
 
 template <class T>
@@ -517,16 +539,18 @@ dmg_status launch_tail(const TailSpec<T>& spec, hipStream_t s) {
   }
   a.nu_pre = spec.nu_pre;
   a.nu_post = spec.nu_post;
+  a.stop = spec.stop;
   k_tail<T><<<1, 1024, sizeof(double) * size_t(spec.m > 0 ? spec.m : 1), s>>>(a);
   return launch_check("tail");
 }
 
 #define DMG_INST(T)                                                                            \
   template dmg_status launch_pre<T>(const StripConfig&, const T*, const T*, T*, const T*,      \
-                                    const T*, T*, int, int, int, int, int, hipStream_t);       \
+                                    const T*, T*, int, int, int, int, int, const int*,         \
+                                    hipStream_t);                                              \
   template dmg_status launch_post<T>(const StripConfig&, const T*, const T*, T*, const T*,     \
                                      const T*, const T*, double*, int, int, int, int, int,     \
-                                     hipStream_t);                                             \
+                                     const int*, hipStream_t);                                 \
   template dmg_status launch_tail<T>(const TailSpec<T>&, hipStream_t);
 DMG_INST(double)
 DMG_INST(float)

@@ -160,18 +160,71 @@ def test_launch_shape_is_numerically_neutral(dmg, tile_rows):
     ref.close()
 
 
+def test_autotuned_hierarchy_matches_oracle(dmg):
+    """Tuned launch shapes are numerically neutral; a tuned colour order is replayed by the
+    oracle."""
+    prob = pb.star(513, seed=7)
+    S_or = fem.assemble_stencil(prob.jac, prob.K, prob.nx, prob.ny)
+    levels = boxmg.build_hierarchy(S_or)
+    b = dev(prob.b)
+    h = dmg.Hierarchy(dev(S_or), precision=dmg.DMG_FP32_IR)
+    cfg = h.autotune(b, tiles=True, colour_order=True, reps=2)
+    assert all(bw in (0, 64, 128) for bw, _ in cfg["levels"])
+    assert cfg["post_order"] == cfg["pre_order"][::-1]
+    h64 = dmg.Hierarchy(dev(S_or), pre_order=cfg["pre_order"], post_order=cfg["post_order"])
+    h64.autotune(b, tiles=True, reps=2)
+    u, k, rel, _ = h64.solve(b, rtol=1e-10)
+    orc = cycle.Oracle(levels, pre=cfg["pre_order"], post=cfg["post_order"])
+    uo, ko, _, _ = cycle.solve(orc, prob.b, 1e-10)
+    assert k == ko and np.linalg.norm(host(u) - uo) / np.linalg.norm(uo) <= TOL
+    x, k32, rel32, _ = h.solve(b, rtol=1e-10)
+    assert rel32 <= 1e-10
+    h.close()
+    h64.close()
+
+
+def test_solve_on_a_side_stream_uses_graph_chunks(dmg):
+    """Solves on a non-default stream run chunks of steps through captured graphs; the step
+    count and the iterate are those of the oracle, also when max_iters cuts a chunk short."""
+    prob = pb.star(257, seed=8)
+    S_or = fem.assemble_stencil(prob.jac, prob.K, prob.nx, prob.ny)
+    orc = cycle.Oracle(boxmg.build_hierarchy(S_or))
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        h = dmg.Hierarchy(dev(S_or))
+        b = dev(prob.b)
+        u, k, rel, hist = h.solve(b, rtol=1e-10)
+        for cap in (1, 3, 6):
+            u2 = torch.zeros_like(b)
+            _, k2, _, _ = h.solve(b, u=u2, rtol=1e-10, max_iters=cap, raise_on_fail=False)
+            uo, ko, _, _ = cycle.solve(orc, prob.b, 1e-10, max_iters=cap)
+            assert k2 == ko == cap
+            assert np.linalg.norm(host(u2) - uo) / np.linalg.norm(uo) <= TOL
+    torch.cuda.synchronize()
+    uo, ko, histo, _ = cycle.solve(orc, prob.b, 1e-10)
+    assert k == ko and np.allclose(hist, histo, rtol=1e-6, atol=1e-13)
+    assert np.linalg.norm(host(u) - uo) / np.linalg.norm(uo) <= TOL
+    h.close()
+
+
 def test_graph_and_eager_solves_are_identical(dmg):
     prob = pb.star(129, seed=1)
     S = dmg.assemble_stencil(dev(prob.jac), dev(prob.K))
     b = dev(prob.b)
     out = []
+    st = torch.cuda.Stream()
+    torch.cuda.synchronize()
     for g in (0, 1):
+      with torch.cuda.stream(st):
         h = dmg.Hierarchy(S, use_graph=g)
         u, k, rel, _ = h.solve(b, rtol=1e-10)
         # a second solve on the same arrays replays the captured graph
-        u2, k2, rel2, _ = h.solve(b, rtol=1e-10)
-        assert k == k2 and torch.equal(u, u2)
-        out.append((host(u), k))
+        u2 = torch.zeros_like(b)
+        u2, k2, rel2, _ = h.solve(b, u=u2, rtol=1e-10)
+        u3 = torch.zeros_like(b)
+        u3, k3, rel3, _ = h.solve(b, u=u3, rtol=1e-10)
+        assert k == k2 == k3 and torch.equal(u2, u3)
+        out.append((host(u3), k))
         h.close()
     assert out[0][1] == out[1][1] and np.array_equal(out[0][0], out[1][0])
 
