@@ -138,7 +138,7 @@ dmg_status dmg_vcycle(dmg_hier* h, double* u, const double* b, hipStream_t strea
 dmg_status dmg_sweep(dmg_hier* h, int32_t level, int32_t kind, double* u, const double* b,
                      hipStream_t stream);
 /* Autotuner.  flags bit 0: for every strip-kernel level pick the launch shape (workgroup width
- * in {64,128} columns, segment height in {2,...,128} rows) with the lowest measured time of its
+ * in {64,128} columns, also 256 for float32, segment height in {2,...,128} rows) with the lowest measured time of its
  * pre + post kernels (hipEvents, `reps` launches each, float64 and, for DMG_FP32_IR, float32
  * kernels separately) -- numerically neutral.  flags bit 1: pick the colour order with the
  * lowest measured solve time among the row-separable orders whose post order is the reverse of

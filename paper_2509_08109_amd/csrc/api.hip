@@ -406,7 +406,8 @@ dmg_status tune_levels(dmg_hier* h, int reps, hipStream_t s) {
     Level& L = h->L[l];
     StripConfig best = Prec<T>::cfg(L);
     float best_ms = 1e30f;
-    for (int bw : {64, 128}) {
+    for (int bw : {64, 128, 256}) {
+      if (bw == 256 && sizeof(T) == 8) continue;  // a 256-wide float64 ring exceeds 64 KiB of LDS
       for (int sh = 2; sh <= 128 && st == DMG_OK; sh *= 2) {
         int ns = 0, nseg = 0;
         if (strip_blocks(L.nx, L.ny, bw, sh, &ns, &nseg) > kMaxPartials) continue;

@@ -18,6 +18,8 @@
 //
 //   pre  : u_out <- 4-colour sweep(u_in, b) [u_in = 0: not read]; b_H <- P^T (b - A u_out)
 //   post : u_out <- 4-colour sweep(u_in + P e_H, b); optional partials of ||b - A u_out||^2
+#include <type_traits>
+
 #include "dmg_internal.h"
 
 namespace dmg {
@@ -45,51 +47,65 @@ struct StripArgs {
   const int* stop;    // nullable: when *stop != 0 the kernel does nothing (converged solve)
 };
 
+// Ring slots are taken relative to base = (first A-row) - 1: row j lives in u slot
+// (j - base) mod RU and in stencil/b/residual slot (j - base) mod RS.
+constexpr int umod(int x) { return ((x % RU) + RU) % RU; }
+constexpr int smod(int x) { return ((x % RS) + RS) % RS; }
+
+// This thread's column of the ring rows, in registers (slots are compile-time constants).
 template <class T>
-struct Ring {
-  T* u;   // [RU][BW]
-  T* S;   // [5][RS][BW]
-  T* b;   // [RS][BW]
-  T* r;   // [RS][BW]
+struct ColRing {
+  T u[RU];
+  T s[5][RS];  // C, W, S, SW, SE
+  T b[RS];
 };
 
-// Update (residual) of interior point (i, j) held in ring slot sj of thread t.
-template <class T, int BW>
-__device__ __forceinline__ T offdiag_l(const Ring<T>& R, int t, int j) {
-  const int tm = t > 0 ? t - 1 : 0, tp = t < BW - 1 ? t + 1 : BW - 1;
-  const int sj = j & (RS - 1), sjp = (j + 1) & (RS - 1);
-  const T* uj = R.u + (j & (RU - 1)) * BW;
-  const T* ujm = R.u + ((j - 1) & (RU - 1)) * BW;
-  const T* ujp = R.u + ((j + 1) & (RU - 1)) * BW;
-  const T* W = R.S + (1 * RS) * BW;
-  const T* Sv = R.S + (2 * RS) * BW;
-  const T* SW = R.S + (3 * RS) * BW;
-  const T* SE = R.S + (4 * RS) * BW;
-  const T sw = SW[sj * BW + t] * ujm[tm];
-  const T s = Sv[sj * BW + t] * ujm[t];
-  const T se = SE[sj * BW + t] * ujm[tp];
-  const T w = W[sj * BW + t] * uj[tm];
-  const T e = W[sj * BW + tp] * uj[tp];
-  const T nw = SE[sjp * BW + tm] * ujp[tm];
-  const T n = Sv[sjp * BW + t] * ujp[t];
-  const T ne = SW[sjp * BW + tp] * ujp[tp];
+// LDS rings: u of every column and the couplings that neighbouring columns read
+// (W of the right neighbour, SW of the upper-right and SE of the upper-left neighbour).
+template <class T>
+struct LdsRing {
+  T* u;   // [RU][BW]
+  T* W;   // [RS][BW]
+  T* SW;  // [RS][BW]
+  T* SE;  // [RS][BW]
+  T* r;   // [RS][BW] residuals (pre)
+};
+
+// Off-diagonal part of row j of the operator applied to u, j given by its slots.
+template <class T, int BW, int UM, int U0, int UP, int S0, int SP>
+__device__ __forceinline__ T offdiag_r(const ColRing<T>& c, const LdsRing<T>& L, int tm, int tp) {
+  const T sw = c.s[3][S0] * L.u[UM * BW + tm];
+  const T s = c.s[2][S0] * c.u[UM];
+  const T se = c.s[4][S0] * L.u[UM * BW + tp];
+  const T w = c.s[1][S0] * L.u[U0 * BW + tm];
+  const T e = L.W[S0 * BW + tp] * L.u[U0 * BW + tp];
+  const T nw = L.SE[SP * BW + tm] * L.u[UP * BW + tm];
+  const T n = c.s[2][SP] * c.u[UP];
+  const T ne = L.SW[SP * BW + tp] * L.u[UP * BW + tp];
   return ((((((sw + s) + se) + w) + e) + nw) + n) + ne;
 }
 
-template <class T, int BW>
-__device__ __forceinline__ void gs_point(const Ring<T>& R, int t, int i, int j, int nx, int ny) {
-  if (i < 1 || i > nx - 2 || j < 1 || j > ny - 2) return;
-  const T off = offdiag_l<T, BW>(R, t, j);
-  const int sj = j & (RS - 1);
-  R.u[(j & (RU - 1)) * BW + t] = (R.b[sj * BW + t] - off) / R.S[sj * BW + t];
+// Gauss-Seidel update of this thread's point on the row at relative index JR (interior only).
+template <class T, int BW, int JR>
+__device__ __forceinline__ void gs_col(ColRing<T>& c, const LdsRing<T>& L, int t, int tm, int tp,
+                                       bool interior) {
+  constexpr int U0 = umod(JR), UM = umod(JR - 1), UP = umod(JR + 1);
+  constexpr int S0 = smod(JR), SP = smod(JR + 1);
+  if (!interior) return;
+  const T off = offdiag_r<T, BW, UM, U0, UP, S0, SP>(c, L, tm, tp);
+  const T v = (c.b[S0] - off) / c.s[0][S0];
+  c.u[U0] = v;
+  L.u[U0 * BW + t] = v;
 }
 
-template <class T, int BW>
-__device__ __forceinline__ T resid_point(const Ring<T>& R, int t, int i, int j, int nx, int ny) {
-  if (i < 1 || i > nx - 2 || j < 1 || j > ny - 2) return T(0);
-  const T off = offdiag_l<T, BW>(R, t, j);
-  const int sj = j & (RS - 1);
-  return R.b[sj * BW + t] - (off + R.S[sj * BW + t] * R.u[(j & (RU - 1)) * BW + t]);
+template <class T, int BW, int JR>
+__device__ __forceinline__ T resid_col(const ColRing<T>& c, const LdsRing<T>& L, int tm, int tp,
+                                       bool interior) {
+  constexpr int U0 = umod(JR), UM = umod(JR - 1), UP = umod(JR + 1);
+  constexpr int S0 = smod(JR), SP = smod(JR + 1);
+  if (!interior) return T(0);
+  const T off = offdiag_r<T, BW, UM, U0, UP, S0, SP>(c, L, tm, tp);
+  return c.b[S0] - (off + c.s[0][S0] * c.u[U0]);
 }
 
 // Registers holding one prefetched row for this thread's column.
@@ -98,51 +114,112 @@ struct RowRegs {
   T u, b, s[5];
 };
 
-template <class T, bool POST>
+// Branch-free loads: every lane issues the same loads (out-of-range lanes read a clamped,
+// valid address and discard the value), so the number of memory operations in flight is the
+// same on every path and the compiler can wait for exactly the rows it consumes.
+template <class T, bool READ_U>
 __device__ __forceinline__ void load_row(const StripArgs<T>& a, int i, int j, RowRegs<T>& g) {
-  g.u = T(0);
-  g.b = T(0);
-#pragma unroll
-  for (int k = 0; k < 5; ++k) g.s[k] = T(0);
-  if (i < 0 || i >= a.nx || j < 0 || j >= a.ny) return;
+  const bool ok = i >= 0 && i < a.nx && j >= 0 && j < a.ny;
   const size_t N = size_t(a.nx) * a.ny;
-  const size_t v = size_t(j) * a.nx + i;
+  const size_t v = ok ? size_t(j) * a.nx + i : 0;
+  T s[5];
 #pragma unroll
-  for (int k = 0; k < 5; ++k) g.s[k] = a.S[k * N + v];
-  g.b = a.b[v];
-  if (POST) {
-    T uo = a.uin[v];
-    if (a.e && i >= 1 && i <= a.nx - 2 && j >= 1 && j <= a.ny - 2) {
-      const int ncx = (a.nx + 1) / 2, ncy = (a.ny + 1) / 2;
-      const size_t NC = size_t(ncx) * ncy;
-      const size_t c = size_t(j >> 1) * ncx + (i >> 1);
-      const T* P = a.P;
-      const T* e = a.e;
-      T corr;
-      if (!(i & 1) && !(j & 1)) {
-        corr = e[c];
-      } else if ((i & 1) && !(j & 1)) {
-        corr = P[c] * e[c] + P[NC + c] * e[c + 1];
-      } else if (!(i & 1) && (j & 1)) {
-        corr = P[2 * NC + c] * e[c] + P[3 * NC + c] * e[c + ncx];
-      } else {
-        corr = ((P[4 * NC + c] * e[c] + P[5 * NC + c] * e[c + 1]) + P[6 * NC + c] * e[c + ncx]) +
-               P[7 * NC + c] * e[c + ncx + 1];
-      }
-      uo = uo + corr;
-    }
-    g.u = uo;
-  } else if (a.uin) {
-    g.u = a.uin[v];
-  }
+  for (int k = 0; k < 5; ++k) s[k] = a.S[k * N + v];
+  const T bb = a.b[v];
+  T uu = T(0);
+  if (READ_U) uu = a.uin[v];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) g.s[k] = ok ? s[k] : T(0);
+  g.b = ok ? bb : T(0);
+  g.u = ok ? uu : T(0);
 }
 
-template <class T, int BW>
-__device__ __forceinline__ void store_row(const Ring<T>& R, int t, int j, const RowRegs<T>& g) {
-  R.u[(j & (RU - 1)) * BW + t] = g.u;
-  R.b[(j & (RS - 1)) * BW + t] = g.b;
+template <class T, int BW, int JR>
+__device__ __forceinline__ void store_row(ColRing<T>& c, const LdsRing<T>& L, int t,
+                                          const RowRegs<T>& g) {
+  constexpr int U0 = umod(JR), S0 = smod(JR);
+  c.u[U0] = g.u;
+  c.b[S0] = g.b;
 #pragma unroll
-  for (int k = 0; k < 5; ++k) R.S[(k * RS + (j & (RS - 1))) * BW + t] = g.s[k];
+  for (int k = 0; k < 5; ++k) c.s[k][S0] = g.s[k];
+  L.u[U0 * BW + t] = g.u;
+  L.W[S0 * BW + t] = g.s[1];
+  L.SW[S0 * BW + t] = g.s[3];
+  L.SE[S0 * BW + t] = g.s[4];
+}
+
+// (P e)(i, j) for interior fine point (i, j), read straight from global memory.
+template <class T>
+__device__ __forceinline__ T prolong_global(const StripArgs<T>& a, int i, int j) {
+  const int ncx = (a.nx + 1) / 2, ncy = (a.ny + 1) / 2;
+  const size_t NC = size_t(ncx) * ncy;
+  const size_t c = size_t(j >> 1) * ncx + (i >> 1);
+  const T* P = a.P;
+  const T* e = a.e;
+  if (!(i & 1) && !(j & 1)) return e[c];
+  if ((i & 1) && !(j & 1)) return P[c] * e[c] + P[NC + c] * e[c + 1];
+  if (!(i & 1) && (j & 1)) return P[2 * NC + c] * e[c] + P[3 * NC + c] * e[c + ncx];
+  return ((P[4 * NC + c] * e[c] + P[5 * NC + c] * e[c + 1]) + P[6 * NC + c] * e[c + ncx]) +
+         P[7 * NC + c] * e[c + ncx + 1];
+}
+
+// Coarse data of one row step of the post kernel (two fine rows, one of each parity), one
+// coarse column per thread (threads t < CW): slot 0 e(J_even), 1-2 P0/P1(J_even),
+// 3-4 e(J_odd), e(J_odd+1), 5-10 P2..P7(J_odd).
+constexpr int kCoarseSlots = 11;
+
+template <class T>
+struct CoarseRegs {
+  T v[kCoarseSlots];
+};
+
+template <class T>
+__device__ __forceinline__ void load_coarse(const StripArgs<T>& a, int I, int r0,
+                                            CoarseRegs<T>& c) {
+  const int ncx = (a.nx + 1) / 2, ncy = (a.ny + 1) / 2;
+  const int je = (r0 & 1) ? (r0 + 1) >> 1 : r0 >> 1;  // coarse row of the even fine row
+  const int jo = r0 >> 1;                              // coarse row J of the odd fine row 2J+1
+  const bool okI = I >= 0 && I < ncx;
+  const bool oke = okI && je >= 0 && je < ncy;
+  const bool oko = okI && jo >= 0 && jo < ncy;
+  const bool oko1 = oko && jo + 1 < ncy;
+  const size_t NC = size_t(ncx) * ncy;
+  const size_t ce = oke ? size_t(je) * ncx + I : 0;
+  const size_t co = oko ? size_t(jo) * ncx + I : 0;
+  const size_t co1 = oko1 ? co + ncx : 0;
+  const T* P = a.P;
+  const T* e = a.e;
+  T v[kCoarseSlots];
+  v[0] = e[ce];
+  v[1] = P[ce];
+  v[2] = P[NC + ce];
+  v[3] = e[co];
+  v[4] = e[co1];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) v[5 + k] = P[(2 + k) * NC + co];
+  c.v[0] = oke ? v[0] : T(0);
+  c.v[1] = oke ? v[1] : T(0);
+  c.v[2] = oke ? v[2] : T(0);
+  c.v[3] = oko ? v[3] : T(0);
+  c.v[4] = oko1 ? v[4] : T(0);
+#pragma unroll
+  for (int k = 5; k < kCoarseSlots; ++k) c.v[k] = oko ? v[k] : T(0);
+}
+
+// (P e)(i, j) from the staged coarse rows; k = local coarse column of i.
+template <class T>
+__device__ __forceinline__ T prolong_lds(const T* cb, int cw, int k, int i, int j) {
+  if (!(j & 1)) {
+    const T* e = cb;
+    if (!(i & 1)) return e[k];
+    return cb[cw + k] * e[k] + cb[2 * cw + k] * e[k + 1];
+  }
+  const T* e0 = cb + 3 * cw;
+  const T* e1 = cb + 4 * cw;
+  const T* Pq = cb + 5 * cw;  // P2..P7
+  if (!(i & 1)) return Pq[k] * e0[k] + Pq[cw + k] * e1[k];
+  return ((Pq[2 * cw + k] * e0[k] + Pq[3 * cw + k] * e0[k + 1]) + Pq[4 * cw + k] * e1[k]) +
+         Pq[5 * cw + k] * e1[k + 1];
 }
 
 __device__ __forceinline__ double block_sum(double v) {
@@ -158,12 +235,27 @@ __device__ __forceinline__ double block_sum(double v) {
   return t;
 }
 
-template <class T, int BW, bool POST>
+template <int BW>
+constexpr int coarse_width() { return BW / 2 + 2; }
+
+template <int BW>
+constexpr int strip_lds_elems(bool post) {
+  return (RU + 4 * RS) * BW + (post ? 2 * kCoarseSlots * coarse_width<BW>() : 0);
+}
+
+// MODE: 0 pre from u = 0, 1 pre from u_in, 2 post with prolongation, 3 post without.
+template <class T, int BW, int MODE>
 __global__ __launch_bounds__(BW) void k_strip(StripArgs<T> a) {
+  constexpr bool POST = MODE >= 2;
+  constexpr bool READ_U = MODE != 0;
+  constexpr bool prol = MODE == 2;
   if (a.stop && *a.stop) return;
   extern __shared__ __align__(16) unsigned char smem[];
-  T* base = reinterpret_cast<T*>(smem);
-  Ring<T> R{base, base + RU * BW, base + (RU + 5 * RS) * BW, base + (RU + 6 * RS) * BW};
+  T* base_l = reinterpret_cast<T*>(smem);
+  LdsRing<T> L{base_l, base_l + RU * BW, base_l + (RU + RS) * BW, base_l + (RU + 2 * RS) * BW,
+               base_l + (RU + 3 * RS) * BW};
+  constexpr int CW = coarse_width<BW>();
+  T* cbuf = base_l + (RU + 4 * RS) * BW;  // post: 2 x kCoarseSlots x CW staged coarse rows
 
   // XCD-aware tile order: the hardware hands workgroup ids to the 8 XCDs round-robin, so
   // give each XCD a contiguous run of tiles (adjacent strips and segments share halos in
@@ -176,9 +268,11 @@ __global__ __launch_bounds__(BW) void k_strip(StripArgs<T> a) {
   const int strip = active ? tile % a.nstrips : 0;
 
   const int t = threadIdx.x;
+  const int tm = t > 0 ? t - 1 : 0, tp = t < BW - 1 ? t + 1 : BW - 1;
   const int out_w = BW - 2 * HALO;
   const int x0 = strip * out_w;
   const int i = x0 - HALO + t;
+  const int cI = ((x0 - HALO) >> 1) + t;  // coarse column staged by thread t (t < CW)
   const int j0 = seg * a.seg_h;
   const int j1 = min(j0 + a.seg_h, a.ny);
   // first A-row: the largest row of parity pf not after j0-2 (pre) / j0-1 (post)
@@ -186,88 +280,123 @@ __global__ __launch_bounds__(BW) void k_strip(StripArgs<T> a) {
   const int a0 = lim - (((lim - a.pf) % 2) + 2) % 2;
   // last A-row: residual rows up to j1-1 must be complete -> front a >= j1
   const int alast = j1 + (((j1 - a.pf) % 2) + 2) % 2;
+  const int base = a0 - 1;
+  const bool interior_i = i >= 1 && i <= a.nx - 2;
+  const bool out_col = active && t >= HALO && t < BW - HALO && i < a.nx;
+  const int ncx = (a.nx + 1) / 2, ncy = (a.ny + 1) / 2;
+  auto row_ok = [&](int j) { return interior_i && j >= 1 && j <= a.ny - 2; };
 
-  // zero the ring, then prime it with row a0-1
-  for (int k = t; k < (RU + 7 * RS) * BW; k += BW) base[k] = T(0);
+  ColRing<T> c;
+#pragma unroll
+  for (int k = 0; k < RU; ++k) c.u[k] = T(0);
+#pragma unroll
+  for (int k = 0; k < RS; ++k) {
+    c.b[k] = T(0);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) c.s[q][k] = T(0);
+  }
+  for (int k = t; k < (RU + 4 * RS) * BW; k += BW) base_l[k] = T(0);
   __syncthreads();
-  RowRegs<T> g0, g1;
+  RowRegs<T> gA0, gA1, gB0, gB1;
+  CoarseRegs<T> cr;
   if (active) {
-    load_row<T, POST>(a, i, a0 - 1, g0);
-    store_row<T, BW>(R, t, a0 - 1, g0);
-    load_row<T, POST>(a, i, a0, g0);
-    load_row<T, POST>(a, i, a0 + 1, g1);
+    load_row<T, READ_U>(a, i, a0 - 1, gA0);
+    if (prol && row_ok(a0 - 1)) gA0.u = gA0.u + prolong_global<T>(a, i, a0 - 1);
+    store_row<T, BW, 0>(c, L, t, gA0);
+    if (prol) {
+      load_coarse<T>(a, cI, a0, cr);
+      if (t < CW) {
+#pragma unroll
+        for (int k = 0; k < kCoarseSlots; ++k) cbuf[k * CW + t] = cr.v[k];
+      }
+    }
+    load_row<T, READ_U>(a, i, a0, gA0);
+    load_row<T, READ_U>(a, i, a0 + 1, gA1);
+    load_row<T, READ_U>(a, i, a0 + 2, gB0);
+    load_row<T, READ_U>(a, i, a0 + 3, gB1);
   }
   __syncthreads();
   double acc = 0.0;
-  const bool out_col = active && t >= HALO && t < BW - HALO && i < a.nx;
-  const int ncx = (a.nx + 1) / 2, ncy = (a.ny + 1) / 2;
 
-  for (int ar = a0; active && ar <= alast; ar += 2) {
-    store_row<T, BW>(R, t, ar, g0);
-    store_row<T, BW>(R, t, ar + 1, g1);
-    __syncthreads();
-    if (ar + 2 <= alast) {  // prefetch the next two rows while this step computes
-      load_row<T, POST>(a, i, ar + 2, g0);
-      load_row<T, POST>(a, i, ar + 3, g1);
+  // One row step with ar = base + 1 + 2K (mod the ring period): smooth A-row ar and B-row
+  // ar-1 from the rows in (g0, g1), then prefetch the rows two steps ahead into (g0, g1).
+  auto step = [&](auto KC, int ar, RowRegs<T>& g0, RowRegs<T>& g1) {
+    constexpr int K = decltype(KC)::value;
+    constexpr int JA = 1 + 2 * K;  // relative index of A-row ar
+    if (prol) {
+      const T* cb = cbuf + (K & 1) * kCoarseSlots * CW;
+      const int kk = t >> 1;
+      if (row_ok(ar)) g0.u = g0.u + prolong_lds<T>(cb, CW, kk, i, ar);
+      if (row_ok(ar + 1)) g1.u = g1.u + prolong_lds<T>(cb, CW, kk, i, ar + 1);
     }
-    // restriction weights of this step's coarse row, loaded now and used after the sweep
+    store_row<T, BW, JA>(c, L, t, g0);
+    store_row<T, BW, JA + 1>(c, L, t, g1);
+    __syncthreads();
+    // loads consumed at the end of this step first (vector memory returns in issue order),
+    // then the rows of the step after next
+    if (prol) load_coarse<T>(a, cI, ar + 2, cr);
     const int fj = (ar - 2) & ~1;  // fine row 2J of the coarse row restricted in this step
     const int J = fj >> 1;
     const int I = i >> 1;
     const bool do_restrict = !POST && out_col && !(i & 1) && fj >= j0 && fj < j1;
     const bool inner_c = I >= 1 && I <= ncx - 2 && J >= 1 && J <= ncy - 2;
     T pw[8];
-    if (do_restrict && inner_c) {
+    if (!POST) {
       const size_t NC = size_t(ncx) * ncy;
-      const size_t c = size_t(J) * ncx + I;
+      const size_t cc = (do_restrict && inner_c) ? size_t(J) * ncx + I : size_t(ncx) + 1;
       const T* P = a.P;
-      pw[0] = P[7 * NC + c - ncx - 1];
-      pw[1] = P[3 * NC + c - ncx];
-      pw[2] = P[6 * NC + c - ncx];
-      pw[3] = P[1 * NC + c - 1];
-      pw[4] = P[0 * NC + c];
-      pw[5] = P[5 * NC + c - 1];
-      pw[6] = P[2 * NC + c];
-      pw[7] = P[4 * NC + c];
+      pw[0] = P[7 * NC + cc - ncx - 1];
+      pw[1] = P[3 * NC + cc - ncx];
+      pw[2] = P[6 * NC + cc - ncx];
+      pw[3] = P[1 * NC + cc - 1];
+      pw[4] = P[0 * NC + cc];
+      pw[5] = P[5 * NC + cc - 1];
+      pw[6] = P[2 * NC + cc];
+      pw[7] = P[4 * NC + cc];
     }
-    // A-row ar: column parity cA first, then the other
-    if ((i & 1) == a.cA) gs_point<T, BW>(R, t, i, ar, a.nx, a.ny);
+    load_row<T, READ_U>(a, i, ar + 4, g0);
+    load_row<T, READ_U>(a, i, ar + 5, g1);
+    // A-row ar: column parity cA first, then the other; then B-row ar-1
+    const bool okA = row_ok(ar), okB = row_ok(ar - 1);
+    const bool firstA = (i & 1) == a.cA, firstB = (i & 1) == a.cB;
+    gs_col<T, BW, JA>(c, L, t, tm, tp, okA && firstA);
     __syncthreads();
-    if ((i & 1) != a.cA) gs_point<T, BW>(R, t, i, ar, a.nx, a.ny);
+    gs_col<T, BW, JA>(c, L, t, tm, tp, okA && !firstA);
     __syncthreads();
-    // B-row ar-1
-    if ((i & 1) == a.cB) gs_point<T, BW>(R, t, i, ar - 1, a.nx, a.ny);
+    gs_col<T, BW, JA - 1>(c, L, t, tm, tp, okB && firstB);
     __syncthreads();
-    if ((i & 1) != a.cB) gs_point<T, BW>(R, t, i, ar - 1, a.nx, a.ny);
+    gs_col<T, BW, JA - 1>(c, L, t, tm, tp, okB && !firstB);
     __syncthreads();
     // rows ar-1 and ar are final: write them out
     if (out_col) {
-      const int rows[2] = {ar - 1, ar};
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int j = rows[q];
-        if (j >= j0 && j < j1) a.u[size_t(j) * a.nx + i] = R.u[(j & (RU - 1)) * BW + t];
-      }
+      if (ar - 1 >= j0 && ar - 1 < j1) a.u[size_t(ar - 1) * a.nx + i] = c.u[umod(JA - 1)];
+      if (ar >= j0 && ar < j1) a.u[size_t(ar) * a.nx + i] = c.u[umod(JA)];
     }
     // residual rows ar-2 and ar-1
-    const T r2 = resid_point<T, BW>(R, t, i, ar - 2, a.nx, a.ny);
-    const T r1 = resid_point<T, BW>(R, t, i, ar - 1, a.nx, a.ny);
+    const T r2 = resid_col<T, BW, JA - 2>(c, L, tm, tp, row_ok(ar - 2));
+    const T r1 = resid_col<T, BW, JA - 1>(c, L, tm, tp, okB);
     if (POST) {
       if (out_col && a.partials) {
         if (ar - 2 >= j0 && ar - 2 < j1) acc += double(r2) * double(r2);
         if (ar - 1 >= j0 && ar - 1 < j1) acc += double(r1) * double(r1);
       }
+      if (prol && t < CW) {  // stage the next step's coarse rows
+        T* cbn = cbuf + ((K + 1) & 1) * kCoarseSlots * CW;
+#pragma unroll
+        for (int k = 0; k < kCoarseSlots; ++k) cbn[k * CW + t] = cr.v[k];
+      }
     } else {
-      R.r[((ar - 2) & (RS - 1)) * BW + t] = r2;
-      R.r[((ar - 1) & (RS - 1)) * BW + t] = r1;
+      L.r[smod(JA - 2) * BW + t] = r2;
+      L.r[smod(JA - 1) * BW + t] = r1;
       __syncthreads();
       // restriction for the coarse row whose fine rows 2J-1..2J+1 are now complete
       if (do_restrict) {
         T acc2 = T(0);
         if (inner_c) {
-          const T* rm = R.r + ((fj - 1) & (RS - 1)) * BW;
-          const T* r0 = R.r + (fj & (RS - 1)) * BW;
-          const T* rp = R.r + ((fj + 1) & (RS - 1)) * BW;
+          const int rel = fj - base;  // relative index of fine row 2J
+          const T* rm = L.r + smod(rel - 1) * BW;
+          const T* r0 = L.r + smod(rel) * BW;
+          const T* rp = L.r + smod(rel + 1) * BW;
           acc2 = pw[0] * rm[t - 1];
           acc2 += pw[1] * rm[t];
           acc2 += pw[2] * rm[t + 1];
@@ -282,10 +411,20 @@ __global__ __launch_bounds__(BW) void k_strip(StripArgs<T> a) {
       }
     }
     __syncthreads();
+  };
+
+  // steps k = 0, 1, 2, ...: ring slots repeat every 4 steps; the prefetch registers alternate
+  for (int ar = a0, k = 0; active && ar <= alast; ar += 2, ++k) {
+    switch (k & 3) {
+      case 0: step(std::integral_constant<int, 0>{}, ar, gA0, gA1); break;
+      case 1: step(std::integral_constant<int, 1>{}, ar, gB0, gB1); break;
+      case 2: step(std::integral_constant<int, 2>{}, ar, gA0, gA1); break;
+      default: step(std::integral_constant<int, 3>{}, ar, gB0, gB1); break;
+    }
   }
   if (POST && a.partials) {
-    const double s = block_sum(acc);
-    if (t == 0) a.partials[blockIdx.x] = s;
+    const double sacc = block_sum(acc);
+    if (t == 0) a.partials[blockIdx.x] = sacc;
   }
 }
 
@@ -482,20 +621,25 @@ dmg_status launch_strip(const StripConfig& cfg, const T* S, const T* uin, T* u, 
   a.cB = cB;
   a.stop = stop;
   const int nb = strip_blocks(nx, ny, cfg.bw, cfg.seg_h, &a.nstrips, &a.nsegs);
-  const size_t lds = size_t(RU + 7 * RS) * cfg.bw * sizeof(T);
+  const size_t lds =
+      (size_t(RU + 4 * RS) * cfg.bw + (POST ? size_t(2 * kCoarseSlots) * (cfg.bw / 2 + 2) : 0)) *
+      sizeof(T);
+  const int mode = POST ? (e ? 2 : 3) : (uin ? 1 : 0);
+#define DMG_STRIP_BW(BWV)                                                   \
+  switch (mode) {                                                           \
+    case 0: k_strip<T, BWV, 0><<<nb, BWV, lds, s>>>(a); break;              \
+    case 1: k_strip<T, BWV, 1><<<nb, BWV, lds, s>>>(a); break;              \
+    case 2: k_strip<T, BWV, 2><<<nb, BWV, lds, s>>>(a); break;              \
+    default: k_strip<T, BWV, 3><<<nb, BWV, lds, s>>>(a); break;             \
+  }
   switch (cfg.bw) {
-    case 64:
-      k_strip<T, 64, POST><<<nb, 64, lds, s>>>(a);
-      break;
-    case 128:
-      k_strip<T, 128, POST><<<nb, 128, lds, s>>>(a);
-      break;
-    case 256:
-      k_strip<T, 256, POST><<<nb, 256, lds, s>>>(a);
-      break;
+    case 64: DMG_STRIP_BW(64) break;
+    case 128: DMG_STRIP_BW(128) break;
+    case 256: DMG_STRIP_BW(256) break;
     default:
       return fail(DMG_ERR_INVALID_ARG, "unsupported strip width %d", cfg.bw);
   }
+#undef DMG_STRIP_BW
   return launch_check(POST ? "strip_post" : "strip_pre");
 }
 
