@@ -413,14 +413,16 @@ __global__ __launch_bounds__(BW) void k_strip(StripArgs<T> a) {
     __syncthreads();
   };
 
-  // steps k = 0, 1, 2, ...: ring slots repeat every 4 steps; the prefetch registers alternate
-  for (int ar = a0, k = 0; active && ar <= alast; ar += 2, ++k) {
-    switch (k & 3) {
-      case 0: step(std::integral_constant<int, 0>{}, ar, gA0, gA1); break;
-      case 1: step(std::integral_constant<int, 1>{}, ar, gB0, gB1); break;
-      case 2: step(std::integral_constant<int, 2>{}, ar, gA0, gA1); break;
-      default: step(std::integral_constant<int, 3>{}, ar, gB0, gB1); break;
-    }
+  // steps k = 0, 1, 2, ...: ring slots repeat every 4 steps and the prefetch registers
+  // alternate, so the period is unrolled straight-line (uniform early exits)
+  for (int ar = a0; active && ar <= alast; ar += 8) {
+    step(std::integral_constant<int, 0>{}, ar, gA0, gA1);
+    if (ar + 2 > alast) break;
+    step(std::integral_constant<int, 1>{}, ar + 2, gB0, gB1);
+    if (ar + 4 > alast) break;
+    step(std::integral_constant<int, 2>{}, ar + 4, gA0, gA1);
+    if (ar + 6 > alast) break;
+    step(std::integral_constant<int, 3>{}, ar + 6, gB0, gB1);
   }
   if (POST && a.partials) {
     const double sacc = block_sum(acc);
