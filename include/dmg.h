@@ -72,7 +72,10 @@ typedef struct dmg_options {
   int32_t use_graph;     /* capture one cycle in a hipGraph and replay it (default 1)      */
   int32_t tile_rows;     /* launch-shape knob of the fused sweep kernels; 0 = built-in
                             table.  Numerically neutral.                                   */
-  int32_t reserved[7];
+  int32_t strip_kernel;  /* implementation of the large-level sweeps before autotuning:
+                            0 = LDS strips, 1 = one-wavefront strips (default 1).
+                            Numerically neutral.                                           */
+  int32_t reserved[6];
 } dmg_options;
 
 typedef struct dmg_hier dmg_hier;
@@ -137,8 +140,9 @@ dmg_status dmg_vcycle(dmg_hier* h, double* u, const double* b, hipStream_t strea
  * level must be above the coarse tail (max(nx,ny) > 65); DMG_ERR_INVALID_ARG otherwise. */
 dmg_status dmg_sweep(dmg_hier* h, int32_t level, int32_t kind, double* u, const double* b,
                      hipStream_t stream);
-/* Autotuner.  flags bit 0: for every strip-kernel level pick the launch shape (workgroup width
- * in {64,128} columns, also 256 for float32, segment height in {2,...,128} rows) with the lowest measured time of its
+/* Autotuner.  flags bit 0: for every strip-kernel level pick the kernel and launch shape
+ * (LDS strips of {64,128} columns, also 256 for float32, or one-wavefront strips that exchange
+ * neighbour columns between lanes; segment height in {2,...,128} rows) with the lowest measured time of its
  * pre + post kernels (hipEvents, `reps` launches each, float64 and, for DMG_FP32_IR, float32
  * kernels separately) -- numerically neutral.  flags bit 1: pick the colour order with the
  * lowest measured solve time among the row-separable orders whose post order is the reverse of
@@ -147,8 +151,9 @@ dmg_status dmg_sweep(dmg_hier* h, int32_t level, int32_t kind, double* u, const 
  * of the level-0 shape.  Synchronous.  Invalidates captured graphs. */
 dmg_status dmg_autotune(dmg_hier* h, double* u, const double* b, int32_t flags, int32_t reps,
                         hipStream_t stream);
-/* The launch shape of level `level` (bw, seg_h; 0,0 for tail levels) and the colour orders in
- * use (host arrays of 4, nullable). */
+/* The launch shape of level `level`: bw = strip width in columns of the LDS strip kernel, or 1
+ * for the one-wavefront kernel; seg_h = rows per segment (0,0 for tail levels); and the colour
+ * orders in use (host arrays of 4, nullable). */
 dmg_status dmg_hier_config(const dmg_hier* h, int32_t level, int32_t* bw, int32_t* seg_h,
                            int32_t* pre_order, int32_t* post_order);
 /* ||b - A u||_2 over interior vertices (deterministic fixed-order reduction).  Synchronous. */

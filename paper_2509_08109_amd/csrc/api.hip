@@ -56,6 +56,8 @@ dmg_status check_options(const dmg_options* o) {
     return fail(DMG_ERR_INVALID_ARG, "unknown precision %d", o->precision);
   if (o->inner_cycles < 1 || o->inner_cycles > 16)
     return fail(DMG_ERR_INVALID_ARG, "inner_cycles must be in [1,16]");
+  if (o->strip_kernel != 0 && o->strip_kernel != 1)
+    return fail(DMG_ERR_INVALID_ARG, "strip_kernel must be 0 or 1");
   return DMG_OK;
 }
 
@@ -77,7 +79,8 @@ dmg_status level_dims(int nx, int ny, int coarsest_n, std::vector<std::pair<int,
 // with as few recomputed halo rows/columns as possible.  tile_rows overrides the segment height.
 StripConfig default_strip_config(int nx, int ny, const dmg_options& o) {
   StripConfig c;
-  c.bw = nx >= 257 ? 128 : 64;
+  c.wave = o.strip_kernel == 1;
+  c.bw = (c.wave || nx < 257) ? 64 : 128;
   int ns = 0, nseg = 0;
   c.seg_h = 16;
   for (int h = 128; h >= 16; h >>= 1) {
@@ -406,14 +409,15 @@ dmg_status tune_levels(dmg_hier* h, int reps, hipStream_t s) {
     Level& L = h->L[l];
     StripConfig best = Prec<T>::cfg(L);
     float best_ms = 1e30f;
-    for (int bw : {64, 128, 256}) {
+    for (int bw : {1, 64, 128, 256}) {  // 1: one-wavefront DPP strips (64 columns)
       if (bw == 256 && sizeof(T) == 8) continue;  // a 256-wide float64 ring exceeds 64 KiB of LDS
       for (int sh = 2; sh <= 128 && st == DMG_OK; sh *= 2) {
         int ns = 0, nseg = 0;
-        if (strip_blocks(L.nx, L.ny, bw, sh, &ns, &nseg) > kMaxPartials) continue;
         StripConfig c;
-        c.bw = bw;
+        c.wave = bw == 1;
+        c.bw = bw == 1 ? 64 : bw;
         c.seg_h = sh;
+        if (strip_blocks(L.nx, L.ny, c.bw, sh, &ns, &nseg) > kMaxPartials) continue;
         float ms = 0.f;
         st = time_level<T>(h, l, c, reps, s, e0, e1, &ms);
         if (st == DMG_OK && ms < best_ms) {
@@ -484,6 +488,7 @@ void dmg_default_options(dmg_options* o) {
   o->inner_cycles = 1;
   o->use_graph = 1;
   o->tile_rows = 0;
+  o->strip_kernel = 1;
 }
 
 const char* dmg_last_error(void) { return g_err; }
@@ -630,7 +635,7 @@ dmg_status dmg_hier_config(const dmg_hier* h, int32_t level, int32_t* bw, int32_
   if (level < 0 || level >= int(h->L.size()))
     return fail(DMG_ERR_INVALID_ARG, "level %d out of range", level);
   const bool strip = level < h->tail;
-  if (bw) *bw = strip ? h->L[level].cfg.bw : 0;
+  if (bw) *bw = strip ? (h->L[level].cfg.wave ? 1 : h->L[level].cfg.bw) : 0;
   if (seg_h) *seg_h = strip ? h->L[level].cfg.seg_h : 0;
   for (int k = 0; k < 4; ++k) {
     if (pre_order) pre_order[k] = h->opts.pre_order[k];

@@ -53,6 +53,7 @@ struct Arena {
 struct StripConfig {
   int bw = 128;     // columns (threads) per workgroup: 64, 128 or 256
   int seg_h = 32;   // rows per segment (even)
+  int wave = 0;     // 1: one-wavefront strips with DPP lane exchange (bw = 64)
 };
 
 // ---- hierarchy ---------------------------------------------------------------------------

@@ -149,8 +149,12 @@ __device__ __forceinline__ void store_row(ColRing<T>& c, const LdsRing<T>& L, in
 }
 
 // (P e)(i, j) for interior fine point (i, j), read straight from global memory.
+// The prolongation helpers below keep multiply and add separate (no FMA contraction): the
+// first row of a segment is corrected by prolong_global and the others by the staged
+// variants, and all must round identically for launch shapes to be bitwise neutral.
 template <class T>
 __device__ __forceinline__ T prolong_global(const StripArgs<T>& a, int i, int j) {
+#pragma clang fp contract(off)
   const int ncx = (a.nx + 1) / 2, ncy = (a.ny + 1) / 2;
   const size_t NC = size_t(ncx) * ncy;
   const size_t c = size_t(j >> 1) * ncx + (i >> 1);
@@ -209,6 +213,7 @@ __device__ __forceinline__ void load_coarse(const StripArgs<T>& a, int I, int r0
 // (P e)(i, j) from the staged coarse rows; k = local coarse column of i.
 template <class T>
 __device__ __forceinline__ T prolong_lds(const T* cb, int cw, int k, int i, int j) {
+#pragma clang fp contract(off)
   if (!(j & 1)) {
     const T* e = cb;
     if (!(i & 1)) return e[k];
@@ -591,6 +596,263 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs<T> a) {
 
 }  // namespace
 
+// -----------------------------------------------------------------------------------------
+// Wave-strip kernels: the same row pipeline with one wavefront per strip of 64 columns.  Each
+// lane owns one column and keeps its ring rows in registers; values of the neighbouring
+// columns come from the neighbouring lanes through DPP whole-wave shifts, so the kernel uses
+// no LDS and no barriers.  Lanes 0 and 63 receive their own value from a shift (they are halo
+// columns, whose results are never written).
+// -----------------------------------------------------------------------------------------
+__device__ __forceinline__ int lane_from_left(int v) {   // value held by lane - 1
+  return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xf, 0xf, false);  // wave_shr:1
+}
+__device__ __forceinline__ int lane_from_right(int v) {  // value held by lane + 1
+  return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xf, 0xf, false);  // wave_shl:1
+}
+__device__ __forceinline__ double from_left(double v) {
+  const long long x = __double_as_longlong(v);
+  const int lo = lane_from_left(int(x & 0xffffffffll)), hi = lane_from_left(int(x >> 32));
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+__device__ __forceinline__ double from_right(double v) {
+  const long long x = __double_as_longlong(v);
+  const int lo = lane_from_right(int(x & 0xffffffffll)), hi = lane_from_right(int(x >> 32));
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+__device__ __forceinline__ float from_left(float v) {
+  return __int_as_float(lane_from_left(__float_as_int(v)));
+}
+__device__ __forceinline__ float from_right(float v) {
+  return __int_as_float(lane_from_right(__float_as_int(v)));
+}
+
+template <class T>
+struct WaveCol {
+  T u[RU];
+  T C[RS], W[RS], Sv[RS], SW[RS], SE[RS], b[RS];
+  T Er[RS], NEr[RS], NWl[RS];  // W and SW of lane+1, SE of lane-1, same row
+  T r[RS];                     // residuals (pre)
+};
+
+// Fused multiply-adds are written out: the step copies of the unrolled ring period share
+// products between the smoothing update and the residual, and implicit contraction would then
+// fuse them in some copies and not in others, making the rounding depend on the segment height.
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+template <class T, int UM, int U0, int UP, int S0, int SP>
+__device__ __forceinline__ T offdiag_w(const WaveCol<T>& c) {
+#pragma clang fp contract(off)
+  const T um = c.u[UM], u0 = c.u[U0], up = c.u[UP];
+  T acc = c.SW[S0] * from_left(um);
+  acc = fmad(c.Sv[S0], um, acc);
+  acc = fmad(c.SE[S0], from_right(um), acc);
+  acc = fmad(c.W[S0], from_left(u0), acc);
+  acc = fmad(c.Er[S0], from_right(u0), acc);
+  acc = fmad(c.NWl[SP], from_left(up), acc);
+  acc = fmad(c.Sv[SP], up, acc);
+  return fmad(c.NEr[SP], from_right(up), acc);
+}
+
+// Gauss-Seidel update of this lane's point on the row at relative index JR where `ok` holds.
+// Every lane evaluates (the shifts need all lanes); the others keep their value.
+template <class T, int JR>
+__device__ __forceinline__ void gs_wave(WaveCol<T>& c, bool ok) {
+  constexpr int U0 = umod(JR), UM = umod(JR - 1), UP = umod(JR + 1);
+  constexpr int S0 = smod(JR), SP = smod(JR + 1);
+  const T off = offdiag_w<T, UM, U0, UP, S0, SP>(c);
+  const T v = (c.b[S0] - off) / (ok ? c.C[S0] : T(1));
+  c.u[U0] = ok ? v : c.u[U0];
+}
+
+template <class T, int JR>
+__device__ __forceinline__ T resid_wave(const WaveCol<T>& c, bool ok) {
+  constexpr int U0 = umod(JR), UM = umod(JR - 1), UP = umod(JR + 1);
+  constexpr int S0 = smod(JR), SP = smod(JR + 1);
+  const T off = offdiag_w<T, UM, U0, UP, S0, SP>(c);
+  const T r = c.b[S0] - fmad(c.C[S0], c.u[U0], off);
+  return ok ? r : T(0);
+}
+
+template <class T, int JR>
+__device__ __forceinline__ void store_row_w(WaveCol<T>& c, const RowRegs<T>& g) {
+  constexpr int U0 = umod(JR), S0 = smod(JR);
+  c.u[U0] = g.u;
+  c.b[S0] = g.b;
+  c.C[S0] = g.s[0];
+  c.W[S0] = g.s[1];
+  c.Sv[S0] = g.s[2];
+  c.SW[S0] = g.s[3];
+  c.SE[S0] = g.s[4];
+  c.Er[S0] = from_right(g.s[1]);
+  c.NEr[S0] = from_right(g.s[3]);
+  c.NWl[S0] = from_left(g.s[4]);
+}
+
+// Coarse values of coarse column I for one row step of the post kernel (see load_coarse):
+// v[0] e(J_even), v[1..2] P0/P1(J_even), v[3..4] e(J_odd), e(J_odd+1), v[5..10] P2..P7(J_odd).
+template <class T>
+__device__ __forceinline__ T prolong_wave(const CoarseRegs<T>& cv, int i, int j) {
+#pragma clang fp contract(off)
+  if (!(j & 1)) {
+    const T e = cv.v[0];
+    const T e1 = from_right(from_right(e));  // coarse column I+1 lives two lanes to the right
+    return (i & 1) ? cv.v[1] * e + cv.v[2] * e1 : e;
+  }
+  const T e0 = cv.v[3], e1 = cv.v[4];
+  const T e0r = from_right(from_right(e0)), e1r = from_right(from_right(e1));
+  if (!(i & 1)) return cv.v[5] * e0 + cv.v[6] * e1;
+  return ((cv.v[7] * e0 + cv.v[8] * e0r) + cv.v[9] * e1) + cv.v[10] * e1r;
+}
+
+// MODE as k_strip; PF = row parity smoothed first.
+template <class T, int MODE, int PF>
+__global__ __launch_bounds__(64) void k_wave(StripArgs<T> a) {
+  constexpr bool POST = MODE >= 2;
+  constexpr bool READ_U = MODE != 0;
+  constexpr bool prol = MODE == 2;
+  constexpr int BW = 64;
+  if (a.stop && *a.stop) return;
+  const int ntiles = a.nstrips * a.nsegs;
+  const int per = (int(gridDim.x) + 7) >> 3;
+  const int tile = (int(blockIdx.x) & 7) * per + (int(blockIdx.x) >> 3);
+  if (tile >= ntiles) {
+    if (POST && a.partials && threadIdx.x == 0) a.partials[blockIdx.x] = 0.0;
+    return;
+  }
+  const int seg = tile / a.nstrips;
+  const int strip = tile % a.nstrips;
+  const int t = threadIdx.x;
+  const int out_w = BW - 2 * HALO;
+  const int x0 = strip * out_w;
+  const int i = x0 - HALO + t;
+  // coarse column whose values this lane loads: lanes 2m and 2m+1 share column I = i >> 1
+  const int cI = i >> 1;
+  const int j0 = seg * a.seg_h;
+  const int j1 = min(j0 + a.seg_h, a.ny);
+  const int lim = POST ? j0 - 1 : j0 - 2;
+  const int a0 = lim - (((lim - PF) % 2) + 2) % 2;
+  const int alast = j1 + (((j1 - PF) % 2) + 2) % 2;
+  const int base = a0 - 1;
+  (void)base;
+  const bool interior_i = i >= 1 && i <= a.nx - 2;
+  const bool out_col = t >= HALO && t < BW - HALO && i < a.nx;
+  const int ncx = (a.nx + 1) / 2, ncy = (a.ny + 1) / 2;
+  auto row_ok = [&](int j) { return interior_i && j >= 1 && j <= a.ny - 2; };
+
+  WaveCol<T> c;
+#pragma unroll
+  for (int k = 0; k < RU; ++k) c.u[k] = T(0);
+#pragma unroll
+  for (int k = 0; k < RS; ++k)
+    c.C[k] = c.W[k] = c.Sv[k] = c.SW[k] = c.SE[k] = c.b[k] = c.Er[k] = c.NEr[k] = c.NWl[k] =
+        c.r[k] = T(0);
+  RowRegs<T> gA0, gA1, gB0, gB1;
+  CoarseRegs<T> cr;
+  load_row<T, READ_U>(a, i, a0 - 1, gA0);
+  if (prol && row_ok(a0 - 1)) gA0.u = gA0.u + prolong_global<T>(a, i, a0 - 1);
+  store_row_w<T, 0>(c, gA0);
+  if (prol) load_coarse<T>(a, cI, a0, cr);
+  load_row<T, READ_U>(a, i, a0, gA0);
+  load_row<T, READ_U>(a, i, a0 + 1, gA1);
+  load_row<T, READ_U>(a, i, a0 + 2, gB0);
+  load_row<T, READ_U>(a, i, a0 + 3, gB1);
+  double acc = 0.0;
+
+  auto step = [&](auto KC, int ar, RowRegs<T>& g0, RowRegs<T>& g1) {
+    constexpr int K = decltype(KC)::value;
+    constexpr int JA = 1 + 2 * K;
+    if (prol) {
+      const T c0 = prolong_wave<T>(cr, i, ar), c1 = prolong_wave<T>(cr, i, ar + 1);
+      if (row_ok(ar)) g0.u = g0.u + c0;
+      if (row_ok(ar + 1)) g1.u = g1.u + c1;
+    }
+    store_row_w<T, JA>(c, g0);
+    store_row_w<T, JA + 1>(c, g1);
+    // loads in the order they are consumed: restriction weights (end of this step), coarse
+    // values (top of the next step), rows of the step after next
+    const int fj = (ar - 2) & ~1;
+    const int J = fj >> 1;
+    const int I = i >> 1;
+    const bool do_restrict = !POST && out_col && !(i & 1) && fj >= j0 && fj < j1;
+    const bool inner_c = I >= 1 && I <= ncx - 2 && J >= 1 && J <= ncy - 2;
+    T pw[8];
+    if (!POST) {
+      const size_t NC = size_t(ncx) * ncy;
+      const size_t cc = (do_restrict && inner_c) ? size_t(J) * ncx + I : size_t(ncx) + 1;
+      const T* P = a.P;
+      pw[0] = P[7 * NC + cc - ncx - 1];
+      pw[1] = P[3 * NC + cc - ncx];
+      pw[2] = P[6 * NC + cc - ncx];
+      pw[3] = P[1 * NC + cc - 1];
+      pw[4] = P[0 * NC + cc];
+      pw[5] = P[5 * NC + cc - 1];
+      pw[6] = P[2 * NC + cc];
+      pw[7] = P[4 * NC + cc];
+    }
+    if (prol) load_coarse<T>(a, cI, ar + 2, cr);
+    load_row<T, READ_U>(a, i, ar + 4, g0);
+    load_row<T, READ_U>(a, i, ar + 5, g1);
+    const bool okA = row_ok(ar), okB = row_ok(ar - 1);
+    const bool firstA = (i & 1) == a.cA, firstB = (i & 1) == a.cB;
+    gs_wave<T, JA>(c, okA && firstA);
+    gs_wave<T, JA>(c, okA && !firstA);
+    gs_wave<T, JA - 1>(c, okB && firstB);
+    gs_wave<T, JA - 1>(c, okB && !firstB);
+    if (out_col) {
+      if (ar - 1 >= j0 && ar - 1 < j1) a.u[size_t(ar - 1) * a.nx + i] = c.u[umod(JA - 1)];
+      if (ar >= j0 && ar < j1) a.u[size_t(ar) * a.nx + i] = c.u[umod(JA)];
+    }
+    const T r2 = resid_wave<T, JA - 2>(c, row_ok(ar - 2));
+    const T r1 = resid_wave<T, JA - 1>(c, okB);
+    if (POST) {
+      if (out_col && a.partials) {
+        if (ar - 2 >= j0 && ar - 2 < j1) acc += double(r2) * double(r2);
+        if (ar - 1 >= j0 && ar - 1 < j1) acc += double(r1) * double(r1);
+      }
+    } else {
+      c.r[smod(JA - 2)] = r2;
+      c.r[smod(JA - 1)] = r1;
+      constexpr int RF = JA - 2 - PF;  // relative index of fine row 2J
+      const T rm = c.r[smod(RF - 1)], r0 = c.r[smod(RF)], rp = c.r[smod(RF + 1)];
+      const T rml = from_left(rm), rmr = from_right(rm);
+      const T r0l = from_left(r0), r0r = from_right(r0);
+      const T rpl = from_left(rp), rpr = from_right(rp);
+      if (do_restrict) {
+        T acc2 = T(0);
+        if (inner_c) {
+#pragma clang fp contract(off)
+          acc2 = pw[0] * rml;
+          acc2 = fmad(pw[1], rm, acc2);
+          acc2 = fmad(pw[2], rmr, acc2);
+          acc2 = fmad(pw[3], r0l, acc2);
+          acc2 = acc2 + r0;
+          acc2 = fmad(pw[4], r0r, acc2);
+          acc2 = fmad(pw[5], rpl, acc2);
+          acc2 = fmad(pw[6], rp, acc2);
+          acc2 = fmad(pw[7], rpr, acc2);
+        }
+        if (J < ncy) a.bH[size_t(J) * ncx + I] = acc2;
+      }
+    }
+  };
+
+  for (int ar = a0; ar <= alast; ar += 8) {
+    step(std::integral_constant<int, 0>{}, ar, gA0, gA1);
+    if (ar + 2 > alast) break;
+    step(std::integral_constant<int, 1>{}, ar + 2, gB0, gB1);
+    if (ar + 4 > alast) break;
+    step(std::integral_constant<int, 2>{}, ar + 4, gA0, gA1);
+    if (ar + 6 > alast) break;
+    step(std::integral_constant<int, 3>{}, ar + 6, gB0, gB1);
+  }
+  if (POST && a.partials) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if (t == 0) a.partials[blockIdx.x] = acc;
+  }
+}
+
 // ---- launchers -----------------------------------------------------------------------------
 int strip_blocks(int nx, int ny, int bw, int seg_h, int* nstrips, int* nsegs) {
   const int out_w = bw - 2 * HALO;
@@ -627,6 +889,19 @@ dmg_status launch_strip(const StripConfig& cfg, const T* S, const T* uin, T* u, 
       (size_t(RU + 4 * RS) * cfg.bw + (POST ? size_t(2 * kCoarseSlots) * (cfg.bw / 2 + 2) : 0)) *
       sizeof(T);
   const int mode = POST ? (e ? 2 : 3) : (uin ? 1 : 0);
+  if (cfg.wave) {
+    if (cfg.bw != 64) return fail(DMG_ERR_INVALID_ARG, "wave strips are 64 columns wide");
+#define DMG_WAVE(M)                                                                  \
+  (pf ? (void)(k_wave<T, M, 1><<<nb, 64, 0, s>>>(a)) : (void)(k_wave<T, M, 0><<<nb, 64, 0, s>>>(a)))
+    switch (mode) {
+      case 0: DMG_WAVE(0); break;
+      case 1: DMG_WAVE(1); break;
+      case 2: DMG_WAVE(2); break;
+      default: DMG_WAVE(3); break;
+    }
+#undef DMG_WAVE
+    return launch_check(POST ? "wave_post" : "wave_pre");
+  }
 #define DMG_STRIP_BW(BWV)                                                   \
   switch (mode) {                                                           \
     case 0: k_strip<T, BWV, 0><<<nb, BWV, lds, s>>>(a); break;              \

@@ -146,14 +146,40 @@ def test_colour_orders_and_sweep_counts(dmg, pre, post, nu):
     h.close()
 
 
+@pytest.mark.parametrize("wave", [0, 1])
+@pytest.mark.parametrize("pre,post", [((0, 1, 2, 3), (3, 2, 1, 0)), ((2, 3, 1, 0), (0, 1, 3, 2))])
+def test_strip_kernel_variants_match_oracle(dmg, wave, pre, post):
+    """Both strip-kernel implementations (LDS strips, one-wavefront DPP strips) give the oracle's
+    iterates, for both row parities smoothed first."""
+    prob = pb.star(513, seed=9)
+    S_or = fem.assemble_stencil(prob.jac, prob.K, prob.nx, prob.ny)
+    levels = boxmg.build_hierarchy(S_or)
+    h = dmg.Hierarchy(dev(S_or), pre_order=pre, post_order=post, tile_rows=8, strip_kernel=wave)
+    assert all((bw == 1) == bool(wave) for bw, sh in h.config()["levels"] if bw)
+    orc = cycle.Oracle(levels, pre=pre, post=post)
+    b = dev(prob.b)
+    u = torch.zeros_like(b)
+    uo = np.zeros(prob.nx * prob.ny)
+    for k in range(3):
+        h.vcycle(u, b)
+        orc.vcycle(uo, prob.b.ravel().copy())
+        assert np.linalg.norm(host(u).ravel() - uo) / np.linalg.norm(uo) <= TOL, k
+    x, k, rel, hist = h.solve(b, rtol=1e-10)
+    xo, ko, _, _ = cycle.solve(orc, prob.b, 1e-10)
+    assert k == ko and np.linalg.norm(host(x) - xo) / np.linalg.norm(xo) <= TOL
+    h.close()
+
+
+@pytest.mark.parametrize("wave", [0, 1])
 @pytest.mark.parametrize("tile_rows", [2, 6, 64])
-def test_launch_shape_is_numerically_neutral(dmg, tile_rows):
+def test_launch_shape_is_numerically_neutral(dmg, tile_rows, wave):
+    """Within one strip-kernel implementation the segment height changes nothing, bitwise."""
     prob = pb.star(513, seed=6)
     S = dmg.assemble_stencil(dev(prob.jac), dev(prob.K))
     b = dev(prob.b)
-    ref = dmg.Hierarchy(S)
+    ref = dmg.Hierarchy(S, strip_kernel=wave)
     u0, k0, _, _ = ref.solve(b, rtol=1e-10)
-    h = dmg.Hierarchy(S, tile_rows=tile_rows)
+    h = dmg.Hierarchy(S, tile_rows=tile_rows, strip_kernel=wave)
     u1, k1, _, _ = h.solve(b, rtol=1e-10)
     assert k0 == k1 and torch.equal(u0, u1)
     h.close()
@@ -169,7 +195,7 @@ def test_autotuned_hierarchy_matches_oracle(dmg):
     b = dev(prob.b)
     h = dmg.Hierarchy(dev(S_or), precision=dmg.DMG_FP32_IR)
     cfg = h.autotune(b, tiles=True, colour_order=True, reps=2)
-    assert all(bw in (0, 64, 128) for bw, _ in cfg["levels"])   # float64 shapes
+    assert all(bw in (0, 1, 64, 128) for bw, _ in cfg["levels"])   # float64 shapes
     assert cfg["post_order"] == cfg["pre_order"][::-1]
     h64 = dmg.Hierarchy(dev(S_or), pre_order=cfg["pre_order"], post_order=cfg["post_order"])
     h64.autotune(b, tiles=True, reps=2)

@@ -46,7 +46,8 @@ def test_default_options(dmg):
     o = dmg.default_options()
     assert (o.nu_pre, o.nu_post, o.coarsest_n, o.precision, o.inner_cycles) == (1, 1, 3, 0, 1)
     assert list(o.pre_order) == [0, 1, 2, 3] and list(o.post_order) == [3, 2, 1, 0]
-    assert C.sizeof(dmg.Options) == 4 * (2 + 4 + 4 + 5 + 7)
+    assert C.sizeof(dmg.Options) == 4 * (2 + 4 + 4 + 6 + 6)
+    assert o.strip_kernel == 1 and o.use_graph == 1
     assert dmg.version().startswith("dmg")
 
 
@@ -76,7 +77,8 @@ def test_workspace_sizes_scale_with_grid(dmg):
 
 
 @pytest.mark.parametrize("field,value", [("nu_pre", -1), ("coarsest_n", 2), ("precision", 7),
-                                         ("inner_cycles", 0), ("pre_order", [0, 0, 1, 2])])
+                                         ("inner_cycles", 0), ("pre_order", [0, 0, 1, 2]),
+                                         ("strip_kernel", 2)])
 def test_options_validation(dmg, field, value):
     lib = dmg.lib()
     o = dmg.default_options(**{field: value})
