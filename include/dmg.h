@@ -162,12 +162,14 @@ dmg_status dmg_residual_norm(dmg_hier* h, const double* u, const double* b, doub
 
 /* ---- a9: solve (Sec. 4 stopping rule: ||b - A u||_2 <= rtol ||b||_2) ------------------------
  * u in: initial guess, out: solution.  precision DMG_FP64: repeated V-cycles.  DMG_FP32_IR:
- * r = b - A x (fp64); s = ||r||; r32 = fl32(r/s); inner_cycles fp32 V-cycles from e = 0 with
- * fp32-rounded copies of the fp64 Galerkin stencils/weights (coarsest solve in fp64);
- * x += s e.  iters / relres (host, nullable) return the count of cycles or refinement steps
- * and the final relative residual; history (host, nullable, >= max_iters doubles) receives the
- * relative residual after each step.  Returns DMG_ERR_NO_CONVERGENCE (u holds the last
- * iterate) or DMG_ERR_NONFINITE.  Synchronises `stream` once per step. */
+ * r = b - A x in fp64, rounded once to r32 = fl32(r); inner_cycles fp32 V-cycles from e = 0
+ * with fp32-rounded copies of the fp64 Galerkin stencils/weights (coarsest solve in fp64);
+ * x += e in fp64.  (Scaling r by a power of two before the fp32 cycles changes no bit of x;
+ * scaling by ||r|| differs from that only in the rounding of r/||r||.)  iters / relres (host,
+ * nullable) return the count of cycles or refinement steps and the final relative residual;
+ * history (host, nullable, >= max_iters doubles) receives the relative residual after each
+ * step.  Returns DMG_ERR_NO_CONVERGENCE (u holds the last iterate) or DMG_ERR_NONFINITE.  The
+ * convergence test runs on the device; the host synchronises `stream` once per 4 steps. */
 dmg_status dmg_solve(dmg_hier* h, double* u, const double* b, double rtol, int32_t max_iters,
                      int32_t* iters, double* relres, double* history, hipStream_t stream);
 

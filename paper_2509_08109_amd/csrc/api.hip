@@ -144,7 +144,6 @@ void carve(dmg_hier& h, Arena& a, const std::vector<std::pair<int, int>>& dims,
   h.scalars = a.take<double>(16);
   h.flag = a.take<int>(16);
   h.hist = a.take<double>(kMaxHistory);
-  if (fp32) h.r64 = a.take<double>(size_t(dims[0].first) * dims[0].second);
 }
 
 template <class T>
@@ -217,9 +216,11 @@ dmg_status tail_launch(dmg_hier* h, T* u_top, const T* b_top, hipStream_t s, boo
 // strip kernels are out of place: each level alternates between its two iterate buffers and
 // the cycle ends with the level-0 iterate back in u0.  partials (optional) receives the
 // squared-residual partials of the final level-0 iterate.
+// x64 (float cycles only, nullable): float64 iterate that receives the cycle's result, x += u0,
+// fused into the last level-0 sweep.
 template <class T>
 dmg_status vcycle_impl(dmg_hier* h, T* u0, const T* b0, hipStream_t s, double* partials = nullptr,
-                       bool u0_zero = false, const int* stop = nullptr) {
+                       bool u0_zero = false, const int* stop = nullptr, double* x64 = nullptr) {
   using Pr = Prec<T>;
   const dmg_options& o = h->opts;
   const OrderParams pre = order_params(o.pre_order), post = order_params(o.post_order);
@@ -253,13 +254,16 @@ dmg_status vcycle_impl(dmg_hier* h, T* u0, const T* b0, hipStream_t s, double* p
       T* dst = other(l, cur[l]);
       DMG_CHECK(launch_post<T>(Pr::cfg(L), Pr::S(L), cur[l], dst, b, Pr::P(L), first ? e : nullptr,
                                (l == 0 && last) ? partials : nullptr, L.nx, L.ny, post.pf, post.cA,
-                               post.cB, stop, s));
+                               post.cB, stop, s, (l == 0 && last) ? x64 : nullptr));
       cur[l] = dst;
     }
     e = cur[l];
   }
   if (h->tail > 0 && cur[0] != u0)  // odd total sweep count: the iterate ends in the buffer
     DMG_CHECK(launch_copy<T>(cur[0], u0, h->L[0].n(), stop, s));
+  if constexpr (std::is_same<T, float>::value) {
+    if (x64 && h->tail == 0) DMG_CHECK(launch_ir_update(x64, u0, h->L[0].n(), s, stop));
+  }
   return DMG_OK;
 }
 
@@ -316,15 +320,19 @@ dmg_status step_fp64(dmg_hier* h, double* u, const double* b, hipStream_t s) {
 // The repeated step of float32 refinement: r32 = r/s, e = 0, inner fp32 cycles, x += s e,
 // r = b - A x, its norm (slot 4) and the convergence check.
 dmg_status step_ir(dmg_hier* h, double* x, const double* b, hipStream_t s) {
+  // L.b32 holds fl32(b - A x) of the current x (written by the previous step or the solve's
+  // start); the float cycles solve A e = r from e = 0 and the last one adds e into x.  The
+  // refinement runs unscaled: scaling r by a power of two would change no bit of x (float
+  // arithmetic commutes with it), and scaling by ||r|| differs from that only in the rounding
+  // of r / ||r||.
   const int* stop = stop_flag(h);
   const Level& L = h->L[0];
-  DMG_CHECK(launch_ir_scale(h->r64, h->scalars + 4, L.b32, L.n(), s, stop));
-  for (int k = 0; k < h->opts.inner_cycles; ++k)
-    DMG_CHECK(vcycle_impl<float>(h, L.u32, L.b32, s, nullptr, k == 0, stop));
-  DMG_CHECK(launch_ir_update(x, L.u32, h->scalars + 4, L.n(), s, stop));
-  DMG_CHECK(launch_ir_residual(L.S, x, b, h->r64, L.nx, L.ny, h->partials, s, stop));
-  return launch_check_step(h->partials, kReduceBlocks, h->scalars + 4, h->scalars, h->flag + 4,
-                           h->hist, kMaxHistory, s);
+  const int m = h->opts.inner_cycles;
+  for (int k = 0; k < m; ++k)
+    DMG_CHECK(vcycle_impl<float>(h, L.u32, L.b32, s, nullptr, k == 0, stop, k + 1 == m ? x : nullptr));
+  DMG_CHECK(launch_ir_residual(L.S, x, b, L.b32, L.nx, L.ny, h->partials, s, stop));
+  return launch_check_step(h->partials, ir_residual_blocks(L.nx, L.ny), h->scalars + 4, h->scalars,
+                           h->flag + 4, h->hist, kMaxHistory, s);
 }
 
 void graph_reset(Graph& g) {
@@ -727,8 +735,8 @@ dmg_status dmg_solve(dmg_hier* h, double* u, const double* b, double rtol, int32
   const int slot = ir ? 4 : 2;
   if (ir) {
     const Level& L = h->L[0];
-    DMG_CHECK(launch_ir_residual(L.S, u, b, h->r64, L.nx, L.ny, h->partials, stream));
-    DMG_CHECK(launch_finalize(h->partials, h->scalars + 4, stream));
+    DMG_CHECK(launch_ir_residual(L.S, u, b, L.b32, L.nx, L.ny, h->partials, stream));
+    DMG_CHECK(launch_finalize(h->partials, h->scalars + 4, stream, ir_residual_blocks(L.nx, L.ny)));
   } else {
     DMG_CHECK(norm_r(h, u, b, 2, stream));
   }

@@ -208,52 +208,6 @@ __global__ __launch_bounds__(256) void k_check(const double* __restrict__ partia
   }
 }
 
-// ---- iterative refinement --------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_ir_update(double* __restrict__ x,
-                                                   const float* __restrict__ e,
-                                                   const double* __restrict__ s, size_t n,
-                                                   const int* __restrict__ stop) {
-  if (stop && *stop) return;
-  const double sc = s[1];
-  for (size_t k = blockIdx.x * size_t(blockDim.x) + threadIdx.x; k < n;
-       k += size_t(gridDim.x) * blockDim.x)
-    x[k] = x[k] + sc * double(e[k]);
-}
-
-__global__ __launch_bounds__(256) void k_ir_residual(const double* __restrict__ S,
-                                                     const double* __restrict__ x,
-                                                     const double* __restrict__ b,
-                                                     double* __restrict__ r, int nx, int ny,
-                                                     double* __restrict__ partials,
-                                                     const int* __restrict__ stop) {
-  if (stop && *stop) return;
-  const size_t N = size_t(nx) * ny;
-  double acc = 0.0;
-  for (size_t v = blockIdx.x * size_t(blockDim.x) + threadIdx.x; v < N;
-       v += size_t(gridDim.x) * blockDim.x) {
-    const int j = int(v / nx), i = int(v % nx);
-    double rv = 0.0;
-    if (i > 0 && i < nx - 1 && j > 0 && j < ny - 1) {
-      rv = b[v] - (offdiag(S, x, N, nx, v) + S[v] * x[v]);
-      acc += rv * rv;
-    }
-    r[v] = rv;
-  }
-  const double t = block_sum(acc);
-  if (threadIdx.x == 0) partials[blockIdx.x] = t;
-}
-
-__global__ __launch_bounds__(256) void k_ir_scale(const double* __restrict__ r,
-                                                  const double* __restrict__ s,
-                                                  float* __restrict__ r32, size_t n,
-                                                  const int* __restrict__ stop) {
-  if (stop && *stop) return;
-  const double sc = s[1];
-  for (size_t k = blockIdx.x * size_t(blockDim.x) + threadIdx.x; k < n;
-       k += size_t(gridDim.x) * blockDim.x)
-    r32[k] = float(r[k] / sc);
-}
-
 unsigned stride_blocks(size_t n) {
   const size_t b = (n + 255) / 256;
   return unsigned(b < 4096 ? (b ? b : 1) : 4096);
@@ -328,24 +282,6 @@ dmg_status launch_sq_partials(const double* x, size_t, int nx, int ny, double* p
 dmg_status launch_finalize(const double* partials, double* out, hipStream_t s, int count) {
   k_finalize<<<1, 256, 0, s>>>(partials, out, count);
   return launch_check("finalize");
-}
-
-dmg_status launch_ir_update(double* x, const float* e, const double* s_dev, size_t n,
-                            hipStream_t s, const int* stop) {
-  k_ir_update<<<stride_blocks(n), 256, 0, s>>>(x, e, s_dev, n, stop);
-  return launch_check("ir_update");
-}
-
-dmg_status launch_ir_residual(const double* S, const double* x, const double* b, double* r,
-                              int nx, int ny, double* partials, hipStream_t s, const int* stop) {
-  k_ir_residual<<<kReduceBlocks, 256, 0, s>>>(S, x, b, r, nx, ny, partials, stop);
-  return launch_check("ir_residual");
-}
-
-dmg_status launch_ir_scale(const double* r, const double* s_dev, float* r32, size_t n,
-                           hipStream_t s, const int* stop) {
-  k_ir_scale<<<stride_blocks(n), 256, 0, s>>>(r, s_dev, r32, n, stop);
-  return launch_check("ir_scale");
 }
 
 dmg_status launch_check_step(const double* partials, int count, double* out, const double* sc,

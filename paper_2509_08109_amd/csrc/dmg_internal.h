@@ -103,7 +103,6 @@ struct dmg_hier {
   double* chol = nullptr;     // [m][m] Cholesky factor (lower), float64
   double* partials = nullptr; // [kReduceBlocks] reduction partials
   double* scalars = nullptr;  // [16] device scalars (norms, IR scale)
-  double* r64 = nullptr;      // fp64 fine residual for iterative refinement
   int* flag = nullptr;        // device ints: [0] pivot flag, [4..6] solve state (stop, steps, max)
   double* hist = nullptr;     // device history of relative residuals [kMaxHistory]
   double* host = nullptr;     // pinned host scalars [16]
@@ -164,7 +163,7 @@ dmg_status launch_pre(const StripConfig& cfg, const T* S, const T* uin, T* u, co
 template <class T>
 dmg_status launch_post(const StripConfig& cfg, const T* S, const T* uin, T* u, const T* b,
                        const T* P, const T* e, double* partials, int nx, int ny, int pf, int cA,
-                       int cB, const int* stop, hipStream_t s);
+                       int cB, const int* stop, hipStream_t s, double* x64 = nullptr);
 template <class T>
 struct TailSpec {
   const T* S[12];
@@ -186,13 +185,15 @@ template <class T>
 dmg_status launch_tail(const TailSpec<T>& spec, hipStream_t s);
 
 // iterative refinement helpers (stop: nullable device flag, see launch_check_step)
-dmg_status launch_ir_update(double* x, const float* e, const double* s_dev, size_t n,
-                            hipStream_t s, const int* stop = nullptr);
-dmg_status launch_ir_residual(const double* S, const double* x, const double* b, double* r,
+// x += e over n points (used when no float strip sweep carries the update)
+dmg_status launch_ir_update(double* x, const float* e, size_t n, hipStream_t s,
+                            const int* stop = nullptr);
+// r32 = fl32(b - A x) with A, x, b in float64, plus one squared-norm partial per workgroup;
+// *count receives the number of partials written
+int ir_residual_blocks(int nx, int ny);
+dmg_status launch_ir_residual(const double* S, const double* x, const double* b, float* r32,
                               int nx, int ny, double* partials, hipStream_t s,
                               const int* stop = nullptr);
-dmg_status launch_ir_scale(const double* r, const double* s_dev, float* r32, size_t n,
-                           hipStream_t s, const int* stop = nullptr);
 // device-side convergence check of one solve step (see k_check)
 dmg_status launch_check_step(const double* partials, int count, double* out, const double* sc,
                              int* st, double* hist, int hist_cap, hipStream_t s);

@@ -45,6 +45,8 @@ struct StripArgs {
   int pf;             // row parity smoothed first
   int cA, cB;         // column parity smoothed first on A-rows / on B-rows
   const int* stop;    // nullable: when *stop != 0 the kernel does nothing (converged solve)
+  double* x64;        // float post sweeps only (nullable): float64 iterate that receives the
+                      // sweep's output, x += u, at the points this workgroup writes
 };
 
 // Ring slots are taken relative to base = (first A-row) - 1: row j lives in u slot
@@ -285,6 +287,14 @@ __global__ __launch_bounds__(BW) void k_strip(StripArgs<T> a) {
   const int a0 = lim - (((lim - a.pf) % 2) + 2) % 2;
   // last A-row: residual rows up to j1-1 must be complete -> front a >= j1
   const int alast = j1 + (((j1 - a.pf) % 2) + 2) % 2;
+  // rows past alast + 1 are never consumed: their prefetch slots read row -1, which the
+  // loader maps to a fixed, cached address instead of streaming unused rows from memory
+  auto live = [&](int r) { return r <= alast + 1 ? r : -1; };
+  auto emit = [&](size_t v, T val) {
+    a.u[v] = val;
+    if constexpr (POST && std::is_same<T, float>::value)
+      if (a.x64) a.x64[v] += double(val);
+  };
   const int base = a0 - 1;
   const bool interior_i = i >= 1 && i <= a.nx - 2;
   const bool out_col = active && t >= HALO && t < BW - HALO && i < a.nx;
@@ -317,8 +327,8 @@ __global__ __launch_bounds__(BW) void k_strip(StripArgs<T> a) {
     }
     load_row<T, READ_U>(a, i, a0, gA0);
     load_row<T, READ_U>(a, i, a0 + 1, gA1);
-    load_row<T, READ_U>(a, i, a0 + 2, gB0);
-    load_row<T, READ_U>(a, i, a0 + 3, gB1);
+    load_row<T, READ_U>(a, i, live(a0 + 2), gB0);
+    load_row<T, READ_U>(a, i, live(a0 + 3), gB1);
   }
   __syncthreads();
   double acc = 0.0;
@@ -359,8 +369,8 @@ __global__ __launch_bounds__(BW) void k_strip(StripArgs<T> a) {
       pw[6] = P[2 * NC + cc];
       pw[7] = P[4 * NC + cc];
     }
-    load_row<T, READ_U>(a, i, ar + 4, g0);
-    load_row<T, READ_U>(a, i, ar + 5, g1);
+    load_row<T, READ_U>(a, i, live(ar + 4), g0);
+    load_row<T, READ_U>(a, i, live(ar + 5), g1);
     // A-row ar: column parity cA first, then the other; then B-row ar-1
     const bool okA = row_ok(ar), okB = row_ok(ar - 1);
     const bool firstA = (i & 1) == a.cA, firstB = (i & 1) == a.cB;
@@ -374,8 +384,8 @@ __global__ __launch_bounds__(BW) void k_strip(StripArgs<T> a) {
     __syncthreads();
     // rows ar-1 and ar are final: write them out
     if (out_col) {
-      if (ar - 1 >= j0 && ar - 1 < j1) a.u[size_t(ar - 1) * a.nx + i] = c.u[umod(JA - 1)];
-      if (ar >= j0 && ar < j1) a.u[size_t(ar) * a.nx + i] = c.u[umod(JA)];
+      if (ar - 1 >= j0 && ar - 1 < j1) emit(size_t(ar - 1) * a.nx + i, c.u[umod(JA - 1)]);
+      if (ar >= j0 && ar < j1) emit(size_t(ar) * a.nx + i, c.u[umod(JA)]);
     }
     // residual rows ar-2 and ar-1
     const T r2 = resid_col<T, BW, JA - 2>(c, L, tm, tp, row_ok(ar - 2));
@@ -733,6 +743,14 @@ __global__ __launch_bounds__(64) void k_wave(StripArgs<T> a) {
   const int lim = POST ? j0 - 1 : j0 - 2;
   const int a0 = lim - (((lim - PF) % 2) + 2) % 2;
   const int alast = j1 + (((j1 - PF) % 2) + 2) % 2;
+  // rows past alast + 1 are never consumed: their prefetch slots read row -1, which the
+  // loader maps to a fixed, cached address instead of streaming unused rows from memory
+  auto live = [&](int r) { return r <= alast + 1 ? r : -1; };
+  auto emit = [&](size_t v, T val) {
+    a.u[v] = val;
+    if constexpr (POST && std::is_same<T, float>::value)
+      if (a.x64) a.x64[v] += double(val);
+  };
   const int base = a0 - 1;
   (void)base;
   const bool interior_i = i >= 1 && i <= a.nx - 2;
@@ -755,8 +773,8 @@ __global__ __launch_bounds__(64) void k_wave(StripArgs<T> a) {
   if (prol) load_coarse<T>(a, cI, a0, cr);
   load_row<T, READ_U>(a, i, a0, gA0);
   load_row<T, READ_U>(a, i, a0 + 1, gA1);
-  load_row<T, READ_U>(a, i, a0 + 2, gB0);
-  load_row<T, READ_U>(a, i, a0 + 3, gB1);
+  load_row<T, READ_U>(a, i, live(a0 + 2), gB0);
+  load_row<T, READ_U>(a, i, live(a0 + 3), gB1);
   double acc = 0.0;
 
   auto step = [&](auto KC, int ar, RowRegs<T>& g0, RowRegs<T>& g1) {
@@ -791,8 +809,8 @@ __global__ __launch_bounds__(64) void k_wave(StripArgs<T> a) {
       pw[7] = P[4 * NC + cc];
     }
     if (prol) load_coarse<T>(a, cI, ar + 2, cr);
-    load_row<T, READ_U>(a, i, ar + 4, g0);
-    load_row<T, READ_U>(a, i, ar + 5, g1);
+    load_row<T, READ_U>(a, i, live(ar + 4), g0);
+    load_row<T, READ_U>(a, i, live(ar + 5), g1);
     const bool okA = row_ok(ar), okB = row_ok(ar - 1);
     const bool firstA = (i & 1) == a.cA, firstB = (i & 1) == a.cB;
     gs_wave<T, JA>(c, okA && firstA);
@@ -800,8 +818,8 @@ __global__ __launch_bounds__(64) void k_wave(StripArgs<T> a) {
     gs_wave<T, JA - 1>(c, okB && firstB);
     gs_wave<T, JA - 1>(c, okB && !firstB);
     if (out_col) {
-      if (ar - 1 >= j0 && ar - 1 < j1) a.u[size_t(ar - 1) * a.nx + i] = c.u[umod(JA - 1)];
-      if (ar >= j0 && ar < j1) a.u[size_t(ar) * a.nx + i] = c.u[umod(JA)];
+      if (ar - 1 >= j0 && ar - 1 < j1) emit(size_t(ar - 1) * a.nx + i, c.u[umod(JA - 1)]);
+      if (ar >= j0 && ar < j1) emit(size_t(ar) * a.nx + i, c.u[umod(JA)]);
     }
     const T r2 = resid_wave<T, JA - 2>(c, row_ok(ar - 2));
     const T r1 = resid_wave<T, JA - 1>(c, okB);
@@ -853,6 +871,123 @@ __global__ __launch_bounds__(64) void k_wave(StripArgs<T> a) {
   }
 }
 
+// ---- float64 residual of the refinement loop ----------------------------------------------
+// One wavefront per strip of 62 output columns and `rows` rows: lane t holds column
+// i = 62 strip - 1 + t (lanes 0 and 63 are halo), rows slide through registers one ahead of use,
+// and the neighbouring columns come from DPP lane shifts.  The off-diagonal sum runs in the same
+// order, with the same explicit fused multiply-adds, as in the wave sweeps.
+constexpr int kResidOut = 62;
+
+struct ResRow {
+  double x, b, C, W, S, SW, SE;
+};
+
+__device__ __forceinline__ void res_load(const double* S, const double* x, const double* b,
+                                         size_t N, int nx, int ny, int i, int j, ResRow& r) {
+  const bool ok = i >= 0 && i < nx && j >= 0 && j < ny;
+  const size_t v = ok ? size_t(j) * nx + i : 0;
+  const double t0 = x[v], t1 = b[v], t2 = S[v], t3 = S[N + v], t4 = S[2 * N + v],
+               t5 = S[3 * N + v], t6 = S[4 * N + v];
+  r.x = ok ? t0 : 0.0;
+  r.b = ok ? t1 : 0.0;
+  r.C = ok ? t2 : 0.0;
+  r.W = ok ? t3 : 0.0;
+  r.S = ok ? t4 : 0.0;
+  r.SW = ok ? t5 : 0.0;
+  r.SE = ok ? t6 : 0.0;
+}
+
+__global__ __launch_bounds__(64) void k_ir_resid(const double* __restrict__ S,
+                                                 const double* __restrict__ x,
+                                                 const double* __restrict__ b,
+                                                 float* __restrict__ r32, int nx, int ny, int rows,
+                                                 int nstrips, double* __restrict__ partials,
+                                                 const int* __restrict__ stop) {
+  if (stop && *stop) return;
+  const int strip = int(blockIdx.x) % nstrips, seg = int(blockIdx.x) / nstrips;
+  const int t = threadIdx.x;
+  const int i = strip * kResidOut - 1 + t;
+  const int j0 = seg * rows, j1 = min(j0 + rows, ny);
+  const size_t N = size_t(nx) * ny;
+  const bool out_col = t >= 1 && t <= kResidOut && i < nx;
+  const bool int_col = i >= 1 && i <= nx - 2;
+  ResRow m, c, n, nn;
+  res_load(S, x, b, N, nx, ny, i, j0 - 1, m);
+  res_load(S, x, b, N, nx, ny, i, j0, c);
+  res_load(S, x, b, N, nx, ny, i, j0 + 1, n);
+  double acc = 0.0;
+  for (int j = j0; j < j1; ++j) {
+    // row j + 2 is needed for the next row only (rows past the segment read a cached address)
+    res_load(S, x, b, N, nx, ny, i, j + 2 <= j1 ? j + 2 : -1, nn);
+    double o;
+    {
+#pragma clang fp contract(off)
+      o = c.SW * from_left(m.x);
+      o = fmad(c.S, m.x, o);
+      o = fmad(c.SE, from_right(m.x), o);
+      o = fmad(c.W, from_left(c.x), o);
+      o = fmad(from_right(c.W), from_right(c.x), o);
+      o = fmad(from_left(n.SE), from_left(n.x), o);
+      o = fmad(n.S, n.x, o);
+      o = fmad(from_right(n.SW), from_right(n.x), o);
+    }
+    const double r = c.b - fmad(c.C, c.x, o);
+    const bool interior = int_col && j >= 1 && j <= ny - 2;
+    const double rv = interior ? r : 0.0;
+    if (out_col) {
+      r32[size_t(j) * nx + i] = float(rv);
+      acc += rv * rv;
+    }
+    m = c;
+    c = n;
+    n = nn;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (t == 0) partials[blockIdx.x] = acc;
+}
+
+// x += e (float64 += float32) where no float strip sweep carries the update.
+__global__ __launch_bounds__(256) void k_ir_add(double* __restrict__ x, const float* __restrict__ e,
+                                                size_t n, const int* __restrict__ stop) {
+  if (stop && *stop) return;
+  for (size_t k = blockIdx.x * size_t(blockDim.x) + threadIdx.x; k < n;
+       k += size_t(gridDim.x) * blockDim.x)
+    x[k] = x[k] + double(e[k]);
+}
+
+namespace {
+void resid_shape(int nx, int ny, int* rows, int* nstrips, int* nblocks) {
+  *nstrips = (nx + kResidOut - 1) / kResidOut;
+  int r = 64;
+  auto blocks = [&](int rr) { return *nstrips * ((ny + rr - 1) / rr); };
+  while (r > 2 && blocks(r) < 2048) r /= 2;
+  while (blocks(r) > kMaxPartials) r *= 2;
+  *rows = r;
+  *nblocks = blocks(r);
+}
+}  // namespace
+
+int ir_residual_blocks(int nx, int ny) {
+  int rows = 0, ns = 0, nb = 0;
+  resid_shape(nx, ny, &rows, &ns, &nb);
+  return nb;
+}
+
+dmg_status launch_ir_residual(const double* S, const double* x, const double* b, float* r32,
+                              int nx, int ny, double* partials, hipStream_t s, const int* stop) {
+  int rows = 0, ns = 0, nb = 0;
+  resid_shape(nx, ny, &rows, &ns, &nb);
+  k_ir_resid<<<nb, 64, 0, s>>>(S, x, b, r32, nx, ny, rows, ns, partials, stop);
+  return launch_check("ir_residual");
+}
+
+dmg_status launch_ir_update(double* x, const float* e, size_t n, hipStream_t s, const int* stop) {
+  const size_t nb = (n + 255) / 256;
+  k_ir_add<<<unsigned(nb < 4096 ? (nb ? nb : 1) : 4096), 256, 0, s>>>(x, e, n, stop);
+  return launch_check("ir_update");
+}
+
 // ---- launchers -----------------------------------------------------------------------------
 int strip_blocks(int nx, int ny, int bw, int seg_h, int* nstrips, int* nsegs) {
   const int out_w = bw - 2 * HALO;
@@ -865,7 +1000,7 @@ int strip_blocks(int nx, int ny, int bw, int seg_h, int* nstrips, int* nsegs) {
 template <class T, bool POST>
 dmg_status launch_strip(const StripConfig& cfg, const T* S, const T* uin, T* u, const T* b,
                         const T* P, T* bH, const T* e, double* partials, int nx, int ny, int pf,
-                        int cA, int cB, const int* stop, hipStream_t s) {
+                        int cA, int cB, const int* stop, hipStream_t s, double* x64 = nullptr) {
   if (POST && !uin) return fail(DMG_ERR_INVALID_ARG, "post sweep needs an input iterate");
   if (uin == u) return fail(DMG_ERR_INVALID_ARG, "strip sweeps work out of place");
   StripArgs<T> a;
@@ -884,6 +1019,7 @@ dmg_status launch_strip(const StripConfig& cfg, const T* S, const T* uin, T* u, 
   a.cA = cA;
   a.cB = cB;
   a.stop = stop;
+  a.x64 = x64;
   const int nb = strip_blocks(nx, ny, cfg.bw, cfg.seg_h, &a.nstrips, &a.nsegs);
   const size_t lds =
       (size_t(RU + 4 * RS) * cfg.bw + (POST ? size_t(2 * kCoarseSlots) * (cfg.bw / 2 + 2) : 0)) *
@@ -931,9 +1067,11 @@ dmg_status launch_pre(const StripConfig& cfg, const T* S, const T* uin, T* u, co
 template <class T>
 dmg_status launch_post(const StripConfig& cfg, const T* S, const T* uin, T* u, const T* b,
                        const T* P, const T* e, double* partials, int nx, int ny, int pf, int cA,
-                       int cB, const int* stop, hipStream_t s) {
+                       int cB, const int* stop, hipStream_t s, double* x64) {
+  if (x64 && !std::is_same<T, float>::value)
+    return fail(DMG_ERR_INVALID_ARG, "the float64 iterate update belongs to float sweeps");
   return launch_strip<T, true>(cfg, S, uin, u, b, P, nullptr, e, partials, nx, ny, pf, cA, cB,
-                               stop, s);
+                               stop, s, x64);
 }
 
 template <class T>
@@ -971,7 +1109,7 @@ dmg_status launch_tail(const TailSpec<T>& spec, hipStream_t s) {
                                     hipStream_t);                                              \
   template dmg_status launch_post<T>(const StripConfig&, const T*, const T*, T*, const T*,     \
                                      const T*, const T*, double*, int, int, int, int, int,     \
-                                     const int*, hipStream_t);                                 \
+                                     const int*, hipStream_t, double*);                        \
   template dmg_status launch_tail<T>(const TailSpec<T>&, hipStream_t);
 DMG_INST(double)
 DMG_INST(float)
