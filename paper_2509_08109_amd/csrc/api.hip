@@ -109,9 +109,13 @@ void carve(dmg_hier& h, Arena& a, const std::vector<std::pair<int, int>>& dims,
     L.ny = dims[l].second;
     const size_t n = L.n();
     L.S = a.take<double>(5 * n);
+    if (int(l) < h.tail || l == 0) L.Sp = a.take<double>(5 * n);
     if (int(l) < h.tail) {
       L.t = a.take<double>(n);
-      if (fp32) L.t32 = a.take<float>(n);
+      if (fp32) {
+        L.t32 = a.take<float>(n);
+        L.Sp32 = a.take<float>(5 * n);
+      }
     }
     if (l + 1 < dims.size()) {
       const size_t nc = size_t(dims[l + 1].first) * dims[l + 1].second;
@@ -127,7 +131,7 @@ void carve(dmg_hier& h, Arena& a, const std::vector<std::pair<int, int>>& dims,
       L.b = a.take<double>(n);
     }
     if (fp32) {
-      L.S32 = a.take<float>(5 * n);
+      if (int(l) >= h.tail) L.S32 = a.take<float>(5 * n);
       L.u32 = a.take<float>(n);
       L.b32 = a.take<float>(n);
     }
@@ -153,6 +157,7 @@ struct Prec<double> {
   static const StripConfig& cfg(const Level& L) { return L.cfg; }
   static double* t(const Level& L) { return L.t; }
   static const double* S(const Level& L) { return L.S; }
+  static const double* Sp(const Level& L) { return L.Sp; }
   static const double* P(const Level& L) { return L.P; }
   static double* u(const Level& L) { return L.u; }
   static double* b(const Level& L) { return L.b; }
@@ -163,6 +168,7 @@ struct Prec<float> {
   static const StripConfig& cfg(const Level& L) { return L.cfg32; }
   static float* t(const Level& L) { return L.t32; }
   static const float* S(const Level& L) { return L.S32; }
+  static const float* Sp(const Level& L) { return L.Sp32; }
   static const float* P(const Level& L) { return L.P32; }
   static float* u(const Level& L) { return L.u32; }
   static float* b(const Level& L) { return L.b32; }
@@ -236,7 +242,7 @@ dmg_status vcycle_impl(dmg_hier* h, T* u0, const T* b0, hipStream_t s, double* p
     // every sweep writes the restriction of its residual; the last sweep's is the one used
     for (int k = 0; k < o.nu_pre; ++k) {
       T* dst = src ? other(l, src) : Pr::t(L);
-      DMG_CHECK(launch_pre<T>(Pr::cfg(L), Pr::S(L), src, dst, b, Pr::P(L), Pr::b(h->L[l + 1]), L.nx,
+      DMG_CHECK(launch_pre<T>(Pr::cfg(L), Pr::Sp(L), src, dst, b, Pr::P(L), Pr::b(h->L[l + 1]), L.nx,
                               L.ny, pre.pf, pre.cA, pre.cB, stop, s));
       src = dst;
     }
@@ -252,7 +258,7 @@ dmg_status vcycle_impl(dmg_hier* h, T* u0, const T* b0, hipStream_t s, double* p
     for (int k = 0; k < o.nu_post; ++k) {
       const bool first = k == 0, last = k + 1 == o.nu_post;  // prolongate once, norm once
       T* dst = other(l, cur[l]);
-      DMG_CHECK(launch_post<T>(Pr::cfg(L), Pr::S(L), cur[l], dst, b, Pr::P(L), first ? e : nullptr,
+      DMG_CHECK(launch_post<T>(Pr::cfg(L), Pr::Sp(L), cur[l], dst, b, Pr::P(L), first ? e : nullptr,
                                (l == 0 && last) ? partials : nullptr, L.nx, L.ny, post.pf, post.cA,
                                post.cB, stop, s, (l == 0 && last) ? x64 : nullptr));
       cur[l] = dst;
@@ -330,7 +336,7 @@ dmg_status step_ir(dmg_hier* h, double* x, const double* b, hipStream_t s) {
   const int m = h->opts.inner_cycles;
   for (int k = 0; k < m; ++k)
     DMG_CHECK(vcycle_impl<float>(h, L.u32, L.b32, s, nullptr, k == 0, stop, k + 1 == m ? x : nullptr));
-  DMG_CHECK(launch_ir_residual(L.S, x, b, L.b32, L.nx, L.ny, h->partials, s, stop));
+  DMG_CHECK(launch_ir_residual(L.Sp, x, b, L.b32, L.nx, L.ny, h->partials, s, stop));
   return launch_check_step(h->partials, ir_residual_blocks(L.nx, L.ny), h->scalars + 4, h->scalars,
                            h->flag + 4, h->hist, kMaxHistory, s);
 }
@@ -389,11 +395,11 @@ dmg_status time_level(dmg_hier* h, int l, const StripConfig& c, int reps, hipStr
   // Level 0 has no u/b of its own: use the residual scratch and the stencil's first plane.
   T* u = l == 0 ? Pr::r(L) : Pr::u(L);
   T* t = Pr::t(L);
-  const T* b = l == 0 ? Pr::S(L) : Pr::b(L);
+  const T* b = l == 0 ? Pr::Sp(L) : Pr::b(L);
   auto run = [&]() -> dmg_status {
-    DMG_CHECK(launch_pre<T>(c, Pr::S(L), u, t, b, Pr::P(L), Pr::b(h->L[l + 1]), L.nx, L.ny, pre.pf,
+    DMG_CHECK(launch_pre<T>(c, Pr::Sp(L), u, t, b, Pr::P(L), Pr::b(h->L[l + 1]), L.nx, L.ny, pre.pf,
                             pre.cA, pre.cB, nullptr, s));
-    return launch_post<T>(c, Pr::S(L), t, u, b, Pr::P(L), Pr::u(h->L[l + 1]), nullptr, L.nx, L.ny,
+    return launch_post<T>(c, Pr::Sp(L), t, u, b, Pr::P(L), Pr::u(h->L[l + 1]), nullptr, L.nx, L.ny,
                           post.pf, post.cA, post.cB, nullptr, s);
   };
   DMG_CHECK(run());  // warm-up
@@ -453,10 +459,15 @@ dmg_status setup_impl(dmg_hier* h, const double* S, hipStream_t s) {
   }
   const Level& C = h->L.back();
   DMG_CHECK(launch_coarse_factor(C.S, C.nx, C.ny, h->m_coarse, h->coarse_idx, h->chol, h->flag, s));
+  for (size_t l = 0; l < h->L.size(); ++l) {
+    const Level& L = h->L[l];
+    if (L.Sp) DMG_CHECK(launch_pack<double>(L.S, L.Sp, L.n(), s));
+    if (L.Sp32) DMG_CHECK(launch_pack<float>(L.S, L.Sp32, L.n(), s));
+  }
   if (h->opts.precision == DMG_FP32_IR) {
     for (size_t l = 0; l < h->L.size(); ++l) {
       const Level& L = h->L[l];
-      DMG_CHECK(launch_cast(L.S, L.S32, 5 * L.n(), s));
+      if (L.S32) DMG_CHECK(launch_cast(L.S, L.S32, 5 * L.n(), s));
       if (L.P) {
         const Level& Cn = h->L[l + 1];
         DMG_CHECK(launch_cast(L.P, L.P32, 8 * Cn.n(), s));
@@ -588,9 +599,9 @@ dmg_status dmg_sweep(dmg_hier* h, int32_t level, int32_t kind, double* u, const 
   const Level& L = h->L[level];
   const OrderParams pre = order_params(h->opts.pre_order), post = order_params(h->opts.post_order);
   if (kind == 0)
-    return launch_pre<double>(L.cfg, L.S, u, L.t, b, L.P, h->L[level + 1].b, L.nx, L.ny, pre.pf,
+    return launch_pre<double>(L.cfg, L.Sp, u, L.t, b, L.P, h->L[level + 1].b, L.nx, L.ny, pre.pf,
                               pre.cA, pre.cB, nullptr, stream);
-  return launch_post<double>(L.cfg, L.S, u, L.t, b, L.P, h->L[level + 1].u, nullptr, L.nx, L.ny,
+  return launch_post<double>(L.cfg, L.Sp, u, L.t, b, L.P, h->L[level + 1].u, nullptr, L.nx, L.ny,
                              post.pf, post.cA, post.cB, nullptr, stream);
 }
 
@@ -735,7 +746,7 @@ dmg_status dmg_solve(dmg_hier* h, double* u, const double* b, double rtol, int32
   const int slot = ir ? 4 : 2;
   if (ir) {
     const Level& L = h->L[0];
-    DMG_CHECK(launch_ir_residual(L.S, u, b, L.b32, L.nx, L.ny, h->partials, stream));
+    DMG_CHECK(launch_ir_residual(L.Sp, u, b, L.b32, L.nx, L.ny, h->partials, stream));
     DMG_CHECK(launch_finalize(h->partials, h->scalars + 4, stream, ir_residual_blocks(L.nx, L.ny)));
   } else {
     DMG_CHECK(norm_r(h, u, b, 2, stream));

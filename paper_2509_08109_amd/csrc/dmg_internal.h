@@ -62,12 +62,15 @@ struct Level {
   StripConfig cfg32;      // the same for the float32 kernels
   int nx = 0, ny = 0;
   double* S = nullptr;    // [5][ny][nx]
+  double* Sp = nullptr;   // [ny][nx][5] point-major copy of S read by the strip sweeps (levels
+                          // above the tail, and level 0 always: the refinement residual)
+  float* Sp32 = nullptr;  // its fp32 rounding for DMG_FP32_IR (levels above the tail)
   double* P = nullptr;    // [8][nyc][nxc] weights to the next coarser level (null at coarsest)
   double* u = nullptr;    // correction on coarse levels (level 0 uses the caller's array)
   double* t = nullptr;    // second iterate buffer for the out-of-place strip sweeps
   double* b = nullptr;    // right-hand side on coarse levels
   double* r = nullptr;    // residual scratch
-  float* S32 = nullptr;   // fp32 copies for DMG_FP32_IR
+  float* S32 = nullptr;   // fp32 copies for DMG_FP32_IR (S32: tail levels only)
   float* P32 = nullptr;
   float* u32 = nullptr;
   float* t32 = nullptr;
@@ -120,6 +123,9 @@ dmg_status launch_rap(const double* S, const double* P, int nx, int ny, double* 
                       hipStream_t s);
 dmg_status launch_coarse_factor(const double* S, int nx, int ny, int m, int* idx, double* chol,
                                 int* flag, hipStream_t s);
+// point-major copy of a planar stencil: out[5 v + k] = T(S[k n + v])
+template <class T>
+dmg_status launch_pack(const double* S, T* out, size_t n, hipStream_t s);
 dmg_status launch_cast(const double* in, float* out, size_t n, hipStream_t s);
 dmg_status launch_grad_K(const double* jac, const double* lam, const double* u, int nx, int ny,
                          double* dK, hipStream_t s);
@@ -154,7 +160,8 @@ dmg_status launch_finalize(const double* partials, double* out, hipStream_t s,
 
 // fused strip kernels (fused_kernels.hip)
 int strip_blocks(int nx, int ny, int bw, int seg_h, int* nstrips, int* nsegs);
-// Out-of-place: u_in (pre: nullptr = zero) -> u_out, u_in != u_out.
+// Out-of-place: u_in (pre: nullptr = zero) -> u_out, u_in != u_out.  S is the point-major
+// [ny][nx][5] stencil copy.
 // stop (nullable): device flag; the kernels do nothing once it is set (converged solves).
 template <class T>
 dmg_status launch_pre(const StripConfig& cfg, const T* S, const T* uin, T* u, const T* b,
@@ -188,8 +195,8 @@ dmg_status launch_tail(const TailSpec<T>& spec, hipStream_t s);
 // x += e over n points (used when no float strip sweep carries the update)
 dmg_status launch_ir_update(double* x, const float* e, size_t n, hipStream_t s,
                             const int* stop = nullptr);
-// r32 = fl32(b - A x) with A, x, b in float64, plus one squared-norm partial per workgroup;
-// *count receives the number of partials written
+// r32 = fl32(b - A x) with A (point-major [ny][nx][5]), x, b in float64, plus one squared-norm
+// partial per workgroup; ir_residual_blocks gives the number of partials written
 int ir_residual_blocks(int nx, int ny);
 dmg_status launch_ir_residual(const double* S, const double* x, const double* b, float* r32,
                               int nx, int ny, double* partials, hipStream_t s,

@@ -31,7 +31,7 @@ constexpr int RS = 4;     // ring rows of S, b, r
 
 template <class T>
 struct StripArgs {
-  const T* S;         // [5][ny][nx]
+  const T* S;         // [ny][nx][5] point-major stencil (C, W, S, SW, SE of each point)
   const T* uin;       // [ny][nx] iterate before the sweep (pre: nullptr = zero)
   T* u;               // [ny][nx] iterate after the sweep (written)
   const T* b;         // [ny][nx]
@@ -122,11 +122,10 @@ struct RowRegs {
 template <class T, bool READ_U>
 __device__ __forceinline__ void load_row(const StripArgs<T>& a, int i, int j, RowRegs<T>& g) {
   const bool ok = i >= 0 && i < a.nx && j >= 0 && j < a.ny;
-  const size_t N = size_t(a.nx) * a.ny;
   const size_t v = ok ? size_t(j) * a.nx + i : 0;
   T s[5];
 #pragma unroll
-  for (int k = 0; k < 5; ++k) s[k] = a.S[k * N + v];
+  for (int k = 0; k < 5; ++k) s[k] = a.S[5 * v + k];
   const T bb = a.b[v];
   T uu = T(0);
   if (READ_U) uu = a.uin[v];
@@ -883,11 +882,11 @@ struct ResRow {
 };
 
 __device__ __forceinline__ void res_load(const double* S, const double* x, const double* b,
-                                         size_t N, int nx, int ny, int i, int j, ResRow& r) {
+                                         int nx, int ny, int i, int j, ResRow& r) {
   const bool ok = i >= 0 && i < nx && j >= 0 && j < ny;
   const size_t v = ok ? size_t(j) * nx + i : 0;
-  const double t0 = x[v], t1 = b[v], t2 = S[v], t3 = S[N + v], t4 = S[2 * N + v],
-               t5 = S[3 * N + v], t6 = S[4 * N + v];
+  const double* sv = S + 5 * v;
+  const double t0 = x[v], t1 = b[v], t2 = sv[0], t3 = sv[1], t4 = sv[2], t5 = sv[3], t6 = sv[4];
   r.x = ok ? t0 : 0.0;
   r.b = ok ? t1 : 0.0;
   r.C = ok ? t2 : 0.0;
@@ -908,17 +907,16 @@ __global__ __launch_bounds__(64) void k_ir_resid(const double* __restrict__ S,
   const int t = threadIdx.x;
   const int i = strip * kResidOut - 1 + t;
   const int j0 = seg * rows, j1 = min(j0 + rows, ny);
-  const size_t N = size_t(nx) * ny;
   const bool out_col = t >= 1 && t <= kResidOut && i < nx;
   const bool int_col = i >= 1 && i <= nx - 2;
-  ResRow m, c, n, nn;
-  res_load(S, x, b, N, nx, ny, i, j0 - 1, m);
-  res_load(S, x, b, N, nx, ny, i, j0, c);
-  res_load(S, x, b, N, nx, ny, i, j0 + 1, n);
+  ResRow m, c, n, nn;  // rows j - 1, j, j + 1 and the prefetched j + 2
+  res_load(S, x, b, nx, ny, i, j0 - 1, m);
+  res_load(S, x, b, nx, ny, i, j0, c);
+  res_load(S, x, b, nx, ny, i, j0 + 1, n);
   double acc = 0.0;
   for (int j = j0; j < j1; ++j) {
     // row j + 2 is needed for the next row only (rows past the segment read a cached address)
-    res_load(S, x, b, N, nx, ny, i, j + 2 <= j1 ? j + 2 : -1, nn);
+    res_load(S, x, b, nx, ny, i, j + 2 <= j1 ? j + 2 : -1, nn);
     double o;
     {
 #pragma clang fp contract(off)

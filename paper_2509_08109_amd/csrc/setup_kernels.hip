@@ -370,6 +370,16 @@ __global__ __launch_bounds__(256) void k_cast(const double* __restrict__ in, flo
     out[k] = float(in[k]);
 }
 
+template <class T>
+__global__ __launch_bounds__(256) void k_pack(const double* __restrict__ S, T* __restrict__ out,
+                                              size_t n) {
+  for (size_t v = blockIdx.x * size_t(blockDim.x) + threadIdx.x; v < n;
+       v += size_t(gridDim.x) * blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) out[5 * v + k] = T(S[k * n + v]);
+  }
+}
+
 dim3 grid2(int nx, int ny) { return dim3((nx + kBX - 1) / kBX, (ny + kBY - 1) / kBY); }
 
 }  // namespace
@@ -413,6 +423,15 @@ template dmg_status launch_coarse_solve<double>(const double*, double*, int, con
                                                 const double*, size_t, hipStream_t);
 template dmg_status launch_coarse_solve<float>(const float*, float*, int, const int*,
                                                const double*, size_t, hipStream_t);
+
+template <class T>
+dmg_status launch_pack(const double* S, T* out, size_t n, hipStream_t s) {
+  const size_t blocks = (n + 255) / 256;
+  k_pack<T><<<dim3(unsigned(blocks < 65535 ? (blocks ? blocks : 1) : 65535)), 256, 0, s>>>(S, out, n);
+  return launch_check("pack");
+}
+template dmg_status launch_pack<double>(const double*, double*, size_t, hipStream_t);
+template dmg_status launch_pack<float>(const double*, float*, size_t, hipStream_t);
 
 dmg_status launch_cast(const double* in, float* out, size_t n, hipStream_t s) {
   const size_t blocks = (n + 255) / 256;

@@ -67,8 +67,9 @@ def test_workspace_sizes_scale_with_grid(dmg):
         nb = C.c_size_t()
         assert lib.dmg_workspace_bytes(n, n, C.byref(dmg.default_options()), C.byref(nb)) == 0
         sizes.append(nb.value)
-    # ~ (5 S + 2 P + u,b,r) words per fine point, times 4/3 for the coarse levels
-    assert 8 * 5 * 257 * 257 < sizes[2] < 8 * 16 * 257 * 257
+    # ~ (5 S + 5 point-major S + 2 P + u, t, b, r) words per fine point, times 4/3 for the
+    # coarse levels
+    assert 8 * 10 * 257 * 257 < sizes[2] < 8 * 22 * 257 * 257
     assert 3.5 < sizes[2] / sizes[1] < 4.5
     nb32 = C.c_size_t()
     o = dmg.default_options(precision=dmg.DMG_FP32_IR)
