@@ -100,8 +100,23 @@ void carve(dmg_hier& h, Arena& a, const std::vector<std::pair<int, int>>& dims,
            const dmg_options& o) {
   const bool fp32 = o.precision == DMG_FP32_IR;
   h.L.assign(dims.size(), Level{});
+  // the coarse tail takes the coarsest levels up to kTailMaxN whose float64 data fits in the
+  // LDS of one workgroup (it always holds the coarsest level)
+  const int lds = device_lds_limit();
+  const int m = (dims.back().first - 2) * (dims.back().second - 2);
+  auto fits = [&](int top) {
+    const int nlev = int(dims.size()) - top;
+    if (nlev > kMaxTail) return false;
+    int nx[kMaxTail], ny[kMaxTail];
+    for (int k = 0; k < nlev; ++k) {
+      nx[k] = dims[top + k].first;
+      ny[k] = dims[top + k].second;
+    }
+    return tail_layout(nx, ny, nlev, m, int(sizeof(double))).bytes <= size_t(lds);
+  };
   h.tail = int(dims.size()) - 1;
-  while (h.tail > 0 && std::max(dims[h.tail - 1].first, dims[h.tail - 1].second) <= kTailMaxN)
+  while (h.tail > 0 && std::max(dims[h.tail - 1].first, dims[h.tail - 1].second) <= kTailMaxN &&
+         fits(h.tail - 1))
     --h.tail;
   for (size_t l = 0; l < dims.size(); ++l) {
     Level& L = h.L[l];
@@ -195,9 +210,8 @@ dmg_status tail_launch(dmg_hier* h, T* u_top, const T* b_top, hipStream_t s, boo
     const Level& L = h->L[l];
     const int k = l - h->tail;
     sp.S[k] = Pr::S(L);
-    sp.u[k] = l == 0 ? u_top : Pr::u(L);
-    sp.b[k] = l == 0 ? const_cast<T*>(b_top) : Pr::b(L);
-    sp.r[k] = Pr::r(L);
+    sp.u[k] = k == 0 ? u_top : Pr::u(L);
+    sp.b[k] = k == 0 ? const_cast<T*>(b_top) : Pr::b(L);
     sp.P[k] = Pr::P(L);
     sp.nx[k] = L.nx;
     sp.ny[k] = L.ny;

@@ -81,10 +81,11 @@ struct Level {
 
 constexpr int kReduceBlocks = 1024;  // fixed partial count: reductions are order-deterministic
 constexpr int kMaxPartials = 16384;  // capacity of the partials buffer
-constexpr int kTailMaxN = 65;
+constexpr int kTailMaxN = 65;    // levels with max(nx, ny) <= this may run in the coarse tail
+constexpr int kMaxTail = 12;     // at most this many levels in the coarse tail
 constexpr int kMaxLevels = 32;
 constexpr int kMaxHistory = 4096;
-constexpr int kChunk = 4;            // solve steps per host synchronisation        // levels with max(nx,ny) <= this run in the one-workgroup tail
+constexpr int kChunk = 4;            // solve steps per host synchronisation
 
 struct Graph {
   hipGraphExec_t exec = nullptr;
@@ -173,12 +174,11 @@ dmg_status launch_post(const StripConfig& cfg, const T* S, const T* uin, T* u, c
                        int cB, const int* stop, hipStream_t s, double* x64 = nullptr);
 template <class T>
 struct TailSpec {
-  const T* S[12];
-  T* u[12];
-  T* b[12];
-  T* r[12];
-  const T* P[12];
-  int nx[12], ny[12];
+  const T* S[kMaxTail];
+  T* u[kMaxTail];
+  T* b[kMaxTail];
+  const T* P[kMaxTail];
+  int nx[kMaxTail], ny[kMaxTail];
   int nlev = 0;
   int zero_top = 1;
   int m = 0;
@@ -188,6 +188,18 @@ struct TailSpec {
   int nu_pre = 1, nu_post = 1;
   const int* stop = nullptr;
 };
+// LDS layout of the coarse-tail kernel for levels nx[0..nlev) (the last one the coarsest, with
+// m unknowns): per level S [5 n] and P [8 n_next] (not at the coarsest), u [n], b [n]; then the
+// residual scratch and the float64 coarsest-solve scratch.  Offsets in elements of `elem`
+// bytes, except y (bytes).
+struct TailLayout {
+  int S[kMaxTail], u[kMaxTail], b[kMaxTail], P[kMaxTail];
+  int r = 0;
+  int y = 0;
+  size_t bytes = 0;
+};
+TailLayout tail_layout(const int* nx, const int* ny, int nlev, int m, int elem);
+int device_lds_limit();  // LDS bytes one workgroup may use on the current device
 template <class T>
 dmg_status launch_tail(const TailSpec<T>& spec, hipStream_t s);
 

@@ -445,25 +445,26 @@ __global__ __launch_bounds__(BW) void k_strip(StripArgs<T> a) {
 }
 
 // -----------------------------------------------------------------------------------------
-// Coarse tail: one workgroup runs the V-cycle from level `top` down to the coarsest level
-// and back, with workgroup barriers between the colour passes.  Level data lives in the
-// hierarchy arrays (small enough to stay in L2).
+// Coarse tail: one workgroup runs the V-cycle from level `top` down to the coarsest level and
+// back, entirely in LDS.  It stages the stencils and weights of its levels and the top level's
+// right-hand side (and iterate) once per cycle, separates the colour passes with workgroup
+// barriers, and writes back only the top level's iterate, which is all the levels above read.
 // -----------------------------------------------------------------------------------------
 template <class T>
 struct TailLevel {
-  const T* S;
-  T* u;
-  T* b;
-  T* r;
-  const T* P;
+  const T* S;  // [5][ny][nx] planar (unused at the coarsest level)
+  T* u;        // top level: iterate in/out; others unused
+  const T* b;  // top level: right-hand side; others unused
+  const T* P;  // [8][nyc][nxc] (unused at the coarsest level)
   int nx, ny;
 };
-
-constexpr int kMaxTail = 12;
 
 template <class T>
 struct TailArgs {
   TailLevel<T> L[kMaxTail];
+  int oS[kMaxTail], ou[kMaxTail], ob[kMaxTail], oP[kMaxTail];  // LDS offsets, elements of T
+  int o_r;            // LDS offset of the residual scratch, elements of T
+  int o_y;            // LDS byte offset of the float64 coarsest-solve scratch
   int nlev;           // levels in the tail (the last one is the coarsest)
   int zero_top;       // the top level starts from u = 0 (it is a coarse level)
   int m;              // coarsest unknowns
@@ -475,8 +476,7 @@ struct TailArgs {
 };
 
 template <class T>
-__device__ __forceinline__ T offdiag_g(const T* __restrict__ S, const T* __restrict__ u, size_t N,
-                                       int nx, size_t v) {
+__device__ __forceinline__ T offdiag_s(const T* S, const T* u, int N, int nx, int v) {
   const T sw = S[3 * N + v] * u[v - nx - 1];
   const T s = S[2 * N + v] * u[v - nx];
   const T se = S[4 * N + v] * u[v - nx + 1];
@@ -489,15 +489,15 @@ __device__ __forceinline__ T offdiag_g(const T* __restrict__ S, const T* __restr
 }
 
 template <class T>
-__device__ void tail_colour(const TailLevel<T>& L, int c) {
+__device__ void tail_colour(const T* S, T* u, const T* b, int nx, int ny, int c) {
   const int ci = c & 1, cj = c >> 1;
-  const int px = (L.nx - ci + 1) / 2, py = (L.ny - cj + 1) / 2;
-  const size_t N = size_t(L.nx) * L.ny;
+  const int px = (nx - ci + 1) / 2, py = (ny - cj + 1) / 2;
+  const int N = nx * ny;
   for (int k = threadIdx.x; k < px * py; k += blockDim.x) {
     const int i = ci + 2 * (k % px), j = cj + 2 * (k / px);
-    if (i <= 0 || i >= L.nx - 1 || j <= 0 || j >= L.ny - 1) continue;
-    const size_t v = size_t(j) * L.nx + i;
-    L.u[v] = (L.b[v] - offdiag_g(L.S, L.u, N, L.nx, v)) / L.S[v];
+    if (i <= 0 || i >= nx - 1 || j <= 0 || j >= ny - 1) continue;
+    const int v = j * nx + i;
+    u[v] = (b[v] - offdiag_s(S, u, N, nx, v)) / S[v];
   }
   __syncthreads();
 }
@@ -505,35 +505,56 @@ __device__ void tail_colour(const TailLevel<T>& L, int c) {
 template <class T>
 __global__ __launch_bounds__(1024) void k_tail(TailArgs<T> a) {
   if (a.stop && *a.stop) return;
-  extern __shared__ double y[];
-  const int nl = a.nlev;
-  for (int l = 0; l < nl - 1; ++l) {
-    const TailLevel<T>& L = a.L[l];
-    const size_t N = size_t(L.nx) * L.ny;
-    if (l > 0 || a.zero_top)
-      for (size_t v = threadIdx.x; v < N; v += blockDim.x) L.u[v] = T(0);
-    __syncthreads();
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* sm = reinterpret_cast<T*>(smem);
+  const int nl = a.nlev, tid = threadIdx.x, nt = blockDim.x;
+  // stage the level data
+  for (int l = 0; l < nl; ++l) {
+    const TailLevel<T>& G = a.L[l];
+    const int n = G.nx * G.ny;
+    T* u = sm + a.ou[l];
+    if (l + 1 < nl) {
+      const int nc = a.L[l + 1].nx * a.L[l + 1].ny;
+      T* S = sm + a.oS[l];
+      T* P = sm + a.oP[l];
+      for (int k = tid; k < 5 * n; k += nt) S[k] = G.S[k];
+      for (int k = tid; k < 8 * nc; k += nt) P[k] = G.P[k];
+    }
+    if (l == 0) {
+      T* b = sm + a.ob[l];
+      for (int k = tid; k < n; k += nt) {
+        b[k] = G.b[k];
+        u[k] = a.zero_top ? T(0) : G.u[k];
+      }
+    } else {
+      for (int k = tid; k < n; k += nt) u[k] = T(0);  // b_l is written by the restriction
+    }
+  }
+  __syncthreads();
+  T* r = sm + a.o_r;
+  for (int l = 0; l + 1 < nl; ++l) {
+    const int nx = a.L[l].nx, ny = a.L[l].ny, N = nx * ny;
+    const T* S = sm + a.oS[l];
+    T* u = sm + a.ou[l];
+    const T* b = sm + a.ob[l];
     for (int s = 0; s < a.nu_pre; ++s)
-      for (int c = 0; c < 4; ++c) tail_colour(L, a.pre[c]);
-    for (size_t v = threadIdx.x; v < N; v += blockDim.x) {
-      const int i = int(v % L.nx), j = int(v / L.nx);
-      T r = T(0);
-      if (i > 0 && i < L.nx - 1 && j > 0 && j < L.ny - 1)
-        r = L.b[v] - (offdiag_g(L.S, L.u, N, L.nx, v) + L.S[v] * L.u[v]);
-      L.r[v] = r;
+      for (int c = 0; c < 4; ++c) tail_colour(S, u, b, nx, ny, a.pre[c]);
+    for (int v = tid; v < N; v += nt) {
+      const int i = v % nx, j = v / nx;
+      T rv = T(0);
+      if (i > 0 && i < nx - 1 && j > 0 && j < ny - 1)
+        rv = b[v] - (offdiag_s(S, u, N, nx, v) + S[v] * u[v]);
+      r[v] = rv;
     }
     __syncthreads();
-    const TailLevel<T>& Cn = a.L[l + 1];
-    const int ncx = Cn.nx, ncy = Cn.ny;
-    const size_t NC = size_t(ncx) * ncy;
-    for (size_t c = threadIdx.x; c < NC; c += blockDim.x) {
-      const int I = int(c % ncx), J = int(c / ncx);
+    const int ncx = a.L[l + 1].nx, ncy = a.L[l + 1].ny, NC = ncx * ncy;
+    const T* P = sm + a.oP[l];
+    T* bH = sm + a.ob[l + 1];
+    for (int c = tid; c < NC; c += nt) {
+      const int I = c % ncx, J = c / ncx;
       T acc = T(0);
       if (I > 0 && I < ncx - 1 && J > 0 && J < ncy - 1) {
-        const T* P = L.P;
-        const T* r = L.r;
-        const size_t f = size_t(2 * J) * L.nx + 2 * I;
-        const int nx = L.nx;
+        const int f = 2 * J * nx + 2 * I;
         acc = P[7 * NC + c - ncx - 1] * r[f - nx - 1];
         acc += P[3 * NC + c - ncx] * r[f - nx];
         acc += P[6 * NC + c - ncx] * r[f - nx + 1];
@@ -544,46 +565,48 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs<T> a) {
         acc += P[2 * NC + c] * r[f + nx];
         acc += P[4 * NC + c] * r[f + nx + 1];
       }
-      Cn.b[c] = acc;
+      bH[c] = acc;
     }
     __syncthreads();
   }
   // coarsest: dense Cholesky solve in float64
   {
-    const TailLevel<T>& C = a.L[nl - 1];
-    const size_t N = size_t(C.nx) * C.ny;
+    T* uc = sm + a.ou[nl - 1];
+    const T* bc = sm + a.ob[nl - 1];
+    double* y = reinterpret_cast<double*>(smem + a.o_y);
     const int m = a.m;
     const double* L = a.chol;
-    for (size_t v = threadIdx.x; v < N; v += blockDim.x) C.u[v] = T(0);
-    for (int k = threadIdx.x; k < m; k += blockDim.x) y[k] = double(C.b[a.idx[k]]);
+    const int ncn = a.L[nl - 1].nx * a.L[nl - 1].ny;
+    for (int k = tid; k < m; k += nt) y[k] = double(bc[a.idx[k]]);
+    for (int k = tid; k < ncn; k += nt) uc[k] = T(0);  // the direct solve ignores the guess
     __syncthreads();
     for (int k = 0; k < m; ++k) {
-      if (threadIdx.x == 0) y[k] /= L[k * m + k];
+      if (tid == 0) y[k] /= L[k * m + k];
       __syncthreads();
-      for (int r = k + 1 + threadIdx.x; r < m; r += blockDim.x) y[r] -= L[r * m + k] * y[k];
+      for (int q = k + 1 + tid; q < m; q += nt) y[q] -= L[q * m + k] * y[k];
       __syncthreads();
     }
     for (int k = m - 1; k >= 0; --k) {
-      if (threadIdx.x == 0) y[k] /= L[k * m + k];
+      if (tid == 0) y[k] /= L[k * m + k];
       __syncthreads();
-      for (int r = threadIdx.x; r < k; r += blockDim.x) y[r] -= L[k * m + r] * y[k];
+      for (int q = tid; q < k; q += nt) y[q] -= L[k * m + q] * y[k];
       __syncthreads();
     }
-    for (int k = threadIdx.x; k < m; k += blockDim.x) C.u[a.idx[k]] = T(y[k]);
+    for (int k = tid; k < m; k += nt) uc[a.idx[k]] = T(y[k]);
     __syncthreads();
   }
   for (int l = nl - 2; l >= 0; --l) {
-    const TailLevel<T>& L = a.L[l];
-    const TailLevel<T>& Cn = a.L[l + 1];
-    const int ncx = Cn.nx, ncy = Cn.ny;
-    const size_t NC = size_t(ncx) * ncy;
-    const size_t N = size_t(L.nx) * L.ny;
-    for (size_t v = threadIdx.x; v < N; v += blockDim.x) {
-      const int i = int(v % L.nx), j = int(v / L.nx);
-      if (i <= 0 || i >= L.nx - 1 || j <= 0 || j >= L.ny - 1) continue;
-      const size_t c = size_t(j >> 1) * ncx + (i >> 1);
-      const T* P = L.P;
-      const T* e = Cn.u;
+    const int nx = a.L[l].nx, ny = a.L[l].ny, N = nx * ny;
+    const int ncx = a.L[l + 1].nx, ncy = a.L[l + 1].ny, NC = ncx * ncy;
+    const T* S = sm + a.oS[l];
+    const T* P = sm + a.oP[l];
+    const T* e = sm + a.ou[l + 1];
+    T* u = sm + a.ou[l];
+    const T* b = sm + a.ob[l];
+    for (int v = tid; v < N; v += nt) {
+      const int i = v % nx, j = v / nx;
+      if (i <= 0 || i >= nx - 1 || j <= 0 || j >= ny - 1) continue;
+      const int c = (j >> 1) * ncx + (i >> 1);
       T corr;
       if (!(i & 1) && !(j & 1)) {
         corr = e[c];
@@ -595,11 +618,17 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs<T> a) {
         corr = ((P[4 * NC + c] * e[c] + P[5 * NC + c] * e[c + 1]) + P[6 * NC + c] * e[c + ncx]) +
                P[7 * NC + c] * e[c + ncx + 1];
       }
-      L.u[v] = L.u[v] + corr;
+      u[v] = u[v] + corr;
     }
     __syncthreads();
     for (int s = 0; s < a.nu_post; ++s)
-      for (int c = 0; c < 4; ++c) tail_colour(L, a.post[c]);
+      for (int c = 0; c < 4; ++c) tail_colour(S, u, b, nx, ny, a.post[c]);
+  }
+  // write back the top level's iterate
+  {
+    const TailLevel<T>& G = a.L[0];
+    const T* u = sm + a.ou[0];
+    for (int k = tid; k < G.nx * G.ny; k += nt) G.u[k] = u[k];
   }
 }
 
@@ -1072,19 +1101,64 @@ dmg_status launch_post(const StripConfig& cfg, const T* S, const T* uin, T* u, c
                                stop, s, x64);
 }
 
+TailLayout tail_layout(const int* nx, const int* ny, int nlev, int m, int elem) {
+  TailLayout t;
+  int off = 0;
+  int rmax = 0;
+  for (int l = 0; l < nlev; ++l) {
+    const int n = nx[l] * ny[l];
+    if (l + 1 < nlev) {
+      t.S[l] = off;
+      off += 5 * n;
+      t.P[l] = off;
+      off += 8 * nx[l + 1] * ny[l + 1];
+      rmax = n > rmax ? n : rmax;
+    } else {
+      t.S[l] = t.P[l] = -1;
+    }
+    t.u[l] = off;
+    off += n;
+    t.b[l] = off;
+    off += n;
+  }
+  t.r = off;
+  off += rmax;
+  size_t bytes = size_t(off) * elem;
+  bytes = (bytes + 15) & ~size_t(15);
+  t.y = int(bytes);
+  t.bytes = bytes + size_t(m > 0 ? m : 1) * sizeof(double);
+  return t;
+}
+
+int device_lds_limit() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 65536;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return 65536;
+  return v > 0 ? v : 65536;
+}
+
 template <class T>
 dmg_status launch_tail(const TailSpec<T>& spec, hipStream_t s) {
   TailArgs<T> a;
   if (spec.nlev > kMaxTail) return fail(DMG_ERR_INVALID_ARG, "tail too deep (%d)", spec.nlev);
+  const TailLayout lay = tail_layout(spec.nx, spec.ny, spec.nlev, spec.m, int(sizeof(T)));
+  if (lay.bytes > size_t(device_lds_limit()))
+    return fail(DMG_ERR_INVALID_ARG, "coarse tail needs %zu bytes of LDS", lay.bytes);
   for (int l = 0; l < spec.nlev; ++l) {
     a.L[l].S = spec.S[l];
     a.L[l].u = spec.u[l];
     a.L[l].b = spec.b[l];
-    a.L[l].r = spec.r[l];
     a.L[l].P = spec.P[l];
     a.L[l].nx = spec.nx[l];
     a.L[l].ny = spec.ny[l];
+    a.oS[l] = lay.S[l];
+    a.ou[l] = lay.u[l];
+    a.ob[l] = lay.b[l];
+    a.oP[l] = lay.P[l];
   }
+  a.o_r = lay.r;
+  a.o_y = lay.y;
   a.nlev = spec.nlev;
   a.zero_top = spec.zero_top;
   a.m = spec.m;
@@ -1097,7 +1171,7 @@ dmg_status launch_tail(const TailSpec<T>& spec, hipStream_t s) {
   a.nu_pre = spec.nu_pre;
   a.nu_post = spec.nu_post;
   a.stop = spec.stop;
-  k_tail<T><<<1, 1024, sizeof(double) * size_t(spec.m > 0 ? spec.m : 1), s>>>(a);
+  k_tail<T><<<1, 1024, lay.bytes, s>>>(a);
   return launch_check("tail");
 }
 
