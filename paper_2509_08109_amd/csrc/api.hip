@@ -227,6 +227,7 @@ dmg_status tail_launch(dmg_hier* h, T* u_top, const T* b_top, hipStream_t s, boo
   sp.nu_pre = h->opts.nu_pre;
   sp.nu_post = h->opts.nu_post;
   sp.stop = stop;
+  sp.threads = h->tail_threads;
   return launch_tail<T>(sp, s);
 }
 
@@ -463,6 +464,39 @@ dmg_status tune_levels(dmg_hier* h, int reps, hipStream_t s) {
   return st;
 }
 
+// Picks the coarse-tail workgroup size by timing the tail alone on (u_top, b_top).
+template <class T>
+dmg_status tune_tail(dmg_hier* h, T* u_top, const T* b_top, int reps, hipStream_t s) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  DMG_HIP(hipEventCreate(&e0));
+  DMG_HIP(hipEventCreate(&e1));
+  dmg_status st = DMG_OK;
+  int best = h->tail_threads;
+  float best_ms = 1e30f;
+  for (int nt : {256, 512, 1024}) {
+    h->tail_threads = nt;
+    for (int w = 0; w < 2 && st == DMG_OK; ++w) st = tail_launch<T>(h, u_top, b_top, s, true, nullptr);
+    if (st != DMG_OK) break;
+    if (hipEventRecord(e0, s) != hipSuccess) { st = fail(DMG_ERR_HIP, "event record failed"); break; }
+    for (int r = 0; r < reps && st == DMG_OK; ++r) st = tail_launch<T>(h, u_top, b_top, s, true, nullptr);
+    if (st != DMG_OK) break;
+    float ms = 0.f;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      st = fail(DMG_ERR_HIP, "event timing failed");
+      break;
+    }
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = nt;
+    }
+  }
+  h->tail_threads = best;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
+}
+
 dmg_status setup_impl(dmg_hier* h, const double* S, hipStream_t s) {
   const size_t n0 = h->L[0].n();
   DMG_HIP(hipMemcpyAsync(h->L[0].S, S, 5 * n0 * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -685,7 +719,13 @@ dmg_status dmg_autotune(dmg_hier* h, double* u, const double* b, int32_t flags, 
   graph_reset(h->graph);
   if (flags & 1) {
     DMG_CHECK(tune_levels<double>(h, reps, stream));
-    if (h->opts.precision == DMG_FP32_IR) DMG_CHECK(tune_levels<float>(h, reps, stream));
+    Level& T0 = h->L[h->tail];
+    if (h->opts.precision == DMG_FP32_IR) {
+      DMG_CHECK(tune_levels<float>(h, reps, stream));
+      DMG_CHECK(tune_tail<float>(h, T0.u32, T0.b32, reps, stream));
+    } else {
+      DMG_CHECK(tune_tail<double>(h, h->tail == 0 ? u : T0.u, h->tail == 0 ? b : T0.b, reps, stream));
+    }
   }
   if (flags & 2) {
     static const int32_t cand[4][4] = {{0, 1, 2, 3}, {1, 0, 3, 2}, {2, 3, 0, 1}, {3, 2, 1, 0}};

@@ -102,6 +102,8 @@ struct dmg_hier {
   dmg_options opts;
   std::vector<dmg::Level> L;
   int tail = 0;               // first level handled by the coarse-tail kernel
+  int tail_threads = 1024;    // workgroup size of the coarse-tail kernel (tuned; no effect on
+                              // the result)
   int m_coarse = 0;           // unknowns of the coarsest interior system
   int* coarse_idx = nullptr;  // [m] vertex index of each coarsest unknown
   double* chol = nullptr;     // [m][m] Cholesky factor (lower), float64
@@ -187,6 +189,7 @@ struct TailSpec {
   int pre[4], post[4];
   int nu_pre = 1, nu_post = 1;
   const int* stop = nullptr;
+  int threads = 1024;  // workgroup size: a multiple of 64 in [64, 1024]
 };
 // LDS layout of the coarse-tail kernel for levels nx[0..nlev) (the last one the coarsest, with
 // m unknowns): per level S [5 n] and P [8 n_next] (not at the coarsest), u [n], b [n]; then the

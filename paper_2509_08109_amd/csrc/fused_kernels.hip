@@ -668,6 +668,7 @@ template <class T>
 struct WaveCol {
   T u[RU];
   T C[RS], W[RS], Sv[RS], SW[RS], SE[RS], b[RS];
+  T rC[RS];                    // 1 / C, formed when the row is stored
   T Er[RS], NEr[RS], NWl[RS];  // W and SW of lane+1, SE of lane-1, same row
   T r[RS];                     // residuals (pre)
 };
@@ -678,18 +679,22 @@ struct WaveCol {
 __device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
+// Off-diagonal part of row JR's stencil applied to u, summed per stencil row (south, own, north)
+// and then (south + north) + own: each group waits only for its own row of u, so the group fed
+// by the update just made is short.
 template <class T, int UM, int U0, int UP, int S0, int SP>
 __device__ __forceinline__ T offdiag_w(const WaveCol<T>& c) {
 #pragma clang fp contract(off)
   const T um = c.u[UM], u0 = c.u[U0], up = c.u[UP];
-  T acc = c.SW[S0] * from_left(um);
-  acc = fmad(c.Sv[S0], um, acc);
-  acc = fmad(c.SE[S0], from_right(um), acc);
-  acc = fmad(c.W[S0], from_left(u0), acc);
-  acc = fmad(c.Er[S0], from_right(u0), acc);
-  acc = fmad(c.NWl[SP], from_left(up), acc);
-  acc = fmad(c.Sv[SP], up, acc);
-  return fmad(c.NEr[SP], from_right(up), acc);
+  T s1 = c.SW[S0] * from_left(um);
+  s1 = fmad(c.Sv[S0], um, s1);
+  s1 = fmad(c.SE[S0], from_right(um), s1);
+  T s3 = c.NWl[SP] * from_left(up);
+  s3 = fmad(c.Sv[SP], up, s3);
+  s3 = fmad(c.NEr[SP], from_right(up), s3);
+  T s2 = c.W[S0] * from_left(u0);
+  s2 = fmad(c.Er[S0], from_right(u0), s2);
+  return (s1 + s3) + s2;
 }
 
 // Gauss-Seidel update of this lane's point on the row at relative index JR where `ok` holds.
@@ -698,8 +703,10 @@ template <class T, int JR>
 __device__ __forceinline__ void gs_wave(WaveCol<T>& c, bool ok) {
   constexpr int U0 = umod(JR), UM = umod(JR - 1), UP = umod(JR + 1);
   constexpr int S0 = smod(JR), SP = smod(JR + 1);
-  const T off = offdiag_w<T, UM, U0, UP, S0, SP>(c);
-  const T v = (c.b[S0] - off) / (ok ? c.C[S0] : T(1));
+  const T num = c.b[S0] - offdiag_w<T, UM, U0, UP, S0, SP>(c);
+  // num / C from the stored reciprocal and one residual correction
+  const T q0 = num * c.rC[S0];
+  const T v = fmad(fmad(-q0, c.C[S0], num), c.rC[S0], q0);
   c.u[U0] = ok ? v : c.u[U0];
 }
 
@@ -718,6 +725,7 @@ __device__ __forceinline__ void store_row_w(WaveCol<T>& c, const RowRegs<T>& g) 
   c.u[U0] = g.u;
   c.b[S0] = g.b;
   c.C[S0] = g.s[0];
+  c.rC[S0] = T(1) / (g.s[0] != T(0) ? g.s[0] : T(1));
   c.W[S0] = g.s[1];
   c.Sv[S0] = g.s[2];
   c.SW[S0] = g.s[3];
@@ -791,8 +799,8 @@ __global__ __launch_bounds__(64) void k_wave(StripArgs<T> a) {
   for (int k = 0; k < RU; ++k) c.u[k] = T(0);
 #pragma unroll
   for (int k = 0; k < RS; ++k)
-    c.C[k] = c.W[k] = c.Sv[k] = c.SW[k] = c.SE[k] = c.b[k] = c.Er[k] = c.NEr[k] = c.NWl[k] =
-        c.r[k] = T(0);
+    c.C[k] = c.rC[k] = c.W[k] = c.Sv[k] = c.SW[k] = c.SE[k] = c.b[k] = c.Er[k] = c.NEr[k] =
+        c.NWl[k] = c.r[k] = T(0);
   RowRegs<T> gA0, gA1, gB0, gB1;
   CoarseRegs<T> cr;
   load_row<T, READ_U>(a, i, a0 - 1, gA0);
@@ -868,15 +876,15 @@ __global__ __launch_bounds__(64) void k_wave(StripArgs<T> a) {
         T acc2 = T(0);
         if (inner_c) {
 #pragma clang fp contract(off)
-          acc2 = pw[0] * rml;
-          acc2 = fmad(pw[1], rm, acc2);
-          acc2 = fmad(pw[2], rmr, acc2);
-          acc2 = fmad(pw[3], r0l, acc2);
-          acc2 = acc2 + r0;
-          acc2 = fmad(pw[4], r0r, acc2);
-          acc2 = fmad(pw[5], rpl, acc2);
-          acc2 = fmad(pw[6], rp, acc2);
-          acc2 = fmad(pw[7], rpr, acc2);
+          T g1 = pw[0] * rml;
+          g1 = fmad(pw[1], rm, g1);
+          g1 = fmad(pw[2], rmr, g1);
+          T g2 = fmad(pw[3], r0l, r0);
+          g2 = fmad(pw[4], r0r, g2);
+          T g3 = pw[5] * rpl;
+          g3 = fmad(pw[6], rp, g3);
+          g3 = fmad(pw[7], rpr, g3);
+          acc2 = (g1 + g2) + g3;
         }
         if (J < ncy) a.bH[size_t(J) * ncx + I] = acc2;
       }
@@ -1145,6 +1153,8 @@ dmg_status launch_tail(const TailSpec<T>& spec, hipStream_t s) {
   const TailLayout lay = tail_layout(spec.nx, spec.ny, spec.nlev, spec.m, int(sizeof(T)));
   if (lay.bytes > size_t(device_lds_limit()))
     return fail(DMG_ERR_INVALID_ARG, "coarse tail needs %zu bytes of LDS", lay.bytes);
+  if (spec.threads < 64 || spec.threads > 1024 || spec.threads % 64)
+    return fail(DMG_ERR_INVALID_ARG, "coarse tail workgroup size %d", spec.threads);
   for (int l = 0; l < spec.nlev; ++l) {
     a.L[l].S = spec.S[l];
     a.L[l].u = spec.u[l];
@@ -1171,7 +1181,7 @@ dmg_status launch_tail(const TailSpec<T>& spec, hipStream_t s) {
   a.nu_pre = spec.nu_pre;
   a.nu_post = spec.nu_post;
   a.stop = spec.stop;
-  k_tail<T><<<1, 1024, lay.bytes, s>>>(a);
+  k_tail<T><<<1, spec.threads, lay.bytes, s>>>(a);
   return launch_check("tail");
 }
 
