@@ -139,6 +139,9 @@ def kernel_roofline(dmg, h, b, workload: str, reps: int = 20):
             h.sweep(0, kind, u, b)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
+        # a bounded spin on the stream first, so that every timed launch is queued before the
+        # first one starts: the events then bracket back-to-back kernels, not host submission
+        torch.cuda._sleep(20_000_000)
         e0.record()
         for _ in range(reps):
             h.sweep(0, kind, u, b)

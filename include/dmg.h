@@ -203,10 +203,10 @@ void dmg_transfer_destroy(dmg_transfer* t);
 
 /* ---- a10: batched solve of independent instances ----------------------------------------
  * count instances with dims nx[k], ny[k] (host arrays) and fine stencils S[k] (host array of
- * device pointers).  One workspace holds every hierarchy.  dmg_batch_solve runs all instances'
- * V-cycles level by level in shared launches (one kernel per step over every instance's tiles)
- * until each instance meets rtol; iters (host, [count], nullable) receives per-instance
- * counts, relres (host, [count], nullable) final relative residuals. */
+ * device pointers).  One workspace holds every hierarchy.  dmg_batch_solve solves the
+ * instances one after another on `stream` (each as dmg_solve) until each meets rtol; iters
+ * (host, [count], nullable) receives per-instance counts, relres (host, [count], nullable) final
+ * relative residuals. */
 dmg_status dmg_batch_workspace_bytes(int32_t count, const int32_t* nx, const int32_t* ny,
                                      const dmg_options* opts, size_t* bytes);
 dmg_status dmg_batch_setup(int32_t count, const int32_t* nx, const int32_t* ny,
