@@ -12,10 +12,11 @@ hierarchy setup (operator-induced interpolation, Galerkin levels, coarsest facto
 solve.  value = interior DoF x steps / wall time.
 
 Extra legs (same JSON line): the float32-refined solve at the same size, the 4097 x 4097 size
-in float64 and float32-refined form, the roofline of the dominant kernel (timed with HIP events
-on its own stream), and the float64 CPU oracle timed on the host (cpu_baseline).
+in float64 and float32-refined form, the batch of 256 uneven instances, the roofline of the
+dominant kernel (timed with HIP events on the library's stream), and the float64 CPU oracle
+timed on the host (cpu_baseline).
 
-    python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--n 1025] [--no-c3] [--no-cpu]
+    python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--n 1025] [--no-c3] [--no-c4] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -158,6 +159,50 @@ def kernel_roofline(dmg, h, b, workload: str, reps: int = 20):
                 bytes_per_launch=bytes_per_launch, avg_us=dom["avg_us"], kernels=out)
 
 
+def run_batch_leg(dmg, dev, steps: int, count: int = 256):
+    """The batch workload: ``count`` independent star instances, sizes uniform over
+    {129, 257, 513, 1025}^2, each with its own map deformation, K and b (root seed 3), solved to
+    1e-10 together by the batched schedule.  Generation + assembly and setup are timed apart
+    from the solves (solve-only rate = interior DoF of all instances x steps / wall)."""
+    import torch
+
+    from problems.batch_device import star_batch_device
+    t0 = time.perf_counter()
+    Ss, bs, sizes = [], [], []
+    for n, jac, K, b in star_batch_device(count, device=dev):
+        Ss.append(dmg.assemble_stencil(jac, K))
+        bs.append(b)
+        sizes.append(n)
+        del jac, K
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    bt = dmg.BatchSolver(Ss)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    bt.autotune(bs, reps=2)
+    us = [torch.zeros_like(b) for b in bs]
+    _, its, rels = bt.solve(bs, us=us, rtol=1e-10)          # warm-up (schedule, graph capture)
+    wall = 0.0
+    for _ in range(steps):
+        for u in us:
+            u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, its, rels = bt.solve(bs, us=us, rtol=1e-10)
+        torch.cuda.synchronize()
+        wall += time.perf_counter() - t0
+    dof = sum((n - 2) ** 2 for n in sizes)
+    bt.close()
+    del Ss, bs, us
+    torch.cuda.empty_cache()
+    return {"value": round(dof * steps / wall, 1), "unit": "DoF/s", "instances": count,
+            "dof": dof, "sizes": {str(n): sizes.count(n) for n in sorted(set(sizes))},
+            "cycles_min": min(its), "cycles_max": max(its), "max_relres": max(rels),
+            "ms_per_batch_solve": round(1e3 * wall / steps, 2), "steps": steps,
+            "generate_and_assemble_s": round(t_gen, 2), "setup_s": round(t_setup, 2)}
+
+
 CPU_SNIPPET = r"""
 import json, sys, time
 sys.path.insert(0, {root!r})
@@ -206,6 +251,7 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-c3", action="store_true", help="skip the 4097 x 4097 legs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-c4", action="store_true", help="skip the 256-instance batch leg")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -290,6 +336,9 @@ def main():
             "roofline": roof3, "steps": st3,
         }
         del jac3, K3, b3, u3, x3, u3_64
+    if not args.no_c4:
+        log("batch leg: 256 star instances")
+        res["c4_batch"] = run_batch_leg(dmg, dev, max(1, args.steps // 2))
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         res["cpu_baseline"] = cpu_baseline(args.n, args.seed)

@@ -202,11 +202,18 @@ dmg_status dmg_transfer_to_grid(dmg_transfer* t, const double* r_p, double* r_c,
 void dmg_transfer_destroy(dmg_transfer* t);
 
 /* ---- a10: batched solve of independent instances ----------------------------------------
- * count instances with dims nx[k], ny[k] (host arrays) and fine stencils S[k] (host array of
- * device pointers).  One workspace holds every hierarchy.  dmg_batch_solve solves the
- * instances one after another on `stream` (each as dmg_solve) until each meets rtol; iters
- * (host, [count], nullable) receives per-instance counts, relres (host, [count], nullable) final
- * relative residuals. */
+ * count instances with dims nx[k], ny[k] (host arrays, any mix of 2^k+1 sizes) and fine stencils
+ * S[k] (host array of device pointers).  One workspace holds every hierarchy plus the batch's
+ * schedule.  dmg_batch_solve runs one batched V-cycle per step: each fused sweep is launched
+ * once per level size over the tiles of every instance having a level of that size (largest
+ * first going down, smallest first going up), then every instance's coarse tail (one workgroup
+ * each) and convergence check.  Four steps are captured in one hipGraph (when `stream` is not
+ * the legacy default stream) and replayed until each instance meets ||b - A u|| <= rtol ||b||
+ * or max_iters; a converged instance's work stops at once.  The iterates equal those of
+ * dmg_solve on each instance.  u (in: initial guess, out: solution) and b are host arrays of
+ * device pointers; iters / relres (host, [count], nullable) receive per-instance counts and
+ * final relative residuals.  float64 only (DMG_ERR_UNSUPPORTED otherwise); nu_pre + nu_post
+ * must be even.  Returns DMG_ERR_NO_CONVERGENCE if any instance did not converge. */
 dmg_status dmg_batch_workspace_bytes(int32_t count, const int32_t* nx, const int32_t* ny,
                                      const dmg_options* opts, size_t* bytes);
 dmg_status dmg_batch_setup(int32_t count, const int32_t* nx, const int32_t* ny,
@@ -215,6 +222,11 @@ dmg_status dmg_batch_setup(int32_t count, const int32_t* nx, const int32_t* ny,
 dmg_status dmg_batch_solve(dmg_batch* bt, double* const* u, const double* const* b,
                            double rtol, int32_t max_iters, int32_t* iters, double* relres,
                            hipStream_t stream);
+/* Picks the wave-strip segment height of each level size and the coarse-tail workgroup size by
+ * timing batched steps on (u, b) -- numerically neutral.  u is scratch (overwritten).
+ * Synchronous. */
+dmg_status dmg_batch_autotune(dmg_batch* bt, double* const* u, const double* const* b,
+                              int32_t reps, hipStream_t stream);
 void dmg_batch_destroy(dmg_batch* bt);
 
 #ifdef __cplusplus

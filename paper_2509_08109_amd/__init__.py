@@ -275,11 +275,20 @@ class BatchSolver:
                                          int(nbytes.value), _stream(self.device), C.byref(h)))
         self._h = h
 
+    def _ptrs(self, arrays, name):
+        return (C.c_void_p * self.count)(*[_dev(a, (ny, nx), name) for a, (nx, ny) in zip(arrays, self.dims)])
+
+    def autotune(self, bs, reps: int = 3) -> None:
+        """Pick per-size launch shapes and the tail workgroup size by timing batched steps."""
+        us = [torch.zeros((ny, nx), dtype=torch.float64, device=self.device) for nx, ny in self.dims]
+        _lib.check(lib().dmg_batch_autotune(self._h, self._ptrs(us, "u"), self._ptrs(bs, "b"), int(reps),
+                                            _stream(self.device)))
+
     def solve(self, bs, us=None, rtol: float = 1e-10, max_iters: int = 200, raise_on_fail: bool = True):
         if us is None:
             us = [torch.zeros((ny, nx), dtype=torch.float64, device=self.device) for nx, ny in self.dims]
-        up = (C.c_void_p * self.count)(*[_dev(u, (ny, nx), "u") for u, (nx, ny) in zip(us, self.dims)])
-        bp = (C.c_void_p * self.count)(*[_dev(b, (ny, nx), "b") for b, (nx, ny) in zip(bs, self.dims)])
+        up = self._ptrs(us, "u")
+        bp = self._ptrs(bs, "b")
         it = (C.c_int32 * self.count)()
         rr = (C.c_double * self.count)()
         st = lib().dmg_batch_solve(self._h, up, bp, float(rtol), int(max_iters), it, rr, _stream(self.device))

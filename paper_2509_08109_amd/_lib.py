@@ -60,6 +60,7 @@ SIGNATURES = {
     "dmg_batch_workspace_bytes": (_st, [_i32, _p, _p, C.POINTER(Options), C.POINTER(C.c_size_t)]),
     "dmg_batch_setup": (_st, [_i32, _p, _p, _p, C.POINTER(Options), _p, C.c_size_t, _p, C.POINTER(_p)]),
     "dmg_batch_solve": (_st, [_p, _p, _p, C.c_double, _i32, _p, _p, _p]),
+    "dmg_batch_autotune": (_st, [_p, _p, _p, _i32, _p]),
     "dmg_batch_destroy": (None, [_p]),
 }
 

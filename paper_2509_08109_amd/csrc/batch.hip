@@ -1,17 +1,431 @@
-// Batched solves of independent instances.  Every instance's hierarchy is carved out of one
-// caller workspace; dmg_batch_solve advances all unconverged instances cycle by cycle.
+// Batched solves of independent instances (uneven sizes).  Every instance's hierarchy is carved
+// out of one caller workspace.  One batched V-cycle launches each fused sweep once per level
+// size, over the tiles of every instance that has a level of that size: largest size first on
+// the way down and smallest first on the way up, which keeps each instance's own level order.
+// Then come the coarse tails (one workgroup per instance) and the convergence checks (one
+// workgroup per instance).  Four such steps are captured in one hipGraph and replayed until
+// every instance has stopped; each instance has its own stop flag, so the tiles of converged
+// instances exit at once.  Results equal those of dmg_solve on each instance alone (the wave
+// sweeps, the tail and the check do the same arithmetic; launch shapes are numerically neutral).
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <map>
 #include <memory>
+#include <tuple>
+#include <vector>
 
 #include "dmg_internal.h"
 
+namespace {
+
+constexpr int kNormBlocks = 64;     // workgroups per instance for the starting norms
+constexpr size_t kArgAlign = 256;   // alignment of each argument list in the argument buffer
+
+struct Launch {
+  enum Kind { WAVE, TAIL, RESID, CHECK } kind;
+  int mode = 0;        // WAVE: 1 pre, 2 post with prolongation, 3 post
+  int count = 0;       // instances (list length)
+  int tiles_per = 0;   // WAVE: tiles per instance
+  size_t off = 0;      // byte offset of the list in the device argument buffer
+  size_t lds = 0;      // TAIL: LDS bytes
+};
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
 struct dmg_batch {
+  dmg_options opts;
   std::vector<dmg_hier*> inst;
+  int* state = nullptr;           // [count][4] device: stop, steps, max steps, unused
+  double* summary = nullptr;      // [count][2] device: ||b||, starting ||r||
+  double* rel = nullptr;          // [count] device: final relative residual
+  int* steps = nullptr;           // [count] device: steps taken
+  double* npart = nullptr;        // [count][kNormBlocks][2] device
+  unsigned char* args = nullptr;  // device argument lists
+  size_t args_cap = 0;
+  int tail_threads = 256;
+  std::map<std::pair<int, int>, int> seg_h;  // wave-strip rows per segment, per level size
+  // schedule for the current arrays
+  std::vector<Launch> step;
+  size_t norm_off = 0, check_off = 0;
+  std::vector<const void*> key;
+  double key_rtol = -1.0;
+  int key_max = -1;
+  bool built = false;
+  // graph of kChunk steps
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t gstream = nullptr;
+  // pinned host mirrors
+  int* h_state = nullptr;
+  double* h_summary = nullptr;
+  double* h_rel = nullptr;
+  int* h_steps = nullptr;
+
+  void reset_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    gstream = nullptr;
+  }
   ~dmg_batch() {
+    reset_graph();
+    if (h_state) (void)hipHostFree(h_state);
+    if (h_summary) (void)hipHostFree(h_summary);
+    if (h_rel) (void)hipHostFree(h_rel);
+    if (h_steps) (void)hipHostFree(h_steps);
     for (auto* h : inst) dmg_destroy(h);
   }
 };
 
 using namespace dmg;
+
+namespace {
+
+size_t args_capacity(int count, const dmg_options& o) {
+  const size_t sweeps = size_t(o.nu_pre + o.nu_post);
+  const size_t per_inst = size_t(kMaxLevels) * sweeps * sizeof(StripArgs<double>) +
+                          sizeof(TailArgs<double>) + sizeof(CheckArgs) + 2 * sizeof(NormArgs);
+  const size_t lists = size_t(count) * kMaxLevels * sweeps + 8;
+  return size_t(count) * per_inst + lists * kArgAlign;
+}
+
+size_t batch_extra_bytes(int count, const dmg_options& o) {
+  size_t b = 0;
+  b += align_up(size_t(count) * 4 * sizeof(int), 256);
+  b += align_up(size_t(count) * 2 * sizeof(double), 256);
+  b += align_up(size_t(count) * sizeof(double), 256);
+  b += align_up(size_t(count) * sizeof(int), 256);
+  b += align_up(size_t(count) * kNormBlocks * 2 * sizeof(double), 256);
+  b += align_up(args_capacity(count, o), 256);
+  return b;
+}
+
+int tiles_of(int nx, int ny, int seg_h) {
+  int ns = 0, nseg = 0;
+  strip_blocks(nx, ny, 64, seg_h, &ns, &nseg);
+  return ns * nseg;
+}
+
+// Default launch shape of one level size shared by `members` instances: the tallest segment that
+// still gives >= 2048 tiles in the launch, within the per-instance partials capacity.
+int default_seg_h(int nx, int ny, int members) {
+  int h = 8;
+  for (int c = 128; c >= 8; c >>= 1)
+    if (long(members) * tiles_of(nx, ny, c) >= 2048) {
+      h = c;
+      break;
+    }
+  while (tiles_of(nx, ny, h) > kMaxPartials) h *= 2;
+  return h;
+}
+
+struct OrderP {
+  int pf, cA, cB;
+};
+OrderP order_of(const int32_t* ord) { return OrderP{ord[0] >> 1, ord[0] & 1, ord[2] & 1}; }
+
+// Builds the argument lists and launch sequence of one batched step for arrays (u, b).
+dmg_status build_schedule(dmg_batch* bt, double* const* u, const double* const* b, double rtol,
+                          int32_t max_iters) {
+  const int count = int(bt->inst.size());
+  const dmg_options& o = bt->opts;
+  const OrderP pre = order_of(o.pre_order), post = order_of(o.post_order);
+  std::vector<unsigned char> host(bt->args_cap);
+  size_t used = 0;
+  auto put = [&](const void* p, size_t n, size_t* off) -> dmg_status {
+    const size_t at = align_up(used, kArgAlign);
+    if (at + n > host.size()) return fail(DMG_ERR_WORKSPACE, "batch argument buffer too small");
+    std::memcpy(host.data() + at, p, n);
+    used = at + n;
+    *off = at;
+    return DMG_OK;
+  };
+  struct Sweep {
+    const double* uin;
+    double* u;
+    const double* e;
+    double* partials;
+  };
+  // per instance and strip level: the buffers of each pre and post sweep (as in one V-cycle)
+  std::vector<std::vector<std::vector<Sweep>>> pre_sw(count), post_sw(count);
+  for (int k = 0; k < count; ++k) {
+    dmg_hier* h = bt->inst[k];
+    const int T = h->tail;
+    double* u0 = u[k];
+    auto other = [&](int l, const double* x) -> double* {
+      double* a = l == 0 ? u0 : h->L[l].u;
+      return x == a ? h->L[l].t : a;
+    };
+    std::vector<const double*> cur(size_t(T) + 1, nullptr);
+    pre_sw[k].assign(size_t(T), {});
+    post_sw[k].assign(size_t(T), {});
+    for (int l = 0; l < T; ++l) {
+      const double* src = l == 0 ? u0 : nullptr;
+      for (int s = 0; s < o.nu_pre; ++s) {
+        double* dst = src ? other(l, src) : h->L[l].t;
+        pre_sw[k][l].push_back(Sweep{src, dst, nullptr, nullptr});
+        src = dst;
+      }
+      cur[l] = src;
+    }
+    const double* e = T == 0 ? u0 : h->L[T].u;
+    for (int l = T - 1; l >= 0; --l) {
+      for (int s = 0; s < o.nu_post; ++s) {
+        double* dst = other(l, cur[l]);
+        const bool last = s + 1 == o.nu_post;
+        post_sw[k][l].push_back(
+            Sweep{cur[l], dst, s == 0 ? e : nullptr, (l == 0 && last) ? h->partials : nullptr});
+        cur[l] = dst;
+      }
+      e = cur[l];
+    }
+    if (T > 0 && cur[0] != u0)
+      return fail(DMG_ERR_UNSUPPORTED, "batched cycles need an even number of level-0 sweeps");
+  }
+  // level sizes, largest first
+  std::map<std::tuple<long, int, int>, std::vector<std::pair<int, int>>, std::greater<>> groups;
+  for (int k = 0; k < count; ++k)
+    for (int l = 0; l < bt->inst[k]->tail; ++l) {
+      const Level& L = bt->inst[k]->L[l];
+      groups[{long(L.nx) * L.ny, L.nx, L.ny}].push_back({k, l});
+    }
+  std::vector<int> level0_tiles(count, 0);
+  auto wave_list = [&](const std::vector<std::pair<int, int>>& mem, bool is_pre, int s,
+                       Launch* out) -> dmg_status {
+    std::vector<StripArgs<double>> list;
+    int tiles_per = 0;
+    for (auto [k, l] : mem) {
+      dmg_hier* h = bt->inst[k];
+      const Level& L = h->L[l];
+      const Sweep& sw = is_pre ? pre_sw[k][l][s] : post_sw[k][l][s];
+      StripArgs<double> a{};
+      a.S = L.Sp;
+      a.uin = sw.uin;
+      a.u = sw.u;
+      a.b = l == 0 ? b[k] : L.b;
+      a.P = L.P;
+      a.bH = is_pre ? h->L[l + 1].b : nullptr;
+      a.e = sw.e;
+      a.partials = sw.partials;
+      a.nx = L.nx;
+      a.ny = L.ny;
+      a.seg_h = bt->seg_h[{L.nx, L.ny}];
+      strip_blocks(L.nx, L.ny, 64, a.seg_h, &a.nstrips, &a.nsegs);
+      const OrderP& op = is_pre ? pre : post;
+      a.pf = op.pf;
+      a.cA = op.cA;
+      a.cB = op.cB;
+      a.stop = bt->state + 4 * k;
+      a.x64 = nullptr;
+      tiles_per = a.nstrips * a.nsegs;
+      if (l == 0) level0_tiles[k] = tiles_per;
+      list.push_back(a);
+    }
+    out->kind = Launch::WAVE;
+    out->count = int(list.size());
+    out->tiles_per = tiles_per;
+    return put(list.data(), list.size() * sizeof(list[0]), &out->off);
+  };
+  std::vector<Launch> seq;
+  for (auto& [key, mem] : groups)
+    for (int s = 0; s < o.nu_pre; ++s) {
+      Launch L;
+      DMG_CHECK(wave_list(mem, true, s, &L));
+      L.mode = 1;
+      seq.push_back(L);
+    }
+  {  // coarse tails
+    std::vector<TailArgs<double>> list(count);
+    size_t lds = 0;
+    for (int k = 0; k < count; ++k) {
+      dmg_hier* h = bt->inst[k];
+      const int T = h->tail, nl = int(h->L.size());
+      TailSpec<double> sp;
+      sp.nlev = nl - T;
+      for (int l = T; l < nl; ++l) {
+        const Level& L = h->L[l];
+        const int i = l - T;
+        sp.S[i] = L.S;
+        sp.u[i] = i == 0 ? (T == 0 ? u[k] : L.u) : L.u;
+        sp.b[i] = i == 0 ? (T == 0 ? const_cast<double*>(b[k]) : L.b) : L.b;
+        sp.P[i] = L.P;
+        sp.nx[i] = L.nx;
+        sp.ny[i] = L.ny;
+      }
+      sp.zero_top = T > 0;
+      sp.m = h->m_coarse;
+      sp.idx = h->coarse_idx;
+      sp.chol = h->chol;
+      for (int c = 0; c < 4; ++c) {
+        sp.pre[c] = o.pre_order[c];
+        sp.post[c] = o.post_order[c];
+      }
+      sp.nu_pre = o.nu_pre;
+      sp.nu_post = o.nu_post;
+      sp.stop = bt->state + 4 * k;
+      sp.threads = bt->tail_threads;
+      size_t bytes = 0;
+      DMG_CHECK(make_tail_args<double>(sp, &list[k], &bytes));
+      lds = std::max(lds, bytes);
+    }
+    Launch L;
+    L.kind = Launch::TAIL;
+    L.count = count;
+    L.lds = lds;
+    DMG_CHECK(put(list.data(), list.size() * sizeof(list[0]), &L.off));
+    seq.push_back(L);
+  }
+  for (auto it = groups.rbegin(); it != groups.rend(); ++it)
+    for (int s = 0; s < o.nu_post; ++s) {
+      Launch L;
+      DMG_CHECK(wave_list(it->second, false, s, &L));
+      L.mode = s == 0 ? 2 : 3;
+      seq.push_back(L);
+    }
+  // per-instance norm arguments (starting norms; residual partials of all-tail instances)
+  std::vector<NormArgs> norms(count), tail_only;
+  for (int k = 0; k < count; ++k) {
+    dmg_hier* h = bt->inst[k];
+    const Level& L0 = h->L[0];
+    norms[k] = NormArgs{L0.S, u[k], b[k], L0.nx, L0.ny, h->scalars, bt->state + 4 * k, rtol,
+                        max_iters, h->partials};
+    if (h->tail == 0) tail_only.push_back(norms[k]);
+  }
+  if (!tail_only.empty()) {
+    Launch L;
+    L.kind = Launch::RESID;
+    L.count = int(tail_only.size());
+    DMG_CHECK(put(tail_only.data(), tail_only.size() * sizeof(NormArgs), &L.off));
+    seq.push_back(L);
+  }
+  {
+    std::vector<CheckArgs> list(count);
+    for (int k = 0; k < count; ++k) {
+      dmg_hier* h = bt->inst[k];
+      list[k] = CheckArgs{h->partials, h->tail > 0 ? level0_tiles[k] : kNormBlocks,
+                          h->scalars + 2, h->scalars, bt->state + 4 * k, h->hist, kMaxHistory};
+    }
+    Launch L;
+    L.kind = Launch::CHECK;
+    L.count = count;
+    DMG_CHECK(put(list.data(), list.size() * sizeof(CheckArgs), &L.off));
+    bt->check_off = L.off;
+    seq.push_back(L);
+  }
+  DMG_CHECK(put(norms.data(), norms.size() * sizeof(NormArgs), &bt->norm_off));
+  DMG_HIP(hipMemcpy(bt->args, host.data(), used, hipMemcpyHostToDevice));
+  bt->step = std::move(seq);
+  bt->built = true;
+  return DMG_OK;
+}
+
+dmg_status run_step(dmg_batch* bt, hipStream_t s) {
+  for (const Launch& L : bt->step) {
+    const unsigned char* p = bt->args + L.off;
+    switch (L.kind) {
+      case Launch::WAVE:
+        DMG_CHECK(launch_wave_multi<double>(reinterpret_cast<const StripArgs<double>*>(p), L.count,
+                                            L.tiles_per, L.mode,
+                                            L.mode == 1 ? order_of(bt->opts.pre_order).pf
+                                                        : order_of(bt->opts.post_order).pf,
+                                            s));
+        break;
+      case Launch::TAIL:
+        DMG_CHECK(launch_tail_multi<double>(reinterpret_cast<const TailArgs<double>*>(p), L.count,
+                                            L.lds, bt->tail_threads, s));
+        break;
+      case Launch::RESID:
+        DMG_CHECK(launch_resid_multi(reinterpret_cast<const NormArgs*>(p), L.count, kNormBlocks, s));
+        break;
+      case Launch::CHECK:
+        DMG_CHECK(launch_check_multi(reinterpret_cast<const CheckArgs*>(p), L.count, s));
+        break;
+    }
+  }
+  return DMG_OK;
+}
+
+// kChunk batched steps, through one captured graph when the stream allows capture.
+dmg_status run_chunk(dmg_batch* bt, hipStream_t s) {
+  auto steps = [&]() -> dmg_status {
+    for (int k = 0; k < kChunk; ++k) DMG_CHECK(run_step(bt, s));
+    return DMG_OK;
+  };
+  if (!bt->opts.use_graph || s == nullptr) return steps();
+  if (!(bt->exec && bt->gstream == s)) {
+    bt->reset_graph();
+    DMG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    const dmg_status st = steps();
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &g);
+    if (st != DMG_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return fail(DMG_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
+    bt->graph = g;
+    const hipError_t ei = hipGraphInstantiate(&bt->exec, g, nullptr, nullptr, 0);
+    if (ei != hipSuccess) {
+      bt->reset_graph();
+      return fail(DMG_ERR_HIP, "graph instantiate failed: %s", hipGetErrorString(ei));
+    }
+    bt->gstream = s;
+  }
+  DMG_HIP(hipGraphLaunch(bt->exec, s));
+  return DMG_OK;
+}
+
+dmg_status ensure_schedule(dmg_batch* bt, double* const* u, const double* const* b, double rtol,
+                           int32_t max_iters) {
+  const int count = int(bt->inst.size());
+  std::vector<const void*> key;
+  key.reserve(2 * size_t(count));
+  for (int k = 0; k < count; ++k) {
+    key.push_back(u[k]);
+    key.push_back(b[k]);
+  }
+  if (bt->built && key == bt->key && rtol == bt->key_rtol && max_iters == bt->key_max)
+    return DMG_OK;
+  bt->reset_graph();
+  bt->built = false;
+  DMG_CHECK(build_schedule(bt, u, b, rtol, max_iters));
+  bt->key = std::move(key);
+  bt->key_rtol = rtol;
+  bt->key_max = max_iters;
+  return DMG_OK;
+}
+
+// Solve state of every instance from its starting norms; returns the count still to iterate.
+dmg_status start_solve(dmg_batch* bt, double* const* u, double rtol, hipStream_t s, int* active) {
+  const int count = int(bt->inst.size());
+  DMG_CHECK(launch_norms_multi(reinterpret_cast<const NormArgs*>(bt->args + bt->norm_off), count,
+                               kNormBlocks, bt->npart, bt->summary, s));
+  DMG_HIP(hipMemcpyAsync(bt->h_summary, bt->summary, size_t(count) * 2 * sizeof(double),
+                         hipMemcpyDeviceToHost, s));
+  DMG_HIP(hipMemcpyAsync(bt->h_state, bt->state, size_t(count) * 4 * sizeof(int),
+                         hipMemcpyDeviceToHost, s));
+  DMG_HIP(hipStreamSynchronize(s));
+  int n = 0;
+  for (int k = 0; k < count; ++k) {
+    const double bn = bt->h_summary[2 * k], rn = bt->h_summary[2 * k + 1];
+    if (!std::isfinite(bn))
+      return fail(DMG_ERR_NONFINITE, "instance %d: right-hand side norm is not finite", k);
+    if (!std::isfinite(rn))
+      return fail(DMG_ERR_NONFINITE, "instance %d: initial residual norm is not finite", k);
+    if (bn == 0.0) DMG_CHECK(launch_fill<double>(u[k], 0.0, bt->inst[k]->L[0].n(), s));
+    if (!bt->h_state[4 * k]) ++n;
+  }
+  (void)rtol;
+  *active = n;
+  return DMG_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -19,13 +433,16 @@ dmg_status dmg_batch_workspace_bytes(int32_t count, const int32_t* nx, const int
                                      const dmg_options* opts, size_t* bytes) {
   clear_error();
   if (count <= 0 || !nx || !ny || !bytes) return fail(DMG_ERR_INVALID_ARG, "bad batch arguments");
+  dmg_options o;
+  dmg_default_options(&o);
+  if (opts) o = *opts;
   size_t total = 0;
   for (int k = 0; k < count; ++k) {
     size_t b = 0;
-    DMG_CHECK(dmg_workspace_bytes(nx[k], ny[k], opts, &b));
-    total += (b + 255) & ~size_t(255);
+    DMG_CHECK(dmg_workspace_bytes(nx[k], ny[k], &o, &b));
+    total += align_up(b, 256);
   }
-  *bytes = total;
+  *bytes = total + batch_extra_bytes(count, o);
   return DMG_OK;
 }
 
@@ -36,23 +453,53 @@ dmg_status dmg_batch_setup(int32_t count, const int32_t* nx, const int32_t* ny,
   if (!out) return fail(DMG_ERR_INVALID_ARG, "null output handle");
   *out = nullptr;
   if (count <= 0 || !nx || !ny || !S) return fail(DMG_ERR_INVALID_ARG, "bad batch arguments");
+  dmg_options o;
+  dmg_default_options(&o);
+  if (opts) o = *opts;
+  if (o.precision != DMG_FP64)
+    return fail(DMG_ERR_UNSUPPORTED, "batched solves run in float64 (precision DMG_FP64)");
   size_t need = 0;
-  DMG_CHECK(dmg_batch_workspace_bytes(count, nx, ny, opts, &need));
+  DMG_CHECK(dmg_batch_workspace_bytes(count, nx, ny, &o, &need));
   if (!workspace || ws_bytes < need)
     return fail(DMG_ERR_WORKSPACE, "batch workspace too small: %zu < %zu bytes", ws_bytes, need);
+  if (reinterpret_cast<uintptr_t>(workspace) % 256)
+    return fail(DMG_ERR_WORKSPACE, "batch workspace must be 256-byte aligned");
   std::unique_ptr<dmg_batch> bt(new dmg_batch);
+  bt->opts = o;
   char* base = static_cast<char*>(workspace);
   size_t off = 0;
   for (int k = 0; k < count; ++k) {
     size_t b = 0;
-    DMG_CHECK(dmg_workspace_bytes(nx[k], ny[k], opts, &b));
-    b = (b + 255) & ~size_t(255);
+    DMG_CHECK(dmg_workspace_bytes(nx[k], ny[k], &o, &b));
+    b = align_up(b, 256);
     dmg_hier* h = nullptr;
-    dmg_status st = dmg_setup(S[k], nx[k], ny[k], opts, base + off, b, stream, &h);
+    const dmg_status st = dmg_setup(S[k], nx[k], ny[k], &o, base + off, b, stream, &h);
     if (st != DMG_OK) return st;
     bt->inst.push_back(h);
     off += b;
   }
+  auto take = [&](size_t n) {
+    void* p = base + off;
+    off += align_up(n, 256);
+    return p;
+  };
+  bt->state = static_cast<int*>(take(size_t(count) * 4 * sizeof(int)));
+  bt->summary = static_cast<double*>(take(size_t(count) * 2 * sizeof(double)));
+  bt->rel = static_cast<double*>(take(size_t(count) * sizeof(double)));
+  bt->steps = static_cast<int*>(take(size_t(count) * sizeof(int)));
+  bt->npart = static_cast<double*>(take(size_t(count) * kNormBlocks * 2 * sizeof(double)));
+  bt->args_cap = args_capacity(count, o);
+  bt->args = static_cast<unsigned char*>(take(bt->args_cap));
+  DMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&bt->h_state), size_t(count) * 4 * sizeof(int)));
+  DMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&bt->h_summary),
+                        size_t(count) * 2 * sizeof(double)));
+  DMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&bt->h_rel), size_t(count) * sizeof(double)));
+  DMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&bt->h_steps), size_t(count) * sizeof(int)));
+  // launch shapes: one per level size, shared by every instance that has that size
+  std::map<std::pair<int, int>, int> members;
+  for (auto* h : bt->inst)
+    for (int l = 0; l < h->tail; ++l) ++members[{h->L[l].nx, h->L[l].ny}];
+  for (auto& [d, m] : members) bt->seg_h[d] = default_seg_h(d.first, d.second, m);
   *out = bt.release();
   return DMG_OK;
 }
@@ -61,18 +508,104 @@ dmg_status dmg_batch_solve(dmg_batch* bt, double* const* u, const double* const*
                            int32_t max_iters, int32_t* iters, double* relres, hipStream_t stream) {
   clear_error();
   if (!bt || !u || !b) return fail(DMG_ERR_INVALID_ARG, "null pointer argument");
-  dmg_status worst = DMG_OK;
-  for (size_t k = 0; k < bt->inst.size(); ++k) {
-    int32_t it = 0;
-    double rr = 0.0;
-    dmg_status st = dmg_solve(bt->inst[k], u[k], b[k], rtol, max_iters, &it, &rr, nullptr, stream);
-    if (iters) iters[k] = it;
-    if (relres) relres[k] = rr;
-    if (st != DMG_OK && st != DMG_ERR_NO_CONVERGENCE) return st;
-    if (st != DMG_OK) worst = st;
+  if (!(rtol >= 0.0) || max_iters < 0) return fail(DMG_ERR_INVALID_ARG, "bad rtol/max_iters");
+  const int count = int(bt->inst.size());
+  for (int k = 0; k < count; ++k)
+    if (!u[k] || !b[k]) return fail(DMG_ERR_INVALID_ARG, "instance %d: null array", k);
+  DMG_CHECK(ensure_schedule(bt, u, b, rtol, max_iters));
+  int active = 0;
+  DMG_CHECK(start_solve(bt, u, rtol, stream, &active));
+  while (active > 0) {
+    DMG_CHECK(run_chunk(bt, stream));
+    DMG_HIP(hipMemcpyAsync(bt->h_state, bt->state, size_t(count) * 4 * sizeof(int),
+                           hipMemcpyDeviceToHost, stream));
+    DMG_HIP(hipStreamSynchronize(stream));
+    active = 0;
+    for (int k = 0; k < count; ++k) active += bt->h_state[4 * k] ? 0 : 1;
   }
-  if (worst != DMG_OK) return fail(worst, "at least one instance did not converge");
+  DMG_CHECK(launch_gather_multi(reinterpret_cast<const CheckArgs*>(bt->args + bt->check_off), count,
+                                bt->rel, bt->steps, stream));
+  DMG_HIP(hipMemcpyAsync(bt->h_rel, bt->rel, size_t(count) * sizeof(double), hipMemcpyDeviceToHost,
+                         stream));
+  DMG_HIP(hipMemcpyAsync(bt->h_steps, bt->steps, size_t(count) * sizeof(int),
+                         hipMemcpyDeviceToHost, stream));
+  DMG_HIP(hipStreamSynchronize(stream));
+  int failed = -1, nonfinite = -1;
+  for (int k = 0; k < count; ++k) {
+    const bool zero_b = bt->h_summary[2 * k] == 0.0;
+    const double r = zero_b ? 0.0 : bt->h_rel[k];
+    if (iters) iters[k] = zero_b ? 0 : bt->h_steps[k];
+    if (relres) relres[k] = r;
+    if (!std::isfinite(r)) nonfinite = k;
+    else if (r > rtol && failed < 0) failed = k;
+  }
+  if (nonfinite >= 0)
+    return fail(DMG_ERR_NONFINITE, "instance %d: residual norm became non-finite", nonfinite);
+  if (failed >= 0)
+    return fail(DMG_ERR_NO_CONVERGENCE, "instance %d (and maybe others) did not converge", failed);
   return DMG_OK;
+}
+
+dmg_status dmg_batch_autotune(dmg_batch* bt, double* const* u, const double* const* b,
+                              int32_t reps, hipStream_t stream) {
+  clear_error();
+  if (!bt || !u || !b) return fail(DMG_ERR_INVALID_ARG, "null pointer argument");
+  if (reps < 1 || reps > 1000) return fail(DMG_ERR_INVALID_ARG, "reps must be in [1,1000]");
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  DMG_HIP(hipEventCreate(&e0));
+  DMG_HIP(hipEventCreate(&e1));
+  // time `reps` batched steps with every instance active (rtol 0, no step limit reached)
+  auto time_steps = [&](float* ms) -> dmg_status {
+    bt->built = false;
+    bt->reset_graph();
+    DMG_CHECK(ensure_schedule(bt, u, b, 0.0, 1 << 30));
+    int active = 0;
+    DMG_CHECK(start_solve(bt, u, 0.0, stream, &active));
+    DMG_CHECK(run_step(bt, stream));
+    DMG_HIP(hipEventRecord(e0, stream));
+    for (int r = 0; r < reps; ++r) DMG_CHECK(run_step(bt, stream));
+    DMG_HIP(hipEventRecord(e1, stream));
+    DMG_HIP(hipEventSynchronize(e1));
+    DMG_HIP(hipEventElapsedTime(ms, e0, e1));
+    return DMG_OK;
+  };
+  dmg_status st = DMG_OK;
+  for (auto& [d, h] : bt->seg_h) {
+    int best = h;
+    float best_ms = 1e30f;
+    for (int c = 2; c <= 128 && st == DMG_OK; c *= 2) {
+      if (tiles_of(d.first, d.second, c) > kMaxPartials) continue;
+      h = c;
+      float ms = 0.f;
+      st = time_steps(&ms);
+      if (st == DMG_OK && ms < best_ms) {
+        best_ms = ms;
+        best = c;
+      }
+      if (c * 2 > d.second + 1) break;
+    }
+    h = best;
+  }
+  if (st == DMG_OK) {
+    int best = bt->tail_threads;
+    float best_ms = 1e30f;
+    for (int t : {256, 512, 1024}) {
+      bt->tail_threads = t;
+      float ms = 0.f;
+      st = time_steps(&ms);
+      if (st != DMG_OK) break;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = t;
+      }
+    }
+    bt->tail_threads = best;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  bt->built = false;
+  bt->reset_graph();
+  return st;
 }
 
 void dmg_batch_destroy(dmg_batch* bt) { delete bt; }

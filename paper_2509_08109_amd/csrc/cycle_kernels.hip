@@ -189,11 +189,10 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ par
 // (||r||^2, ||r||), appends ||r||/||b|| to the history and raises *stop when
 // ||r||^2 <= target^2, the step budget is spent, or the norm is not finite.
 // st[0] = stop flag, st[1] = steps done, st[2] = max steps; sc[1] = ||b||, sc[6] = target^2.
-__global__ __launch_bounds__(256) void k_check(const double* __restrict__ partials, int count,
-                                               double* __restrict__ out,
-                                               const double* __restrict__ sc,
-                                               int* __restrict__ st, double* __restrict__ hist,
-                                               int hist_cap) {
+__device__ __forceinline__ void check_body(const double* __restrict__ partials, int count,
+                                           double* __restrict__ out, const double* __restrict__ sc,
+                                           int* __restrict__ st, double* __restrict__ hist,
+                                           int hist_cap) {
   if (st[0]) return;
   double acc = 0.0;
   for (int k = threadIdx.x; k < count; k += 256) acc += partials[k];
@@ -205,6 +204,108 @@ __global__ __launch_bounds__(256) void k_check(const double* __restrict__ partia
     st[1] = k;
     if (k <= hist_cap) hist[k - 1] = sc[1] > 0.0 ? sqrt(t) / sc[1] : sqrt(t);
     if (!(t > sc[6]) || k >= st[2] || !isfinite(t)) st[0] = 1;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_check(const double* __restrict__ partials, int count,
+                                               double* __restrict__ out,
+                                               const double* __restrict__ sc,
+                                               int* __restrict__ st, double* __restrict__ hist,
+                                               int hist_cap) {
+  check_body(partials, count, out, sc, st, hist, hist_cap);
+}
+
+// One workgroup per instance.
+__global__ __launch_bounds__(256) void k_check_multi(const CheckArgs* __restrict__ list) {
+  const CheckArgs& c = list[blockIdx.x];
+  check_body(c.partials, c.count, c.out, c.sc, c.st, c.hist, c.hist_cap);
+}
+
+// Squared norms of b and of b - A u over the interior of each instance: blocks_per workgroups
+// per instance, partials [instance][workgroup][2] (u null: r = b).
+__global__ __launch_bounds__(256) void k_norms_multi(const NormArgs* __restrict__ list,
+                                                     int blocks_per, double* __restrict__ partials) {
+  const int inst = int(blockIdx.x) / blocks_per, sub = int(blockIdx.x) % blocks_per;
+  const NormArgs& a = list[inst];
+  const int nx = a.nx, ny = a.ny;
+  const size_t N = size_t(nx) * ny;
+  double sb = 0.0, sr = 0.0;
+  for (size_t v = size_t(sub) * 256 + threadIdx.x; v < N; v += size_t(blocks_per) * 256) {
+    const int j = int(v / nx), i = int(v % nx);
+    if (i <= 0 || i >= nx - 1 || j <= 0 || j >= ny - 1) continue;
+    const double bv = a.b[v];
+    const double r = a.u ? bv - (offdiag(a.S, a.u, N, nx, v) + a.S[v] * a.u[v]) : bv;
+    sb += bv * bv;
+    sr += r * r;
+  }
+  const double tb = block_sum(sb);
+  const double tr = block_sum(sr);
+  if (threadIdx.x == 0) {
+    partials[2 * size_t(blockIdx.x)] = tb;
+    partials[2 * size_t(blockIdx.x) + 1] = tr;
+  }
+}
+
+// Squared-residual partials of instances whose whole cycle runs in the coarse tail (no strip
+// sweep produces them): blocks_per workgroups per instance into list[k].partials[0..blocks_per).
+__global__ __launch_bounds__(256) void k_resid_multi(const NormArgs* __restrict__ list,
+                                                     int blocks_per) {
+  const int inst = int(blockIdx.x) / blocks_per, sub = int(blockIdx.x) % blocks_per;
+  const NormArgs& a = list[inst];
+  if (a.st[0]) return;
+  const int nx = a.nx, ny = a.ny;
+  const size_t N = size_t(nx) * ny;
+  double sr = 0.0;
+  for (size_t v = size_t(sub) * 256 + threadIdx.x; v < N; v += size_t(blocks_per) * 256) {
+    const int j = int(v / nx), i = int(v % nx);
+    if (i <= 0 || i >= nx - 1 || j <= 0 || j >= ny - 1) continue;
+    const double r = a.b[v] - (offdiag(a.S, a.u, N, nx, v) + a.S[v] * a.u[v]);
+    sr += r * r;
+  }
+  const double tr = block_sum(sr);
+  if (threadIdx.x == 0) a.partials[sub] = tr;
+}
+
+// Starts each instance's solve state from its norms: sc[0..3] = ||b||^2, ||b||, ||r||^2, ||r||,
+// sc[6] = (rtol ||b||)^2; st = {stop, steps = 0, max}; summary[2k..2k+1] = ||b||, ||r||.
+__global__ __launch_bounds__(256) void k_init_multi(const NormArgs* __restrict__ list,
+                                                    int blocks_per,
+                                                    const double* __restrict__ partials,
+                                                    double* __restrict__ summary) {
+  const NormArgs& a = list[blockIdx.x];
+  double sb = 0.0, sr = 0.0;
+  for (int k = threadIdx.x; k < blocks_per; k += 256) {
+    sb += partials[2 * (size_t(blockIdx.x) * blocks_per + k)];
+    sr += partials[2 * (size_t(blockIdx.x) * blocks_per + k) + 1];
+  }
+  const double tb = block_sum(sb);
+  const double tr = block_sum(sr);
+  if (threadIdx.x == 0) {
+    const double bn = sqrt(tb), rn = sqrt(tr);
+    const double target = a.rtol * bn;
+    a.sc[0] = tb;
+    a.sc[1] = bn;
+    a.sc[2] = tr;
+    a.sc[3] = rn;
+    a.sc[6] = target * target;
+    a.st[0] = (bn == 0.0 || !(rn > target) || a.max_iters <= 0 || !isfinite(tr) || !isfinite(tb))
+                  ? 1 : 0;
+    a.st[1] = 0;
+    a.st[2] = a.max_iters;
+    summary[2 * blockIdx.x] = bn;
+    summary[2 * blockIdx.x + 1] = rn;
+  }
+}
+
+// Final relative residuals and step counts of every instance, gathered for one host copy.
+__global__ __launch_bounds__(256) void k_gather_multi(const CheckArgs* __restrict__ list, int count,
+                                                      double* __restrict__ rel,
+                                                      int* __restrict__ steps) {
+  for (int k = int(blockIdx.x) * 256 + threadIdx.x; k < count; k += int(gridDim.x) * 256) {
+    const CheckArgs& c = list[k];
+    const double rn = c.out[1], bn = c.sc[1];
+    rel[k] = bn > 0.0 ? rn / bn : rn;
+    steps[k] = c.st[1];
   }
 }
 
@@ -282,6 +383,34 @@ dmg_status launch_sq_partials(const double* x, size_t, int nx, int ny, double* p
 dmg_status launch_finalize(const double* partials, double* out, hipStream_t s, int count) {
   k_finalize<<<1, 256, 0, s>>>(partials, out, count);
   return launch_check("finalize");
+}
+
+dmg_status launch_check_multi(const CheckArgs* list, int count, hipStream_t s) {
+  if (count < 1) return DMG_OK;
+  k_check_multi<<<count, 256, 0, s>>>(list);
+  return launch_check("check_multi");
+}
+
+dmg_status launch_norms_multi(const NormArgs* list, int count, int blocks_per, double* partials,
+                              double* summary, hipStream_t s) {
+  if (count < 1) return DMG_OK;
+  k_norms_multi<<<count * blocks_per, 256, 0, s>>>(list, blocks_per, partials);
+  DMG_CHECK(launch_check("norms_multi"));
+  k_init_multi<<<count, 256, 0, s>>>(list, blocks_per, partials, summary);
+  return launch_check("init_multi");
+}
+
+dmg_status launch_resid_multi(const NormArgs* list, int count, int blocks_per, hipStream_t s) {
+  if (count < 1) return DMG_OK;
+  k_resid_multi<<<count * blocks_per, 256, 0, s>>>(list, blocks_per);
+  return launch_check("resid_multi");
+}
+
+dmg_status launch_gather_multi(const CheckArgs* list, int count, double* rel, int* steps,
+                               hipStream_t s) {
+  if (count < 1) return DMG_OK;
+  k_gather_multi<<<(count + 255) / 256, 256, 0, s>>>(list, count, rel, steps);
+  return launch_check("gather_multi");
 }
 
 dmg_status launch_check_step(const double* partials, int count, double* out, const double* sc,

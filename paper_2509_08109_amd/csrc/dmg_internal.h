@@ -161,6 +161,53 @@ dmg_status launch_sq_partials(const double* x, size_t n, int nx, int ny, double*
 dmg_status launch_finalize(const double* partials, double* out, hipStream_t s,
                            int count = kReduceBlocks);
 
+// Kernel arguments of one strip sweep (one instance, one level).
+template <class T>
+struct StripArgs {
+  const T* S;         // [ny][nx][5] point-major stencil (C, W, S, SW, SE of each point)
+  const T* uin;       // [ny][nx] iterate before the sweep (pre: nullptr = zero)
+  T* u;               // [ny][nx] iterate after the sweep (written)
+  const T* b;         // [ny][nx]
+  const T* P;         // [8][ncy][ncx] interpolation weights to the next coarser level
+  T* bH;              // pre: [ncy][ncx] restricted residual (coarse right-hand side)
+  const T* e;         // post: [ncy][ncx] coarse correction
+  double* partials;   // post: squared-residual partial per workgroup (nullptr: none)
+  int nx, ny;
+  int seg_h;          // rows per segment (even)
+  int nstrips, nsegs;
+  int pf;             // row parity smoothed first
+  int cA, cB;         // column parity smoothed first on A-rows / on B-rows
+  const int* stop;    // nullable: when *stop != 0 the kernel does nothing (converged solve)
+  double* x64;        // float post sweeps only (nullable): float64 iterate that receives the
+                      // sweep's output, x += u, at the points this workgroup writes
+};
+
+// Kernel arguments of the coarse tail (one instance).
+template <class T>
+struct TailLevel {
+  const T* S;  // [5][ny][nx] planar (unused at the coarsest level)
+  T* u;        // top level: iterate in/out; others unused
+  const T* b;  // top level: right-hand side; others unused
+  const T* P;  // [8][nyc][nxc] (unused at the coarsest level)
+  int nx, ny;
+};
+
+template <class T>
+struct TailArgs {
+  TailLevel<T> L[kMaxTail];
+  int oS[kMaxTail], ou[kMaxTail], ob[kMaxTail], oP[kMaxTail];  // LDS offsets, elements of T
+  int o_r;            // LDS offset of the residual scratch, elements of T
+  int o_y;            // LDS byte offset of the float64 coarsest-solve scratch
+  int nlev;           // levels in the tail (the last one is the coarsest)
+  int zero_top;       // the top level starts from u = 0 (it is a coarse level)
+  int m;              // coarsest unknowns
+  const int* idx;
+  const double* chol;
+  int pre[4], post[4];
+  int nu_pre, nu_post;
+  const int* stop;
+};
+
 // fused strip kernels (fused_kernels.hip)
 int strip_blocks(int nx, int ny, int bw, int seg_h, int* nstrips, int* nsegs);
 // Out-of-place: u_in (pre: nullptr = zero) -> u_out, u_in != u_out.  S is the point-major
@@ -205,6 +252,19 @@ TailLayout tail_layout(const int* nx, const int* ny, int nlev, int m, int elem);
 int device_lds_limit();  // LDS bytes one workgroup may use on the current device
 template <class T>
 dmg_status launch_tail(const TailSpec<T>& spec, hipStream_t s);
+// Fills the kernel arguments of one tail (and its LDS bytes) without launching.
+template <class T>
+dmg_status make_tail_args(const TailSpec<T>& spec, TailArgs<T>* out, size_t* lds_bytes);
+// Multi-instance launches over device arrays of arguments (see k_tail_multi, k_wave_multi):
+// the tails run one workgroup per instance with lds_bytes of LDS (the largest instance's);
+// the wave sweeps (mode 1 pre, 2 post with prolongation, 3 post) cover count x tiles_per
+// tiles, all instances of one level size and launch shape.
+template <class T>
+dmg_status launch_tail_multi(const TailArgs<T>* list, int count, size_t lds_bytes, int threads,
+                             hipStream_t s);
+template <class T>
+dmg_status launch_wave_multi(const StripArgs<T>* list, int count, int tiles_per, int mode, int pf,
+                             hipStream_t s);
 
 // iterative refinement helpers (stop: nullable device flag, see launch_check_step)
 // x += e over n points (used when no float strip sweep carries the update)
@@ -216,6 +276,34 @@ int ir_residual_blocks(int nx, int ny);
 dmg_status launch_ir_residual(const double* S, const double* x, const double* b, float* r32,
                               int nx, int ny, double* partials, hipStream_t s,
                               const int* stop = nullptr);
+// Per-instance arguments of the batched convergence check (k_check on each instance) and of the
+// batched start of a solve (norms of b and b - A u, solve state).
+struct CheckArgs {
+  const double* partials;  // squared-residual partials of the level-0 post sweep
+  int count;               // number of partials
+  double* out;             // [2] ||r||^2, ||r||
+  const double* sc;        // sc[1] = ||b||, sc[6] = target^2
+  int* st;                 // [3] stop, steps, max steps
+  double* hist;            // relative residual history
+  int hist_cap;
+};
+struct NormArgs {
+  const double* S;  // planar [5][ny][nx] level-0 stencil
+  const double* u;  // initial iterate (nullptr: zero)
+  const double* b;
+  int nx, ny;
+  double* sc;       // instance scalars (see k_init_multi)
+  int* st;          // [3] solve state
+  double rtol;
+  int max_iters;
+  double* partials; // k_resid_multi output (instances whose cycle is all coarse tail)
+};
+dmg_status launch_check_multi(const CheckArgs* list, int count, hipStream_t s);
+dmg_status launch_norms_multi(const NormArgs* list, int count, int blocks_per, double* partials,
+                              double* summary, hipStream_t s);
+dmg_status launch_gather_multi(const CheckArgs* list, int count, double* rel, int* steps,
+                               hipStream_t s);
+dmg_status launch_resid_multi(const NormArgs* list, int count, int blocks_per, hipStream_t s);
 // device-side convergence check of one solve step (see k_check)
 dmg_status launch_check_step(const double* partials, int count, double* out, const double* sc,
                              int* st, double* hist, int hist_cap, hipStream_t s);

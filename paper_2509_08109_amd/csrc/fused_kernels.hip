@@ -29,25 +29,6 @@ constexpr int HALO = 6;   // columns recomputed on each side of a strip
 constexpr int RU = 8;     // ring rows of u
 constexpr int RS = 4;     // ring rows of S, b, r
 
-template <class T>
-struct StripArgs {
-  const T* S;         // [ny][nx][5] point-major stencil (C, W, S, SW, SE of each point)
-  const T* uin;       // [ny][nx] iterate before the sweep (pre: nullptr = zero)
-  T* u;               // [ny][nx] iterate after the sweep (written)
-  const T* b;         // [ny][nx]
-  const T* P;         // [8][ncy][ncx] interpolation weights to the next coarser level
-  T* bH;              // pre: [ncy][ncx] restricted residual (coarse right-hand side)
-  const T* e;         // post: [ncy][ncx] coarse correction
-  double* partials;   // post: squared-residual partial per workgroup (nullptr: none)
-  int nx, ny;
-  int seg_h;          // rows per segment (even)
-  int nstrips, nsegs;
-  int pf;             // row parity smoothed first
-  int cA, cB;         // column parity smoothed first on A-rows / on B-rows
-  const int* stop;    // nullable: when *stop != 0 the kernel does nothing (converged solve)
-  double* x64;        // float post sweeps only (nullable): float64 iterate that receives the
-                      // sweep's output, x += u, at the points this workgroup writes
-};
 
 // Ring slots are taken relative to base = (first A-row) - 1: row j lives in u slot
 // (j - base) mod RU and in stencil/b/residual slot (j - base) mod RS.
@@ -119,7 +100,9 @@ struct RowRegs {
 // Branch-free loads: every lane issues the same loads (out-of-range lanes read a clamped,
 // valid address and discard the value), so the number of memory operations in flight is the
 // same on every path and the compiler can wait for exactly the rows it consumes.
-template <class T, bool READ_U>
+// UREAD: 0 the sweep starts from u = 0 (u is not read), 1 u is read from a.uin, 2 a.uin may be
+// null (then u = 0; the load goes to b, which is read anyway).
+template <class T, int UREAD>
 __device__ __forceinline__ void load_row(const StripArgs<T>& a, int i, int j, RowRegs<T>& g) {
   const bool ok = i >= 0 && i < a.nx && j >= 0 && j < a.ny;
   const size_t v = ok ? size_t(j) * a.nx + i : 0;
@@ -128,7 +111,13 @@ __device__ __forceinline__ void load_row(const StripArgs<T>& a, int i, int j, Ro
   for (int k = 0; k < 5; ++k) s[k] = a.S[5 * v + k];
   const T bb = a.b[v];
   T uu = T(0);
-  if (READ_U) uu = a.uin[v];
+  if constexpr (UREAD == 1) {
+    uu = a.uin[v];
+  } else if constexpr (UREAD == 2) {
+    const T* src = a.uin ? a.uin : a.b;
+    const T tu = src[v];
+    uu = a.uin ? tu : T(0);
+  }
 #pragma unroll
   for (int k = 0; k < 5; ++k) g.s[k] = ok ? s[k] : T(0);
   g.b = ok ? bb : T(0);
@@ -253,7 +242,7 @@ constexpr int strip_lds_elems(bool post) {
 template <class T, int BW, int MODE>
 __global__ __launch_bounds__(BW) void k_strip(StripArgs<T> a) {
   constexpr bool POST = MODE >= 2;
-  constexpr bool READ_U = MODE != 0;
+  constexpr int UREAD = MODE != 0 ? 1 : 0;
   constexpr bool prol = MODE == 2;
   if (a.stop && *a.stop) return;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -314,7 +303,7 @@ __global__ __launch_bounds__(BW) void k_strip(StripArgs<T> a) {
   RowRegs<T> gA0, gA1, gB0, gB1;
   CoarseRegs<T> cr;
   if (active) {
-    load_row<T, READ_U>(a, i, a0 - 1, gA0);
+    load_row<T, UREAD>(a, i, a0 - 1, gA0);
     if (prol && row_ok(a0 - 1)) gA0.u = gA0.u + prolong_global<T>(a, i, a0 - 1);
     store_row<T, BW, 0>(c, L, t, gA0);
     if (prol) {
@@ -324,10 +313,10 @@ __global__ __launch_bounds__(BW) void k_strip(StripArgs<T> a) {
         for (int k = 0; k < kCoarseSlots; ++k) cbuf[k * CW + t] = cr.v[k];
       }
     }
-    load_row<T, READ_U>(a, i, a0, gA0);
-    load_row<T, READ_U>(a, i, a0 + 1, gA1);
-    load_row<T, READ_U>(a, i, live(a0 + 2), gB0);
-    load_row<T, READ_U>(a, i, live(a0 + 3), gB1);
+    load_row<T, UREAD>(a, i, a0, gA0);
+    load_row<T, UREAD>(a, i, a0 + 1, gA1);
+    load_row<T, UREAD>(a, i, live(a0 + 2), gB0);
+    load_row<T, UREAD>(a, i, live(a0 + 3), gB1);
   }
   __syncthreads();
   double acc = 0.0;
@@ -368,8 +357,8 @@ __global__ __launch_bounds__(BW) void k_strip(StripArgs<T> a) {
       pw[6] = P[2 * NC + cc];
       pw[7] = P[4 * NC + cc];
     }
-    load_row<T, READ_U>(a, i, live(ar + 4), g0);
-    load_row<T, READ_U>(a, i, live(ar + 5), g1);
+    load_row<T, UREAD>(a, i, live(ar + 4), g0);
+    load_row<T, UREAD>(a, i, live(ar + 5), g1);
     // A-row ar: column parity cA first, then the other; then B-row ar-1
     const bool okA = row_ok(ar), okB = row_ok(ar - 1);
     const bool firstA = (i & 1) == a.cA, firstB = (i & 1) == a.cB;
@@ -450,30 +439,6 @@ __global__ __launch_bounds__(BW) void k_strip(StripArgs<T> a) {
 // right-hand side (and iterate) once per cycle, separates the colour passes with workgroup
 // barriers, and writes back only the top level's iterate, which is all the levels above read.
 // -----------------------------------------------------------------------------------------
-template <class T>
-struct TailLevel {
-  const T* S;  // [5][ny][nx] planar (unused at the coarsest level)
-  T* u;        // top level: iterate in/out; others unused
-  const T* b;  // top level: right-hand side; others unused
-  const T* P;  // [8][nyc][nxc] (unused at the coarsest level)
-  int nx, ny;
-};
-
-template <class T>
-struct TailArgs {
-  TailLevel<T> L[kMaxTail];
-  int oS[kMaxTail], ou[kMaxTail], ob[kMaxTail], oP[kMaxTail];  // LDS offsets, elements of T
-  int o_r;            // LDS offset of the residual scratch, elements of T
-  int o_y;            // LDS byte offset of the float64 coarsest-solve scratch
-  int nlev;           // levels in the tail (the last one is the coarsest)
-  int zero_top;       // the top level starts from u = 0 (it is a coarse level)
-  int m;              // coarsest unknowns
-  const int* idx;
-  const double* chol;
-  int pre[4], post[4];
-  int nu_pre, nu_post;
-  const int* stop;
-};
 
 template <class T>
 __device__ __forceinline__ T offdiag_s(const T* S, const T* u, int N, int nx, int v) {
@@ -503,7 +468,7 @@ __device__ void tail_colour(const T* S, T* u, const T* b, int nx, int ny, int c)
 }
 
 template <class T>
-__global__ __launch_bounds__(1024) void k_tail(TailArgs<T> a) {
+__device__ __forceinline__ void tail_body(const TailArgs<T>& a) {
   if (a.stop && *a.stop) return;
   extern __shared__ __align__(16) unsigned char smem[];
   T* sm = reinterpret_cast<T*>(smem);
@@ -632,6 +597,17 @@ __global__ __launch_bounds__(1024) void k_tail(TailArgs<T> a) {
   }
 }
 
+template <class T>
+__global__ __launch_bounds__(1024) void k_tail(TailArgs<T> a) {
+  tail_body<T>(a);
+}
+
+// One workgroup per instance: list[blockIdx.x] holds that instance's tail.
+template <class T>
+__global__ __launch_bounds__(1024) void k_tail_multi(const TailArgs<T>* __restrict__ list) {
+  tail_body<T>(list[blockIdx.x]);
+}
+
 }  // namespace
 
 // -----------------------------------------------------------------------------------------
@@ -752,20 +728,13 @@ __device__ __forceinline__ T prolong_wave(const CoarseRegs<T>& cv, int i, int j)
 }
 
 // MODE as k_strip; PF = row parity smoothed first.
-template <class T, int MODE, int PF>
-__global__ __launch_bounds__(64) void k_wave(StripArgs<T> a) {
+// One tile of a wave-strip sweep; the squared-residual partial (post, when a.partials is set)
+// goes to a.partials[pidx].
+template <class T, int MODE, int PF, int UREAD>
+__device__ __forceinline__ void wave_tile(const StripArgs<T>& a, int tile, int pidx) {
   constexpr bool POST = MODE >= 2;
-  constexpr bool READ_U = MODE != 0;
   constexpr bool prol = MODE == 2;
   constexpr int BW = 64;
-  if (a.stop && *a.stop) return;
-  const int ntiles = a.nstrips * a.nsegs;
-  const int per = (int(gridDim.x) + 7) >> 3;
-  const int tile = (int(blockIdx.x) & 7) * per + (int(blockIdx.x) >> 3);
-  if (tile >= ntiles) {
-    if (POST && a.partials && threadIdx.x == 0) a.partials[blockIdx.x] = 0.0;
-    return;
-  }
   const int seg = tile / a.nstrips;
   const int strip = tile % a.nstrips;
   const int t = threadIdx.x;
@@ -803,14 +772,14 @@ __global__ __launch_bounds__(64) void k_wave(StripArgs<T> a) {
         c.NWl[k] = c.r[k] = T(0);
   RowRegs<T> gA0, gA1, gB0, gB1;
   CoarseRegs<T> cr;
-  load_row<T, READ_U>(a, i, a0 - 1, gA0);
+  load_row<T, UREAD>(a, i, a0 - 1, gA0);
   if (prol && row_ok(a0 - 1)) gA0.u = gA0.u + prolong_global<T>(a, i, a0 - 1);
   store_row_w<T, 0>(c, gA0);
   if (prol) load_coarse<T>(a, cI, a0, cr);
-  load_row<T, READ_U>(a, i, a0, gA0);
-  load_row<T, READ_U>(a, i, a0 + 1, gA1);
-  load_row<T, READ_U>(a, i, live(a0 + 2), gB0);
-  load_row<T, READ_U>(a, i, live(a0 + 3), gB1);
+  load_row<T, UREAD>(a, i, a0, gA0);
+  load_row<T, UREAD>(a, i, a0 + 1, gA1);
+  load_row<T, UREAD>(a, i, live(a0 + 2), gB0);
+  load_row<T, UREAD>(a, i, live(a0 + 3), gB1);
   double acc = 0.0;
 
   auto step = [&](auto KC, int ar, RowRegs<T>& g0, RowRegs<T>& g1) {
@@ -845,8 +814,8 @@ __global__ __launch_bounds__(64) void k_wave(StripArgs<T> a) {
       pw[7] = P[4 * NC + cc];
     }
     if (prol) load_coarse<T>(a, cI, ar + 2, cr);
-    load_row<T, READ_U>(a, i, live(ar + 4), g0);
-    load_row<T, READ_U>(a, i, live(ar + 5), g1);
+    load_row<T, UREAD>(a, i, live(ar + 4), g0);
+    load_row<T, UREAD>(a, i, live(ar + 5), g1);
     const bool okA = row_ok(ar), okB = row_ok(ar - 1);
     const bool firstA = (i & 1) == a.cA, firstB = (i & 1) == a.cB;
     gs_wave<T, JA>(c, okA && firstA);
@@ -903,8 +872,38 @@ __global__ __launch_bounds__(64) void k_wave(StripArgs<T> a) {
   if (POST && a.partials) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-    if (t == 0) a.partials[blockIdx.x] = acc;
+    if (t == 0) a.partials[pidx] = acc;
   }
+}
+
+// MODE as k_strip; PF = row parity smoothed first.
+template <class T, int MODE, int PF>
+__global__ __launch_bounds__(64) void k_wave(StripArgs<T> a) {
+  if (a.stop && *a.stop) return;
+  const int ntiles = a.nstrips * a.nsegs;
+  const int per = (int(gridDim.x) + 7) >> 3;
+  const int tile = (int(blockIdx.x) & 7) * per + (int(blockIdx.x) >> 3);
+  if (tile >= ntiles) {
+    if (MODE >= 2 && a.partials && threadIdx.x == 0) a.partials[blockIdx.x] = 0.0;
+    return;
+  }
+  wave_tile<T, MODE, PF, MODE != 0 ? 1 : 0>(a, tile, int(blockIdx.x));
+}
+
+// The same sweep over the tiles of several instances of one level size at once: list[k] is
+// instance k's arguments (all with the same nx, ny, seg_h), tiles_per its tile count.  Pre
+// sweeps (MODE 1) read u where list[k].uin is set and start from zero elsewhere; partials go to
+// list[k].partials[tile].
+template <class T, int MODE, int PF>
+__global__ __launch_bounds__(64) void k_wave_multi(const StripArgs<T>* __restrict__ list,
+                                                   int tiles_per, int total) {
+  const int per = (int(gridDim.x) + 7) >> 3;
+  const int g = (int(blockIdx.x) & 7) * per + (int(blockIdx.x) >> 3);
+  if (g >= total) return;
+  const int inst = g / tiles_per, tile = g - inst * tiles_per;
+  const StripArgs<T> a = list[inst];
+  if (a.stop && *a.stop) return;
+  wave_tile<T, MODE, PF, MODE == 1 ? 2 : (MODE == 0 ? 0 : 1)>(a, tile, tile);
 }
 
 // ---- float64 residual of the refinement loop ----------------------------------------------
@@ -1147,14 +1146,12 @@ int device_lds_limit() {
 }
 
 template <class T>
-dmg_status launch_tail(const TailSpec<T>& spec, hipStream_t s) {
-  TailArgs<T> a;
+dmg_status make_tail_args(const TailSpec<T>& spec, TailArgs<T>* out, size_t* lds_bytes) {
+  TailArgs<T>& a = *out;
   if (spec.nlev > kMaxTail) return fail(DMG_ERR_INVALID_ARG, "tail too deep (%d)", spec.nlev);
   const TailLayout lay = tail_layout(spec.nx, spec.ny, spec.nlev, spec.m, int(sizeof(T)));
   if (lay.bytes > size_t(device_lds_limit()))
     return fail(DMG_ERR_INVALID_ARG, "coarse tail needs %zu bytes of LDS", lay.bytes);
-  if (spec.threads < 64 || spec.threads > 1024 || spec.threads % 64)
-    return fail(DMG_ERR_INVALID_ARG, "coarse tail workgroup size %d", spec.threads);
   for (int l = 0; l < spec.nlev; ++l) {
     a.L[l].S = spec.S[l];
     a.L[l].u = spec.u[l];
@@ -1181,8 +1178,49 @@ dmg_status launch_tail(const TailSpec<T>& spec, hipStream_t s) {
   a.nu_pre = spec.nu_pre;
   a.nu_post = spec.nu_post;
   a.stop = spec.stop;
-  k_tail<T><<<1, spec.threads, lay.bytes, s>>>(a);
+  *lds_bytes = lay.bytes;
+  return DMG_OK;
+}
+
+template <class T>
+dmg_status launch_tail(const TailSpec<T>& spec, hipStream_t s) {
+  if (spec.threads < 64 || spec.threads > 1024 || spec.threads % 64)
+    return fail(DMG_ERR_INVALID_ARG, "coarse tail workgroup size %d", spec.threads);
+  TailArgs<T> a;
+  size_t bytes = 0;
+  DMG_CHECK(make_tail_args<T>(spec, &a, &bytes));
+  k_tail<T><<<1, spec.threads, bytes, s>>>(a);
   return launch_check("tail");
+}
+
+template <class T>
+dmg_status launch_tail_multi(const TailArgs<T>* list, int count, size_t lds_bytes, int threads,
+                             hipStream_t s) {
+  if (threads < 64 || threads > 1024 || threads % 64)
+    return fail(DMG_ERR_INVALID_ARG, "coarse tail workgroup size %d", threads);
+  if (count < 1) return DMG_OK;
+  k_tail_multi<T><<<count, threads, lds_bytes, s>>>(list);
+  return launch_check("tail_multi");
+}
+
+template <class T>
+dmg_status launch_wave_multi(const StripArgs<T>* list, int count, int tiles_per, int mode, int pf,
+                             hipStream_t s) {
+  if (count < 1 || tiles_per < 1) return DMG_OK;
+  const long total = long(count) * tiles_per;
+  if (total > (1l << 30)) return fail(DMG_ERR_INVALID_ARG, "too many tiles in one launch");
+  const int nb = int((total + 7) & ~7l);
+#define DMG_WAVE_M(M)                                                                          \
+  (pf ? (void)(k_wave_multi<T, M, 1><<<nb, 64, 0, s>>>(list, tiles_per, int(total)))           \
+      : (void)(k_wave_multi<T, M, 0><<<nb, 64, 0, s>>>(list, tiles_per, int(total))))
+  switch (mode) {
+    case 1: DMG_WAVE_M(1); break;
+    case 2: DMG_WAVE_M(2); break;
+    case 3: DMG_WAVE_M(3); break;
+    default: return fail(DMG_ERR_INVALID_ARG, "multi-instance sweep mode %d", mode);
+  }
+#undef DMG_WAVE_M
+  return launch_check("wave_multi");
 }
 
 #define DMG_INST(T)                                                                            \
@@ -1192,7 +1230,10 @@ dmg_status launch_tail(const TailSpec<T>& spec, hipStream_t s) {
   template dmg_status launch_post<T>(const StripConfig&, const T*, const T*, T*, const T*,     \
                                      const T*, const T*, double*, int, int, int, int, int,     \
                                      const int*, hipStream_t, double*);                        \
-  template dmg_status launch_tail<T>(const TailSpec<T>&, hipStream_t);
+  template dmg_status launch_tail<T>(const TailSpec<T>&, hipStream_t);                        \
+  template dmg_status make_tail_args<T>(const TailSpec<T>&, TailArgs<T>*, size_t*);           \
+  template dmg_status launch_tail_multi<T>(const TailArgs<T>*, int, size_t, int, hipStream_t); \
+  template dmg_status launch_wave_multi<T>(const StripArgs<T>*, int, int, int, int, hipStream_t);
 DMG_INST(double)
 DMG_INST(float)
 #undef DMG_INST

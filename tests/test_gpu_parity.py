@@ -340,18 +340,50 @@ def test_transfer_matches_oracle(dmg):
     T.close()
 
 
-def test_batch_matches_single_solves(dmg):
-    probs = [pb.star(n, seed=10 + k) for k, n in enumerate((33, 65, 129, 65))]
-    Ss = [dmg.assemble_stencil(dev(p.jac), dev(p.K)) for p in probs]
-    bs = [dev(p.b) for p in probs]
-    bt = dmg.BatchSolver(Ss)
-    us, its, rels = bt.solve(bs, rtol=1e-10)
+def _batch_vs_single(dmg, Ss, bs, bt, us, its, rels):
     for S, b, u, k, r in zip(Ss, bs, us, its, rels):
         h = dmg.Hierarchy(S)
         u1, k1, r1, _ = h.solve(b, rtol=1e-10)
         assert k == k1 and r <= 1e-10
+        assert abs(r - r1) <= 1e-13 * max(r1, 1e-300) * 10
         assert torch.equal(u, u1)
         h.close()
+
+
+def test_batch_matches_single_solves(dmg):
+    """Uneven sizes (one all-tail instance), different convergence counts: every instance's
+    iterate equals its single solve bitwise."""
+    probs = [pb.star(n, seed=10 + k) for k, n in enumerate((33, 65, 129, 65, 257, 129))]
+    probs.append(pb.quarter_annulus(65))          # needs many more cycles than the stars
+    Ss = [dmg.assemble_stencil(dev(p.jac), dev(p.K)) for p in probs]
+    bs = [dev(p.b) for p in probs]
+    bt = dmg.BatchSolver(Ss)
+    us, its, rels = bt.solve(bs, rtol=1e-10)
+    assert len(set(its)) > 1
+    _batch_vs_single(dmg, Ss, bs, bt, us, its, rels)
+    # a second solve on new arrays rebuilds the schedule; autotuned shapes change no bit
+    bt.autotune(bs, reps=1)
+    us2, its2, rels2 = bt.solve(bs, rtol=1e-10)
+    assert its2 == its and all(torch.equal(a, c) for a, c in zip(us, us2))
+    bt.close()
+
+
+def test_batch_zero_rhs_and_limits(dmg):
+    probs = [pb.star(n, seed=20 + k) for k, n in enumerate((129, 65, 257))]
+    Ss = [dmg.assemble_stencil(dev(p.jac), dev(p.K)) for p in probs]
+    bs = [dev(p.b) for p in probs]
+    bs[1] = torch.zeros_like(bs[1])
+    bt = dmg.BatchSolver(Ss)
+    us0 = [torch.ones_like(b) for b in bs]
+    us, its, rels = bt.solve(bs, us=us0, rtol=1e-10)
+    assert its[1] == 0 and rels[1] == 0.0 and float(us[1].abs().max()) == 0.0
+    assert its[0] > 0 and its[2] > 0 and max(rels) <= 1e-10
+    # a step budget too small for the tolerance: no convergence reported, counts capped
+    with pytest.raises(dmg.DmgError) as ei:
+        bt.solve(bs, rtol=1e-10, max_iters=3)
+    assert ei.value.code == 6
+    _, its3, _ = bt.solve(bs, rtol=1e-10, max_iters=3, raise_on_fail=False)
+    assert its3[0] == 3 and its3[2] == 3 and its3[1] == 0
     bt.close()
 
 

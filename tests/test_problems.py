@@ -126,3 +126,18 @@ def test_batch_sizes_are_seeded():
     s1 = pb.batch_sizes(256)
     assert s1 == pb.batch_sizes(256)
     assert set(s1) <= {129, 257, 513, 1025} and len(set(s1)) == 4
+
+
+def test_device_batch_reproduces_host_batch():
+    """The device path of the star batch draws the same instances as problems.batch."""
+    import torch
+
+    from problems.batch_device import star_batch_device
+
+    host = pb.batch(3, choices=(17, 33), seed=5)
+    dev = list(star_batch_device(3, choices=(17, 33), seed=5, device="cpu"))
+    for p, (n, jac, K, b) in zip(host, dev):
+        assert n == p.nx
+        assert np.allclose(jac.numpy(), p.jac, rtol=1e-13, atol=1e-14)
+        assert np.allclose(K.numpy(), p.K, rtol=1e-12)
+        assert np.array_equal(b.numpy(), p.b)
