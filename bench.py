@@ -12,11 +12,12 @@ hierarchy setup (operator-induced interpolation, Galerkin levels, coarsest facto
 solve.  value = interior DoF x steps / wall time.
 
 Extra legs (same JSON line): the float32-refined solve at the same size, the 4097 x 4097 size
-in float64 and float32-refined form, the batch of 256 uneven instances, the roofline of the
+in float64 and float32-refined form, the batch of 256 uneven instances, the differentiable solve
+on 2049 x 2049 with its finite-difference check, the roofline of the
 dominant kernel (timed with HIP events on the library's stream), and the float64 CPU oracle
 timed on the host (cpu_baseline).
 
-    python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--n 1025] [--no-c3] [--no-c4] [--no-cpu]
+    python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--n 1025] [--no-c3] [--no-c4] [--no-c5] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -203,6 +204,75 @@ def run_batch_leg(dmg, dev, steps: int, count: int = 256):
             "generate_and_assemble_s": round(t_gen, 2), "setup_s": round(t_setup, 2)}
 
 
+def run_diff_leg(dmg, dev, steps: int, n: int = 2049, n_dirs: int = 64):
+    """Differentiable solve on the n x n star (root seed 4): J(u) = 1/2 ||u - u_t||^2 over the
+    interior, forward (assemble + setup + solve) and backward (hierarchy recomputed, adjoint
+    solve, dJ/dK per cell, dJ/db) timed; then central differences along n_dirs seeded random
+    directions (dK = K z, db = z with z ~ N(0,1), eps = 1e-4, solves to 1e-13) against the
+    adjoint's directional derivatives."""
+    import torch
+
+    prob, jac, K0, b0 = make_inputs(n, 4, dev)
+    t = torch.as_tensor(prob.target, dtype=torch.float64, device=dev)
+    del prob
+
+    def J_of(Kv, bv, rtol):
+        u = dmg.DiffSolve.apply(Kv, bv, jac, rtol)
+        d = (u - t)[1:-1, 1:-1]
+        return 0.5 * (d * d).sum()
+
+    K = K0.clone().requires_grad_(True)
+    b = b0.clone().requires_grad_(True)
+    for _ in range(1):                                   # warm-up
+        J_of(K, b, 1e-10).backward()
+    K.grad = None
+    b.grad = None
+    fwd = bwd = 0.0
+    for _ in range(steps):
+        K.grad = None
+        b.grad = None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J = J_of(K, b, 1e-10)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        J.backward()
+        torch.cuda.synchronize()
+        fwd += t1 - t0
+        bwd += time.perf_counter() - t1
+    # finite differences against the adjoint gradient of a tight solve
+    K.grad = None
+    b.grad = None
+    J_of(K, b, 1e-13).backward()
+    gK, gb = K.grad.detach(), b.grad.detach()
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(4)
+    eps = 1e-4
+    fd, ad = [], []
+    with torch.no_grad():
+        for _ in range(n_dirs):
+            zK = torch.randn(K0.shape, generator=gen, device=dev, dtype=torch.float64) * K0
+            zb = torch.randn(b0.shape, generator=gen, device=dev, dtype=torch.float64)
+            zb[0, :] = 0.0
+            zb[-1, :] = 0.0
+            zb[:, 0] = 0.0
+            zb[:, -1] = 0.0
+            fK = (J_of(K0 + eps * zK, b0, 1e-13) - J_of(K0 - eps * zK, b0, 1e-13)) / (2 * eps)
+            fb = (J_of(K0, b0 + eps * zb, 1e-13) - J_of(K0, b0 - eps * zb, 1e-13)) / (2 * eps)
+            fd.append(torch.stack([fK, fb]))
+            ad.append(torch.stack([(gK * zK).sum(), (gb * zb).sum()]))
+    fd = torch.stack(fd)
+    ad = torch.stack(ad)
+    err = (torch.linalg.norm(fd - ad, dim=0) / torch.linalg.norm(ad, dim=0)).tolist()
+    dof = (n - 2) ** 2
+    del jac, K0, b0, K, b, gK, gb, t
+    torch.cuda.empty_cache()
+    return {"value": round(dof * steps / (fwd + bwd), 1), "unit": "DoF/s (forward + backward)",
+            "grid": [n, n], "dof": dof, "forward_ms": round(1e3 * fwd / steps, 2),
+            "backward_ms": round(1e3 * bwd / steps, 2), "steps": steps,
+            "fd_directions": n_dirs, "fd_relerr_dK": err[0], "fd_relerr_db": err[1]}
+
+
 CPU_SNIPPET = r"""
 import json, sys, time
 sys.path.insert(0, {root!r})
@@ -252,6 +322,7 @@ def main():
     ap.add_argument("--no-c3", action="store_true", help="skip the 4097 x 4097 legs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-c4", action="store_true", help="skip the 256-instance batch leg")
+    ap.add_argument("--no-c5", action="store_true", help="skip the 2049 x 2049 gradient leg")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -339,6 +410,9 @@ def main():
     if not args.no_c4:
         log("batch leg: 256 star instances")
         res["c4_batch"] = run_batch_leg(dmg, dev, max(1, args.steps // 2))
+    if not args.no_c5:
+        log("gradient leg: 2049x2049 star")
+        res["c5_gradient"] = run_diff_leg(dmg, dev, max(1, args.steps // 2))
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         res["cpu_baseline"] = cpu_baseline(args.n, args.seed)
