@@ -13,11 +13,11 @@ solve.  value = interior DoF x steps / wall time.
 
 Extra legs (same JSON line): the float32-refined solve at the same size, the 4097 x 4097 size
 in float64 and float32-refined form, the batch of 256 uneven instances, the differentiable solve
-on 2049 x 2049 with its finite-difference check, the roofline of the
+on 2049 x 2049 with its finite-difference check, the grid <-> mesh transfers, the roofline of the
 dominant kernel (timed with HIP events on the library's stream), and the float64 CPU oracle
 timed on the host (cpu_baseline).
 
-    python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--n 1025] [--no-c3] [--no-c4] [--no-c5] [--no-cpu]
+    python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--n 1025] [--no-c3] [--no-c4] [--no-c5] [--no-transfer] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -273,6 +273,57 @@ def run_diff_leg(dmg, dev, steps: int, n: int = 2049, n_dirs: int = 64):
             "fd_directions": n_dirs, "fd_relerr_dK": err[0], "fd_relerr_db": err[1]}
 
 
+def run_transfer_leg(dmg, dev, n: int = 1025, seed: int = 1, reps: int = 20):
+    """Grid <-> mesh transfers on the n x n grid of the star (root seed `seed`): a jittered P1
+    lattice with about n^2 / 0.28 vertices mapped through the same star map; C and M_p are
+    assembled on the host at creation; from_grid = CG2(M_p, C u_c) and to_grid = C^T CG2(M_p, r_p)
+    are timed with HIP events (mean of `reps` back-to-back applies)."""
+    import numpy as np
+    import torch
+
+    import problems as pb
+    mp = pb.Star.random(pb.streams(seed)[0])
+    m = pb.mesh_points_for_grid(n)
+    t0 = time.perf_counter()
+    mesh = pb.lattice_mesh(mp, m, np.random.default_rng(seed))
+    t_mesh = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    T = dmg.Transfer(mesh.xy_c, mesh.xy_p, mesh.tris, mesh.dof, n, n, nq=4, device=dev)
+    torch.cuda.synchronize()
+    t_create = time.perf_counter() - t0
+    nnzC, nnzM = T.nnz()
+    uc = torch.zeros((n, n), dtype=torch.float64, device=dev)
+    uc[1:-1, 1:-1] = 1.0
+    rp = torch.ones(mesh.nv, dtype=torch.float64, device=dev)
+    up = torch.empty(mesh.nv, dtype=torch.float64, device=dev)
+    rc = torch.empty((n, n), dtype=torch.float64, device=dev)
+    out = {}
+    for name, fn in (("from_grid", lambda: T.from_grid(uc, out=up)), ("to_grid", lambda: T.to_grid(rp, out=rc))):
+        for _ in range(3):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        torch.cuda._sleep(20_000_000)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name + "_us"] = round(1e3 * e0.elapsed_time(e1) / reps, 1)
+    # algorithmic bytes of one apply: C (or C^T) once and M_p twice at 12 B per nonzero (value +
+    # column index) plus 4 B row pointers, the CG2 vectors (r0 written; r0, q0 for q0 = M r0;
+    # r1 from r0, q0; r0, r1 for p1; r0, r1 and the result for x2: 11 passes of nv float64 plus
+    # the int32 permutation) and the grid vector (read or written once)
+    bytes_apply = (12.0 * (nnzC + 2 * nnzM) + 4.0 * 3 * mesh.nv + 8.0 * 11 * mesh.nv + 4.0 * mesh.nv
+                   + 8.0 * n * n)
+    T.close()
+    return {"grid": [n, n], "mesh_vertices": int(mesh.nv), "mesh_triangles": int(mesh.tris.shape[0]),
+            "nnz_C": nnzC, "nnz_M": nnzM, "mesh_s": round(t_mesh, 2), "create_s": round(t_create, 2),
+            **out, "apply_bytes": bytes_apply,
+            "from_grid_gbs": round(bytes_apply / (out["from_grid_us"] * 1e-6) / 1e9, 1),
+            "to_grid_gbs": round(bytes_apply / (out["to_grid_us"] * 1e-6) / 1e9, 1)}
+
+
 CPU_SNIPPET = r"""
 import json, sys, time
 sys.path.insert(0, {root!r})
@@ -323,6 +374,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-c4", action="store_true", help="skip the 256-instance batch leg")
     ap.add_argument("--no-c5", action="store_true", help="skip the 2049 x 2049 gradient leg")
+    ap.add_argument("--no-transfer", action="store_true", help="skip the grid <-> mesh transfer leg")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -413,6 +465,9 @@ def main():
     if not args.no_c5:
         log("gradient leg: 2049x2049 star")
         res["c5_gradient"] = run_diff_leg(dmg, dev, max(1, args.steps // 2))
+    if not args.no_transfer:
+        log("transfer leg: 1025x1025 grid, ~3.8M-vertex mesh")
+        res["transfer"] = run_transfer_leg(dmg, dev)
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         res["cpu_baseline"] = cpu_baseline(args.n, args.seed)

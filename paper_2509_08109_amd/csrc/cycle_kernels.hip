@@ -1,14 +1,9 @@
-// Cycle-phase kernels: four-colour Gauss-Seidel colour sweep, residual, restriction P^T r,
-// interpolation-correction u += P e, deterministic norms, and the float32-in-float64
-// iterative-refinement helpers.  Templated on the working precision T (double or float).
+// Small cycle-side kernels: deterministic norms and the device convergence check (single and
+// multi-instance), fills and copies.  The sweeps themselves live in fused_kernels.hip.
 #include "dmg_internal.h"
 
 namespace dmg {
 namespace {
-
-constexpr int kBX = 64, kBY = 4;
-
-dim3 grid2(int nx, int ny) { return dim3((nx + kBX - 1) / kBX, (ny + kBY - 1) / kBY); }
 
 // Off-diagonal part of row (i,j) applied to u, summed in ascending neighbour index order.
 template <class T>
@@ -25,88 +20,6 @@ __device__ __forceinline__ T offdiag(const T* __restrict__ S, const T* __restric
   return ((((((sw + s) + se) + w) + e) + nw) + n) + ne;
 }
 
-template <class T>
-__global__ __launch_bounds__(256) void k_smooth(const T* __restrict__ S, T* __restrict__ u,
-                                                const T* __restrict__ b, int nx, int ny, int ci,
-                                                int cj) {
-  const int i = ci + 2 * int(blockIdx.x * kBX + threadIdx.x);
-  const int j = cj + 2 * int(blockIdx.y * kBY + threadIdx.y);
-  if (i <= 0 || i >= nx - 1 || j <= 0 || j >= ny - 1) return;
-  const size_t N = size_t(nx) * ny;
-  const size_t v = size_t(j) * nx + i;
-  u[v] = (b[v] - offdiag(S, u, N, nx, v)) / S[v];
-}
-
-template <class T>
-__global__ __launch_bounds__(256) void k_residual(const T* __restrict__ S, const T* __restrict__ u,
-                                                  const T* __restrict__ b, T* __restrict__ r,
-                                                  int nx, int ny) {
-  const int i = blockIdx.x * kBX + threadIdx.x;
-  const int j = blockIdx.y * kBY + threadIdx.y;
-  if (i >= nx || j >= ny) return;
-  const size_t N = size_t(nx) * ny;
-  const size_t v = size_t(j) * nx + i;
-  if (i == 0 || i == nx - 1 || j == 0 || j == ny - 1) {
-    r[v] = T(0);
-    return;
-  }
-  r[v] = b[v] - (offdiag(S, u, N, nx, v) + S[v] * u[v]);
-}
-
-// b_H(I,J) = sum over the fine 3x3 block around (2I,2J) of P[f,(I,J)] r_f.
-template <class T>
-__global__ __launch_bounds__(256) void k_restrict(const T* __restrict__ P, const T* __restrict__ r,
-                                                  T* __restrict__ bH, int nx, int ny) {
-  const int ncx = (nx + 1) / 2, ncy = (ny + 1) / 2;
-  const int I = blockIdx.x * kBX + threadIdx.x;
-  const int J = blockIdx.y * kBY + threadIdx.y;
-  if (I >= ncx || J >= ncy) return;
-  const size_t c = size_t(J) * ncx + I;
-  if (I == 0 || I == ncx - 1 || J == 0 || J == ncy - 1) {
-    bH[c] = T(0);
-    return;
-  }
-  const size_t NC = size_t(ncx) * ncy;
-  const size_t f = size_t(2 * J) * nx + 2 * I;
-  // rows j-1, j, j+1 in ascending fine index order
-  T acc = P[7 * NC + c - ncx - 1] * r[f - nx - 1];      // centre (2I-1,2J-1) -> NE weight
-  acc += P[3 * NC + c - ncx] * r[f - nx];                // y-line (2I,2J-1)   -> N weight
-  acc += P[6 * NC + c - ncx] * r[f - nx + 1];            // centre (2I+1,2J-1) -> NW weight
-  acc += P[1 * NC + c - 1] * r[f - 1];                   // x-line (2I-1,2J)   -> E weight
-  acc += r[f];                                           // coarse point: injection
-  acc += P[0 * NC + c] * r[f + 1];                       // x-line (2I+1,2J)   -> W weight
-  acc += P[5 * NC + c - 1] * r[f + nx - 1];              // centre (2I-1,2J+1) -> SE weight
-  acc += P[2 * NC + c] * r[f + nx];                      // y-line (2I,2J+1)   -> S weight
-  acc += P[4 * NC + c] * r[f + nx + 1];                  // centre (2I+1,2J+1) -> SW weight
-  bH[c] = acc;
-}
-
-// u_f += (P e)_f on interior fine points.
-template <class T>
-__global__ __launch_bounds__(256) void k_prolong_add(const T* __restrict__ P,
-                                                     const T* __restrict__ e, T* __restrict__ u,
-                                                     int nx, int ny) {
-  const int i = blockIdx.x * kBX + threadIdx.x;
-  const int j = blockIdx.y * kBY + threadIdx.y;
-  if (i <= 0 || i >= nx - 1 || j <= 0 || j >= ny - 1) return;
-  const int ncx = (nx + 1) / 2, ncy = (ny + 1) / 2;
-  const size_t NC = size_t(ncx) * ncy;
-  const int I = i >> 1, J = j >> 1;
-  const size_t c = size_t(J) * ncx + I;
-  T corr;
-  if (!(i & 1) && !(j & 1)) {
-    corr = e[c];
-  } else if ((i & 1) && !(j & 1)) {
-    corr = P[c] * e[c] + P[NC + c] * e[c + 1];
-  } else if (!(i & 1) && (j & 1)) {
-    corr = P[2 * NC + c] * e[c] + P[3 * NC + c] * e[c + ncx];
-  } else {
-    corr = ((P[4 * NC + c] * e[c] + P[5 * NC + c] * e[c + 1]) + P[6 * NC + c] * e[c + ncx]) +
-           P[7 * NC + c] * e[c + ncx + 1];
-  }
-  const size_t v = size_t(j) * nx + i;
-  u[v] = u[v] + corr;
-}
 
 template <class T>
 __global__ __launch_bounds__(256) void k_copy(const T* __restrict__ x, T* __restrict__ y, size_t n,
@@ -317,34 +230,6 @@ unsigned stride_blocks(size_t n) {
 }  // namespace
 
 template <class T>
-dmg_status launch_smooth(const T* S, T* u, const T* b, int nx, int ny, int colour,
-                         hipStream_t s) {
-  const int ci = colour & 1, cj = colour >> 1;
-  const int px = (nx - ci + 1) / 2, py = (ny - cj + 1) / 2;
-  k_smooth<T><<<grid2(px, py), dim3(kBX, kBY), 0, s>>>(S, u, b, nx, ny, ci, cj);
-  return launch_check("smooth");
-}
-
-template <class T>
-dmg_status launch_residual(const T* S, const T* u, const T* b, T* r, int nx, int ny,
-                           hipStream_t s) {
-  k_residual<T><<<grid2(nx, ny), dim3(kBX, kBY), 0, s>>>(S, u, b, r, nx, ny);
-  return launch_check("residual");
-}
-
-template <class T>
-dmg_status launch_restrict(const T* P, const T* r, T* bH, int nx, int ny, hipStream_t s) {
-  k_restrict<T><<<grid2((nx + 1) / 2, (ny + 1) / 2), dim3(kBX, kBY), 0, s>>>(P, r, bH, nx, ny);
-  return launch_check("restrict");
-}
-
-template <class T>
-dmg_status launch_prolong_add(const T* P, const T* eH, T* u, int nx, int ny, hipStream_t s) {
-  k_prolong_add<T><<<grid2(nx, ny), dim3(kBX, kBY), 0, s>>>(P, eH, u, nx, ny);
-  return launch_check("prolong_add");
-}
-
-template <class T>
 dmg_status launch_copy(const T* x, T* y, size_t n, const int* stop, hipStream_t s) {
   k_copy<T><<<stride_blocks(n), 256, 0, s>>>(x, y, n, stop);
   return launch_check("copy");
@@ -357,11 +242,6 @@ dmg_status launch_fill(T* x, T v, size_t n, hipStream_t s) {
 }
 
 #define DMG_INST(T)                                                                          \
-  template dmg_status launch_smooth<T>(const T*, T*, const T*, int, int, int, hipStream_t);  \
-  template dmg_status launch_residual<T>(const T*, const T*, const T*, T*, int, int,         \
-                                         hipStream_t);                                       \
-  template dmg_status launch_restrict<T>(const T*, const T*, T*, int, int, hipStream_t);     \
-  template dmg_status launch_prolong_add<T>(const T*, const T*, T*, int, int, hipStream_t);  \
   template dmg_status launch_fill<T>(T*, T, size_t, hipStream_t);                            \
   template dmg_status launch_copy<T>(const T*, T*, size_t, const int*, hipStream_t);
 DMG_INST(double)

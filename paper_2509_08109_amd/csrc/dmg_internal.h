@@ -134,19 +134,6 @@ dmg_status launch_grad_K(const double* jac, const double* lam, const double* u, 
                          double* dK, hipStream_t s);
 
 template <class T>
-dmg_status launch_coarse_solve(const T* b, T* u, int m, const int* idx, const double* chol,
-                               size_t n, hipStream_t s);
-template <class T>
-dmg_status launch_smooth(const T* S, T* u, const T* b, int nx, int ny, int colour,
-                         hipStream_t s);
-template <class T>
-dmg_status launch_residual(const T* S, const T* u, const T* b, T* r, int nx, int ny,
-                           hipStream_t s);
-template <class T>
-dmg_status launch_restrict(const T* P, const T* r, T* bH, int nx, int ny, hipStream_t s);
-template <class T>
-dmg_status launch_prolong_add(const T* P, const T* eH, T* u, int nx, int ny, hipStream_t s);
-template <class T>
 dmg_status launch_fill(T* x, T v, size_t n, hipStream_t s);
 template <class T>
 dmg_status launch_copy(const T* x, T* y, size_t n, const int* stop, hipStream_t s);

@@ -337,31 +337,6 @@ __global__ __launch_bounds__(256) void k_coarse_factor(const double* __restrict_
   }
 }
 
-template <class T>
-__global__ __launch_bounds__(256) void k_coarse_solve(const T* __restrict__ b, T* __restrict__ u,
-                                                      int m, const int* __restrict__ idx,
-                                                      const double* __restrict__ L, size_t n) {
-  extern __shared__ double y[];
-  // zero the whole coarsest vector first (boundary ring included)
-  for (size_t v = threadIdx.x; v < n; v += blockDim.x) u[v] = T(0);
-  for (int k = threadIdx.x; k < m; k += blockDim.x) y[k] = double(b[idx[k]]);
-  __syncthreads();
-  // forward: L y = b (column-oriented so that each step is a parallel update)
-  for (int k = 0; k < m; ++k) {
-    if (threadIdx.x == 0) y[k] /= L[k * m + k];
-    __syncthreads();
-    for (int r = k + 1 + threadIdx.x; r < m; r += blockDim.x) y[r] -= L[r * m + k] * y[k];
-    __syncthreads();
-  }
-  // backward: L^T x = y
-  for (int k = m - 1; k >= 0; --k) {
-    if (threadIdx.x == 0) y[k] /= L[k * m + k];
-    __syncthreads();
-    for (int r = threadIdx.x; r < k; r += blockDim.x) y[r] -= L[k * m + r] * y[k];
-    __syncthreads();
-  }
-  for (int k = threadIdx.x; k < m; k += blockDim.x) u[idx[k]] = T(y[k]);
-}
 
 __global__ __launch_bounds__(256) void k_cast(const double* __restrict__ in, float* __restrict__ out,
                                               size_t n) {
@@ -413,16 +388,6 @@ dmg_status launch_coarse_factor(const double* S, int nx, int ny, int m, int* idx
   return launch_check("coarse_factor");
 }
 
-template <class T>
-dmg_status launch_coarse_solve(const T* b, T* u, int m, const int* idx, const double* chol,
-                               size_t n, hipStream_t s) {
-  k_coarse_solve<T><<<1, 256, sizeof(double) * size_t(m), s>>>(b, u, m, idx, chol, n);
-  return launch_check("coarse_solve");
-}
-template dmg_status launch_coarse_solve<double>(const double*, double*, int, const int*,
-                                                const double*, size_t, hipStream_t);
-template dmg_status launch_coarse_solve<float>(const float*, float*, int, const int*,
-                                               const double*, size_t, hipStream_t);
 
 template <class T>
 dmg_status launch_pack(const double* S, T* out, size_t n, hipStream_t s) {

@@ -26,8 +26,9 @@ struct dmg_transfer {
   int *Crp = nullptr, *Cci = nullptr, *CTrp = nullptr, *CTci = nullptr, *Mrp = nullptr,
       *Mci = nullptr;
   double *Cv = nullptr, *CTv = nullptr, *Mv = nullptr;
-  unsigned char* dof = nullptr;
-  double *y = nullptr, *x = nullptr, *r = nullptr, *p = nullptr, *q = nullptr;
+  unsigned char* dof = nullptr;  // internal order
+  int* perm = nullptr;           // internal row i holds the caller's vertex perm[i]
+  double *x = nullptr, *r = nullptr, *p = nullptr, *q = nullptr;
   double *partials = nullptr, *scal = nullptr;
   void* block = nullptr;
   ~dmg_transfer() {
@@ -254,125 +255,220 @@ __device__ __forceinline__ double block_sum(double v) {
   return t;
 }
 
-// y = A x, one row per thread
-__global__ __launch_bounds__(256) void k_spmv(const int* __restrict__ rp, const int* __restrict__ ci,
-                                              const double* __restrict__ v,
-                                              const double* __restrict__ x, double* __restrict__ y,
-                                              int n) {
-  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
-    double acc = 0.0;
-    for (int k = rp[r]; k < rp[r + 1]; ++k) acc += v[k] * x[ci[k]];
-    y[r] = acc;
-  }
+// Row products run on groups of G consecutive lanes (G divides 64): lane l of a group reads
+// entries rp[r] + l, rp[r] + l + G, ... (coalesced), and the group sums its lanes with xor
+// shuffles in a fixed order.  Kernels walk row groups grid-stride; kernels that reduce write one
+// partial per workgroup.
+constexpr int kTBlocks = 4096;  // workgroup cap of the transfer kernels (= partials capacity)
+constexpr int kMG = 4;  // lanes per mesh row (rows of C and M_p hold ~7-9 entries; 4 measured best)
+constexpr int kCG = 8;  // lanes per grid row of C^T (~30 entries; 8 measured best)
+
+int tblocks(int n, int lanes) {
+  const long b = (long(n) * lanes + 255) / 256;
+  return int(std::max(1l, std::min(b, long(kTBlocks))));
 }
 
-// q = M p; partials of p.q
-__global__ __launch_bounds__(256) void k_spmv_dot(const int* __restrict__ rp,
-                                                  const int* __restrict__ ci,
-                                                  const double* __restrict__ v,
-                                                  const double* __restrict__ p,
-                                                  double* __restrict__ q, int n,
-                                                  double* __restrict__ partials) {
+template <int G, class X>
+__device__ __forceinline__ double row_dot(const int* __restrict__ rp, const int* __restrict__ ci,
+                                          const double* __restrict__ v, int r, int lane, X&& x) {
+  const int e = rp[r + 1];
   double acc = 0.0;
-  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int k = rp[r]; k < rp[r + 1]; ++k) s += v[k] * p[ci[k]];
-    q[r] = s;
-    acc += p[r] * s;
+  for (int k = rp[r] + lane; k < e; k += G) acc = __builtin_fma(v[k], x(ci[k]), acc);
+#pragma unroll
+  for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
+  return acc;
+}
+
+// from_grid start: r0 = dof * (C u_c) (mesh rows in the internal order); partials of r0.r0
+__global__ __launch_bounds__(256) void k_t_init_from(const int* __restrict__ rp,
+                                                     const int* __restrict__ ci,
+                                                     const double* __restrict__ v,
+                                                     const double* __restrict__ u_c,
+                                                     const unsigned char* __restrict__ dof,
+                                                     double* __restrict__ r0, int n,
+                                                     double* __restrict__ partials) {
+  const int lane = threadIdx.x & (kMG - 1);
+  const int g0 = int((blockIdx.x * 256u + threadIdx.x) / kMG), ng = int(gridDim.x * 256u / kMG);
+  double acc = 0.0;
+  for (int r = g0; r < n; r += ng) {
+    const double y = row_dot<kMG>(rp, ci, v, r, lane, [&](int c) { return u_c[c]; });
+    const double val = dof[r] ? y : 0.0;
+    if (lane == 0) {
+      r0[r] = val;
+      acc += val * val;
+    }
   }
   const double t = block_sum(acc);
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
-// r = p = mask * y; x = 0; partials of r.r
-__global__ __launch_bounds__(256) void k_cg_init(const double* __restrict__ y,
-                                                 const unsigned char* __restrict__ dof,
-                                                 double* __restrict__ x, double* __restrict__ r,
-                                                 double* __restrict__ p, int n,
-                                                 double* __restrict__ partials) {
+// to_grid start: r0 = dof * r_p taken into the internal order; partials of r0.r0
+__global__ __launch_bounds__(256) void k_t_init_to(const double* __restrict__ r_p,
+                                                   const int* __restrict__ perm,
+                                                   const unsigned char* __restrict__ dof,
+                                                   double* __restrict__ r0, int n,
+                                                   double* __restrict__ partials) {
   double acc = 0.0;
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
-    const double val = dof[k] ? y[k] : 0.0;
-    r[k] = val;
-    p[k] = val;
-    x[k] = 0.0;
+  for (int r = blockIdx.x * 256 + threadIdx.x; r < n; r += gridDim.x * 256) {
+    const double val = dof[r] ? r_p[perm[r]] : 0.0;
+    r0[r] = val;
     acc += val * val;
   }
   const double t = block_sum(acc);
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
-// alpha = rr/pq (0 when rr == 0); x += alpha p; optionally r -= alpha q with partials of r.r
-__global__ __launch_bounds__(256) void k_cg_xr(double* __restrict__ x, double* __restrict__ r,
-                                               const double* __restrict__ p,
-                                               const double* __restrict__ q,
-                                               const double* __restrict__ rr,
-                                               const double* __restrict__ pq, int n,
-                                               int update_r, double* __restrict__ partials) {
-  const double alpha = rr[0] == 0.0 ? 0.0 : rr[0] / pq[0];
+// q0 = M r0; partials of r0.q0
+__global__ __launch_bounds__(256) void k_t_mq(const int* __restrict__ rp, const int* __restrict__ ci,
+                                              const double* __restrict__ v,
+                                              const double* __restrict__ p, double* __restrict__ q,
+                                              int n, double* __restrict__ partials) {
+  const int lane = threadIdx.x & (kMG - 1);
+  const int g0 = int((blockIdx.x * 256u + threadIdx.x) / kMG), ng = int(gridDim.x * 256u / kMG);
   double acc = 0.0;
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
-    x[k] = x[k] + alpha * p[k];
-    if (update_r) {
-      const double rv = r[k] - alpha * q[k];
-      r[k] = rv;
-      acc += rv * rv;
+  for (int r = g0; r < n; r += ng) {
+    const double s = row_dot<kMG>(rp, ci, v, r, lane, [&](int c) { return p[c]; });
+    if (lane == 0) {
+      q[r] = s;
+      acc += p[r] * s;
     }
   }
-  if (update_r) {
-    const double t = block_sum(acc);
-    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+// scalars: sc[0] rr0, sc[2] pq0, sc[4] rr1, sc[6] pq1 (textbook CG: a zero rr gives a zero step)
+__device__ __forceinline__ double cg_alpha0(const double* sc) { return sc[0] == 0.0 ? 0.0 : sc[0] / sc[2]; }
+__device__ __forceinline__ double cg_beta(const double* sc) { return sc[0] == 0.0 ? 0.0 : sc[4] / sc[0]; }
+__device__ __forceinline__ double cg_alpha1(const double* sc) { return sc[4] == 0.0 ? 0.0 : sc[4] / sc[6]; }
+
+// r1 = r0 - alpha0 q0; partials of r1.r1
+__global__ __launch_bounds__(256) void k_t_r1(const double* __restrict__ r0,
+                                              const double* __restrict__ q0,
+                                              double* __restrict__ r1,
+                                              const double* __restrict__ sc, int n,
+                                              double* __restrict__ partials) {
+  const double alpha = cg_alpha0(sc);
+  double acc = 0.0;
+  for (int r = blockIdx.x * 256 + threadIdx.x; r < n; r += gridDim.x * 256) {
+    const double rv = __builtin_fma(-alpha, q0[r], r0[r]);
+    r1[r] = rv;
+    acc += rv * rv;
+  }
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+// p1 = r1 + beta r0 (formed where read); partials of p1.(M p1) -- M p1 itself is not needed
+__global__ __launch_bounds__(256) void k_t_mp1(const int* __restrict__ rp, const int* __restrict__ ci,
+                                               const double* __restrict__ v,
+                                               const double* __restrict__ r0,
+                                               const double* __restrict__ r1,
+                                               const double* __restrict__ sc, int n,
+                                               double* __restrict__ partials) {
+  const double beta = cg_beta(sc);
+  const int lane = threadIdx.x & (kMG - 1);
+  const int g0 = int((blockIdx.x * 256u + threadIdx.x) / kMG), ng = int(gridDim.x * 256u / kMG);
+  double acc = 0.0;
+  for (int r = g0; r < n; r += ng) {
+    const double s = row_dot<kMG>(rp, ci, v, r, lane,
+                                  [&](int c) { return __builtin_fma(beta, r0[c], r1[c]); });
+    if (lane == 0) acc += __builtin_fma(beta, r0[r], r1[r]) * s;
+  }
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+// x2 = alpha0 r0 + alpha1 p1; from_grid writes it in the caller's vertex order (out[perm[r]]),
+// to_grid keeps the internal order for C^T
+template <bool SCATTER>
+__global__ __launch_bounds__(256) void k_t_x(const double* __restrict__ r0,
+                                             const double* __restrict__ r1,
+                                             const double* __restrict__ sc,
+                                             const int* __restrict__ perm,
+                                             double* __restrict__ out, int n) {
+  const double alpha0 = cg_alpha0(sc), beta = cg_beta(sc), alpha1 = cg_alpha1(sc);
+  for (int r = blockIdx.x * 256 + threadIdx.x; r < n; r += gridDim.x * 256) {
+    const double x1 = alpha0 * r0[r];
+    const double p1 = __builtin_fma(beta, r0[r], r1[r]);
+    const double x2 = __builtin_fma(alpha1, p1, x1);
+    out[SCATTER ? perm[r] : r] = x2;
   }
 }
 
-// p = r + (rr_new / rr_old) p
-__global__ __launch_bounds__(256) void k_cg_p(double* __restrict__ p, const double* __restrict__ r,
-                                              const double* __restrict__ rr_old,
-                                              const double* __restrict__ rr_new, int n) {
-  const double beta = rr_old[0] == 0.0 ? 0.0 : rr_new[0] / rr_old[0];
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x)
-    p[k] = r[k] + beta * p[k];
-}
-
-__global__ __launch_bounds__(256) void k_zero_ring(double* __restrict__ v, int nx, int ny) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < nx) {
-    v[k] = 0.0;
-    v[size_t(ny - 1) * nx + k] = 0.0;
-  }
-  if (k < ny) {
-    v[size_t(k) * nx] = 0.0;
-    v[size_t(k) * nx + nx - 1] = 0.0;
+// r_c = C^T x over the grid rows
+__global__ __launch_bounds__(256) void k_t_ct(const int* __restrict__ rp, const int* __restrict__ ci,
+                                              const double* __restrict__ v,
+                                              const double* __restrict__ x,
+                                              double* __restrict__ out, int n) {
+  const int lane = threadIdx.x & (kCG - 1);
+  const int g0 = int((blockIdx.x * 256u + threadIdx.x) / kCG), ng = int(gridDim.x * 256u / kCG);
+  for (int r = g0; r < n; r += ng) {
+    const double s = row_dot<kCG>(rp, ci, v, r, lane, [&](int c) { return x[c]; });
+    if (lane == 0) out[r] = s;
   }
 }
 
-unsigned nblocks(int n) {
-  const int b = (n + 255) / 256;
-  return unsigned(std::max(1, std::min(b, kReduceBlocks)));
+// Two CG iterations from x = 0 on M_p, continuing from r0 (already in t->r with its partials):
+// leaves x2 = CG2(M_p, r0) in `out` (scattered to the caller's order when `scatter`).
+dmg_status cg2_tail(dmg_transfer* t, double* out, bool scatter, hipStream_t s) {
+  const int n = t->nv, nb = tblocks(n, kMG);
+  double* sc = t->scal;
+  DMG_CHECK(launch_finalize(t->partials, sc + 0, s, nb));
+  k_t_mq<<<nb, 256, 0, s>>>(t->Mrp, t->Mci, t->Mv, t->r, t->q, n, t->partials);
+  DMG_CHECK(launch_check("transfer M r0"));
+  DMG_CHECK(launch_finalize(t->partials, sc + 2, s, nb));
+  k_t_r1<<<nb, 256, 0, s>>>(t->r, t->q, t->p, sc, n, t->partials);
+  DMG_CHECK(launch_check("transfer r1"));
+  DMG_CHECK(launch_finalize(t->partials, sc + 4, s, nb));
+  k_t_mp1<<<nb, 256, 0, s>>>(t->Mrp, t->Mci, t->Mv, t->r, t->p, sc, n, t->partials);
+  DMG_CHECK(launch_check("transfer M p1"));
+  DMG_CHECK(launch_finalize(t->partials, sc + 6, s, nb));
+  if (scatter)
+    k_t_x<true><<<nb, 256, 0, s>>>(t->r, t->p, sc, t->perm, out, n);
+  else
+    k_t_x<false><<<nb, 256, 0, s>>>(t->r, t->p, sc, t->perm, out, n);
+  return launch_check("transfer x2");
 }
 
-// x = CG2(M, y) on the transfer's vectors (x is t->x).
-dmg_status cg2(dmg_transfer* t, const double* y, hipStream_t s) {
-  const int n = t->nv;
-  double* sc = t->scal;  // pairs: [0] rr0, [2] pq0, [4] rr1, [6] pq1
-  k_cg_init<<<kReduceBlocks, 256, 0, s>>>(y, t->dof, t->x, t->r, t->p, n, t->partials);
-  DMG_CHECK(launch_check("cg_init"));
-  DMG_CHECK(launch_finalize(t->partials, sc + 0, s));
-  // iteration 1
-  k_spmv_dot<<<kReduceBlocks, 256, 0, s>>>(t->Mrp, t->Mci, t->Mv, t->p, t->q, n, t->partials);
-  DMG_CHECK(launch_check("spmv_dot"));
-  DMG_CHECK(launch_finalize(t->partials, sc + 2, s));
-  k_cg_xr<<<kReduceBlocks, 256, 0, s>>>(t->x, t->r, t->p, t->q, sc + 0, sc + 2, n, 1, t->partials);
-  DMG_CHECK(launch_check("cg_xr"));
-  DMG_CHECK(launch_finalize(t->partials, sc + 4, s));
-  k_cg_p<<<nblocks(n), 256, 0, s>>>(t->p, t->r, sc + 0, sc + 4, n);
-  DMG_CHECK(launch_check("cg_p"));
-  // iteration 2 (r and p are not needed afterwards)
-  k_spmv_dot<<<kReduceBlocks, 256, 0, s>>>(t->Mrp, t->Mci, t->Mv, t->p, t->q, n, t->partials);
-  DMG_CHECK(launch_check("spmv_dot"));
-  DMG_CHECK(launch_finalize(t->partials, sc + 6, s));
-  k_cg_xr<<<kReduceBlocks, 256, 0, s>>>(t->x, t->r, t->p, t->q, sc + 4, sc + 6, n, 0, t->partials);
-  return launch_check("cg_xr");
+// Internal vertex order: by the grid cell holding each vertex's image (row-major), so that the
+// rows of C and M_p that are used together sit together and their gathers stay in cache.
+std::vector<int> locality_order(const Mesh& m, int nx, int ny) {
+  const double hx = 2.0 / (nx - 1), hy = 2.0 / (ny - 1);
+  std::vector<long> key(m.nv);
+  for (int v = 0; v < m.nv; ++v) {
+    const int ix = std::min(std::max(int(std::floor((m.xy_c[2 * v] + 1.0) / hx)), 0), nx - 2);
+    const int iy = std::min(std::max(int(std::floor((m.xy_c[2 * v + 1] + 1.0) / hy)), 0), ny - 2);
+    key[v] = long(iy) * (nx - 1) + ix;
+  }
+  std::vector<int> perm(m.nv);
+  for (int v = 0; v < m.nv; ++v) perm[v] = v;
+  std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return key[a] < key[b]; });
+  return perm;
+}
+
+// Rows of a taken in the order perm (new row i = old row perm[i]); columns through colmap when
+// given (then each row is re-sorted by its new column).
+Csr permute_rows(const Csr& a, const std::vector<int>& perm, const std::vector<int>* colmap) {
+  Csr out;
+  const int n = int(perm.size());
+  out.rp.assign(n + 1, 0);
+  out.ci.reserve(a.ci.size());
+  out.v.reserve(a.v.size());
+  std::vector<std::pair<int, double>> row;
+  for (int i = 0; i < n; ++i) {
+    const int o = perm[i];
+    row.clear();
+    for (int k = a.rp[o]; k < a.rp[o + 1]; ++k)
+      row.emplace_back(colmap ? (*colmap)[a.ci[k]] : a.ci[k], a.v[k]);
+    if (colmap) std::sort(row.begin(), row.end());
+    for (auto& e : row) {
+      out.ci.push_back(e.first);
+      out.v.push_back(e.second);
+    }
+    out.rp[i + 1] = int(out.ci.size());
+  }
+  return out;
 }
 
 }  // namespace
@@ -397,9 +493,14 @@ dmg_status dmg_transfer_create(int32_t nv, int32_t nt, const double* xy_c, const
       return fail(DMG_ERR_INVALID_ARG, "triangle vertex index %d out of range", tris[k]);
   Mesh m{nv, nt, xy_c, xy_p, tris, dof, {}, {}};
   build_adjacency(m);
-  Csr C = assemble_C(m, nx, ny, nq);
-  Csr M = assemble_M(m);
-  Csr CT = transpose(C, nx * ny);
+  const std::vector<int> perm = locality_order(m, nx, ny);
+  std::vector<int> newidx(nv);
+  for (int i = 0; i < nv; ++i) newidx[perm[i]] = i;
+  const Csr C = permute_rows(assemble_C(m, nx, ny, nq), perm, nullptr);
+  const Csr M = permute_rows(assemble_M(m), perm, &newidx);
+  const Csr CT = transpose(C, nx * ny);
+  std::vector<uint8_t> dof_p(nv);
+  for (int i = 0; i < nv; ++i) dof_p[i] = dof[perm[i]];
   if (C.ci.size() >= (size_t(1) << 31) || M.ci.size() >= (size_t(1) << 31))
     return fail(DMG_ERR_INVALID_ARG, "transfer matrices exceed 2^31 nonzeros");
   std::unique_ptr<dmg_transfer> t(new dmg_transfer);
@@ -421,12 +522,12 @@ dmg_status dmg_transfer_create(int32_t nv, int32_t nt, const double* xy_c, const
     t->Mci = a.take<int>(M.ci.size() + 1);
     t->Mv = a.take<double>(M.v.size() + 1);
     t->dof = a.take<unsigned char>(nv);
-    t->y = a.take<double>(nv);
+    t->perm = a.take<int>(nv);
     t->x = a.take<double>(nv);
     t->r = a.take<double>(nv);
     t->p = a.take<double>(nv);
     t->q = a.take<double>(nv);
-    t->partials = a.take<double>(kReduceBlocks);
+    t->partials = a.take<double>(kTBlocks);
     t->scal = a.take<double>(16);
   };
   layout(sz);
@@ -448,7 +549,8 @@ dmg_status dmg_transfer_create(int32_t nv, int32_t nt, const double* xy_c, const
   DMG_CHECK(up(t->Mrp, M.rp.data(), M.rp.size() * sizeof(int)));
   DMG_CHECK(up(t->Mci, M.ci.data(), M.ci.size() * sizeof(int)));
   DMG_CHECK(up(t->Mv, M.v.data(), M.v.size() * sizeof(double)));
-  DMG_CHECK(up(t->dof, dof, size_t(nv)));
+  DMG_CHECK(up(t->dof, dof_p.data(), size_t(nv)));
+  DMG_CHECK(up(t->perm, perm.data(), size_t(nv) * sizeof(int)));
   DMG_HIP(hipStreamSynchronize(stream));  // host vectors go out of scope
   *out = t.release();
   return DMG_OK;
@@ -466,23 +568,24 @@ dmg_status dmg_transfer_from_grid(dmg_transfer* t, const double* u_c, double* u_
                                   hipStream_t stream) {
   clear_error();
   if (!t || !u_c || !u_p) return fail(DMG_ERR_INVALID_ARG, "null pointer argument");
-  k_spmv<<<nblocks(t->nv), 256, 0, stream>>>(t->Crp, t->Cci, t->Cv, u_c, t->y, t->nv);
-  DMG_CHECK(launch_check("spmv C"));
-  DMG_CHECK(cg2(t, t->y, stream));
-  DMG_HIP(hipMemcpyAsync(u_p, t->x, size_t(t->nv) * sizeof(double), hipMemcpyDeviceToDevice,
-                         stream));
-  return DMG_OK;
+  const int nb = tblocks(t->nv, kMG);
+  k_t_init_from<<<nb, 256, 0, stream>>>(t->Crp, t->Cci, t->Cv, u_c, t->dof, t->r, t->nv,
+                                        t->partials);
+  DMG_CHECK(launch_check("transfer C u"));
+  return cg2_tail(t, u_p, true, stream);
 }
 
 dmg_status dmg_transfer_to_grid(dmg_transfer* t, const double* r_p, double* r_c,
                                 hipStream_t stream) {
   clear_error();
   if (!t || !r_p || !r_c) return fail(DMG_ERR_INVALID_ARG, "null pointer argument");
-  DMG_CHECK(cg2(t, r_p, stream));
+  const int nb = tblocks(t->nv, kMG);
+  k_t_init_to<<<nb, 256, 0, stream>>>(r_p, t->perm, t->dof, t->r, t->nv, t->partials);
+  DMG_CHECK(launch_check("transfer r_p"));
+  DMG_CHECK(cg2_tail(t, t->x, false, stream));
   const int ng = t->nx * t->ny;
-  k_spmv<<<nblocks(ng), 256, 0, stream>>>(t->CTrp, t->CTci, t->CTv, t->x, r_c, ng);
-  DMG_CHECK(launch_check("spmv C^T"));
-  return DMG_OK;
+  k_t_ct<<<tblocks(ng, kCG), 256, 0, stream>>>(t->CTrp, t->CTci, t->CTv, t->x, r_c, ng);
+  return launch_check("transfer C^T x");
 }
 
 void dmg_transfer_destroy(dmg_transfer* t) { delete t; }
