@@ -155,7 +155,7 @@ void carve(dmg_hier& h, Arena& a, const std::vector<std::pair<int, int>>& dims,
   h.m_coarse = (c.first - 2) * (c.second - 2);
   h.coarse_idx = a.take<int>(size_t(h.m_coarse));
   h.chol = a.take<double>(size_t(h.m_coarse) * h.m_coarse);
-  h.partials = a.take<double>(kMaxPartials);
+  h.partials = a.take<double>(kMaxPartials + kReduceBlocks);  // + the b-norm partials of a solve start
   for (size_t l = 0; l < dims.size(); ++l) {
     h.L[l].cfg = default_strip_config(dims[l].first, dims[l].second, o);
     h.L[l].cfg32 = h.L[l].cfg;
@@ -498,18 +498,35 @@ dmg_status tune_tail(dmg_hier* h, T* u_top, const T* b_top, int reps, hipStream_
 }
 
 dmg_status setup_impl(dmg_hier* h, const double* S, hipStream_t s) {
-  const size_t n0 = h->L[0].n();
-  DMG_HIP(hipMemcpyAsync(h->L[0].S, S, 5 * n0 * sizeof(double), hipMemcpyDeviceToDevice, s));
-  for (size_t l = 0; l + 1 < h->L.size(); ++l) {
+  const int nl = int(h->L.size());
+  // levels from first_small down run their whole setup in one single-workgroup kernel
+  int first_small = nl - 1;
+  while (first_small > 0 && std::max(h->L[first_small - 1].nx, h->L[first_small - 1].ny) <= kSmallSetupN &&
+         nl - (first_small - 1) <= kMaxTail + 1)
+    --first_small;
+  DMG_CHECK(launch_copy_pack(S, h->L[0].S, h->L[0].Sp, h->L[0].n(), s));
+  for (int l = 0; l < first_small; ++l) {
     const Level& L = h->L[l];
     DMG_CHECK(launch_interp_weights(L.S, L.nx, L.ny, L.P, s));
-    DMG_CHECK(launch_rap(L.S, L.P, L.nx, L.ny, h->L[l + 1].S, s));
+    DMG_CHECK(launch_rap(L.S, L.P, L.nx, L.ny, h->L[l + 1].S, h->L[l + 1].Sp, s));
   }
-  const Level& C = h->L.back();
-  DMG_CHECK(launch_coarse_factor(C.S, C.nx, C.ny, h->m_coarse, h->coarse_idx, h->chol, h->flag, s));
-  for (size_t l = 0; l < h->L.size(); ++l) {
+  SmallSetup ss;
+  ss.nlev = nl - first_small;
+  for (int k = 0; k < ss.nlev; ++k) {
+    const Level& L = h->L[first_small + k];
+    ss.S[k] = L.S;
+    ss.Sp[k] = L.Sp;
+    ss.P[k] = L.P;
+    ss.nx[k] = L.nx;
+    ss.ny[k] = L.ny;
+  }
+  ss.m = h->m_coarse;
+  ss.idx = h->coarse_idx;
+  ss.chol = h->chol;
+  ss.flag = h->flag;
+  DMG_CHECK(launch_setup_small(ss, s));
+  for (int l = 0; l < nl; ++l) {
     const Level& L = h->L[l];
-    if (L.Sp) DMG_CHECK(launch_pack<double>(L.S, L.Sp, L.n(), s));
     if (L.Sp32) DMG_CHECK(launch_pack<float>(L.S, L.Sp32, L.n(), s));
   }
   if (h->opts.precision == DMG_FP32_IR) {
@@ -787,56 +804,49 @@ dmg_status dmg_solve(dmg_hier* h, double* u, const double* b, double rtol, int32
   if (!h || !u || !b) return fail(DMG_ERR_INVALID_ARG, "null pointer argument");
   if (!(rtol >= 0.0) || max_iters < 0) return fail(DMG_ERR_INVALID_ARG, "bad rtol/max_iters");
   if (iters) *iters = 0;
-  double bn = 0.0, rn = 0.0;
-  DMG_CHECK(norm_b(h, b, stream));
-  DMG_CHECK(read_scalar(h, 1, &bn, stream));
+  const bool ir = h->opts.precision == DMG_FP32_IR;
+  const int slot = ir ? 4 : 2;
+  const Level& L0 = h->L[0];
+  // starting norms and the solve state on the device: no host synchronisation before the first
+  // chunk of steps (a solve that is done at the start runs one chunk of skipped kernels)
+  double* pb = h->partials + kMaxPartials;
+  DMG_CHECK(launch_sq_partials(b, L0.n(), L0.nx, L0.ny, pb, stream));
+  int nr = kReduceBlocks;
+  if (ir) {
+    DMG_CHECK(launch_ir_residual(L0.Sp, u, b, L0.b32, L0.nx, L0.ny, h->partials, stream));
+    nr = ir_residual_blocks(L0.nx, L0.ny);
+  } else {
+    DMG_CHECK(launch_resid_sq_partials(L0.S, u, b, L0.nx, L0.ny, h->partials, stream));
+  }
+  DMG_CHECK(launch_solve_start(pb, kReduceBlocks, h->partials, nr, h->scalars, h->scalars + slot,
+                               h->flag + 4, rtol, max_iters, u, L0.n(), stream));
+  int* hs = reinterpret_cast<int*>(h->host + 8);
+  double* hsc = h->host;  // scalars [0..7]
+  for (;;) {
+    DMG_CHECK(run_step(h, ir ? 1 : 0, u, b, stream));
+    DMG_HIP(hipMemcpyAsync(hs, h->flag + 4, 2 * sizeof(int), hipMemcpyDeviceToHost, stream));
+    DMG_HIP(hipMemcpyAsync(hsc, h->scalars, 8 * sizeof(double), hipMemcpyDeviceToHost, stream));
+    DMG_HIP(hipStreamSynchronize(stream));
+    if (hs[0]) break;
+  }
+  const int k = hs[1];
+  const double bn = hsc[1], rn = hsc[slot + 1];
   if (!std::isfinite(bn)) return fail(DMG_ERR_NONFINITE, "right-hand side norm is not finite");
-  if (bn == 0.0) {  // the solution of A u = 0 is u = 0
-    DMG_CHECK(launch_fill<double>(u, 0.0, h->L[0].n(), stream));
+  if (bn == 0.0) {  // u was set to 0, the solution of A u = 0
     if (relres) *relres = 0.0;
     return DMG_OK;
   }
-  const bool ir = h->opts.precision == DMG_FP32_IR;
-  const int slot = ir ? 4 : 2;
-  if (ir) {
-    const Level& L = h->L[0];
-    DMG_CHECK(launch_ir_residual(L.Sp, u, b, L.b32, L.nx, L.ny, h->partials, stream));
-    DMG_CHECK(launch_finalize(h->partials, h->scalars + 4, stream, ir_residual_blocks(L.nx, L.ny)));
-  } else {
-    DMG_CHECK(norm_r(h, u, b, 2, stream));
-  }
-  DMG_CHECK(read_scalar(h, slot + 1, &rn, stream));
-  if (!std::isfinite(rn)) return fail(DMG_ERR_NONFINITE, "initial residual norm is not finite");
-  const double target = rtol * bn;
-  int k = 0;
-  if (rn > target && max_iters > 0) {
-    // device solve state: stop = 0, steps = 0, max = max_iters, target^2
-    int* hs = reinterpret_cast<int*>(h->host + 8);
-    hs[0] = 0;
-    hs[1] = 0;
-    hs[2] = max_iters;
-    h->host[12] = target * target;
-    DMG_HIP(hipMemcpyAsync(h->flag + 4, hs, 3 * sizeof(int), hipMemcpyHostToDevice, stream));
-    DMG_HIP(hipMemcpyAsync(h->scalars + 6, h->host + 12, sizeof(double), hipMemcpyHostToDevice,
-                           stream));
-    for (;;) {
-      DMG_CHECK(run_step(h, ir ? 1 : 0, u, b, stream));
-      DMG_HIP(hipMemcpyAsync(hs, h->flag + 4, 2 * sizeof(int), hipMemcpyDeviceToHost, stream));
-      DMG_HIP(hipStreamSynchronize(stream));
-      if (hs[0]) break;
-    }
-    k = hs[1];
-    DMG_CHECK(read_scalar(h, slot + 1, &rn, stream));
-    if (history && k > 0)
-      DMG_HIP(hipMemcpy(history, h->hist, size_t(std::min(k, kMaxHistory)) * sizeof(double),
-                        hipMemcpyDeviceToHost));
-  }
+  if (history && k > 0)
+    DMG_HIP(hipMemcpy(history, h->hist, size_t(std::min(k, kMaxHistory)) * sizeof(double),
+                      hipMemcpyDeviceToHost));
   if (iters) *iters = k;
-  if (relres) *relres = bn > 0 ? rn / bn : rn;
-  if (!std::isfinite(rn)) return fail(DMG_ERR_NONFINITE, "residual norm became non-finite at step %d", k);
-  if (rn > target)
+  if (relres) *relres = rn / bn;
+  if (!std::isfinite(rn))
+    return fail(DMG_ERR_NONFINITE, k > 0 ? "residual norm became non-finite at step %d"
+                                         : "initial residual norm is not finite", k);
+  if (rn > rtol * bn)
     return fail(DMG_ERR_NO_CONVERGENCE, "no convergence in %d steps (rel. residual %.3e)", k,
-                bn > 0 ? rn / bn : rn);
+                rn / bn);
   return DMG_OK;
 }
 

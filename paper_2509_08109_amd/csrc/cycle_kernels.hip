@@ -44,6 +44,7 @@ __device__ __forceinline__ double block_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
   __shared__ double ws[4];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();  // earlier readers of ws (a previous call) are done
   if (lane == 0) ws[wid] = v;
   __syncthreads();
   double t = 0.0;
@@ -159,6 +160,40 @@ __global__ __launch_bounds__(256) void k_norms_multi(const NormArgs* __restrict_
   }
 }
 
+__global__ __launch_bounds__(256) void k_solve_start(const double* __restrict__ pb, int nb,
+                                                     const double* __restrict__ pr, int nr,
+                                                     double* __restrict__ sc_b,
+                                                     double* __restrict__ sc_r,
+                                                     int* __restrict__ st, double rtol,
+                                                     int max_iters) {
+  double ab = 0.0, ar = 0.0;
+  for (int k = threadIdx.x; k < nb; k += 256) ab += pb[k];
+  for (int k = threadIdx.x; k < nr; k += 256) ar += pr[k];
+  const double tb = block_sum(ab);
+  const double tr = block_sum(ar);
+  if (threadIdx.x == 0) {
+    const double bn = sqrt(tb), rn = sqrt(tr);
+    const double target = rtol * bn;
+    sc_b[0] = tb;
+    sc_b[1] = bn;
+    sc_r[0] = tr;
+    sc_r[1] = rn;
+    sc_b[6] = target * target;
+    st[0] = (bn == 0.0 || !(rn > target) || max_iters <= 0 || !isfinite(tb) || !isfinite(tr)) ? 1 : 0;
+    st[1] = 0;
+    st[2] = max_iters;
+  }
+}
+
+// u = 0 when ||b|| (sc_b[1]) is zero: the solution of A u = 0
+__global__ __launch_bounds__(256) void k_zero_if_b0(double* __restrict__ u, size_t n,
+                                                    const double* __restrict__ sc_b) {
+  if (sc_b[1] != 0.0) return;
+  for (size_t k = blockIdx.x * size_t(blockDim.x) + threadIdx.x; k < n;
+       k += size_t(gridDim.x) * blockDim.x)
+    u[k] = 0.0;
+}
+
 // Squared-residual partials of instances whose whole cycle runs in the coarse tail (no strip
 // sweep produces them): blocks_per workgroups per instance into list[k].partials[0..blocks_per).
 __global__ __launch_bounds__(256) void k_resid_multi(const NormArgs* __restrict__ list,
@@ -263,6 +298,15 @@ dmg_status launch_sq_partials(const double* x, size_t, int nx, int ny, double* p
 dmg_status launch_finalize(const double* partials, double* out, hipStream_t s, int count) {
   k_finalize<<<1, 256, 0, s>>>(partials, out, count);
   return launch_check("finalize");
+}
+
+dmg_status launch_solve_start(const double* pb, int nb, const double* pr, int nr, double* sc_b,
+                              double* sc_r, int* st, double rtol, int max_iters, double* u,
+                              size_t n, hipStream_t s) {
+  k_solve_start<<<1, 256, 0, s>>>(pb, nb, pr, nr, sc_b, sc_r, st, rtol, max_iters);
+  DMG_CHECK(launch_check("solve_start"));
+  k_zero_if_b0<<<stride_blocks(n), 256, 0, s>>>(u, n, sc_b);
+  return launch_check("zero_if_b0");
 }
 
 dmg_status launch_check_multi(const CheckArgs* list, int count, hipStream_t s) {

@@ -83,6 +83,7 @@ constexpr int kReduceBlocks = 1024;  // fixed partial count: reductions are orde
 constexpr int kMaxPartials = 16384;  // capacity of the partials buffer
 constexpr int kTailMaxN = 65;    // levels with max(nx, ny) <= this may run in the coarse tail
 constexpr int kMaxTail = 12;     // at most this many levels in the coarse tail
+constexpr int kSmallSetupN = 65;  // levels with max(nx, ny) <= this are set up in one workgroup
 constexpr int kMaxLevels = 32;
 constexpr int kMaxHistory = 4096;
 constexpr int kChunk = 4;            // solve steps per host synchronisation
@@ -122,10 +123,26 @@ namespace dmg {
 dmg_status launch_assemble(const double* jac, const double* K, int nx, int ny, double* S,
                            hipStream_t s);
 dmg_status launch_interp_weights(const double* S, int nx, int ny, double* P, hipStream_t s);
+// SHp (nullable): also write the coarse stencil point-major [nyc][nxc][5]
 dmg_status launch_rap(const double* S, const double* P, int nx, int ny, double* SH,
-                      hipStream_t s);
-dmg_status launch_coarse_factor(const double* S, int nx, int ny, int m, int* idx, double* chol,
-                                int* flag, hipStream_t s);
+                      double* SHp, hipStream_t s);
+// Setup of levels small enough for one workgroup: level k = 0..nlev-1 of this list is
+// (S[k] planar, Sp[k] point-major or null, P[k], nx[k], ny[k]); computes P[k] and S[k+1]
+// (and Sp[k+1]) for k < nlev-1, then the Cholesky factor of the last level.
+struct SmallSetup {
+  double* S[kMaxTail + 1];
+  double* Sp[kMaxTail + 1];
+  double* P[kMaxTail + 1];
+  int nx[kMaxTail + 1], ny[kMaxTail + 1];
+  int nlev = 0;
+  int m = 0;
+  int* idx = nullptr;
+  double* chol = nullptr;
+  int* flag = nullptr;
+};
+dmg_status launch_setup_small(const SmallSetup& a, hipStream_t s);
+// level 0: S (caller, planar) -> Sd (planar) and Sp (point-major, nullable)
+dmg_status launch_copy_pack(const double* S, double* Sd, double* Sp, size_t n, hipStream_t s);
 // point-major copy of a planar stencil: out[5 v + k] = T(S[k n + v])
 template <class T>
 dmg_status launch_pack(const double* S, T* out, size_t n, hipStream_t s);
@@ -286,6 +303,13 @@ struct NormArgs {
   double* partials; // k_resid_multi output (instances whose cycle is all coarse tail)
 };
 dmg_status launch_check_multi(const CheckArgs* list, int count, hipStream_t s);
+// Start of a solve on the device: sums the b-norm and residual-norm partials (fixed order) into
+// sc_b[0..1] = ||b||^2, ||b|| and sc_r[0..1] = ||r||^2, ||r||, sets sc_b[6] = (rtol ||b||)^2 and
+// the state st = {stop, steps = 0, max}: stop when ||r|| <= rtol ||b||, max_iters <= 0, b = 0 or
+// a norm is not finite.  When b = 0 it also zeroes u (n values).
+dmg_status launch_solve_start(const double* pb, int nb, const double* pr, int nr, double* sc_b,
+                              double* sc_r, int* st, double rtol, int max_iters, double* u,
+                              size_t n, hipStream_t s);
 dmg_status launch_norms_multi(const NormArgs* list, int count, int blocks_per, double* partials,
                               double* summary, hipStream_t s);
 dmg_status launch_gather_multi(const CheckArgs* list, int count, double* rel, int* steps,

@@ -184,12 +184,10 @@ __device__ __forceinline__ void yline_w(const double* S, size_t N, int nx, int n
   wN = -(a.N + a.NW + a.NE) / d;
 }
 
-__global__ __launch_bounds__(256) void k_interp(const double* __restrict__ S, int nx, int ny,
-                                                double* __restrict__ P) {
+// Weights of coarse point (I, J) (see the layout of P in the library header).
+__device__ __forceinline__ void interp_point(const double* __restrict__ S, int nx, int ny,
+                                             double* __restrict__ P, int I, int J) {
   const int ncx = (nx + 1) / 2, ncy = (ny + 1) / 2;
-  const int I = blockIdx.x * kBX + threadIdx.x;
-  const int J = blockIdx.y * kBY + threadIdx.y;
-  if (I >= ncx || J >= ncy) return;
   const size_t N = size_t(nx) * ny;
   const size_t NC = size_t(ncx) * ncy;
   const size_t c = size_t(J) * ncx + I;
@@ -211,6 +209,14 @@ __global__ __launch_bounds__(256) void k_interp(const double* __restrict__ S, in
   }
 #pragma unroll
   for (int p = 0; p < 8; ++p) P[p * NC + c] = w[p];
+}
+
+__global__ __launch_bounds__(256) void k_interp(const double* __restrict__ S, int nx, int ny,
+                                                double* __restrict__ P) {
+  const int I = blockIdx.x * kBX + threadIdx.x;
+  const int J = blockIdx.y * kBY + threadIdx.y;
+  if (I >= (nx + 1) / 2 || J >= (ny + 1) / 2) return;
+  interp_point(S, nx, ny, P, I, J);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -244,13 +250,12 @@ __device__ __forceinline__ double aentry(const double* __restrict__ S, size_t N,
   return S[4 * N + v + nx - 1];  // da < 0, db > 0
 }
 
-__global__ __launch_bounds__(256) void k_rap(const double* __restrict__ S,
-                                             const double* __restrict__ P, int nx, int ny,
-                                             double* __restrict__ SH) {
+// Coarse stencil at (I, J): planar into SH and, when SHp is given, point-major into SHp.
+__device__ __forceinline__ void rap_point(const double* __restrict__ S,
+                                          const double* __restrict__ P, int nx, int ny,
+                                          double* __restrict__ SH, double* __restrict__ SHp,
+                                          int I, int J) {
   const int ncx = (nx + 1) / 2, ncy = (ny + 1) / 2;
-  const int I = blockIdx.x * kBX + threadIdx.x;
-  const int J = blockIdx.y * kBY + threadIdx.y;
-  if (I >= ncx || J >= ncy) return;
   const size_t N = size_t(nx) * ny;
   const size_t NC = size_t(ncx) * ncy;
   const size_t c = size_t(J) * ncx + I;
@@ -292,16 +297,28 @@ __global__ __launch_bounds__(256) void k_rap(const double* __restrict__ S,
   }
 #pragma unroll
   for (int t = 0; t < 5; ++t) SH[t * NC + c] = acc[t];
+  if (SHp) {
+#pragma unroll
+    for (int t = 0; t < 5; ++t) SHp[5 * c + t] = acc[t];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_rap(const double* __restrict__ S,
+                                             const double* __restrict__ P, int nx, int ny,
+                                             double* __restrict__ SH, double* __restrict__ SHp) {
+  const int I = blockIdx.x * kBX + threadIdx.x;
+  const int J = blockIdx.y * kBY + threadIdx.y;
+  if (I >= (nx + 1) / 2 || J >= (ny + 1) / 2) return;
+  rap_point(S, P, nx, ny, SH, SHp, I, J);
 }
 
 // ---------------------------------------------------------------------------------------
 // Coarsest level: gather the m interior unknowns into a dense matrix and factor it in place
 // (lower Cholesky) with one workgroup.  flag[0] = 1 on a non-positive pivot.
 // ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_coarse_factor(const double* __restrict__ S, int nx,
-                                                       int ny, int m, int* __restrict__ idx,
-                                                       double* __restrict__ L,
-                                                       int* __restrict__ flag) {
+__device__ void coarse_factor_body(const double* __restrict__ S, int nx, int ny, int m,
+                                   int* __restrict__ idx, double* __restrict__ L,
+                                   int* __restrict__ flag) {
   const size_t N = size_t(nx) * ny;
   const int mx = nx - 2;
   for (int k = threadIdx.x; k < m; k += blockDim.x) idx[k] = (k / mx + 1) * nx + (k % mx + 1);
@@ -337,6 +354,39 @@ __global__ __launch_bounds__(256) void k_coarse_factor(const double* __restrict_
   }
 }
 
+
+
+// Setup of the small levels in one workgroup: for k = 0..nlev-2, the weights P[k] of level k and
+// the Galerkin stencil of level k+1 (planar, and point-major where Sp[k+1] is set), then the
+// Cholesky factor of the last level.
+__global__ __launch_bounds__(1024) void k_setup_small(SmallSetup a) {
+  for (int k = 0; k + 1 < a.nlev; ++k) {
+    const int nx = a.nx[k], ny = a.ny[k];
+    const int ncx = (nx + 1) / 2, ncy = (ny + 1) / 2;
+    for (int c = threadIdx.x; c < ncx * ncy; c += blockDim.x) interp_point(a.S[k], nx, ny, a.P[k], c % ncx, c / ncx);
+    __syncthreads();
+    for (int c = threadIdx.x; c < ncx * ncy; c += blockDim.x)
+      rap_point(a.S[k], a.P[k], nx, ny, a.S[k + 1], a.Sp[k + 1], c % ncx, c / ncx);
+    __syncthreads();
+  }
+  const int l = a.nlev - 1;
+  coarse_factor_body(a.S[l], a.nx[l], a.ny[l], a.m, a.idx, a.chol, a.flag);
+}
+
+// Level 0: the caller's planar stencil copied into the hierarchy, planar and point-major.
+__global__ __launch_bounds__(256) void k_copy_pack(const double* __restrict__ S,
+                                                   double* __restrict__ Sd,
+                                                   double* __restrict__ Sp, size_t n) {
+  for (size_t v = blockIdx.x * size_t(blockDim.x) + threadIdx.x; v < n;
+       v += size_t(gridDim.x) * blockDim.x) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const double x = S[k * n + v];
+      Sd[k * n + v] = x;
+      if (Sp) Sp[5 * v + k] = x;
+    }
+  }
+}
 
 __global__ __launch_bounds__(256) void k_cast(const double* __restrict__ in, float* __restrict__ out,
                                               size_t n) {
@@ -377,17 +427,24 @@ dmg_status launch_interp_weights(const double* S, int nx, int ny, double* P, hip
 }
 
 dmg_status launch_rap(const double* S, const double* P, int nx, int ny, double* SH,
-                      hipStream_t s) {
-  k_rap<<<grid2((nx + 1) / 2, (ny + 1) / 2), dim3(kBX, kBY), 0, s>>>(S, P, nx, ny, SH);
+                      double* SHp, hipStream_t s) {
+  k_rap<<<grid2((nx + 1) / 2, (ny + 1) / 2), dim3(kBX, kBY), 0, s>>>(S, P, nx, ny, SH, SHp);
   return launch_check("rap");
 }
 
-dmg_status launch_coarse_factor(const double* S, int nx, int ny, int m, int* idx, double* chol,
-                                int* flag, hipStream_t s) {
-  k_coarse_factor<<<1, 256, 0, s>>>(S, nx, ny, m, idx, chol, flag);
-  return launch_check("coarse_factor");
+
+
+dmg_status launch_setup_small(const SmallSetup& a, hipStream_t s) {
+  if (a.nlev < 1 || a.nlev > kMaxTail + 1) return fail(DMG_ERR_INVALID_ARG, "small setup depth %d", a.nlev);
+  k_setup_small<<<1, 1024, 0, s>>>(a);
+  return launch_check("setup_small");
 }
 
+dmg_status launch_copy_pack(const double* S, double* Sd, double* Sp, size_t n, hipStream_t s) {
+  const size_t blocks = (n + 255) / 256;
+  k_copy_pack<<<dim3(unsigned(blocks < 65535 ? (blocks ? blocks : 1) : 65535)), 256, 0, s>>>(S, Sd, Sp, n);
+  return launch_check("copy_pack");
+}
 
 template <class T>
 dmg_status launch_pack(const double* S, T* out, size_t n, hipStream_t s) {

@@ -248,6 +248,7 @@ __device__ __forceinline__ double block_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
   __shared__ double ws[4];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();  // earlier readers of ws (a previous call) are done
   if (lane == 0) ws[wid] = v;
   __syncthreads();
   double t = 0.0;
