@@ -16,24 +16,34 @@ from .fields import GAUSS_OFFSETS, grid_coords, uniform_rhs
 from .maps import Star, conformal_square_to_disk
 
 
-def _phi_tables(n: int, device):
+def _phi_tables(n: int, device, row_block: int = 64):
     """w and dw/dz of the conformal map at the 2x2 Gauss points ([4][n-1][n-1]) and w at the
-    cell centres ([n-1][n-1]), as complex128 tensors on ``device``."""
+    cell centres ([n-1][n-1]), as complex128 tensors on ``device`` (row blocks on a thread
+    pool: the special functions release the GIL)."""
+    import concurrent.futures as cf
+    import os
+
     import torch
 
     xi, eta = grid_coords(n, n)
     h = xi[1] - xi[0]
-    ws, dws = [], []
-    for q in range(4):
-        qx, qy = q & 1, q >> 1
-        XX, YY = np.meshgrid(xi[:-1] + h * GAUSS_OFFSETS[qx], eta[:-1] + h * GAUSS_OFFSETS[qy])
-        w, dw = conformal_square_to_disk(XX, YY)
-        ws.append(w)
-        dws.append(dw)
-    XC, YC = np.meshgrid(0.5 * (xi[:-1] + xi[1:]), 0.5 * (eta[:-1] + eta[1:]))
-    wc, _ = conformal_square_to_disk(XC, YC)
-    t = lambda a: torch.as_tensor(np.asarray(a), dtype=torch.complex128, device=device)
-    return t(np.stack(ws)), t(np.stack(dws)), t(wc)
+    w = np.empty((4, n - 1, n - 1), dtype=np.complex128)
+    dw = np.empty((4, n - 1, n - 1), dtype=np.complex128)
+    wc = np.empty((n - 1, n - 1), dtype=np.complex128)
+
+    def block(j0):
+        j1 = min(n - 1, j0 + row_block)
+        for q in range(4):
+            qx, qy = q & 1, q >> 1
+            XX, YY = np.meshgrid(xi[:-1] + h * GAUSS_OFFSETS[qx], eta[j0:j1] + h * GAUSS_OFFSETS[qy])
+            w[q, j0:j1], dw[q, j0:j1] = conformal_square_to_disk(XX, YY)
+        XC, YC = np.meshgrid(0.5 * (xi[:-1] + xi[1:]), 0.5 * (eta[j0:j1] + eta[j0 + 1:j1 + 1]))
+        wc[j0:j1], _ = conformal_square_to_disk(XC, YC)
+
+    with cf.ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        list(ex.map(block, range(0, n - 1, row_block)))
+    t = lambda a: torch.as_tensor(a, dtype=torch.complex128, device=device)
+    return t(w), t(dw), t(wc)
 
 
 def _h_torch(mp: Star, w):
@@ -108,3 +118,20 @@ def star_batch_device(count: int, choices=(129, 257, 513, 1025), seed: int = 3, 
         jac = torch.stack([J[e][q] for q in range(4) for e in range(4)])
         b = torch.as_tensor(uniform_rhs(n, n, g_b), dtype=torch.float64, device=device)
         yield n, jac.contiguous(), K.contiguous(), b
+
+
+def star_device(n: int, seed: int = 1, device="cuda"):
+    """(jac [16][n-1][n-1], K [n-1][n-1], b [n][n]) of ``problems.star(n, seed)`` as float64
+    tensors on ``device``."""
+    import torch
+
+    from . import streams
+
+    g_map, g_k, g_b, _, _ = streams(seed)
+    mp = Star.random(g_map)
+    w, dw, wc = _phi_tables(n, device)
+    K = _lognormal_torch(mp, wc, g_k)
+    J = _jacobian_torch(mp, w, dw)
+    jac = torch.stack([J[e][q] for q in range(4) for e in range(4)])
+    b = torch.as_tensor(uniform_rhs(n, n, g_b), dtype=torch.float64, device=device)
+    return jac.contiguous(), K.contiguous(), b

@@ -105,3 +105,32 @@ def smooth_target(nx: int, ny: int, rng: np.random.Generator, modes: int = 8) ->
     u[0, :] = u[-1, :] = 0.0
     u[:, 0] = u[:, -1] = 0.0
     return u
+
+
+def sample_jacobian_patch(mp, n: int, i0: int, j0: int, m: int) -> np.ndarray:
+    """The [16][m][m] block of ``sample_jacobian(mp, n, n)`` for cells [i0, i0+m) x [j0, j0+m)."""
+    xi, eta = grid_coords(n, n)
+    hx, hy = xi[1] - xi[0], eta[1] - eta[0]
+    out = np.empty((16, m, m))
+    for q in range(4):
+        qx, qy = q & 1, q >> 1
+        XX, YY = np.meshgrid(xi[i0:i0 + m] + hx * GAUSS_OFFSETS[qx], eta[j0:j0 + m] + hy * GAUSS_OFFSETS[qy])
+        J = mp.jacobian(XX, YY)
+        for e in range(4):
+            out[4 * q + e] = J[e]
+    return out
+
+
+def lognormal_K_patch(mp, n: int, i0: int, j0: int, m: int, rng: np.random.Generator,
+                      sigma: float = 1.0, ell: float = 0.1, n_features: int = 1024) -> np.ndarray:
+    """The [m][m] block of ``lognormal_K(mp, n, n, rng)`` for cells [i0, i0+m) x [j0, j0+m),
+    drawing the same random features from ``rng`` (evaluated with NumPy)."""
+    omega = rng.normal(0.0, 1.0 / ell, size=(n_features, 2))
+    phase = rng.uniform(0.0, 2 * math.pi, size=n_features)
+    xi, eta = grid_coords(n, n)
+    XX, YY = np.meshgrid(0.5 * (xi[i0:i0 + m] + xi[i0 + 1:i0 + m + 1]),
+                         0.5 * (eta[j0:j0 + m] + eta[j0 + 1:j0 + m + 1]))
+    x, y = mp(XX, YY)
+    pts = np.stack([np.ravel(x), np.ravel(y)], axis=1)
+    g = sigma * math.sqrt(2.0 / n_features) * np.cos(pts @ omega.T + phase).sum(axis=1)
+    return np.exp(g).reshape(m, m)

@@ -141,3 +141,20 @@ def test_device_batch_reproduces_host_batch():
         assert np.allclose(jac.numpy(), p.jac, rtol=1e-13, atol=1e-14)
         assert np.allclose(K.numpy(), p.K, rtol=1e-12)
         assert np.array_equal(b.numpy(), p.b)
+
+
+def test_device_star_and_patches_reproduce_host_star():
+    """star_device and the patch samplers draw the inputs of problems.star."""
+    import torch  # noqa: F401
+
+    from problems.batch_device import star_device
+    from problems.fields import lognormal_K_patch, sample_jacobian_patch
+
+    p = pb.star(33, seed=3)
+    jac, K, b = star_device(33, seed=3, device="cpu")
+    assert np.allclose(jac.numpy(), p.jac, rtol=1e-13, atol=1e-14)
+    assert np.allclose(K.numpy(), p.K, rtol=1e-12)
+    assert np.array_equal(b.numpy(), p.b)
+    assert np.allclose(sample_jacobian_patch(p.map, 33, 6, 10, 8), p.jac[:, 10:18, 6:14], rtol=1e-14, atol=1e-15)
+    Kp = lognormal_K_patch(p.map, 33, 6, 10, 8, pb.streams(3)[1])
+    assert np.allclose(Kp, p.K[10:18, 6:14], rtol=1e-12)
