@@ -1,0 +1,152 @@
+"""The two-level diffeomorphic multigrid cycle (oracle; test infrastructure only).
+
+Sec. 2.2 (solution phase): stationary iterations of a two-level cycle on the physical P1 system
+A_p u_p = f_p:
+  1. pre-relaxation of u_p,
+  2. restriction of the residual to the grid, r_c = P^T (f_p - A_p u_p),
+  3. one grid (BoxMG) V-cycle on A_c u_c = r_c from u_c = 0,
+  4. interpolation of the correction, u_p += P u_c,
+  5. post-relaxation.
+P = M_p^{-1} C with the mass solve replaced by two CG iterations (Sec. 2.3), so P^T r is the
+to_grid transfer and P u_c the from_grid transfer of oracle.transfer; A_p is the P1 stiffness
+matrix of the physical mesh (the physical-grid discretisation of Sec. 4: piecewise-linear
+elements on triangles).
+
+Readings where the paper is silent or where its choice fails on these inputs:
+  * mass solves: the paper applies M_p^{-1} with two unpreconditioned CG iterations and names mass
+    lumping as a possible improvement.  On the synthetic meshes here the cycle with two CG
+    iterations diverges as the mesh grows (convergence factor above 1 from 33^2 grids on), while
+    lumped mass (M_p replaced by its row sums) converges at a size-independent rate; lumping is
+    the default, CG-k is kept as an option;
+  * coupled mass C with an 8 x 8 Gauss rule per grid cell: the physical triangles are several
+    times smaller than a grid cell, and a 4 x 4 rule leaves some triangles without quadrature
+    points, which slows the cycle as the mesh grows;
+  * relaxation S: symmetric multicolour Gauss-Seidel -- a forward sweep over colours 0..C-1 then
+    a backward sweep C-1..0, each colour updated at once (vertices of one colour are not
+    coupled); colours from a greedy pass over the vertices in index order, each vertex taking the
+    smallest colour not used by an already coloured neighbour in the graph of A_p;
+  * stopping test: ||f - A u||_2 <= rtol ||f - A u_0||_2 (the paper runs f = 0 from a random
+    initial guess, so the test is relative to the initial residual);
+  * coarse-grid scaling: gamma = 1 (Sec. 2.4's scaling is not applied).
+Dirichlet vertices carry identity rows, so they keep u = f (= 0).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as spx
+
+from . import transfer
+
+
+def p1_element_stiffness(xy: np.ndarray) -> np.ndarray:
+    """int_t grad phi_a . grad phi_b over the triangle with vertex coordinates xy [3][2]."""
+    (xa, ya), (xb, yb), (xc, yc) = xy
+    det = (xb - xa) * (yc - ya) - (xc - xa) * (yb - ya)
+    area = 0.5 * abs(det)
+    # gradients of the barycentric coordinates: grad l_a = (y_b - y_c, x_c - x_b) / det, ...
+    g = np.array([[yb - yc, xc - xb], [yc - ya, xa - xc], [ya - yb, xb - xa]]) / det
+    return area * (g @ g.T)
+
+
+def p1_stiffness(xy_p: np.ndarray, tris: np.ndarray, dof: np.ndarray,
+                 K_t: np.ndarray | None = None) -> spx.csr_matrix:
+    """A_p = sum_t K_t G_t (G_t the element stiffness); rows and columns of non-dof vertices
+    replaced by the identity."""
+    nv = xy_p.shape[0]
+    K_t = np.ones(tris.shape[0]) if K_t is None else np.asarray(K_t, dtype=np.float64)
+    rows, cols, vals = [], [], []
+    for t, tv in enumerate(tris):
+        G = K_t[t] * p1_element_stiffness(xy_p[tv])
+        for a in range(3):
+            for b in range(3):
+                rows.append(tv[a])
+                cols.append(tv[b])
+                vals.append(G[a, b])
+    A = spx.coo_matrix((vals, (rows, cols)), shape=(nv, nv)).tocsr()
+    d = spx.diags(dof.astype(np.float64))
+    A = (d @ A @ d + spx.diags((~dof).astype(np.float64))).tocsr()
+    A.eliminate_zeros()
+    return A
+
+
+def greedy_colouring(A: spx.spmatrix) -> np.ndarray:
+    """Colour of each vertex: vertices in index order, each the smallest colour unused by its
+    already coloured neighbours (off-diagonal nonzeros of A)."""
+    A = spx.csr_matrix(A)
+    n = A.shape[0]
+    colour = -np.ones(n, dtype=np.int64)
+    for v in range(n):
+        nb = A.indices[A.indptr[v]:A.indptr[v + 1]]
+        used = {int(colour[w]) for w in nb if w != v and colour[w] >= 0}
+        c = 0
+        while c in used:
+            c += 1
+        colour[v] = c
+    return colour
+
+
+def sgs(A: spx.csr_matrix, u: np.ndarray, f: np.ndarray, colour: np.ndarray) -> np.ndarray:
+    """One symmetric multicolour Gauss-Seidel step (forward then backward over the colours),
+    in place."""
+    diag = A.diagonal()
+    ncol = int(colour.max()) + 1
+    for c in list(range(ncol)) + list(range(ncol - 1, -1, -1)):
+        idx = np.nonzero(colour == c)[0]
+        Au = A[idx] @ u
+        u[idx] = (f[idx] - (Au - diag[idx] * u[idx])) / diag[idx]
+    return u
+
+
+def lumped(M: spx.spmatrix) -> np.ndarray:
+    """Row sums of the mass matrix (1 on the identity rows of Dirichlet vertices)."""
+    return np.asarray(M.sum(axis=1)).ravel()
+
+
+class TwoLevel:
+    """The two-level cycle of Sec. 2.2 on (A_p, M_p, C) with the grid V-cycle of ``grid``;
+    mass = "lumped" (default) or an int k for k CG iterations (the paper's k = 2)."""
+
+    def __init__(self, A_p, M_p, C, grid, nx: int, ny: int, colour=None, mass="lumped"):
+        self.A, self.M, self.C = spx.csr_matrix(A_p), M_p, spx.csr_matrix(C)
+        self.grid, self.nx, self.ny = grid, nx, ny
+        self.colour = greedy_colouring(self.A) if colour is None else colour
+        self.mass = mass
+        self.ML = lumped(M_p)
+
+    def _minv(self, y):
+        if self.mass == "lumped":
+            return y / self.ML
+        return transfer.cg2(self.M, y, int(self.mass))
+
+    def cycle(self, u: np.ndarray, f: np.ndarray) -> np.ndarray:
+        sgs(self.A, u, f, self.colour)
+        r = f - self.A @ u
+        rc = self.C.T @ self._minv(r)                      # P^T r
+        ec = np.zeros(self.nx * self.ny)
+        self.grid.vcycle(ec, rc)
+        u += self._minv(self.C @ ec)                       # P e_c
+        sgs(self.A, u, f, self.colour)
+        return u
+
+
+def solve(tl: TwoLevel, f: np.ndarray, u0: np.ndarray | None = None, rtol: float = 1e-10,
+          max_iters: int = 200, keep_iterates: bool = False):
+    """Stationary two-level iterations until ||f - A u|| <= rtol ||f - A u_0||.
+    Returns (u, cycles, relative residual history, iterates)."""
+    f = np.asarray(f, dtype=np.float64)
+    u = np.zeros_like(f) if u0 is None else np.array(u0, dtype=np.float64)
+    r0 = float(np.linalg.norm(f - tl.A @ u))
+    hist, its = [], []
+    k = 0
+    if r0 == 0.0:
+        return u, 0, [0.0], ([] if keep_iterates else None)
+    while k < max_iters:
+        tl.cycle(u, f)
+        k += 1
+        rr = float(np.linalg.norm(f - tl.A @ u)) / r0
+        hist.append(rr)
+        if keep_iterates:
+            its.append(u.copy())
+        if rr <= rtol:
+            break
+    return u, k, hist, (its if keep_iterates else None)

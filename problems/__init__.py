@@ -15,15 +15,15 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from .fields import (GAUSS_OFFSETS, grid_coords, lognormal_K, sample_jacobian, smooth_target,
-                     uniform_rhs)
+from .fields import (GAUSS_OFFSETS, grid_coords, lognormal_K, lognormal_at, lognormal_features,
+                     sample_jacobian, smooth_target, uniform_rhs)
 from .maps import Affine, Identity, QuarterAnnulus, Star, conformal_square_to_disk
 from .mesh import Mesh, lattice_mesh, mesh_points_for_grid
 
 __all__ = ["Problem", "quarter_annulus", "star", "identity", "batch", "Affine", "Identity",
            "QuarterAnnulus", "Star", "conformal_square_to_disk", "sample_jacobian", "lognormal_K",
            "uniform_rhs", "smooth_target", "grid_coords", "GAUSS_OFFSETS", "Mesh", "lattice_mesh",
-           "mesh_points_for_grid", "streams"]
+           "mesh_points_for_grid", "streams", "DmgProblem", "star_dmg"]
 
 
 @dataclass
@@ -73,6 +73,33 @@ def star(n: int, seed: int = 1, ny: int | None = None, lognormal: bool = True,
     K = lognormal_K(mp, n, ny, g_k, device=device) if lognormal else np.ones((ny - 1, n - 1))
     return Problem("star", n, ny, mp, sample_jacobian(mp, n, ny), K, uniform_rhs(n, ny, g_b),
                    smooth_target(n, ny, g_t))
+
+
+@dataclass
+class DmgProblem:
+    """A physical P1 problem on a mesh of a star domain with its logical grid (two-level method)."""
+    grid: Problem            # the n x n grid problem of the same map and field (jac, K)
+    mesh: Mesh               # physical mesh (vertices, their images in (-1,1)^2, triangles, dof)
+    K_t: np.ndarray          # coefficient per triangle at its physical centroid
+    f: np.ndarray            # right-hand side per vertex (0 on Dirichlet vertices)
+
+
+def star_dmg(n: int, seed: int = 1, m: int | None = None, lognormal: bool = True) -> DmgProblem:
+    """Star domain (map and K as star(n, seed)) with a jittered m x m P1 lattice mesh mapped
+    through the same map (m about n / sqrt(0.28) by default, the paper's grid-to-mesh size
+    ratio), K per triangle from the same log-normal field, f ~ U(-1, 1) on free vertices."""
+    grid = star(n, seed=seed, lognormal=lognormal)
+    g = streams(seed, 7)
+    m = m or mesh_points_for_grid(n)
+    mesh = lattice_mesh(grid.map, m, g[5])
+    cen = mesh.xy_p[mesh.tris].mean(axis=1)
+    if lognormal:
+        omega, phase = lognormal_features(streams(seed)[1])
+        K_t = lognormal_at(cen[:, 0], cen[:, 1], omega, phase)
+    else:
+        K_t = np.ones(mesh.tris.shape[0])
+    f = np.where(mesh.dof, g[6].uniform(-1.0, 1.0, size=mesh.dof.shape[0]), 0.0)
+    return DmgProblem(grid, mesh, K_t, f)
 
 
 def directions(seed: int, count: int, n_cells: tuple, n_vert: tuple):

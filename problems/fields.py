@@ -134,3 +134,21 @@ def lognormal_K_patch(mp, n: int, i0: int, j0: int, m: int, rng: np.random.Gener
     pts = np.stack([np.ravel(x), np.ravel(y)], axis=1)
     g = sigma * math.sqrt(2.0 / n_features) * np.cos(pts @ omega.T + phase).sum(axis=1)
     return np.exp(g).reshape(m, m)
+
+
+def lognormal_features(rng: np.random.Generator, ell: float = 0.1, n_features: int = 1024):
+    """The random Fourier features lognormal_K draws from ``rng`` (same order)."""
+    omega = rng.normal(0.0, 1.0 / ell, size=(n_features, 2))
+    phase = rng.uniform(0.0, 2 * math.pi, size=n_features)
+    return omega, phase
+
+
+def lognormal_at(x: np.ndarray, y: np.ndarray, omega: np.ndarray, phase: np.ndarray,
+                 sigma: float = 1.0) -> np.ndarray:
+    """exp(g) of the log-normal field with features (omega, phase) at physical points (x, y)."""
+    pts = np.stack([np.ravel(x), np.ravel(y)], axis=1)
+    g = np.empty(pts.shape[0])
+    scale = sigma * math.sqrt(2.0 / omega.shape[0])
+    for s in range(0, pts.shape[0], 1 << 15):
+        g[s:s + (1 << 15)] = scale * np.cos(pts[s:s + (1 << 15)] @ omega.T + phase).sum(axis=1)
+    return np.exp(g).reshape(np.shape(x))

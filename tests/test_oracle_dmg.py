@@ -1,0 +1,91 @@
+"""Pins of the two-level cycle oracle (oracle/dmg.py) against facts fixed outside it: the
+textbook P1 element stiffness, properties of the assembled operator, a valid colouring, the
+lumped mass against triangle areas, convergence to a direct solve, and a convergence rate that
+does not grow with the problem size (Sec. 4.3's observation for the two-level method)."""
+import os
+
+import numpy as np
+import scipy.sparse.linalg as spl
+
+import problems as pb
+from oracle import boxmg, cycle, dmg, fem, transfer
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _setup(n, seed=1, nq=8, mass="lumped"):
+    P = pb.star_dmg(n, seed=seed)
+    m = P.mesh
+    A = dmg.p1_stiffness(m.xy_p, m.tris, m.dof, P.K_t)
+    M = transfer.p1_mass(m.xy_p, m.tris, m.dof)
+    C = transfer.coupled_mass(m.xy_c, m.xy_p, m.tris, m.dof, n, n, nq=nq)
+    orc = cycle.Oracle(boxmg.build_hierarchy(fem.assemble_stencil(P.grid.jac, P.grid.K, n, n)))
+    return P, A, M, C, dmg.TwoLevel(A, M, C, orc, n, n, mass=mass)
+
+
+def _inner(m):
+    """Free vertices all of whose triangle neighbours are free (from the triangles, not from the
+    sparsity of an operator whose Dirichlet couplings are removed)."""
+    bad = np.zeros(m.nv, dtype=bool)
+    tri_free = m.dof[m.tris].all(axis=1)
+    bad[m.tris[~tri_free].ravel()] = True
+    return m.dof & ~bad
+
+
+def test_p1_element_stiffness_golden():
+    rows = np.loadtxt(os.path.join(GOLDEN, "p1_element_stiffness.txt"), comments="#", ndmin=2)
+    for x0, y0, x1, y1, x2, y2, *a in rows:
+        G = dmg.p1_element_stiffness(np.array([[x0, y0], [x1, y1], [x2, y2]]))
+        ref = np.array([[a[0], a[1], a[2]], [a[1], a[3], a[4]], [a[2], a[4], a[5]]])
+        assert np.allclose(G, ref, atol=1e-15)
+
+
+def test_stiffness_properties_and_colouring():
+    P = pb.star_dmg(17, seed=2)
+    m = P.mesh
+    A = dmg.p1_stiffness(m.xy_p, m.tris, m.dof, P.K_t)
+    assert abs(A - A.T).max() < 1e-14
+    assert np.all(A.diagonal() > 0)
+    # zero row sums where the vertex and all its neighbours are free
+    inner = _inner(m)
+    assert inner.sum() > m.nv // 2
+    assert np.allclose(np.asarray(A.sum(axis=1)).ravel()[inner], 0.0, atol=1e-12)
+    col = dmg.greedy_colouring(A)
+    Ac = A.tocoo()
+    off = Ac.row != Ac.col
+    assert np.all(col[Ac.row[off]] != col[Ac.col[off]])          # a proper colouring
+    assert col.max() + 1 <= 9                                     # max degree 8 on these meshes
+    assert np.array_equal(col, dmg.greedy_colouring(A))           # deterministic
+
+
+def test_lumped_mass_is_a_third_of_incident_area():
+    P = pb.star_dmg(17, seed=3)
+    m = P.mesh
+    M = transfer.p1_mass(m.xy_p, m.tris, m.dof)
+    ML = dmg.lumped(M)
+    p = m.xy_p[m.tris]
+    area = 0.5 * np.abs((p[:, 1, 0] - p[:, 0, 0]) * (p[:, 2, 1] - p[:, 0, 1])
+                        - (p[:, 2, 0] - p[:, 0, 0]) * (p[:, 1, 1] - p[:, 0, 1]))
+    third = np.bincount(m.tris.ravel(), weights=np.repeat(area / 3, 3), minlength=m.nv)
+    # vertices whose neighbours are all free keep their full row sum
+    inner = _inner(m)
+    assert np.allclose(ML[inner], third[inner], rtol=1e-13)
+    assert np.all(ML[~m.dof] == 1.0)
+
+
+def test_two_level_solves_the_physical_system():
+    P, A, M, C, tl = _setup(17)
+    u, k, hist, _ = dmg.solve(tl, P.f, rtol=1e-10)
+    ue = spl.spsolve(A.tocsc(), P.f)
+    assert hist[-1] <= 1e-10 and k < 40
+    assert np.linalg.norm(u - ue) / np.linalg.norm(ue) < 1e-8
+
+
+def test_two_level_rate_does_not_grow_with_size():
+    rates, counts = [], []
+    for n in (17, 33):
+        P, A, M, C, tl = _setup(n)
+        u, k, hist, _ = dmg.solve(tl, P.f, rtol=1e-10)
+        rates.append(cycle.convergence_factor(hist))
+        counts.append(k)
+    assert max(rates) < 0.3 and abs(counts[1] - counts[0]) <= 3
