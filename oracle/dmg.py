@@ -24,7 +24,10 @@ Readings where the paper is silent or where its choice fails on these inputs:
   * relaxation S: symmetric multicolour Gauss-Seidel -- a forward sweep over colours 0..C-1 then
     a backward sweep C-1..0, each colour updated at once (vertices of one colour are not
     coupled); colours from a greedy pass over the vertices in index order, each vertex taking the
-    smallest colour not used by an already coloured neighbour in the graph of A_p;
+    smallest colour not used by an already coloured neighbour in the mesh graph (two unknowns
+    are neighbours when they share a triangle; Dirichlet vertices have none).  The mesh graph
+    holds the pattern of A_p, and unlike the numerical pattern it does not depend on whether a
+    coupling cancels to exactly zero (right angles opposite an edge do that);
   * stopping test: ||f - A u||_2 <= rtol ||f - A u_0||_2 (the paper runs f = 0 from a random
     initial guess, so the test is relative to the initial residual);
   * coarse-grid scaling: gamma = 1 (Sec. 2.4's scaling is not applied).
@@ -69,9 +72,30 @@ def p1_stiffness(xy_p: np.ndarray, tris: np.ndarray, dof: np.ndarray,
     return A
 
 
+def mesh_graph(tris: np.ndarray, dof: np.ndarray) -> spx.csr_matrix:
+    """Pattern of the unknowns' couplings: v ~ w when v != w share a triangle and both are
+    unknowns (dof); Dirichlet vertices are isolated."""
+    nv = dof.shape[0]
+    rows, cols = [], []
+    for tv in tris:
+        for a in range(3):
+            for b in range(3):
+                if a != b and dof[tv[a]] and dof[tv[b]]:
+                    rows.append(tv[a])
+                    cols.append(tv[b])
+    G = spx.coo_matrix((np.ones(len(rows)), (rows, cols)), shape=(nv, nv)).tocsr()
+    G.sum_duplicates()
+    return G
+
+
+def mesh_colouring(tris: np.ndarray, dof: np.ndarray) -> np.ndarray:
+    """Greedy colouring of the mesh graph (the relaxation's colours)."""
+    return greedy_colouring(mesh_graph(tris, dof))
+
+
 def greedy_colouring(A: spx.spmatrix) -> np.ndarray:
     """Colour of each vertex: vertices in index order, each the smallest colour unused by its
-    already coloured neighbours (off-diagonal nonzeros of A)."""
+    already coloured neighbours (off-diagonal entries of the pattern of A)."""
     A = spx.csr_matrix(A)
     n = A.shape[0]
     colour = -np.ones(n, dtype=np.int64)
@@ -104,12 +128,13 @@ def lumped(M: spx.spmatrix) -> np.ndarray:
 
 class TwoLevel:
     """The two-level cycle of Sec. 2.2 on (A_p, M_p, C) with the grid V-cycle of ``grid``;
-    mass = "lumped" (default) or an int k for k CG iterations (the paper's k = 2)."""
+    colour: the relaxation colours (mesh_colouring of the mesh); mass = "lumped" (default) or an
+    int k for k CG iterations (the paper's k = 2)."""
 
-    def __init__(self, A_p, M_p, C, grid, nx: int, ny: int, colour=None, mass="lumped"):
+    def __init__(self, A_p, M_p, C, grid, nx: int, ny: int, colour, mass="lumped"):
         self.A, self.M, self.C = spx.csr_matrix(A_p), M_p, spx.csr_matrix(C)
         self.grid, self.nx, self.ny = grid, nx, ny
-        self.colour = greedy_colouring(self.A) if colour is None else colour
+        self.colour = np.asarray(colour)
         self.mass = mass
         self.ML = lumped(M_p)
 

@@ -5,6 +5,7 @@ does not grow with the problem size (Sec. 4.3's observation for the two-level me
 import os
 
 import numpy as np
+import scipy.sparse as spx
 import scipy.sparse.linalg as spl
 
 import problems as pb
@@ -20,7 +21,7 @@ def _setup(n, seed=1, nq=8, mass="lumped"):
     M = transfer.p1_mass(m.xy_p, m.tris, m.dof)
     C = transfer.coupled_mass(m.xy_c, m.xy_p, m.tris, m.dof, n, n, nq=nq)
     orc = cycle.Oracle(boxmg.build_hierarchy(fem.assemble_stencil(P.grid.jac, P.grid.K, n, n)))
-    return P, A, M, C, dmg.TwoLevel(A, M, C, orc, n, n, mass=mass)
+    return P, A, M, C, dmg.TwoLevel(A, M, C, orc, n, n, dmg.mesh_colouring(m.tris, m.dof), mass=mass)
 
 
 def _inner(m):
@@ -50,12 +51,22 @@ def test_stiffness_properties_and_colouring():
     inner = _inner(m)
     assert inner.sum() > m.nv // 2
     assert np.allclose(np.asarray(A.sum(axis=1)).ravel()[inner], 0.0, atol=1e-12)
-    col = dmg.greedy_colouring(A)
+    col = dmg.mesh_colouring(m.tris, m.dof)
     Ac = A.tocoo()
     off = Ac.row != Ac.col
-    assert np.all(col[Ac.row[off]] != col[Ac.col[off]])          # a proper colouring
+    assert np.all(col[Ac.row[off]] != col[Ac.col[off]])          # a proper colouring of A_p
+    G = dmg.mesh_graph(m.tris, m.dof)
+    assert abs(G - G.T).max() == 0 and G.diagonal().sum() == 0
+    # every coupling of A_p is a mesh edge, and every mesh edge a coupling (no cancellation here)
+    Gp = (abs(A) > 0).astype(float) - spx.eye(m.nv)
+    assert abs((Gp != 0).astype(float) - (G != 0).astype(float)).max() == 0
     assert col.max() + 1 <= 9                                     # max degree 8 on these meshes
-    assert np.array_equal(col, dmg.greedy_colouring(A))           # deterministic
+    assert np.all(col[~m.dof] == 0)                               # isolated Dirichlet vertices
+    # greedy: each vertex takes the smallest colour unused by its earlier neighbours
+    for v in range(0, m.nv, 7):
+        nb = G.indices[G.indptr[v]:G.indptr[v + 1]]
+        used = set(col[nb[nb < v]].tolist())
+        assert col[v] == min(set(range(10)) - used)
 
 
 def test_lumped_mass_is_a_third_of_incident_area():
