@@ -81,6 +81,7 @@ typedef struct dmg_options {
 typedef struct dmg_hier dmg_hier;
 typedef struct dmg_transfer dmg_transfer;
 typedef struct dmg_batch dmg_batch;
+typedef struct dmg_twolevel dmg_twolevel;
 
 void dmg_default_options(dmg_options* opts);
 const char* dmg_last_error(void);
@@ -228,6 +229,42 @@ dmg_status dmg_batch_solve(dmg_batch* bt, double* const* u, const double* const*
 dmg_status dmg_batch_autotune(dmg_batch* bt, double* const* u, const double* const* b,
                               int32_t reps, hipStream_t stream);
 void dmg_batch_destroy(dmg_batch* bt);
+
+/* ---- the two-level cycle on the physical mesh (Sec. 2.2, solution phase) -----------------
+ * Solves A_p u_p = f_p, A_p the P1 stiffness of the physical mesh (element matrices K_t G_t on
+ * the physical triangles, Dirichlet rows and columns replaced by the identity), with stationary
+ * cycles: a symmetric multicolour Gauss-Seidel sweep, r_c = C^T M^{-1} (f_p - A_p u_p), one
+ * float64 V-cycle of `grid` on A_c e_c = r_c from e_c = 0, u_p += M^{-1} C e_c, a second
+ * symmetric sweep.  M^{-1} is mass = 0: the lumped mass (row sums of M_p), or mass = 2: two CG
+ * iterations on M_p (Sec. 2.3).  Colours: greedy over the vertices in index order on the mesh
+ * graph (unknowns sharing a triangle are neighbours; Dirichlet vertices have none, colour 0);
+ * the symmetric sweep updates colours 0..C-1 then C-2..0.
+ * Create: mesh arrays on the HOST as for dmg_transfer_create; K_t [nt] host coefficient per
+ * triangle (null: 1); grid: a hierarchy built on the nx x ny grid that C maps to (its level-0
+ * dims), borrowed -- it must outlive the handle, and no other call may use it while a cycle or
+ * solve of this handle runs.  The handle owns device memory allocated here; cycle and solve
+ * allocate nothing.  DMG_ERR_INVALID_ARG for a degenerate physical triangle or a non-positive
+ * diagonal of A_p.
+ * info: number of colours, stored entries of A_p (nullable outputs); colour (nullable, host
+ * [nv]) receives each vertex's colour.
+ * cycle: one cycle on u_p [nv] (device, in/out) for f_p [nv] (device).
+ * solve: cycles from u_p until ||f - A u|| <= rtol ||f - A u_0|| or max_iters; a zero initial
+ * residual returns at once with iters = 0 and relres = 0.  history (host, nullable,
+ * >= max_iters entries) receives ||f - A u_k|| / ||f - A u_0||.  Chunks of four cycles run in
+ * one captured hipGraph (when `stream` is not the legacy default stream).  Returns
+ * DMG_ERR_NO_CONVERGENCE or DMG_ERR_NONFINITE with u_p holding the last iterate. */
+dmg_status dmg_twolevel_create(int32_t nv, int32_t nt, const double* xy_c, const double* xy_p,
+                               const int32_t* tris, const uint8_t* dof, const double* K_t,
+                               dmg_hier* grid, int32_t nq, int32_t mass, hipStream_t stream,
+                               dmg_twolevel** out);
+dmg_status dmg_twolevel_info(const dmg_twolevel* tl, int32_t* colours, int64_t* nnz_A,
+                             int32_t* colour);
+dmg_status dmg_twolevel_cycle(dmg_twolevel* tl, double* u_p, const double* f_p,
+                              hipStream_t stream);
+dmg_status dmg_twolevel_solve(dmg_twolevel* tl, double* u_p, const double* f_p, double rtol,
+                              int32_t max_iters, int32_t* iters, double* relres, double* history,
+                              hipStream_t stream);
+void dmg_twolevel_destroy(dmg_twolevel* tl);
 
 #ifdef __cplusplus
 }

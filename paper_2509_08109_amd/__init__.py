@@ -18,7 +18,7 @@ import torch
 from . import _lib
 from ._lib import DMG_FP32_IR, DMG_FP64, DmgError, Options, default_options
 
-__all__ = ["Hierarchy", "assemble_stencil", "grad_K", "Transfer", "BatchSolver", "DiffSolve",
+__all__ = ["Hierarchy", "assemble_stencil", "grad_K", "Transfer", "TwoLevel", "BatchSolver", "DiffSolve",
            "default_options", "Options", "DmgError", "DMG_FP64", "DMG_FP32_IR", "lib", "version"]
 
 
@@ -243,6 +243,78 @@ class Transfer:
     def close(self):
         if getattr(self, "_h", None):
             lib().dmg_transfer_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class TwoLevel:
+    """The two-level cycle on a physical P1 mesh (host mesh arrays) over the grid hierarchy
+    ``grid`` (a Hierarchy on the grid that the mesh maps to; it must outlive this object).
+    mass: "lumped" or "cg2"."""
+
+    def __init__(self, grid: Hierarchy, xy_c, xy_p, tris, dof, K_t=None, nq: int = 8, mass: str = "lumped"):
+        if mass not in ("lumped", "cg2"):
+            raise ValueError("mass must be 'lumped' or 'cg2'")
+        self.grid = grid
+        self.device = grid.device
+        xy_c = np.ascontiguousarray(xy_c, dtype=np.float64)
+        xy_p = np.ascontiguousarray(xy_p, dtype=np.float64)
+        tris = np.ascontiguousarray(tris, dtype=np.int32)
+        dof = np.ascontiguousarray(dof, dtype=np.uint8)
+        self.nv, self.nt = xy_c.shape[0], tris.shape[0]
+        if xy_c.shape != (self.nv, 2) or xy_p.shape != (self.nv, 2) or tris.shape != (self.nt, 3) \
+                or dof.shape != (self.nv,):
+            raise ValueError("mesh arrays have inconsistent shapes")
+        kt = None
+        if K_t is not None:
+            kt = np.ascontiguousarray(K_t, dtype=np.float64)
+            if kt.shape != (self.nt,):
+                raise ValueError("K_t must hold one value per triangle")
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _lib.check(lib().dmg_twolevel_create(self.nv, self.nt, xy_c.ctypes.data, xy_p.ctypes.data,
+                                                 tris.ctypes.data, dof.ctypes.data,
+                                                 None if kt is None else kt.ctypes.data, grid._h, nq,
+                                                 0 if mass == "lumped" else 2, _stream(self.device),
+                                                 C.byref(h)))
+        self._h = h
+
+    def info(self):
+        """(number of colours, stored entries of A_p, colour of each vertex)."""
+        nc, nnz = C.c_int32(), C.c_int64()
+        col = np.empty(self.nv, dtype=np.int32)
+        _lib.check(lib().dmg_twolevel_info(self._h, C.byref(nc), C.byref(nnz), col.ctypes.data))
+        return int(nc.value), int(nnz.value), col
+
+    def cycle(self, u: torch.Tensor, f: torch.Tensor) -> torch.Tensor:
+        """One cycle on u (in place)."""
+        _lib.check(lib().dmg_twolevel_cycle(self._h, _dev(u, (self.nv,), "u"), _dev(f, (self.nv,), "f"),
+                                            _stream(self.device)))
+        return u
+
+    def solve(self, f: torch.Tensor, u: torch.Tensor | None = None, rtol: float = 1e-10,
+              max_iters: int = 200, raise_on_fail: bool = True):
+        """Cycles from u (default zeros) until ||f - A u|| <= rtol ||f - A u_0||;
+        returns (u, cycles, relres, history)."""
+        if u is None:
+            u = torch.zeros(self.nv, dtype=torch.float64, device=self.device)
+        hist = (C.c_double * max(1, max_iters))()
+        it, rr = C.c_int32(), C.c_double()
+        st = lib().dmg_twolevel_solve(self._h, _dev(u, (self.nv,), "u"), _dev(f, (self.nv,), "f"), float(rtol),
+                                      int(max_iters), C.byref(it), C.byref(rr), hist, _stream(self.device))
+        if st != 0 and (raise_on_fail or st != 6):
+            _lib.check(st)
+        k = int(it.value)
+        return u, k, float(rr.value), [hist[i] for i in range(k)]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().dmg_twolevel_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -547,6 +547,12 @@ dmg_status setup_impl(dmg_hier* h, const double* S, hipStream_t s) {
 }
 
 }  // namespace
+
+dmg_status grid_vcycle(dmg_hier* h, double* u, const double* b, bool u_zero, const int* stop,
+                       hipStream_t s) {
+  return vcycle_impl<double>(h, u, b, s, nullptr, u_zero, stop);
+}
+
 }  // namespace dmg
 
 dmg_hier::~dmg_hier() {

@@ -319,4 +319,9 @@ dmg_status launch_resid_multi(const NormArgs* list, int count, int blocks_per, h
 dmg_status launch_check_step(const double* partials, int count, double* out, const double* sc,
                              int* st, double* hist, int hist_cap, hipStream_t s);
 
+// One float64 V-cycle of hierarchy h on level-0 arrays (u, b); u_zero: start from u = 0
+// without reading u.  Every kernel is a no-op once *stop (nullable) is set.
+dmg_status grid_vcycle(dmg_hier* h, double* u, const double* b, bool u_zero, const int* stop,
+                       hipStream_t s);
+
 }  // namespace dmg

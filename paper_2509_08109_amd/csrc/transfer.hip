@@ -18,31 +18,10 @@
 #include <thread>
 #include <unordered_map>
 
-#include "dmg_internal.h"
-
-struct dmg_transfer {
-  int nv = 0, nx = 0, ny = 0;
-  int64_t nnzC = 0, nnzM = 0;
-  int *Crp = nullptr, *Cci = nullptr, *CTrp = nullptr, *CTci = nullptr, *Mrp = nullptr,
-      *Mci = nullptr;
-  double *Cv = nullptr, *CTv = nullptr, *Mv = nullptr;
-  unsigned char* dof = nullptr;  // internal order
-  int* perm = nullptr;           // internal row i holds the caller's vertex perm[i]
-  double *x = nullptr, *r = nullptr, *p = nullptr, *q = nullptr;
-  double *partials = nullptr, *scal = nullptr;
-  void* block = nullptr;
-  ~dmg_transfer() {
-    if (block) (void)hipFree(block);
-  }
-};
+#include "mesh_internal.h"
 
 namespace dmg {
 namespace {
-
-struct Csr {
-  std::vector<int> rp, ci;
-  std::vector<double> v;
-};
 
 void gauss01(int nq, std::vector<double>& x, std::vector<double>& w) {
   // Gauss-Legendre nodes on [-1,1] by Newton iteration on P_nq, mapped to [0,1].
@@ -89,13 +68,7 @@ Csr merge(int n, const std::vector<Csr>& parts, const std::vector<int>& first_ro
   return out;
 }
 
-struct Mesh {
-  int nv, nt;
-  const double *xy_c, *xy_p;
-  const int* tris;
-  const uint8_t* dof;
-  std::vector<int> vt_ptr, vt;  // vertex -> incident triangles
-};
+}  // namespace
 
 void build_adjacency(Mesh& m) {
   m.vt_ptr.assign(m.nv + 1, 0);
@@ -114,6 +87,8 @@ double tri_area2(const double* xy, const int* tv) {
   const double* c = xy + 2 * tv[2];
   return (b[0] - a[0]) * (c[1] - a[1]) - (c[0] - a[0]) * (b[1] - a[1]);
 }
+
+namespace {
 
 Csr assemble_C(const Mesh& m, int nx, int ny, int nq) {
   std::vector<double> qx, qw;
@@ -243,42 +218,8 @@ Csr transpose(const Csr& a, int ncols) {
 }
 
 // ---- device kernels ----------------------------------------------------------------------
-__device__ __forceinline__ double block_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  __shared__ double ws[4];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  __syncthreads();  // earlier readers of ws (a previous call) are done
-  if (lane == 0) ws[wid] = v;
-  __syncthreads();
-  double t = 0.0;
-  if (threadIdx.x == 0) t = ((ws[0] + ws[1]) + ws[2]) + ws[3];
-  return t;
-}
-
-// Row products run on groups of G consecutive lanes (G divides 64): lane l of a group reads
-// entries rp[r] + l, rp[r] + l + G, ... (coalesced), and the group sums its lanes with xor
-// shuffles in a fixed order.  Kernels walk row groups grid-stride; kernels that reduce write one
-// partial per workgroup.
-constexpr int kTBlocks = 4096;  // workgroup cap of the transfer kernels (= partials capacity)
-constexpr int kMG = 4;  // lanes per mesh row (rows of C and M_p hold ~7-9 entries; 4 measured best)
-constexpr int kCG = 8;  // lanes per grid row of C^T (~30 entries; 8 measured best)
-
-int tblocks(int n, int lanes) {
-  const long b = (long(n) * lanes + 255) / 256;
-  return int(std::max(1l, std::min(b, long(kTBlocks))));
-}
-
-template <int G, class X>
-__device__ __forceinline__ double row_dot(const int* __restrict__ rp, const int* __restrict__ ci,
-                                          const double* __restrict__ v, int r, int lane, X&& x) {
-  const int e = rp[r + 1];
-  double acc = 0.0;
-  for (int k = rp[r] + lane; k < e; k += G) acc = __builtin_fma(v[k], x(ci[k]), acc);
-#pragma unroll
-  for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
-  return acc;
-}
+// stop (nullable): the kernel does nothing once the device flag is set.
+__device__ __forceinline__ bool stopped(const int* stop) { return stop && *stop; }
 
 // from_grid start: r0 = dof * (C u_c) (mesh rows in the internal order); partials of r0.r0
 __global__ __launch_bounds__(256) void k_t_init_from(const int* __restrict__ rp,
@@ -287,7 +228,9 @@ __global__ __launch_bounds__(256) void k_t_init_from(const int* __restrict__ rp,
                                                      const double* __restrict__ u_c,
                                                      const unsigned char* __restrict__ dof,
                                                      double* __restrict__ r0, int n,
-                                                     double* __restrict__ partials) {
+                                                     double* __restrict__ partials,
+                                                     const int* __restrict__ stop) {
+  if (stopped(stop)) return;
   const int lane = threadIdx.x & (kMG - 1);
   const int g0 = int((blockIdx.x * 256u + threadIdx.x) / kMG), ng = int(gridDim.x * 256u / kMG);
   double acc = 0.0;
@@ -299,7 +242,7 @@ __global__ __launch_bounds__(256) void k_t_init_from(const int* __restrict__ rp,
       acc += val * val;
     }
   }
-  const double t = block_sum(acc);
+  const double t = mesh_block_sum(acc);
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
@@ -315,7 +258,7 @@ __global__ __launch_bounds__(256) void k_t_init_to(const double* __restrict__ r_
     r0[r] = val;
     acc += val * val;
   }
-  const double t = block_sum(acc);
+  const double t = mesh_block_sum(acc);
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
@@ -323,7 +266,9 @@ __global__ __launch_bounds__(256) void k_t_init_to(const double* __restrict__ r_
 __global__ __launch_bounds__(256) void k_t_mq(const int* __restrict__ rp, const int* __restrict__ ci,
                                               const double* __restrict__ v,
                                               const double* __restrict__ p, double* __restrict__ q,
-                                              int n, double* __restrict__ partials) {
+                                              int n, double* __restrict__ partials,
+                                              const int* __restrict__ stop) {
+  if (stopped(stop)) return;
   const int lane = threadIdx.x & (kMG - 1);
   const int g0 = int((blockIdx.x * 256u + threadIdx.x) / kMG), ng = int(gridDim.x * 256u / kMG);
   double acc = 0.0;
@@ -334,7 +279,7 @@ __global__ __launch_bounds__(256) void k_t_mq(const int* __restrict__ rp, const 
       acc += p[r] * s;
     }
   }
-  const double t = block_sum(acc);
+  const double t = mesh_block_sum(acc);
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
@@ -348,7 +293,9 @@ __global__ __launch_bounds__(256) void k_t_r1(const double* __restrict__ r0,
                                               const double* __restrict__ q0,
                                               double* __restrict__ r1,
                                               const double* __restrict__ sc, int n,
-                                              double* __restrict__ partials) {
+                                              double* __restrict__ partials,
+                                              const int* __restrict__ stop) {
+  if (stopped(stop)) return;
   const double alpha = cg_alpha0(sc);
   double acc = 0.0;
   for (int r = blockIdx.x * 256 + threadIdx.x; r < n; r += gridDim.x * 256) {
@@ -356,7 +303,7 @@ __global__ __launch_bounds__(256) void k_t_r1(const double* __restrict__ r0,
     r1[r] = rv;
     acc += rv * rv;
   }
-  const double t = block_sum(acc);
+  const double t = mesh_block_sum(acc);
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
@@ -366,7 +313,9 @@ __global__ __launch_bounds__(256) void k_t_mp1(const int* __restrict__ rp, const
                                                const double* __restrict__ r0,
                                                const double* __restrict__ r1,
                                                const double* __restrict__ sc, int n,
-                                               double* __restrict__ partials) {
+                                               double* __restrict__ partials,
+                                               const int* __restrict__ stop) {
+  if (stopped(stop)) return;
   const double beta = cg_beta(sc);
   const int lane = threadIdx.x & (kMG - 1);
   const int g0 = int((blockIdx.x * 256u + threadIdx.x) / kMG), ng = int(gridDim.x * 256u / kMG);
@@ -376,24 +325,28 @@ __global__ __launch_bounds__(256) void k_t_mp1(const int* __restrict__ rp, const
                                   [&](int c) { return __builtin_fma(beta, r0[c], r1[c]); });
     if (lane == 0) acc += __builtin_fma(beta, r0[r], r1[r]) * s;
   }
-  const double t = block_sum(acc);
+  const double t = mesh_block_sum(acc);
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
-// x2 = alpha0 r0 + alpha1 p1; from_grid writes it in the caller's vertex order (out[perm[r]]),
-// to_grid keeps the internal order for C^T
-template <bool SCATTER>
+// x2 = alpha0 r0 + alpha1 p1, stored in the internal order, scattered to the caller's order
+// (out[perm[r]]), or added into an internal-order vector
+template <X2Mode MODE>
 __global__ __launch_bounds__(256) void k_t_x(const double* __restrict__ r0,
                                              const double* __restrict__ r1,
                                              const double* __restrict__ sc,
                                              const int* __restrict__ perm,
-                                             double* __restrict__ out, int n) {
+                                             double* __restrict__ out, int n,
+                                             const int* __restrict__ stop) {
+  if (stopped(stop)) return;
   const double alpha0 = cg_alpha0(sc), beta = cg_beta(sc), alpha1 = cg_alpha1(sc);
   for (int r = blockIdx.x * 256 + threadIdx.x; r < n; r += gridDim.x * 256) {
     const double x1 = alpha0 * r0[r];
     const double p1 = __builtin_fma(beta, r0[r], r1[r]);
     const double x2 = __builtin_fma(alpha1, p1, x1);
-    out[SCATTER ? perm[r] : r] = x2;
+    if constexpr (MODE == X2Mode::kScatter) out[perm[r]] = x2;
+    else if constexpr (MODE == X2Mode::kAdd) out[r] += x2;
+    else out[r] = x2;
   }
 }
 
@@ -401,7 +354,9 @@ __global__ __launch_bounds__(256) void k_t_x(const double* __restrict__ r0,
 __global__ __launch_bounds__(256) void k_t_ct(const int* __restrict__ rp, const int* __restrict__ ci,
                                               const double* __restrict__ v,
                                               const double* __restrict__ x,
-                                              double* __restrict__ out, int n) {
+                                              double* __restrict__ out, int n,
+                                              const int* __restrict__ stop) {
+  if (stopped(stop)) return;
   const int lane = threadIdx.x & (kCG - 1);
   const int g0 = int((blockIdx.x * 256u + threadIdx.x) / kCG), ng = int(gridDim.x * 256u / kCG);
   for (int r = g0; r < n; r += ng) {
@@ -410,26 +365,45 @@ __global__ __launch_bounds__(256) void k_t_ct(const int* __restrict__ rp, const 
   }
 }
 
-// Two CG iterations from x = 0 on M_p, continuing from r0 (already in t->r with its partials):
-// leaves x2 = CG2(M_p, r0) in `out` (scattered to the caller's order when `scatter`).
-dmg_status cg2_tail(dmg_transfer* t, double* out, bool scatter, hipStream_t s) {
+}  // namespace
+
+dmg_status launch_from_start(dmg_transfer* t, const double* u_c, const int* stop, hipStream_t s) {
+  k_t_init_from<<<tblocks(t->nv, kMG), 256, 0, s>>>(t->Crp, t->Cci, t->Cv, u_c, t->dof, t->r,
+                                                     t->nv, t->partials, stop);
+  return launch_check("transfer C u");
+}
+
+dmg_status cg2_tail(dmg_transfer* t, double* out, X2Mode mode, const int* stop, hipStream_t s) {
   const int n = t->nv, nb = tblocks(n, kMG);
   double* sc = t->scal;
   DMG_CHECK(launch_finalize(t->partials, sc + 0, s, nb));
-  k_t_mq<<<nb, 256, 0, s>>>(t->Mrp, t->Mci, t->Mv, t->r, t->q, n, t->partials);
+  k_t_mq<<<nb, 256, 0, s>>>(t->Mrp, t->Mci, t->Mv, t->r, t->q, n, t->partials, stop);
   DMG_CHECK(launch_check("transfer M r0"));
   DMG_CHECK(launch_finalize(t->partials, sc + 2, s, nb));
-  k_t_r1<<<nb, 256, 0, s>>>(t->r, t->q, t->p, sc, n, t->partials);
+  k_t_r1<<<nb, 256, 0, s>>>(t->r, t->q, t->p, sc, n, t->partials, stop);
   DMG_CHECK(launch_check("transfer r1"));
   DMG_CHECK(launch_finalize(t->partials, sc + 4, s, nb));
-  k_t_mp1<<<nb, 256, 0, s>>>(t->Mrp, t->Mci, t->Mv, t->r, t->p, sc, n, t->partials);
+  k_t_mp1<<<nb, 256, 0, s>>>(t->Mrp, t->Mci, t->Mv, t->r, t->p, sc, n, t->partials, stop);
   DMG_CHECK(launch_check("transfer M p1"));
   DMG_CHECK(launch_finalize(t->partials, sc + 6, s, nb));
-  if (scatter)
-    k_t_x<true><<<nb, 256, 0, s>>>(t->r, t->p, sc, t->perm, out, n);
-  else
-    k_t_x<false><<<nb, 256, 0, s>>>(t->r, t->p, sc, t->perm, out, n);
+  switch (mode) {
+    case X2Mode::kStore:
+      k_t_x<X2Mode::kStore><<<nb, 256, 0, s>>>(t->r, t->p, sc, t->perm, out, n, stop);
+      break;
+    case X2Mode::kScatter:
+      k_t_x<X2Mode::kScatter><<<nb, 256, 0, s>>>(t->r, t->p, sc, t->perm, out, n, stop);
+      break;
+    case X2Mode::kAdd:
+      k_t_x<X2Mode::kAdd><<<nb, 256, 0, s>>>(t->r, t->p, sc, t->perm, out, n, stop);
+      break;
+  }
   return launch_check("transfer x2");
+}
+
+dmg_status launch_ct(dmg_transfer* t, const double* x, double* r_c, const int* stop, hipStream_t s) {
+  const int ng = t->nx * t->ny;
+  k_t_ct<<<tblocks(ng, kCG), 256, 0, s>>>(t->CTrp, t->CTci, t->CTv, x, r_c, ng, stop);
+  return launch_check("transfer C^T x");
 }
 
 // Internal vertex order: by the grid cell holding each vertex's image (row-major), so that the
@@ -448,8 +422,6 @@ std::vector<int> locality_order(const Mesh& m, int nx, int ny) {
   return perm;
 }
 
-// Rows of a taken in the order perm (new row i = old row perm[i]); columns through colmap when
-// given (then each row is re-sorted by its new column).
 Csr permute_rows(const Csr& a, const std::vector<int>& perm, const std::vector<int>* colmap) {
   Csr out;
   const int n = int(perm.size());
@@ -472,36 +444,16 @@ Csr permute_rows(const Csr& a, const std::vector<int>& perm, const std::vector<i
   return out;
 }
 
-}  // namespace
-}  // namespace dmg
-
-using namespace dmg;
-
-extern "C" {
-
-dmg_status dmg_transfer_create(int32_t nv, int32_t nt, const double* xy_c, const double* xy_p,
-                               const int32_t* tris, const uint8_t* dof, int32_t nx, int32_t ny,
-                               int32_t nq, hipStream_t stream, dmg_transfer** out) {
-  clear_error();
-  if (!out) return fail(DMG_ERR_INVALID_ARG, "null output handle");
-  *out = nullptr;
-  if (!xy_c || !xy_p || !tris || !dof) return fail(DMG_ERR_INVALID_ARG, "null mesh array");
-  if (nv <= 0 || nt <= 0) return fail(DMG_ERR_INVALID_ARG, "empty mesh (nv=%d, nt=%d)", nv, nt);
-  if (nx < 3 || ny < 3) return fail(DMG_ERR_DIMS, "grid dims must be >= 3");
-  if (nq < 1 || nq > 32) return fail(DMG_ERR_INVALID_ARG, "nq must be in [1,32]");
-  for (int64_t k = 0; k < int64_t(nt) * 3; ++k)
-    if (tris[k] < 0 || tris[k] >= nv)
-      return fail(DMG_ERR_INVALID_ARG, "triangle vertex index %d out of range", tris[k]);
-  Mesh m{nv, nt, xy_c, xy_p, tris, dof, {}, {}};
-  build_adjacency(m);
-  const std::vector<int> perm = locality_order(m, nx, ny);
+dmg_status transfer_build(const Mesh& m, int nx, int ny, int nq, const std::vector<int>& perm,
+                          hipStream_t stream, std::unique_ptr<dmg_transfer>& out) {
+  const int nv = m.nv;
   std::vector<int> newidx(nv);
   for (int i = 0; i < nv; ++i) newidx[perm[i]] = i;
   const Csr C = permute_rows(assemble_C(m, nx, ny, nq), perm, nullptr);
   const Csr M = permute_rows(assemble_M(m), perm, &newidx);
   const Csr CT = transpose(C, nx * ny);
   std::vector<uint8_t> dof_p(nv);
-  for (int i = 0; i < nv; ++i) dof_p[i] = dof[perm[i]];
+  for (int i = 0; i < nv; ++i) dof_p[i] = m.dof[perm[i]];
   if (C.ci.size() >= (size_t(1) << 31) || M.ci.size() >= (size_t(1) << 31))
     return fail(DMG_ERR_INVALID_ARG, "transfer matrices exceed 2^31 nonzeros");
   std::unique_ptr<dmg_transfer> t(new dmg_transfer);
@@ -553,6 +505,33 @@ dmg_status dmg_transfer_create(int32_t nv, int32_t nt, const double* xy_c, const
   DMG_CHECK(up(t->dof, dof_p.data(), size_t(nv)));
   DMG_CHECK(up(t->perm, perm.data(), size_t(nv) * sizeof(int)));
   DMG_HIP(hipStreamSynchronize(stream));  // host vectors go out of scope
+  out = std::move(t);
+  return DMG_OK;
+}
+
+}  // namespace dmg
+
+using namespace dmg;
+
+extern "C" {
+
+dmg_status dmg_transfer_create(int32_t nv, int32_t nt, const double* xy_c, const double* xy_p,
+                               const int32_t* tris, const uint8_t* dof, int32_t nx, int32_t ny,
+                               int32_t nq, hipStream_t stream, dmg_transfer** out) {
+  clear_error();
+  if (!out) return fail(DMG_ERR_INVALID_ARG, "null output handle");
+  *out = nullptr;
+  if (!xy_c || !xy_p || !tris || !dof) return fail(DMG_ERR_INVALID_ARG, "null mesh array");
+  if (nv <= 0 || nt <= 0) return fail(DMG_ERR_INVALID_ARG, "empty mesh (nv=%d, nt=%d)", nv, nt);
+  if (nx < 3 || ny < 3) return fail(DMG_ERR_DIMS, "grid dims must be >= 3");
+  if (nq < 1 || nq > 32) return fail(DMG_ERR_INVALID_ARG, "nq must be in [1,32]");
+  for (int64_t k = 0; k < int64_t(nt) * 3; ++k)
+    if (tris[k] < 0 || tris[k] >= nv)
+      return fail(DMG_ERR_INVALID_ARG, "triangle vertex index %d out of range", tris[k]);
+  Mesh m{nv, nt, xy_c, xy_p, tris, dof, {}, {}};
+  build_adjacency(m);
+  std::unique_ptr<dmg_transfer> t;
+  DMG_CHECK(transfer_build(m, nx, ny, nq, locality_order(m, nx, ny), stream, t));
   *out = t.release();
   return DMG_OK;
 }
@@ -569,24 +548,19 @@ dmg_status dmg_transfer_from_grid(dmg_transfer* t, const double* u_c, double* u_
                                   hipStream_t stream) {
   clear_error();
   if (!t || !u_c || !u_p) return fail(DMG_ERR_INVALID_ARG, "null pointer argument");
-  const int nb = tblocks(t->nv, kMG);
-  k_t_init_from<<<nb, 256, 0, stream>>>(t->Crp, t->Cci, t->Cv, u_c, t->dof, t->r, t->nv,
-                                        t->partials);
-  DMG_CHECK(launch_check("transfer C u"));
-  return cg2_tail(t, u_p, true, stream);
+  DMG_CHECK(launch_from_start(t, u_c, nullptr, stream));
+  return cg2_tail(t, u_p, X2Mode::kScatter, nullptr, stream);
 }
 
 dmg_status dmg_transfer_to_grid(dmg_transfer* t, const double* r_p, double* r_c,
                                 hipStream_t stream) {
   clear_error();
   if (!t || !r_p || !r_c) return fail(DMG_ERR_INVALID_ARG, "null pointer argument");
-  const int nb = tblocks(t->nv, kMG);
-  k_t_init_to<<<nb, 256, 0, stream>>>(r_p, t->perm, t->dof, t->r, t->nv, t->partials);
+  k_t_init_to<<<tblocks(t->nv, kMG), 256, 0, stream>>>(r_p, t->perm, t->dof, t->r, t->nv,
+                                                       t->partials);
   DMG_CHECK(launch_check("transfer r_p"));
-  DMG_CHECK(cg2_tail(t, t->x, false, stream));
-  const int ng = t->nx * t->ny;
-  k_t_ct<<<tblocks(ng, kCG), 256, 0, stream>>>(t->CTrp, t->CTci, t->CTv, t->x, r_c, ng);
-  return launch_check("transfer C^T x");
+  DMG_CHECK(cg2_tail(t, t->x, X2Mode::kStore, nullptr, stream));
+  return launch_ct(t, t->x, r_c, nullptr, stream);
 }
 
 void dmg_transfer_destroy(dmg_transfer* t) { delete t; }

@@ -1,0 +1,538 @@
+// The two-level cycle of diffeomorphic multigrid (paper Sec. 2.2, solution phase) on the
+// physical P1 system A_p u_p = f_p: symmetric multicolour Gauss-Seidel on the mesh, the residual
+// restricted to the grid by R = C^T M_p^{-1}, one BoxMG V-cycle on the grid from zero, the
+// correction interpolated by P = M_p^{-1} C, and a second symmetric sweep.  M_p^{-1} is the
+// lumped mass (row sums of M_p) or two CG iterations on M_p (Sec. 2.3).
+//
+// Setup (host, once per mesh): A_p = sum_t K_t G_t with G_t the P1 element stiffness on the
+// physical triangle (Dirichlet rows and columns replaced by the identity); colours by a greedy
+// pass over the vertices in the caller's index order on the mesh graph (unknowns sharing a
+// triangle are neighbours; Dirichlet vertices have none); internal vertex order colour-major,
+// each colour in the grid-cell order of the transfers, so one colour is one contiguous row range.
+// The transfers (C, C^T, M_p) are built in the same internal order.
+//
+// Solve (device): the state and the vectors live in the handle in the internal order; the caller's
+// u_p and f_p are gathered at the start and u_p scattered back at the end.  Chunks of cycles run
+// in one captured graph; the convergence test is taken on the device after every cycle, and
+// every kernel of the chunk is a no-op once it has stopped the solve.
+#include <algorithm>
+#include <cmath>
+
+#include "mesh_internal.h"
+
+struct dmg_twolevel {
+  std::unique_ptr<dmg_transfer> t;
+  dmg_hier* grid = nullptr;  // borrowed
+  int nv = 0, nx = 0, ny = 0, mass = 0;
+  int64_t nnzA = 0;  // stored off-diagonal entries of A_p
+  std::vector<int> cs;      // colour c holds internal rows [cs[c], cs[c + 1])
+  std::vector<int> colour;  // colour of each vertex, caller order
+  int *Arp = nullptr, *Aci = nullptr;  // off-diagonal part of A_p, internal order
+  double *Av = nullptr, *Ad = nullptr;  // its values; the diagonal
+  double* ML = nullptr;                 // lumped mass (1 on Dirichlet rows)
+  double *u = nullptr, *f = nullptr;    // iterate and right-hand side, internal order
+  double *w = nullptr;                  // scaled residual, internal order
+  double *ec = nullptr, *rc = nullptr;  // grid correction and restricted residual [ny][nx]
+  double *partials = nullptr, *scal = nullptr, *hist = nullptr;
+  int* flag = nullptr;  // [0] stop, [1] cycles done, [2] max cycles
+  void* block = nullptr;
+  double* host = nullptr;  // pinned: scalars [0..7], flags at [8..]
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  hipStream_t graph_stream = nullptr;
+  void reset_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    graph_stream = nullptr;
+  }
+  ~dmg_twolevel() {
+    reset_graph();
+    if (block) (void)hipFree(block);
+    if (host) (void)hipHostFree(host);
+  }
+};
+
+namespace dmg {
+namespace {
+
+__device__ __forceinline__ bool halted(const int* stop) { return stop && *stop; }
+
+// One colour of the sweep: u_r = (f_r - sum_{k != r} a_rk u_k) / a_rr for the rows of one colour
+// [r0, r1).  Rows of one colour are not coupled, so every u_k read belongs to another colour and
+// the update can be made in place.
+__global__ __launch_bounds__(256) void k_tl_colour(const int* __restrict__ rp,
+                                                   const int* __restrict__ ci,
+                                                   const double* __restrict__ v,
+                                                   const double* __restrict__ d,
+                                                   const double* __restrict__ f, double* u, int r0,
+                                                   int r1, const int* __restrict__ stop) {
+  if (halted(stop)) return;
+  const int lane = threadIdx.x & (kMG - 1);
+  const int g0 = int((blockIdx.x * 256u + threadIdx.x) / kMG), ng = int(gridDim.x * 256u / kMG);
+  for (int r = r0 + g0; r < r1; r += ng) {
+    const double s = row_dot<kMG>(rp, ci, v, r, lane, [&](int c) { return u[c]; });
+    if (lane == 0) u[r] = (f[r] - s) / d[r];
+  }
+}
+
+// Residual r = f - A_p u.  kLumped: w = dof ? r / ML : 0.  kMasked: w = dof ? r : 0 with partials
+// of w.w (the start of CG on M_p).  kNorm: partials of r.r only.
+enum class RMode { kLumped, kMasked, kNorm };
+
+template <RMode MODE>
+__global__ __launch_bounds__(256) void k_tl_resid(const int* __restrict__ rp,
+                                                  const int* __restrict__ ci,
+                                                  const double* __restrict__ v,
+                                                  const double* __restrict__ d,
+                                                  const double* __restrict__ f,
+                                                  const double* __restrict__ u,
+                                                  const double* __restrict__ ML,
+                                                  const unsigned char* __restrict__ dof,
+                                                  double* __restrict__ w, int n,
+                                                  double* __restrict__ partials,
+                                                  const int* __restrict__ stop) {
+  if (halted(stop)) return;
+  const int lane = threadIdx.x & (kMG - 1);
+  const int g0 = int((blockIdx.x * 256u + threadIdx.x) / kMG), ng = int(gridDim.x * 256u / kMG);
+  double acc = 0.0;
+  for (int r = g0; r < n; r += ng) {
+    const double s = row_dot<kMG>(rp, ci, v, r, lane, [&](int c) { return u[c]; });
+    if (lane == 0) {
+      const double res = f[r] - __builtin_fma(d[r], u[r], s);
+      if constexpr (MODE == RMode::kLumped) {
+        w[r] = dof[r] ? res / ML[r] : 0.0;
+      } else if constexpr (MODE == RMode::kMasked) {
+        const double m = dof[r] ? res : 0.0;
+        w[r] = m;
+        acc += m * m;
+      } else {
+        acc += res * res;
+      }
+    }
+  }
+  if constexpr (MODE != RMode::kLumped) {
+    const double t = mesh_block_sum(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+  }
+}
+
+// u += dof * (C e_c) / ML: the lumped interpolation of the grid correction, added in place.
+__global__ __launch_bounds__(256) void k_tl_prolong(const int* __restrict__ rp,
+                                                    const int* __restrict__ ci,
+                                                    const double* __restrict__ v,
+                                                    const double* __restrict__ ec,
+                                                    const double* __restrict__ ML,
+                                                    const unsigned char* __restrict__ dof,
+                                                    double* __restrict__ u, int n,
+                                                    const int* __restrict__ stop) {
+  if (halted(stop)) return;
+  const int lane = threadIdx.x & (kMG - 1);
+  const int g0 = int((blockIdx.x * 256u + threadIdx.x) / kMG), ng = int(gridDim.x * 256u / kMG);
+  for (int r = g0; r < n; r += ng) {
+    const double s = row_dot<kMG>(rp, ci, v, r, lane, [&](int c) { return ec[c]; });
+    if (lane == 0 && dof[r]) u[r] += s / ML[r];
+  }
+}
+
+// Internal-order copies of the caller's vectors (u_p may be null) and the way back.
+__global__ __launch_bounds__(256) void k_tl_gather(const double* __restrict__ u_p,
+                                                   const double* __restrict__ f_p,
+                                                   const int* __restrict__ perm,
+                                                   double* __restrict__ u, double* __restrict__ f,
+                                                   int n) {
+  for (int r = blockIdx.x * 256 + threadIdx.x; r < n; r += gridDim.x * 256) {
+    const int o = perm[r];
+    u[r] = u_p ? u_p[o] : 0.0;
+    f[r] = f_p[o];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_tl_scatter(const double* __restrict__ u,
+                                                    const int* __restrict__ perm,
+                                                    double* __restrict__ u_p, int n) {
+  for (int r = blockIdx.x * 256 + threadIdx.x; r < n; r += gridDim.x * 256) u_p[perm[r]] = u[r];
+}
+
+// Solve start from the partials of ||f - A u_0||^2: sc[0..1] = sc[2..3] = (r0^2, r0) (the
+// history's denominator and the current residual), sc[6] = (rtol r0)^2; the solve stops at once
+// only when r0 is zero or not finite, or when no cycle is allowed.
+__global__ __launch_bounds__(256) void k_tl_start(const double* __restrict__ partials, int count,
+                                                  double* __restrict__ sc, int* __restrict__ st,
+                                                  double rtol, int max_iters) {
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < count; k += 256) acc += partials[k];
+  const double t = mesh_block_sum(acc);
+  if (threadIdx.x == 0) {
+    const double r0 = sqrt(t), target = rtol * r0;
+    sc[0] = t;
+    sc[1] = r0;
+    sc[2] = t;
+    sc[3] = r0;
+    sc[6] = target * target;
+    st[0] = (t == 0.0 || max_iters <= 0 || !isfinite(t)) ? 1 : 0;
+    st[1] = 0;
+    st[2] = max_iters;
+  }
+}
+
+inline int row_blocks(int rows) { return tblocks(rows, kMG); }
+
+dmg_status symmetric_sweep(dmg_twolevel* tl, const int* stop, hipStream_t s) {
+  const int nc = int(tl->cs.size()) - 1;
+  auto colour = [&](int c) -> dmg_status {
+    const int r0 = tl->cs[c], r1 = tl->cs[c + 1];
+    if (r1 == r0) return DMG_OK;
+    k_tl_colour<<<row_blocks(r1 - r0), 256, 0, s>>>(tl->Arp, tl->Aci, tl->Av, tl->Ad, tl->f,
+                                                    tl->u, r0, r1, stop);
+    return launch_check("two-level colour sweep");
+  };
+  for (int c = 0; c < nc; ++c) DMG_CHECK(colour(c));
+  // the backward sweep starts with the colour just swept; sweeping it again would recompute the
+  // same values from the same inputs, so it starts one colour lower
+  for (int c = nc - 2; c >= 0; --c) DMG_CHECK(colour(c));
+  return DMG_OK;
+}
+
+// One two-level cycle on tl->u.
+dmg_status cycle(dmg_twolevel* tl, const int* stop, hipStream_t s) {
+  dmg_transfer* t = tl->t.get();
+  const int n = tl->nv, nb = row_blocks(n);
+  DMG_CHECK(symmetric_sweep(tl, stop, s));
+  if (tl->mass == 0) {
+    k_tl_resid<RMode::kLumped><<<nb, 256, 0, s>>>(tl->Arp, tl->Aci, tl->Av, tl->Ad, tl->f, tl->u,
+                                                  tl->ML, t->dof, tl->w, n, nullptr, stop);
+    DMG_CHECK(launch_check("two-level residual"));
+    DMG_CHECK(launch_ct(t, tl->w, tl->rc, stop, s));
+  } else {
+    // r0 of CG on M_p (and its partials) straight into the transfer's CG state
+    k_tl_resid<RMode::kMasked><<<nb, 256, 0, s>>>(tl->Arp, tl->Aci, tl->Av, tl->Ad, tl->f, tl->u,
+                                                  tl->ML, t->dof, t->r, n, t->partials, stop);
+    DMG_CHECK(launch_check("two-level residual"));
+    DMG_CHECK(cg2_tail(t, tl->w, X2Mode::kStore, stop, s));
+    DMG_CHECK(launch_ct(t, tl->w, tl->rc, stop, s));
+  }
+  DMG_CHECK(grid_vcycle(tl->grid, tl->ec, tl->rc, true, stop, s));
+  if (tl->mass == 0) {
+    k_tl_prolong<<<nb, 256, 0, s>>>(t->Crp, t->Cci, t->Cv, tl->ec, tl->ML, t->dof, tl->u, n, stop);
+    DMG_CHECK(launch_check("two-level interpolation"));
+  } else {
+    DMG_CHECK(launch_from_start(t, tl->ec, stop, s));
+    DMG_CHECK(cg2_tail(t, tl->u, X2Mode::kAdd, stop, s));
+  }
+  return symmetric_sweep(tl, stop, s);
+}
+
+// The repeated step of a solve: one cycle, the residual norm, the convergence test.
+dmg_status step(dmg_twolevel* tl, hipStream_t s) {
+  const int* stop = tl->flag;
+  DMG_CHECK(cycle(tl, stop, s));
+  const int nb = row_blocks(tl->nv);
+  k_tl_resid<RMode::kNorm><<<nb, 256, 0, s>>>(tl->Arp, tl->Aci, tl->Av, tl->Ad, tl->f, tl->u,
+                                              tl->ML, tl->t->dof, nullptr, tl->nv, tl->partials,
+                                              stop);
+  DMG_CHECK(launch_check("two-level residual norm"));
+  return launch_check_step(tl->partials, nb, tl->scal + 2, tl->scal, tl->flag, tl->hist,
+                           kMaxHistory, s);
+}
+
+dmg_status run_chunk(dmg_twolevel* tl, hipStream_t s) {
+  auto chunk = [&]() -> dmg_status {
+    for (int k = 0; k < kChunk; ++k) DMG_CHECK(step(tl, s));
+    return DMG_OK;
+  };
+  if (s == nullptr) return chunk();  // the legacy default stream cannot be captured
+  if (!(tl->exec && tl->graph_stream == s)) {
+    tl->reset_graph();
+    DMG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    const dmg_status st = chunk();
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (st != DMG_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return fail(DMG_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
+    tl->graph = g;
+    e = hipGraphInstantiate(&tl->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      tl->reset_graph();
+      return fail(DMG_ERR_HIP, "graph instantiate failed: %s", hipGetErrorString(e));
+    }
+    tl->graph_stream = s;
+  }
+  DMG_HIP(hipGraphLaunch(tl->exec, s));
+  return DMG_OK;
+}
+
+// P1 element stiffness of triangle tv (physical coordinates xy): area * grad l_a . grad l_b with
+// grad l_a = (y_b - y_c, x_c - x_b) / det over the cyclic triple (a, b, c).
+void element_stiffness(const double* xy, const int* tv, double G[3][3]) {
+  const double* P[3] = {xy + 2 * tv[0], xy + 2 * tv[1], xy + 2 * tv[2]};
+  const double det = tri_area2(xy, tv);
+  double g[3][2];
+  for (int a = 0; a < 3; ++a) {
+    const double* pb = P[(a + 1) % 3];
+    const double* pc = P[(a + 2) % 3];
+    g[a][0] = (pb[1] - pc[1]) / det;
+    g[a][1] = (pc[0] - pb[0]) / det;
+  }
+  const double area = 0.5 * std::fabs(det);
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) G[a][b] = area * (g[a][0] * g[b][0] + g[a][1] * g[b][1]);
+}
+
+// A_p in the caller's order, split into its diagonal and its off-diagonal CSR.
+void assemble_A(const Mesh& m, const double* K_t, Csr& off, std::vector<double>& diag) {
+  off = Csr{};
+  off.rp.assign(1, 0);
+  diag.assign(m.nv, 1.0);
+  std::vector<std::pair<int, double>> row;
+  for (int v = 0; v < m.nv; ++v) {
+    row.clear();
+    if (m.dof[v]) {
+      double dv = 0.0;
+      for (int k = m.vt_ptr[v]; k < m.vt_ptr[v + 1]; ++k) {
+        const int* tv = m.tris + 3 * m.vt[k];
+        const int a = tv[0] == v ? 0 : (tv[1] == v ? 1 : 2);
+        double G[3][3];
+        element_stiffness(m.xy_p, tv, G);
+        const double kt = K_t ? K_t[m.vt[k]] : 1.0;
+        for (int b = 0; b < 3; ++b) {
+          if (b == a) dv += kt * G[a][a];
+          else if (m.dof[tv[b]]) row.emplace_back(tv[b], kt * G[a][b]);
+        }
+      }
+      diag[v] = dv;
+      std::stable_sort(row.begin(), row.end(),
+                       [](const std::pair<int, double>& x, const std::pair<int, double>& y) {
+                         return x.first < y.first;
+                       });
+      size_t w = 0;
+      for (size_t k = 0; k < row.size(); ++k) {
+        if (w > 0 && row[w - 1].first == row[k].first) row[w - 1].second += row[k].second;
+        else row[w++] = row[k];
+      }
+      row.resize(w);
+    }
+    for (auto& e : row) {
+      off.ci.push_back(e.first);
+      off.v.push_back(e.second);
+    }
+    off.rp.push_back(int(off.ci.size()));
+  }
+}
+
+// Greedy colours on the mesh graph, vertices in the caller's index order.
+std::vector<int> greedy_colours(const Mesh& m) {
+  std::vector<int> col(m.nv, -1);
+  std::vector<int> mark;  // mark[c] == v: colour c is taken by a neighbour of v
+  for (int v = 0; v < m.nv; ++v) {
+    if (!m.dof[v]) {
+      col[v] = 0;
+      continue;
+    }
+    for (int k = m.vt_ptr[v]; k < m.vt_ptr[v + 1]; ++k) {
+      const int* tv = m.tris + 3 * m.vt[k];
+      for (int b = 0; b < 3; ++b) {
+        const int w = tv[b];
+        if (w == v || !m.dof[w] || col[w] < 0) continue;
+        if (col[w] >= int(mark.size())) mark.resize(col[w] + 1, -1);
+        mark[col[w]] = v;
+      }
+    }
+    int c = 0;
+    while (c < int(mark.size()) && mark[c] == v) ++c;
+    col[v] = c;
+  }
+  return col;
+}
+
+}  // namespace
+}  // namespace dmg
+
+using namespace dmg;
+
+extern "C" {
+
+dmg_status dmg_twolevel_create(int32_t nv, int32_t nt, const double* xy_c, const double* xy_p,
+                               const int32_t* tris, const uint8_t* dof, const double* K_t,
+                               dmg_hier* grid, int32_t nq, int32_t mass, hipStream_t stream,
+                               dmg_twolevel** out) {
+  clear_error();
+  if (!out) return fail(DMG_ERR_INVALID_ARG, "null output handle");
+  *out = nullptr;
+  if (!xy_c || !xy_p || !tris || !dof || !grid) return fail(DMG_ERR_INVALID_ARG, "null argument");
+  if (nv <= 0 || nt <= 0) return fail(DMG_ERR_INVALID_ARG, "empty mesh (nv=%d, nt=%d)", nv, nt);
+  if (nq < 1 || nq > 32) return fail(DMG_ERR_INVALID_ARG, "nq must be in [1,32]");
+  if (mass != 0 && mass != 2) return fail(DMG_ERR_INVALID_ARG, "mass must be 0 (lumped) or 2 (CG2)");
+  for (int64_t k = 0; k < int64_t(nt) * 3; ++k)
+    if (tris[k] < 0 || tris[k] >= nv)
+      return fail(DMG_ERR_INVALID_ARG, "triangle vertex index %d out of range", tris[k]);
+  for (int t = 0; t < nt; ++t)
+    if (tri_area2(xy_p, tris + 3 * t) == 0.0)
+      return fail(DMG_ERR_INVALID_ARG, "physical triangle %d is degenerate", t);
+  const int nx = grid->L[0].nx, ny = grid->L[0].ny;
+  Mesh m{nv, nt, xy_c, xy_p, tris, dof, {}, {}};
+  build_adjacency(m);
+  std::unique_ptr<dmg_twolevel> tl(new dmg_twolevel);
+  tl->grid = grid;
+  tl->nv = nv;
+  tl->nx = nx;
+  tl->ny = ny;
+  tl->mass = mass;
+  tl->colour = greedy_colours(m);
+  const int ncol = 1 + *std::max_element(tl->colour.begin(), tl->colour.end());
+  // internal order: colour-major, the transfers' grid-cell order within a colour
+  std::vector<int> perm = locality_order(m, nx, ny);
+  std::stable_sort(perm.begin(), perm.end(),
+                   [&](int a, int b) { return tl->colour[a] < tl->colour[b]; });
+  tl->cs.assign(ncol + 1, 0);
+  for (int v = 0; v < nv; ++v) tl->cs[tl->colour[v] + 1]++;
+  for (int c = 0; c < ncol; ++c) tl->cs[c + 1] += tl->cs[c];
+  DMG_CHECK(transfer_build(m, nx, ny, nq, perm, stream, tl->t));
+  std::vector<int> newidx(nv);
+  for (int i = 0; i < nv; ++i) newidx[perm[i]] = i;
+  Csr off;
+  std::vector<double> diag;
+  assemble_A(m, K_t, off, diag);
+  for (int v = 0; v < nv; ++v)
+    if (!(diag[v] > 0.0) || !std::isfinite(diag[v]))
+      return fail(DMG_ERR_INVALID_ARG, "A_p has a non-positive diagonal at vertex %d", v);
+  const Csr A = permute_rows(off, perm, &newidx);
+  std::vector<double> d(nv), ml(nv, 0.0);
+  for (int i = 0; i < nv; ++i) d[i] = diag[perm[i]];
+  // lumped mass: the row sums of M_p, whose element entries are area/12 times 2 (diagonal) or 1
+  // (a free neighbour in the triangle); 1 on the identity rows of Dirichlet vertices
+  for (int v = 0; v < nv; ++v) {
+    double s = 0.0;
+    if (!dof[v]) {
+      s = 1.0;
+    } else {
+      for (int k = m.vt_ptr[v]; k < m.vt_ptr[v + 1]; ++k) {
+        const int* tv = tris + 3 * m.vt[k];
+        const double area = 0.5 * std::fabs(tri_area2(xy_p, tv));
+        for (int b = 0; b < 3; ++b)
+          if (dof[tv[b]]) s += (tv[b] == v ? 2.0 : 1.0) * area / 12.0;
+      }
+    }
+    ml[newidx[v]] = s;
+  }
+  tl->nnzA = int64_t(A.ci.size());
+  const size_t ng = size_t(nx) * ny;
+  Arena sz;
+  auto layout = [&](Arena& a) {
+    tl->Arp = a.take<int>(nv + 1);
+    tl->Aci = a.take<int>(A.ci.size() + 1);
+    tl->Av = a.take<double>(A.v.size() + 1);
+    tl->Ad = a.take<double>(nv);
+    tl->ML = a.take<double>(nv);
+    tl->u = a.take<double>(nv);
+    tl->f = a.take<double>(nv);
+    tl->w = a.take<double>(nv);
+    tl->ec = a.take<double>(ng);
+    tl->rc = a.take<double>(ng);
+    tl->partials = a.take<double>(kTBlocks);
+    tl->scal = a.take<double>(16);
+    tl->hist = a.take<double>(kMaxHistory);
+    tl->flag = a.take<int>(4);
+  };
+  layout(sz);
+  DMG_HIP(hipMalloc(&tl->block, sz.used));
+  Arena a;
+  a.base = static_cast<char*>(tl->block);
+  a.cap = sz.used;
+  layout(a);
+  DMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&tl->host), 16 * sizeof(double),
+                        hipHostMallocDefault));
+  auto up = [&](void* dst, const void* src, size_t bytes) -> dmg_status {
+    if (bytes) DMG_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream));
+    return DMG_OK;
+  };
+  DMG_CHECK(up(tl->Arp, A.rp.data(), A.rp.size() * sizeof(int)));
+  DMG_CHECK(up(tl->Aci, A.ci.data(), A.ci.size() * sizeof(int)));
+  DMG_CHECK(up(tl->Av, A.v.data(), A.v.size() * sizeof(double)));
+  DMG_CHECK(up(tl->Ad, d.data(), size_t(nv) * sizeof(double)));
+  DMG_CHECK(up(tl->ML, ml.data(), size_t(nv) * sizeof(double)));
+  // the grid correction's boundary stays zero (the V-cycle writes interior points only)
+  DMG_HIP(hipMemsetAsync(tl->ec, 0, ng * sizeof(double), stream));
+  DMG_HIP(hipMemsetAsync(tl->rc, 0, ng * sizeof(double), stream));
+  DMG_HIP(hipMemsetAsync(tl->flag, 0, 4 * sizeof(int), stream));
+  DMG_HIP(hipStreamSynchronize(stream));  // host vectors go out of scope
+  *out = tl.release();
+  return DMG_OK;
+}
+
+dmg_status dmg_twolevel_info(const dmg_twolevel* tl, int32_t* colours, int64_t* nnz_A,
+                             int32_t* colour) {
+  clear_error();
+  if (!tl) return fail(DMG_ERR_INVALID_ARG, "null two-level handle");
+  if (colours) *colours = int32_t(tl->cs.size()) - 1;
+  if (nnz_A) *nnz_A = tl->nnzA + tl->nv;
+  if (colour) std::copy(tl->colour.begin(), tl->colour.end(), colour);
+  return DMG_OK;
+}
+
+dmg_status dmg_twolevel_cycle(dmg_twolevel* tl, double* u_p, const double* f_p,
+                              hipStream_t stream) {
+  clear_error();
+  if (!tl || !u_p || !f_p) return fail(DMG_ERR_INVALID_ARG, "null pointer argument");
+  const int n = tl->nv, nb = row_blocks(n);
+  k_tl_gather<<<nb, 256, 0, stream>>>(u_p, f_p, tl->t->perm, tl->u, tl->f, n);
+  DMG_CHECK(launch_check("two-level gather"));
+  DMG_CHECK(cycle(tl, nullptr, stream));
+  k_tl_scatter<<<nb, 256, 0, stream>>>(tl->u, tl->t->perm, u_p, n);
+  return launch_check("two-level scatter");
+}
+
+dmg_status dmg_twolevel_solve(dmg_twolevel* tl, double* u_p, const double* f_p, double rtol,
+                              int32_t max_iters, int32_t* iters, double* relres, double* history,
+                              hipStream_t stream) {
+  clear_error();
+  if (!tl || !u_p || !f_p) return fail(DMG_ERR_INVALID_ARG, "null pointer argument");
+  if (!(rtol >= 0.0) || max_iters < 0) return fail(DMG_ERR_INVALID_ARG, "bad rtol/max_iters");
+  if (iters) *iters = 0;
+  const int n = tl->nv, nb = row_blocks(n);
+  k_tl_gather<<<nb, 256, 0, stream>>>(u_p, f_p, tl->t->perm, tl->u, tl->f, n);
+  DMG_CHECK(launch_check("two-level gather"));
+  k_tl_resid<RMode::kNorm><<<nb, 256, 0, stream>>>(tl->Arp, tl->Aci, tl->Av, tl->Ad, tl->f, tl->u,
+                                                   tl->ML, tl->t->dof, nullptr, n, tl->partials,
+                                                   nullptr);
+  DMG_CHECK(launch_check("two-level initial residual"));
+  k_tl_start<<<1, 256, 0, stream>>>(tl->partials, nb, tl->scal, tl->flag, rtol, max_iters);
+  DMG_CHECK(launch_check("two-level start"));
+  int* hs = reinterpret_cast<int*>(tl->host + 8);
+  double* hsc = tl->host;
+  for (;;) {
+    DMG_CHECK(run_chunk(tl, stream));
+    DMG_HIP(hipMemcpyAsync(hs, tl->flag, 2 * sizeof(int), hipMemcpyDeviceToHost, stream));
+    DMG_HIP(hipMemcpyAsync(hsc, tl->scal, 8 * sizeof(double), hipMemcpyDeviceToHost, stream));
+    DMG_HIP(hipStreamSynchronize(stream));
+    if (hs[0]) break;
+  }
+  k_tl_scatter<<<nb, 256, 0, stream>>>(tl->u, tl->t->perm, u_p, n);
+  DMG_CHECK(launch_check("two-level scatter"));
+  const int k = hs[1];
+  const double r0 = hsc[1], rn = hsc[3];
+  if (!std::isfinite(r0)) return fail(DMG_ERR_NONFINITE, "initial residual norm is not finite");
+  if (r0 == 0.0) {  // u_0 already solves the system
+    if (relres) *relres = 0.0;
+    return DMG_OK;
+  }
+  if (history && k > 0)
+    DMG_HIP(hipMemcpy(history, tl->hist, size_t(std::min(k, kMaxHistory)) * sizeof(double),
+                      hipMemcpyDeviceToHost));
+  if (iters) *iters = k;
+  if (relres) *relres = rn / r0;
+  if (!std::isfinite(rn))
+    return fail(DMG_ERR_NONFINITE, "residual norm became non-finite at cycle %d", k);
+  if (rn > rtol * r0)
+    return fail(DMG_ERR_NO_CONVERGENCE, "no convergence in %d cycles (rel. residual %.3e)", k,
+                rn / r0);
+  return DMG_OK;
+}
+
+void dmg_twolevel_destroy(dmg_twolevel* tl) { delete tl; }
+
+}  // extern "C"

@@ -1,0 +1,132 @@
+"""Parity of the two-level cycle on the physical mesh (HIP library through the C ABI) with the
+float64 oracle (oracle/dmg.py) on star-domain meshes: the relaxation colours bit for bit, every
+iterate to 1e-12 relative for both mass modes, whole solves (cycle counts, residual histories,
+solutions), the zero-residual start, the iteration cap, and the captured-graph path against the
+eager one."""
+import numpy as np
+import pytest
+import torch
+
+import problems as pb
+from oracle import boxmg, cycle, dmg, fem, transfer
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2509_08109_amd as m
+    m.lib()
+    return m
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def relerr(a, b):
+    den = np.max(np.abs(b))
+    return np.max(np.abs(a - b)) / (den if den > 0 else 1.0)
+
+
+_CACHE = {}
+
+
+def pair(lib, n, seed=1, mass="lumped"):
+    """(problem, oracle two-level, GPU two-level) on the star mesh of grid size n."""
+    key = (n, seed, mass)
+    if key not in _CACHE:
+        P = pb.star_dmg(n, seed=seed)
+        m = P.mesh
+        A = dmg.p1_stiffness(m.xy_p, m.tris, m.dof, P.K_t)
+        M = transfer.p1_mass(m.xy_p, m.tris, m.dof)
+        Cm = transfer.coupled_mass(m.xy_c, m.xy_p, m.tris, m.dof, n, n, nq=8)
+        grid = cycle.Oracle(boxmg.build_hierarchy(fem.assemble_stencil(P.grid.jac, P.grid.K, n, n)))
+        orc = dmg.TwoLevel(A, M, Cm, grid, n, n, dmg.mesh_colouring(m.tris, m.dof),
+                           mass="lumped" if mass == "lumped" else 2)
+        H = lib.Hierarchy(lib.assemble_stencil(dev(P.grid.jac), dev(P.grid.K)))
+        tl = lib.TwoLevel(H, m.xy_c, m.xy_p, m.tris, m.dof, K_t=P.K_t, nq=8, mass=mass)
+        _CACHE[key] = (P, orc, tl)
+    return _CACHE[key]
+
+
+def test_colouring_and_operator_size(lib):
+    P, orc, tl = pair(lib, 33)
+    nc, nnz, col = tl.info()
+    assert np.array_equal(col, orc.colour.astype(np.int32))
+    assert nc == int(orc.colour.max()) + 1
+    assert nnz == orc.A.nnz
+
+
+@pytest.mark.parametrize("n,mass", [(17, "lumped"), (33, "lumped"), (17, "cg2"), (33, "cg2")])
+def test_cycles_match_oracle(lib, n, mass):
+    P, orc, tl = pair(lib, n, mass=mass)
+    g = np.random.Generator(np.random.PCG64(11))
+    u0 = np.where(P.mesh.dof, g.uniform(-1, 1, P.mesh.nv), 0.0)
+    uo = u0.copy()
+    ug = dev(u0)
+    fg = dev(P.f)
+    for k in range(3):
+        orc.cycle(uo, P.f)
+        tl.cycle(ug, fg)
+        e = relerr(host(ug), uo)
+        assert e <= TOL, f"cycle {k + 1}: {e:.3e}"
+
+
+@pytest.mark.parametrize("n", [17, 33])
+def test_solve_matches_oracle(lib, n):
+    P, orc, tl = pair(lib, n)
+    u, k, rel, hist = tl.solve(dev(P.f), rtol=1e-10)
+    uo, ko, histo, _ = dmg.solve(orc, P.f, rtol=1e-10)
+    assert k == ko and rel <= 1e-10
+    assert np.allclose(hist, histo, rtol=1e-6, atol=1e-13)
+    assert relerr(host(u), uo) <= 1e-11
+
+
+def test_solve_from_random_guess_with_zero_rhs(lib):
+    """The paper's convergence setting: f = 0 from a random initial guess."""
+    P, orc, tl = pair(lib, 33)
+    g = np.random.Generator(np.random.PCG64(5))
+    u0 = np.where(P.mesh.dof, g.uniform(-1, 1, P.mesh.nv), 0.0)
+    f0 = np.zeros(P.mesh.nv)
+    u, k, rel, hist = tl.solve(dev(f0), u=dev(u0), rtol=1e-10)
+    uo, ko, histo, _ = dmg.solve(orc, f0, u0=u0, rtol=1e-10)
+    assert k == ko
+    assert np.allclose(hist, histo, rtol=1e-6, atol=1e-13)
+    # the iterates decay towards 0: compare against the starting scale
+    assert np.max(np.abs(host(u) - uo)) <= 1e-12 * np.max(np.abs(u0))
+
+
+def test_zero_initial_residual_and_iteration_cap(lib):
+    P, orc, tl = pair(lib, 17)
+    z = torch.zeros(P.mesh.nv, dtype=torch.float64, device="cuda")
+    u, k, rel, hist = tl.solve(torch.zeros_like(z), u=z.clone(), rtol=1e-10)
+    assert k == 0 and rel == 0.0 and hist == [] and float(u.abs().max()) == 0.0
+    u, k, rel, hist = tl.solve(dev(P.f), rtol=1e-30, max_iters=3, raise_on_fail=False)
+    uo, ko, histo, _ = dmg.solve(orc, P.f, rtol=1e-30, max_iters=3)
+    assert k == ko == 3 and np.allclose(hist, histo, rtol=1e-6, atol=1e-13)
+    assert relerr(host(u), uo) <= TOL
+    with pytest.raises(lib.DmgError):
+        tl.solve(dev(P.f), rtol=1e-30, max_iters=2)
+
+
+def test_graph_path_matches_eager(lib):
+    """Solves on a side stream run through captured graphs of four cycles; the default stream
+    runs them eagerly.  Both give the same iterate bit for bit."""
+    P, orc, tl = pair(lib, 33)
+    f = dev(P.f)
+    u_e, k_e, _, h_e = tl.solve(f, rtol=1e-10)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for _ in range(2):  # the second solve replays the captured graph
+            u_g, k_g, _, h_g = tl.solve(f, rtol=1e-10)
+    torch.cuda.synchronize()
+    assert k_g == k_e and h_g == h_e
+    assert torch.equal(u_g, u_e)

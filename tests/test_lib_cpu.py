@@ -30,7 +30,8 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ("dmg_assemble_stencil", "dmg_setup", "dmg_vcycle", "dmg_solve",
                      "dmg_transfer_to_grid", "dmg_transfer_from_grid", "dmg_grad_K",
-                     "dmg_batch_solve"):
+                     "dmg_batch_solve", "dmg_twolevel_create", "dmg_twolevel_cycle",
+                     "dmg_twolevel_solve"):
         assert required in names
 
 
@@ -116,6 +117,30 @@ def test_transfer_validation_on_host(dmg):
     assert st == 1 and "out of range" in lib.dmg_last_error().decode()
     assert lib.dmg_transfer_create(3, 1, xy.ctypes.data, xy.ctypes.data, tris.ctypes.data, dof.ctypes.data,
                                    9, 9, 0, None, C.byref(h)) == 1
+
+
+def test_twolevel_validation_on_host(dmg):
+    """Argument checks that return before any device work (the grid handle is not read)."""
+    import numpy as np
+    lib = dmg.lib()
+    h = C.c_void_p()
+    fake = C.c_void_p(0x1000)
+    xy = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 1.0]])
+    tris = np.array([[0, 1, 2]], dtype=np.int32)
+    dof = np.ones(3, dtype=np.uint8)
+    args = lambda tr, xyp: (3, 1, xy.ctypes.data, xyp.ctypes.data, tr.ctypes.data, dof.ctypes.data)
+    assert lib.dmg_twolevel_create(*args(tris, xy), None, None, 8, 0, None, C.byref(h)) == 1
+    assert lib.dmg_twolevel_create(*args(tris, xy), None, fake, 8, 3, None, C.byref(h)) == 1
+    assert "mass" in lib.dmg_last_error().decode()
+    assert lib.dmg_twolevel_create(*args(tris, xy), None, fake, 0, 0, None, C.byref(h)) == 1
+    bad = np.array([[0, 1, 7]], dtype=np.int32)
+    assert lib.dmg_twolevel_create(*args(bad, xy), None, fake, 8, 0, None, C.byref(h)) == 1
+    assert "out of range" in lib.dmg_last_error().decode()
+    flat = np.array([[0.0, 0.0], [1.0, 0.0], [2.0, 0.0]])
+    assert lib.dmg_twolevel_create(*args(tris, flat), None, fake, 8, 0, None, C.byref(h)) == 1
+    assert "degenerate" in lib.dmg_last_error().decode()
+    assert lib.dmg_twolevel_solve(None, fake, fake, 1e-10, 10, None, None, None, None) == 1
+    assert lib.dmg_twolevel_cycle(None, fake, fake, None) == 1
 
 
 def test_batch_validation_on_host(dmg):
