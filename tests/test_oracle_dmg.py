@@ -14,7 +14,7 @@ from oracle import boxmg, cycle, dmg, fem, transfer
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
-def _setup(n, seed=1, nq=8, mass="lumped"):
+def _setup(n, seed=1, nq=0, mass="lumped"):
     P = pb.star_dmg(n, seed=seed)
     m = P.mesh
     A = dmg.p1_stiffness(m.xy_p, m.tris, m.dof, P.K_t)
