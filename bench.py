@@ -324,6 +324,63 @@ def run_transfer_leg(dmg, dev, n: int = 1025, seed: int = 1, reps: int = 20):
             "to_grid_gbs": round(bytes_apply / (out["to_grid_us"] * 1e-6) / 1e9, 1)}
 
 
+def run_twolevel_leg(dmg, dev, sizes=(129, 257, 513), seed: int = 1, reps: int = 3):
+    """The two-level cycle on the physical P1 system of star meshes of growing size (grid n x n,
+    mesh about n^2 / 0.28 vertices, log-normal K per triangle, f ~ U(-1, 1); lumped mass, exact
+    coupled mass): cycles to 1e-10 of the initial residual, wall time per solve
+    (mean of `reps` solves after one that captures the graph) and per cycle, and one grid
+    V-cycle timed alone with HIP events for the grid's share of a cycle."""
+    import torch
+
+    from problems.batch_device import star_dmg_device
+    rows = []
+    for n in sizes:
+        t0 = time.perf_counter()
+        jac, K, mesh, K_t, f = star_dmg_device(n, seed, dev)
+        t_gen = time.perf_counter() - t0
+        H = dmg.Hierarchy(dmg.assemble_stencil(jac, K))
+        t0 = time.perf_counter()
+        tl = dmg.TwoLevel(H, mesh.xy_c, mesh.xy_p, mesh.tris, mesh.dof, K_t=K_t, nq=0, mass="lumped")
+        torch.cuda.synchronize()
+        t_create = time.perf_counter() - t0
+        ncol, nnz_A, _ = tl.info()
+        fd = torch.as_tensor(f, dtype=torch.float64, device=dev)
+        tl.solve(fd, rtol=1e-10)
+        walls = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            u, k, rel, hist = tl.solve(fd, rtol=1e-10)
+            torch.cuda.synchronize()
+            walls.append(time.perf_counter() - t0)
+        wall = sum(walls) / len(walls)
+        ec = torch.zeros((n, n), dtype=torch.float64, device=dev)
+        rc = torch.zeros_like(ec)
+        rc[1:-1, 1:-1] = 1.0
+        for _ in range(3):
+            H.vcycle(ec, rc)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(20):
+            H.vcycle(ec, rc)
+        e1.record()
+        torch.cuda.synchronize()
+        free = int(mesh.dof.sum())
+        rows.append({"grid": n, "mesh_vertices": int(mesh.nv), "unknowns": free,
+                     "triangles": int(mesh.tris.shape[0]), "colours": ncol, "nnz_A": nnz_A,
+                     "cycles": k, "relres": rel, "rate": round(rel ** (1.0 / k), 4),
+                     "solve_ms": round(1e3 * wall, 3), "ms_per_cycle": round(1e3 * wall / k, 4),
+                     "grid_vcycle_ms": round(e0.elapsed_time(e1) / 20, 4),
+                     "unknowns_per_s": round(free / wall, 1),
+                     "gen_s": round(t_gen, 2), "create_s": round(t_create, 2)})
+        log(f"two-level {n}: {k} cycles, {1e3 * wall:.2f} ms, create {t_create:.1f} s")
+        tl.close()
+        H.close()
+    return {"workload": "star meshes, physical P1 system, lumped mass, exact coupled mass, FP64 grid V(1,1), "
+                        "rtol 1e-10 relative to the initial residual", "sizes": rows}
+
+
 CPU_SNIPPET = r"""
 import json, sys, time
 sys.path.insert(0, {root!r})
@@ -375,6 +432,7 @@ def main():
     ap.add_argument("--no-c4", action="store_true", help="skip the 256-instance batch leg")
     ap.add_argument("--no-c5", action="store_true", help="skip the 2049 x 2049 gradient leg")
     ap.add_argument("--no-transfer", action="store_true", help="skip the grid <-> mesh transfer leg")
+    ap.add_argument("--no-twolevel", action="store_true", help="skip the two-level mesh cycle leg")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -468,6 +526,9 @@ def main():
     if not args.no_transfer:
         log("transfer leg: 1025x1025 grid, ~3.8M-vertex mesh")
         res["transfer"] = run_transfer_leg(dmg, dev)
+    if not args.no_twolevel:
+        log("two-level leg: star meshes at grids 129, 257, 513")
+        res["twolevel"] = run_twolevel_leg(dmg, dev)
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         res["cpu_baseline"] = cpu_baseline(args.n, args.seed)

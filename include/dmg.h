@@ -185,8 +185,9 @@ dmg_status dmg_grad_K(const double* jac, const double* lambda, const double* u, 
  * Create from a P1 mesh given as HOST arrays: xy_c [nv][2] the images T(x_v) in (-1,1)^2,
  * xy_p [nv][2] physical coordinates, tris [nt][3] (int32, any orientation), dof [nv] (uint8,
  * 0 = Dirichlet vertex).  C is assembled by rasterising each mapped triangle over the grid
- * cells it overlaps with an nq x nq Gauss rule per cell (points outside the triangle count as
- * zero; |J_T^{-1}| taken as area(tau_p)/area(mapped tau)); M_p is the P1 mass matrix.  The
+ * cells it overlaps with an nq x nq Gauss rule per cell, nq in [1, 32] (points outside the
+ * triangle count as zero; |J_T^{-1}| taken as area(tau_p)/area(mapped tau)); nq = 0 integrates
+ * exactly over each triangle-cell overlap polygon instead.  M_p is the P1 mass matrix.  The
  * handle owns device memory allocated here (freed by dmg_transfer_destroy); the apply calls
  * allocate nothing.
  * from_grid: u_p = CG2(M_p, C u_c)      u_c [ny][nx] -> u_p [nv]
@@ -239,7 +240,9 @@ void dmg_batch_destroy(dmg_batch* bt);
  * iterations on M_p (Sec. 2.3).  Colours: greedy over the vertices in index order on the mesh
  * graph (unknowns sharing a triangle are neighbours; Dirichlet vertices have none, colour 0);
  * the symmetric sweep updates colours 0..C-1 then C-2..0.
- * Create: mesh arrays on the HOST as for dmg_transfer_create; K_t [nt] host coefficient per
+ * Create: mesh arrays on the HOST and nq as for dmg_transfer_create (nq = 0, the exact overlap
+ * integral, keeps the coarse correction's energy matched to A_p as the mesh is refined; low
+ * quadrature orders let it drift); K_t [nt] host coefficient per
  * triangle (null: 1); grid: a hierarchy built on the nx x ny grid that C maps to (its level-0
  * dims), borrowed -- it must outlive the handle, and no other call may use it while a cycle or
  * solve of this handle runs.  The handle owns device memory allocated here; cycle and solve

@@ -255,9 +255,10 @@ class Transfer:
 class TwoLevel:
     """The two-level cycle on a physical P1 mesh (host mesh arrays) over the grid hierarchy
     ``grid`` (a Hierarchy on the grid that the mesh maps to; it must outlive this object).
+    nq: 0 for the exact coupled mass (default) or the order of the rasterised rule;
     mass: "lumped" or "cg2"."""
 
-    def __init__(self, grid: Hierarchy, xy_c, xy_p, tris, dof, K_t=None, nq: int = 8, mass: str = "lumped"):
+    def __init__(self, grid: Hierarchy, xy_c, xy_p, tris, dof, K_t=None, nq: int = 0, mass: str = "lumped"):
         if mass not in ("lumped", "cg2"):
             raise ValueError("mass must be 'lumped' or 'cg2'")
         self.grid = grid

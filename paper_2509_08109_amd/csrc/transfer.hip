@@ -6,7 +6,9 @@
 // images of its vertices; the grid cells overlapping its bounding box are visited with an
 // nq x nq Gauss rule per cell; quadrature points outside the mapped triangle contribute nothing;
 // inside, the P1 basis is evaluated through the mapped triangle's barycentric coordinates and
-// the Jacobian factor is the constant area(tau_p)/area(mapped tau).  Rows are assembled
+// the Jacobian factor is the constant area(tau_p)/area(mapped tau).  nq = 0 integrates exactly
+// instead: the mapped triangle is clipped against each cell and the cubic integrand is
+// integrated over the overlap polygon (the limit of the rasterised rule).  Rows are assembled
 // independently (vertex -> incident triangles) on host threads, giving CSR directly.
 // M_p is the P1 mass matrix (element matrix area/12 [[2,1,1],[1,2,1],[1,1,2]]).
 // Dirichlet vertices: empty rows of C, identity rows of M_p.  Grid boundary columns dropped.
@@ -90,9 +92,121 @@ double tri_area2(const double* xy, const int* tv) {
 
 namespace {
 
+// Part of triangle tri inside the box [x0, x1] x [y0, y1] (Sutherland-Hodgman, one pass per box
+// side); returns its vertex count (a triangle cut by four half-planes keeps at most 7).
+int clip_triangle(const double tri[3][2], double x0, double x1, double y0, double y1,
+                  double out[8][2]) {
+  double a[8][2], b[8][2];
+  int n = 3;
+  for (int k = 0; k < 3; ++k) {
+    a[k][0] = tri[k][0];
+    a[k][1] = tri[k][1];
+  }
+  // keep the side where sign * (p[axis] - lim) >= 0
+  auto pass = [](const double (*src)[2], int ns, double (*dst)[2], int axis, double lim,
+                 double sign) {
+    int nd = 0;
+    for (int k = 0; k < ns; ++k) {
+      const double* p = src[(k + ns - 1) % ns];
+      const double* q = src[k];
+      const bool ip = sign * (p[axis] - lim) >= 0.0, iq = sign * (q[axis] - lim) >= 0.0;
+      if (ip != iq) {
+        const double t = (lim - p[axis]) / (q[axis] - p[axis]);
+        dst[nd][axis] = lim;
+        dst[nd][1 - axis] = p[1 - axis] + t * (q[1 - axis] - p[1 - axis]);
+        ++nd;
+      }
+      if (iq) {
+        dst[nd][0] = q[0];
+        dst[nd][1] = q[1];
+        ++nd;
+      }
+    }
+    return nd;
+  };
+  n = pass(a, n, b, 0, x0, 1.0);
+  n = n ? pass(b, n, a, 0, x1, -1.0) : 0;
+  n = n ? pass(a, n, b, 1, y0, 1.0) : 0;
+  n = n ? pass(b, n, a, 1, y1, -1.0) : 0;
+  for (int k = 0; k < n; ++k) {
+    out[k][0] = a[k][0];
+    out[k][1] = a[k][1];
+  }
+  return n;
+}
+
+// Dunavant's symmetric 6-point rule on a triangle, exact for degree 4: barycentric orbits
+// (a, a, 1 - 2a) with weights relative to the area.
+constexpr double kTriA1 = 0.445948490915965, kTriW1 = 0.223381589678011;
+constexpr double kTriA2 = 0.091576213509771, kTriW2 = 1.0 / 3.0 - kTriW1;
+
+// Row v of C from triangle tv (a = v's slot in tv) integrated exactly over the overlap of the
+// mapped triangle with each grid cell: the integrand lambda_a * phi_g is a cubic there.
+template <class Acc>
+void exact_row_triangle(const Mesh& m, const int* tv, int a, double hx, double hy, int nx, int ny,
+                        double jac, Acc&& acc) {
+  double tri[3][2];
+  for (int k = 0; k < 3; ++k) {
+    tri[k][0] = m.xy_c[2 * tv[k]];
+    tri[k][1] = m.xy_c[2 * tv[k] + 1];
+  }
+  const double det = (tri[1][0] - tri[0][0]) * (tri[2][1] - tri[0][1]) -
+                     (tri[2][0] - tri[0][0]) * (tri[1][1] - tri[0][1]);
+  // lambda_a(X, Y) = (e0 + e1 X + e2 Y) / det from the edge opposite vertex a
+  const double* p = tri[(a + 1) % 3];
+  const double* q = tri[(a + 2) % 3];
+  const double e1 = p[1] - q[1], e2 = q[0] - p[0], e0 = p[0] * q[1] - q[0] * p[1];
+  const double xmin = std::min({tri[0][0], tri[1][0], tri[2][0]});
+  const double xmax = std::max({tri[0][0], tri[1][0], tri[2][0]});
+  const double ymin = std::min({tri[0][1], tri[1][1], tri[2][1]});
+  const double ymax = std::max({tri[0][1], tri[1][1], tri[2][1]});
+  auto cell = [](double x, double h, int n) {
+    const int c = int(std::floor((x + 1.0) / h));
+    return std::min(std::max(c, 0), n - 2);
+  };
+  const int i0 = cell(xmin, hx, nx), i1 = cell(xmax, hx, nx);
+  const int j0 = cell(ymin, hy, ny), j1 = cell(ymax, hy, ny);
+  static const double orbit[2][2] = {{kTriA1, kTriW1}, {kTriA2, kTriW2}};
+  double poly[8][2];
+  for (int cj = j0; cj <= j1; ++cj)
+    for (int ci = i0; ci <= i1; ++ci) {
+      const double X0 = -1.0 + ci * hx, Y0 = -1.0 + cj * hy;
+      const int np = clip_triangle(tri, X0, X0 + hx, Y0, Y0 + hy, poly);
+      if (np < 3) continue;
+      double w4[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int k = 1; k + 1 < np; ++k) {
+        const double* A = poly[0];
+        const double* B = poly[k];
+        const double* D = poly[k + 1];
+        const double area =
+            0.5 * std::fabs((B[0] - A[0]) * (D[1] - A[1]) - (D[0] - A[0]) * (B[1] - A[1]));
+        if (area == 0.0) continue;
+        for (const auto& o : orbit) {
+          const double la = o[0], lb = 1.0 - 2.0 * o[0];
+          const double bary[3][3] = {{la, la, lb}, {la, lb, la}, {lb, la, la}};
+          for (const auto& l : bary) {
+            const double X = l[0] * A[0] + l[1] * B[0] + l[2] * D[0];
+            const double Y = l[0] * A[1] + l[1] * B[1] + l[2] * D[1];
+            const double w = o[1] * area * (e0 + e1 * X + e2 * Y) / det;
+            const double s = (X - X0) / hx, t = (Y - Y0) / hy;
+            w4[0] += w * (1 - s) * (1 - t);
+            w4[1] += w * s * (1 - t);
+            w4[2] += w * (1 - s) * t;
+            w4[3] += w * s * t;
+          }
+        }
+      }
+      const int g00 = cj * nx + ci;
+      const int gi[4] = {g00, g00 + 1, g00 + nx, g00 + nx + 1};
+      for (int g = 0; g < 4; ++g) acc(gi[g], jac * w4[g]);
+    }
+}
+
+// nq >= 1: the rasterised rule (nq x nq Gauss points per overlapped cell, zero outside the
+// mapped triangle); nq == 0: exact integration over the triangle-cell overlaps.
 Csr assemble_C(const Mesh& m, int nx, int ny, int nq) {
   std::vector<double> qx, qw;
-  gauss01(nq, qx, qw);
+  if (nq > 0) gauss01(nq, qx, qw);
   const double hx = 2.0 / (nx - 1), hy = 2.0 / (ny - 1);
   unsigned nthreads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   if (m.nv < 4096) nthreads = 1;
@@ -116,6 +230,14 @@ Csr assemble_C(const Mesh& m, int nx, int ny, int nq) {
             const double ac2 = tri_area2(m.xy_c, tv);
             if (ac2 == 0.0) continue;
             const double jac = std::fabs(tri_area2(m.xy_p, tv)) / std::fabs(ac2);
+            if (nq == 0) {
+              exact_row_triangle(m, tv, a, hx, hy, nx, ny, jac, [&](int g, double val) {
+                const int gx = g % nx, gy = g / nx;
+                if (gx == 0 || gx == nx - 1 || gy == 0 || gy == ny - 1) return;
+                row[g] += val;
+              });
+              continue;
+            }
             const double* c0 = m.xy_c + 2 * tv[0];
             const double* c1 = m.xy_c + 2 * tv[1];
             const double* c2 = m.xy_c + 2 * tv[2];
@@ -524,7 +646,7 @@ dmg_status dmg_transfer_create(int32_t nv, int32_t nt, const double* xy_c, const
   if (!xy_c || !xy_p || !tris || !dof) return fail(DMG_ERR_INVALID_ARG, "null mesh array");
   if (nv <= 0 || nt <= 0) return fail(DMG_ERR_INVALID_ARG, "empty mesh (nv=%d, nt=%d)", nv, nt);
   if (nx < 3 || ny < 3) return fail(DMG_ERR_DIMS, "grid dims must be >= 3");
-  if (nq < 1 || nq > 32) return fail(DMG_ERR_INVALID_ARG, "nq must be in [1,32]");
+  if (nq < 0 || nq > 32) return fail(DMG_ERR_INVALID_ARG, "nq must be in [0,32]");
   for (int64_t k = 0; k < int64_t(nt) * 3; ++k)
     if (tris[k] < 0 || tris[k] >= nv)
       return fail(DMG_ERR_INVALID_ARG, "triangle vertex index %d out of range", tris[k]);

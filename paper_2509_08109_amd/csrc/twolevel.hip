@@ -365,7 +365,7 @@ dmg_status dmg_twolevel_create(int32_t nv, int32_t nt, const double* xy_c, const
   *out = nullptr;
   if (!xy_c || !xy_p || !tris || !dof || !grid) return fail(DMG_ERR_INVALID_ARG, "null argument");
   if (nv <= 0 || nt <= 0) return fail(DMG_ERR_INVALID_ARG, "empty mesh (nv=%d, nt=%d)", nv, nt);
-  if (nq < 1 || nq > 32) return fail(DMG_ERR_INVALID_ARG, "nq must be in [1,32]");
+  if (nq < 0 || nq > 32) return fail(DMG_ERR_INVALID_ARG, "nq must be in [0,32]");
   if (mass != 0 && mass != 2) return fail(DMG_ERR_INVALID_ARG, "mass must be 0 (lumped) or 2 (CG2)");
   for (int64_t k = 0; k < int64_t(nt) * 3; ++k)
     if (tris[k] < 0 || tris[k] >= nv)

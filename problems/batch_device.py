@@ -135,3 +135,36 @@ def star_device(n: int, seed: int = 1, device="cuda"):
     jac = torch.stack([J[e][q] for q in range(4) for e in range(4)])
     b = torch.as_tensor(uniform_rhs(n, n, g_b), dtype=torch.float64, device=device)
     return jac.contiguous(), K.contiguous(), b
+
+
+def lognormal_at_device(x, y, omega, phase, device, sigma: float = 1.0) -> np.ndarray:
+    """``fields.lognormal_at`` evaluated with torch on ``device`` (host arrays in and out)."""
+    import torch
+
+    om = torch.as_tensor(omega, dtype=torch.float64, device=device)
+    ph = torch.as_tensor(phase, dtype=torch.float64, device=device)
+    pts = torch.as_tensor(np.stack([np.ravel(x), np.ravel(y)], axis=1), dtype=torch.float64,
+                          device=device)
+    g = torch.empty(pts.shape[0], dtype=torch.float64, device=device)
+    chunk = 1 << 16
+    scale = sigma * math.sqrt(2.0 / omega.shape[0])
+    for s in range(0, pts.shape[0], chunk):
+        g[s:s + chunk] = scale * torch.cos(pts[s:s + chunk] @ om.T + ph).sum(dim=1)
+    return torch.exp(g).cpu().numpy().reshape(np.shape(x))
+
+
+def star_dmg_device(n: int, seed: int = 1, device="cuda"):
+    """The inputs of ``problems.star_dmg(n, seed)`` with the coefficient fields evaluated on
+    ``device``: (jac [16][n-1][n-1], K [n-1][n-1]) as float64 tensors there, and the mesh, the
+    per-triangle K_t and the right-hand side f on the host."""
+    from . import lognormal_features, mesh_points_for_grid, lattice_mesh, streams
+
+    jac, K, _ = star_device(n, seed, device)
+    g = streams(seed, 7)
+    mp = Star.random(streams(seed)[0])
+    mesh = lattice_mesh(mp, mesh_points_for_grid(n), g[5])
+    cen = mesh.xy_p[mesh.tris].mean(axis=1)
+    omega, phase = lognormal_features(streams(seed)[1])
+    K_t = lognormal_at_device(cen[:, 0], cen[:, 1], omega, phase, device)
+    f = np.where(mesh.dof, g[6].uniform(-1.0, 1.0, size=mesh.dof.shape[0]), 0.0)
+    return jac, K, mesh, K_t, f

@@ -38,20 +38,21 @@ def relerr(a, b):
 _CACHE = {}
 
 
-def pair(lib, n, seed=1, mass="lumped"):
-    """(problem, oracle two-level, GPU two-level) on the star mesh of grid size n."""
-    key = (n, seed, mass)
+def pair(lib, n, seed=1, mass="lumped", nq=0):
+    """(problem, oracle two-level, GPU two-level) on the star mesh of grid size n; nq = 0 is the
+    exact coupled mass, nq > 0 the rasterised rule of that order."""
+    key = (n, seed, mass, nq)
     if key not in _CACHE:
         P = pb.star_dmg(n, seed=seed)
         m = P.mesh
         A = dmg.p1_stiffness(m.xy_p, m.tris, m.dof, P.K_t)
         M = transfer.p1_mass(m.xy_p, m.tris, m.dof)
-        Cm = transfer.coupled_mass(m.xy_c, m.xy_p, m.tris, m.dof, n, n, nq=8)
+        Cm = transfer.coupled_mass(m.xy_c, m.xy_p, m.tris, m.dof, n, n, nq=nq)
         grid = cycle.Oracle(boxmg.build_hierarchy(fem.assemble_stencil(P.grid.jac, P.grid.K, n, n)))
         orc = dmg.TwoLevel(A, M, Cm, grid, n, n, dmg.mesh_colouring(m.tris, m.dof),
                            mass="lumped" if mass == "lumped" else 2)
         H = lib.Hierarchy(lib.assemble_stencil(dev(P.grid.jac), dev(P.grid.K)))
-        tl = lib.TwoLevel(H, m.xy_c, m.xy_p, m.tris, m.dof, K_t=P.K_t, nq=8, mass=mass)
+        tl = lib.TwoLevel(H, m.xy_c, m.xy_p, m.tris, m.dof, K_t=P.K_t, nq=nq, mass=mass)
         _CACHE[key] = (P, orc, tl)
     return _CACHE[key]
 
@@ -64,9 +65,12 @@ def test_colouring_and_operator_size(lib):
     assert nnz == orc.A.nnz
 
 
-@pytest.mark.parametrize("n,mass", [(17, "lumped"), (33, "lumped"), (17, "cg2"), (33, "cg2")])
-def test_cycles_match_oracle(lib, n, mass):
-    P, orc, tl = pair(lib, n, mass=mass)
+@pytest.mark.parametrize("n,mass,nq", [(17, "lumped", 0), (33, "lumped", 0), (17, "cg2", 0),
+                                       (33, "cg2", 0), (33, "lumped", 8), (65, "lumped", 0)])
+def test_cycles_match_oracle(lib, n, mass, nq):
+    """65 x 65 is the smallest grid whose finest level runs in the strip kernels (smaller grids
+    run whole in the one-workgroup coarse kernel)."""
+    P, orc, tl = pair(lib, n, mass=mass, nq=nq)
     g = np.random.Generator(np.random.PCG64(11))
     u0 = np.where(P.mesh.dof, g.uniform(-1, 1, P.mesh.nv), 0.0)
     uo = u0.copy()

@@ -116,7 +116,8 @@ def test_transfer_validation_on_host(dmg):
                                  9, 9, 4, None, C.byref(h))
     assert st == 1 and "out of range" in lib.dmg_last_error().decode()
     assert lib.dmg_transfer_create(3, 1, xy.ctypes.data, xy.ctypes.data, tris.ctypes.data, dof.ctypes.data,
-                                   9, 9, 0, None, C.byref(h)) == 1
+                                   9, 9, -1, None, C.byref(h)) == 1
+    assert "nq" in lib.dmg_last_error().decode()
 
 
 def test_twolevel_validation_on_host(dmg):
@@ -132,7 +133,7 @@ def test_twolevel_validation_on_host(dmg):
     assert lib.dmg_twolevel_create(*args(tris, xy), None, None, 8, 0, None, C.byref(h)) == 1
     assert lib.dmg_twolevel_create(*args(tris, xy), None, fake, 8, 3, None, C.byref(h)) == 1
     assert "mass" in lib.dmg_last_error().decode()
-    assert lib.dmg_twolevel_create(*args(tris, xy), None, fake, 0, 0, None, C.byref(h)) == 1
+    assert lib.dmg_twolevel_create(*args(tris, xy), None, fake, -1, 0, None, C.byref(h)) == 1
     bad = np.array([[0, 1, 7]], dtype=np.int32)
     assert lib.dmg_twolevel_create(*args(bad, xy), None, fake, 8, 0, None, C.byref(h)) == 1
     assert "out of range" in lib.dmg_last_error().decode()

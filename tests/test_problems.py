@@ -158,3 +158,16 @@ def test_device_star_and_patches_reproduce_host_star():
     assert np.allclose(sample_jacobian_patch(p.map, 33, 6, 10, 8), p.jac[:, 10:18, 6:14], rtol=1e-14, atol=1e-15)
     Kp = lognormal_K_patch(p.map, 33, 6, 10, 8, pb.streams(3)[1])
     assert np.allclose(Kp, p.K[10:18, 6:14], rtol=1e-12)
+
+
+def test_device_star_dmg_reproduces_host_star_dmg():
+    """star_dmg_device draws the inputs of problems.star_dmg (fields evaluated with torch)."""
+    from problems.batch_device import star_dmg_device
+    P = pb.star_dmg(17, seed=2)
+    jac, K, mesh, K_t, f = star_dmg_device(17, seed=2, device="cpu")
+    assert np.array_equal(mesh.tris, P.mesh.tris) and np.array_equal(mesh.dof, P.mesh.dof)
+    assert np.array_equal(mesh.xy_c, P.mesh.xy_c) and np.array_equal(mesh.xy_p, P.mesh.xy_p)
+    assert np.array_equal(f, P.f)
+    assert np.allclose(K_t, P.K_t, rtol=1e-12, atol=0)
+    assert np.allclose(jac.numpy(), P.grid.jac, rtol=1e-12, atol=1e-14)
+    assert np.allclose(K.numpy(), P.grid.K, rtol=1e-12, atol=0)
