@@ -30,13 +30,17 @@ Readings where the paper is silent or where its choice fails on these inputs:
     coupling cancels to exactly zero (right angles opposite an edge do that);
   * stopping test: ||f - A u||_2 <= rtol ||f - A u_0||_2 (the paper runs f = 0 from a random
     initial guess, so the test is relative to the initial residual);
-  * coarse-grid scaling: gamma = 1 (Sec. 2.4's scaling is not applied).
+  * coarse-grid scaling (Sec. 2.4): u_p += gamma P u_c with gamma = 1 unless set; gamma is
+    estimated as the mean of the Ritz values of k steps of the generalized Lanczos recurrence
+    for P^T A_p P x = lambda A_c x (the paper's k = 12), which is trace(T_k) / k, from a
+    caller-supplied start vector on the interior grid points.
 Dirichlet vertices carry identity rows, so they keep u = f (= 0).
 """
 from __future__ import annotations
 
 import numpy as np
 import scipy.sparse as spx
+import scipy.sparse.linalg as spl
 
 from . import transfer
 
@@ -137,6 +141,7 @@ class TwoLevel:
         self.colour = np.asarray(colour)
         self.mass = mass
         self.ML = lumped(M_p)
+        self.gamma = 1.0
 
     def _minv(self, y):
         if self.mass == "lumped":
@@ -149,9 +154,59 @@ class TwoLevel:
         rc = self.C.T @ self._minv(r)                      # P^T r
         ec = np.zeros(self.nx * self.ny)
         self.grid.vcycle(ec, rc)
-        u += self._minv(self.C @ ec)                       # P e_c
+        u += self.gamma * self._minv(self.C @ ec)          # gamma P e_c
         sgs(self.A, u, f, self.colour)
         return u
+
+
+def lanczos_mean(apply_G, solve_A, apply_A, v0: np.ndarray, k: int):
+    """k steps of the Lanczos recurrence for the pencil G x = lambda A x (A SPD, G symmetric) in
+    the A-inner product, from v0:
+        v_1 = v0 / |v0|_A;  w = A^{-1} G v_j;  alpha_j = (G v_j) . v_j;
+        w -= alpha_j v_j + beta_{j-1} v_{j-1};  beta_j = |w|_A;  v_{j+1} = w / beta_j.
+    The recurrence stops early when the Krylov space is invariant (beta_j <= 1e-13 |alpha_j|):
+    the Ritz values found are then eigenvalues of the pencil.  Returns (mean of the Ritz values =
+    trace(T_m) / m, the m x m tridiagonal T_m), m <= k the steps taken."""
+    v = np.asarray(v0, dtype=np.float64).copy()
+    Av = apply_A(v)
+    nrm = np.sqrt(float(v @ Av))
+    v, Av = v / nrm, Av / nrm
+    v_prev, Av_prev, beta = np.zeros_like(v), np.zeros_like(v), 0.0
+    alphas, betas = [], []
+    for j in range(k):
+        g = apply_G(v)
+        alpha = float(g @ v)
+        w = solve_A(g) - alpha * v - beta * v_prev
+        Aw = g - alpha * Av - beta * Av_prev                # = A w for the exact solve
+        alphas.append(alpha)
+        if j + 1 == k:
+            break
+        beta = np.sqrt(max(float(w @ Aw), 0.0))
+        if not beta > 1e-13 * abs(alpha):
+            break
+        betas.append(beta)
+        v_prev, Av_prev = v, Av
+        v, Av = w / beta, Aw / beta
+    T = np.diag(alphas) + np.diag(betas, 1) + np.diag(betas, -1)
+    return float(np.mean(alphas)), T
+
+
+def coarse_scaling(tl: TwoLevel, v0: np.ndarray, k: int = 12):
+    """Sec. 2.4's gamma for the lumped-mass cycle: the generalized Lanczos mean of
+    P^T A_p P x = lambda A_c x over the interior grid unknowns (A_c the grid operator, solved
+    exactly), from v0 (a grid vector; its boundary ring is ignored).  Returns (gamma, T_k)."""
+    if tl.mass != "lumped":
+        raise ValueError("the scaling estimate is defined for the linear (lumped) transfer")
+    nx, ny = tl.nx, tl.ny
+    inner = np.zeros((ny, nx), dtype=bool)
+    inner[1:-1, 1:-1] = True
+    ii = np.nonzero(inner.ravel())[0]
+    Ac = spx.csr_matrix(tl.grid.levels[0].A)[ii][:, ii].tocsc()
+    lu = spl.splu(Ac)
+    P = (spx.diags(1.0 / tl.ML) @ tl.C).tocsr()[:, ii]     # lumped P restricted to the unknowns
+    G = (P.T @ tl.A @ P).tocsr()
+    return lanczos_mean(lambda x: G @ x, lu.solve, lambda x: Ac @ x,
+                        np.asarray(v0, dtype=np.float64).ravel()[ii], k)
 
 
 def solve(tl: TwoLevel, f: np.ndarray, u0: np.ndarray | None = None, rtol: float = 1e-10,

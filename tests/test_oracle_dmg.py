@@ -100,3 +100,62 @@ def test_two_level_rate_does_not_grow_with_size():
         rates.append(cycle.convergence_factor(hist))
         counts.append(k)
     assert max(rates) < 0.3 and abs(counts[1] - counts[0]) <= 3
+
+
+def _dense_pencil(n, seed):
+    g = np.random.Generator(np.random.PCG64(seed))
+    Q = g.normal(size=(n, n))
+    A = Q @ Q.T + n * np.eye(n)                       # SPD
+    B = g.normal(size=(n, n))
+    G = B @ B.T                                       # symmetric positive semidefinite
+    return A, G, g.normal(size=n)
+
+
+def test_lanczos_mean_over_the_whole_space_is_the_eigenvalue_mean():
+    """k = n steps span the space: T_n is similar to A^{-1} G, so its trace / n is the mean of
+    all generalized eigenvalues (scipy.linalg.eigh of the pencil) and its eigenvalues are them."""
+    import scipy.linalg as sla
+    A, G, v0 = _dense_pencil(8, 3)
+    gam, T = dmg.lanczos_mean(lambda x: G @ x, lambda y: np.linalg.solve(A, y), lambda x: A @ x, v0, 8)
+    lam = sla.eigh(G, A, eigvals_only=True)
+    assert abs(gam - lam.mean()) <= 1e-12 * abs(lam.mean())
+    assert np.allclose(np.sort(np.linalg.eigvalsh(T)), lam, rtol=1e-9, atol=1e-12)
+
+
+def test_lanczos_mean_special_cases():
+    A, G, v0 = _dense_pencil(10, 4)
+    # G = c A: every generalized eigenvalue is c; the space is invariant after one step
+    gam, T = dmg.lanczos_mean(lambda x: 2.5 * (A @ x), lambda y: np.linalg.solve(A, y), lambda x: A @ x, v0, 4)
+    assert abs(gam - 2.5) <= 1e-13 and T.shape == (1, 1)
+    # k < n: Ritz values lie inside the pencil's spectrum (Cauchy interlacing)
+    import scipy.linalg as sla
+    lam = sla.eigh(G, A, eigvals_only=True)
+    gam, T = dmg.lanczos_mean(lambda x: G @ x, lambda y: np.linalg.solve(A, y), lambda x: A @ x, v0, 5)
+    ritz = np.linalg.eigvalsh(T)
+    assert ritz.min() >= lam.min() - 1e-12 and ritz.max() <= lam.max() + 1e-12
+    assert T.shape == (5, 5) and np.allclose(T, T.T)
+
+
+def test_coarse_scaling_of_the_two_level_cycle():
+    """gamma of the star mesh lies inside the range of the generalized eigenvalues (computed
+    independently by scipy's eigsh on the same pencil); with gamma = 0 the cycle drops its coarse
+    correction and is two symmetric Gauss-Seidel sweeps."""
+    P, A, M, C, tl = _setup(17)
+    g = np.random.Generator(np.random.PCG64(9))
+    v0 = g.uniform(-1, 1, (17, 17))
+    gam, T = dmg.coarse_scaling(tl, v0, 12)
+    ii = np.nonzero(np.pad(np.ones((15, 15), bool), 1).ravel())[0]
+    Ac = tl.grid.levels[0].A.tocsr()[ii][:, ii]
+    Pm = (spx.diags(1.0 / tl.ML) @ tl.C).tocsr()[:, ii]
+    Gm = (Pm.T @ tl.A @ Pm).tocsr()
+    hi = spl.eigsh(Gm, k=1, M=Ac.tocsc(), which="LA", return_eigenvectors=False)[0]
+    lo = spl.eigsh(Gm, k=1, M=Ac.tocsc(), sigma=0.0, which="LM", return_eigenvectors=False)[0]
+    assert lo - 1e-10 <= gam <= hi + 1e-10
+    assert np.all(np.linalg.eigvalsh(T) <= hi + 1e-10) and np.all(np.linalg.eigvalsh(T) >= lo - 1e-10)
+    u0 = np.where(P.mesh.dof, g.uniform(-1, 1, P.mesh.nv), 0.0)
+    tl.gamma = 0.0
+    u_g0 = tl.cycle(u0.copy(), P.f)
+    tl.gamma = 1.0
+    u_s = dmg.sgs(tl.A, dmg.sgs(tl.A, u0.copy(), P.f, tl.colour), P.f, tl.colour)
+    assert np.array_equal(u_g0, u_s)
+    assert not np.allclose(tl.cycle(u0.copy(), P.f), u_s)
