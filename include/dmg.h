@@ -267,6 +267,21 @@ dmg_status dmg_twolevel_cycle(dmg_twolevel* tl, double* u_p, const double* f_p,
 dmg_status dmg_twolevel_solve(dmg_twolevel* tl, double* u_p, const double* f_p, double rtol,
                               int32_t max_iters, int32_t* iters, double* relres, double* history,
                               hipStream_t stream);
+/* Coarse-grid scaling (Sec. 2.4): set_scaling makes later cycles add gamma P e_c (default 1;
+ * any finite value).  scaling estimates gamma as the mean of the Ritz values of k steps
+ * (k in [1, 64]; the paper's k = 12) of the generalized Lanczos recurrence for
+ * P^T A_p P x = lambda A_c x in the A_c-inner product, i.e. trace(T_k) / k, started from the
+ * interior part of v0 (device [ny][nx], caller-chosen, e.g. seeded uniform values).  Each step
+ * applies P^T A_p P once and solves with A_c by the grid hierarchy's float64 solve (relative
+ * residual 1e-13); the recurrence stops early when the Krylov space is invariant
+ * (beta_j <= 1e-13 |alpha_j|).  gamma (host) receives the estimate, steps (nullable) the steps
+ * taken m, T (host, nullable, [k][k]) the m x m tridiagonal in its leading block, zeros
+ * elsewhere.  The estimate does not change the handle's gamma.  Lumped mass only
+ * (DMG_ERR_UNSUPPORTED for CG2, whose P is not linear).  Synchronous; allocates and frees
+ * scratch for six grid vectors. */
+dmg_status dmg_twolevel_set_scaling(dmg_twolevel* tl, double gamma);
+dmg_status dmg_twolevel_scaling(dmg_twolevel* tl, const double* v0, int32_t k, double* gamma,
+                                double* T, int32_t* steps, hipStream_t stream);
 void dmg_twolevel_destroy(dmg_twolevel* tl);
 
 #ifdef __cplusplus

@@ -292,6 +292,20 @@ class TwoLevel:
         _lib.check(lib().dmg_twolevel_info(self._h, C.byref(nc), C.byref(nnz), col.ctypes.data))
         return int(nc.value), int(nnz.value), col
 
+    def set_scaling(self, gamma: float) -> None:
+        """Coarse-grid scaling: later cycles add gamma P e_c."""
+        _lib.check(lib().dmg_twolevel_set_scaling(self._h, float(gamma)))
+
+    def estimate_scaling(self, v0: torch.Tensor, k: int = 12):
+        """Generalized Lanczos estimate of gamma from the start vector v0 [ny][nx];
+        returns (gamma, T) with T the tridiagonal of the steps taken."""
+        shp = (self.grid.ny, self.grid.nx)
+        T = np.zeros((k, k))
+        gam, m = C.c_double(), C.c_int32()
+        _lib.check(lib().dmg_twolevel_scaling(self._h, _dev(v0, shp, "v0"), int(k), C.byref(gam),
+                                              T.ctypes.data, C.byref(m), _stream(self.device)))
+        return float(gam.value), T[:m.value, :m.value].copy()
+
     def cycle(self, u: torch.Tensor, f: torch.Tensor) -> torch.Tensor:
         """One cycle on u (in place)."""
         _lib.check(lib().dmg_twolevel_cycle(self._h, _dev(u, (self.nv,), "u"), _dev(f, (self.nv,), "f"),

@@ -61,6 +61,8 @@ SIGNATURES = {
     "dmg_twolevel_info": (_st, [_p, C.POINTER(_i32), C.POINTER(C.c_int64), _p]),
     "dmg_twolevel_cycle": (_st, [_p, _p, _p, _p]),
     "dmg_twolevel_solve": (_st, [_p, _p, _p, C.c_double, _i32, C.POINTER(_i32), C.POINTER(C.c_double), _p, _p]),
+    "dmg_twolevel_set_scaling": (_st, [_p, C.c_double]),
+    "dmg_twolevel_scaling": (_st, [_p, _p, _i32, C.POINTER(C.c_double), _p, C.POINTER(_i32), _p]),
     "dmg_twolevel_destroy": (None, [_p]),
     "dmg_batch_workspace_bytes": (_st, [_i32, _p, _p, C.POINTER(Options), C.POINTER(C.c_size_t)]),
     "dmg_batch_setup": (_st, [_i32, _p, _p, _p, C.POINTER(Options), _p, C.c_size_t, _p, C.POINTER(_p)]),

@@ -21,6 +21,21 @@ __device__ __forceinline__ T offdiag(const T* __restrict__ S, const T* __restric
 }
 
 
+// y = A x on interior rows; the boundary ring of y is set to 0.
+__global__ __launch_bounds__(256) void k_stencil_apply(const double* __restrict__ S,
+                                                       const double* __restrict__ x,
+                                                       double* __restrict__ y, int nx, int ny) {
+  const size_t N = size_t(nx) * ny;
+  for (size_t v = blockIdx.x * size_t(blockDim.x) + threadIdx.x; v < N;
+       v += size_t(gridDim.x) * blockDim.x) {
+    const int j = int(v / nx), i = int(v % nx);
+    if (i > 0 && i < nx - 1 && j > 0 && j < ny - 1)
+      y[v] = offdiag(S, x, N, nx, v) + S[v] * x[v];
+    else
+      y[v] = 0.0;
+  }
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void k_copy(const T* __restrict__ x, T* __restrict__ y, size_t n,
                                               const int* __restrict__ stop) {
@@ -293,6 +308,12 @@ dmg_status launch_sq_partials(const double* x, size_t, int nx, int ny, double* p
                               hipStream_t s) {
   k_sq<<<kReduceBlocks, 256, 0, s>>>(x, nx, ny, partials);
   return launch_check("sq");
+}
+
+dmg_status launch_stencil_apply(const double* S, const double* x, double* y, int nx, int ny,
+                                hipStream_t s) {
+  k_stencil_apply<<<stride_blocks(size_t(nx) * ny), 256, 0, s>>>(S, x, y, nx, ny);
+  return launch_check("stencil_apply");
 }
 
 dmg_status launch_finalize(const double* partials, double* out, hipStream_t s, int count) {

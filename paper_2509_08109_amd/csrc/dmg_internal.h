@@ -319,6 +319,11 @@ dmg_status launch_resid_multi(const NormArgs* list, int count, int blocks_per, h
 dmg_status launch_check_step(const double* partials, int count, double* out, const double* sc,
                              int* st, double* hist, int hist_cap, hipStream_t s);
 
+// y = A x for the planar stencil S [5][ny][nx] on interior rows (boundary ring of y set to 0;
+// x is read at the boundary ring as the stencil's couplings there are zero)
+dmg_status launch_stencil_apply(const double* S, const double* x, double* y, int nx, int ny,
+                                hipStream_t s);
+
 // One float64 V-cycle of hierarchy h on level-0 arrays (u, b); u_zero: start from u = 0
 // without reading u.  Every kernel is a no-op once *stop (nullable) is set.
 dmg_status grid_vcycle(dmg_hier* h, double* u, const double* b, bool u_zero, const int* stop,

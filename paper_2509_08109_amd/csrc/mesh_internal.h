@@ -96,8 +96,10 @@ enum class X2Mode { kStore, kScatter, kAdd };
 // stop (nullable device flag): every kernel below is a no-op once it is set.
 // t->r = dof * (C u_c) and its squared-norm partials: the start of from_grid.
 dmg_status launch_from_start(dmg_transfer* t, const double* u_c, const int* stop, hipStream_t s);
-// Two CG iterations on M_p from x = 0, continuing from r0 in t->r with its partials.
-dmg_status cg2_tail(dmg_transfer* t, double* out, X2Mode mode, const int* stop, hipStream_t s);
+// Two CG iterations on M_p from x = 0, continuing from r0 in t->r with its partials; the add
+// mode adds scale * x2.
+dmg_status cg2_tail(dmg_transfer* t, double* out, X2Mode mode, const int* stop, hipStream_t s,
+                    double scale = 1.0);
 // r_c = C^T x over the grid rows (x in the internal order).
 dmg_status launch_ct(dmg_transfer* t, const double* x, double* r_c, const int* stop, hipStream_t s);
 

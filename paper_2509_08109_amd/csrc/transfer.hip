@@ -452,14 +452,14 @@ __global__ __launch_bounds__(256) void k_t_mp1(const int* __restrict__ rp, const
 }
 
 // x2 = alpha0 r0 + alpha1 p1, stored in the internal order, scattered to the caller's order
-// (out[perm[r]]), or added into an internal-order vector
+// (out[perm[r]]), or added (times scale) into an internal-order vector
 template <X2Mode MODE>
 __global__ __launch_bounds__(256) void k_t_x(const double* __restrict__ r0,
                                              const double* __restrict__ r1,
                                              const double* __restrict__ sc,
                                              const int* __restrict__ perm,
                                              double* __restrict__ out, int n,
-                                             const int* __restrict__ stop) {
+                                             const int* __restrict__ stop, double scale) {
   if (stopped(stop)) return;
   const double alpha0 = cg_alpha0(sc), beta = cg_beta(sc), alpha1 = cg_alpha1(sc);
   for (int r = blockIdx.x * 256 + threadIdx.x; r < n; r += gridDim.x * 256) {
@@ -467,7 +467,7 @@ __global__ __launch_bounds__(256) void k_t_x(const double* __restrict__ r0,
     const double p1 = __builtin_fma(beta, r0[r], r1[r]);
     const double x2 = __builtin_fma(alpha1, p1, x1);
     if constexpr (MODE == X2Mode::kScatter) out[perm[r]] = x2;
-    else if constexpr (MODE == X2Mode::kAdd) out[r] += x2;
+    else if constexpr (MODE == X2Mode::kAdd) out[r] += scale * x2;
     else out[r] = x2;
   }
 }
@@ -495,7 +495,8 @@ dmg_status launch_from_start(dmg_transfer* t, const double* u_c, const int* stop
   return launch_check("transfer C u");
 }
 
-dmg_status cg2_tail(dmg_transfer* t, double* out, X2Mode mode, const int* stop, hipStream_t s) {
+dmg_status cg2_tail(dmg_transfer* t, double* out, X2Mode mode, const int* stop, hipStream_t s,
+                    double scale) {
   const int n = t->nv, nb = tblocks(n, kMG);
   double* sc = t->scal;
   DMG_CHECK(launch_finalize(t->partials, sc + 0, s, nb));
@@ -510,13 +511,13 @@ dmg_status cg2_tail(dmg_transfer* t, double* out, X2Mode mode, const int* stop, 
   DMG_CHECK(launch_finalize(t->partials, sc + 6, s, nb));
   switch (mode) {
     case X2Mode::kStore:
-      k_t_x<X2Mode::kStore><<<nb, 256, 0, s>>>(t->r, t->p, sc, t->perm, out, n, stop);
+      k_t_x<X2Mode::kStore><<<nb, 256, 0, s>>>(t->r, t->p, sc, t->perm, out, n, stop, 1.0);
       break;
     case X2Mode::kScatter:
-      k_t_x<X2Mode::kScatter><<<nb, 256, 0, s>>>(t->r, t->p, sc, t->perm, out, n, stop);
+      k_t_x<X2Mode::kScatter><<<nb, 256, 0, s>>>(t->r, t->p, sc, t->perm, out, n, stop, 1.0);
       break;
     case X2Mode::kAdd:
-      k_t_x<X2Mode::kAdd><<<nb, 256, 0, s>>>(t->r, t->p, sc, t->perm, out, n, stop);
+      k_t_x<X2Mode::kAdd><<<nb, 256, 0, s>>>(t->r, t->p, sc, t->perm, out, n, stop, scale);
       break;
   }
   return launch_check("transfer x2");

@@ -24,6 +24,7 @@ struct dmg_twolevel {
   std::unique_ptr<dmg_transfer> t;
   dmg_hier* grid = nullptr;  // borrowed
   int nv = 0, nx = 0, ny = 0, mass = 0;
+  double gamma = 1.0;  // coarse-grid scaling: u_p += gamma P e_c
   int64_t nnzA = 0;  // stored off-diagonal entries of A_p
   std::vector<int> cs;      // colour c holds internal rows [cs[c], cs[c + 1])
   std::vector<int> colour;  // colour of each vertex, caller order
@@ -118,21 +119,101 @@ __global__ __launch_bounds__(256) void k_tl_resid(const int* __restrict__ rp,
   }
 }
 
-// u += dof * (C e_c) / ML: the lumped interpolation of the grid correction, added in place.
+// u += gamma * dof * (C e_c) / ML: the lumped interpolation of the grid correction, scaled and
+// added in place.
 __global__ __launch_bounds__(256) void k_tl_prolong(const int* __restrict__ rp,
                                                     const int* __restrict__ ci,
                                                     const double* __restrict__ v,
                                                     const double* __restrict__ ec,
                                                     const double* __restrict__ ML,
                                                     const unsigned char* __restrict__ dof,
-                                                    double* __restrict__ u, int n,
+                                                    double* __restrict__ u, int n, double gamma,
                                                     const int* __restrict__ stop) {
   if (halted(stop)) return;
   const int lane = threadIdx.x & (kMG - 1);
   const int g0 = int((blockIdx.x * 256u + threadIdx.x) / kMG), ng = int(gridDim.x * 256u / kMG);
   for (int r = g0; r < n; r += ng) {
     const double s = row_dot<kMG>(rp, ci, v, r, lane, [&](int c) { return ec[c]; });
-    if (lane == 0 && dof[r]) u[r] += s / ML[r];
+    if (lane == 0 && dof[r]) u[r] += gamma * (s / ML[r]);
+  }
+}
+
+// ---- the scaling estimate (generalized Lanczos on grid vectors) ----------------------------
+// x = P v = dof * (C v) / ML on the mesh (lumped interpolation, stored).
+__global__ __launch_bounds__(256) void k_tl_interp(const int* __restrict__ rp,
+                                                   const int* __restrict__ ci,
+                                                   const double* __restrict__ v,
+                                                   const double* __restrict__ vc,
+                                                   const double* __restrict__ ML,
+                                                   const unsigned char* __restrict__ dof,
+                                                   double* __restrict__ x, int n) {
+  const int lane = threadIdx.x & (kMG - 1);
+  const int g0 = int((blockIdx.x * 256u + threadIdx.x) / kMG), ng = int(gridDim.x * 256u / kMG);
+  for (int r = g0; r < n; r += ng) {
+    const double s = row_dot<kMG>(rp, ci, v, r, lane, [&](int c) { return vc[c]; });
+    if (lane == 0) x[r] = dof[r] ? s / ML[r] : 0.0;
+  }
+}
+
+// y = dof * (A_p x) / ML on the mesh (the stiffness product followed by the lumped mass of R).
+__global__ __launch_bounds__(256) void k_tl_apply_scaled(const int* __restrict__ rp,
+                                                         const int* __restrict__ ci,
+                                                         const double* __restrict__ v,
+                                                         const double* __restrict__ d,
+                                                         const double* __restrict__ x,
+                                                         const double* __restrict__ ML,
+                                                         const unsigned char* __restrict__ dof,
+                                                         double* __restrict__ y, int n) {
+  const int lane = threadIdx.x & (kMG - 1);
+  const int g0 = int((blockIdx.x * 256u + threadIdx.x) / kMG), ng = int(gridDim.x * 256u / kMG);
+  for (int r = g0; r < n; r += ng) {
+    const double s = row_dot<kMG>(rp, ci, v, r, lane, [&](int c) { return x[c]; });
+    if (lane == 0) y[r] = dof[r] ? __builtin_fma(d[r], x[r], s) / ML[r] : 0.0;
+  }
+}
+
+constexpr int kLzBlocks = 1024;  // fixed partial count of the Lanczos dot products
+
+// Interior part of v0 (boundary ring 0).
+__global__ __launch_bounds__(256) void k_lz_mask(const double* __restrict__ v0,
+                                                 double* __restrict__ x, int nx, int ny) {
+  const size_t N = size_t(nx) * ny;
+  for (size_t v = blockIdx.x * 256u + threadIdx.x; v < N; v += size_t(gridDim.x) * 256u) {
+    const int j = int(v / nx), i = int(v % nx);
+    x[v] = (i > 0 && i < nx - 1 && j > 0 && j < ny - 1) ? v0[v] : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_lz_dot(const double* __restrict__ x,
+                                                const double* __restrict__ y, size_t n,
+                                                double* __restrict__ partials) {
+  double acc = 0.0;
+  for (size_t k = blockIdx.x * 256u + threadIdx.x; k < n; k += size_t(gridDim.x) * 256u)
+    acc = __builtin_fma(x[k], y[k], acc);
+  const double t = mesh_block_sum(acc);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+// x *= a, y *= a
+__global__ __launch_bounds__(256) void k_lz_scale2(double* __restrict__ x, double* __restrict__ y,
+                                                   double a, size_t n) {
+  for (size_t k = blockIdx.x * 256u + threadIdx.x; k < n; k += size_t(gridDim.x) * 256u) {
+    x[k] *= a;
+    y[k] *= a;
+  }
+}
+
+// w = (w - alpha v) - beta vp and g = (g - alpha Av) - beta Avp (then g = A w)
+__global__ __launch_bounds__(256) void k_lz_update(double* __restrict__ w,
+                                                   const double* __restrict__ v,
+                                                   const double* __restrict__ vp,
+                                                   double* __restrict__ g,
+                                                   const double* __restrict__ Av,
+                                                   const double* __restrict__ Avp, double alpha,
+                                                   double beta, size_t n) {
+  for (size_t k = blockIdx.x * 256u + threadIdx.x; k < n; k += size_t(gridDim.x) * 256u) {
+    w[k] = (w[k] - alpha * v[k]) - beta * vp[k];
+    g[k] = (g[k] - alpha * Av[k]) - beta * Avp[k];
   }
 }
 
@@ -215,11 +296,12 @@ dmg_status cycle(dmg_twolevel* tl, const int* stop, hipStream_t s) {
   }
   DMG_CHECK(grid_vcycle(tl->grid, tl->ec, tl->rc, true, stop, s));
   if (tl->mass == 0) {
-    k_tl_prolong<<<nb, 256, 0, s>>>(t->Crp, t->Cci, t->Cv, tl->ec, tl->ML, t->dof, tl->u, n, stop);
+    k_tl_prolong<<<nb, 256, 0, s>>>(t->Crp, t->Cci, t->Cv, tl->ec, tl->ML, t->dof, tl->u, n,
+                                    tl->gamma, stop);
     DMG_CHECK(launch_check("two-level interpolation"));
   } else {
     DMG_CHECK(launch_from_start(t, tl->ec, stop, s));
-    DMG_CHECK(cg2_tail(t, tl->u, X2Mode::kAdd, stop, s));
+    DMG_CHECK(cg2_tail(t, tl->u, X2Mode::kAdd, stop, s, tl->gamma));
   }
   return symmetric_sweep(tl, stop, s);
 }
@@ -530,6 +612,120 @@ dmg_status dmg_twolevel_solve(dmg_twolevel* tl, double* u_p, const double* f_p, 
   if (rn > rtol * r0)
     return fail(DMG_ERR_NO_CONVERGENCE, "no convergence in %d cycles (rel. residual %.3e)", k,
                 rn / r0);
+  return DMG_OK;
+}
+
+dmg_status dmg_twolevel_set_scaling(dmg_twolevel* tl, double gamma) {
+  clear_error();
+  if (!tl) return fail(DMG_ERR_INVALID_ARG, "null two-level handle");
+  if (!std::isfinite(gamma)) return fail(DMG_ERR_INVALID_ARG, "gamma must be finite");
+  tl->gamma = gamma;
+  tl->reset_graph();  // captured cycles hold the previous value
+  return DMG_OK;
+}
+
+dmg_status dmg_twolevel_scaling(dmg_twolevel* tl, const double* v0, int32_t k, double* gamma,
+                                double* T, int32_t* steps, hipStream_t stream) {
+  clear_error();
+  if (!tl || !v0 || !gamma) return fail(DMG_ERR_INVALID_ARG, "null pointer argument");
+  if (k < 1 || k > 64) return fail(DMG_ERR_INVALID_ARG, "k must be in [1, 64]");
+  if (tl->mass != 0)
+    return fail(DMG_ERR_UNSUPPORTED, "the scaling estimate needs the linear (lumped) transfer");
+  dmg_transfer* t = tl->t.get();
+  dmg_hier* h = tl->grid;
+  const int nx = tl->nx, ny = tl->ny, n = tl->nv, nb = row_blocks(n);
+  const size_t ng = size_t(nx) * ny;
+  // scratch for this call only: six grid vectors, dot partials, one device scalar
+  Arena sz;
+  double *vec[6], *partials, *dscal;
+  auto layout = [&](Arena& a) {
+    for (auto& p : vec) p = a.take<double>(ng);
+    partials = a.take<double>(kLzBlocks);
+    dscal = a.take<double>(4);
+  };
+  layout(sz);
+  void* block = nullptr;
+  DMG_HIP(hipMalloc(&block, sz.used));
+  std::unique_ptr<void, void (*)(void*)> guard(block, [](void* p) { (void)hipFree(p); });
+  Arena a;
+  a.base = static_cast<char*>(block);
+  a.cap = sz.used;
+  layout(a);
+  double *v = vec[0], *Av = vec[1], *vp = vec[2], *Avp = vec[3], *w = vec[4], *g = vec[5];
+  const unsigned gb = unsigned(std::min<size_t>((ng + 255) / 256, 4096));
+  auto dot = [&](const double* x, const double* y, double* out) -> dmg_status {
+    k_lz_dot<<<kLzBlocks, 256, 0, stream>>>(x, y, ng, partials);
+    DMG_CHECK(launch_check("lanczos dot"));
+    DMG_CHECK(launch_finalize(partials, dscal, stream, kLzBlocks));
+    DMG_HIP(hipMemcpyAsync(out, dscal, sizeof(double), hipMemcpyDeviceToHost, stream));
+    DMG_HIP(hipStreamSynchronize(stream));
+    return DMG_OK;
+  };
+  auto scale2 = [&](double* x, double* y, double f) -> dmg_status {
+    k_lz_scale2<<<gb, 256, 0, stream>>>(x, y, f, ng);
+    return launch_check("lanczos scale");
+  };
+  // G x = R A_p P x on grid vectors, R = C^T ML^{-1}
+  auto applyG = [&](const double* x, double* out) -> dmg_status {
+    k_tl_interp<<<nb, 256, 0, stream>>>(t->Crp, t->Cci, t->Cv, x, tl->ML, t->dof, tl->w, n);
+    DMG_CHECK(launch_check("lanczos P"));
+    k_tl_apply_scaled<<<nb, 256, 0, stream>>>(tl->Arp, tl->Aci, tl->Av, tl->Ad, tl->w, tl->ML,
+                                              t->dof, t->x, n);
+    DMG_CHECK(launch_check("lanczos A_p"));
+    return launch_ct(t, t->x, out, nullptr, stream);
+  };
+  k_lz_mask<<<gb, 256, 0, stream>>>(v0, v, nx, ny);
+  DMG_CHECK(launch_check("lanczos start"));
+  DMG_CHECK(launch_stencil_apply(h->L[0].S, v, Av, nx, ny, stream));
+  double vAv = 0.0;
+  DMG_CHECK(dot(v, Av, &vAv));
+  if (!(vAv > 0.0) || !std::isfinite(vAv))
+    return fail(DMG_ERR_INVALID_ARG, "start vector has no interior part");
+  DMG_CHECK(scale2(v, Av, 1.0 / std::sqrt(vAv)));
+  DMG_CHECK(launch_fill<double>(vp, 0.0, ng, stream));
+  DMG_CHECK(launch_fill<double>(Avp, 0.0, ng, stream));
+  std::vector<double> alphas, betas;
+  double beta = 0.0;
+  for (int j = 0; j < k; ++j) {
+    DMG_CHECK(applyG(v, g));
+    double alpha = 0.0;
+    DMG_CHECK(dot(g, v, &alpha));
+    alphas.push_back(alpha);
+    if (j + 1 == k) break;
+    // w = A_c^{-1} g by the grid solve, to a relative residual of 1e-13 or its stagnation
+    DMG_CHECK(launch_fill<double>(w, 0.0, ng, stream));
+    int32_t it = 0;
+    double rr = 0.0;
+    const dmg_status st = dmg_solve(h, w, g, 1e-13, 100, &it, &rr, nullptr, stream);
+    if (st != DMG_OK && !(st == DMG_ERR_NO_CONVERGENCE && rr <= 1e-11)) return st;
+    clear_error();
+    k_lz_update<<<gb, 256, 0, stream>>>(w, v, vp, g, Av, Avp, alpha, beta, ng);
+    DMG_CHECK(launch_check("lanczos update"));
+    double wAw = 0.0;
+    DMG_CHECK(dot(w, g, &wAw));
+    const double bnew = std::sqrt(std::max(wAw, 0.0));
+    if (!(bnew > 1e-13 * std::fabs(alpha))) break;  // invariant Krylov space
+    betas.push_back(bnew);
+    // (vp, v, w) <- (v, w / beta, vp) and the same for the A_c images
+    std::swap(vp, v);
+    std::swap(v, w);
+    std::swap(Avp, Av);
+    std::swap(Av, g);
+    DMG_CHECK(scale2(v, Av, 1.0 / bnew));
+    beta = bnew;
+  }
+  const int m = int(alphas.size());
+  double sum = 0.0;
+  for (double x : alphas) sum += x;
+  *gamma = sum / m;
+  if (steps) *steps = m;
+  if (T) {
+    std::fill(T, T + size_t(k) * k, 0.0);
+    for (int i = 0; i < m; ++i) {
+      T[size_t(i) * k + i] = alphas[i];
+      if (i + 1 < m) T[size_t(i) * k + i + 1] = T[size_t(i + 1) * k + i] = betas[i];
+    }
+  }
   return DMG_OK;
 }
 

@@ -134,3 +134,62 @@ def test_graph_path_matches_eager(lib):
     torch.cuda.synchronize()
     assert k_g == k_e and h_g == h_e
     assert torch.equal(u_g, u_e)
+
+
+@pytest.mark.parametrize("n", [33, 65])
+def test_scaling_estimate_matches_oracle(lib, n):
+    """gamma and the Lanczos tridiagonal of Sec. 2.4's estimate.  The library solves with A_c by
+    the multigrid solve to a relative residual of 1e-13 (the oracle exactly); over 12 steps that
+    leaves gamma within 1e-9 and T within 1e-8 relative."""
+    P, orc, tl = pair(lib, n)
+    v0 = np.random.Generator(np.random.PCG64(9)).uniform(-1, 1, (n, n))
+    go, To = dmg.coarse_scaling(orc, v0, 12)
+    gg, Tg = tl.estimate_scaling(dev(v0), 12)
+    assert Tg.shape == To.shape == (12, 12)
+    assert abs(gg - go) <= 1e-9 * abs(go), (gg, go)
+    assert np.allclose(Tg, To, rtol=1e-8, atol=1e-10)
+
+
+@pytest.mark.parametrize("n,mass", [(33, "lumped"), (17, "cg2")])
+def test_scaled_cycles_match_oracle(lib, n, mass):
+    P, orc, tl = pair(lib, n, mass=mass)
+    g = np.random.Generator(np.random.PCG64(12))
+    u0 = np.where(P.mesh.dof, g.uniform(-1, 1, P.mesh.nv), 0.0)
+    orc.gamma = 0.7
+    tl.set_scaling(0.7)
+    try:
+        uo, ug, fg = u0.copy(), dev(u0), dev(P.f)
+        for k in range(3):
+            orc.cycle(uo, P.f)
+            tl.cycle(ug, fg)
+            assert relerr(host(ug), uo) <= TOL, k
+    finally:
+        orc.gamma = 1.0
+        tl.set_scaling(1.0)
+
+
+def test_set_scaling_replaces_captured_cycles(lib):
+    """A solve captures its cycles in a graph; a new gamma must not replay the old one."""
+    P, orc, tl = pair(lib, 33)
+    f = dev(P.f)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    try:
+        with torch.cuda.stream(s):
+            _, k1, _, _ = tl.solve(f, rtol=1e-10)
+            tl.set_scaling(0.7)
+            u, k, rel, hist = tl.solve(f, rtol=1e-10)
+        torch.cuda.synchronize()
+        orc.gamma = 0.7
+        uo, ko, histo, _ = dmg.solve(orc, P.f, rtol=1e-10)
+        assert k == ko and k != k1
+        assert np.allclose(hist, histo, rtol=1e-6, atol=1e-13)
+    finally:
+        orc.gamma = 1.0
+        tl.set_scaling(1.0)
+
+
+def test_scaling_estimate_needs_lumped_mass(lib):
+    P, orc, tl = pair(lib, 17, mass="cg2")
+    with pytest.raises(lib.DmgError):
+        tl.estimate_scaling(torch.ones((17, 17), dtype=torch.float64, device="cuda"), 4)

@@ -31,7 +31,7 @@ def test_header_declares_the_boundary():
     for required in ("dmg_assemble_stencil", "dmg_setup", "dmg_vcycle", "dmg_solve",
                      "dmg_transfer_to_grid", "dmg_transfer_from_grid", "dmg_grad_K",
                      "dmg_batch_solve", "dmg_twolevel_create", "dmg_twolevel_cycle",
-                     "dmg_twolevel_solve"):
+                     "dmg_twolevel_solve", "dmg_twolevel_scaling", "dmg_twolevel_set_scaling"):
         assert required in names
 
 
