@@ -57,6 +57,9 @@ typedef enum dmg_status {
 
 enum { DMG_FP64 = 0, DMG_FP32_IR = 1 };
 
+/* Mesh setup flags (dmg_transfer_create, dmg_twolevel_create). */
+enum { DMG_MESH_HOST_SETUP = 1 /* assemble C and C^T on the host instead of the device */ };
+
 /* Solver options.  Fill with dmg_default_options() and change what is needed. */
 typedef struct dmg_options {
   int32_t nu_pre;        /* pre-smoothing sweeps per level (default 1)                    */
@@ -189,14 +192,19 @@ dmg_status dmg_grad_K(const double* jac, const double* lambda, const double* u, 
  * triangle count as zero; |J_T^{-1}| taken as area(tau_p)/area(mapped tau)); nq = 0 integrates
  * exactly over each triangle-cell overlap polygon instead.  M_p is the P1 mass matrix.  The
  * handle owns device memory allocated here (freed by dmg_transfer_destroy); the apply calls
- * allocate nothing.
+ * allocate nothing.  C and C^T are assembled on the device unless flags has
+ * DMG_MESH_HOST_SETUP (or a row of C holds more than 64 grid columns, when the host assembly
+ * takes over); both give the same bits.  M_p is assembled on the host (threads).
  * from_grid: u_p = CG2(M_p, C u_c)      u_c [ny][nx] -> u_p [nv]
  * to_grid:   r_c = C^T CG2(M_p, r_p)    r_p [nv]     -> r_c [ny][nx]
  * CG2 = two iterations of unpreconditioned CG from 0.  Dirichlet entries are ignored/zero. */
 dmg_status dmg_transfer_create(int32_t nv, int32_t nt, const double* xy_c, const double* xy_p,
                                const int32_t* tris, const uint8_t* dof, int32_t nx, int32_t ny,
-                               int32_t nq, hipStream_t stream, dmg_transfer** out);
+                               int32_t nq, int32_t flags, hipStream_t stream, dmg_transfer** out);
 dmg_status dmg_transfer_info(const dmg_transfer* t, int64_t* nnz_C, int64_t* nnz_M);
+/* C as a host CSR with rows in the caller's vertex order: rp [nv + 1], ci and v [nnz_C] (from
+ * dmg_transfer_info), columns ascending within a row.  Synchronous. */
+dmg_status dmg_transfer_copy_C(const dmg_transfer* t, int32_t* rp, int32_t* ci, double* v);
 dmg_status dmg_transfer_from_grid(dmg_transfer* t, const double* u_c, double* u_p,
                                   hipStream_t stream);
 dmg_status dmg_transfer_to_grid(dmg_transfer* t, const double* r_p, double* r_c,
@@ -240,7 +248,7 @@ void dmg_batch_destroy(dmg_batch* bt);
  * iterations on M_p (Sec. 2.3).  Colours: greedy over the vertices in index order on the mesh
  * graph (unknowns sharing a triangle are neighbours; Dirichlet vertices have none, colour 0);
  * the symmetric sweep updates colours 0..C-1 then C-2..0.
- * Create: mesh arrays on the HOST and nq as for dmg_transfer_create (nq = 0, the exact overlap
+ * Create: mesh arrays on the HOST, nq and flags as for dmg_transfer_create (nq = 0, the exact overlap
  * integral, keeps the coarse correction's energy matched to A_p as the mesh is refined; low
  * quadrature orders let it drift); K_t [nt] host coefficient per
  * triangle (null: 1); grid: a hierarchy built on the nx x ny grid that C maps to (its level-0
@@ -258,8 +266,8 @@ void dmg_batch_destroy(dmg_batch* bt);
  * DMG_ERR_NO_CONVERGENCE or DMG_ERR_NONFINITE with u_p holding the last iterate. */
 dmg_status dmg_twolevel_create(int32_t nv, int32_t nt, const double* xy_c, const double* xy_p,
                                const int32_t* tris, const uint8_t* dof, const double* K_t,
-                               dmg_hier* grid, int32_t nq, int32_t mass, hipStream_t stream,
-                               dmg_twolevel** out);
+                               dmg_hier* grid, int32_t nq, int32_t mass, int32_t flags,
+                               hipStream_t stream, dmg_twolevel** out);
 dmg_status dmg_twolevel_info(const dmg_twolevel* tl, int32_t* colours, int64_t* nnz_A,
                              int32_t* colour);
 dmg_status dmg_twolevel_cycle(dmg_twolevel* tl, double* u_p, const double* f_p,

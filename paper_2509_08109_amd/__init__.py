@@ -16,7 +16,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import DMG_FP32_IR, DMG_FP64, DmgError, Options, default_options
+from ._lib import DMG_FP32_IR, DMG_FP64, DMG_MESH_HOST_SETUP, DmgError, Options, default_options
 
 __all__ = ["Hierarchy", "assemble_stencil", "grad_K", "Transfer", "TwoLevel", "BatchSolver", "DiffSolve",
            "default_options", "Options", "DmgError", "DMG_FP64", "DMG_FP32_IR", "lib", "version"]
@@ -203,7 +203,8 @@ class Hierarchy:
 class Transfer:
     """L2-projection transfers between a P1 mesh and the grid (host mesh arrays)."""
 
-    def __init__(self, xy_c, xy_p, tris, dof, nx: int, ny: int, nq: int = 4, device="cuda"):
+    def __init__(self, xy_c, xy_p, tris, dof, nx: int, ny: int, nq: int = 4, device="cuda",
+                 host_setup: bool = False):
         self.xy_c = np.ascontiguousarray(xy_c, dtype=np.float64)
         self.xy_p = np.ascontiguousarray(xy_p, dtype=np.float64)
         self.tris = np.ascontiguousarray(tris, dtype=np.int32)
@@ -218,8 +219,18 @@ class Transfer:
         with torch.cuda.device(self.device):
             _lib.check(lib().dmg_transfer_create(self.nv, self.nt, self.xy_c.ctypes.data, self.xy_p.ctypes.data,
                                                  self.tris.ctypes.data, self.dof.ctypes.data, nx, ny, nq,
+                                                 DMG_MESH_HOST_SETUP if host_setup else 0,
                                                  _stream(self.device), C.byref(h)))
         self._h = h
+
+    def copy_C(self):
+        """C as (rp, ci, v) host arrays, rows in the caller's vertex order."""
+        nnz = self.nnz()[0]
+        rp = np.empty(self.nv + 1, dtype=np.int32)
+        ci = np.empty(max(nnz, 1), dtype=np.int32)
+        v = np.empty(max(nnz, 1), dtype=np.float64)
+        _lib.check(lib().dmg_transfer_copy_C(self._h, rp.ctypes.data, ci.ctypes.data, v.ctypes.data))
+        return rp, ci[:nnz], v[:nnz]
 
     def nnz(self):
         a, b = C.c_int64(), C.c_int64()
@@ -256,9 +267,10 @@ class TwoLevel:
     """The two-level cycle on a physical P1 mesh (host mesh arrays) over the grid hierarchy
     ``grid`` (a Hierarchy on the grid that the mesh maps to; it must outlive this object).
     nq: 0 for the exact coupled mass (default) or the order of the rasterised rule;
-    mass: "lumped" or "cg2"."""
+    mass: "lumped" or "cg2"; host_setup: assemble C on the host (the default is the device)."""
 
-    def __init__(self, grid: Hierarchy, xy_c, xy_p, tris, dof, K_t=None, nq: int = 0, mass: str = "lumped"):
+    def __init__(self, grid: Hierarchy, xy_c, xy_p, tris, dof, K_t=None, nq: int = 0, mass: str = "lumped",
+                 host_setup: bool = False):
         if mass not in ("lumped", "cg2"):
             raise ValueError("mass must be 'lumped' or 'cg2'")
         self.grid = grid
@@ -281,8 +293,9 @@ class TwoLevel:
             _lib.check(lib().dmg_twolevel_create(self.nv, self.nt, xy_c.ctypes.data, xy_p.ctypes.data,
                                                  tris.ctypes.data, dof.ctypes.data,
                                                  None if kt is None else kt.ctypes.data, grid._h, nq,
-                                                 0 if mass == "lumped" else 2, _stream(self.device),
-                                                 C.byref(h)))
+                                                 0 if mass == "lumped" else 2,
+                                                 DMG_MESH_HOST_SETUP if host_setup else 0,
+                                                 _stream(self.device), C.byref(h)))
         self._h = h
 
     def info(self):

@@ -12,6 +12,7 @@ STATUS_NAMES = {0: "DMG_OK", 1: "DMG_ERR_INVALID_ARG", 2: "DMG_ERR_DIMS", 3: "DM
                 4: "DMG_ERR_NOT_SPD", 5: "DMG_ERR_NONFINITE", 6: "DMG_ERR_NO_CONVERGENCE",
                 7: "DMG_ERR_HIP", 8: "DMG_ERR_UNSUPPORTED"}
 DMG_FP64, DMG_FP32_IR = 0, 1
+DMG_MESH_HOST_SETUP = 1
 
 
 class DmgError(RuntimeError):
@@ -52,12 +53,13 @@ SIGNATURES = {
     "dmg_solve": (_st, [_p, _p, _p, C.c_double, _i32, C.POINTER(_i32), C.POINTER(C.c_double),
                         C.POINTER(C.c_double), _p]),
     "dmg_grad_K": (_st, [_p, _p, _p, _i32, _i32, _p, _p]),
-    "dmg_transfer_create": (_st, [_i32, _i32, _p, _p, _p, _p, _i32, _i32, _i32, _p, C.POINTER(_p)]),
+    "dmg_transfer_create": (_st, [_i32, _i32, _p, _p, _p, _p, _i32, _i32, _i32, _i32, _p, C.POINTER(_p)]),
     "dmg_transfer_info": (_st, [_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "dmg_transfer_copy_C": (_st, [_p, _p, _p, _p]),
     "dmg_transfer_from_grid": (_st, [_p, _p, _p, _p]),
     "dmg_transfer_to_grid": (_st, [_p, _p, _p, _p]),
     "dmg_transfer_destroy": (None, [_p]),
-    "dmg_twolevel_create": (_st, [_i32, _i32, _p, _p, _p, _p, _p, _p, _i32, _i32, _p, C.POINTER(_p)]),
+    "dmg_twolevel_create": (_st, [_i32, _i32, _p, _p, _p, _p, _p, _p, _i32, _i32, _i32, _p, C.POINTER(_p)]),
     "dmg_twolevel_info": (_st, [_p, C.POINTER(_i32), C.POINTER(C.c_int64), _p]),
     "dmg_twolevel_cycle": (_st, [_p, _p, _p, _p]),
     "dmg_twolevel_solve": (_st, [_p, _p, _p, C.c_double, _i32, C.POINTER(_i32), C.POINTER(C.c_double), _p, _p]),

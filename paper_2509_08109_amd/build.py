@@ -27,7 +27,7 @@ FLAGS = [
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
     "-I" + os.path.join(ROOT, "include"),
 ]
-SOURCES = ["setup_kernels.hip", "cycle_kernels.hip", "fused_kernels.hip", "transfer.hip",
+SOURCES = ["setup_kernels.hip", "cycle_kernels.hip", "fused_kernels.hip", "transfer.hip", "mesh_setup.hip",
            "twolevel.hip", "batch.hip", "api.hip"]
 
 

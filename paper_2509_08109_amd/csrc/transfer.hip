@@ -50,26 +50,6 @@ void gauss01(int nq, std::vector<double>& x, std::vector<double>& w) {
   }
 }
 
-// Merge per-thread row blocks (rows [r0,r1) of thread t) into one CSR.
-Csr merge(int n, const std::vector<Csr>& parts, const std::vector<int>& first_row) {
-  Csr out;
-  out.rp.assign(n + 1, 0);
-  size_t nnz = 0;
-  for (const auto& p : parts) nnz += p.ci.size();
-  out.ci.reserve(nnz);
-  out.v.reserve(nnz);
-  for (size_t t = 0; t < parts.size(); ++t) {
-    const Csr& p = parts[t];
-    const int r0 = first_row[t];
-    const int rows = int(p.rp.size()) - 1;
-    const int base = int(out.ci.size());
-    for (int k = 0; k < rows; ++k) out.rp[r0 + k + 1] = base + p.rp[k + 1];
-    out.ci.insert(out.ci.end(), p.ci.begin(), p.ci.end());
-    out.v.insert(out.v.end(), p.v.begin(), p.v.end());
-  }
-  return out;
-}
-
 }  // namespace
 
 void build_adjacency(Mesh& m) {
@@ -83,124 +63,9 @@ void build_adjacency(Mesh& m) {
     for (int a = 0; a < 3; ++a) m.vt[fill[m.tris[3 * t + a]]++] = t;
 }
 
-double tri_area2(const double* xy, const int* tv) {
-  const double* a = xy + 2 * tv[0];
-  const double* b = xy + 2 * tv[1];
-  const double* c = xy + 2 * tv[2];
-  return (b[0] - a[0]) * (c[1] - a[1]) - (c[0] - a[0]) * (b[1] - a[1]);
-}
+void gauss_rule01(int nq, std::vector<double>& x, std::vector<double>& w) { gauss01(nq, x, w); }
 
 namespace {
-
-// Part of triangle tri inside the box [x0, x1] x [y0, y1] (Sutherland-Hodgman, one pass per box
-// side); returns its vertex count (a triangle cut by four half-planes keeps at most 7).
-int clip_triangle(const double tri[3][2], double x0, double x1, double y0, double y1,
-                  double out[8][2]) {
-  double a[8][2], b[8][2];
-  int n = 3;
-  for (int k = 0; k < 3; ++k) {
-    a[k][0] = tri[k][0];
-    a[k][1] = tri[k][1];
-  }
-  // keep the side where sign * (p[axis] - lim) >= 0
-  auto pass = [](const double (*src)[2], int ns, double (*dst)[2], int axis, double lim,
-                 double sign) {
-    int nd = 0;
-    for (int k = 0; k < ns; ++k) {
-      const double* p = src[(k + ns - 1) % ns];
-      const double* q = src[k];
-      const bool ip = sign * (p[axis] - lim) >= 0.0, iq = sign * (q[axis] - lim) >= 0.0;
-      if (ip != iq) {
-        const double t = (lim - p[axis]) / (q[axis] - p[axis]);
-        dst[nd][axis] = lim;
-        dst[nd][1 - axis] = p[1 - axis] + t * (q[1 - axis] - p[1 - axis]);
-        ++nd;
-      }
-      if (iq) {
-        dst[nd][0] = q[0];
-        dst[nd][1] = q[1];
-        ++nd;
-      }
-    }
-    return nd;
-  };
-  n = pass(a, n, b, 0, x0, 1.0);
-  n = n ? pass(b, n, a, 0, x1, -1.0) : 0;
-  n = n ? pass(a, n, b, 1, y0, 1.0) : 0;
-  n = n ? pass(b, n, a, 1, y1, -1.0) : 0;
-  for (int k = 0; k < n; ++k) {
-    out[k][0] = a[k][0];
-    out[k][1] = a[k][1];
-  }
-  return n;
-}
-
-// Dunavant's symmetric 6-point rule on a triangle, exact for degree 4: barycentric orbits
-// (a, a, 1 - 2a) with weights relative to the area.
-constexpr double kTriA1 = 0.445948490915965, kTriW1 = 0.223381589678011;
-constexpr double kTriA2 = 0.091576213509771, kTriW2 = 1.0 / 3.0 - kTriW1;
-
-// Row v of C from triangle tv (a = v's slot in tv) integrated exactly over the overlap of the
-// mapped triangle with each grid cell: the integrand lambda_a * phi_g is a cubic there.
-template <class Acc>
-void exact_row_triangle(const Mesh& m, const int* tv, int a, double hx, double hy, int nx, int ny,
-                        double jac, Acc&& acc) {
-  double tri[3][2];
-  for (int k = 0; k < 3; ++k) {
-    tri[k][0] = m.xy_c[2 * tv[k]];
-    tri[k][1] = m.xy_c[2 * tv[k] + 1];
-  }
-  const double det = (tri[1][0] - tri[0][0]) * (tri[2][1] - tri[0][1]) -
-                     (tri[2][0] - tri[0][0]) * (tri[1][1] - tri[0][1]);
-  // lambda_a(X, Y) = (e0 + e1 X + e2 Y) / det from the edge opposite vertex a
-  const double* p = tri[(a + 1) % 3];
-  const double* q = tri[(a + 2) % 3];
-  const double e1 = p[1] - q[1], e2 = q[0] - p[0], e0 = p[0] * q[1] - q[0] * p[1];
-  const double xmin = std::min({tri[0][0], tri[1][0], tri[2][0]});
-  const double xmax = std::max({tri[0][0], tri[1][0], tri[2][0]});
-  const double ymin = std::min({tri[0][1], tri[1][1], tri[2][1]});
-  const double ymax = std::max({tri[0][1], tri[1][1], tri[2][1]});
-  auto cell = [](double x, double h, int n) {
-    const int c = int(std::floor((x + 1.0) / h));
-    return std::min(std::max(c, 0), n - 2);
-  };
-  const int i0 = cell(xmin, hx, nx), i1 = cell(xmax, hx, nx);
-  const int j0 = cell(ymin, hy, ny), j1 = cell(ymax, hy, ny);
-  static const double orbit[2][2] = {{kTriA1, kTriW1}, {kTriA2, kTriW2}};
-  double poly[8][2];
-  for (int cj = j0; cj <= j1; ++cj)
-    for (int ci = i0; ci <= i1; ++ci) {
-      const double X0 = -1.0 + ci * hx, Y0 = -1.0 + cj * hy;
-      const int np = clip_triangle(tri, X0, X0 + hx, Y0, Y0 + hy, poly);
-      if (np < 3) continue;
-      double w4[4] = {0.0, 0.0, 0.0, 0.0};
-      for (int k = 1; k + 1 < np; ++k) {
-        const double* A = poly[0];
-        const double* B = poly[k];
-        const double* D = poly[k + 1];
-        const double area =
-            0.5 * std::fabs((B[0] - A[0]) * (D[1] - A[1]) - (D[0] - A[0]) * (B[1] - A[1]));
-        if (area == 0.0) continue;
-        for (const auto& o : orbit) {
-          const double la = o[0], lb = 1.0 - 2.0 * o[0];
-          const double bary[3][3] = {{la, la, lb}, {la, lb, la}, {lb, la, la}};
-          for (const auto& l : bary) {
-            const double X = l[0] * A[0] + l[1] * B[0] + l[2] * D[0];
-            const double Y = l[0] * A[1] + l[1] * B[1] + l[2] * D[1];
-            const double w = o[1] * area * (e0 + e1 * X + e2 * Y) / det;
-            const double s = (X - X0) / hx, t = (Y - Y0) / hy;
-            w4[0] += w * (1 - s) * (1 - t);
-            w4[1] += w * s * (1 - t);
-            w4[2] += w * (1 - s) * t;
-            w4[3] += w * s * t;
-          }
-        }
-      }
-      const int g00 = cj * nx + ci;
-      const int gi[4] = {g00, g00 + 1, g00 + nx, g00 + nx + 1};
-      for (int g = 0; g < 4; ++g) acc(gi[g], jac * w4[g]);
-    }
-}
 
 // nq >= 1: the rasterised rule (nq x nq Gauss points per overlapped cell, zero outside the
 // mapped triangle); nq == 0: exact integration over the triangle-cell overlaps.
@@ -208,90 +73,57 @@ Csr assemble_C(const Mesh& m, int nx, int ny, int nq) {
   std::vector<double> qx, qw;
   if (nq > 0) gauss01(nq, qx, qw);
   const double hx = 2.0 / (nx - 1), hy = 2.0 / (ny - 1);
-  unsigned nthreads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-  if (m.nv < 4096) nthreads = 1;
-  std::vector<Csr> parts(nthreads);
-  std::vector<int> first(nthreads);
-  std::vector<std::thread> th;
-  for (unsigned t = 0; t < nthreads; ++t) {
-    const int r0 = int(int64_t(m.nv) * t / nthreads), r1 = int(int64_t(m.nv) * (t + 1) / nthreads);
-    first[t] = r0;
-    th.emplace_back([&, t, r0, r1]() {
-      Csr& out = parts[t];
-      out.rp.assign(1, 0);
-      std::unordered_map<int, double> row;
-      std::vector<std::pair<int, double>> sorted;
-      for (int v = r0; v < r1; ++v) {
-        row.clear();
-        if (m.dof[v]) {
-          for (int k = m.vt_ptr[v]; k < m.vt_ptr[v + 1]; ++k) {
-            const int* tv = m.tris + 3 * m.vt[k];
-            const int a = tv[0] == v ? 0 : (tv[1] == v ? 1 : 2);
-            const double ac2 = tri_area2(m.xy_c, tv);
-            if (ac2 == 0.0) continue;
-            const double jac = std::fabs(tri_area2(m.xy_p, tv)) / std::fabs(ac2);
-            if (nq == 0) {
-              exact_row_triangle(m, tv, a, hx, hy, nx, ny, jac, [&](int g, double val) {
-                const int gx = g % nx, gy = g / nx;
-                if (gx == 0 || gx == nx - 1 || gy == 0 || gy == ny - 1) return;
-                row[g] += val;
-              });
-              continue;
-            }
-            const double* c0 = m.xy_c + 2 * tv[0];
-            const double* c1 = m.xy_c + 2 * tv[1];
-            const double* c2 = m.xy_c + 2 * tv[2];
-            const double xmin = std::min({c0[0], c1[0], c2[0]}), xmax = std::max({c0[0], c1[0], c2[0]});
-            const double ymin = std::min({c0[1], c1[1], c2[1]}), ymax = std::max({c0[1], c1[1], c2[1]});
-            auto cell = [](double x, double h, int n) {
-              int c = int(std::floor((x + 1.0) / h));
-              return std::min(std::max(c, 0), n - 2);
-            };
-            const int i0 = cell(xmin, hx, nx), i1 = cell(xmax, hx, nx);
-            const int j0 = cell(ymin, hy, ny), j1 = cell(ymax, hy, ny);
-            for (int cj = j0; cj <= j1; ++cj)
-              for (int ci = i0; ci <= i1; ++ci)
-                for (int sy = 0; sy < nq; ++sy)
-                  for (int sx = 0; sx < nq; ++sx) {
-                    const double s = qx[sx], tt = qx[sy];
-                    const double X = -1.0 + (ci + s) * hx, Y = -1.0 + (cj + tt) * hy;
-                    const double l1 = ((c2[1] - c0[1]) * (X - c0[0]) - (c2[0] - c0[0]) * (Y - c0[1])) / ac2;
-                    const double l2 = ((c1[0] - c0[0]) * (Y - c0[1]) - (c1[1] - c0[1]) * (X - c0[0])) / ac2;
-                    const double l0 = 1.0 - l1 - l2;
-                    if (l0 < 0.0 || l1 < 0.0 || l2 < 0.0) continue;
-                    const double la = a == 0 ? l0 : (a == 1 ? l1 : l2);
-                    const double w = qw[sx] * qw[sy] * hx * hy * jac * la;
-                    const int g00 = cj * nx + ci;
-                    const double ph[4] = {(1 - s) * (1 - tt), s * (1 - tt), (1 - s) * tt, s * tt};
-                    const int gi[4] = {g00, g00 + 1, g00 + nx, g00 + nx + 1};
-                    for (int g = 0; g < 4; ++g) {
-                      const int gx = gi[g] % nx, gy = gi[g] / nx;
-                      if (gx == 0 || gx == nx - 1 || gy == 0 || gy == ny - 1) continue;
-                      row[gi[g]] += w * ph[g];
-                    }
-                  }
+  return rows_parallel(m.nv, [&](int r0, int r1, Csr& out) {
+    std::unordered_map<int, double> row;
+    std::vector<std::pair<int, double>> sorted;
+    for (int v = r0; v < r1; ++v) {
+      row.clear();
+      if (m.dof[v]) {
+        for (int k = m.vt_ptr[v]; k < m.vt_ptr[v + 1]; ++k) {
+          const int* tv = m.tris + 3 * m.vt[k];
+          const int a = tv[0] == v ? 0 : (tv[1] == v ? 1 : 2);
+          const double det = tri_area2(m.xy_c, tv);
+          if (det == 0.0) continue;
+          const double jac = std::fabs(tri_area2(m.xy_p, tv)) / std::fabs(det);
+          double tri[3][2];
+          for (int q = 0; q < 3; ++q) {
+            tri[q][0] = m.xy_c[2 * tv[q]];
+            tri[q][1] = m.xy_c[2 * tv[q] + 1];
           }
+          const int i0 = grid_cell(std::min({tri[0][0], tri[1][0], tri[2][0]}), hx, nx);
+          const int i1 = grid_cell(std::max({tri[0][0], tri[1][0], tri[2][0]}), hx, nx);
+          const int j0 = grid_cell(std::min({tri[0][1], tri[1][1], tri[2][1]}), hy, ny);
+          const int j1 = grid_cell(std::max({tri[0][1], tri[1][1], tri[2][1]}), hy, ny);
+          for (int cj = j0; cj <= j1; ++cj)
+            for (int ci = i0; ci <= i1; ++ci) {
+              double w[3][4];
+              cell_integrals(tri, det, ci, cj, hx, hy, nq, qx.data(), qw.data(), w);
+              const int g00 = cj * nx + ci;
+              const int gi[4] = {g00, g00 + 1, g00 + nx, g00 + nx + 1};
+              for (int g = 0; g < 4; ++g) {
+                const int gx = gi[g] % nx, gy = gi[g] / nx;
+                if (gx == 0 || gx == nx - 1 || gy == 0 || gy == ny - 1) continue;
+                row[gi[g]] += jac * w[a][g];
+              }
+            }
         }
-        sorted.assign(row.begin(), row.end());
-        std::sort(sorted.begin(), sorted.end());
-        for (auto& e : sorted) {
-          if (e.second == 0.0) continue;
-          out.ci.push_back(e.first);
-          out.v.push_back(e.second);
-        }
-        out.rp.push_back(int(out.ci.size()));
       }
-    });
-  }
-  for (auto& x : th) x.join();
-  return merge(m.nv, parts, first);
+      sorted.assign(row.begin(), row.end());
+      std::sort(sorted.begin(), sorted.end());
+      for (auto& e : sorted) {
+        if (e.second == 0.0) continue;
+        out.ci.push_back(e.first);
+        out.v.push_back(e.second);
+      }
+      out.rp.push_back(int(out.ci.size()));
+    }
+  });
 }
 
 Csr assemble_M(const Mesh& m) {
-  Csr out;
-  out.rp.assign(1, 0);
+  return rows_parallel(m.nv, [&](int r0, int r1, Csr& out) {
   std::vector<std::pair<int, double>> row;
-  for (int v = 0; v < m.nv; ++v) {
+  for (int v = r0; v < r1; ++v) {
     row.clear();
     if (!m.dof[v]) {
       row.emplace_back(v, 1.0);
@@ -318,7 +150,7 @@ Csr assemble_M(const Mesh& m) {
     }
     out.rp.push_back(int(out.ci.size()));
   }
-  return out;
+  });
 }
 
 Csr transpose(const Csr& a, int ncols) {
@@ -532,68 +364,112 @@ dmg_status launch_ct(dmg_transfer* t, const double* x, double* r_c, const int* s
 // Internal vertex order: by the grid cell holding each vertex's image (row-major), so that the
 // rows of C and M_p that are used together sit together and their gathers stay in cache.
 std::vector<int> locality_order(const Mesh& m, int nx, int ny) {
+  // counting sort by cell (stable: vertices of one cell keep their index order)
   const double hx = 2.0 / (nx - 1), hy = 2.0 / (ny - 1);
-  std::vector<long> key(m.nv);
+  const size_t ncell = size_t(nx - 1) * (ny - 1);
+  std::vector<int> key(m.nv);
+  std::vector<int> start(ncell + 1, 0);
   for (int v = 0; v < m.nv; ++v) {
     const int ix = std::min(std::max(int(std::floor((m.xy_c[2 * v] + 1.0) / hx)), 0), nx - 2);
     const int iy = std::min(std::max(int(std::floor((m.xy_c[2 * v + 1] + 1.0) / hy)), 0), ny - 2);
-    key[v] = long(iy) * (nx - 1) + ix;
+    key[v] = iy * (nx - 1) + ix;
+    start[size_t(key[v]) + 1]++;
   }
+  for (size_t c = 0; c < ncell; ++c) start[c + 1] += start[c];
   std::vector<int> perm(m.nv);
-  for (int v = 0; v < m.nv; ++v) perm[v] = v;
-  std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return key[a] < key[b]; });
+  for (int v = 0; v < m.nv; ++v) perm[start[key[v]]++] = v;
   return perm;
 }
 
 Csr permute_rows(const Csr& a, const std::vector<int>& perm, const std::vector<int>* colmap) {
-  Csr out;
-  const int n = int(perm.size());
-  out.rp.assign(n + 1, 0);
-  out.ci.reserve(a.ci.size());
-  out.v.reserve(a.v.size());
-  std::vector<std::pair<int, double>> row;
-  for (int i = 0; i < n; ++i) {
-    const int o = perm[i];
-    row.clear();
-    for (int k = a.rp[o]; k < a.rp[o + 1]; ++k)
-      row.emplace_back(colmap ? (*colmap)[a.ci[k]] : a.ci[k], a.v[k]);
-    if (colmap) std::sort(row.begin(), row.end());
-    for (auto& e : row) {
-      out.ci.push_back(e.first);
-      out.v.push_back(e.second);
+  return rows_parallel(int(perm.size()), [&](int r0, int r1, Csr& out) {
+    std::vector<std::pair<int, double>> row;
+    for (int i = r0; i < r1; ++i) {
+      const int o = perm[i];
+      row.clear();
+      for (int k = a.rp[o]; k < a.rp[o + 1]; ++k)
+        row.emplace_back(colmap ? (*colmap)[a.ci[k]] : a.ci[k], a.v[k]);
+      if (colmap) std::sort(row.begin(), row.end());
+      for (auto& e : row) {
+        out.ci.push_back(e.first);
+        out.v.push_back(e.second);
+      }
+      out.rp.push_back(int(out.ci.size()));
     }
-    out.rp[i + 1] = int(out.ci.size());
-  }
-  return out;
+  });
 }
 
 dmg_status transfer_build(const Mesh& m, int nx, int ny, int nq, const std::vector<int>& perm,
-                          hipStream_t stream, std::unique_ptr<dmg_transfer>& out) {
+                          bool device_C, hipStream_t stream, std::unique_ptr<dmg_transfer>& out) {
   const int nv = m.nv;
-  std::vector<int> newidx(nv);
-  for (int i = 0; i < nv; ++i) newidx[perm[i]] = i;
-  const Csr C = permute_rows(assemble_C(m, nx, ny, nq), perm, nullptr);
-  const Csr M = permute_rows(assemble_M(m), perm, &newidx);
-  const Csr CT = transpose(C, nx * ny);
-  std::vector<uint8_t> dof_p(nv);
-  for (int i = 0; i < nv; ++i) dof_p[i] = m.dof[perm[i]];
-  if (C.ci.size() >= (size_t(1) << 31) || M.ci.size() >= (size_t(1) << 31))
-    return fail(DMG_ERR_INVALID_ARG, "transfer matrices exceed 2^31 nonzeros");
+  const size_t ng = size_t(nx) * ny;
   std::unique_ptr<dmg_transfer> t(new dmg_transfer);
   t->nv = nv;
   t->nx = nx;
   t->ny = ny;
-  t->nnzC = int64_t(C.ci.size());
+  auto up = [&](void* dst, const void* src, size_t bytes) -> dmg_status {
+    if (bytes) DMG_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream));
+    return DMG_OK;
+  };
+  // C and C^T: on the device, else (or when a row is too long for the device merge) on the host
+  bool have_C = false;
+  if (device_C) {
+    DeviceCsrPair d;
+    const dmg_status st = device_assemble_C(m, nx, ny, nq, perm, stream, d);
+    if (st == DMG_OK) {
+      t->cblock = d.block;
+      t->Crp = d.rp;
+      t->Cci = d.ci;
+      t->Cv = d.v;
+      t->CTrp = d.trp;
+      t->CTci = d.tci;
+      t->CTv = d.tv;
+      t->nnzC = d.nnz;
+      t->device_C = have_C = true;
+    } else if (st != DMG_ERR_UNSUPPORTED) {
+      return st;
+    }
+    clear_error();
+  }
+  if (!have_C) {
+    const Csr C = permute_rows(assemble_C(m, nx, ny, nq), perm, nullptr);
+    if (C.ci.size() >= (size_t(1) << 31))
+      return fail(DMG_ERR_INVALID_ARG, "transfer matrices exceed 2^31 nonzeros");
+    const Csr CT = transpose(C, int(ng));
+    t->nnzC = int64_t(C.ci.size());
+    Arena sz;
+    auto layout = [&](Arena& a) {
+      t->Crp = a.take<int>(nv + 1);
+      t->Cci = a.take<int>(C.ci.size() + 1);
+      t->Cv = a.take<double>(C.v.size() + 1);
+      t->CTrp = a.take<int>(ng + 1);
+      t->CTci = a.take<int>(CT.ci.size() + 1);
+      t->CTv = a.take<double>(CT.v.size() + 1);
+    };
+    layout(sz);
+    DMG_HIP(hipMalloc(&t->cblock, sz.used));
+    Arena a;
+    a.base = static_cast<char*>(t->cblock);
+    a.cap = sz.used;
+    layout(a);
+    DMG_CHECK(up(t->Crp, C.rp.data(), C.rp.size() * sizeof(int)));
+    DMG_CHECK(up(t->Cci, C.ci.data(), C.ci.size() * sizeof(int)));
+    DMG_CHECK(up(t->Cv, C.v.data(), C.v.size() * sizeof(double)));
+    DMG_CHECK(up(t->CTrp, CT.rp.data(), CT.rp.size() * sizeof(int)));
+    DMG_CHECK(up(t->CTci, CT.ci.data(), CT.ci.size() * sizeof(int)));
+    DMG_CHECK(up(t->CTv, CT.v.data(), CT.v.size() * sizeof(double)));
+    DMG_HIP(hipStreamSynchronize(stream));  // host vectors go out of scope
+  }
+  std::vector<int> newidx(nv);
+  for (int i = 0; i < nv; ++i) newidx[perm[i]] = i;
+  const Csr M = permute_rows(assemble_M(m), perm, &newidx);
+  if (M.ci.size() >= (size_t(1) << 31))
+    return fail(DMG_ERR_INVALID_ARG, "transfer matrices exceed 2^31 nonzeros");
+  std::vector<uint8_t> dof_p(nv);
+  for (int i = 0; i < nv; ++i) dof_p[i] = m.dof[perm[i]];
   t->nnzM = int64_t(M.ci.size());
-  const size_t ng = size_t(nx) * ny;
   Arena sz;
   auto layout = [&](Arena& a) {
-    t->Crp = a.take<int>(nv + 1);
-    t->Cci = a.take<int>(C.ci.size() + 1);
-    t->Cv = a.take<double>(C.v.size() + 1);
-    t->CTrp = a.take<int>(ng + 1);
-    t->CTci = a.take<int>(CT.ci.size() + 1);
-    t->CTv = a.take<double>(CT.v.size() + 1);
     t->Mrp = a.take<int>(nv + 1);
     t->Mci = a.take<int>(M.ci.size() + 1);
     t->Mv = a.take<double>(M.v.size() + 1);
@@ -612,16 +488,6 @@ dmg_status transfer_build(const Mesh& m, int nx, int ny, int nq, const std::vect
   a.base = static_cast<char*>(t->block);
   a.cap = sz.used;
   layout(a);
-  auto up = [&](void* dst, const void* src, size_t bytes) -> dmg_status {
-    if (bytes) DMG_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream));
-    return DMG_OK;
-  };
-  DMG_CHECK(up(t->Crp, C.rp.data(), C.rp.size() * sizeof(int)));
-  DMG_CHECK(up(t->Cci, C.ci.data(), C.ci.size() * sizeof(int)));
-  DMG_CHECK(up(t->Cv, C.v.data(), C.v.size() * sizeof(double)));
-  DMG_CHECK(up(t->CTrp, CT.rp.data(), CT.rp.size() * sizeof(int)));
-  DMG_CHECK(up(t->CTci, CT.ci.data(), CT.ci.size() * sizeof(int)));
-  DMG_CHECK(up(t->CTv, CT.v.data(), CT.v.size() * sizeof(double)));
   DMG_CHECK(up(t->Mrp, M.rp.data(), M.rp.size() * sizeof(int)));
   DMG_CHECK(up(t->Mci, M.ci.data(), M.ci.size() * sizeof(int)));
   DMG_CHECK(up(t->Mv, M.v.data(), M.v.size() * sizeof(double)));
@@ -640,7 +506,7 @@ extern "C" {
 
 dmg_status dmg_transfer_create(int32_t nv, int32_t nt, const double* xy_c, const double* xy_p,
                                const int32_t* tris, const uint8_t* dof, int32_t nx, int32_t ny,
-                               int32_t nq, hipStream_t stream, dmg_transfer** out) {
+                               int32_t nq, int32_t flags, hipStream_t stream, dmg_transfer** out) {
   clear_error();
   if (!out) return fail(DMG_ERR_INVALID_ARG, "null output handle");
   *out = nullptr;
@@ -654,7 +520,8 @@ dmg_status dmg_transfer_create(int32_t nv, int32_t nt, const double* xy_c, const
   Mesh m{nv, nt, xy_c, xy_p, tris, dof, {}, {}};
   build_adjacency(m);
   std::unique_ptr<dmg_transfer> t;
-  DMG_CHECK(transfer_build(m, nx, ny, nq, locality_order(m, nx, ny), stream, t));
+  DMG_CHECK(transfer_build(m, nx, ny, nq, locality_order(m, nx, ny),
+                           (flags & DMG_MESH_HOST_SETUP) == 0, stream, t));
   *out = t.release();
   return DMG_OK;
 }
@@ -664,6 +531,34 @@ dmg_status dmg_transfer_info(const dmg_transfer* t, int64_t* nnz_C, int64_t* nnz
   if (!t) return fail(DMG_ERR_INVALID_ARG, "null transfer");
   if (nnz_C) *nnz_C = t->nnzC;
   if (nnz_M) *nnz_M = t->nnzM;
+  return DMG_OK;
+}
+
+dmg_status dmg_transfer_copy_C(const dmg_transfer* t, int32_t* rp, int32_t* ci, double* v) {
+  clear_error();
+  if (!t || !rp || (t->nnzC > 0 && (!ci || !v)))
+    return fail(DMG_ERR_INVALID_ARG, "null pointer argument");
+  const int n = t->nv;
+  std::vector<int> irp(n + 1), perm(n), ici(size_t(t->nnzC));
+  std::vector<double> iv(size_t(t->nnzC));
+  DMG_HIP(hipMemcpy(irp.data(), t->Crp, (n + 1) * sizeof(int), hipMemcpyDeviceToHost));
+  DMG_HIP(hipMemcpy(perm.data(), t->perm, n * sizeof(int), hipMemcpyDeviceToHost));
+  if (t->nnzC > 0) {
+    DMG_HIP(hipMemcpy(ici.data(), t->Cci, ici.size() * sizeof(int), hipMemcpyDeviceToHost));
+    DMG_HIP(hipMemcpy(iv.data(), t->Cv, iv.size() * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  // internal row i is the caller's row perm[i]
+  std::vector<int> len(n);
+  for (int i = 0; i < n; ++i) len[perm[i]] = irp[i + 1] - irp[i];
+  rp[0] = 0;
+  for (int r = 0; r < n; ++r) rp[r + 1] = rp[r] + len[r];
+  for (int i = 0; i < n; ++i) {
+    const int dst = rp[perm[i]];
+    for (int k = irp[i]; k < irp[i + 1]; ++k) {
+      ci[dst + k - irp[i]] = ici[k];
+      v[dst + k - irp[i]] = iv[k];
+    }
+  }
   return DMG_OK;
 }
 

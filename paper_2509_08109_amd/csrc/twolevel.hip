@@ -367,11 +367,10 @@ void element_stiffness(const double* xy, const int* tv, double G[3][3]) {
 
 // A_p in the caller's order, split into its diagonal and its off-diagonal CSR.
 void assemble_A(const Mesh& m, const double* K_t, Csr& off, std::vector<double>& diag) {
-  off = Csr{};
-  off.rp.assign(1, 0);
   diag.assign(m.nv, 1.0);
+  off = rows_parallel(m.nv, [&](int r0, int r1, Csr& out) {
   std::vector<std::pair<int, double>> row;
-  for (int v = 0; v < m.nv; ++v) {
+  for (int v = r0; v < r1; ++v) {
     row.clear();
     if (m.dof[v]) {
       double dv = 0.0;
@@ -399,11 +398,12 @@ void assemble_A(const Mesh& m, const double* K_t, Csr& off, std::vector<double>&
       row.resize(w);
     }
     for (auto& e : row) {
-      off.ci.push_back(e.first);
-      off.v.push_back(e.second);
+      out.ci.push_back(e.first);
+      out.v.push_back(e.second);
     }
-    off.rp.push_back(int(off.ci.size()));
+    out.rp.push_back(int(out.ci.size()));
   }
+  });
 }
 
 // Greedy colours on the mesh graph, vertices in the caller's index order.
@@ -440,8 +440,8 @@ extern "C" {
 
 dmg_status dmg_twolevel_create(int32_t nv, int32_t nt, const double* xy_c, const double* xy_p,
                                const int32_t* tris, const uint8_t* dof, const double* K_t,
-                               dmg_hier* grid, int32_t nq, int32_t mass, hipStream_t stream,
-                               dmg_twolevel** out) {
+                               dmg_hier* grid, int32_t nq, int32_t mass, int32_t flags,
+                               hipStream_t stream, dmg_twolevel** out) {
   clear_error();
   if (!out) return fail(DMG_ERR_INVALID_ARG, "null output handle");
   *out = nullptr;
@@ -466,14 +466,19 @@ dmg_status dmg_twolevel_create(int32_t nv, int32_t nt, const double* xy_c, const
   tl->mass = mass;
   tl->colour = greedy_colours(m);
   const int ncol = 1 + *std::max_element(tl->colour.begin(), tl->colour.end());
-  // internal order: colour-major, the transfers' grid-cell order within a colour
-  std::vector<int> perm = locality_order(m, nx, ny);
-  std::stable_sort(perm.begin(), perm.end(),
-                   [&](int a, int b) { return tl->colour[a] < tl->colour[b]; });
+  // internal order: colour-major, the transfers' grid-cell order within a colour (a stable
+  // counting sort of the cell order by colour)
   tl->cs.assign(ncol + 1, 0);
   for (int v = 0; v < nv; ++v) tl->cs[tl->colour[v] + 1]++;
   for (int c = 0; c < ncol; ++c) tl->cs[c + 1] += tl->cs[c];
-  DMG_CHECK(transfer_build(m, nx, ny, nq, perm, stream, tl->t));
+  std::vector<int> perm(nv);
+  {
+    const std::vector<int> cell = locality_order(m, nx, ny);
+    std::vector<int> pos(tl->cs.begin(), tl->cs.end() - 1);
+    for (int v : cell) perm[pos[tl->colour[v]]++] = v;
+  }
+  DMG_CHECK(transfer_build(m, nx, ny, nq, perm, (flags & DMG_MESH_HOST_SETUP) == 0, stream,
+                           tl->t));
   std::vector<int> newidx(nv);
   for (int i = 0; i < nv; ++i) newidx[perm[i]] = i;
   Csr off;

@@ -113,10 +113,10 @@ def test_transfer_validation_on_host(dmg):
     tris = np.array([[0, 1, 5]], dtype=np.int32)       # index out of range
     dof = np.ones(3, dtype=np.uint8)
     st = lib.dmg_transfer_create(3, 1, xy.ctypes.data, xy.ctypes.data, tris.ctypes.data, dof.ctypes.data,
-                                 9, 9, 4, None, C.byref(h))
+                                 9, 9, 4, 0, None, C.byref(h))
     assert st == 1 and "out of range" in lib.dmg_last_error().decode()
     assert lib.dmg_transfer_create(3, 1, xy.ctypes.data, xy.ctypes.data, tris.ctypes.data, dof.ctypes.data,
-                                   9, 9, -1, None, C.byref(h)) == 1
+                                   9, 9, -1, 0, None, C.byref(h)) == 1
     assert "nq" in lib.dmg_last_error().decode()
 
 
@@ -130,15 +130,15 @@ def test_twolevel_validation_on_host(dmg):
     tris = np.array([[0, 1, 2]], dtype=np.int32)
     dof = np.ones(3, dtype=np.uint8)
     args = lambda tr, xyp: (3, 1, xy.ctypes.data, xyp.ctypes.data, tr.ctypes.data, dof.ctypes.data)
-    assert lib.dmg_twolevel_create(*args(tris, xy), None, None, 8, 0, None, C.byref(h)) == 1
-    assert lib.dmg_twolevel_create(*args(tris, xy), None, fake, 8, 3, None, C.byref(h)) == 1
+    assert lib.dmg_twolevel_create(*args(tris, xy), None, None, 8, 0, 0, None, C.byref(h)) == 1
+    assert lib.dmg_twolevel_create(*args(tris, xy), None, fake, 8, 3, 0, None, C.byref(h)) == 1
     assert "mass" in lib.dmg_last_error().decode()
-    assert lib.dmg_twolevel_create(*args(tris, xy), None, fake, -1, 0, None, C.byref(h)) == 1
+    assert lib.dmg_twolevel_create(*args(tris, xy), None, fake, -1, 0, 0, None, C.byref(h)) == 1
     bad = np.array([[0, 1, 7]], dtype=np.int32)
-    assert lib.dmg_twolevel_create(*args(bad, xy), None, fake, 8, 0, None, C.byref(h)) == 1
+    assert lib.dmg_twolevel_create(*args(bad, xy), None, fake, 8, 0, 0, None, C.byref(h)) == 1
     assert "out of range" in lib.dmg_last_error().decode()
     flat = np.array([[0.0, 0.0], [1.0, 0.0], [2.0, 0.0]])
-    assert lib.dmg_twolevel_create(*args(tris, flat), None, fake, 8, 0, None, C.byref(h)) == 1
+    assert lib.dmg_twolevel_create(*args(tris, flat), None, fake, 8, 0, 0, None, C.byref(h)) == 1
     assert "degenerate" in lib.dmg_last_error().decode()
     assert lib.dmg_twolevel_solve(None, fake, fake, 1e-10, 10, None, None, None, None) == 1
     assert lib.dmg_twolevel_cycle(None, fake, fake, None) == 1
