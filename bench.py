@@ -396,6 +396,56 @@ def run_twolevel_leg(dmg, dev, sizes=(129, 257, 513), seed: int = 1, reps: int =
                         "rtol 1e-10 relative to the initial residual", "sizes": rows}
 
 
+def run_discontinuous_leg(dmg, dev, n: int = 513):
+    """The paper's variable-coefficient problems on the unit square (identity map; diffusivity
+    100 in a disc of radius 3/5, on a 4 x 4 checkerboard, or 1e-10 in a stripe of width 0.06;
+    K per cell = mean at the Gauss points, K per triangle at the centroid): grid solves and
+    two-level solves (lumped mass, exact C) to 1e-10, cycles and wall time; a two-level solve that
+    does not converge in 300 cycles is reported as such."""
+    import numpy as np
+    import torch
+
+    import problems as pb
+    out = {}
+    for kind in pb.DISCONTINUOUS:
+        D = pb.discontinuous_dmg(kind, n)
+        P = D.grid
+        as_dev = lambda x: torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
+        H = dmg.Hierarchy(dmg.assemble_stencil(as_dev(P.jac), as_dev(P.K)))
+        b = as_dev(P.b)
+        H.solve(b, rtol=1e-10, max_iters=300, raise_on_fail=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, k_g, rel_g, _ = H.solve(b, rtol=1e-10, max_iters=300, raise_on_fail=False)
+        torch.cuda.synchronize()
+        t_g = time.perf_counter() - t0
+        m = D.mesh
+        tl = dmg.TwoLevel(H, m.xy_c, m.xy_p, m.tris, m.dof, K_t=D.K_t)
+        f = as_dev(D.f)
+        try:
+            tl.solve(f, rtol=1e-10, max_iters=300, raise_on_fail=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, k_t, rel_t, _ = tl.solve(f, rtol=1e-10, max_iters=300, raise_on_fail=False)
+            torch.cuda.synchronize()
+            t_t = time.perf_counter() - t0
+        except dmg.DmgError as e:      # the iterates overflowed: the cycle diverges here
+            k_t, rel_t, t_t = None, float("inf"), float("nan")
+            log(f"{kind}: two-level solve diverged ({e})")
+        out[kind] = {"grid_cycles": k_g, "grid_relres": rel_g, "grid_solve_ms": round(1e3 * t_g, 3),
+                     "mesh_vertices": int(m.nv), "twolevel_cycles": k_t, "twolevel_relres": rel_t,
+                     "twolevel_converged": bool(rel_t <= 1e-10),
+                     "twolevel_solve_ms": round(1e3 * t_t, 3)}
+        log(f"{kind}: grid {k_g} cycles, two-level {k_t} cycles (rel. residual {rel_t:.1e})")
+        if not np.isfinite(out[kind]["twolevel_solve_ms"]):
+            out[kind]["twolevel_solve_ms"] = None
+        if not np.isfinite(rel_t):
+            out[kind]["twolevel_relres"] = None
+        tl.close()
+        H.close()
+    return {"grid": [n, n], "workload": "unit square, identity map, discontinuous diffusivity", **out}
+
+
 CPU_SNIPPET = r"""
 import json, sys, time
 sys.path.insert(0, {root!r})
@@ -448,6 +498,7 @@ def main():
     ap.add_argument("--no-c5", action="store_true", help="skip the 2049 x 2049 gradient leg")
     ap.add_argument("--no-transfer", action="store_true", help="skip the grid <-> mesh transfer leg")
     ap.add_argument("--no-twolevel", action="store_true", help="skip the two-level mesh cycle leg")
+    ap.add_argument("--no-disc", action="store_true", help="skip the discontinuous-coefficient leg")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -544,6 +595,9 @@ def main():
     if not args.no_twolevel:
         log("two-level leg: star meshes at grids 129, 257, 513")
         res["twolevel"] = run_twolevel_leg(dmg, dev)
+    if not args.no_disc:
+        log("discontinuous-coefficient leg: 513x513 unit square")
+        res["discontinuous"] = run_discontinuous_leg(dmg, dev)
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         res["cpu_baseline"] = cpu_baseline(args.n, args.seed)

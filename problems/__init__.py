@@ -8,6 +8,8 @@ Workloads (every random draw comes from numpy.random.SeedSequence(root).spawn(..
   quarter_annulus(n, seed)   : n x n grid, K = 1, b ~ U(-1,1)         (root 0)
   star(n, seed)              : star domain, log-normal K, b ~ U(-1,1)  (roots 1, 2, 4)
   batch(count, sizes, seed)  : independent star instances of mixed sizes (root 3)
+  discontinuous(kind, n)     : unit square, identity map, the discontinuous diffusivities of
+                               the paper's variable-coefficient problems, b ~ U(-1,1) (root 5)
 """
 from __future__ import annotations
 
@@ -23,7 +25,8 @@ from .mesh import Mesh, lattice_mesh, mesh_points_for_grid
 __all__ = ["Problem", "quarter_annulus", "star", "identity", "batch", "Affine", "Identity",
            "QuarterAnnulus", "Star", "conformal_square_to_disk", "sample_jacobian", "lognormal_K",
            "uniform_rhs", "smooth_target", "grid_coords", "GAUSS_OFFSETS", "Mesh", "lattice_mesh",
-           "mesh_points_for_grid", "streams", "DmgProblem", "star_dmg"]
+           "mesh_points_for_grid", "streams", "DmgProblem", "star_dmg", "unit_square_K",
+           "discontinuous", "discontinuous_dmg", "DISCONTINUOUS"]
 
 
 @dataclass
@@ -130,3 +133,83 @@ def batch(count: int, choices=(129, 257, 513, 1025), seed: int = 3, lognormal: b
         out.append(Problem(f"star[{k}]", n, n, mp, sample_jacobian(mp, n, n), K,
                            uniform_rhs(n, n, g_b), None))
     return out
+
+
+DISCONTINUOUS = ("circle", "checker", "layer")
+
+
+def unit_square_K(kind: str, x, y) -> np.ndarray:
+    """The discontinuous diffusivities of Sec. 4.2's variable-coefficient problems on the unit
+    square, at physical points (x, y):
+      circle : 100 inside the circle of radius 3/5 about the origin, 1 elsewhere;
+      checker: 100 where floor(4x) + floor(4y) is even, 1 elsewhere (a 4 x 4 checkerboard);
+      layer  : 1e-10 in the stripe 0 <= x < 0.06, 2 elsewhere."""
+    x, y = np.asarray(x, dtype=np.float64), np.asarray(y, dtype=np.float64)
+    if kind == "circle":
+        return np.where(np.hypot(x, y) < 0.6, 100.0, 1.0)
+    if kind == "checker":
+        return np.where((np.floor(4 * x) + np.floor(4 * y)) % 2 == 0, 100.0, 1.0)
+    if kind == "layer":
+        return np.where((x >= 0.0) & (x < 0.06), 1e-10, 2.0)
+    raise ValueError(f"unknown coefficient {kind!r}")
+
+
+def _unit_square():
+    # (-1, 1)^2 -> [0, 1]^2: the identity up to a uniform scaling, which leaves the pulled-back
+    # operator of a scalar coefficient unchanged (D_c = K I)
+    return Affine(0.5 * np.eye(2), np.array([0.5, 0.5]))
+
+
+SUB = 16  # sub-samples per direction for cell and triangle averages of a discontinuous K
+
+
+def discontinuous(kind: str, n: int, seed: int = 5, ny: int | None = None) -> Problem:
+    """Unit square with the discontinuous diffusivity ``kind``, b ~ U(-1, 1).  A cell's K is the
+    cell average of the diffusivity (a 16 x 16 midpoint rule): with the constant metric of this
+    affine map, that is what a stiffness quadrature of high order in the coefficient computes,
+    which is what a rapidly changing coefficient calls for.  (The grid is not aligned with the
+    circle or the stripe; the checkerboard lines fall on grid lines when 4 divides n - 1.)"""
+    ny = ny or n
+    _, _, g_b, g_t, _ = streams(seed)
+    mp = _unit_square()
+    xi, eta = grid_coords(n, ny)
+    hx, hy = xi[1] - xi[0], eta[1] - eta[0]
+    K = np.zeros((ny - 1, n - 1))
+    for qy in range(SUB):
+        for qx in range(SUB):
+            XX, YY = np.meshgrid(xi[:-1] + hx * (qx + 0.5) / SUB, eta[:-1] + hy * (qy + 0.5) / SUB)
+            x, y = mp(XX, YY)
+            K += unit_square_K(kind, x, y) / SUB ** 2
+    return Problem(f"disc_{kind}", n, ny, mp, sample_jacobian(mp, n, ny), K,
+                   uniform_rhs(n, ny, g_b), smooth_target(n, ny, g_t))
+
+
+def triangle_average(kind: str, xy: np.ndarray) -> np.ndarray:
+    """Average of unit_square_K over each triangle xy [nt][3][2]: the mean over the centroids of
+    its 16 congruent sub-triangles (4 x 4 subdivision)."""
+    out = np.zeros(xy.shape[0])
+    s = 4
+    cnt = 0
+    for i in range(s):
+        for j in range(s - i):
+            # upward sub-triangle (i, j) and, where it exists, the downward one beside it
+            cents = [((i + 1 / 3) / s, (j + 1 / 3) / s)]
+            if i + j < s - 1:
+                cents.append(((i + 2 / 3) / s, (j + 2 / 3) / s))
+            for a, b in cents:
+                p = xy[:, 0] + a * (xy[:, 1] - xy[:, 0]) + b * (xy[:, 2] - xy[:, 0])
+                out += unit_square_K(kind, p[:, 0], p[:, 1])
+                cnt += 1
+    return out / cnt
+
+
+def discontinuous_dmg(kind: str, n: int, seed: int = 5, m: int | None = None) -> DmgProblem:
+    """The physical P1 problem of ``discontinuous(kind, n)``: a jittered lattice mesh of the unit
+    square (about n^2 / 0.28 vertices; not aligned with the discontinuities), K per triangle its
+    average over the triangle (triangle_average), f ~ U(-1, 1) on free vertices."""
+    grid = discontinuous(kind, n, seed)
+    g = streams(seed, 7)
+    mesh = lattice_mesh(grid.map, m or mesh_points_for_grid(n), g[5])
+    K_t = triangle_average(kind, mesh.xy_p[mesh.tris])
+    f = np.where(mesh.dof, g[6].uniform(-1.0, 1.0, size=mesh.dof.shape[0]), 0.0)
+    return DmgProblem(grid, mesh, K_t, f)

@@ -42,6 +42,10 @@ PROBLEMS = {
     "annulus65": lambda: pb.quarter_annulus(65),
     "star129": lambda: pb.star(129, seed=1),
     "star65x129": lambda: pb.star(65, seed=1, ny=129),
+    # the discontinuous diffusivities of the paper's variable-coefficient problems
+    "circle65": lambda: pb.discontinuous("circle", 65),
+    "checker65": lambda: pb.discontinuous("checker", 65),
+    "layer65": lambda: pb.discontinuous("layer", 65),
 }
 
 

@@ -38,12 +38,13 @@ def relerr(a, b):
 _CACHE = {}
 
 
-def pair(lib, n, seed=1, mass="lumped", nq=0):
-    """(problem, oracle two-level, GPU two-level) on the star mesh of grid size n; nq = 0 is the
-    exact coupled mass, nq > 0 the rasterised rule of that order."""
-    key = (n, seed, mass, nq)
+def pair(lib, n, seed=1, mass="lumped", nq=0, kind=None):
+    """(problem, oracle two-level, GPU two-level) on the star mesh of grid size n (or on the unit
+    square with the discontinuous diffusivity ``kind``); nq = 0 is the exact coupled mass, nq > 0
+    the rasterised rule of that order."""
+    key = (n, seed, mass, nq, kind)
     if key not in _CACHE:
-        P = pb.star_dmg(n, seed=seed)
+        P = pb.star_dmg(n, seed=seed) if kind is None else pb.discontinuous_dmg(kind, n)
         m = P.mesh
         A = dmg.p1_stiffness(m.xy_p, m.tris, m.dof, P.K_t)
         M = transfer.p1_mass(m.xy_p, m.tris, m.dof)
@@ -193,3 +194,16 @@ def test_scaling_estimate_needs_lumped_mass(lib):
     P, orc, tl = pair(lib, 17, mass="cg2")
     with pytest.raises(lib.DmgError):
         tl.estimate_scaling(torch.ones((17, 17), dtype=torch.float64, device="cuda"), 4)
+
+
+@pytest.mark.parametrize("kind", ["circle", "checker", "layer"])
+def test_discontinuous_cycles_match_oracle(lib, kind):
+    """The unit-square problems with discontinuous diffusivity (contrast up to 2e10)."""
+    P, orc, tl = pair(lib, 33, kind=kind)
+    g = np.random.Generator(np.random.PCG64(13))
+    u0 = np.where(P.mesh.dof, g.uniform(-1, 1, P.mesh.nv), 0.0)
+    uo, ug, fg = u0.copy(), dev(u0), dev(P.f)
+    for k in range(2):
+        orc.cycle(uo, P.f)
+        tl.cycle(ug, fg)
+        assert relerr(host(ug), uo) <= TOL, k

@@ -171,3 +171,46 @@ def test_device_star_dmg_reproduces_host_star_dmg():
     assert np.allclose(K_t, P.K_t, rtol=1e-12, atol=0)
     assert np.allclose(jac.numpy(), P.grid.jac, rtol=1e-12, atol=1e-14)
     assert np.allclose(K.numpy(), P.grid.K, rtol=1e-12, atol=0)
+
+
+def test_discontinuous_coefficients():
+    """The unit-square problems: the map is the uniform scaling (-1, 1)^2 -> [0, 1]^2 (constant
+    Jacobian I / 2) and each cell's K is the mean of the diffusivity at its Gauss points."""
+    n = 33
+    for kind in pb.DISCONTINUOUS:
+        P = pb.discontinuous(kind, n)
+        assert P.jac.shape == (16, n - 1, n - 1)
+        J = P.jac.reshape(4, 4, n - 1, n - 1)
+        assert np.allclose(J[:, 0], 0.5) and np.allclose(J[:, 3], 0.5)
+        assert np.allclose(J[:, 1], 0.0) and np.allclose(J[:, 2], 0.0)
+    # checkerboard lines fall on grid lines when 4 divides n - 1: cells are pure, half of each
+    K = pb.discontinuous("checker", n).K
+    assert set(np.unique(K)) == {1.0, 100.0} and np.count_nonzero(K == 100.0) == K.size // 2
+    assert K[0, 0] == 100.0 and K[0, (n - 1) // 4] == 1.0
+    # circle of radius 3/5 about the corner: a quarter disc, area 0.09 pi of the unit square
+    K = pb.discontinuous("circle", 129).K
+    frac = (K - 1.0).sum() / (99.0 * K.size)
+    assert abs(frac - 0.09 * np.pi) < 5e-3
+    # the stripe 0 <= x < 0.06 along the left edge
+    K = pb.discontinuous("layer", 129).K
+    assert np.allclose(K[:, 0], 1e-10, rtol=1e-12) and np.all(K[:, 10:] == 2.0)
+    # triangle averages: triangles wholly inside or outside the stripe keep its value, the
+    # others lie in between
+    D = pb.discontinuous_dmg("layer", 17)
+    xs = D.mesh.xy_p[D.mesh.tris][:, :, 0]
+    inside, outside = (xs < 0.06).all(axis=1), (xs >= 0.06).all(axis=1)
+    assert inside.any() and outside.any() and (~inside & ~outside).any()
+    assert np.allclose(D.K_t[inside], 1e-10, rtol=1e-12) and np.all(D.K_t[outside] == 2.0)
+    mixed = D.K_t[~inside & ~outside]
+    assert np.all((mixed >= 1e-10) & (mixed <= 2.0))
+    # the average over a triangle integrates a linear function exactly: the 16 sub-triangle
+    # centroids have the triangle's centroid as their mean
+    tri = np.array([[[0.1, 0.2], [0.7, 0.3], [0.4, 0.9]]])
+    xs = []
+    saved = pb.unit_square_K
+    try:
+        pb.unit_square_K = lambda kind, x, y: np.asarray(x)      # K(x, y) = x
+        avg = pb.triangle_average("linear", tri)
+    finally:
+        pb.unit_square_K = saved
+    assert abs(avg[0] - tri[0, :, 0].mean()) < 1e-15
