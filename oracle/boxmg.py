@@ -129,9 +129,12 @@ class Level:
 
 
 def build_hierarchy(S: np.ndarray, coarsest_n: int = 3):
-    """Levels from the fine stencil down to the first grid with min(nx, ny) <= coarsest_n."""
+    """Levels from the fine stencil down to the first grid with min(nx, ny) <= coarsest_n, or
+    with an even dimension (coarsening by two keeps the boundary on a coarse line only for odd
+    dims), which is solved directly."""
     levels = [Level(np.array(S, dtype=np.float64))]
-    while min(levels[-1].nx, levels[-1].ny) > coarsest_n:
+    while (min(levels[-1].nx, levels[-1].ny) > coarsest_n
+           and levels[-1].nx % 2 == 1 and levels[-1].ny % 2 == 1):
         L = levels[-1]
         L.P = interpolation(L.S)
         levels.append(Level(galerkin(L.S, L.P)))

@@ -211,3 +211,31 @@ def test_complexities_are_bounded():
     levels = boxmg.build_hierarchy(_S(pb.star(129, seed=1)))
     gc, oc = boxmg.complexities(levels)
     assert 1.0 < gc < 4.0 / 3.0 + 1e-12 and 1.0 < oc < 1.4
+
+
+def test_odd_dims_coarsen_until_a_dim_turns_even():
+    """Dims of the form c 2^k + 1 (c odd): 25 = 3 * 8 + 1 stops at 4; the identity map still
+    gives the coarse Q1 stencil at every level (2:1 coarsening with aligned boundaries), and the
+    solve equals a sparse direct solve on a grid with the paper's 1.5 aspect ratio."""
+    levels = boxmg.build_hierarchy(_S(pb.identity(25)))
+    assert [L.nx for L in levels] == [25, 13, 7, 4]
+    for L in levels[:-1]:
+        S = L.S
+        assert np.allclose(S[0][1:-1, 1:-1], 8 / 3, atol=1e-12)
+        assert np.allclose(S[1][1:-1, 2:-1], -1 / 3, atol=1e-12)
+        assert np.allclose(S[3][2:-1, 2:-1], -1 / 3, atol=1e-12)
+    # the coarsest 4 x 4 level (2 x 2 unknowns) is the Galerkin product, solved directly
+    assert np.allclose(levels[-1].S[0][1:-1, 1:-1], 8 / 3, atol=1e-12)
+    prob = pb.quarter_annulus(33, ny=49)
+    levels = boxmg.build_hierarchy(_S(prob))
+    assert [(L.nx, L.ny) for L in levels] == [(33, 49), (17, 25), (9, 13), (5, 7), (3, 4)]
+    orc = cycle.Oracle(levels)
+    u, k, hist, _ = cycle.solve(orc, prob.b, rtol=1e-10)
+    m = np.zeros((49, 33), bool)
+    m[1:-1, 1:-1] = True
+    A = levels[0].A.tocsr()
+    x = spl.spsolve(A[m.ravel()][:, m.ravel()].tocsc(), prob.b[m])
+    assert hist[-1] <= 1e-10 and np.linalg.norm(u[m] - x) / np.linalg.norm(x) < 1e-7
+    # 45 x 67: 67 -> 34 turns even after one coarsening; the 23 x 34 coarsest is solved directly
+    levels = boxmg.build_hierarchy(_S(pb.star(45, seed=1, ny=67)))
+    assert [(L.nx, L.ny) for L in levels] == [(45, 67), (23, 34)]
