@@ -46,7 +46,7 @@ extern "C" {
 typedef enum dmg_status {
   DMG_OK = 0,
   DMG_ERR_INVALID_ARG = 1,    /* null pointer, negative size, bad option value          */
-  DMG_ERR_DIMS = 2,           /* grid dims not 2^k+1, or inconsistent sizes               */
+  DMG_ERR_DIMS = 2,           /* grid dims even or < 3, coarsest grid too large          */
   DMG_ERR_WORKSPACE = 3,      /* workspace missing, misaligned (256 B) or too small        */
   DMG_ERR_NOT_SPD = 4,        /* coarsest-level Cholesky met a non-positive pivot          */
   DMG_ERR_NONFINITE = 5,      /* NaN/Inf in a residual norm                               */
@@ -108,7 +108,11 @@ dmg_status dmg_assemble_stencil(const double* jac, const double* K, int32_t nx, 
  * aligned) which must outlive the handle; the library does not allocate device memory for it.
  * The fine stencil S is copied into the workspace (the caller may free it after setup).
  * Setup synchronises `stream` once to read the coarsest pivot check.
- * Errors: DMG_ERR_DIMS (not 2^k+1), DMG_ERR_WORKSPACE, DMG_ERR_NOT_SPD, DMG_ERR_HIP. */
+ * Dims: each odd and >= 3.  A level of odd dims coarsens to ((nx + 1) / 2, (ny + 1) / 2); the
+ * first level with min(nx, ny) <= coarsest_n or an even dim is the coarsest, which must be at
+ * most 65 points a side with at most 4096 unknowns (2^k + 1 dims reach 3; c 2^k + 1 with c
+ * odd reaches c + 1).
+ * Errors: DMG_ERR_DIMS, DMG_ERR_WORKSPACE, DMG_ERR_NOT_SPD, DMG_ERR_HIP. */
 dmg_status dmg_workspace_bytes(int32_t nx, int32_t ny, const dmg_options* opts, size_t* bytes);
 dmg_status dmg_setup(const double* S, int32_t nx, int32_t ny, const dmg_options* opts,
                      void* workspace, size_t ws_bytes, hipStream_t stream, dmg_hier** out);
@@ -212,7 +216,7 @@ dmg_status dmg_transfer_to_grid(dmg_transfer* t, const double* r_p, double* r_c,
 void dmg_transfer_destroy(dmg_transfer* t);
 
 /* ---- a10: batched solve of independent instances ----------------------------------------
- * count instances with dims nx[k], ny[k] (host arrays, any mix of 2^k+1 sizes) and fine stencils
+ * count instances with dims nx[k], ny[k] (host arrays, any mix of sizes dmg_setup accepts) and fine stencils
  * S[k] (host array of device pointers).  One workspace holds every hierarchy plus the batch's
  * schedule.  dmg_batch_solve runs one batched V-cycle per step: each fused sweep is launched
  * once per level size over the tiles of every instance having a level of that size (largest

@@ -27,12 +27,6 @@ void clear_error() { g_err[0] = 0; }
 
 namespace {
 
-bool pow2p1(int n) {
-  if (n < 3) return false;
-  const int m = n - 1;
-  return (m & (m - 1)) == 0;
-}
-
 dmg_status check_options(const dmg_options* o) {
   if (!o) return fail(DMG_ERR_INVALID_ARG, "options pointer is null");
   if (o->nu_pre < 0 || o->nu_post < 0 || o->nu_pre + o->nu_post == 0 || o->nu_pre > 8 ||
@@ -61,14 +55,25 @@ dmg_status check_options(const dmg_options* o) {
   return DMG_OK;
 }
 
+// Levels: an odd n coarsens to (n + 1) / 2, which keeps the boundaries aligned; coarsening stops
+// at the first level with min(nx, ny) <= coarsest_n or with an even dimension, which is the
+// coarsest (solved directly).  2^k + 1 dims coarsen down to 3; n = c 2^k + 1 (c odd) down to
+// c + 1.
 dmg_status level_dims(int nx, int ny, int coarsest_n, std::vector<std::pair<int, int>>& dims) {
-  if (!pow2p1(nx) || !pow2p1(ny))
-    return fail(DMG_ERR_DIMS, "grid dims %d x %d: each must be 2^k+1 with k >= 1", nx, ny);
+  if (nx < 3 || ny < 3 || nx % 2 == 0 || ny % 2 == 0)
+    return fail(DMG_ERR_DIMS, "grid dims %d x %d: each must be odd and >= 3", nx, ny);
   dims.clear();
   dims.emplace_back(nx, ny);
-  while (std::min(dims.back().first, dims.back().second) > coarsest_n)
-    dims.emplace_back((dims.back().first + 1) / 2, (dims.back().second + 1) / 2);
+  for (;;) {
+    const auto c = dims.back();
+    if (std::min(c.first, c.second) <= coarsest_n || c.first % 2 == 0 || c.second % 2 == 0) break;
+    dims.emplace_back((c.first + 1) / 2, (c.second + 1) / 2);
+  }
   const auto& c = dims.back();
+  if (std::max(c.first, c.second) > kTailMaxN)
+    return fail(DMG_ERR_DIMS,
+                "coarsest grid %d x %d is wider than %d points; use dims of the form c 2^k + 1 "
+                "with a small odd c", c.first, c.second, kTailMaxN);
   const long m = long(c.first - 2) * long(c.second - 2);
   if (m > 4096)
     return fail(DMG_ERR_DIMS, "coarsest system has %ld unknowns (max 4096); lower coarsest_n", m);

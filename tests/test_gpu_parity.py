@@ -42,6 +42,11 @@ PROBLEMS = {
     "annulus65": lambda: pb.quarter_annulus(65),
     "star129": lambda: pb.star(129, seed=1),
     "star65x129": lambda: pb.star(65, seed=1, ny=129),
+    # odd dims that are not 2^k + 1: the paper's 1.5 aspect ratio (33 x 49 -> ... -> 3 x 4),
+    # 97 = 3 * 32 + 1 (coarsest 4 x 3), and 45 x 67 (coarsest 23 x 34, 672 unknowns)
+    "annulus33x49": lambda: pb.quarter_annulus(33, ny=49),
+    "star97x65": lambda: pb.star(97, seed=1, ny=65),
+    "star45x67": lambda: pb.star(45, seed=1, ny=67),
     # the discontinuous diffusivities of the paper's variable-coefficient problems
     "circle65": lambda: pb.discontinuous("circle", 65),
     "checker65": lambda: pb.discontinuous("checker", 65),
@@ -370,6 +375,29 @@ def test_batch_matches_single_solves(dmg):
     us2, its2, rels2 = bt.solve(bs, rtol=1e-10)
     assert its2 == its and all(torch.equal(a, c) for a, c in zip(us, us2))
     bt.close()
+
+
+def test_batch_with_odd_dims_matches_single_solves(dmg):
+    """Odd dims that are not 2^k + 1, rectangular, mixed with a 2^k + 1 instance; two instances
+    share every level size (97 x 65)."""
+    probs = [pb.star(97, seed=31, ny=65), pb.quarter_annulus(33, ny=49), pb.star(65, seed=32),
+             pb.star(45, seed=33, ny=67), pb.star(97, seed=34, ny=65)]
+    Ss = [dmg.assemble_stencil(dev(p.jac), dev(p.K)) for p in probs]
+    bs = [dev(p.b) for p in probs]
+    bt = dmg.BatchSolver(Ss)
+    us, its, rels = bt.solve(bs, rtol=1e-10)
+    _batch_vs_single(dmg, Ss, bs, bt, us, its, rels)
+    bt.close()
+
+
+def test_fp32_refinement_on_odd_dims(dmg):
+    prob = pb.star(97, seed=1, ny=65)
+    S_or = fem.assemble_stencil(prob.jac, prob.K, prob.nx, prob.ny)
+    h = dmg.Hierarchy(dev(S_or), precision=dmg.DMG_FP32_IR)
+    x, k, rel, hist = h.solve(dev(prob.b), rtol=1e-10)
+    uo, ko, histo, _ = cycle.solve(cycle.Oracle(boxmg.build_hierarchy(S_or)), prob.b, rtol=1e-10)
+    assert rel <= 1e-10 and abs(k - ko) <= 1
+    assert relerr(host(x), uo) <= 1e-8
 
 
 def test_batch_zero_rhs_and_limits(dmg):

@@ -58,7 +58,23 @@ def test_workspace_rejects_bad_dims(dmg, nx, ny):
     nbytes = C.c_size_t()
     st = lib.dmg_workspace_bytes(nx, ny, C.byref(dmg.default_options()), C.byref(nbytes))
     assert st == 2
-    assert "2^k+1" in lib.dmg_last_error().decode()
+    assert "odd" in lib.dmg_last_error().decode()
+
+
+@pytest.mark.parametrize("nx,ny", [(33, 49), (97, 65), (45, 67), (25, 25)])
+def test_workspace_accepts_odd_dims(dmg, nx, ny):
+    """Odd dims that are not 2^k + 1 coarsen until a dim turns even (33 x 49 -> ... -> 3 x 4)."""
+    nbytes = C.c_size_t()
+    assert dmg.lib().dmg_workspace_bytes(nx, ny, C.byref(dmg.default_options()), C.byref(nbytes)) == 0
+    assert nbytes.value > 8 * 10 * nx * ny
+
+
+def test_workspace_rejects_a_wide_coarsest_grid(dmg):
+    """131 = 2 * 65 + 1 stops at 66 points a side, more than the coarse kernel holds."""
+    lib = dmg.lib()
+    nbytes = C.c_size_t()
+    assert lib.dmg_workspace_bytes(131, 131, C.byref(dmg.default_options()), C.byref(nbytes)) == 2
+    assert "coarsest grid" in lib.dmg_last_error().decode()
 
 
 def test_workspace_sizes_scale_with_grid(dmg):
