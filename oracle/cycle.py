@@ -7,7 +7,11 @@ colour(i,j) = (i mod 2) + 2 (j mod 2); points of one colour are never coupled by
 stencil, so each colour step updates all its points from
     u_p <- (b_p - sum_{q != p} A_pq u_q) / A_pp.
 Pre-smoothing visits colours 0,1,2,3 and post-smoothing 3,2,1,0, which makes the V-cycle a
-symmetric operator.
+symmetric operator.  For anisotropic operators (BoxMG's robustness for them is what the paper
+relies on for its computational solve) the smoother may instead be zebra line Gauss-Seidel:
+each interior line of one parity solves its own equations exactly with the other unknowns
+held, x-lines (rows), y-lines (columns) or both alternately, even lines first, reversed in the
+post-smoothing sweep.
 
 Every routine takes a ``dtype`` so the same definitions run in float64 or float32; the float32
 V-cycle keeps the coarsest solve in float64 (upcast, solve, round back).
@@ -20,6 +24,14 @@ import scipy.sparse as spx
 
 PRE_ORDER = (0, 1, 2, 3)
 POST_ORDER = (3, 2, 1, 0)
+# Line relaxation (zebra line Gauss-Seidel): the pre-smoothing sweeps as (direction, parity),
+# even lines first; the post-smoothing sweep runs them in reverse, which keeps the V-cycle
+# symmetric.  "alt" alternates x-lines (rows) and y-lines (columns).
+LINE_SWEEPS = {
+    "xline": (("x", 0), ("x", 1)),
+    "yline": (("y", 0), ("y", 1)),
+    "alt": (("x", 0), ("x", 1), ("y", 0), ("y", 1)),
+}
 
 
 def colour_masks(nx: int, ny: int):
@@ -50,11 +62,15 @@ class Oracle:
     once by dense Cholesky in float64.  ``pre``/``post`` are the colour orders of one pre/post
     sweep and ``nu_pre``/``nu_post`` the sweep counts of a V(nu_pre, nu_post) cycle."""
 
-    def __init__(self, levels, dtype=np.float64, pre=None, post=None, nu_pre=1, nu_post=1):
+    def __init__(self, levels, dtype=np.float64, pre=None, post=None, nu_pre=1, nu_post=1,
+                 smoother="point"):
         self.dtype = np.dtype(dtype)
         self.pre = tuple(PRE_ORDER if pre is None else pre)
         self.post = tuple(POST_ORDER if post is None else post)
         self.nu_pre, self.nu_post = nu_pre, nu_post
+        if smoother not in LINE_SWEEPS and smoother != "point":
+            raise ValueError(f"unknown smoother {smoother!r}")
+        self.smoother = smoother
         self.levels = [OracleLevel(L, self.dtype) for L in levels]
         last = levels[-1]
         inner = colour_masks(last.nx, last.ny)
@@ -69,6 +85,37 @@ class Oracle:
             m = L.masks[c]
             t = b - L.off @ u
             u[m] = t[m] / L.diag[m]
+        return u
+
+    def line_smooth(self, l: int, u: np.ndarray, b: np.ndarray, direction: str,
+                    parity: int) -> np.ndarray:
+        """Line Gauss-Seidel on the interior lines of one parity: x-lines are rows j, y-lines are
+        columns i, with index % 2 == parity.  Each line solves its own equations exactly for its
+        own unknowns, the other unknowns held at their current values; lines of one parity are
+        not coupled by a 9-point stencil, so their order does not matter."""
+        L = self.levels[l]
+        nx, ny = L.nx, L.ny
+        A = L.A.tocsr()
+        count = ny if direction == "x" else nx
+        for k in range(1, count - 1):
+            if k % 2 != parity:
+                continue
+            if direction == "x":
+                I = k * nx + np.arange(1, nx - 1)
+            else:
+                I = np.arange(1, ny - 1) * nx + k
+            AI = A[I]
+            AII = AI[:, I].toarray()
+            rhs = b[I] - (AI @ u - AII @ u[I])
+            u[I] = np.linalg.solve(AII, rhs)
+        return u
+
+    def _sweep(self, l: int, u: np.ndarray, b: np.ndarray, pre: bool) -> np.ndarray:
+        if self.smoother == "point":
+            return self.smooth(l, u, b, self.pre if pre else self.post)
+        seq = LINE_SWEEPS[self.smoother]
+        for direction, parity in (seq if pre else seq[::-1]):
+            self.line_smooth(l, u, b, direction, parity)
         return u
 
     def residual(self, l: int, u: np.ndarray, b: np.ndarray) -> np.ndarray:
@@ -98,14 +145,14 @@ class Oracle:
             u[:] = self.coarse_solve(b)
             return u
         for _ in range(self.nu_pre):
-            self.smooth(l, u, b, self.pre)
+            self._sweep(l, u, b, True)
         r = self.residual(l, u, b)
         bc = self.restrict(l, r)
         ec = np.zeros_like(bc)
         self.vcycle(ec, bc, l + 1)
         u += self.prolong(l, ec)
         for _ in range(self.nu_post):
-            self.smooth(l, u, b, self.post)
+            self._sweep(l, u, b, False)
         return u
 
 
