@@ -446,6 +446,40 @@ def run_discontinuous_leg(dmg, dev, n: int = 513):
     return {"grid": [n, n], "workload": "unit square, identity map, discontinuous diffusivity", **out}
 
 
+def run_annulus_leg(dmg, dev, sizes=(65, 1025), reps: int = 5):
+    """The quarter annulus (the paper's quarter annulus map, K = 1, b ~ U(-1, 1)): its pull-back
+    is anisotropic (coupling along x up to 10x that along y), so 4-colour point smoothing
+    converges slowly; the same solve with alternating zebra line relaxation.  Cycles and solve
+    wall time (mean of `reps` solves after one that captures the graph)."""
+    import numpy as np
+    import torch
+
+    import problems as pb
+    rows = []
+    for n in sizes:
+        prob = pb.quarter_annulus(n)
+        as_dev = lambda x: torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device=dev)
+        S = dmg.assemble_stencil(as_dev(prob.jac), as_dev(prob.K))
+        b = as_dev(prob.b)
+        row = {"grid": n}
+        for name, sm in (("point", 0), ("alternating_lines", 3)):
+            h = dmg.Hierarchy(S, smoother=sm)
+            h.solve(b, rtol=1e-10, max_iters=300, raise_on_fail=False)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                _, k, rel, _ = h.solve(b, rtol=1e-10, max_iters=300, raise_on_fail=False)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) / reps
+            row[name] = {"cycles": k, "relres": rel, "solve_ms": round(1e3 * wall, 3),
+                         "dof_per_s": round((n - 2) ** 2 / wall, 1)}
+            h.close()
+        log(f"annulus {n}: point {row['point']['cycles']} cycles {row['point']['solve_ms']} ms, "
+            f"lines {row['alternating_lines']['cycles']} cycles {row['alternating_lines']['solve_ms']} ms")
+        rows.append(row)
+    return {"workload": "quarter annulus, K = 1, FP64 V(1,1) to 1e-10", "sizes": rows}
+
+
 CPU_SNIPPET = r"""
 import json, sys, time
 sys.path.insert(0, {root!r})
@@ -499,6 +533,7 @@ def main():
     ap.add_argument("--no-transfer", action="store_true", help="skip the grid <-> mesh transfer leg")
     ap.add_argument("--no-twolevel", action="store_true", help="skip the two-level mesh cycle leg")
     ap.add_argument("--no-disc", action="store_true", help="skip the discontinuous-coefficient leg")
+    ap.add_argument("--no-annulus", action="store_true", help="skip the quarter-annulus smoother leg")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -595,6 +630,9 @@ def main():
     if not args.no_twolevel:
         log("two-level leg: star meshes at grids 129, 257, 513")
         res["twolevel"] = run_twolevel_leg(dmg, dev)
+    if not args.no_annulus:
+        log("quarter-annulus leg: point vs line smoothing")
+        res["annulus"] = run_annulus_leg(dmg, dev)
     if not args.no_disc:
         log("discontinuous-coefficient leg: 513x513 unit square")
         res["discontinuous"] = run_discontinuous_leg(dmg, dev)

@@ -78,7 +78,15 @@ typedef struct dmg_options {
   int32_t strip_kernel;  /* implementation of the large-level sweeps before autotuning:
                             0 = LDS strips, 1 = one-wavefront strips (default 1).
                             Numerically neutral.                                           */
-  int32_t reserved[6];
+  int32_t smoother;      /* 0 = 4-colour point Gauss-Seidel (default, fused kernels);
+                            zebra line Gauss-Seidel for anisotropic operators: 1 = x-lines
+                            (rows), 2 = y-lines (columns), 3 = alternating x then y.  Each
+                            interior line of one parity, even lines first, is solved exactly
+                            with the other lines held; the post sweep runs in reverse (the
+                            V-cycle stays symmetric).  Line smoothing runs unfused level by
+                            level, float64 only (DMG_FP32_IR and the batch solve return
+                            DMG_ERR_UNSUPPORTED); nu_pre / nu_post count whole line sweeps. */
+  int32_t reserved[5];
 } dmg_options;
 
 typedef struct dmg_hier dmg_hier;

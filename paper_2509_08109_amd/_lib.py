@@ -27,7 +27,8 @@ class Options(C.Structure):
                 ("pre_order", C.c_int32 * 4), ("post_order", C.c_int32 * 4),
                 ("coarsest_n", C.c_int32), ("precision", C.c_int32),
                 ("inner_cycles", C.c_int32), ("use_graph", C.c_int32),
-                ("tile_rows", C.c_int32), ("strip_kernel", C.c_int32), ("reserved", C.c_int32 * 6)]
+                ("tile_rows", C.c_int32), ("strip_kernel", C.c_int32), ("smoother", C.c_int32),
+                ("reserved", C.c_int32 * 5)]
 
 
 _p = C.c_void_p

@@ -28,7 +28,7 @@ FLAGS = [
     "-I" + os.path.join(ROOT, "include"),
 ]
 SOURCES = ["setup_kernels.hip", "cycle_kernels.hip", "fused_kernels.hip", "transfer.hip", "mesh_setup.hip",
-           "twolevel.hip", "batch.hip", "api.hip"]
+           "twolevel.hip", "line_smoother.hip", "batch.hip", "api.hip"]
 
 
 def _compile(src: str) -> str:

@@ -52,6 +52,10 @@ dmg_status check_options(const dmg_options* o) {
     return fail(DMG_ERR_INVALID_ARG, "inner_cycles must be in [1,16]");
   if (o->strip_kernel != 0 && o->strip_kernel != 1)
     return fail(DMG_ERR_INVALID_ARG, "strip_kernel must be 0 or 1");
+  if (o->smoother < 0 || o->smoother > 3)
+    return fail(DMG_ERR_INVALID_ARG, "smoother must be 0 (point), 1 (x-lines), 2 (y-lines) or 3");
+  if (o->smoother != 0 && o->precision != DMG_FP64)
+    return fail(DMG_ERR_UNSUPPORTED, "line relaxation runs in float64 only");
   return DMG_OK;
 }
 
@@ -150,6 +154,7 @@ void carve(dmg_hier& h, Arena& a, const std::vector<std::pair<int, int>>& dims,
       L.u = a.take<double>(n);
       L.b = a.take<double>(n);
     }
+    if (o.smoother != 0 && int(l) < h.tail) L.lf = a.take<double>(4 * n);
     if (fp32) {
       if (int(l) >= h.tail) L.S32 = a.take<float>(5 * n);
       L.u32 = a.take<float>(n);
@@ -231,9 +236,36 @@ dmg_status tail_launch(dmg_hier* h, T* u_top, const T* b_top, hipStream_t s, boo
   }
   sp.nu_pre = h->opts.nu_pre;
   sp.nu_post = h->opts.nu_post;
+  sp.smoother = h->opts.smoother;
   sp.stop = stop;
   sp.threads = h->tail_threads;
   return launch_tail<T>(sp, s);
+}
+
+// One float64 V-cycle with zebra line relaxation: unfused kernels on the levels above the coarse
+// tail (coarse levels start from u = 0; u0_zero says the same of level 0), the tail levels with
+// their line sweeps and the coarsest solve in the one-workgroup coarse kernel.
+dmg_status vcycle_line(dmg_hier* h, double* u0, const double* b0, bool u0_zero, const int* stop,
+                       hipStream_t s) {
+  const dmg_options& o = h->opts;
+  const int T = h->tail;
+  auto U = [&](int l) { return l == 0 ? u0 : h->L[l].u; };
+  auto B = [&](int l) { return l == 0 ? b0 : static_cast<const double*>(h->L[l].b); };
+  for (int l = 0; l < T; ++l) {
+    const Level& L = h->L[l];
+    if (l > 0 || u0_zero) DMG_CHECK(launch_fill<double>(U(l), 0.0, L.n(), s));
+    for (int k = 0; k < o.nu_pre; ++k)
+      DMG_CHECK(line_sweep(L, U(l), B(l), o.smoother, true, stop, s));
+    DMG_CHECK(line_resid_restrict(L, h->L[l + 1], U(l), B(l), stop, s));
+  }
+  DMG_CHECK(tail_launch<double>(h, U(T), B(T), s, T == 0 && u0_zero, stop));
+  for (int l = T - 1; l >= 0; --l) {
+    const Level& L = h->L[l];
+    DMG_CHECK(line_prolong(L, U(l + 1), U(l), stop, s));
+    for (int k = 0; k < o.nu_post; ++k)
+      DMG_CHECK(line_sweep(L, U(l), B(l), o.smoother, false, stop, s));
+  }
+  return DMG_OK;
 }
 
 // One V-cycle in precision T on level-0 arrays (u0, b0); coarse levels use hierarchy arrays.
@@ -249,6 +281,10 @@ dmg_status vcycle_impl(dmg_hier* h, T* u0, const T* b0, hipStream_t s, double* p
                        bool u0_zero = false, const int* stop = nullptr, double* x64 = nullptr) {
   using Pr = Prec<T>;
   const dmg_options& o = h->opts;
+  if (o.smoother != 0) {
+    if constexpr (std::is_same<T, double>::value) return vcycle_line(h, u0, b0, u0_zero, stop, s);
+    return fail(DMG_ERR_UNSUPPORTED, "line relaxation runs in float64 only");
+  }
   const OrderParams pre = order_params(o.pre_order), post = order_params(o.post_order);
   T* cur[kMaxLevels];
   auto other = [&](int l, const T* x) -> T* {
@@ -331,7 +367,7 @@ int* stop_flag(dmg_hier* h) { return h->flag + 4; }
 dmg_status step_fp64(dmg_hier* h, double* u, const double* b, hipStream_t s) {
   const int* stop = stop_flag(h);
   int count = kReduceBlocks;
-  if (h->tail == 0) {
+  if (h->tail == 0 || h->opts.smoother != 0) {  // no fused post sweep carries the norm
     DMG_CHECK(vcycle_impl<double>(h, u, b, s, nullptr, false, stop));
     const Level& L = h->L[0];
     DMG_CHECK(launch_resid_sq_partials(L.S, u, b, L.nx, L.ny, h->partials, s, stop));
@@ -544,6 +580,8 @@ dmg_status setup_impl(dmg_hier* h, const double* S, hipStream_t s) {
       }
     }
   }
+  if (h->opts.smoother != 0)
+    for (int l = 0; l < h->tail; ++l) DMG_CHECK(line_factors(h->L[l], s));
   int flag = 0;
   DMG_HIP(hipMemcpyAsync(&flag, h->flag, sizeof(int), hipMemcpyDeviceToHost, s));
   DMG_HIP(hipStreamSynchronize(s));

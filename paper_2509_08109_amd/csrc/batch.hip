@@ -436,6 +436,7 @@ dmg_status dmg_batch_workspace_bytes(int32_t count, const int32_t* nx, const int
   dmg_options o;
   dmg_default_options(&o);
   if (opts) o = *opts;
+  if (o.smoother != 0) return fail(DMG_ERR_UNSUPPORTED, "the batch solve uses point smoothing");
   size_t total = 0;
   for (int k = 0; k < count; ++k) {
     size_t b = 0;
@@ -456,6 +457,7 @@ dmg_status dmg_batch_setup(int32_t count, const int32_t* nx, const int32_t* ny,
   dmg_options o;
   dmg_default_options(&o);
   if (opts) o = *opts;
+  if (o.smoother != 0) return fail(DMG_ERR_UNSUPPORTED, "the batch solve uses point smoothing");
   if (o.precision != DMG_FP64)
     return fail(DMG_ERR_UNSUPPORTED, "batched solves run in float64 (precision DMG_FP64)");
   size_t need = 0;

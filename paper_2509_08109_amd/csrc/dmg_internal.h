@@ -70,6 +70,8 @@ struct Level {
   double* t = nullptr;    // second iterate buffer for the out-of-place strip sweeps
   double* b = nullptr;    // right-hand side on coarse levels
   double* r = nullptr;    // residual scratch
+  double* lf = nullptr;   // line relaxation (levels above the tail): [4][ny][nx] Thomas factors
+                          // of the x-lines (super-diagonal, reciprocal pivot), then the y-lines
   float* S32 = nullptr;   // fp32 copies for DMG_FP32_IR (S32: tail levels only)
   float* P32 = nullptr;
   float* u32 = nullptr;
@@ -209,6 +211,7 @@ struct TailArgs {
   const double* chol;
   int pre[4], post[4];
   int nu_pre, nu_post;
+  int smoother;       // 0: 4-colour point Gauss-Seidel; 1-3: zebra lines (x, y, alternating)
   const int* stop;
 };
 
@@ -239,6 +242,7 @@ struct TailSpec {
   const double* chol = nullptr;
   int pre[4], post[4];
   int nu_pre = 1, nu_post = 1;
+  int smoother = 0;    // as dmg_options::smoother
   const int* stop = nullptr;
   int threads = 1024;  // workgroup size: a multiple of 64 in [64, 1024]
 };
@@ -323,6 +327,20 @@ dmg_status launch_check_step(const double* partials, int count, double* out, con
 // x is read at the boundary ring as the stencil's couplings there are zero)
 dmg_status launch_stencil_apply(const double* S, const double* x, double* y, int nx, int ny,
                                 hipStream_t s);
+
+// Zebra line relaxation on the levels above the coarse tail (line_smoother.hip), float64.
+// Every kernel is a no-op once *stop (nullable) is set.
+// The line sweeps of smoother 1-3 on level L (pre order, or reversed for the post sweep).
+dmg_status line_sweep(const Level& L, double* u, const double* b, int smoother, bool pre,
+                      const int* stop, hipStream_t s);
+// The Thomas factors of every x-line and y-line of level L into L.lf (at setup).
+dmg_status line_factors(const Level& L, hipStream_t s);
+// L.r = b - A u, then Lc.b = P^T L.r.
+dmg_status line_resid_restrict(const Level& L, const Level& Lc, const double* u, const double* b,
+                               const int* stop, hipStream_t s);
+// u += P e.
+dmg_status line_prolong(const Level& L, const double* e, double* u, const int* stop,
+                        hipStream_t s);
 
 // One float64 V-cycle of hierarchy h on level-0 arrays (u, b); u_zero: start from u = 0
 // without reading u.  Every kernel is a no-op once *stop (nullable) is set.

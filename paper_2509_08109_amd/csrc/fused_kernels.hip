@@ -468,6 +468,76 @@ __device__ void tail_colour(const T* S, T* u, const T* b, int nx, int ny, int c)
   __syncthreads();
 }
 
+// One zebra line sweep in LDS: dir 0 x-lines (rows), 1 y-lines (columns), interior lines of
+// one parity, one thread per line by the Thomas algorithm (modified super-diagonal in cp).
+template <class T>
+__device__ void tail_line(const T* S, T* u, const T* b, T* cp, int nx, int ny, int dir,
+                          int parity) {
+  const int N = nx * ny;
+  const T *C = S, *W = S + N, *So = S + 2 * N, *SW = S + 3 * N, *SE = S + 4 * N;
+  const int first = parity == 0 ? 2 : 1;
+  const int len = dir == 0 ? nx : ny;       // points along a line, boundary included
+  const int step = dir == 0 ? 1 : nx;       // index step along a line
+  const int count = dir == 0 ? ny : nx;
+  for (int t = threadIdx.x; first + 2 * t <= count - 2; t += blockDim.x) {
+    const int line = first + 2 * t;
+    const int v0 = dir == 0 ? line * nx : line;
+    T pc = T(0), pd = T(0);
+    for (int k = 1; k <= len - 2; ++k) {
+      const int v = v0 + k * step;
+      T off, a, c;
+      if (dir == 0) {
+        off = ((((So[v] * u[v - nx] + So[v + nx] * u[v + nx]) + SW[v] * u[v - nx - 1]) +
+                SE[v] * u[v - nx + 1]) +
+               SE[v + nx - 1] * u[v + nx - 1]) +
+              SW[v + nx + 1] * u[v + nx + 1];
+        a = W[v];
+        c = W[v + 1];
+      } else {
+        off = ((((W[v] * u[v - 1] + W[v + 1] * u[v + 1]) + SW[v] * u[v - nx - 1]) +
+                SE[v] * u[v - nx + 1]) +
+               SE[v + nx - 1] * u[v + nx - 1]) +
+              SW[v + nx + 1] * u[v + nx + 1];
+        a = So[v];
+        c = So[v + nx];
+      }
+      const T im = T(1) / (C[v] - a * pc);  // one division per step
+      pc = c * im;
+      pd = ((b[v] - off) - a * pd) * im;
+      cp[v] = pc;
+      u[v] = pd;
+    }
+    for (int k = len - 3; k >= 1; --k) {
+      const int v = v0 + k * step;
+      u[v] = u[v] - cp[v] * u[v + step];
+    }
+  }
+  __syncthreads();
+}
+
+// One smoothing sweep of the tail (pre: the pre order, else the post order / reversed lines).
+template <class T>
+__device__ void tail_smooth(const TailArgs<T>& a, const T* S, T* u, const T* b, T* cp, int nx,
+                            int ny, bool pre) {
+  if (a.smoother == 0) {
+    for (int c = 0; c < 4; ++c) tail_colour(S, u, b, nx, ny, pre ? a.pre[c] : a.post[c]);
+    return;
+  }
+  int dir[4], par[4], n = 0;
+  if (a.smoother == 1 || a.smoother == 3) {
+    dir[n] = 0, par[n++] = 0;
+    dir[n] = 0, par[n++] = 1;
+  }
+  if (a.smoother == 2 || a.smoother == 3) {
+    dir[n] = 1, par[n++] = 0;
+    dir[n] = 1, par[n++] = 1;
+  }
+  for (int k = 0; k < n; ++k) {
+    const int q = pre ? k : n - 1 - k;
+    tail_line(S, u, b, cp, nx, ny, dir[q], par[q]);
+  }
+}
+
 template <class T>
 __device__ __forceinline__ void tail_body(const TailArgs<T>& a) {
   if (a.stop && *a.stop) return;
@@ -503,8 +573,7 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& a) {
     const T* S = sm + a.oS[l];
     T* u = sm + a.ou[l];
     const T* b = sm + a.ob[l];
-    for (int s = 0; s < a.nu_pre; ++s)
-      for (int c = 0; c < 4; ++c) tail_colour(S, u, b, nx, ny, a.pre[c]);
+    for (int s = 0; s < a.nu_pre; ++s) tail_smooth(a, S, u, b, r, nx, ny, true);
     for (int v = tid; v < N; v += nt) {
       const int i = v % nx, j = v / nx;
       T rv = T(0);
@@ -587,8 +656,7 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& a) {
       u[v] = u[v] + corr;
     }
     __syncthreads();
-    for (int s = 0; s < a.nu_post; ++s)
-      for (int c = 0; c < 4; ++c) tail_colour(S, u, b, nx, ny, a.post[c]);
+    for (int s = 0; s < a.nu_post; ++s) tail_smooth(a, S, u, b, sm + a.o_r, nx, ny, false);
   }
   // write back the top level's iterate
   {
@@ -1178,6 +1246,7 @@ dmg_status make_tail_args(const TailSpec<T>& spec, TailArgs<T>* out, size_t* lds
   }
   a.nu_pre = spec.nu_pre;
   a.nu_post = spec.nu_post;
+  a.smoother = spec.smoother;
   a.stop = spec.stop;
   *lds_bytes = lay.bytes;
   return DMG_OK;

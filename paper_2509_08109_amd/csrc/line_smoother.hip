@@ -1,0 +1,280 @@
+// V-cycles with zebra line relaxation, the smoother for anisotropic operators (float64).
+//
+// A line sweep solves, for every interior line of one parity, the line's own equations exactly
+// with the unknowns of the other lines held: the tridiagonal system of the couplings along the
+// line, right-hand side b minus the couplings to the two neighbouring lines.  Lines of one parity
+// are not coupled by a 9-point stencil, so they are solved at once, one thread per line, by the
+// Thomas algorithm.  Its factors (modified super-diagonal, reciprocal pivots) depend on the
+// stencil only and are computed at setup, so a sweep is a forward pass d = (rhs - a d') / m into
+// scratch, which only reads u, and a back substitution into the line of u.  x-lines are grid rows
+// (a thread walks a row), y-lines grid columns (consecutive threads take consecutive columns, so
+// their loads coalesce).
+//
+// Levels above the coarse tail run these unfused kernels: sweeps, residual, restriction P^T r,
+// interpolation u += P e, sweeps in reverse order; the tail levels run in the one-workgroup
+// coarse kernel with its own line sweeps.  Every kernel is a no-op once *stop (nullable) is set.
+#include <algorithm>
+
+#include "dmg_internal.h"
+
+namespace dmg {
+namespace {
+
+__device__ __forceinline__ bool halted(const int* stop) { return stop && *stop; }
+
+// Thomas factors of the x-lines: for every interior row, walking i, the pivot m = C - W cp_prev
+// (W the sub-diagonal, the previous point's E the super-diagonal) and cp = E / m; stored as cp and
+// 1 / m.  They depend on the stencil only, so the sweeps need no divisions.
+__global__ __launch_bounds__(64) void k_line_factor_x(const double* __restrict__ S,
+                                                      double* __restrict__ lf, int nx, int ny) {
+  const size_t N = size_t(nx) * ny;
+  const int j = 1 + int(blockIdx.x * blockDim.x + threadIdx.x);
+  if (j > ny - 2) return;
+  const double *C = S, *W = S + N;
+  double pc = 0.0;
+  for (int i = 1; i <= nx - 2; ++i) {
+    const size_t v = size_t(j) * nx + i;
+    const double im = 1.0 / (C[v] - W[v] * pc);
+    pc = W[v + 1] * im;
+    lf[v] = pc;
+    lf[N + v] = im;
+  }
+}
+
+// The same along the y-lines (sub-diagonal S, super-diagonal N(i,j) = S(i,j+1)).
+__global__ __launch_bounds__(64) void k_line_factor_y(const double* __restrict__ S,
+                                                      double* __restrict__ lf, int nx, int ny) {
+  const size_t N = size_t(nx) * ny;
+  const int i = 1 + int(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i > nx - 2) return;
+  const double *C = S, *So = S + 2 * N;
+  double pc = 0.0;
+  for (int j = 1; j <= ny - 2; ++j) {
+    const size_t v = size_t(j) * nx + i;
+    const double im = 1.0 / (C[v] - So[v] * pc);
+    pc = So[v + nx] * im;
+    lf[2 * N + v] = pc;
+    lf[3 * N + v] = im;
+  }
+}
+
+// One x-line sweep: interior rows j with j % 2 == parity.  Stencil planes (planar, N = nx ny):
+// C, W, S, SW, SE; E(i,j) = W(i+1,j), N(i,j) = S(i,j+1), NE(i,j) = SW(i+1,j+1),
+// NW(i,j) = SE(i-1,j+1).  Forward: d = (rhs - W d_prev) / m with the stored 1 / m, into the
+// scratch dp (u is only read there: the neighbouring rows, so the loads run ahead of the
+// recurrence); back substitution x = d - cp x_next into the row of u.
+__global__ __launch_bounds__(64) void k_line_x(const double* __restrict__ S,
+                                               const double* __restrict__ uin,
+                                               const double* __restrict__ b,
+                                               const double* __restrict__ lf,
+                                               double* __restrict__ dp, int nx, int ny,
+                                               int parity, const int* __restrict__ stop,
+                                               double* u) {
+  if (halted(stop)) return;
+  const size_t N = size_t(nx) * ny;
+  const int first = parity == 0 ? 2 : 1;
+  const int j = first + 2 * int(blockIdx.x * blockDim.x + threadIdx.x);
+  if (j > ny - 2) return;
+  const double *W = S + N, *So = S + 2 * N, *SW = S + 3 * N, *SE = S + 4 * N;
+  const double *cp = lf, *im = lf + N;
+  double pd = 0.0;
+#pragma unroll 8
+  for (int i = 1; i <= nx - 2; ++i) {
+    const size_t v = size_t(j) * nx + i;
+    const double off =
+        ((((So[v] * uin[v - nx] + So[v + nx] * uin[v + nx]) + SW[v] * uin[v - nx - 1]) +
+          SE[v] * uin[v - nx + 1]) +
+         SE[v + nx - 1] * uin[v + nx - 1]) +
+        SW[v + nx + 1] * uin[v + nx + 1];
+    pd = ((b[v] - off) - W[v] * pd) * im[v];
+    dp[v] = pd;
+  }
+  double x = pd;
+  u[size_t(j) * nx + nx - 2] = x;
+#pragma unroll 8
+  for (int i = nx - 3; i >= 1; --i) {
+    const size_t v = size_t(j) * nx + i;
+    x = dp[v] - cp[v] * x;
+    u[v] = x;
+  }
+}
+
+// One y-line sweep: interior columns i with i % 2 == parity (as the x-line sweep, along j).
+__global__ __launch_bounds__(64) void k_line_y(const double* __restrict__ S,
+                                               const double* __restrict__ uin,
+                                               const double* __restrict__ b,
+                                               const double* __restrict__ lf,
+                                               double* __restrict__ dp, int nx, int ny,
+                                               int parity, const int* __restrict__ stop,
+                                               double* u) {
+  if (halted(stop)) return;
+  const size_t N = size_t(nx) * ny;
+  const int first = parity == 0 ? 2 : 1;
+  const int i = first + 2 * int(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i > nx - 2) return;
+  const double *W = S + N, *So = S + 2 * N, *SW = S + 3 * N, *SE = S + 4 * N;
+  const double *cp = lf + 2 * N, *im = lf + 3 * N;
+  double pd = 0.0;
+#pragma unroll 8
+  for (int j = 1; j <= ny - 2; ++j) {
+    const size_t v = size_t(j) * nx + i;
+    const double off =
+        ((((W[v] * uin[v - 1] + W[v + 1] * uin[v + 1]) + SW[v] * uin[v - nx - 1]) +
+          SE[v] * uin[v - nx + 1]) +
+         SE[v + nx - 1] * uin[v + nx - 1]) +
+        SW[v + nx + 1] * uin[v + nx + 1];
+    pd = ((b[v] - off) - So[v] * pd) * im[v];
+    dp[v] = pd;
+  }
+  double x = pd;
+  u[size_t(ny - 2) * nx + i] = x;
+#pragma unroll 8
+  for (int j = ny - 3; j >= 1; --j) {
+    const size_t v = size_t(j) * nx + i;
+    x = dp[v] - cp[v] * x;
+    u[v] = x;
+  }
+}
+
+// r = b - A u on interior points, 0 on the boundary ring.
+__global__ __launch_bounds__(256) void k_line_resid(const double* __restrict__ S,
+                                                    const double* __restrict__ u,
+                                                    const double* __restrict__ b,
+                                                    double* __restrict__ r, int nx, int ny,
+                                                    const int* __restrict__ stop) {
+  if (halted(stop)) return;
+  const size_t N = size_t(nx) * ny;
+  for (size_t v = blockIdx.x * 256u + threadIdx.x; v < N; v += size_t(gridDim.x) * 256u) {
+    const int j = int(v / nx), i = int(v % nx);
+    if (i > 0 && i < nx - 1 && j > 0 && j < ny - 1) {
+      const double off = ((((((S[3 * N + v] * u[v - nx - 1] + S[2 * N + v] * u[v - nx]) +
+                              S[4 * N + v] * u[v - nx + 1]) +
+                             S[N + v] * u[v - 1]) +
+                            S[N + v + 1] * u[v + 1]) +
+                           S[4 * N + v + nx - 1] * u[v + nx - 1]) +
+                          S[2 * N + v + nx] * u[v + nx]) +
+                         S[3 * N + v + nx + 1] * u[v + nx + 1];
+      r[v] = b[v] - (off + S[v] * u[v]);
+    } else {
+      r[v] = 0.0;
+    }
+  }
+}
+
+// b_H = P^T r on interior coarse points (boundary 0).  P per coarse cell c = J ncx + I: planes
+// 0-1 the x-line weights of fine (2I+1, 2J) on coarse (I, J), (I+1, J); 2-3 the y-line weights
+// of (2I, 2J+1) on (I, J), (I, J+1); 4-7 the centre weights of (2I+1, 2J+1) on (I, J), (I+1, J),
+// (I, J+1), (I+1, J+1).
+__global__ __launch_bounds__(256) void k_line_restrict(const double* __restrict__ P,
+                                                       const double* __restrict__ r,
+                                                       double* __restrict__ bH, int nx, int ny,
+                                                       const int* __restrict__ stop) {
+  if (halted(stop)) return;
+  const int ncx = (nx + 1) / 2, ncy = (ny + 1) / 2;
+  const size_t NC = size_t(ncx) * ncy;
+  for (size_t k = blockIdx.x * 256u + threadIdx.x; k < NC; k += size_t(gridDim.x) * 256u) {
+    const int J = int(k / ncx), I = int(k % ncx);
+    if (I == 0 || I == ncx - 1 || J == 0 || J == ncy - 1) {
+      bH[k] = 0.0;
+      continue;
+    }
+    const size_t f = size_t(2 * J) * nx + 2 * I;  // fine (2I, 2J)
+    const size_t c = k, cw = k - 1, cs = k - ncx, csw = k - ncx - 1;
+    double acc = r[f];
+    acc += P[c] * r[f + 1] + P[NC + cw] * r[f - 1];
+    acc += P[2 * NC + c] * r[f + nx] + P[3 * NC + cs] * r[f - nx];
+    acc += P[4 * NC + c] * r[f + nx + 1] + P[5 * NC + cw] * r[f + nx - 1];
+    acc += P[6 * NC + cs] * r[f - nx + 1] + P[7 * NC + csw] * r[f - nx - 1];
+    bH[k] = acc;
+  }
+}
+
+// u += P e on interior fine points.
+__global__ __launch_bounds__(256) void k_line_prolong(const double* __restrict__ P,
+                                                      const double* __restrict__ e,
+                                                      double* __restrict__ u, int nx, int ny,
+                                                      const int* __restrict__ stop) {
+  if (halted(stop)) return;
+  const int ncx = (nx + 1) / 2, ncy = (ny + 1) / 2;
+  const size_t NC = size_t(ncx) * ncy, N = size_t(nx) * ny;
+  for (size_t v = blockIdx.x * 256u + threadIdx.x; v < N; v += size_t(gridDim.x) * 256u) {
+    const int j = int(v / nx), i = int(v % nx);
+    if (i == 0 || i == nx - 1 || j == 0 || j == ny - 1) continue;
+    const size_t c = size_t(j >> 1) * ncx + (i >> 1);
+    double x;
+    if (!(i & 1) && !(j & 1))
+      x = e[c];
+    else if ((i & 1) && !(j & 1))
+      x = P[c] * e[c] + P[NC + c] * e[c + 1];
+    else if (!(i & 1) && (j & 1))
+      x = P[2 * NC + c] * e[c] + P[3 * NC + c] * e[c + ncx];
+    else
+      x = ((P[4 * NC + c] * e[c] + P[5 * NC + c] * e[c + 1]) + P[6 * NC + c] * e[c + ncx]) +
+          P[7 * NC + c] * e[c + ncx + 1];
+    u[v] += x;
+  }
+}
+
+unsigned grid_blocks(size_t n) {
+  return unsigned(std::max<size_t>(1, std::min<size_t>((n + 255) / 256, 16384)));
+}
+
+// the pre-smoothing sweeps of smoother s as (direction, parity): 0 = x-lines, 1 = y-lines
+int line_sweeps(int smoother, int dir[4], int par[4]) {
+  int n = 0;
+  if (smoother == 1 || smoother == 3) {
+    dir[n] = 0, par[n++] = 0;
+    dir[n] = 0, par[n++] = 1;
+  }
+  if (smoother == 2 || smoother == 3) {
+    dir[n] = 1, par[n++] = 0;
+    dir[n] = 1, par[n++] = 1;
+  }
+  return n;
+}
+
+}  // namespace
+
+dmg_status line_sweep(const Level& L, double* u, const double* b, int smoother, bool pre,
+                      const int* stop, hipStream_t s) {
+  int dir[4], par[4];
+  const int n = line_sweeps(smoother, dir, par);
+  for (int k = 0; k < n; ++k) {
+    const int q = pre ? k : n - 1 - k;
+    // dp scratch: r (free during the sweeps)
+    if (dir[q] == 0) {
+      const int lines = (L.ny - 2 + 1) / 2;
+      k_line_x<<<(lines + 63) / 64, 64, 0, s>>>(L.S, u, b, L.lf, L.r, L.nx, L.ny, par[q], stop,
+                                                u);
+    } else {
+      const int lines = (L.nx - 2 + 1) / 2;
+      k_line_y<<<(lines + 63) / 64, 64, 0, s>>>(L.S, u, b, L.lf, L.r, L.nx, L.ny, par[q], stop,
+                                                u);
+    }
+    DMG_CHECK(launch_check("line sweep"));
+  }
+  return DMG_OK;
+}
+
+dmg_status line_factors(const Level& L, hipStream_t s) {
+  k_line_factor_x<<<(L.ny - 2 + 63) / 64, 64, 0, s>>>(L.S, L.lf, L.nx, L.ny);
+  DMG_CHECK(launch_check("line factors x"));
+  k_line_factor_y<<<(L.nx - 2 + 63) / 64, 64, 0, s>>>(L.S, L.lf, L.nx, L.ny);
+  return launch_check("line factors y");
+}
+
+dmg_status line_resid_restrict(const Level& L, const Level& Lc, const double* u, const double* b,
+                               const int* stop, hipStream_t s) {
+  k_line_resid<<<grid_blocks(L.n()), 256, 0, s>>>(L.S, u, b, L.r, L.nx, L.ny, stop);
+  DMG_CHECK(launch_check("line residual"));
+  k_line_restrict<<<grid_blocks(Lc.n()), 256, 0, s>>>(L.P, L.r, Lc.b, L.nx, L.ny, stop);
+  return launch_check("line restriction");
+}
+
+dmg_status line_prolong(const Level& L, const double* e, double* u, const int* stop,
+                        hipStream_t s) {
+  k_line_prolong<<<grid_blocks(L.n()), 256, 0, s>>>(L.P, e, u, L.nx, L.ny, stop);
+  return launch_check("line interpolation");
+}
+
+}  // namespace dmg
