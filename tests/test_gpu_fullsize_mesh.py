@@ -1,0 +1,117 @@
+"""Parity at benchmark sizes for the mesh side and the line smoother, on sampled outputs and
+through properties that hold at any size.
+
+* The device-assembled coupled mass at a 1025^2 grid (3.76M-vertex mesh): a row of C depends only
+  on the triangles incident to its vertex, so the oracle computes sampled rows exactly from those
+  triangles alone and they are compared entry by entry (same columns; values to the rounding
+  bound eps / h^2 of the barycentric evaluations).
+* The two-level solve at a 513^2 grid (0.94M vertices, the bench's largest two-level size):
+  the residual of the returned solution, recomputed on the host with A_p assembled here by
+  vectorised NumPy (independently of the library), meets the tolerance.
+* The alternating-line solve of the 1025^2 quarter annulus: its residual, recomputed with the
+  oracle's assembled matrix, meets the tolerance.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as spx
+import torch
+
+import problems as pb
+from oracle import fem, transfer
+from problems.batch_device import star_dmg_device
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2509_08109_amd as m
+    m.lib()
+    return m
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def _incident(tris, v):
+    return tris[np.any(tris == v, axis=1)]
+
+
+def test_coupled_mass_sampled_rows_at_1025(lib):
+    n = 1025
+    _, _, mesh, _, _ = star_dmg_device(n, 1, "cuda")
+    T = lib.Transfer(mesh.xy_c, mesh.xy_p, mesh.tris, mesh.dof, n, n, nq=0)
+    rp, ci, v = T.copy_C()
+    T.close()
+    rng = np.random.default_rng(7)
+    free = np.flatnonzero(mesh.dof)
+    for vtx in rng.choice(free, size=24, replace=False):
+        sub = _incident(mesh.tris, vtx)
+        verts = np.unique(sub)
+        local = np.searchsorted(verts, sub)
+        Co = transfer.coupled_mass_exact(mesh.xy_c[verts], mesh.xy_p[verts], local,
+                                         mesh.dof[verts], n, n).tocsr()
+        row = Co.getrow(int(np.searchsorted(verts, vtx)))
+        row.sort_indices()
+        cols, vals = ci[rp[vtx]:rp[vtx + 1]], v[rp[vtx]:rp[vtx + 1]]
+        assert np.array_equal(cols, row.indices)
+        # both sides evaluate barycentric coordinates from O(1) vertex coordinates whose
+        # combinations cancel down to O(h^2) areas (h = 2 / (n - 1) the cell width), so their
+        # roundings differ by up to about eps / h^2 relative: ~6e-11 at 1025^2
+        tol = 4 * np.finfo(float).eps / (2.0 / (n - 1)) ** 2
+        assert np.max(np.abs(vals - row.data)) <= tol * np.max(np.abs(row.data))
+
+
+def _p1_stiffness_vectorised(xy, tris, dof, K_t):
+    """A_p by vectorised element matrices (the same definition as the library and the oracle,
+    written here once more), Dirichlet rows and columns replaced by the identity."""
+    p = xy[tris]                                             # [nt][3][2]
+    det = ((p[:, 1, 0] - p[:, 0, 0]) * (p[:, 2, 1] - p[:, 0, 1])
+           - (p[:, 2, 0] - p[:, 0, 0]) * (p[:, 1, 1] - p[:, 0, 1]))
+    g = np.empty((tris.shape[0], 3, 2))
+    for a in range(3):
+        b, c = (a + 1) % 3, (a + 2) % 3
+        g[:, a, 0] = (p[:, b, 1] - p[:, c, 1]) / det
+        g[:, a, 1] = (p[:, c, 0] - p[:, b, 0]) / det
+    G = 0.5 * np.abs(det)[:, None, None] * np.einsum("tad,tbd->tab", g, g) * K_t[:, None, None]
+    rows = np.repeat(tris, 3, axis=1).ravel()
+    cols = np.tile(tris, (1, 3)).ravel()
+    A = spx.coo_matrix((G.ravel(), (rows, cols)), shape=(xy.shape[0],) * 2).tocsr()
+    d = spx.diags(dof.astype(np.float64))
+    return (d @ A @ d + spx.diags((~dof).astype(np.float64))).tocsr()
+
+
+def test_twolevel_residual_at_513(lib):
+    n = 513
+    jac, K, mesh, K_t, f = star_dmg_device(n, 1, "cuda")
+    H = lib.Hierarchy(lib.assemble_stencil(jac, K))
+    tl = lib.TwoLevel(H, mesh.xy_c, mesh.xy_p, mesh.tris, mesh.dof, K_t=K_t)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):                     # the bench's captured-graph path
+        u, k, rel, hist = tl.solve(dev(f), rtol=1e-10)
+    torch.cuda.synchronize()
+    A = _p1_stiffness_vectorised(mesh.xy_p, mesh.tris, mesh.dof, K_t)
+    r = f - A @ u.cpu().numpy()
+    rel_host = np.linalg.norm(r) / np.linalg.norm(f)
+    assert k == 13 and rel <= 1e-10
+    assert rel_host <= 1e-10 * (1 + 1e-6) and abs(rel_host - rel) <= 1e-6 * rel
+    tl.close()
+    H.close()
+
+
+def test_line_smoothed_annulus_residual_at_1025(lib):
+    n = 1025
+    prob = pb.quarter_annulus(n)
+    S = fem.assemble_stencil(prob.jac, prob.K, n, n)
+    h = lib.Hierarchy(dev(S), smoother=3)
+    u, k, rel, hist = h.solve(dev(prob.b), rtol=1e-10)
+    A = fem.stencil_to_matrix(S)
+    r = prob.b.ravel() - A @ u.cpu().numpy().ravel()
+    m = np.zeros((n, n), bool)
+    m[1:-1, 1:-1] = True
+    rel_host = np.linalg.norm(r[m.ravel()]) / np.linalg.norm(prob.b[m])
+    assert k <= 10 and rel <= 1e-10
+    assert rel_host <= 1e-10 * (1 + 1e-6) and abs(rel_host - rel) <= 1e-6 * rel
+    h.close()
