@@ -158,18 +158,20 @@ dmg_status dmg_sweep(dmg_hier* h, int32_t level, int32_t kind, double* u, const 
                      hipStream_t stream);
 /* Autotuner.  flags bit 0: for every strip-kernel level pick the kernel and launch shape
  * (LDS strips of {64,128} columns, also 256 for float32, or one-wavefront strips that exchange
- * neighbour columns between lanes; segment height in {2,...,128} rows) with the lowest measured time of its
- * pre + post kernels (hipEvents, `reps` launches each, float64 and, for DMG_FP32_IR, float32
- * kernels separately) -- numerically neutral.  flags bit 1: pick the colour order with the
+ * neighbour columns between lanes; segment height in {2,...,128} rows) with the lowest measured
+ * time, for the pre and the post sweep separately (`reps` back-to-back launches replayed from a
+ * captured graph and timed with hipEvents, so host launch overhead does not enter; float64 and,
+ * for DMG_FP32_IR, float32 kernels separately), and the coarse-tail workgroup size the same
+ * way -- numerically neutral.  flags bit 1: pick the colour order with the
  * lowest measured solve time among the row-separable orders whose post order is the reverse of
  * the pre order (0123/3210, 1032/2301, 2301/1032, 3210/0123) -- this changes the iterates, so
  * read the choice back with dmg_hier_config.  u is scratch (overwritten), b a right-hand side
  * of the level-0 shape.  Synchronous.  Invalidates captured graphs. */
 dmg_status dmg_autotune(dmg_hier* h, double* u, const double* b, int32_t flags, int32_t reps,
                         hipStream_t stream);
-/* The launch shape of level `level`: bw = strip width in columns of the LDS strip kernel, or 1
- * for the one-wavefront kernel; seg_h = rows per segment (0,0 for tail levels); and the colour
- * orders in use (host arrays of 4, nullable). */
+/* The launch shape of level `level`'s float64 pre sweep: bw = strip width in columns of the LDS
+ * strip kernel, or 1 for the one-wavefront kernel; seg_h = rows per segment (0,0 for tail
+ * levels); and the colour orders in use (host arrays of 4, nullable). */
 dmg_status dmg_hier_config(const dmg_hier* h, int32_t level, int32_t* bw, int32_t* seg_h,
                            int32_t* pre_order, int32_t* post_order);
 /* ||b - A u||_2 over interior vertices (deterministic fixed-order reduction).  Synchronous. */

@@ -110,29 +110,73 @@ void carve(dmg_hier& h, Arena& a, const std::vector<std::pair<int, int>>& dims,
   const bool fp32 = o.precision == DMG_FP32_IR;
   h.L.assign(dims.size(), Level{});
   // the coarse tail takes the coarsest levels up to kTailMaxN whose float64 data fits in the
-  // LDS of one workgroup (it always holds the coarsest level)
+  // LDS of one workgroup (it always holds the coarsest level, or the dense level above it)
   const int lds = device_lds_limit();
-  const int m = (dims.back().first - 2) * (dims.back().second - 2);
-  auto fits = [&](int top) {
-    const int nlev = int(dims.size()) - top;
-    if (nlev > kMaxTail) return false;
+  const int nl = int(dims.size());
+  auto interior = [&](int l) { return (dims[l].first - 2) * (dims[l].second - 2); };
+  // levels the tail kernel holds when it starts at `top`: down to the first level with at most
+  // kDenseMax interior unknowns (solved by its dense matrix), else down to the coarsest
+  auto shape = [&](int top, int* nlev, int* mm, int* dense) {
+    *nlev = nl - top;
+    *mm = interior(nl - 1);
+    *dense = 0;
+    for (int l = top; l < nl; ++l)
+      if (interior(l) <= kDenseMax) {
+        *nlev = l - top + 1;
+        *mm = interior(l);
+        *dense = 1;
+        break;
+      }
+  };
+  auto layout = [&](int top) {
+    int nlev = 0, mm = 0, dense = 0;
+    shape(top, &nlev, &mm, &dense);
     int nx[kMaxTail], ny[kMaxTail];
-    for (int k = 0; k < nlev; ++k) {
+    for (int k = 0; k < nlev && k < kMaxTail; ++k) {
       nx[k] = dims[top + k].first;
       ny[k] = dims[top + k].second;
     }
-    return tail_layout(nx, ny, nlev, m, int(sizeof(double))).bytes <= size_t(lds);
+    return std::make_pair(nlev, nlev > kMaxTail ? TailLayout{}
+                                                : tail_layout(nx, ny, nlev, mm, int(sizeof(double)), dense));
   };
-  h.tail = int(dims.size()) - 1;
+  auto fits = [&](int top) {
+    const auto t = layout(top);
+    return t.first <= kMaxTail && t.second.bytes <= size_t(lds);
+  };
+  h.tail = nl - 1;
   while (h.tail > 0 && std::max(dims[h.tail - 1].first, dims[h.tail - 1].second) <= kTailMaxN &&
          fits(h.tail - 1))
     --h.tail;
+  shape(h.tail, &h.tail_nlev, &h.tail_m, &h.tail_dense);
+  // Below level 0 the tail levels' S, P and right-hand sides (and the dense matrix) are slots of
+  // one block laid out as the tail kernel's LDS (see TailSpec::image); its iterate slots are
+  // zeroed at setup.
+  const TailLayout img = layout(h.tail).second;
+  h.tail_img = nullptr;
+  h.tail_img32 = nullptr;
+  h.tail_img_n = 0;
+  h.basis = nullptr;
+  h.basis32 = nullptr;
+  if (h.tail > 0) {
+    h.tail_img_n = img.r;
+    h.tail_img = a.take<double>(size_t(img.r));
+    if (fp32) h.tail_img32 = a.take<float>(size_t(img.r));
+  }
+  auto slot = [](auto* base, int off) { return base ? base + off : nullptr; };
+  if (h.tail_dense) {
+    const size_t mm = size_t(h.tail_m) * h.tail_m;
+    h.basis = h.tail > 0 ? slot(h.tail_img, img.B) : a.take<double>(mm);
+    if (fp32) h.basis32 = h.tail > 0 ? slot(h.tail_img32, img.B) : a.take<float>(mm);
+  }
   for (size_t l = 0; l < dims.size(); ++l) {
     Level& L = h.L[l];
     L.nx = dims[l].first;
     L.ny = dims[l].second;
     const size_t n = L.n();
-    L.S = a.take<double>(5 * n);
+    const int k = int(l) - h.tail;  // index within the tail kernel's levels
+    const bool in_img = h.tail > 0 && k >= 0 && k < h.tail_nlev;
+    const bool staged = in_img && k + 1 < h.tail_nlev;  // S and P of the tail's last level are not
+    L.S = staged ? slot(h.tail_img, img.S[k]) : a.take<double>(5 * n);
     if (int(l) < h.tail || l == 0) L.Sp = a.take<double>(5 * n);
     if (int(l) < h.tail) {
       L.t = a.take<double>(n);
@@ -143,22 +187,22 @@ void carve(dmg_hier& h, Arena& a, const std::vector<std::pair<int, int>>& dims,
     }
     if (l + 1 < dims.size()) {
       const size_t nc = size_t(dims[l + 1].first) * dims[l + 1].second;
-      L.P = a.take<double>(8 * nc);
+      L.P = staged ? slot(h.tail_img, img.P[k]) : a.take<double>(8 * nc);
       L.r = a.take<double>(n);
       if (fp32) {
-        L.P32 = a.take<float>(8 * nc);
+        L.P32 = staged ? slot(h.tail_img32, img.P[k]) : a.take<float>(8 * nc);
         L.r32 = a.take<float>(n);
       }
     }
     if (l > 0) {
       L.u = a.take<double>(n);
-      L.b = a.take<double>(n);
+      L.b = in_img ? slot(h.tail_img, img.b[k]) : a.take<double>(n);
     }
     if (o.smoother != 0 && int(l) < h.tail) L.lf = a.take<double>(4 * n);
     if (fp32) {
-      if (int(l) >= h.tail) L.S32 = a.take<float>(5 * n);
+      if (int(l) >= h.tail) L.S32 = staged ? slot(h.tail_img32, img.S[k]) : a.take<float>(5 * n);
       L.u32 = a.take<float>(n);
-      L.b32 = a.take<float>(n);
+      L.b32 = in_img ? slot(h.tail_img32, img.b[k]) : a.take<float>(n);
     }
   }
   const auto& c = dims.back();
@@ -168,7 +212,7 @@ void carve(dmg_hier& h, Arena& a, const std::vector<std::pair<int, int>>& dims,
   h.partials = a.take<double>(kMaxPartials + kReduceBlocks);  // + the b-norm partials of a solve start
   for (size_t l = 0; l < dims.size(); ++l) {
     h.L[l].cfg = default_strip_config(dims[l].first, dims[l].second, o);
-    h.L[l].cfg32 = h.L[l].cfg;
+    h.L[l].cfg32 = h.L[l].cfgp = h.L[l].cfgp32 = h.L[l].cfg;
   }
   h.scalars = a.take<double>(16);
   h.flag = a.take<int>(16);
@@ -180,6 +224,7 @@ struct Prec;
 template <>
 struct Prec<double> {
   static const StripConfig& cfg(const Level& L) { return L.cfg; }
+  static const StripConfig& cfgp(const Level& L) { return L.cfgp; }
   static double* t(const Level& L) { return L.t; }
   static const double* S(const Level& L) { return L.S; }
   static const double* Sp(const Level& L) { return L.Sp; }
@@ -187,10 +232,13 @@ struct Prec<double> {
   static double* u(const Level& L) { return L.u; }
   static double* b(const Level& L) { return L.b; }
   static double* r(const Level& L) { return L.r; }
+  static const double* img(const dmg_hier& h) { return h.tail_img; }
+  static const double* basis(const dmg_hier& h) { return h.basis; }
 };
 template <>
 struct Prec<float> {
   static const StripConfig& cfg(const Level& L) { return L.cfg32; }
+  static const StripConfig& cfgp(const Level& L) { return L.cfgp32; }
   static float* t(const Level& L) { return L.t32; }
   static const float* S(const Level& L) { return L.S32; }
   static const float* Sp(const Level& L) { return L.Sp32; }
@@ -198,7 +246,94 @@ struct Prec<float> {
   static float* u(const Level& L) { return L.u32; }
   static float* b(const Level& L) { return L.b32; }
   static float* r(const Level& L) { return L.r32; }
+  static const float* img(const dmg_hier& h) { return h.tail_img32; }
+  static const float* basis(const dmg_hier& h) { return h.basis32; }
 };
+
+}  // namespace
+
+// Kernel arguments of a hierarchy's coarse tail: levels [tail, tail + tail_nlev), the top one's
+// iterate and right-hand side at (u_top, b_top).
+template <class T>
+void tail_spec(const dmg_hier* h, T* u_top, const T* b_top, bool zero_top, const int* stop,
+               TailSpec<T>* out) {
+  using Pr = Prec<T>;
+  TailSpec<T>& sp = *out;
+  sp.nlev = h->tail_nlev;
+  for (int k = 0; k < sp.nlev; ++k) {
+    const Level& L = h->L[h->tail + k];
+    sp.S[k] = Pr::S(L);
+    sp.u[k] = k == 0 ? u_top : Pr::u(L);
+    sp.b[k] = k == 0 ? const_cast<T*>(b_top) : Pr::b(L);
+    sp.P[k] = Pr::P(L);
+    sp.nx[k] = L.nx;
+    sp.ny[k] = L.ny;
+  }
+  sp.zero_top = zero_top;
+  sp.m = h->tail_dense ? h->tail_m : h->m_coarse;
+  sp.idx = h->coarse_idx;
+  sp.chol = h->chol;
+  sp.dense = h->tail_dense;
+  sp.B = Pr::basis(*h);
+  for (int k = 0; k < 4; ++k) {
+    sp.pre[k] = h->opts.pre_order[k];
+    sp.post[k] = h->opts.post_order[k];
+  }
+  sp.nu_pre = h->opts.nu_pre;
+  sp.nu_post = h->opts.nu_post;
+  sp.smoother = h->opts.smoother;
+  sp.stop = stop;
+  sp.threads = h->tail_threads;
+  const T* img = Pr::img(*h);
+  if (img && h->tail > 0 && zero_top && b_top == Pr::b(h->L[h->tail])) {
+    sp.image = img;
+    sp.image_n = h->tail_img_n;
+  }
+}
+template void tail_spec<double>(const dmg_hier*, double*, const double*, bool, const int*,
+                                TailSpec<double>*);
+template void tail_spec<float>(const dmg_hier*, float*, const float*, bool, const int*,
+                               TailSpec<float>*);
+
+namespace {
+
+// The dense operator of the tail's last level (when it has one): the cycle from that level
+// down, run on each of its interior unit vectors with the current options, in float64 (and
+// rounded to float32 for the float tail).  Depends on the smoother, the colour orders and the
+// sweep counts, so it is recomputed whenever one of them changes.
+dmg_status compute_basis(dmg_hier* h, hipStream_t s) {
+  if (!h->tail_dense) return DMG_OK;
+  const int nl = int(h->L.size());
+  const int c = h->tail + h->tail_nlev - 1;
+  TailSpec<double> sp;
+  sp.nlev = nl - c;
+  for (int k = 0; k < sp.nlev; ++k) {
+    const Level& L = h->L[c + k];
+    sp.S[k] = L.S;
+    sp.u[k] = L.u;
+    sp.b[k] = L.b;
+    sp.P[k] = L.P;
+    sp.nx[k] = L.nx;
+    sp.ny[k] = L.ny;
+  }
+  sp.zero_top = 1;
+  sp.m = h->m_coarse;
+  sp.idx = h->coarse_idx;
+  sp.chol = h->chol;
+  for (int k = 0; k < 4; ++k) {
+    sp.pre[k] = h->opts.pre_order[k];
+    sp.post[k] = h->opts.post_order[k];
+  }
+  sp.nu_pre = h->opts.nu_pre;
+  sp.nu_post = h->opts.nu_post;
+  sp.smoother = h->opts.smoother;
+  sp.threads = 256;
+  DMG_CHECK(launch_tail_basis(sp, h->basis, s));
+  if (h->basis32)
+    DMG_CHECK(launch_cast(h->basis, h->basis32, size_t(h->tail_m) * h->tail_m, s));
+  return DMG_OK;
+}
+
 
 // Strip-kernel colour-order parameters: row parity smoothed first and the column parity
 // smoothed first on each row parity.
@@ -212,33 +347,8 @@ OrderParams order_params(const int32_t* ord) {
 template <class T>
 dmg_status tail_launch(dmg_hier* h, T* u_top, const T* b_top, hipStream_t s, bool u0_zero,
                        const int* stop) {
-  using Pr = Prec<T>;
   TailSpec<T> sp;
-  const int nl = int(h->L.size());
-  sp.nlev = nl - h->tail;
-  for (int l = h->tail; l < nl; ++l) {
-    const Level& L = h->L[l];
-    const int k = l - h->tail;
-    sp.S[k] = Pr::S(L);
-    sp.u[k] = k == 0 ? u_top : Pr::u(L);
-    sp.b[k] = k == 0 ? const_cast<T*>(b_top) : Pr::b(L);
-    sp.P[k] = Pr::P(L);
-    sp.nx[k] = L.nx;
-    sp.ny[k] = L.ny;
-  }
-  sp.zero_top = h->tail > 0 || u0_zero;
-  sp.m = h->m_coarse;
-  sp.idx = h->coarse_idx;
-  sp.chol = h->chol;
-  for (int k = 0; k < 4; ++k) {
-    sp.pre[k] = h->opts.pre_order[k];
-    sp.post[k] = h->opts.post_order[k];
-  }
-  sp.nu_pre = h->opts.nu_pre;
-  sp.nu_post = h->opts.nu_post;
-  sp.smoother = h->opts.smoother;
-  sp.stop = stop;
-  sp.threads = h->tail_threads;
+  tail_spec<T>(h, u_top, b_top, h->tail > 0 || u0_zero, stop, &sp);
   return launch_tail<T>(sp, s);
 }
 
@@ -314,7 +424,7 @@ dmg_status vcycle_impl(dmg_hier* h, T* u0, const T* b0, hipStream_t s, double* p
     for (int k = 0; k < o.nu_post; ++k) {
       const bool first = k == 0, last = k + 1 == o.nu_post;  // prolongate once, norm once
       T* dst = other(l, cur[l]);
-      DMG_CHECK(launch_post<T>(Pr::cfg(L), Pr::Sp(L), cur[l], dst, b, Pr::P(L), first ? e : nullptr,
+      DMG_CHECK(launch_post<T>(Pr::cfgp(L), Pr::Sp(L), cur[l], dst, b, Pr::P(L), first ? e : nullptr,
                                (l == 0 && last) ? partials : nullptr, L.nx, L.ny, post.pf, post.cA,
                                post.cB, stop, s, (l == 0 && last) ? x64 : nullptr));
       cur[l] = dst;
@@ -332,7 +442,7 @@ dmg_status vcycle_impl(dmg_hier* h, T* u0, const T* b0, hipStream_t s, double* p
 int post_partials_count(const dmg_hier* h) {
   const Level& L = h->L[0];
   int ns = 0, nseg = 0;
-  return strip_blocks(L.nx, L.ny, L.cfg.bw, L.cfg.seg_h, &ns, &nseg);
+  return strip_blocks(L.nx, L.ny, L.cfgp.bw, L.cfgp.seg_h, &ns, &nseg);
 }
 
 dmg_status read_scalar(dmg_hier* h, int slot, double* out, hipStream_t s) {
@@ -440,10 +550,49 @@ dmg_status run_step(dmg_hier* h, int kind, double* u, const double* b, hipStream
   return DMG_OK;
 }
 
-// Mean duration (ms) of `reps` pre + post launches of level l in precision T with shape c.
+// Mean duration (ms) of run() over `reps` back-to-back runs, timed on the device.  The runs are
+// captured into one graph and replayed, so that host launch overhead (larger than a small
+// level's kernels) neither enters the timing nor hides the difference between launch shapes;
+// the legacy default stream cannot be captured and is timed with eager launches.
+template <class F>
+dmg_status time_runs(F&& run, int reps, hipStream_t s, hipEvent_t e0, hipEvent_t e1, float* ms) {
+  DMG_CHECK(run());  // warm-up, and the argument checks outside any capture
+  hipGraphExec_t exec = nullptr;
+  if (s != nullptr) {
+    DMG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    dmg_status st = DMG_OK;
+    for (int k = 0; k < reps && st == DMG_OK; ++k) st = run();
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (st == DMG_OK && e == hipSuccess) e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (st != DMG_OK) return st;
+    if (e != hipSuccess) return fail(DMG_ERR_HIP, "timing graph failed: %s", hipGetErrorString(e));
+  }
+  auto once = [&]() -> hipError_t {
+    if (exec) return hipGraphLaunch(exec, s);
+    for (int k = 0; k < reps; ++k)
+      if (run() != DMG_OK) return hipErrorLaunchFailure;
+    return hipSuccess;
+  };
+  hipError_t e = once();  // uploads the graph
+  if (e == hipSuccess) e = hipEventRecord(e0, s);
+  if (e == hipSuccess) e = once();
+  if (e == hipSuccess) e = hipEventRecord(e1, s);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float t_ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t_ms, e0, e1);
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (e != hipSuccess) return fail(DMG_ERR_HIP, "kernel timing failed: %s", hipGetErrorString(e));
+  *ms = t_ms / float(reps);
+  return DMG_OK;
+}
+
+// Mean durations (ms) of `reps` pre launches and of `reps` post launches of level l in
+// precision T with shape c.
 template <class T>
 dmg_status time_level(dmg_hier* h, int l, const StripConfig& c, int reps, hipStream_t s,
-                      hipEvent_t e0, hipEvent_t e1, float* ms) {
+                      hipEvent_t e0, hipEvent_t e1, float* ms_pre, float* ms_post) {
   using Pr = Prec<T>;
   const Level& L = h->L[l];
   const OrderParams pre = order_params(h->opts.pre_order), post = order_params(h->opts.post_order);
@@ -452,21 +601,14 @@ dmg_status time_level(dmg_hier* h, int l, const StripConfig& c, int reps, hipStr
   T* u = l == 0 ? Pr::r(L) : Pr::u(L);
   T* t = Pr::t(L);
   const T* b = l == 0 ? Pr::Sp(L) : Pr::b(L);
-  auto run = [&]() -> dmg_status {
-    DMG_CHECK(launch_pre<T>(c, Pr::Sp(L), u, t, b, Pr::P(L), Pr::b(h->L[l + 1]), L.nx, L.ny, pre.pf,
-                            pre.cA, pre.cB, nullptr, s));
+  DMG_CHECK(time_runs([&]() {
+    return launch_pre<T>(c, Pr::Sp(L), u, t, b, Pr::P(L), Pr::b(h->L[l + 1]), L.nx, L.ny, pre.pf,
+                         pre.cA, pre.cB, nullptr, s);
+  }, reps, s, e0, e1, ms_pre));
+  return time_runs([&]() {
     return launch_post<T>(c, Pr::Sp(L), t, u, b, Pr::P(L), Pr::u(h->L[l + 1]), nullptr, L.nx, L.ny,
                           post.pf, post.cA, post.cB, nullptr, s);
-  };
-  DMG_CHECK(run());  // warm-up
-  DMG_HIP(hipEventRecord(e0, s));
-  for (int k = 0; k < reps; ++k) DMG_CHECK(run());
-  DMG_HIP(hipEventRecord(e1, s));
-  DMG_HIP(hipEventSynchronize(e1));
-  float t_ms = 0.f;
-  DMG_HIP(hipEventElapsedTime(&t_ms, e0, e1));
-  *ms = t_ms / float(reps);
-  return DMG_OK;
+  }, reps, s, e0, e1, ms_post);
 }
 
 template <class T>
@@ -477,8 +619,8 @@ dmg_status tune_levels(dmg_hier* h, int reps, hipStream_t s) {
   dmg_status st = DMG_OK;
   for (int l = 0; l < h->tail && st == DMG_OK; ++l) {
     Level& L = h->L[l];
-    StripConfig best = Prec<T>::cfg(L);
-    float best_ms = 1e30f;
+    StripConfig best_pre = Prec<T>::cfg(L), best_post = Prec<T>::cfgp(L);
+    float best_pre_ms = 1e30f, best_post_ms = 1e30f;
     for (int bw : {1, 64, 128, 256}) {  // 1: one-wavefront DPP strips (64 columns)
       if (bw == 256 && sizeof(T) == 8) continue;  // a 256-wide float64 ring exceeds 64 KiB of LDS
       for (int sh = 2; sh <= 128 && st == DMG_OK; sh *= 2) {
@@ -488,17 +630,26 @@ dmg_status tune_levels(dmg_hier* h, int reps, hipStream_t s) {
         c.bw = bw == 1 ? 64 : bw;
         c.seg_h = sh;
         if (strip_blocks(L.nx, L.ny, c.bw, sh, &ns, &nseg) > kMaxPartials) continue;
-        float ms = 0.f;
-        st = time_level<T>(h, l, c, reps, s, e0, e1, &ms);
-        if (st == DMG_OK && ms < best_ms) {
-          best_ms = ms;
-          best = c;
+        float ms_pre = 0.f, ms_post = 0.f;
+        st = time_level<T>(h, l, c, reps, s, e0, e1, &ms_pre, &ms_post);
+        if (st == DMG_OK && ms_pre < best_pre_ms) {
+          best_pre_ms = ms_pre;
+          best_pre = c;
+        }
+        if (st == DMG_OK && ms_post < best_post_ms) {
+          best_post_ms = ms_post;
+          best_post = c;
         }
         if (sh * 2 > L.ny + 1) break;
       }
     }
-    if (sizeof(T) == 8) L.cfg = best;
-    else L.cfg32 = best;
+    if (sizeof(T) == 8) {
+      L.cfg = best_pre;
+      L.cfgp = best_post;
+    } else {
+      L.cfg32 = best_pre;
+      L.cfgp32 = best_post;
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -516,17 +667,10 @@ dmg_status tune_tail(dmg_hier* h, T* u_top, const T* b_top, int reps, hipStream_
   float best_ms = 1e30f;
   for (int nt : {256, 512, 1024}) {
     h->tail_threads = nt;
-    for (int w = 0; w < 2 && st == DMG_OK; ++w) st = tail_launch<T>(h, u_top, b_top, s, true, nullptr);
-    if (st != DMG_OK) break;
-    if (hipEventRecord(e0, s) != hipSuccess) { st = fail(DMG_ERR_HIP, "event record failed"); break; }
-    for (int r = 0; r < reps && st == DMG_OK; ++r) st = tail_launch<T>(h, u_top, b_top, s, true, nullptr);
-    if (st != DMG_OK) break;
     float ms = 0.f;
-    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-      st = fail(DMG_ERR_HIP, "event timing failed");
-      break;
-    }
+    st = time_runs([&]() { return tail_launch<T>(h, u_top, b_top, s, true, nullptr); }, reps, s, e0,
+                   e1, &ms);
+    if (st != DMG_OK) break;
     if (ms < best_ms) {
       best_ms = ms;
       best = nt;
@@ -545,6 +689,10 @@ dmg_status setup_impl(dmg_hier* h, const double* S, hipStream_t s) {
   while (first_small > 0 && std::max(h->L[first_small - 1].nx, h->L[first_small - 1].ny) <= kSmallSetupN &&
          nl - (first_small - 1) <= kMaxTail + 1)
     --first_small;
+  // the tail image's iterate (and unused right-hand side) slots start at zero; its S and P slots
+  // are written below
+  if (h->tail_img) DMG_CHECK(launch_fill<double>(h->tail_img, 0.0, size_t(h->tail_img_n), s));
+  if (h->tail_img32) DMG_CHECK(launch_fill<float>(h->tail_img32, 0.f, size_t(h->tail_img_n), s));
   DMG_CHECK(launch_copy_pack(S, h->L[0].S, h->L[0].Sp, h->L[0].n(), s));
   for (int l = 0; l < first_small; ++l) {
     const Level& L = h->L[l];
@@ -582,6 +730,7 @@ dmg_status setup_impl(dmg_hier* h, const double* S, hipStream_t s) {
   }
   if (h->opts.smoother != 0)
     for (int l = 0; l < h->tail; ++l) DMG_CHECK(line_factors(h->L[l], s));
+  DMG_CHECK(compute_basis(h, s));
   int flag = 0;
   DMG_HIP(hipMemcpyAsync(&flag, h->flag, sizeof(int), hipMemcpyDeviceToHost, s));
   DMG_HIP(hipStreamSynchronize(s));
@@ -715,7 +864,7 @@ dmg_status dmg_sweep(dmg_hier* h, int32_t level, int32_t kind, double* u, const 
   if (kind == 0)
     return launch_pre<double>(L.cfg, L.Sp, u, L.t, b, L.P, h->L[level + 1].b, L.nx, L.ny, pre.pf,
                               pre.cA, pre.cB, nullptr, stream);
-  return launch_post<double>(L.cfg, L.Sp, u, L.t, b, L.P, h->L[level + 1].u, nullptr, L.nx, L.ny,
+  return launch_post<double>(L.cfgp, L.Sp, u, L.t, b, L.P, h->L[level + 1].u, nullptr, L.nx, L.ny,
                              post.pf, post.cA, post.cB, nullptr, stream);
 }
 
@@ -807,6 +956,7 @@ dmg_status dmg_autotune(dmg_hier* h, double* u, const double* b, int32_t flags, 
         h->opts.post_order[k] = cand[c][3 - k];
       }
       graph_reset(h->graph);
+      DMG_CHECK(compute_basis(h, stream));
       float total = 0.f;
       dmg_status st = DMG_OK;
       for (int r = 0; r < std::max(1, reps / 4) && st == DMG_OK; ++r) {
@@ -835,6 +985,7 @@ dmg_status dmg_autotune(dmg_hier* h, double* u, const double* b, int32_t flags, 
       }
     graph_reset(h->graph);
     clear_error();
+    DMG_CHECK(compute_basis(h, stream));  // for the order kept
   }
   return DMG_OK;
 }

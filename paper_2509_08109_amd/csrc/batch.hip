@@ -246,28 +246,8 @@ dmg_status build_schedule(dmg_batch* bt, double* const* u, const double* const* 
       dmg_hier* h = bt->inst[k];
       const int T = h->tail, nl = int(h->L.size());
       TailSpec<double> sp;
-      sp.nlev = nl - T;
-      for (int l = T; l < nl; ++l) {
-        const Level& L = h->L[l];
-        const int i = l - T;
-        sp.S[i] = L.S;
-        sp.u[i] = i == 0 ? (T == 0 ? u[k] : L.u) : L.u;
-        sp.b[i] = i == 0 ? (T == 0 ? const_cast<double*>(b[k]) : L.b) : L.b;
-        sp.P[i] = L.P;
-        sp.nx[i] = L.nx;
-        sp.ny[i] = L.ny;
-      }
-      sp.zero_top = T > 0;
-      sp.m = h->m_coarse;
-      sp.idx = h->coarse_idx;
-      sp.chol = h->chol;
-      for (int c = 0; c < 4; ++c) {
-        sp.pre[c] = o.pre_order[c];
-        sp.post[c] = o.post_order[c];
-      }
-      sp.nu_pre = o.nu_pre;
-      sp.nu_post = o.nu_post;
-      sp.stop = bt->state + 4 * k;
+      tail_spec<double>(h, T == 0 ? u[k] : h->L[T].u, T == 0 ? b[k] : h->L[T].b, T > 0,
+                        bt->state + 4 * k, &sp);
       sp.threads = bt->tail_threads;
       size_t bytes = 0;
       DMG_CHECK(make_tail_args<double>(sp, &list[k], &bytes));

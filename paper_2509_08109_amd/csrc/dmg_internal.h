@@ -58,8 +58,10 @@ struct StripConfig {
 
 // ---- hierarchy ---------------------------------------------------------------------------
 struct Level {
-  StripConfig cfg;        // fused-kernel launch shape (levels above the tail), float64
+  StripConfig cfg;        // fused-kernel launch shape (levels above the tail), float64 pre sweeps
   StripConfig cfg32;      // the same for the float32 kernels
+  StripConfig cfgp;       // ... and for the post sweeps (tuned separately)
+  StripConfig cfgp32;
   int nx = 0, ny = 0;
   double* S = nullptr;    // [5][ny][nx]
   double* Sp = nullptr;   // [ny][nx][5] point-major copy of S read by the strip sweeps (levels
@@ -87,6 +89,7 @@ constexpr int kTailMaxN = 65;    // levels with max(nx, ny) <= this may run in t
 constexpr int kMaxTail = 12;     // at most this many levels in the coarse tail
 constexpr int kSmallSetupN = 65;  // levels with max(nx, ny) <= this are set up in one workgroup
 constexpr int kMaxLevels = 32;
+constexpr int kDenseMax = 64;    // interior unknowns of a level whose sub-cycle is a dense matrix
 constexpr int kMaxHistory = 4096;
 constexpr int kChunk = 4;            // solve steps per host synchronisation
 
@@ -115,6 +118,20 @@ struct dmg_hier {
   int* flag = nullptr;        // device ints: [0] pivot flag, [4..6] solve state (stop, steps, max)
   double* hist = nullptr;     // device history of relative residuals [kMaxHistory]
   double* host = nullptr;     // pinned host scalars [16]
+  // With a coarse tail below level 0: its levels' S, P and right-hand sides stored in one block
+  // laid out as the tail kernel's LDS (iterate slots zero), which the kernel stages in one copy
+  double* tail_img = nullptr;
+  float* tail_img32 = nullptr;  // the same for the float32 tail (DMG_FP32_IR)
+  int tail_img_n = 0;           // elements of each
+  // The tail kernel holds levels [tail, tail + tail_nlev).  With tail_dense its last level (the
+  // first with at most kDenseMax interior unknowns, tail_m of them) is solved by the dense
+  // matrix `basis` (float32 copy basis32), the cycle from that level down applied exactly as
+  // the linear map it is; the levels below it are then used only to compute that matrix.
+  int tail_nlev = 0;
+  int tail_m = 0;
+  int tail_dense = 0;
+  double* basis = nullptr;
+  float* basis32 = nullptr;
   dmg::Graph graph;
   ~dmg_hier();
 };
@@ -213,6 +230,12 @@ struct TailArgs {
   int nu_pre, nu_post;
   int smoother;       // 0: 4-colour point Gauss-Seidel; 1-3: zebra lines (x, y, alternating)
   const int* stop;
+  const T* image;     // nullable: prepacked LDS image of the first image_n elements
+  int image_n;
+  int dense;          // the last level's solve is the dense matrix at LDS offset oB
+  int oB;
+  const T* Bg;        // that matrix in global memory (staged from here without an image)
+  T* basis_out;       // basis run: [m0][m0] top-level interior results, one column per workgroup
 };
 
 // fused strip kernels (fused_kernels.hip)
@@ -245,6 +268,16 @@ struct TailSpec {
   int smoother = 0;    // as dmg_options::smoother
   const int* stop = nullptr;
   int threads = 1024;  // workgroup size: a multiple of 64 in [64, 1024]
+  // nullable: the first image_n elements of the kernel's LDS layout, prepacked in global memory
+  // (S and P of the levels, zero iterates, the top right-hand side in its b slot); only with
+  // zero_top, and b[0] must then be the image's top b slot
+  const T* image = nullptr;
+  int image_n = 0;
+  // dense: the last level is solved by B (m = its interior count, transposed: B[j m + i] is
+  // interior point i of the cycle's result for the j-th interior unit vector), the exact linear
+  // map of the cycle from that level down, instead of by the Cholesky factor
+  int dense = 0;
+  const T* B = nullptr;
 };
 // LDS layout of the coarse-tail kernel for levels nx[0..nlev) (the last one the coarsest, with
 // m unknowns): per level S [5 n] and P [8 n_next] (not at the coarsest), u [n], b [n]; then the
@@ -252,11 +285,21 @@ struct TailSpec {
 // bytes, except y (bytes).
 struct TailLayout {
   int S[kMaxTail], u[kMaxTail], b[kMaxTail], P[kMaxTail];
+  int B = 0;  // dense coarse operator [m][m] (empty unless dense)
   int r = 0;
   int y = 0;
   size_t bytes = 0;
 };
-TailLayout tail_layout(const int* nx, const int* ny, int nlev, int m, int elem);
+TailLayout tail_layout(const int* nx, const int* ny, int nlev, int m, int elem, int dense);
+// The dense coarse operator of a tail: one workgroup per top-level interior unknown j runs the
+// full cycle (spec: no image, not dense, zero_top) on the j-th unit vector and writes the top
+// level's interior result to out[j m0 ...].
+dmg_status launch_tail_basis(const TailSpec<double>& spec, double* out, hipStream_t s);
+// Kernel arguments of hierarchy h's coarse tail (api.hip), the top level's iterate and
+// right-hand side at (u_top, b_top); the prepacked image is used when b_top is its top slot.
+template <class T>
+void tail_spec(const dmg_hier* h, T* u_top, const T* b_top, bool zero_top, const int* stop,
+               TailSpec<T>* out);
 int device_lds_limit();  // LDS bytes one workgroup may use on the current device
 template <class T>
 dmg_status launch_tail(const TailSpec<T>& spec, hipStream_t s);

@@ -538,14 +538,45 @@ __device__ void tail_smooth(const TailArgs<T>& a, const T* S, T* u, const T* b, 
   }
 }
 
+// Copies n elements from global src to LDS dst (both 16-byte aligned) in 16-byte words; each
+// thread issues all loads of a round before its stores, so a round costs one memory latency.
+template <class T>
+__device__ __forceinline__ void stage_lds(T* dst, const T* src, int n, int tid, int nt) {
+  constexpr int K = 8;
+  const int nv = int((size_t(n) * sizeof(T)) / 16);
+  const uint4* s4 = reinterpret_cast<const uint4*>(src);
+  uint4* d4 = reinterpret_cast<uint4*>(dst);
+  for (int base = tid; base < nv; base += K * nt) {
+    uint4 v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int q = base + k * nt;
+      v[k] = s4[q < nv ? q : 0];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int q = base + k * nt;
+      if (q < nv) d4[q] = v[k];
+    }
+  }
+  for (int k = int(size_t(nv) * 16 / sizeof(T)) + tid; k < n; k += nt) dst[k] = src[k];
+}
+
 template <class T>
 __device__ __forceinline__ void tail_body(const TailArgs<T>& a) {
   if (a.stop && *a.stop) return;
   extern __shared__ __align__(16) unsigned char smem[];
   T* sm = reinterpret_cast<T*>(smem);
   const int nl = a.nlev, tid = threadIdx.x, nt = blockDim.x;
-  // stage the level data
-  for (int l = 0; l < nl; ++l) {
+  // stage the level data: the prepacked image in one copy, else array by array
+  if (a.image) stage_lds(sm, a.image, a.image_n, tid, nt);
+  // basis run (workgroup j): the top right-hand side is the j-th interior unit vector
+  const int vj = a.basis_out ? (int(blockIdx.x) / (a.L[0].nx - 2) + 1) * a.L[0].nx +
+                                   int(blockIdx.x) % (a.L[0].nx - 2) + 1
+                             : -1;
+  if (a.dense && !a.image)
+    for (int k = tid; k < a.m * a.m; k += nt) sm[a.oB + k] = a.Bg[k];
+  for (int l = 0; l < nl && !a.image; ++l) {
     const TailLevel<T>& G = a.L[l];
     const int n = G.nx * G.ny;
     T* u = sm + a.ou[l];
@@ -559,7 +590,7 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& a) {
     if (l == 0) {
       T* b = sm + a.ob[l];
       for (int k = tid; k < n; k += nt) {
-        b[k] = G.b[k];
+        b[k] = a.basis_out ? T(k == vj ? 1 : 0) : G.b[k];
         u[k] = a.zero_top ? T(0) : G.u[k];
       }
     } else {
@@ -604,8 +635,39 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& a) {
     }
     __syncthreads();
   }
-  // coarsest: dense Cholesky solve in float64
-  {
+  if (a.dense) {
+    // last level: its precomputed dense operator B (transposed, [j][i]) on the interior, the
+    // exact linear map of the cycle from this level down; on a top level that carries an
+    // iterate (u != 0) the cycle is u + B (b - A u)
+    const int cx = a.L[nl - 1].nx, cy = a.L[nl - 1].ny, mx = cx - 2, m = a.m, N = cx * cy;
+    T* uc = sm + a.ou[nl - 1];
+    const T* bc = sm + a.ob[nl - 1];
+    const T* B = sm + a.oB;
+    const bool corr = nl == 1 && !a.zero_top;
+    T* rr = sm + a.o_r;
+    if (corr) {  // this level's stencil is not staged: read it from global memory
+      const T* Sg = a.L[nl - 1].S;
+      for (int v = tid; v < N; v += nt) {
+        const int i = v % cx, j = v / cx;
+        T rv = T(0);
+        if (i > 0 && i < cx - 1 && j > 0 && j < cy - 1)
+          rv = bc[v] - (offdiag_s(Sg, uc, N, cx, v) + Sg[v] * uc[v]);
+        rr[v] = rv;
+      }
+      __syncthreads();
+    }
+    const T* rhs = corr ? rr : bc;
+    for (int i = tid; i < m; i += nt) {
+      T acc = T(0);
+      int j = 0;
+      for (int jy = 1; jy < cy - 1; ++jy)
+        for (int jx = 1; jx < cx - 1; ++jx, ++j) acc += B[j * m + i] * rhs[jy * cx + jx];
+      const int v = (i / mx + 1) * cx + i % mx + 1;
+      uc[v] = corr ? uc[v] + acc : acc;
+    }
+    __syncthreads();
+  } else {
+    // coarsest: dense Cholesky solve in float64
     T* uc = sm + a.ou[nl - 1];
     const T* bc = sm + a.ob[nl - 1];
     double* y = reinterpret_cast<double*>(smem + a.o_y);
@@ -658,11 +720,17 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& a) {
     __syncthreads();
     for (int s = 0; s < a.nu_post; ++s) tail_smooth(a, S, u, b, sm + a.o_r, nx, ny, false);
   }
-  // write back the top level's iterate
+  // write back the top level's iterate (basis run: its interior as column blockIdx.x)
   {
     const TailLevel<T>& G = a.L[0];
     const T* u = sm + a.ou[0];
-    for (int k = tid; k < G.nx * G.ny; k += nt) G.u[k] = u[k];
+    if (a.basis_out) {
+      const int mx = G.nx - 2, m0 = mx * (G.ny - 2);
+      for (int i = tid; i < m0; i += nt)
+        a.basis_out[size_t(blockIdx.x) * m0 + i] = u[(i / mx + 1) * G.nx + i % mx + 1];
+    } else {
+      for (int k = tid; k < G.nx * G.ny; k += nt) G.u[k] = u[k];
+    }
   }
 }
 
@@ -1177,12 +1245,13 @@ dmg_status launch_post(const StripConfig& cfg, const T* S, const T* uin, T* u, c
                                stop, s, x64);
 }
 
-TailLayout tail_layout(const int* nx, const int* ny, int nlev, int m, int elem) {
+TailLayout tail_layout(const int* nx, const int* ny, int nlev, int m, int elem, int dense) {
   TailLayout t;
   int off = 0;
   int rmax = 0;
   for (int l = 0; l < nlev; ++l) {
     const int n = nx[l] * ny[l];
+    if (dense && l + 1 == nlev) rmax = n > rmax ? n : rmax;  // the residual of a dense top level
     if (l + 1 < nlev) {
       t.S[l] = off;
       off += 5 * n;
@@ -1197,6 +1266,8 @@ TailLayout tail_layout(const int* nx, const int* ny, int nlev, int m, int elem) 
     t.b[l] = off;
     off += n;
   }
+  t.B = off;
+  off += dense ? m * m : 0;
   t.r = off;
   off += rmax;
   size_t bytes = size_t(off) * elem;
@@ -1218,7 +1289,10 @@ template <class T>
 dmg_status make_tail_args(const TailSpec<T>& spec, TailArgs<T>* out, size_t* lds_bytes) {
   TailArgs<T>& a = *out;
   if (spec.nlev > kMaxTail) return fail(DMG_ERR_INVALID_ARG, "tail too deep (%d)", spec.nlev);
-  const TailLayout lay = tail_layout(spec.nx, spec.ny, spec.nlev, spec.m, int(sizeof(T)));
+  if (spec.dense && spec.m != (spec.nx[spec.nlev - 1] - 2) * (spec.ny[spec.nlev - 1] - 2))
+    return fail(DMG_ERR_INVALID_ARG, "dense coarse operator size does not match its level");
+  const TailLayout lay =
+      tail_layout(spec.nx, spec.ny, spec.nlev, spec.m, int(sizeof(T)), spec.dense);
   if (lay.bytes > size_t(device_lds_limit()))
     return fail(DMG_ERR_INVALID_ARG, "coarse tail needs %zu bytes of LDS", lay.bytes);
   for (int l = 0; l < spec.nlev; ++l) {
@@ -1248,6 +1322,20 @@ dmg_status make_tail_args(const TailSpec<T>& spec, TailArgs<T>* out, size_t* lds
   a.nu_post = spec.nu_post;
   a.smoother = spec.smoother;
   a.stop = spec.stop;
+  a.image = nullptr;
+  a.image_n = 0;
+  a.dense = spec.dense;
+  a.oB = lay.B;
+  a.Bg = spec.B;
+  a.basis_out = nullptr;
+  if (spec.dense && !spec.B) return fail(DMG_ERR_INVALID_ARG, "dense coarse tail without its matrix");
+  if (spec.image) {
+    if (!spec.zero_top || spec.image_n != lay.r || spec.b[0] != spec.image + lay.b[0] ||
+        (spec.dense && spec.B != spec.image + lay.B))
+      return fail(DMG_ERR_INVALID_ARG, "coarse tail image does not match its layout");
+    a.image = spec.image;
+    a.image_n = spec.image_n;
+  }
   *lds_bytes = lay.bytes;
   return DMG_OK;
 }
@@ -1261,6 +1349,20 @@ dmg_status launch_tail(const TailSpec<T>& spec, hipStream_t s) {
   DMG_CHECK(make_tail_args<T>(spec, &a, &bytes));
   k_tail<T><<<1, spec.threads, bytes, s>>>(a);
   return launch_check("tail");
+}
+
+dmg_status launch_tail_basis(const TailSpec<double>& spec, double* out, hipStream_t s) {
+  if (spec.threads < 64 || spec.threads > 1024 || spec.threads % 64)
+    return fail(DMG_ERR_INVALID_ARG, "coarse tail workgroup size %d", spec.threads);
+  if (spec.dense || spec.image || !spec.zero_top || !out)
+    return fail(DMG_ERR_INVALID_ARG, "basis run of a coarse tail: full cycle from zero only");
+  TailArgs<double> a;
+  size_t bytes = 0;
+  DMG_CHECK(make_tail_args<double>(spec, &a, &bytes));
+  a.basis_out = out;
+  const int m0 = (spec.nx[0] - 2) * (spec.ny[0] - 2);
+  k_tail<double><<<m0, spec.threads, bytes, s>>>(a);
+  return launch_check("tail basis");
 }
 
 template <class T>
