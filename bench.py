@@ -92,7 +92,7 @@ def run_leg(dmg, jac, K, b, steps: int, warmup: int, precision: int, inner: int 
 def level0_kernel(h, n_x: int, n_y: int, kind: int):
     """Name and launch shape of the level-0 sweep kernel the hierarchy runs (kind 0 pre with
     restriction, 1 prolongation with post), as rocprofv3 lists it."""
-    bw, seg_h = h.config()["levels"][0]
+    bw, seg_h = h.config()["levels" if kind == 0 else "post_levels"][0]
     wave = bw == 1
     width = 64 if wave else bw
     out_w = width - 12

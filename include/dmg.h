@@ -127,7 +127,10 @@ dmg_status dmg_setup(const double* S, int32_t nx, int32_t ny, const dmg_options*
 void dmg_destroy(dmg_hier* h);
 /* Recompute the whole hierarchy of h from a new fine stencil S of the same dims, in place (same
  * workspace, options and launch shapes).  Used when coefficients change (time stepping,
- * gradient steps: the hierarchy is recomputed rather than stored).  Synchronises `stream`. */
+ * gradient steps: the hierarchy is recomputed rather than stored).  Asynchronous: the work is
+ * enqueued on `stream` and the call returns without waiting (S must stay valid until that work
+ * has run); a non-positive coarsest pivot (DMG_ERR_NOT_SPD) is reported by the next dmg_solve
+ * on h. */
 dmg_status dmg_refresh(dmg_hier* h, const double* S, hipStream_t stream);
 
 /* Inspection of level l (0 = finest): dims and device pointers to its float64 stencil
@@ -174,6 +177,10 @@ dmg_status dmg_autotune(dmg_hier* h, double* u, const double* b, int32_t flags, 
  * levels); and the colour orders in use (host arrays of 4, nullable). */
 dmg_status dmg_hier_config(const dmg_hier* h, int32_t level, int32_t* bw, int32_t* seg_h,
                            int32_t* pre_order, int32_t* post_order);
+/* The launch shape of level `level`'s float64 sweep of the given kind (0 pre, 1 post; the
+ * autotuner picks them separately): bw and seg_h as in dmg_hier_config. */
+dmg_status dmg_hier_sweep_config(const dmg_hier* h, int32_t level, int32_t kind, int32_t* bw,
+                                 int32_t* seg_h);
 /* ||b - A u||_2 over interior vertices (deterministic fixed-order reduction).  Synchronous. */
 dmg_status dmg_residual_norm(dmg_hier* h, const double* u, const double* b, double* norm,
                              hipStream_t stream);

@@ -121,7 +121,9 @@ class Hierarchy:
         return S, P
 
     def refresh(self, S: torch.Tensor) -> None:
-        """Recompute the hierarchy in place from a new fine stencil of the same dims."""
+        """Recompute the hierarchy in place from a new fine stencil of the same dims (enqueued
+        on the current stream without waiting; a non-SPD coarsest grid is reported by the next
+        solve)."""
         _lib.check(lib().dmg_refresh(self._h, _dev(S, (5, self.ny, self.nx), "S"), _stream(self.device)))
 
     @property
@@ -151,14 +153,18 @@ class Hierarchy:
         return self.config()
 
     def config(self):
-        """{'levels': [(bw, seg_h) per level], 'pre_order': [...], 'post_order': [...]}"""
-        out = []
+        """{'levels': [(bw, seg_h) of the pre sweep per level], 'post_levels': [the same for the
+        post sweep], 'pre_order': [...], 'post_order': [...]}"""
+        out, post_out = [], []
         pre, post = (C.c_int32 * 4)(), (C.c_int32 * 4)()
         for l in range(self.num_levels):
             bw, sh = C.c_int32(), C.c_int32()
             _lib.check(lib().dmg_hier_config(self._h, l, C.byref(bw), C.byref(sh), pre, post))
             out.append((int(bw.value), int(sh.value)))
-        return {"levels": out, "pre_order": list(pre), "post_order": list(post)}
+            _lib.check(lib().dmg_hier_sweep_config(self._h, l, 1, C.byref(bw), C.byref(sh)))
+            post_out.append((int(bw.value), int(sh.value)))
+        return {"levels": out, "post_levels": post_out, "pre_order": list(pre),
+                "post_order": list(post)}
 
     # -- cycles and solves ---------------------------------------------------------------
     def vcycle(self, u: torch.Tensor, b: torch.Tensor) -> torch.Tensor:

@@ -682,7 +682,9 @@ dmg_status tune_tail(dmg_hier* h, T* u_top, const T* b_top, int reps, hipStream_
   return st;
 }
 
-dmg_status setup_impl(dmg_hier* h, const double* S, hipStream_t s) {
+// sync: wait for the setup and report a non-positive coarsest pivot here; otherwise the setup
+// is only enqueued and the next solve reports it.
+dmg_status setup_impl(dmg_hier* h, const double* S, hipStream_t s, bool sync) {
   const int nl = int(h->L.size());
   // levels from first_small down run their whole setup in one single-workgroup kernel
   int first_small = nl - 1;
@@ -714,23 +716,24 @@ dmg_status setup_impl(dmg_hier* h, const double* S, hipStream_t s) {
   ss.chol = h->chol;
   ss.flag = h->flag;
   DMG_CHECK(launch_setup_small(ss, s));
-  for (int l = 0; l < nl; ++l) {
-    const Level& L = h->L[l];
-    if (L.Sp32) DMG_CHECK(launch_pack<float>(L.S, L.Sp32, L.n(), s));
-  }
-  if (h->opts.precision == DMG_FP32_IR) {
-    for (size_t l = 0; l < h->L.size(); ++l) {
+  if (h->opts.precision == DMG_FP32_IR) {  // the float32 copies, in one launch
+    F32Batch fb;
+    for (int l = 0; l < nl; ++l) {
       const Level& L = h->L[l];
-      if (L.S32) DMG_CHECK(launch_cast(L.S, L.S32, 5 * L.n(), s));
-      if (L.P) {
-        const Level& Cn = h->L[l + 1];
-        DMG_CHECK(launch_cast(L.P, L.P32, 8 * Cn.n(), s));
+      if (fb.count + 3 > kMaxF32Segs) {
+        DMG_CHECK(launch_f32_batch(fb, s));
+        fb.count = 0;
       }
+      if (L.Sp32) DMG_CHECK(fb.add(L.S, L.Sp32, L.n(), 1));
+      if (L.S32) DMG_CHECK(fb.add(L.S, L.S32, 5 * L.n(), 0));
+      if (L.P && L.P32) DMG_CHECK(fb.add(L.P, L.P32, 8 * h->L[l + 1].n(), 0));
     }
+    DMG_CHECK(launch_f32_batch(fb, s));
   }
   if (h->opts.smoother != 0)
     for (int l = 0; l < h->tail; ++l) DMG_CHECK(line_factors(h->L[l], s));
   DMG_CHECK(compute_basis(h, s));
+  if (!sync) return DMG_OK;
   int flag = 0;
   DMG_HIP(hipMemcpyAsync(&flag, h->flag, sizeof(int), hipMemcpyDeviceToHost, s));
   DMG_HIP(hipStreamSynchronize(s));
@@ -838,7 +841,7 @@ dmg_status dmg_setup(const double* S, int32_t nx, int32_t ny, const dmg_options*
   carve(*h, a, dims, o);
   DMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&h->host), 16 * sizeof(double),
                         hipHostMallocDefault));
-  DMG_CHECK(setup_impl(h.get(), S, stream));
+  DMG_CHECK(setup_impl(h.get(), S, stream, true));
   *out = h.release();
   return DMG_OK;
 }
@@ -848,7 +851,7 @@ void dmg_destroy(dmg_hier* h) { delete h; }
 dmg_status dmg_refresh(dmg_hier* h, const double* S, hipStream_t stream) {
   clear_error();
   if (!h || !S) return fail(DMG_ERR_INVALID_ARG, "null pointer argument");
-  return setup_impl(h, S, stream);
+  return setup_impl(h, S, stream, false);
 }
 
 dmg_status dmg_sweep(dmg_hier* h, int32_t level, int32_t kind, double* u, const double* b,
@@ -923,6 +926,20 @@ dmg_status dmg_hier_config(const dmg_hier* h, int32_t level, int32_t* bw, int32_
     if (pre_order) pre_order[k] = h->opts.pre_order[k];
     if (post_order) post_order[k] = h->opts.post_order[k];
   }
+  return DMG_OK;
+}
+
+dmg_status dmg_hier_sweep_config(const dmg_hier* h, int32_t level, int32_t kind, int32_t* bw,
+                                 int32_t* seg_h) {
+  clear_error();
+  if (!h) return fail(DMG_ERR_INVALID_ARG, "null hierarchy");
+  if (level < 0 || level >= int(h->L.size()))
+    return fail(DMG_ERR_INVALID_ARG, "level %d out of range", level);
+  if (kind != 0 && kind != 1) return fail(DMG_ERR_INVALID_ARG, "kind must be 0 or 1");
+  const bool strip = level < h->tail;
+  const StripConfig& c = kind == 0 ? h->L[level].cfg : h->L[level].cfgp;
+  if (bw) *bw = strip ? (c.wave ? 1 : c.bw) : 0;
+  if (seg_h) *seg_h = strip ? c.seg_h : 0;
   return DMG_OK;
 }
 
@@ -1020,16 +1037,18 @@ dmg_status dmg_solve(dmg_hier* h, double* u, const double* b, double rtol, int32
   }
   DMG_CHECK(launch_solve_start(pb, kReduceBlocks, h->partials, nr, h->scalars, h->scalars + slot,
                                h->flag + 4, rtol, max_iters, u, L0.n(), stream));
-  int* hs = reinterpret_cast<int*>(h->host + 8);
+  int* hs = reinterpret_cast<int*>(h->host + 8);  // device flags [0..8): pivot, -, -, -, stop, steps
   double* hsc = h->host;  // scalars [0..7]
   for (;;) {
     DMG_CHECK(run_step(h, ir ? 1 : 0, u, b, stream));
-    DMG_HIP(hipMemcpyAsync(hs, h->flag + 4, 2 * sizeof(int), hipMemcpyDeviceToHost, stream));
+    DMG_HIP(hipMemcpyAsync(hs, h->flag, 8 * sizeof(int), hipMemcpyDeviceToHost, stream));
     DMG_HIP(hipMemcpyAsync(hsc, h->scalars, 8 * sizeof(double), hipMemcpyDeviceToHost, stream));
     DMG_HIP(hipStreamSynchronize(stream));
-    if (hs[0]) break;
+    if (hs[4] || hs[0]) break;
   }
-  const int k = hs[1];
+  // a refresh does not wait for its setup: its coarsest factorisation is checked here
+  if (hs[0]) return fail(DMG_ERR_NOT_SPD, "coarsest-level Cholesky met a non-positive pivot");
+  const int k = hs[5];
   const double bn = hsc[1], rn = hsc[slot + 1];
   if (!std::isfinite(bn)) return fail(DMG_ERR_NONFINITE, "right-hand side norm is not finite");
   if (bn == 0.0) {  // u was set to 0, the solution of A u = 0

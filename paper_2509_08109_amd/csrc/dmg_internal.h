@@ -87,7 +87,7 @@ constexpr int kReduceBlocks = 1024;  // fixed partial count: reductions are orde
 constexpr int kMaxPartials = 16384;  // capacity of the partials buffer
 constexpr int kTailMaxN = 65;    // levels with max(nx, ny) <= this may run in the coarse tail
 constexpr int kMaxTail = 12;     // at most this many levels in the coarse tail
-constexpr int kSmallSetupN = 65;  // levels with max(nx, ny) <= this are set up in one workgroup
+constexpr int kSmallSetupN = 33;  // levels with max(nx, ny) <= this are set up in one workgroup
 constexpr int kMaxLevels = 32;
 constexpr int kDenseMax = 64;    // interior unknowns of a level whose sub-cycle is a dense matrix
 constexpr int kMaxHistory = 4096;
@@ -166,6 +166,22 @@ dmg_status launch_copy_pack(const double* S, double* Sd, double* Sp, size_t n, h
 template <class T>
 dmg_status launch_pack(const double* S, T* out, size_t n, hipStream_t s);
 dmg_status launch_cast(const double* in, float* out, size_t n, hipStream_t s);
+// Float32 roundings of several arrays in one launch: plain copies (pack 0: dst[v] = src[v],
+// v < n) and point-major packs of planar stencils (pack 1: dst[5 v + k] = src[k n + v]).
+struct F32Seg {
+  const double* src;
+  float* dst;
+  size_t n;
+  int pack;
+  int blocks;
+};
+constexpr int kMaxF32Segs = 48;
+struct F32Batch {
+  F32Seg seg[kMaxF32Segs];
+  int count = 0;
+  dmg_status add(const double* src, float* dst, size_t n, int pack);
+};
+dmg_status launch_f32_batch(const F32Batch& a, hipStream_t s);
 dmg_status launch_grad_K(const double* jac, const double* lam, const double* u, int nx, int ny,
                          double* dK, hipStream_t s);
 

@@ -9,6 +9,9 @@ namespace dmg {
 namespace {
 
 constexpr int kBX = 64, kBY = 4;
+// workgroup of the small-level setup: one wave per SIMD, so that the Galerkin product of a
+// coarse point keeps all its operands in registers
+constexpr int kSmallThreads = 256;
 
 // ---------------------------------------------------------------------------------------
 // Element matrices.  On cell e with widths hx, hy and reference coordinates (s,t) in [0,1]^2
@@ -221,20 +224,8 @@ __global__ __launch_bounds__(256) void k_interp(const double* __restrict__ S, in
 
 // ---------------------------------------------------------------------------------------
 // Galerkin coarse stencil A_H = P^T A P.  Coarse column (I,J) of P is supported on the fine
-// 3x3 block around (2I,2J); pw() returns its weight at fine offset (a,b) in {-1,0,1}^2.
+// 3x3 block around (2I,2J); pw9() returns its weights at the fine offsets (a,b) in {-1,0,1}^2.
 // ---------------------------------------------------------------------------------------
-__device__ __forceinline__ double pw(const double* __restrict__ P, size_t NC, int ncx, int I,
-                                     int J, int a, int b) {
-  const size_t c = size_t(J) * ncx + I;
-  if (a == 0 && b == 0) return 1.0;
-  if (b == 0) return a > 0 ? P[0 * NC + c] : P[1 * NC + c - 1];
-  if (a == 0) return b > 0 ? P[2 * NC + c] : P[3 * NC + c - ncx];
-  if (a > 0 && b > 0) return P[4 * NC + c];
-  if (a < 0 && b > 0) return P[5 * NC + c - 1];
-  if (a > 0 && b < 0) return P[6 * NC + c - ncx];
-  return P[7 * NC + c - ncx - 1];
-}
-
 // fine matrix entry A[(i,j), (i+da, j+db)]
 __device__ __forceinline__ double aentry(const double* __restrict__ S, size_t N, int nx, int i,
                                          int j, int da, int db) {
@@ -250,7 +241,27 @@ __device__ __forceinline__ double aentry(const double* __restrict__ S, size_t N,
   return S[4 * N + v + nx - 1];  // da < 0, db > 0
 }
 
+// The weights of coarse column (I, J) of P at the fine offsets (a, b) in {-1,0,1}^2, as
+// w[3 (b + 1) + (a + 1)] (the centre weight is 1).
+__device__ __forceinline__ void pw9(const double* __restrict__ P, size_t NC, int ncx, int I, int J,
+                                    double w[9]) {
+  const size_t c = size_t(J) * ncx + I;
+  w[0] = P[7 * NC + c - ncx - 1];
+  w[1] = P[3 * NC + c - ncx];
+  w[2] = P[6 * NC + c - ncx];
+  w[3] = P[1 * NC + c - 1];
+  w[4] = 1.0;
+  w[5] = P[0 * NC + c];
+  w[6] = P[5 * NC + c - 1];
+  w[7] = P[2 * NC + c];
+  w[8] = P[4 * NC + c];
+}
+
 // Coarse stencil at (I, J): planar into SH and, when SHp is given, point-major into SHp.
+// Every operand is loaded up front (the 3x3 fine stencils under the coarse point and the
+// weights of the five target columns), then the triple product is summed with compile-time
+// offsets in the order (fine point, its neighbour, target).  Zero weights and couplings add
+// exact zeros, so the sums equal those that skip them.
 __device__ __forceinline__ void rap_point(const double* __restrict__ S,
                                           const double* __restrict__ P, int nx, int ny,
                                           double* __restrict__ SH, double* __restrict__ SHp,
@@ -260,35 +271,45 @@ __device__ __forceinline__ void rap_point(const double* __restrict__ S,
   const size_t NC = size_t(ncx) * ncy;
   const size_t c = size_t(J) * ncx + I;
   // targets: C (0,0), W (-1,0), S (0,-1), SW (-1,-1), SE (1,-1)
-  const int tI[5] = {0, -1, 0, -1, 1};
-  const int tJ[5] = {0, 0, -1, -1, -1};
+  constexpr int tI[5] = {0, -1, 0, -1, 1};
+  constexpr int tJ[5] = {0, 0, -1, -1, -1};
   double acc[5] = {0, 0, 0, 0, 0};
   const bool interior = I > 0 && I < ncx - 1 && J > 0 && J < ncy - 1;
   if (interior) {
     bool live[5];
+    double wt[5][9];
 #pragma unroll
     for (int t = 0; t < 5; ++t) {
       const int I2 = I + tI[t], J2 = J + tJ[t];
       live[t] = I2 > 0 && I2 < ncx - 1 && J2 > 0 && J2 < ncy - 1;
+      // a boundary target contributes nothing: read the centre's weights in its place
+      pw9(P, NC, ncx, live[t] ? I2 : I, live[t] ? J2 : J, wt[t]);
     }
+    Nine a9[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) a9[q] = load9(S, N, nx, 2 * I + q % 3 - 1, 2 * J + q / 3 - 1);
+    // every load above is issued before any product below: one memory round trip per point
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
     for (int b1 = -1; b1 <= 1; ++b1) {
+#pragma unroll
       for (int a1 = -1; a1 <= 1; ++a1) {
-        const int fi = 2 * I + a1, fj = 2 * J + b1;
-        const double w1 = pw(P, NC, ncx, I, J, a1, b1);
-        if (w1 == 0.0) continue;
+        const double w1 = wt[0][3 * (b1 + 1) + (a1 + 1)];
+        const Nine& A = a9[3 * (b1 + 1) + (a1 + 1)];
+        const double av9[9] = {A.SW, A.S, A.SE, A.W, A.C, A.E, A.NW, A.N, A.NE};
+#pragma unroll
         for (int db = -1; db <= 1; ++db) {
+#pragma unroll
           for (int da = -1; da <= 1; ++da) {
-            const double av = aentry(S, N, nx, fi, fj, da, db);
-            if (av == 0.0) continue;
-            const double wa = w1 * av;
+            const double wa = w1 * av9[3 * (db + 1) + (da + 1)];
 #pragma unroll
             for (int t = 0; t < 5; ++t) {
-              if (!live[t]) continue;
               // offset of the fine neighbour from the target coarse point's fine position
               const int oa = a1 + da - 2 * tI[t];
               const int ob = b1 + db - 2 * tJ[t];
               if (oa < -1 || oa > 1 || ob < -1 || ob > 1) continue;
-              acc[t] += wa * pw(P, NC, ncx, I + tI[t], J + tJ[t], oa, ob);
+              const double v = acc[t] + wa * wt[t][3 * (ob + 1) + (oa + 1)];
+              acc[t] = live[t] ? v : acc[t];
             }
           }
         }
@@ -303,7 +324,9 @@ __device__ __forceinline__ void rap_point(const double* __restrict__ S,
   }
 }
 
-__global__ __launch_bounds__(256) void k_rap(const double* __restrict__ S,
+// One wave per SIMD: the ~120 operands of a coarse point stay in registers.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_rap(
+    const double* __restrict__ S,
                                              const double* __restrict__ P, int nx, int ny,
                                              double* __restrict__ SH, double* __restrict__ SHp) {
   const int I = blockIdx.x * kBX + threadIdx.x;
@@ -359,7 +382,8 @@ __device__ void coarse_factor_body(const double* __restrict__ S, int nx, int ny,
 // Setup of the small levels in one workgroup: for k = 0..nlev-2, the weights P[k] of level k and
 // the Galerkin stencil of level k+1 (planar, and point-major where Sp[k+1] is set), then the
 // Cholesky factor of the last level.
-__global__ __launch_bounds__(1024) void k_setup_small(SmallSetup a) {
+__global__ __launch_bounds__(kSmallThreads) __attribute__((amdgpu_waves_per_eu(1, 1))) void
+k_setup_small(SmallSetup a) {
   for (int k = 0; k + 1 < a.nlev; ++k) {
     const int nx = a.nx[k], ny = a.ny[k];
     const int ncx = (nx + 1) / 2, ncy = (ny + 1) / 2;
@@ -405,9 +429,48 @@ __global__ __launch_bounds__(256) void k_pack(const double* __restrict__ S, T* _
   }
 }
 
+// Several float32 roundings in one launch: workgroup b serves the segment whose block range
+// holds b (a scan over the segment table, uniform per workgroup).
+__global__ __launch_bounds__(256) void k_f32_batch(F32Batch a) {
+  int b = blockIdx.x, k = 0;
+  while (k < a.count && b >= a.seg[k].blocks) b -= a.seg[k++].blocks;
+  if (k >= a.count) return;
+  const F32Seg g = a.seg[k];
+  const size_t step = size_t(g.blocks) * blockDim.x;
+  for (size_t v = size_t(b) * blockDim.x + threadIdx.x; v < g.n; v += step) {
+    if (g.pack) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) g.dst[5 * v + c] = float(g.src[c * g.n + v]);
+    } else {
+      g.dst[v] = float(g.src[v]);
+    }
+  }
+}
+
 dim3 grid2(int nx, int ny) { return dim3((nx + kBX - 1) / kBX, (ny + kBY - 1) / kBY); }
 
 }  // namespace
+
+dmg_status F32Batch::add(const double* src, float* dst, size_t n, int pack) {
+  if (n == 0) return DMG_OK;
+  if (count >= kMaxF32Segs) return fail(DMG_ERR_INVALID_ARG, "too many float32 segments");
+  F32Seg& g = seg[count++];
+  g.src = src;
+  g.dst = dst;
+  g.n = n;
+  g.pack = pack;
+  const size_t blocks = (n + 255) / 256;
+  g.blocks = int(blocks < 2048 ? blocks : 2048);
+  return DMG_OK;
+}
+
+dmg_status launch_f32_batch(const F32Batch& a, hipStream_t s) {
+  if (a.count == 0) return DMG_OK;
+  long blocks = 0;
+  for (int k = 0; k < a.count; ++k) blocks += a.seg[k].blocks;
+  k_f32_batch<<<dim3(unsigned(blocks)), 256, 0, s>>>(a);
+  return launch_check("f32 batch");
+}
 
 dmg_status launch_assemble(const double* jac, const double* K, int nx, int ny, double* S,
                            hipStream_t s) {
@@ -436,7 +499,7 @@ dmg_status launch_rap(const double* S, const double* P, int nx, int ny, double* 
 
 dmg_status launch_setup_small(const SmallSetup& a, hipStream_t s) {
   if (a.nlev < 1 || a.nlev > kMaxTail + 1) return fail(DMG_ERR_INVALID_ARG, "small setup depth %d", a.nlev);
-  k_setup_small<<<1, 1024, 0, s>>>(a);
+  k_setup_small<<<1, kSmallThreads, 0, s>>>(a);
   return launch_check("setup_small");
 }
 
