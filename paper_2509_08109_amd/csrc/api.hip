@@ -137,7 +137,7 @@ void carve(dmg_hier& h, Arena& a, const std::vector<std::pair<int, int>>& dims,
       ny[k] = dims[top + k].second;
     }
     return std::make_pair(nlev, nlev > kMaxTail ? TailLayout{}
-                                                : tail_layout(nx, ny, nlev, mm, int(sizeof(double)), dense));
+                                                : tail_layout(nx, ny, nlev, mm, int(sizeof(double)), dense, 1));
   };
   auto fits = [&](int top) {
     const auto t = layout(top);
@@ -163,6 +163,16 @@ void carve(dmg_hier& h, Arena& a, const std::vector<std::pair<int, int>>& dims,
     if (fp32) h.tail_img32 = a.take<float>(size_t(img.r));
   }
   auto slot = [](auto* base, int off) { return base ? base + off : nullptr; };
+  h.gemv = 0;
+  h.gbasis = h.gscratch = nullptr;
+  h.gbasis32 = nullptr;
+  if (h.tail > 0 && interior(h.tail) > kDenseMax && interior(h.tail) <= kGemvMax) {
+    const size_t mm = size_t(interior(h.tail)) * interior(h.tail);
+    h.gemv = 1;
+    h.gbasis = a.take<double>(mm);
+    h.gscratch = a.take<double>(mm);
+    if (fp32) h.gbasis32 = a.take<float>(mm);
+  }
   if (h.tail_dense) {
     const size_t mm = size_t(h.tail_m) * h.tail_m;
     h.basis = h.tail > 0 ? slot(h.tail_img, img.B) : a.take<double>(mm);
@@ -234,6 +244,7 @@ struct Prec<double> {
   static double* r(const Level& L) { return L.r; }
   static const double* img(const dmg_hier& h) { return h.tail_img; }
   static const double* basis(const dmg_hier& h) { return h.basis; }
+  static const double* gbasis(const dmg_hier& h) { return h.gbasis; }
 };
 template <>
 struct Prec<float> {
@@ -248,6 +259,7 @@ struct Prec<float> {
   static float* r(const Level& L) { return L.r32; }
   static const float* img(const dmg_hier& h) { return h.tail_img32; }
   static const float* basis(const dmg_hier& h) { return h.basis32; }
+  static const float* gbasis(const dmg_hier& h) { return h.gbasis32; }
 };
 
 }  // namespace
@@ -334,6 +346,25 @@ dmg_status compute_basis(dmg_hier* h, hipStream_t s) {
   return DMG_OK;
 }
 
+// The whole-GPU dense operator of the tail's top level (when gemv): the tail's cycle from that
+// level down (with its own dense level) run on each interior unit vector, the stencils read in
+// global memory so that several runs share a CU, then transposed to row-major.
+dmg_status compute_gemv_basis(dmg_hier* h, hipStream_t s) {
+  if (!h->gemv) return DMG_OK;
+  const Level& Lt = h->L[h->tail];
+  const int m = (Lt.nx - 2) * (Lt.ny - 2);
+  TailSpec<double> sp;
+  tail_spec<double>(h, Lt.u, Lt.b, true, nullptr, &sp);
+  sp.image = nullptr;
+  sp.image_n = 0;
+  sp.unstaged = 1;
+  sp.threads = 256;
+  DMG_CHECK(launch_tail_basis(sp, h->gscratch, s));
+  DMG_CHECK(launch_transpose(h->gscratch, h->gbasis, m, s));
+  if (h->gbasis32) DMG_CHECK(launch_cast(h->gbasis, h->gbasis32, size_t(m) * m, s));
+  return DMG_OK;
+}
+
 
 // Strip-kernel colour-order parameters: row parity smoothed first and the column parity
 // smoothed first on each row parity.
@@ -352,6 +383,19 @@ dmg_status tail_launch(dmg_hier* h, T* u_top, const T* b_top, hipStream_t s, boo
   return launch_tail<T>(sp, s);
 }
 
+// The cycle from the tail's top level down: its dense operator over the whole GPU (gemv), else
+// the one-workgroup tail kernel.
+template <class T>
+dmg_status coarse_launch(dmg_hier* h, T* u_top, const T* b_top, hipStream_t s, bool u0_zero,
+                         const int* stop) {
+  using Pr = Prec<T>;
+  if (h->gemv && h->tail > 0) {
+    const Level& Lt = h->L[h->tail];
+    return launch_dense<T>(DenseArgs<T>{Pr::gbasis(*h), b_top, u_top, Lt.nx, Lt.ny, stop}, s);
+  }
+  return tail_launch<T>(h, u_top, b_top, s, u0_zero, stop);
+}
+
 // One float64 V-cycle with zebra line relaxation: unfused kernels on the levels above the coarse
 // tail (coarse levels start from u = 0; u0_zero says the same of level 0), the tail levels with
 // their line sweeps and the coarsest solve in the one-workgroup coarse kernel.
@@ -368,7 +412,7 @@ dmg_status vcycle_line(dmg_hier* h, double* u0, const double* b0, bool u0_zero, 
       DMG_CHECK(line_sweep(L, U(l), B(l), o.smoother, true, stop, s));
     DMG_CHECK(line_resid_restrict(L, h->L[l + 1], U(l), B(l), stop, s));
   }
-  DMG_CHECK(tail_launch<double>(h, U(T), B(T), s, T == 0 && u0_zero, stop));
+  DMG_CHECK(coarse_launch<double>(h, U(T), B(T), s, T == 0 && u0_zero, stop));
   for (int l = T - 1; l >= 0; --l) {
     const Level& L = h->L[l];
     DMG_CHECK(line_prolong(L, U(l + 1), U(l), stop, s));
@@ -416,7 +460,7 @@ dmg_status vcycle_impl(dmg_hier* h, T* u0, const T* b0, hipStream_t s, double* p
   }
   T* ut = h->tail == 0 ? u0 : Pr::u(h->L[h->tail]);
   const T* bt = h->tail == 0 ? b0 : Pr::b(h->L[h->tail]);
-  DMG_CHECK(tail_launch<T>(h, ut, bt, s, u0_zero, stop));
+  DMG_CHECK(coarse_launch<T>(h, ut, bt, s, u0_zero, stop));
   const T* e = ut;
   for (int l = h->tail - 1; l >= 0; --l) {
     const Level& L = h->L[l];
@@ -733,6 +777,7 @@ dmg_status setup_impl(dmg_hier* h, const double* S, hipStream_t s, bool sync) {
   if (h->opts.smoother != 0)
     for (int l = 0; l < h->tail; ++l) DMG_CHECK(line_factors(h->L[l], s));
   DMG_CHECK(compute_basis(h, s));
+  DMG_CHECK(compute_gemv_basis(h, s));
   if (!sync) return DMG_OK;
   int flag = 0;
   DMG_HIP(hipMemcpyAsync(&flag, h->flag, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -974,6 +1019,7 @@ dmg_status dmg_autotune(dmg_hier* h, double* u, const double* b, int32_t flags, 
       }
       graph_reset(h->graph);
       DMG_CHECK(compute_basis(h, stream));
+      DMG_CHECK(compute_gemv_basis(h, stream));
       float total = 0.f;
       dmg_status st = DMG_OK;
       for (int r = 0; r < std::max(1, reps / 4) && st == DMG_OK; ++r) {
@@ -1003,6 +1049,7 @@ dmg_status dmg_autotune(dmg_hier* h, double* u, const double* b, int32_t flags, 
     graph_reset(h->graph);
     clear_error();
     DMG_CHECK(compute_basis(h, stream));  // for the order kept
+    DMG_CHECK(compute_gemv_basis(h, stream));
   }
   return DMG_OK;
 }

@@ -24,10 +24,10 @@ constexpr int kNormBlocks = 64;     // workgroups per instance for the starting 
 constexpr size_t kArgAlign = 256;   // alignment of each argument list in the argument buffer
 
 struct Launch {
-  enum Kind { WAVE, TAIL, RESID, CHECK } kind;
+  enum Kind { WAVE, TAIL, DENSE, RESID, CHECK } kind;
   int mode = 0;        // WAVE: 1 pre, 2 post with prolongation, 3 post
   int count = 0;       // instances (list length)
-  int tiles_per = 0;   // WAVE: tiles per instance
+  int tiles_per = 0;   // WAVE: tiles per instance; DENSE: largest interior unknown count
   size_t off = 0;      // byte offset of the list in the device argument buffer
   size_t lds = 0;      // TAIL: LDS bytes
 };
@@ -239,26 +239,45 @@ dmg_status build_schedule(dmg_batch* bt, double* const* u, const double* const* 
       L.mode = 1;
       seq.push_back(L);
     }
-  {  // coarse tails
-    std::vector<TailArgs<double>> list(count);
+  {  // coarse tails: the one-workgroup tail kernel, or the dense operator of the tail's top
+    std::vector<TailArgs<double>> list;
+    std::vector<DenseArgs<double>> dense;
     size_t lds = 0;
+    int max_m = 0;
     for (int k = 0; k < count; ++k) {
       dmg_hier* h = bt->inst[k];
-      const int T = h->tail, nl = int(h->L.size());
+      const int T = h->tail;
+      if (h->gemv) {
+        const Level& Lt = h->L[T];
+        dense.push_back(DenseArgs<double>{h->gbasis, Lt.b, Lt.u, Lt.nx, Lt.ny, bt->state + 4 * k});
+        max_m = std::max(max_m, (Lt.nx - 2) * (Lt.ny - 2));
+        continue;
+      }
       TailSpec<double> sp;
       tail_spec<double>(h, T == 0 ? u[k] : h->L[T].u, T == 0 ? b[k] : h->L[T].b, T > 0,
                         bt->state + 4 * k, &sp);
       sp.threads = bt->tail_threads;
       size_t bytes = 0;
-      DMG_CHECK(make_tail_args<double>(sp, &list[k], &bytes));
+      list.emplace_back();
+      DMG_CHECK(make_tail_args<double>(sp, &list.back(), &bytes));
       lds = std::max(lds, bytes);
     }
-    Launch L;
-    L.kind = Launch::TAIL;
-    L.count = count;
-    L.lds = lds;
-    DMG_CHECK(put(list.data(), list.size() * sizeof(list[0]), &L.off));
-    seq.push_back(L);
+    if (!list.empty()) {
+      Launch L;
+      L.kind = Launch::TAIL;
+      L.count = int(list.size());
+      L.lds = lds;
+      DMG_CHECK(put(list.data(), list.size() * sizeof(list[0]), &L.off));
+      seq.push_back(L);
+    }
+    if (!dense.empty()) {
+      Launch L;
+      L.kind = Launch::DENSE;
+      L.count = int(dense.size());
+      L.tiles_per = max_m;
+      DMG_CHECK(put(dense.data(), dense.size() * sizeof(dense[0]), &L.off));
+      seq.push_back(L);
+    }
   }
   for (auto it = groups.rbegin(); it != groups.rend(); ++it)
     for (int s = 0; s < o.nu_post; ++s) {
@@ -318,6 +337,10 @@ dmg_status run_step(dmg_batch* bt, hipStream_t s) {
       case Launch::TAIL:
         DMG_CHECK(launch_tail_multi<double>(reinterpret_cast<const TailArgs<double>*>(p), L.count,
                                             L.lds, bt->tail_threads, s));
+        break;
+      case Launch::DENSE:
+        DMG_CHECK(launch_dense_multi<double>(reinterpret_cast<const DenseArgs<double>*>(p), L.count,
+                                             L.tiles_per, s));
         break;
       case Launch::RESID:
         DMG_CHECK(launch_resid_multi(reinterpret_cast<const NormArgs*>(p), L.count, kNormBlocks, s));

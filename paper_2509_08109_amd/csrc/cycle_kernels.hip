@@ -277,7 +277,92 @@ unsigned stride_blocks(size_t n) {
   return unsigned(b < 4096 ? (b ? b : 1) : 4096);
 }
 
+// ---- dense coarse operator ------------------------------------------------------------
+// u = B b on the interior of one coarse level (B row-major [m][m], interior unknowns in row-major
+// order of the level's interior points), boundary ring of u = 0.  One wavefront per row: lane
+// l sums the terms j = l, l + 64, ... in order, then the 64 lane sums are added by a fixed tree.
+template <class T>
+__device__ __forceinline__ void dense_rows(const DenseArgs<T>& a, int row_block) {
+  if (a.stop && *a.stop) return;
+  const int mx = a.nx - 2, m = mx * (a.ny - 2);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int i = row_block * (blockDim.x >> 6) + wave;
+  // the boundary ring, by the first workgroup
+  if (row_block == 0) {
+    const int nb = 2 * a.nx + 2 * (a.ny - 2);
+    for (int k = threadIdx.x; k < nb; k += blockDim.x) {
+      int v;
+      if (k < a.nx) v = k;
+      else if (k < 2 * a.nx) v = (a.ny - 1) * a.nx + (k - a.nx);
+      else {
+        const int r = k - 2 * a.nx;  // rows 1..ny-2, left then right
+        v = (r / 2 + 1) * a.nx + ((r & 1) ? a.nx - 1 : 0);
+      }
+      a.u[v] = T(0);
+    }
+  }
+  if (i >= m) return;
+  const T* row = a.B + size_t(i) * m;
+  T acc = T(0);
+  for (int j = lane; j < m; j += 64) acc += row[j] * a.b[(j / mx + 1) * a.nx + j % mx + 1];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) a.u[(i / mx + 1) * a.nx + i % mx + 1] = acc;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_dense(DenseArgs<T> a) {
+  dense_rows<T>(a, int(blockIdx.x));
+}
+
+// The same over many instances: workgroup g serves instance g / blocks_per.
+template <class T>
+__global__ __launch_bounds__(256) void k_dense_multi(const DenseArgs<T>* __restrict__ list,
+                                                     int blocks_per) {
+  const int inst = int(blockIdx.x) / blocks_per;
+  dense_rows<T>(list[inst], int(blockIdx.x) - inst * blocks_per);
+}
+
+// out[c][r] = in[r][c] for an n x n float64 matrix, through 64 x 64 LDS tiles.
+__global__ __launch_bounds__(256) void k_transpose(const double* __restrict__ in,
+                                                   double* __restrict__ out, int n) {
+  __shared__ double tile[64][65];
+  const int c0 = blockIdx.x * 64, r0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int r = ty; r < 64; r += 4)
+    if (r0 + r < n && c0 + tx < n) tile[r][tx] = in[size_t(r0 + r) * n + c0 + tx];
+  __syncthreads();
+  for (int c = ty; c < 64; c += 4)
+    if (c0 + c < n && r0 + tx < n) out[size_t(c0 + c) * n + r0 + tx] = tile[tx][c];
+}
+
 }  // namespace
+
+template <class T>
+dmg_status launch_dense(const DenseArgs<T>& a, hipStream_t s) {
+  const int m = (a.nx - 2) * (a.ny - 2);
+  if (m < 1 || !a.B || !a.b || !a.u) return fail(DMG_ERR_INVALID_ARG, "dense coarse operator arguments");
+  k_dense<T><<<(m + 3) / 4, 256, 0, s>>>(a);
+  return launch_check("dense");
+}
+
+template <class T>
+dmg_status launch_dense_multi(const DenseArgs<T>* list, int count, int max_m, hipStream_t s) {
+  if (count < 1) return DMG_OK;
+  const int per = (max_m + 3) / 4;
+  k_dense_multi<T><<<count * per, 256, 0, s>>>(list, per);
+  return launch_check("dense multi");
+}
+template dmg_status launch_dense<double>(const DenseArgs<double>&, hipStream_t);
+template dmg_status launch_dense<float>(const DenseArgs<float>&, hipStream_t);
+template dmg_status launch_dense_multi<double>(const DenseArgs<double>*, int, int, hipStream_t);
+
+dmg_status launch_transpose(const double* in, double* out, int n, hipStream_t s) {
+  if (n < 1) return DMG_OK;
+  const unsigned g = unsigned((n + 63) / 64);
+  k_transpose<<<dim3(g, g), 256, 0, s>>>(in, out, n);
+  return launch_check("transpose");
+}
 
 template <class T>
 dmg_status launch_copy(const T* x, T* y, size_t n, const int* stop, hipStream_t s) {

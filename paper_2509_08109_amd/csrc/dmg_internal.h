@@ -90,6 +90,8 @@ constexpr int kMaxTail = 12;     // at most this many levels in the coarse tail
 constexpr int kSmallSetupN = 33;  // levels with max(nx, ny) <= this are set up in one workgroup
 constexpr int kMaxLevels = 32;
 constexpr int kDenseMax = 64;    // interior unknowns of a level whose sub-cycle is a dense matrix
+constexpr int kGemvMax = 1024;   // ... applied inside the tail kernel; up to this many, by the
+                                 // whole GPU in place of the tail kernel
 constexpr int kMaxHistory = 4096;
 constexpr int kChunk = 4;            // solve steps per host synchronisation
 
@@ -132,6 +134,14 @@ struct dmg_hier {
   int tail_dense = 0;
   double* basis = nullptr;
   float* basis32 = nullptr;
+  // gemv: the tail's top level (a coarse level with at most kGemvMax interior unknowns) is
+  // solved by gbasis (row-major, float32 copy gbasis32), the exact linear map of the whole
+  // cycle from that level down, in one matrix-vector product over the whole GPU instead of the
+  // one-workgroup tail kernel; gscratch holds its columns while it is built
+  int gemv = 0;
+  double* gbasis = nullptr;
+  float* gbasis32 = nullptr;
+  double* gscratch = nullptr;
   dmg::Graph graph;
   ~dmg_hier();
 };
@@ -184,6 +194,23 @@ struct F32Batch {
 dmg_status launch_f32_batch(const F32Batch& a, hipStream_t s);
 dmg_status launch_grad_K(const double* jac, const double* lam, const double* u, int nx, int ny,
                          double* dK, hipStream_t s);
+
+// u = B b on the interior of one coarse level (nx x ny, m = (nx-2)(ny-2) interior unknowns in
+// row-major order, B row-major [m][m]), u = 0 on its boundary ring; a no-op once *stop is set.
+template <class T>
+struct DenseArgs {
+  const T* B;
+  const T* b;
+  T* u;
+  int nx, ny;
+  const int* stop;
+};
+template <class T>
+dmg_status launch_dense(const DenseArgs<T>& a, hipStream_t s);
+// list: device array of count instances, each with at most max_m interior unknowns
+template <class T>
+dmg_status launch_dense_multi(const DenseArgs<T>* list, int count, int max_m, hipStream_t s);
+dmg_status launch_transpose(const double* in, double* out, int n, hipStream_t s);
 
 template <class T>
 dmg_status launch_fill(T* x, T v, size_t n, hipStream_t s);
@@ -252,6 +279,7 @@ struct TailArgs {
   int oB;
   const T* Bg;        // that matrix in global memory (staged from here without an image)
   T* basis_out;       // basis run: [m0][m0] top-level interior results, one column per workgroup
+  int unstaged;       // S, P and B read in global memory (no LDS copies: more workgroups per CU)
 };
 
 // fused strip kernels (fused_kernels.hip)
@@ -294,6 +322,9 @@ struct TailSpec {
   // map of the cycle from that level down, instead of by the Cholesky factor
   int dense = 0;
   const T* B = nullptr;
+  // S, P and B are read where they are in global memory instead of being staged in LDS (the
+  // kernel then needs only the iterates, right-hand sides and scratch in LDS)
+  int unstaged = 0;
 };
 // LDS layout of the coarse-tail kernel for levels nx[0..nlev) (the last one the coarsest, with
 // m unknowns): per level S [5 n] and P [8 n_next] (not at the coarsest), u [n], b [n]; then the
@@ -306,10 +337,11 @@ struct TailLayout {
   int y = 0;
   size_t bytes = 0;
 };
-TailLayout tail_layout(const int* nx, const int* ny, int nlev, int m, int elem, int dense);
-// The dense coarse operator of a tail: one workgroup per top-level interior unknown j runs the
-// full cycle (spec: no image, not dense, zero_top) on the j-th unit vector and writes the top
-// level's interior result to out[j m0 ...].
+TailLayout tail_layout(const int* nx, const int* ny, int nlev, int m, int elem, int dense,
+                       int staged);
+// The dense operator of a tail's top level: one workgroup per top-level interior unknown j runs
+// the cycle (spec: no image, zero_top) on the j-th unit vector and writes the top level's
+// interior result to out[j m0 ...] (column j of the operator).
 dmg_status launch_tail_basis(const TailSpec<double>& spec, double* out, hipStream_t s);
 // Kernel arguments of hierarchy h's coarse tail (api.hip), the top level's iterate and
 // right-hand side at (u_top, b_top); the prepacked image is used when b_top is its top slot.

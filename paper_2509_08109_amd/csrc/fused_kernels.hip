@@ -562,7 +562,8 @@ __device__ __forceinline__ void stage_lds(T* dst, const T* src, int n, int tid, 
   for (int k = int(size_t(nv) * 16 / sizeof(T)) + tid; k < n; k += nt) dst[k] = src[k];
 }
 
-template <class T>
+// U: S, P and the dense operator are read in global memory (a.unstaged), not staged in LDS.
+template <class T, bool U>
 __device__ __forceinline__ void tail_body(const TailArgs<T>& a) {
   if (a.stop && *a.stop) return;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -574,13 +575,22 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& a) {
   const int vj = a.basis_out ? (int(blockIdx.x) / (a.L[0].nx - 2) + 1) * a.L[0].nx +
                                    int(blockIdx.x) % (a.L[0].nx - 2) + 1
                              : -1;
-  if (a.dense && !a.image)
+  if (a.dense && !a.image && !U)
     for (int k = tid; k < a.m * a.m; k += nt) sm[a.oB + k] = a.Bg[k];
+  // S, P and B in LDS, or (U) read where they are in global memory
+  auto Sl = [&](int l) -> const T* {
+    if constexpr (U) return a.L[l].S;
+    else return sm + a.oS[l];
+  };
+  auto Pl = [&](int l) -> const T* {
+    if constexpr (U) return a.L[l].P;
+    else return sm + a.oP[l];
+  };
   for (int l = 0; l < nl && !a.image; ++l) {
     const TailLevel<T>& G = a.L[l];
     const int n = G.nx * G.ny;
     T* u = sm + a.ou[l];
-    if (l + 1 < nl) {
+    if (l + 1 < nl && !U) {
       const int nc = a.L[l + 1].nx * a.L[l + 1].ny;
       T* S = sm + a.oS[l];
       T* P = sm + a.oP[l];
@@ -601,7 +611,7 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& a) {
   T* r = sm + a.o_r;
   for (int l = 0; l + 1 < nl; ++l) {
     const int nx = a.L[l].nx, ny = a.L[l].ny, N = nx * ny;
-    const T* S = sm + a.oS[l];
+    const T* S = Sl(l);
     T* u = sm + a.ou[l];
     const T* b = sm + a.ob[l];
     for (int s = 0; s < a.nu_pre; ++s) tail_smooth(a, S, u, b, r, nx, ny, true);
@@ -614,7 +624,7 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& a) {
     }
     __syncthreads();
     const int ncx = a.L[l + 1].nx, ncy = a.L[l + 1].ny, NC = ncx * ncy;
-    const T* P = sm + a.oP[l];
+    const T* P = Pl(l);
     T* bH = sm + a.ob[l + 1];
     for (int c = tid; c < NC; c += nt) {
       const int I = c % ncx, J = c / ncx;
@@ -642,7 +652,7 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& a) {
     const int cx = a.L[nl - 1].nx, cy = a.L[nl - 1].ny, mx = cx - 2, m = a.m, N = cx * cy;
     T* uc = sm + a.ou[nl - 1];
     const T* bc = sm + a.ob[nl - 1];
-    const T* B = sm + a.oB;
+    const T* B = U ? a.Bg : sm + a.oB;
     const bool corr = nl == 1 && !a.zero_top;
     T* rr = sm + a.o_r;
     if (corr) {  // this level's stencil is not staged: read it from global memory
@@ -695,8 +705,8 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& a) {
   for (int l = nl - 2; l >= 0; --l) {
     const int nx = a.L[l].nx, ny = a.L[l].ny, N = nx * ny;
     const int ncx = a.L[l + 1].nx, ncy = a.L[l + 1].ny, NC = ncx * ncy;
-    const T* S = sm + a.oS[l];
-    const T* P = sm + a.oP[l];
+    const T* S = Sl(l);
+    const T* P = Pl(l);
     const T* e = sm + a.ou[l + 1];
     T* u = sm + a.ou[l];
     const T* b = sm + a.ob[l];
@@ -736,13 +746,18 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& a) {
 
 template <class T>
 __global__ __launch_bounds__(1024) void k_tail(TailArgs<T> a) {
-  tail_body<T>(a);
+  tail_body<T, false>(a);
+}
+
+// Basis runs of a dense operator: the tail with its stencils read in global memory.
+__global__ __launch_bounds__(256) void k_tail_unstaged(TailArgs<double> a) {
+  tail_body<double, true>(a);
 }
 
 // One workgroup per instance: list[blockIdx.x] holds that instance's tail.
 template <class T>
 __global__ __launch_bounds__(1024) void k_tail_multi(const TailArgs<T>* __restrict__ list) {
-  tail_body<T>(list[blockIdx.x]);
+  tail_body<T, false>(list[blockIdx.x]);
 }
 
 }  // namespace
@@ -1245,7 +1260,8 @@ dmg_status launch_post(const StripConfig& cfg, const T* S, const T* uin, T* u, c
                                stop, s, x64);
 }
 
-TailLayout tail_layout(const int* nx, const int* ny, int nlev, int m, int elem, int dense) {
+TailLayout tail_layout(const int* nx, const int* ny, int nlev, int m, int elem, int dense,
+                       int staged) {
   TailLayout t;
   int off = 0;
   int rmax = 0;
@@ -1253,10 +1269,10 @@ TailLayout tail_layout(const int* nx, const int* ny, int nlev, int m, int elem, 
     const int n = nx[l] * ny[l];
     if (dense && l + 1 == nlev) rmax = n > rmax ? n : rmax;  // the residual of a dense top level
     if (l + 1 < nlev) {
-      t.S[l] = off;
-      off += 5 * n;
-      t.P[l] = off;
-      off += 8 * nx[l + 1] * ny[l + 1];
+      t.S[l] = staged ? off : -1;
+      off += staged ? 5 * n : 0;
+      t.P[l] = staged ? off : -1;
+      off += staged ? 8 * nx[l + 1] * ny[l + 1] : 0;
       rmax = n > rmax ? n : rmax;
     } else {
       t.S[l] = t.P[l] = -1;
@@ -1267,7 +1283,7 @@ TailLayout tail_layout(const int* nx, const int* ny, int nlev, int m, int elem, 
     off += n;
   }
   t.B = off;
-  off += dense ? m * m : 0;
+  off += (dense && staged) ? m * m : 0;
   t.r = off;
   off += rmax;
   size_t bytes = size_t(off) * elem;
@@ -1291,8 +1307,10 @@ dmg_status make_tail_args(const TailSpec<T>& spec, TailArgs<T>* out, size_t* lds
   if (spec.nlev > kMaxTail) return fail(DMG_ERR_INVALID_ARG, "tail too deep (%d)", spec.nlev);
   if (spec.dense && spec.m != (spec.nx[spec.nlev - 1] - 2) * (spec.ny[spec.nlev - 1] - 2))
     return fail(DMG_ERR_INVALID_ARG, "dense coarse operator size does not match its level");
-  const TailLayout lay =
-      tail_layout(spec.nx, spec.ny, spec.nlev, spec.m, int(sizeof(T)), spec.dense);
+  if (spec.unstaged && spec.image)
+    return fail(DMG_ERR_INVALID_ARG, "an unstaged coarse tail has no LDS image");
+  const TailLayout lay = tail_layout(spec.nx, spec.ny, spec.nlev, spec.m, int(sizeof(T)),
+                                     spec.dense, !spec.unstaged);
   if (lay.bytes > size_t(device_lds_limit()))
     return fail(DMG_ERR_INVALID_ARG, "coarse tail needs %zu bytes of LDS", lay.bytes);
   for (int l = 0; l < spec.nlev; ++l) {
@@ -1328,6 +1346,7 @@ dmg_status make_tail_args(const TailSpec<T>& spec, TailArgs<T>* out, size_t* lds
   a.oB = lay.B;
   a.Bg = spec.B;
   a.basis_out = nullptr;
+  a.unstaged = spec.unstaged;
   if (spec.dense && !spec.B) return fail(DMG_ERR_INVALID_ARG, "dense coarse tail without its matrix");
   if (spec.image) {
     if (!spec.zero_top || spec.image_n != lay.r || spec.b[0] != spec.image + lay.b[0] ||
@@ -1354,14 +1373,19 @@ dmg_status launch_tail(const TailSpec<T>& spec, hipStream_t s) {
 dmg_status launch_tail_basis(const TailSpec<double>& spec, double* out, hipStream_t s) {
   if (spec.threads < 64 || spec.threads > 1024 || spec.threads % 64)
     return fail(DMG_ERR_INVALID_ARG, "coarse tail workgroup size %d", spec.threads);
-  if (spec.dense || spec.image || !spec.zero_top || !out)
+  if (spec.image || !spec.zero_top || !out)
     return fail(DMG_ERR_INVALID_ARG, "basis run of a coarse tail: full cycle from zero only");
   TailArgs<double> a;
   size_t bytes = 0;
   DMG_CHECK(make_tail_args<double>(spec, &a, &bytes));
   a.basis_out = out;
   const int m0 = (spec.nx[0] - 2) * (spec.ny[0] - 2);
-  k_tail<double><<<m0, spec.threads, bytes, s>>>(a);
+  if (spec.unstaged) {
+    if (spec.threads > 256) return fail(DMG_ERR_INVALID_ARG, "unstaged basis runs use <= 256 threads");
+    k_tail_unstaged<<<m0, spec.threads, bytes, s>>>(a);
+  } else {
+    k_tail<double><<<m0, spec.threads, bytes, s>>>(a);
+  }
   return launch_check("tail basis");
 }
 

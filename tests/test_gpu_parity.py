@@ -506,11 +506,14 @@ def test_line_smoother_graph_and_limits(dmg):
     torch.cuda.synchronize()
     assert k_g == k_e and h_g == h_e and torch.equal(x_g, x_e)
     assert k_e <= 10                # point smoothing needs ~55 cycles here
-    # refresh recomputes the line factors: the operator doubled halves every iterate exactly
-    # (scaling by two commutes with every rounding)
+    # refresh recomputes the line factors: the operator doubled halves every iterate.  Scaling
+    # by two commutes with every rounding except the square roots of the coarsest Cholesky
+    # factor, whose rounding now reaches every cycle through the dense coarse operators: equal
+    # to a few ulps
     h.refresh(2.0 * S)
     x_2, k_2, _, _ = h.solve(b, rtol=1e-10)
-    assert k_2 == k_e and torch.equal(2.0 * x_2, x_e)
+    assert k_2 == k_e
+    assert float((2.0 * x_2 - x_e).abs().max()) <= 1e-13 * float(x_e.abs().max())
     h.close()
     with pytest.raises(dmg.DmgError):
         dmg.Hierarchy(S, smoother=3, precision=dmg.DMG_FP32_IR)
