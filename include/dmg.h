@@ -86,7 +86,14 @@ typedef struct dmg_options {
                             V-cycle stays symmetric).  Line smoothing runs unfused level by
                             level, float64 only (DMG_FP32_IR and the batch solve return
                             DMG_ERR_UNSUPPORTED); nu_pre / nu_post count whole line sweeps. */
-  int32_t reserved[5];
+  int32_t coarse_gemv;   /* 1 (default): when the coarse kernel's top level is a coarse level
+                            with at most 1024 interior unknowns (33 x 33), apply the cycle from
+                            there down as its dense matrix (built at setup) with one
+                            matrix-vector product over the whole GPU; 0: the one-workgroup
+                            coarse kernel.  The same cycle: only the rounding differs.  The
+                            batch solver always uses 0 (its instances' matrices together would
+                            cost more bandwidth than they save).                           */
+  int32_t reserved[4];
 } dmg_options;
 
 typedef struct dmg_hier dmg_hier;
@@ -162,14 +169,17 @@ dmg_status dmg_sweep(dmg_hier* h, int32_t level, int32_t kind, double* u, const 
 /* Autotuner.  flags bit 0: for every strip-kernel level pick the kernel and launch shape
  * (LDS strips of {64,128} columns, also 256 for float32, or one-wavefront strips that exchange
  * neighbour columns between lanes; segment height in {2,...,128} rows) with the lowest measured
- * time, for the pre and the post sweep separately (`reps` back-to-back launches replayed from a
- * captured graph and timed with hipEvents, so host launch overhead does not enter; float64 and,
- * for DMG_FP32_IR, float32 kernels separately), and the coarse-tail workgroup size the same
- * way -- numerically neutral.  flags bit 1: pick the colour order with the
+ * time, for the pre and the post sweep separately: first each kernel alone (`reps` back-to-back
+ * launches replayed from a captured graph and timed with hipEvents, so host launch overhead
+ * does not enter), then level by level inside whole V-cycles (graphs of max(2, reps/2)
+ * cycles); float64 and, for DMG_FP32_IR, float32 kernels separately; and the coarse-tail
+ * workgroup size -- numerically neutral.  flags bit 1: pick the colour order with the
  * lowest measured solve time among the row-separable orders whose post order is the reverse of
  * the pre order (0123/3210, 1032/2301, 2301/1032, 3210/0123) -- this changes the iterates, so
- * read the choice back with dmg_hier_config.  u is scratch (overwritten), b a right-hand side
- * of the level-0 shape.  Synchronous.  Invalidates captured graphs. */
+ * read the choice back with dmg_hier_config.  flags bit 2 (DMG_FP32_IR): pick inner_cycles in
+ * 1..4 with the lowest measured solve time to 1e-10 -- this changes the iterates (read it back
+ * with dmg_hier_inner_cycles).  u is scratch (overwritten), b a right-hand side of the level-0
+ * shape.  Synchronous.  Invalidates captured graphs. */
 dmg_status dmg_autotune(dmg_hier* h, double* u, const double* b, int32_t flags, int32_t reps,
                         hipStream_t stream);
 /* The launch shape of level `level`'s float64 pre sweep: bw = strip width in columns of the LDS
@@ -177,6 +187,8 @@ dmg_status dmg_autotune(dmg_hier* h, double* u, const double* b, int32_t flags, 
  * levels); and the colour orders in use (host arrays of 4, nullable). */
 dmg_status dmg_hier_config(const dmg_hier* h, int32_t level, int32_t* bw, int32_t* seg_h,
                            int32_t* pre_order, int32_t* post_order);
+/* The float32 cycles per refinement step in use (dmg_options.inner_cycles, or the tuner's). */
+dmg_status dmg_hier_inner_cycles(const dmg_hier* h, int32_t* inner_cycles);
 /* The launch shape of level `level`'s float64 sweep of the given kind (0 pre, 1 post; the
  * autotuner picks them separately): bw and seg_h as in dmg_hier_config. */
 dmg_status dmg_hier_sweep_config(const dmg_hier* h, int32_t level, int32_t kind, int32_t* bw,

@@ -143,11 +143,12 @@ class Hierarchy:
         _lib.check(lib().dmg_sweep(self._h, level, kind, _dev(u, shp, "u"), _dev(b, shp, "b"),
                                    _stream(self.device)))
 
-    def autotune(self, b: torch.Tensor, tiles: bool = True, colour_order: bool = False, reps: int = 10):
-        """Pick launch shapes per level (and optionally the colour order) by timing on this
-        hierarchy; returns config()."""
+    def autotune(self, b: torch.Tensor, tiles: bool = True, colour_order: bool = False, reps: int = 10,
+                 inner_cycles: bool = False):
+        """Pick launch shapes per level (and optionally the colour order, and for float32
+        refinement the float32 cycles per step) by timing on this hierarchy; returns config()."""
         u = torch.zeros((self.ny, self.nx), dtype=torch.float64, device=self.device)
-        flags = (1 if tiles else 0) | (2 if colour_order else 0)
+        flags = (1 if tiles else 0) | (2 if colour_order else 0) | (4 if inner_cycles else 0)
         _lib.check(lib().dmg_autotune(self._h, _dev(u, (self.ny, self.nx), "u"),
                                       _dev(b, (self.ny, self.nx), "b"), flags, reps, _stream(self.device)))
         return self.config()
@@ -163,8 +164,10 @@ class Hierarchy:
             out.append((int(bw.value), int(sh.value)))
             _lib.check(lib().dmg_hier_sweep_config(self._h, l, 1, C.byref(bw), C.byref(sh)))
             post_out.append((int(bw.value), int(sh.value)))
+        inner = C.c_int32()
+        _lib.check(lib().dmg_hier_inner_cycles(self._h, C.byref(inner)))
         return {"levels": out, "post_levels": post_out, "pre_order": list(pre),
-                "post_order": list(post)}
+                "post_order": list(post), "inner_cycles": int(inner.value)}
 
     # -- cycles and solves ---------------------------------------------------------------
     def vcycle(self, u: torch.Tensor, b: torch.Tensor) -> torch.Tensor:

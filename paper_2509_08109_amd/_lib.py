@@ -28,7 +28,7 @@ class Options(C.Structure):
                 ("coarsest_n", C.c_int32), ("precision", C.c_int32),
                 ("inner_cycles", C.c_int32), ("use_graph", C.c_int32),
                 ("tile_rows", C.c_int32), ("strip_kernel", C.c_int32), ("smoother", C.c_int32),
-                ("reserved", C.c_int32 * 5)]
+                ("coarse_gemv", C.c_int32), ("reserved", C.c_int32 * 4)]
 
 
 _p = C.c_void_p
@@ -52,6 +52,7 @@ SIGNATURES = {
     "dmg_autotune": (_st, [_p, _p, _p, _i32, _i32, _p]),
     "dmg_hier_config": (_st, [_p, _i32, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32)]),
     "dmg_hier_sweep_config": (_st, [_p, _i32, _i32, C.POINTER(_i32), C.POINTER(_i32)]),
+    "dmg_hier_inner_cycles": (_st, [_p, C.POINTER(_i32)]),
     "dmg_solve": (_st, [_p, _p, _p, C.c_double, _i32, C.POINTER(_i32), C.POINTER(C.c_double),
                         C.POINTER(C.c_double), _p]),
     "dmg_grad_K": (_st, [_p, _p, _p, _i32, _i32, _p, _p]),

@@ -56,6 +56,8 @@ dmg_status check_options(const dmg_options* o) {
     return fail(DMG_ERR_INVALID_ARG, "smoother must be 0 (point), 1 (x-lines), 2 (y-lines) or 3");
   if (o->smoother != 0 && o->precision != DMG_FP64)
     return fail(DMG_ERR_UNSUPPORTED, "line relaxation runs in float64 only");
+  if (o->coarse_gemv != 0 && o->coarse_gemv != 1)
+    return fail(DMG_ERR_INVALID_ARG, "coarse_gemv must be 0 or 1");
   return DMG_OK;
 }
 
@@ -166,7 +168,8 @@ void carve(dmg_hier& h, Arena& a, const std::vector<std::pair<int, int>>& dims,
   h.gemv = 0;
   h.gbasis = h.gscratch = nullptr;
   h.gbasis32 = nullptr;
-  if (h.tail > 0 && interior(h.tail) > kDenseMax && interior(h.tail) <= kGemvMax) {
+  if (o.coarse_gemv && h.tail > 0 && interior(h.tail) > kDenseMax &&
+      interior(h.tail) <= kGemvMax) {
     const size_t mm = size_t(interior(h.tail)) * interior(h.tail);
     h.gemv = 1;
     h.gbasis = a.take<double>(mm);
@@ -700,6 +703,57 @@ dmg_status tune_levels(dmg_hier* h, int reps, hipStream_t s) {
   return st;
 }
 
+// Second tuning pass, in the cycle itself: for each strip level and each sweep kind in turn,
+// every launch shape is timed as a graph of `reps` whole V-cycles (u, b of level 0) with the
+// other levels' shapes held, and the fastest is kept.  A kernel timed alone replays on data
+// that stays in the caches; inside the cycle it competes with the other levels for them, which
+// can favour another shape.
+template <class T>
+dmg_status refine_levels(dmg_hier* h, T* u, const T* b, int reps, hipStream_t s) {
+  if (h->opts.smoother != 0 || h->tail == 0) return DMG_OK;  // no fused strip sweeps to shape
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  DMG_HIP(hipEventCreate(&e0));
+  DMG_HIP(hipEventCreate(&e1));
+  dmg_status st = DMG_OK;
+  auto cycles = [&](float* ms) {
+    return time_runs([&]() { return vcycle_impl<T>(h, u, b, s); }, reps, s, e0, e1, ms);
+  };
+  for (int l = 0; l < h->tail && st == DMG_OK; ++l) {
+    Level& L = h->L[l];
+    for (int kind = 0; kind < 2 && st == DMG_OK; ++kind) {
+      StripConfig& cur = sizeof(T) == 8 ? (kind == 0 ? L.cfg : L.cfgp)
+                                        : (kind == 0 ? L.cfg32 : L.cfgp32);
+      StripConfig best = cur;
+      float best_ms = 1e30f;
+      st = cycles(&best_ms);
+      for (int bw : {1, 64, 128, 256}) {
+        if (bw == 256 && sizeof(T) == 8) continue;
+        for (int sh = 2; sh <= 128 && st == DMG_OK; sh *= 2) {
+          int ns = 0, nseg = 0;
+          StripConfig c;
+          c.wave = bw == 1;
+          c.bw = bw == 1 ? 64 : bw;
+          c.seg_h = sh;
+          if (strip_blocks(L.nx, L.ny, c.bw, sh, &ns, &nseg) > kMaxPartials) continue;
+          if (c.wave == best.wave && c.bw == best.bw && c.seg_h == best.seg_h) continue;
+          cur = c;
+          float ms = 0.f;
+          st = cycles(&ms);
+          if (st == DMG_OK && ms < best_ms) {
+            best_ms = ms;
+            best = c;
+          }
+          if (sh * 2 > L.ny + 1) break;
+        }
+      }
+      cur = best;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return st;
+}
+
 // Picks the coarse-tail workgroup size by timing the tail alone on (u_top, b_top).
 template <class T>
 dmg_status tune_tail(dmg_hier* h, T* u_top, const T* b_top, int reps, hipStream_t s) {
@@ -819,6 +873,7 @@ void dmg_default_options(dmg_options* o) {
   o->use_graph = 1;
   o->tile_rows = 0;
   o->strip_kernel = 1;
+  o->coarse_gemv = 1;
 }
 
 const char* dmg_last_error(void) { return g_err; }
@@ -974,6 +1029,13 @@ dmg_status dmg_hier_config(const dmg_hier* h, int32_t level, int32_t* bw, int32_
   return DMG_OK;
 }
 
+dmg_status dmg_hier_inner_cycles(const dmg_hier* h, int32_t* inner_cycles) {
+  clear_error();
+  if (!h || !inner_cycles) return fail(DMG_ERR_INVALID_ARG, "null pointer argument");
+  *inner_cycles = h->opts.inner_cycles;
+  return DMG_OK;
+}
+
 dmg_status dmg_hier_sweep_config(const dmg_hier* h, int32_t level, int32_t kind, int32_t* bw,
                                  int32_t* seg_h) {
   clear_error();
@@ -1002,6 +1064,14 @@ dmg_status dmg_autotune(dmg_hier* h, double* u, const double* b, int32_t flags, 
       DMG_CHECK(tune_tail<float>(h, T0.u32, T0.b32, reps, stream));
     } else {
       DMG_CHECK(tune_tail<double>(h, h->tail == 0 ? u : T0.u, h->tail == 0 ? b : T0.b, reps, stream));
+    }
+    DMG_CHECK(launch_fill<double>(u, 0.0, h->L[0].n(), stream));
+    DMG_CHECK(refine_levels<double>(h, u, b, std::max(2, reps / 2), stream));
+    if (h->opts.precision == DMG_FP32_IR) {
+      const Level& L0 = h->L[0];
+      DMG_CHECK(launch_fill<float>(L0.u32, 0.f, L0.n(), stream));
+      DMG_CHECK(launch_cast(b, L0.b32, L0.n(), stream));
+      DMG_CHECK(refine_levels<float>(h, L0.u32, L0.b32, std::max(2, reps / 2), stream));
     }
   }
   if (flags & 2) {
@@ -1050,6 +1120,42 @@ dmg_status dmg_autotune(dmg_hier* h, double* u, const double* b, int32_t flags, 
     clear_error();
     DMG_CHECK(compute_basis(h, stream));  // for the order kept
     DMG_CHECK(compute_gemv_basis(h, stream));
+  }
+  if ((flags & 4) && h->opts.precision == DMG_FP32_IR) {
+    // float32 cycles per refinement step: more cycles per float64 residual trade cheap float
+    // work against the float64 residual pass; keep the count with the fastest solve
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    DMG_HIP(hipEventCreate(&e0));
+    DMG_HIP(hipEventCreate(&e1));
+    float best_ms = 1e30f;
+    int best = h->opts.inner_cycles;
+    dmg_status st = DMG_OK;
+    for (int m = 1; m <= 4 && st == DMG_OK; ++m) {
+      h->opts.inner_cycles = m;
+      graph_reset(h->graph);
+      float total = 0.f;
+      for (int r = 0; r < 3 && st == DMG_OK; ++r) {  // the first captures the graph: untimed
+        st = launch_fill<double>(u, 0.0, h->L[0].n(), stream);
+        if (st == DMG_OK && hipEventRecord(e0, stream) != hipSuccess) st = fail(DMG_ERR_HIP, "event");
+        int32_t it = 0;
+        if (st == DMG_OK) st = dmg_solve(h, u, b, 1e-10, 500, &it, nullptr, nullptr, stream);
+        float ms = 0.f;
+        if (st == DMG_OK && (hipEventRecord(e1, stream) != hipSuccess ||
+                             hipEventSynchronize(e1) != hipSuccess ||
+                             hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+          st = fail(DMG_ERR_HIP, "event timing failed");
+        if (r > 0) total += ms;
+      }
+      if (st == DMG_OK && total < best_ms) {
+        best_ms = total;
+        best = m;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h->opts.inner_cycles = best;
+    graph_reset(h->graph);
+    if (st != DMG_OK) return st;
   }
   return DMG_OK;
 }

@@ -439,6 +439,7 @@ dmg_status dmg_batch_workspace_bytes(int32_t count, const int32_t* nx, const int
   dmg_options o;
   dmg_default_options(&o);
   if (opts) o = *opts;
+  o.coarse_gemv = 0;  // the batch runs its coarse levels in the one-workgroup coarse kernel
   if (o.smoother != 0) return fail(DMG_ERR_UNSUPPORTED, "the batch solve uses point smoothing");
   size_t total = 0;
   for (int k = 0; k < count; ++k) {
@@ -460,6 +461,7 @@ dmg_status dmg_batch_setup(int32_t count, const int32_t* nx, const int32_t* ny,
   dmg_options o;
   dmg_default_options(&o);
   if (opts) o = *opts;
+  o.coarse_gemv = 0;  // the batch runs its coarse levels in the one-workgroup coarse kernel
   if (o.smoother != 0) return fail(DMG_ERR_UNSUPPORTED, "the batch solve uses point smoothing");
   if (o.precision != DMG_FP64)
     return fail(DMG_ERR_UNSUPPORTED, "batched solves run in float64 (precision DMG_FP64)");

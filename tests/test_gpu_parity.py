@@ -350,12 +350,20 @@ def test_transfer_matches_oracle(dmg):
 
 
 def _batch_vs_single(dmg, Ss, bs, bt, us, its, rels):
+    """The batch runs its coarse levels in the one-workgroup coarse kernel: its iterates equal
+    single solves with coarse_gemv=0 bitwise, and single solves with the whole-GPU dense coarse
+    operator (the default) to rounding."""
     for S, b, u, k, r in zip(Ss, bs, us, its, rels):
-        h = dmg.Hierarchy(S)
+        h = dmg.Hierarchy(S, coarse_gemv=0)
         u1, k1, r1, _ = h.solve(b, rtol=1e-10)
         assert k == k1 and r <= 1e-10
         assert abs(r - r1) <= 1e-13 * max(r1, 1e-300) * 10
         assert torch.equal(u, u1)
+        h.close()
+        h = dmg.Hierarchy(S)
+        u2, k2, r2, _ = h.solve(b, rtol=1e-10)
+        assert k2 == k and r2 <= 1e-10
+        assert float((u2 - u).norm() / u.norm()) <= 1e-12
         h.close()
 
 

@@ -96,7 +96,7 @@ def test_workspace_sizes_scale_with_grid(dmg):
 
 @pytest.mark.parametrize("field,value", [("nu_pre", -1), ("coarsest_n", 2), ("precision", 7),
                                          ("inner_cycles", 0), ("pre_order", [0, 0, 1, 2]),
-                                         ("strip_kernel", 2)])
+                                         ("strip_kernel", 2), ("coarse_gemv", 2)])
 def test_options_validation(dmg, field, value):
     lib = dmg.lib()
     o = dmg.default_options(**{field: value})
