@@ -55,7 +55,7 @@ def run_leg(dmg, jac, K, b, steps: int, warmup: int, precision: int, inner: int 
     S = torch.empty((5, n_y, n_x), dtype=torch.float64, device=b.device)
     dmg.assemble_stencil(jac, K, out=S)
     h = dmg.Hierarchy(S, precision=precision, inner_cycles=inner)
-    # launch shapes (numerically neutral) and, for float32 refinement, the float32 cycles per
+    # launch shapes (rounding-level effect only) and, for float32 refinement, the float32 cycles per
     # refinement step (fastest solve to the same tolerance)
     info = {"tuned": h.autotune(b, tiles=True, reps=5, inner_cycles=precision == dmg.DMG_FP32_IR)}
     u = torch.zeros_like(b)

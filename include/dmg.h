@@ -76,8 +76,9 @@ typedef struct dmg_options {
   int32_t tile_rows;     /* launch-shape knob of the fused sweep kernels; 0 = built-in
                             table.  Numerically neutral.                                   */
   int32_t strip_kernel;  /* implementation of the large-level sweeps before autotuning:
-                            0 = LDS strips, 1 = one-wavefront strips (default 1).
-                            Numerically neutral.                                           */
+                            0 = LDS strips, 1 = one-wavefront strips (default 1).  The two
+                            sum the stencil terms in different orders: their iterates agree
+                            to rounding (~1e-14 relative), not bitwise.                     */
   int32_t smoother;      /* 0 = 4-colour point Gauss-Seidel (default, fused kernels);
                             zebra line Gauss-Seidel for anisotropic operators: 1 = x-lines
                             (rows), 2 = y-lines (columns), 3 = alternating x then y.  Each
@@ -173,7 +174,8 @@ dmg_status dmg_sweep(dmg_hier* h, int32_t level, int32_t kind, double* u, const 
  * launches replayed from a captured graph and timed with hipEvents, so host launch overhead
  * does not enter), then level by level inside whole V-cycles (graphs of max(2, reps/2)
  * cycles); float64 and, for DMG_FP32_IR, float32 kernels separately; and the coarse-tail
- * workgroup size -- numerically neutral.  flags bit 1: pick the colour order with the
+ * workgroup size -- launch shapes within one kernel family change no bit, a switch between
+ * the LDS and the one-wavefront strip kernels only the rounding.  flags bit 1: pick the colour order with the
  * lowest measured solve time among the row-separable orders whose post order is the reverse of
  * the pre order (0123/3210, 1032/2301, 2301/1032, 3210/0123) -- this changes the iterates, so
  * read the choice back with dmg_hier_config.  flags bit 2 (DMG_FP32_IR): pick inner_cycles in

@@ -5,8 +5,9 @@
 // Then come the coarse tails (one workgroup per instance) and the convergence checks (one
 // workgroup per instance).  Four such steps are captured in one hipGraph and replayed until
 // every instance has stopped; each instance has its own stop flag, so the tiles of converged
-// instances exit at once.  Results equal those of dmg_solve on each instance alone (the wave
-// sweeps, the tail and the check do the same arithmetic; launch shapes are numerically neutral).
+// instances exit at once.  Results equal bitwise those of dmg_solve on each instance alone with
+// one-wavefront sweeps and coarse_gemv = 0 (the wave sweeps, the tail and the check do the same
+// arithmetic, and segment heights change no bit).
 #include <algorithm>
 #include <cmath>
 #include <cstdint>

@@ -49,7 +49,8 @@ struct Arena {
   }
 };
 
-// Launch shape of the fused strip kernels on one level (numerically neutral).
+// Launch shape of the fused strip kernels on one level (bitwise neutral within one kernel
+// family; the LDS and one-wavefront families round differently).
 struct StripConfig {
   int bw = 128;     // columns (threads) per workgroup: 64, 128 or 256
   int seg_h = 32;   // rows per segment (even)

@@ -195,6 +195,23 @@ def test_launch_shape_is_numerically_neutral(dmg, tile_rows, wave):
     ref.close()
 
 
+@pytest.mark.parametrize("wave", [0, 1])
+@pytest.mark.parametrize("tile_rows", [2, 64])
+def test_launch_shape_is_numerically_neutral_fp32(dmg, tile_rows, wave):
+    """The same for the float32 sweeps of refinement (which also add into the float64
+    iterate)."""
+    prob = pb.star(513, seed=6)
+    S = dmg.assemble_stencil(dev(prob.jac), dev(prob.K))
+    b = dev(prob.b)
+    ref = dmg.Hierarchy(S, strip_kernel=wave, precision=dmg.DMG_FP32_IR)
+    u0, k0, _, _ = ref.solve(b, rtol=1e-10)
+    h = dmg.Hierarchy(S, tile_rows=tile_rows, strip_kernel=wave, precision=dmg.DMG_FP32_IR)
+    u1, k1, _, _ = h.solve(b, rtol=1e-10)
+    assert k0 == k1 and torch.equal(u0, u1)
+    h.close()
+    ref.close()
+
+
 def test_autotuned_hierarchy_matches_oracle(dmg):
     """Tuned launch shapes are numerically neutral; a tuned colour order is replayed by the
     oracle."""
