@@ -30,12 +30,14 @@ __device__ __forceinline__ void ref_grad(int a, double s, double t, double& ds, 
   }
 }
 
-// Row a of the element matrix of cell c (4 entries).
-__device__ void element_row(const double* __restrict__ jac, size_t ncell, size_t c, int a,
-                            double rx, double ry, double* row) {
+// The four rows of the element matrix of cell c (row a = node a), each accumulated over the
+// Gauss points in order; the metric of each Gauss point is formed once for all four rows.
+__device__ __forceinline__ void element_rows(const double* __restrict__ jac, size_t ncell,
+                                             size_t c, double rx, double ry, double rows[4][4]) {
   const double g0 = 0.5 - 0.28867513459481287;  // 1/2 - 1/(2 sqrt 3)
   const double g1 = 0.5 + 0.28867513459481287;
-  row[0] = row[1] = row[2] = row[3] = 0.0;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) rows[a][0] = rows[a][1] = rows[a][2] = rows[a][3] = 0.0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const double s = (q & 1) ? g1 : g0;
@@ -48,67 +50,77 @@ __device__ void element_row(const double* __restrict__ jac, size_t ncell, size_t
     const double M11 = (J22 * J22 + J12 * J12) * inv;
     const double M12 = -(J22 * J21 + J12 * J11) * inv;
     const double M22 = (J21 * J21 + J11 * J11) * inv;
-    double das, dat;
-    ref_grad(a, s, t, das, dat);
-    // M applied to the scaled gradient of phi_a: (M11 das*ry + M12 dat, M12 das + M22 dat*rx)
-    const double va = 0.25 * (M11 * das * ry + M12 * dat);
-    const double vb = 0.25 * (M12 * das + M22 * dat * rx);
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      double dbs, dbt;
-      ref_grad(b, s, t, dbs, dbt);
-      row[b] += va * dbs + vb * dbt;
+    for (int a = 0; a < 4; ++a) {
+      double das, dat;
+      ref_grad(a, s, t, das, dat);
+      // M applied to the scaled gradient of phi_a: (M11 das*ry + M12 dat, M12 das + M22 dat*rx)
+      const double va = 0.25 * (M11 * das * ry + M12 * dat);
+      const double vb = 0.25 * (M12 * das + M22 * dat * rx);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        double dbs, dbt;
+        ref_grad(b, s, t, dbs, dbt);
+        rows[a][b] += va * dbs + vb * dbt;
+      }
     }
   }
 }
 
+// The stencil of a 64 x 4 tile of vertices.  Each of the 65 x 5 cells under the tile gets its
+// element rows once, scaled by its K, in LDS (the ten entries the vertices read: row 3 of the
+// cell for its NE vertex, row 2 for the NW, row 1 for the SE, row 0 for the SW); each vertex
+// then sums the rows of its four cells in the order SW cell, SE cell, NW cell, NE cell.
+constexpr int kTileCX = kBX + 1, kTileCY = kBY + 1, kTileCells = kTileCX * kTileCY;
 __global__ __launch_bounds__(256) void k_assemble(const double* __restrict__ jac,
                                                   const double* __restrict__ K, int nx, int ny,
                                                   double* __restrict__ S) {
-  const int i = blockIdx.x * kBX + threadIdx.x;
-  const int j = blockIdx.y * kBY + threadIdx.y;
+  // g[e][c]: e = 0..3 row 3 (C, W, S, SW), 4..6 row 2 (C, S, SE), 7..8 row 1 (C, W), 9 row 0 (C)
+  __shared__ double g[10][kTileCells];
+  const int i0 = blockIdx.x * kBX, j0 = blockIdx.y * kBY;
+  const int tid = threadIdx.y * kBX + threadIdx.x;
+  const size_t ncell = size_t(nx - 1) * (ny - 1);
+  const double rx = double(ny - 1) / double(nx - 1);  // hx/hy with hx = 2/(nx-1), hy = 2/(ny-1)
+  const double ry = double(nx - 1) / double(ny - 1);  // hy/hx
+  for (int q = tid; q < kTileCells; q += kBX * kBY) {
+    const int cx = i0 - 1 + q % kTileCX, cy = j0 - 1 + q / kTileCX;
+    if (cx < 0 || cx > nx - 2 || cy < 0 || cy > ny - 2) continue;
+    const size_t c = size_t(cy) * (nx - 1) + cx;
+    double rows[4][4];
+    element_rows(jac, ncell, c, rx, ry, rows);
+    const double k = K[c];
+    g[0][q] = k * rows[3][3];
+    g[1][q] = k * rows[3][2];
+    g[2][q] = k * rows[3][1];
+    g[3][q] = k * rows[3][0];
+    g[4][q] = k * rows[2][2];
+    g[5][q] = k * rows[2][0];
+    g[6][q] = k * rows[2][1];
+    g[7][q] = k * rows[1][1];
+    g[8][q] = k * rows[1][0];
+    g[9][q] = k * rows[0][0];
+  }
+  __syncthreads();
+  const int i = i0 + threadIdx.x, j = j0 + threadIdx.y;
   if (i >= nx || j >= ny) return;
   const size_t N = size_t(nx) * ny;
   const size_t v = size_t(j) * nx + i;
   double C = 0, W = 0, So = 0, SW = 0, SE = 0;
   if (i > 0 && i < nx - 1 && j > 0 && j < ny - 1) {
-    const size_t ncell = size_t(nx - 1) * (ny - 1);
-    const double rx = double(ny - 1) / double(nx - 1);  // hx/hy with hx = 2/(nx-1), hy = 2/(ny-1)
-    const double ry = double(nx - 1) / double(ny - 1);  // hy/hx
-    double row[4];
-    // cell (i-1, j-1): v is its NE node (3)
-    {
-      const size_t c = size_t(j - 1) * (nx - 1) + (i - 1);
-      element_row(jac, ncell, c, 3, rx, ry, row);
-      const double k = K[c];
-      C += k * row[3];
-      if (i - 1 > 0) W += k * row[2];
-      if (j - 1 > 0) So += k * row[1];
-      if (i - 1 > 0 && j - 1 > 0) SW += k * row[0];
-    }
-    // cell (i, j-1): v is its NW node (2)
-    {
-      const size_t c = size_t(j - 1) * (nx - 1) + i;
-      element_row(jac, ncell, c, 2, rx, ry, row);
-      const double k = K[c];
-      C += k * row[2];
-      if (j - 1 > 0) So += k * row[0];
-      if (j - 1 > 0 && i + 1 < nx - 1) SE += k * row[1];
-    }
-    // cell (i-1, j): v is its SE node (1)
-    {
-      const size_t c = size_t(j) * (nx - 1) + (i - 1);
-      element_row(jac, ncell, c, 1, rx, ry, row);
-      const double k = K[c];
-      C += k * row[1];
-      if (i - 1 > 0) W += k * row[0];
-    }
-    // cell (i, j): v is its SW node (0)
-    {
-      const size_t c = size_t(j) * (nx - 1) + i;
-      element_row(jac, ncell, c, 0, rx, ry, row);
-      C += K[c] * row[0];
-    }
+    const int qsw = threadIdx.y * kTileCX + threadIdx.x;  // cell (i-1, j-1): v is its NE node
+    const int qse = qsw + 1;                              // cell (i, j-1): v is its NW node
+    const int qnw = qsw + kTileCX;                        // cell (i-1, j): v is its SE node
+    const int qne = qnw + 1;                              // cell (i, j): v is its SW node
+    C += g[0][qsw];
+    if (i - 1 > 0) W += g[1][qsw];
+    if (j - 1 > 0) So += g[2][qsw];
+    if (i - 1 > 0 && j - 1 > 0) SW += g[3][qsw];
+    C += g[4][qse];
+    if (j - 1 > 0) So += g[5][qse];
+    if (j - 1 > 0 && i + 1 < nx - 1) SE += g[6][qse];
+    C += g[7][qnw];
+    if (i - 1 > 0) W += g[8][qnw];
+    C += g[9][qne];
   }
   S[0 * N + v] = C;
   S[1 * N + v] = W;
@@ -117,7 +129,6 @@ __global__ __launch_bounds__(256) void k_assemble(const double* __restrict__ jac
   S[4 * N + v] = SE;
 }
 
-// dK_e = -lam_e^T G_e u_e
 __global__ __launch_bounds__(256) void k_grad_K(const double* __restrict__ jac,
                                                 const double* __restrict__ lam,
                                                 const double* __restrict__ u, int nx, int ny,
@@ -133,10 +144,11 @@ __global__ __launch_bounds__(256) void k_grad_K(const double* __restrict__ jac,
   const double uv[4] = {u[v0], u[v0 + 1], u[v0 + nx], u[v0 + nx + 1]};
   const double lv[4] = {lam[v0], lam[v0 + 1], lam[v0 + nx], lam[v0 + nx + 1]};
   double acc = 0.0;
-  double row[4];
+  double rows[4][4];
+  element_rows(jac, ncell, c, rx, ry, rows);
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
-    element_row(jac, ncell, c, a, rx, ry, row);
+    const double* row = rows[a];
     acc += lv[a] * (row[0] * uv[0] + row[1] * uv[1] + row[2] * uv[2] + row[3] * uv[3]);
   }
   dK[c] = -acc;
