@@ -780,19 +780,20 @@ dmg_status tune_tail(dmg_hier* h, T* u_top, const T* b_top, int reps, hipStream_
   return st;
 }
 
-// sync: wait for the setup and report a non-positive coarsest pivot here; otherwise the setup
-// is only enqueued and the next solve reports it.
-dmg_status setup_impl(dmg_hier* h, const double* S, hipStream_t s, bool sync) {
+// first: the hierarchy's initial setup, which zeroes the tail image, waits for the setup and
+// reports a non-positive coarsest pivot; otherwise a refresh, only enqueued (the next solve
+// reports the pivot).
+dmg_status setup_impl(dmg_hier* h, const double* S, hipStream_t s, bool first) {
   const int nl = int(h->L.size());
   // levels from first_small down run their whole setup in one single-workgroup kernel
   int first_small = nl - 1;
   while (first_small > 0 && std::max(h->L[first_small - 1].nx, h->L[first_small - 1].ny) <= kSmallSetupN &&
          nl - (first_small - 1) <= kMaxTail + 1)
     --first_small;
-  // the tail image's iterate (and unused right-hand side) slots start at zero; its S and P slots
-  // are written below
-  if (h->tail_img) DMG_CHECK(launch_fill<double>(h->tail_img, 0.0, size_t(h->tail_img_n), s));
-  if (h->tail_img32) DMG_CHECK(launch_fill<float>(h->tail_img32, 0.f, size_t(h->tail_img_n), s));
+  // the tail image's iterate (and unused right-hand side) slots are zero from the first setup
+  // on (nothing writes them; a refresh rewrites only the S, P and dense-operator slots)
+  if (first && h->tail_img) DMG_CHECK(launch_fill<double>(h->tail_img, 0.0, size_t(h->tail_img_n), s));
+  if (first && h->tail_img32) DMG_CHECK(launch_fill<float>(h->tail_img32, 0.f, size_t(h->tail_img_n), s));
   DMG_CHECK(launch_copy_pack(S, h->L[0].S, h->L[0].Sp, h->L[0].n(), s));
   for (int l = 0; l < first_small; ++l) {
     const Level& L = h->L[l];
@@ -832,7 +833,7 @@ dmg_status setup_impl(dmg_hier* h, const double* S, hipStream_t s, bool sync) {
     for (int l = 0; l < h->tail; ++l) DMG_CHECK(line_factors(h->L[l], s));
   DMG_CHECK(compute_basis(h, s));
   DMG_CHECK(compute_gemv_basis(h, s));
-  if (!sync) return DMG_OK;
+  if (!first) return DMG_OK;
   int flag = 0;
   DMG_HIP(hipMemcpyAsync(&flag, h->flag, sizeof(int), hipMemcpyDeviceToHost, s));
   DMG_HIP(hipStreamSynchronize(s));

@@ -544,10 +544,12 @@ template <class T>
 __device__ __forceinline__ void stage_lds(T* dst, const T* src, int n, int tid, int nt) {
   constexpr int K = 8;
   const int nv = int((size_t(n) * sizeof(T)) / 16);
-  const uint4* s4 = reinterpret_cast<const uint4*>(src);
-  uint4* d4 = reinterpret_cast<uint4*>(dst);
+  // a native vector type: the HIP vector struct kept the array on the stack in some callers
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  const u32x4* s4 = reinterpret_cast<const u32x4*>(src);
+  u32x4* d4 = reinterpret_cast<u32x4*>(dst);
   for (int base = tid; base < nv; base += K * nt) {
-    uint4 v[K];
+    u32x4 v[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int q = base + k * nt;
