@@ -3,12 +3,11 @@
 // A line sweep solves, for every interior line of one parity, the line's own equations exactly
 // with the unknowns of the other lines held: the tridiagonal system of the couplings along the
 // line, right-hand side b minus the couplings to the two neighbouring lines.  Lines of one parity
-// are not coupled by a 9-point stencil, so they are solved at once, one thread per line, by the
-// Thomas algorithm.  Its factors (modified super-diagonal, reciprocal pivots) depend on the
+// are not coupled by a 9-point stencil, so they are solved at once, one wavefront per line, by
+// the Thomas algorithm.  Its factors (modified super-diagonal, reciprocal pivots) depend on the
 // stencil only and are computed at setup, so a sweep is a forward pass d = (rhs - a d') / m into
-// scratch, which only reads u, and a back substitution into the line of u.  x-lines are grid rows
-// (a thread walks a row), y-lines grid columns (consecutive threads take consecutive columns, so
-// their loads coalesce).
+// scratch, which only reads u, and a back substitution into the line of u; both recurrences are
+// split over the 64 lanes of the line's wavefront through a scan of their affine maps.
 //
 // Levels above the coarse tail run these unfused kernels: sweeps, residual, restriction P^T r,
 // interpolation u += P e, sweeps in reverse order; the tail levels run in the one-workgroup
@@ -58,80 +57,107 @@ __global__ __launch_bounds__(64) void k_line_factor_y(const double* __restrict__
   }
 }
 
-// One x-line sweep: interior rows j with j % 2 == parity.  Stencil planes (planar, N = nx ny):
-// C, W, S, SW, SE; E(i,j) = W(i+1,j), N(i,j) = S(i,j+1), NE(i,j) = SW(i+1,j+1),
-// NW(i,j) = SE(i-1,j+1).  Forward: d = (rhs - W d_prev) / m with the stored 1 / m, into the
-// scratch dp (u is only read there: the neighbouring rows, so the loads run ahead of the
-// recurrence); back substitution x = d - cp x_next into the row of u.
-__global__ __launch_bounds__(64) void k_line_x(const double* __restrict__ S,
-                                               const double* __restrict__ uin,
-                                               const double* __restrict__ b,
-                                               const double* __restrict__ lf,
-                                               double* __restrict__ dp, int nx, int ny,
-                                               int parity, const int* __restrict__ stop,
-                                               double* u) {
+// One line sweep: interior lines of one parity (DIR 0: x-lines = rows j, DIR 1: y-lines =
+// columns i), one wavefront per line.  Stencil planes (planar, N = nx ny): C, W, S, SW, SE;
+// E(i,j) = W(i+1,j), N(i,j) = S(i,j+1), NE(i,j) = SW(i+1,j+1), NW(i,j) = SE(i-1,j+1).  Along a
+// line of n interior points k = 1..n, with x = b minus the couplings to the two neighbouring
+// lines, a the sub-diagonal and the stored factors cp and 1 / m, the forward recurrence is
+// pd_k = (x_k - a_k pd_{k-1}) / m_k (pd_0 = 0) and the back substitution u_k = pd_k - cp_k
+// u_{k+1} (u_n = pd_n).  Both are affine in the carried value, so lane p takes the consecutive
+// points k in [1 + p L, 1 + (p + 1) L) (L = ceil(n / 64)), composes its points' maps, a scan over
+// the 64 lanes gives every lane its incoming value, and the lane then runs the recurrence itself
+// over its points.  Lane 0's points round exactly as the sequential recurrence; a later lane's
+// starting value comes from the composed maps, whose rounding differs at the level of a few ulps.
+// dp (scratch) holds x, then pd.  u is read (neighbouring lines) and written (this line).
+template <int DIR>
+__global__ __launch_bounds__(256) void k_line_scan(const double* __restrict__ S,
+                                                   const double* uin,
+                                                   const double* __restrict__ b,
+                                                   const double* __restrict__ lf,
+                                                   double* __restrict__ dp, int nx, int ny,
+                                                   int parity, const int* __restrict__ stop,
+                                                   double* u) {
   if (halted(stop)) return;
   const size_t N = size_t(nx) * ny;
+  const int lane = int(threadIdx.x) & 63;
   const int first = parity == 0 ? 2 : 1;
-  const int j = first + 2 * int(blockIdx.x * blockDim.x + threadIdx.x);
-  if (j > ny - 2) return;
+  const int line = first + 2 * int(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  const int len = DIR == 0 ? nx : ny;     // points along a line, boundary included
+  const int count = DIR == 0 ? ny : nx;   // lines
+  if (line > count - 2) return;           // the whole wavefront
+  const int n = len - 2;
+  const int L = (n + 63) / 64;
+  const int k0 = 1 + lane * L, k1 = min(1 + (lane + 1) * L, n + 1);  // may be empty
+  const size_t step = DIR == 0 ? 1 : size_t(nx);
+  const size_t v0 = DIR == 0 ? size_t(line) * nx : size_t(line);  // point k = 0 of the line
   const double *W = S + N, *So = S + 2 * N, *SW = S + 3 * N, *SE = S + 4 * N;
-  const double *cp = lf, *im = lf + N;
-  double pd = 0.0;
-#pragma unroll 8
-  for (int i = 1; i <= nx - 2; ++i) {
-    const size_t v = size_t(j) * nx + i;
-    const double off =
-        ((((So[v] * uin[v - nx] + So[v + nx] * uin[v + nx]) + SW[v] * uin[v - nx - 1]) +
-          SE[v] * uin[v - nx + 1]) +
-         SE[v + nx - 1] * uin[v + nx - 1]) +
-        SW[v + nx + 1] * uin[v + nx + 1];
-    pd = ((b[v] - off) - W[v] * pd) * im[v];
+  const double* a = DIR == 0 ? W : So;  // coupling to the previous point of the line
+  const double* cp = lf + (DIR == 0 ? 0 : 2 * N);
+  const double* im = lf + (DIR == 0 ? N : 3 * N);
+  // forward: x into dp; this lane's map pd_out = fa + fb pd_in
+  double fa = 0.0, fb = 1.0;
+  // (the unrolled loops keep the loads of several points in flight ahead of the recurrence)
+#pragma unroll 4
+  for (int k = k0; k < k1; ++k) {
+    const size_t v = v0 + size_t(k) * step;
+    double off;
+    if (DIR == 0)
+      off = ((((So[v] * uin[v - nx] + So[v + nx] * uin[v + nx]) + SW[v] * uin[v - nx - 1]) +
+              SE[v] * uin[v - nx + 1]) +
+             SE[v + nx - 1] * uin[v + nx - 1]) +
+            SW[v + nx + 1] * uin[v + nx + 1];
+    else
+      off = ((((W[v] * uin[v - 1] + W[v + 1] * uin[v + 1]) + SW[v] * uin[v - nx - 1]) +
+              SE[v] * uin[v - nx + 1]) +
+             SE[v + nx - 1] * uin[v + nx - 1]) +
+            SW[v + nx + 1] * uin[v + nx + 1];
+    const double x = b[v] - off;
+    dp[v] = x;
+    const double av = a[v], m = im[v];
+    fa = (x - av * fa) * m;
+    fb = -(av * fb) * m;
+  }
+  // inclusive scan of the maps over the lanes (lane p after lane p - 1), then the incoming value
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const double pa = __shfl_up(fa, d, 64), pb = __shfl_up(fb, d, 64);
+    if (lane >= d) {
+      fa = fa + fb * pa;
+      fb = fb * pb;
+    }
+  }
+  double pd = __shfl_up(fa, 1, 64);
+  if (lane == 0) pd = 0.0;
+#pragma unroll 4
+  for (int k = k0; k < k1; ++k) {
+    const size_t v = v0 + size_t(k) * step;
+    pd = (dp[v] - a[v] * pd) * im[v];
     dp[v] = pd;
   }
-  double x = pd;
-  u[size_t(j) * nx + nx - 2] = x;
-#pragma unroll 8
-  for (int i = nx - 3; i >= 1; --i) {
-    const size_t v = size_t(j) * nx + i;
-    x = dp[v] - cp[v] * x;
-    u[v] = x;
+  // backward: this lane's map u_{k0} = ba + bb u_{k1} (cp of the last point taken as 0)
+  double ba = 0.0, bb = 1.0;
+#pragma unroll 4
+  for (int k = k1 - 1; k >= k0; --k) {
+    const size_t v = v0 + size_t(k) * step;
+    const double c = k == n ? 0.0 : cp[v];
+    ba = dp[v] - c * ba;
+    bb = -(c * bb);
   }
-}
-
-// One y-line sweep: interior columns i with i % 2 == parity (as the x-line sweep, along j).
-__global__ __launch_bounds__(64) void k_line_y(const double* __restrict__ S,
-                                               const double* __restrict__ uin,
-                                               const double* __restrict__ b,
-                                               const double* __restrict__ lf,
-                                               double* __restrict__ dp, int nx, int ny,
-                                               int parity, const int* __restrict__ stop,
-                                               double* u) {
-  if (halted(stop)) return;
-  const size_t N = size_t(nx) * ny;
-  const int first = parity == 0 ? 2 : 1;
-  const int i = first + 2 * int(blockIdx.x * blockDim.x + threadIdx.x);
-  if (i > nx - 2) return;
-  const double *W = S + N, *So = S + 2 * N, *SW = S + 3 * N, *SE = S + 4 * N;
-  const double *cp = lf + 2 * N, *im = lf + 3 * N;
-  double pd = 0.0;
-#pragma unroll 8
-  for (int j = 1; j <= ny - 2; ++j) {
-    const size_t v = size_t(j) * nx + i;
-    const double off =
-        ((((W[v] * uin[v - 1] + W[v + 1] * uin[v + 1]) + SW[v] * uin[v - nx - 1]) +
-          SE[v] * uin[v - nx + 1]) +
-         SE[v + nx - 1] * uin[v + nx - 1]) +
-        SW[v + nx + 1] * uin[v + nx + 1];
-    pd = ((b[v] - off) - So[v] * pd) * im[v];
-    dp[v] = pd;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const double na = __shfl_down(ba, d, 64), nb = __shfl_down(bb, d, 64);
+    if (lane + d < 64) {
+      ba = ba + bb * na;
+      bb = bb * nb;
+    }
   }
-  double x = pd;
-  u[size_t(ny - 2) * nx + i] = x;
-#pragma unroll 8
-  for (int j = ny - 3; j >= 1; --j) {
-    const size_t v = size_t(j) * nx + i;
-    x = dp[v] - cp[v] * x;
+  double x = __shfl_down(ba, 1, 64);
+  if (lane == 63) x = 0.0;
+#pragma unroll 4
+  for (int k = k1 - 1; k >= k0; --k) {
+    const size_t v = v0 + size_t(k) * step;
+    const double c = k == n ? 0.0 : cp[v];
+    x = dp[v] - c * x;
     u[v] = x;
   }
 }
@@ -241,15 +267,15 @@ dmg_status line_sweep(const Level& L, double* u, const double* b, int smoother, 
   const int n = line_sweeps(smoother, dir, par);
   for (int k = 0; k < n; ++k) {
     const int q = pre ? k : n - 1 - k;
-    // dp scratch: r (free during the sweeps)
+    // dp scratch: r (free during the sweeps); one wavefront per line, four per workgroup
     if (dir[q] == 0) {
       const int lines = (L.ny - 2 + 1) / 2;
-      k_line_x<<<(lines + 63) / 64, 64, 0, s>>>(L.S, u, b, L.lf, L.r, L.nx, L.ny, par[q], stop,
-                                                u);
+      k_line_scan<0><<<(lines + 3) / 4, 256, 0, s>>>(L.S, u, b, L.lf, L.r, L.nx, L.ny, par[q],
+                                                     stop, u);
     } else {
       const int lines = (L.nx - 2 + 1) / 2;
-      k_line_y<<<(lines + 63) / 64, 64, 0, s>>>(L.S, u, b, L.lf, L.r, L.nx, L.ny, par[q], stop,
-                                                u);
+      k_line_scan<1><<<(lines + 3) / 4, 256, 0, s>>>(L.S, u, b, L.lf, L.r, L.nx, L.ny, par[q],
+                                                     stop, u);
     }
     DMG_CHECK(launch_check("line sweep"));
   }
