@@ -123,6 +123,38 @@ def test_vcycle_iterates_match_oracle(dmg, case):
     h.close()
 
 
+@pytest.mark.parametrize("name", ["star129", "annulus65", "circle65"])
+def test_dense_coarse_operator_matches_coarse_kernel(dmg, name):
+    """The cycle below 33 x 33 applied as its dense matrix (coarse_gemv = 1, built at setup
+    from unit-vector runs) and run in the one-workgroup coarse kernel (0): the same iterates to
+    rounding, each matching the oracle per iterate; also for float32 refinement."""
+    prob = PROBLEMS[name]()
+    S_or = fem.assemble_stencil(prob.jac, prob.K, prob.nx, prob.ny)
+    orc = cycle.Oracle(boxmg.build_hierarchy(S_or))
+    b = dev(prob.b)
+    hs = [dmg.Hierarchy(dev(S_or), coarse_gemv=g) for g in (0, 1)]
+    us = [torch.zeros_like(b) for _ in hs]
+    uo = np.zeros(prob.nx * prob.ny)
+    for k in range(6):
+        for h, u in zip(hs, us):
+            h.vcycle(u, b)
+        orc.vcycle(uo, prob.b.ravel().copy())
+        for u in us:
+            assert np.linalg.norm(host(u).ravel() - uo) / np.linalg.norm(uo) <= TOL
+        assert float((us[0] - us[1]).norm() / us[1].norm()) <= 1e-13
+    for h in hs:
+        h.close()
+    xs = []
+    for g in (0, 1):
+        h = dmg.Hierarchy(dev(S_or), coarse_gemv=g, precision=dmg.DMG_FP32_IR)
+        x, k, rel, _ = h.solve(b, rtol=1e-10)
+        assert rel <= 1e-10
+        xs.append((x, k))
+        h.close()
+    assert abs(xs[0][1] - xs[1][1]) <= 1
+    assert float((xs[0][0] - xs[1][0]).norm() / xs[1][0].norm()) <= 1e-9
+
+
 def test_solve_matches_oracle(dmg, case):
     prob, S_or, levels = case
     h = dmg.Hierarchy(dev(S_or))
