@@ -122,17 +122,21 @@ __device__ __forceinline__ void check_body(const double* __restrict__ partials, 
                                            double* __restrict__ out, const double* __restrict__ sc,
                                            int* __restrict__ st, double* __restrict__ hist,
                                            int hist_cap) {
-  if (st[0]) return;
+  // every load first (the state, the scalars, the partials), so that their latencies overlap;
+  // nothing is written once the solve has stopped
+  const int stopped = st[0], steps = st[1], max_steps = st[2];
+  const double bnorm = sc[1], target = sc[6];
   double acc = 0.0;
   for (int k = threadIdx.x; k < count; k += 256) acc += partials[k];
   const double t = block_sum(acc);
+  if (stopped) return;
   if (threadIdx.x == 0) {
     out[0] = t;
     out[1] = sqrt(t);
-    const int k = st[1] + 1;
+    const int k = steps + 1;
     st[1] = k;
-    if (k <= hist_cap) hist[k - 1] = sc[1] > 0.0 ? sqrt(t) / sc[1] : sqrt(t);
-    if (!(t > sc[6]) || k >= st[2] || !isfinite(t)) st[0] = 1;
+    if (k <= hist_cap) hist[k - 1] = bnorm > 0.0 ? sqrt(t) / bnorm : sqrt(t);
+    if (!(t > target) || k >= max_steps || !isfinite(t)) st[0] = 1;
   }
 }
 
@@ -283,10 +287,20 @@ unsigned stride_blocks(size_t n) {
 // l sums the terms j = l, l + 64, ... in order, then the 64 lane sums are added by a fixed tree.
 template <class T>
 __device__ __forceinline__ void dense_rows(const DenseArgs<T>& a, int row_block) {
-  if (a.stop && *a.stop) return;
+  // the stop flag is tested after the row's loads are issued (their latencies overlap)
+  const int stopped = a.stop ? *a.stop : 0;
   const int mx = a.nx - 2, m = mx * (a.ny - 2);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int i = row_block * (blockDim.x >> 6) + wave;
+  T acc = T(0);
+  if (i < m) {
+    const T* row = a.B + size_t(i) * m;
+    for (int j = lane; j < m; j += 64) acc += row[j] * a.b[(j / mx + 1) * a.nx + j % mx + 1];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  }
+  if (stopped) return;
+  if (i < m && lane == 0) a.u[(i / mx + 1) * a.nx + i % mx + 1] = acc;
   // the boundary ring, by the first workgroup
   if (row_block == 0) {
     const int nb = 2 * a.nx + 2 * (a.ny - 2);
@@ -301,13 +315,6 @@ __device__ __forceinline__ void dense_rows(const DenseArgs<T>& a, int row_block)
       a.u[v] = T(0);
     }
   }
-  if (i >= m) return;
-  const T* row = a.B + size_t(i) * m;
-  T acc = T(0);
-  for (int j = lane; j < m; j += 64) acc += row[j] * a.b[(j / mx + 1) * a.nx + j % mx + 1];
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-  if (lane == 0) a.u[(i / mx + 1) * a.nx + i % mx + 1] = acc;
 }
 
 template <class T>

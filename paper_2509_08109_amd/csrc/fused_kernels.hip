@@ -245,7 +245,9 @@ __global__ __launch_bounds__(BW) void k_strip(StripArgs<T> a) {
   constexpr bool POST = MODE >= 2;
   constexpr int UREAD = MODE != 0 ? 1 : 0;
   constexpr bool prol = MODE == 2;
-  if (a.stop && *a.stop) return;
+  // the stop flag is tested only after the first rows' loads are issued, so that its memory
+  // latency overlaps theirs (a converged solve's kernels still exit before any write)
+  const int stopped = a.stop ? *a.stop : 0;
   extern __shared__ __align__(16) unsigned char smem[];
   T* base_l = reinterpret_cast<T*>(smem);
   LdsRing<T> L{base_l, base_l + RU * BW, base_l + (RU + RS) * BW, base_l + (RU + 2 * RS) * BW,
@@ -300,24 +302,27 @@ __global__ __launch_bounds__(BW) void k_strip(StripArgs<T> a) {
     for (int q = 0; q < 5; ++q) c.s[q][k] = T(0);
   }
   for (int k = t; k < (RU + 4 * RS) * BW; k += BW) base_l[k] = T(0);
-  __syncthreads();
-  RowRegs<T> gA0, gA1, gB0, gB1;
+  RowRegs<T> gM, gA0, gA1, gB0, gB1;
   CoarseRegs<T> cr;
-  if (active) {
-    load_row<T, UREAD>(a, i, a0 - 1, gA0);
-    if (prol && row_ok(a0 - 1)) gA0.u = gA0.u + prolong_global<T>(a, i, a0 - 1);
-    store_row<T, BW, 0>(c, L, t, gA0);
-    if (prol) {
-      load_coarse<T>(a, cI, a0, cr);
-      if (t < CW) {
-#pragma unroll
-        for (int k = 0; k < kCoarseSlots; ++k) cbuf[k * CW + t] = cr.v[k];
-      }
-    }
+  T pm = T(0);
+  if (active) {  // every load of the prologue, then their uses
+    load_row<T, UREAD>(a, i, a0 - 1, gM);
+    if (prol && row_ok(a0 - 1)) pm = prolong_global<T>(a, i, a0 - 1);
+    if (prol) load_coarse<T>(a, cI, a0, cr);
     load_row<T, UREAD>(a, i, a0, gA0);
     load_row<T, UREAD>(a, i, a0 + 1, gA1);
     load_row<T, UREAD>(a, i, live(a0 + 2), gB0);
     load_row<T, UREAD>(a, i, live(a0 + 3), gB1);
+  }
+  __syncthreads();  // the LDS rings are zero before any row is stored
+  if (stopped) return;  // the same for every thread of the workgroup
+  if (active) {
+    if (prol && row_ok(a0 - 1)) gM.u = gM.u + pm;
+    store_row<T, BW, 0>(c, L, t, gM);
+    if (prol && t < CW) {
+#pragma unroll
+      for (int k = 0; k < kCoarseSlots; ++k) cbuf[k * CW + t] = cr.v[k];
+    }
   }
   __syncthreads();
   double acc = 0.0;
@@ -567,7 +572,8 @@ __device__ __forceinline__ void stage_lds(T* dst, const T* src, int n, int tid, 
 // U: S, P and the dense operator are read in global memory (a.unstaged), not staged in LDS.
 template <class T, bool U>
 __device__ __forceinline__ void tail_body(const TailArgs<T>& a) {
-  if (a.stop && *a.stop) return;
+  // the stop flag is tested after the staging loads are issued (their latencies overlap)
+  const int stopped = a.stop ? *a.stop : 0;
   extern __shared__ __align__(16) unsigned char smem[];
   T* sm = reinterpret_cast<T*>(smem);
   const int nl = a.nlev, tid = threadIdx.x, nt = blockDim.x;
@@ -610,6 +616,7 @@ __device__ __forceinline__ void tail_body(const TailArgs<T>& a) {
     }
   }
   __syncthreads();
+  if (stopped) return;  // the same for the whole workgroup
   T* r = sm + a.o_r;
   for (int l = 0; l + 1 < nl; ++l) {
     const int nx = a.L[l].nx, ny = a.L[l].ny, N = nx * ny;
@@ -924,16 +931,21 @@ __device__ __forceinline__ void wave_tile(const StripArgs<T>& a, int tile, int p
   for (int k = 0; k < RS; ++k)
     c.C[k] = c.rC[k] = c.W[k] = c.Sv[k] = c.SW[k] = c.SE[k] = c.b[k] = c.Er[k] = c.NEr[k] =
         c.NWl[k] = c.r[k] = T(0);
-  RowRegs<T> gA0, gA1, gB0, gB1;
+  // every load of the prologue is issued before the stop flag is tested and before any of
+  // them is used, so that their memory latencies overlap
+  const int stopped = a.stop ? *a.stop : 0;
+  RowRegs<T> gM, gA0, gA1, gB0, gB1;
   CoarseRegs<T> cr;
-  load_row<T, UREAD>(a, i, a0 - 1, gA0);
-  if (prol && row_ok(a0 - 1)) gA0.u = gA0.u + prolong_global<T>(a, i, a0 - 1);
-  store_row_w<T, 0>(c, gA0);
+  load_row<T, UREAD>(a, i, a0 - 1, gM);
+  const T pm = (prol && row_ok(a0 - 1)) ? prolong_global<T>(a, i, a0 - 1) : T(0);
   if (prol) load_coarse<T>(a, cI, a0, cr);
   load_row<T, UREAD>(a, i, a0, gA0);
   load_row<T, UREAD>(a, i, a0 + 1, gA1);
   load_row<T, UREAD>(a, i, live(a0 + 2), gB0);
   load_row<T, UREAD>(a, i, live(a0 + 3), gB1);
+  if (stopped) return;
+  if (prol && row_ok(a0 - 1)) gM.u = gM.u + pm;
+  store_row_w<T, 0>(c, gM);
   double acc = 0.0;
 
   auto step = [&](auto KC, int ar, RowRegs<T>& g0, RowRegs<T>& g1) {
@@ -1033,15 +1045,15 @@ __device__ __forceinline__ void wave_tile(const StripArgs<T>& a, int tile, int p
 // MODE as k_strip; PF = row parity smoothed first.
 template <class T, int MODE, int PF>
 __global__ __launch_bounds__(64) void k_wave(StripArgs<T> a) {
-  if (a.stop && *a.stop) return;
   const int ntiles = a.nstrips * a.nsegs;
   const int per = (int(gridDim.x) + 7) >> 3;
   const int tile = (int(blockIdx.x) & 7) * per + (int(blockIdx.x) >> 3);
   if (tile >= ntiles) {
-    if (MODE >= 2 && a.partials && threadIdx.x == 0) a.partials[blockIdx.x] = 0.0;
+    if (MODE >= 2 && a.partials && threadIdx.x == 0 && !(a.stop && *a.stop))
+      a.partials[blockIdx.x] = 0.0;
     return;
   }
-  wave_tile<T, MODE, PF, MODE != 0 ? 1 : 0>(a, tile, int(blockIdx.x));
+  wave_tile<T, MODE, PF, MODE != 0 ? 1 : 0>(a, tile, int(blockIdx.x));  // tests a.stop itself
 }
 
 // The same sweep over the tiles of several instances of one level size at once: list[k] is
@@ -1056,8 +1068,7 @@ __global__ __launch_bounds__(64) void k_wave_multi(const StripArgs<T>* __restric
   if (g >= total) return;
   const int inst = g / tiles_per, tile = g - inst * tiles_per;
   const StripArgs<T> a = list[inst];
-  if (a.stop && *a.stop) return;
-  wave_tile<T, MODE, PF, MODE == 1 ? 2 : (MODE == 0 ? 0 : 1)>(a, tile, tile);
+  wave_tile<T, MODE, PF, MODE == 1 ? 2 : (MODE == 0 ? 0 : 1)>(a, tile, tile);  // tests a.stop
 }
 
 // ---- float64 residual of the refinement loop ----------------------------------------------
