@@ -21,39 +21,74 @@ namespace {
 
 __device__ __forceinline__ bool halted(const int* stop) { return stop && *stop; }
 
-// Thomas factors of the x-lines: for every interior row, walking i, the pivot m = C - W cp_prev
-// (W the sub-diagonal, the previous point's E the super-diagonal) and cp = E / m; stored as cp and
-// 1 / m.  They depend on the stencil only, so the sweeps need no divisions.
-__global__ __launch_bounds__(64) void k_line_factor_x(const double* __restrict__ S,
-                                                      double* __restrict__ lf, int nx, int ny) {
-  const size_t N = size_t(nx) * ny;
-  const int j = 1 + int(blockIdx.x * blockDim.x + threadIdx.x);
-  if (j > ny - 2) return;
-  const double *C = S, *W = S + N;
-  double pc = 0.0;
-  for (int i = 1; i <= nx - 2; ++i) {
-    const size_t v = size_t(j) * nx + i;
-    const double im = 1.0 / (C[v] - W[v] * pc);
-    pc = W[v + 1] * im;
-    lf[v] = pc;
-    lf[N + v] = im;
-  }
+// 2x2 matrix t <- t / 2^e with 2^e the power of two at or above its largest entry: an exact
+// rescaling, which leaves the ratio p / q it produces unchanged and keeps long products finite.
+__device__ __forceinline__ void rescale(double t[4]) {
+  const double mx = fmax(fmax(fabs(t[0]), fabs(t[1])), fmax(fabs(t[2]), fabs(t[3])));
+  if (!(mx > 0.0) || !isfinite(mx)) return;
+  int ex = 0;
+  (void)frexp(mx, &ex);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) t[k] = ldexp(t[k], -ex);
 }
 
-// The same along the y-lines (sub-diagonal S, super-diagonal N(i,j) = S(i,j+1)).
-__global__ __launch_bounds__(64) void k_line_factor_y(const double* __restrict__ S,
-                                                      double* __restrict__ lf, int nx, int ny) {
+// Thomas factors of every interior line (DIR 0: rows, DIR 1: columns), one wavefront per line.
+// Walking the line, the pivot is m_k = C_k - a_k cp_{k-1} (a the sub-diagonal: W along x, S
+// along y) and cp_k = e_k / m_k with e_k the super-diagonal (W or S of the next point), stored
+// as cp and 1 / m; they depend on the stencil only, so the sweeps need no divisions.  The map
+// cp_{k-1} -> cp_k is projective: with cp = p / q it is (p, q) -> (e q, C q - a p), a 2x2 matrix.
+// Lane p multiplies the matrices of its chunk of consecutive points (as in the sweeps), a scan
+// over the lanes gives each chunk its incoming cp, and the lane then runs the recurrence itself
+// over its points (lane 0 exactly as the sequential recurrence).
+template <int DIR>
+__global__ __launch_bounds__(256) void k_line_factor_scan(const double* __restrict__ S,
+                                                          double* __restrict__ lf, int nx,
+                                                          int ny) {
   const size_t N = size_t(nx) * ny;
-  const int i = 1 + int(blockIdx.x * blockDim.x + threadIdx.x);
-  if (i > nx - 2) return;
-  const double *C = S, *So = S + 2 * N;
-  double pc = 0.0;
-  for (int j = 1; j <= ny - 2; ++j) {
-    const size_t v = size_t(j) * nx + i;
-    const double im = 1.0 / (C[v] - So[v] * pc);
-    pc = So[v + nx] * im;
-    lf[2 * N + v] = pc;
-    lf[3 * N + v] = im;
+  const int lane = int(threadIdx.x) & 63;
+  const int line = 1 + int(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  const int len = DIR == 0 ? nx : ny, count = DIR == 0 ? ny : nx;
+  if (line > count - 2) return;  // the whole wavefront
+  const int n = len - 2;
+  const int L = (n + 63) / 64;
+  const int k0 = 1 + lane * L, k1 = min(1 + (lane + 1) * L, n + 1);
+  const size_t step = DIR == 0 ? 1 : size_t(nx);
+  const size_t v0 = DIR == 0 ? size_t(line) * nx : size_t(line);
+  const double* C = S;
+  const double* a = S + (DIR == 0 ? N : 2 * N);
+  double* cpo = lf + (DIR == 0 ? 0 : 2 * N);
+  double* imo = lf + (DIR == 0 ? N : 3 * N);
+  double t[4] = {1.0, 0.0, 0.0, 1.0};  // [[t0, t1], [t2, t3]] on (p, q)
+  for (int k = k0; k < k1; ++k) {
+    const size_t v = v0 + size_t(k) * step;
+    const double e = a[v + step], c = C[v], w = a[v];
+    const double n0 = e * t[2], n1 = e * t[3];
+    const double n2 = c * t[2] - w * t[0], n3 = c * t[3] - w * t[1];
+    t[0] = n0, t[1] = n1, t[2] = n2, t[3] = n3;
+    rescale(t);
+  }
+  // inclusive scan: lane p holds the product of chunks 0..p (later chunks on the left)
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    double q[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) q[k] = __shfl_up(t[k], d, 64);
+    if (lane >= d) {
+      const double n0 = t[0] * q[0] + t[1] * q[2], n1 = t[0] * q[1] + t[1] * q[3];
+      const double n2 = t[2] * q[0] + t[3] * q[2], n3 = t[2] * q[1] + t[3] * q[3];
+      t[0] = n0, t[1] = n1, t[2] = n2, t[3] = n3;
+      rescale(t);
+    }
+  }
+  // incoming (p, q): the product of the earlier chunks applied to (0, 1)
+  const double p_in = __shfl_up(t[1], 1, 64), q_in = __shfl_up(t[3], 1, 64);
+  double pc = lane == 0 ? 0.0 : p_in / q_in;
+  for (int k = k0; k < k1; ++k) {
+    const size_t v = v0 + size_t(k) * step;
+    const double im = 1.0 / (C[v] - a[v] * pc);
+    pc = a[v + step] * im;
+    cpo[v] = pc;
+    imo[v] = im;
   }
 }
 
@@ -283,9 +318,9 @@ dmg_status line_sweep(const Level& L, double* u, const double* b, int smoother, 
 }
 
 dmg_status line_factors(const Level& L, hipStream_t s) {
-  k_line_factor_x<<<(L.ny - 2 + 63) / 64, 64, 0, s>>>(L.S, L.lf, L.nx, L.ny);
+  k_line_factor_scan<0><<<(L.ny - 2 + 3) / 4, 256, 0, s>>>(L.S, L.lf, L.nx, L.ny);
   DMG_CHECK(launch_check("line factors x"));
-  k_line_factor_y<<<(L.nx - 2 + 63) / 64, 64, 0, s>>>(L.S, L.lf, L.nx, L.ny);
+  k_line_factor_scan<1><<<(L.nx - 2 + 3) / 4, 256, 0, s>>>(L.S, L.lf, L.nx, L.ny);
   return launch_check("line factors y");
 }
 
