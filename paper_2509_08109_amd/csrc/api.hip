@@ -1063,7 +1063,7 @@ dmg_status dmg_autotune(dmg_hier* h, double* u, const double* b, int32_t flags, 
     if (h->opts.precision == DMG_FP32_IR) {
       DMG_CHECK(tune_levels<float>(h, reps, stream));
       DMG_CHECK(tune_tail<float>(h, T0.u32, T0.b32, reps, stream));
-    } else {
+    } else if (!h->gemv) {  // with the dense coarse operator the tail kernel does not run
       DMG_CHECK(tune_tail<double>(h, h->tail == 0 ? u : T0.u, h->tail == 0 ? b : T0.b, reps, stream));
     }
     DMG_CHECK(launch_fill<double>(u, 0.0, h->L[0].n(), stream));

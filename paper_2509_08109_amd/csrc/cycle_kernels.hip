@@ -294,8 +294,23 @@ __device__ __forceinline__ void dense_rows(const DenseArgs<T>& a, int row_block)
   const int i = row_block * (blockDim.x >> 6) + wave;
   T acc = T(0);
   if (i < m) {
+    // all of this lane's terms (m <= kGemvMax = 16 x 64) are loaded before the first product,
+    // then summed in order j = lane, lane + 64, ...
     const T* row = a.B + size_t(i) * m;
-    for (int j = lane; j < m; j += 64) acc += row[j] * a.b[(j / mx + 1) * a.nx + j % mx + 1];
+    constexpr int kTerms = kGemvMax / 64;
+    T bv[kTerms], xv[kTerms];
+#pragma unroll
+    for (int q = 0; q < kTerms; ++q) {
+      const int j = lane + 64 * q;
+      const bool ok = j < m;
+      const int jj = ok ? j : 0;
+      bv[q] = row[jj];
+      xv[q] = a.b[(jj / mx + 1) * a.nx + jj % mx + 1];
+      if (!ok) bv[q] = xv[q] = T(0);
+    }
+#pragma unroll
+    for (int q = 0; q < kTerms; ++q)
+      if (lane + 64 * q < m) acc += bv[q] * xv[q];
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
   }
@@ -348,7 +363,8 @@ __global__ __launch_bounds__(256) void k_transpose(const double* __restrict__ in
 template <class T>
 dmg_status launch_dense(const DenseArgs<T>& a, hipStream_t s) {
   const int m = (a.nx - 2) * (a.ny - 2);
-  if (m < 1 || !a.B || !a.b || !a.u) return fail(DMG_ERR_INVALID_ARG, "dense coarse operator arguments");
+  if (m < 1 || m > kGemvMax || !a.B || !a.b || !a.u)
+    return fail(DMG_ERR_INVALID_ARG, "dense coarse operator arguments (m = %d)", m);
   k_dense<T><<<(m + 3) / 4, 256, 0, s>>>(a);
   return launch_check("dense");
 }
@@ -356,6 +372,8 @@ dmg_status launch_dense(const DenseArgs<T>& a, hipStream_t s) {
 template <class T>
 dmg_status launch_dense_multi(const DenseArgs<T>* list, int count, int max_m, hipStream_t s) {
   if (count < 1) return DMG_OK;
+  if (max_m < 1 || max_m > kGemvMax)
+    return fail(DMG_ERR_INVALID_ARG, "dense coarse operator size %d", max_m);
   const int per = (max_m + 3) / 4;
   k_dense_multi<T><<<count * per, 256, 0, s>>>(list, per);
   return launch_check("dense multi");
