@@ -172,8 +172,8 @@ dmg_status dmg_sweep(dmg_hier* h, int32_t level, int32_t kind, double* u, const 
  * neighbour columns between lanes; segment height in {2,...,128} rows) with the lowest measured
  * time, for the pre and the post sweep separately: first each kernel alone (`reps` back-to-back
  * launches replayed from a captured graph and timed with hipEvents, so host launch overhead
- * does not enter), then level by level inside whole V-cycles (graphs of max(2, reps/2)
- * cycles); float64 and, for DMG_FP32_IR, float32 kernels separately; and the coarse-tail
+ * does not enter), then level by level inside whole V-cycles (the faster of two graphs of
+ * max(4, reps) cycles); float64 and, for DMG_FP32_IR, float32 kernels separately; and the coarse-tail
  * workgroup size -- launch shapes within one kernel family change no bit, a switch between
  * the LDS and the one-wavefront strip kernels only the rounding.  flags bit 1: pick the colour order with the
  * lowest measured solve time among the row-separable orders whose post order is the reverse of
