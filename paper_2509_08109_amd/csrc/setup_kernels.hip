@@ -199,24 +199,50 @@ __device__ __forceinline__ void yline_w(const double* S, size_t N, int nx, int n
   wN = -(a.N + a.NW + a.NE) / d;
 }
 
-// Weights of coarse point (I, J) (see the layout of P in the library header).
+// Line weights from a loaded stencil, as xline_w / yline_w.
+__device__ __forceinline__ void xline_of(const Nine& a, double& wW, double& wE) {
+  const double d = a.C + a.N + a.S;
+  wW = -(a.W + a.NW + a.SW) / d;
+  wE = -(a.E + a.NE + a.SE) / d;
+}
+__device__ __forceinline__ void yline_of(const Nine& a, double& wS, double& wN) {
+  const double d = a.C + a.W + a.E;
+  wS = -(a.S + a.SW + a.SE) / d;
+  wN = -(a.N + a.NW + a.NE) / d;
+}
+
+// Weights of coarse point (I, J) (see the layout of P in the library header).  The five fine
+// stencils involved are loaded first (one memory round trip); the x-line point (2I+1, 2J) and
+// the y-line point (2I, 2J+1) also serve as the S and W neighbours of the centre point.
 __device__ __forceinline__ void interp_point(const double* __restrict__ S, int nx, int ny,
                                              double* __restrict__ P, int I, int J) {
   const int ncx = (nx + 1) / 2, ncy = (ny + 1) / 2;
   const size_t N = size_t(nx) * ny;
   const size_t NC = size_t(ncx) * ncy;
   const size_t c = size_t(J) * ncx + I;
+  const bool hasX = I < ncx - 1, hasY = J < ncy - 1, hasC = hasX && hasY;
+  // a line weight is 0 on a boundary row (x-lines) or column (y-lines)
+  const bool xa = hasX && 2 * J > 0 && 2 * J < ny - 1;   // x-line point (2I+1, 2J)
+  const bool ya = hasY && 2 * I > 0 && 2 * I < nx - 1;   // y-line point (2I, 2J+1)
+  const bool xb = hasC && 2 * J + 2 < ny - 1;            // x-line point (2I+1, 2J+2)
+  const bool yb = hasC && 2 * I + 2 < nx - 1;            // y-line point (2I+2, 2J+1)
+  // stencils not needed are read at (1, 1), an interior point, and not used
+  const Nine sxa = load9(S, N, nx, xa ? 2 * I + 1 : 1, xa ? 2 * J : 1);
+  const Nine sya = load9(S, N, nx, ya ? 2 * I : 1, ya ? 2 * J + 1 : 1);
+  const Nine sc = load9(S, N, nx, hasC ? 2 * I + 1 : 1, hasC ? 2 * J + 1 : 1);
+  const Nine sxb = load9(S, N, nx, xb ? 2 * I + 1 : 1, xb ? 2 * J + 2 : 1);
+  const Nine syb = load9(S, N, nx, yb ? 2 * I + 2 : 1, yb ? 2 * J + 1 : 1);
+  __builtin_amdgcn_sched_barrier(0);
   double w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  if (I < ncx - 1) xline_w(S, N, nx, ny, 2 * I + 1, 2 * J, w[0], w[1]);
-  if (J < ncy - 1) yline_w(S, N, nx, ny, 2 * I, 2 * J + 1, w[2], w[3]);
-  if (I < ncx - 1 && J < ncy - 1) {
-    const int i = 2 * I + 1, j = 2 * J + 1;
-    const Nine a = load9(S, N, nx, i, j);
-    double wSw, wNw, wSe, wNe, wWs, wEs, wWn, wEn;
-    yline_w(S, N, nx, ny, i - 1, j, wSw, wNw);   // W neighbour
-    yline_w(S, N, nx, ny, i + 1, j, wSe, wNe);   // E neighbour
-    xline_w(S, N, nx, ny, i, j - 1, wWs, wEs);   // S neighbour
-    xline_w(S, N, nx, ny, i, j + 1, wWn, wEn);   // N neighbour
+  if (xa) xline_of(sxa, w[0], w[1]);
+  if (ya) yline_of(sya, w[2], w[3]);
+  if (hasC) {
+    double wSe = 0, wNe = 0, wWn = 0, wEn = 0;
+    if (yb) yline_of(syb, wSe, wNe);  // E neighbour
+    if (xb) xline_of(sxb, wWn, wEn);  // N neighbour
+    // W neighbour = the y-line point, S neighbour = the x-line point
+    const double wSw = w[2], wNw = w[3], wWs = w[0], wEs = w[1];
+    const Nine& a = sc;
     w[4] = -(a.SW + a.W * wSw + a.S * wWs) / a.C;
     w[5] = -(a.SE + a.E * wSe + a.S * wEs) / a.C;
     w[6] = -(a.NW + a.W * wNw + a.N * wWn) / a.C;
