@@ -138,7 +138,8 @@ void dmg_destroy(dmg_hier* h);
  * gradient steps: the hierarchy is recomputed rather than stored).  Asynchronous: the work is
  * enqueued on `stream` and the call returns without waiting (S must stay valid until that work
  * has run); a non-positive coarsest pivot (DMG_ERR_NOT_SPD) is reported by the next dmg_solve
- * on h. */
+ * on h.  From the second consecutive call with the same S pointer and stream (use_graph), the
+ * setup is captured once into a hipGraph and replayed; it reads S's current contents. */
 dmg_status dmg_refresh(dmg_hier* h, const double* S, hipStream_t stream);
 
 /* Inspection of level l (0 = finest): dims and device pointers to its float64 stencil

@@ -858,6 +858,7 @@ dmg_status grid_vcycle(dmg_hier* h, double* u, const double* b, bool u_zero, con
 
 dmg_hier::~dmg_hier() {
   dmg::graph_reset(graph);
+  dmg::graph_reset(setup_graph);
   if (host) (void)hipHostFree(host);
 }
 
@@ -958,7 +959,39 @@ void dmg_destroy(dmg_hier* h) { delete h; }
 dmg_status dmg_refresh(dmg_hier* h, const double* S, hipStream_t stream) {
   clear_error();
   if (!h || !S) return fail(DMG_ERR_INVALID_ARG, "null pointer argument");
-  return setup_impl(h, S, stream, false);
+  // the legacy default stream cannot be captured
+  if (!h->opts.use_graph || stream == nullptr) return setup_impl(h, S, stream, false);
+  Graph& g = h->setup_graph;
+  if (g.exec && g.key_u == S && g.stream == stream) {
+    DMG_HIP(hipGraphLaunch(g.exec, stream));
+    return DMG_OK;
+  }
+  const bool again = h->last_refresh_S == S && h->last_refresh_stream == stream;
+  h->last_refresh_S = S;
+  h->last_refresh_stream = stream;
+  graph_reset(g);
+  if (!again) return setup_impl(h, S, stream, false);
+  // a second refresh from the same array: capture the setup (its ~25 small launches are
+  // otherwise paced by the host) and replay it from now on
+  DMG_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+  const dmg_status st = setup_impl(h, S, stream, false);
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(stream, &graph);
+  if (st != DMG_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return fail(DMG_ERR_HIP, "setup capture failed: %s", hipGetErrorString(e));
+  g.graph = graph;
+  e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    graph_reset(g);
+    return fail(DMG_ERR_HIP, "setup graph instantiate failed: %s", hipGetErrorString(e));
+  }
+  g.key_u = S;
+  g.stream = stream;
+  DMG_HIP(hipGraphLaunch(g.exec, stream));
+  return DMG_OK;
 }
 
 dmg_status dmg_sweep(dmg_hier* h, int32_t level, int32_t kind, double* u, const double* b,
@@ -1063,6 +1096,8 @@ dmg_status dmg_autotune(dmg_hier* h, double* u, const double* b, int32_t flags, 
   if (!h || !u || !b) return fail(DMG_ERR_INVALID_ARG, "null pointer argument");
   if (reps < 1 || reps > 1000) return fail(DMG_ERR_INVALID_ARG, "reps must be in [1,1000]");
   graph_reset(h->graph);
+  graph_reset(h->setup_graph);  // its dense-operator runs carry the colour orders
+  h->last_refresh_S = nullptr;
   if (flags & 1) {
     DMG_CHECK(tune_levels<double>(h, reps, stream));
     Level& T0 = h->L[h->tail];

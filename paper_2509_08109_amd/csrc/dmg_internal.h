@@ -144,6 +144,12 @@ struct dmg_hier {
   float* gbasis32 = nullptr;
   double* gscratch = nullptr;
   dmg::Graph graph;
+  // refresh: replayed as a captured graph from the second consecutive call with the same
+  // stencil array and stream (the first of such a run goes eagerly: capture costs more than a
+  // one-off setup)
+  dmg::Graph setup_graph;
+  const void* last_refresh_S = nullptr;
+  hipStream_t last_refresh_stream = nullptr;
   ~dmg_hier();
 };
 
