@@ -560,17 +560,21 @@ void graph_reset(Graph& g) {
   g = Graph{};
 }
 
-// Runs kChunk solve steps for (u, b) on stream s, through one captured graph when enabled.
-// The graph is re-captured when the arrays or the stream change.
-dmg_status run_step(dmg_hier* h, int kind, double* u, const double* b, hipStream_t s) {
+void reset_solve_graphs(dmg_hier* h) {
+  for (auto& g : h->graph) graph_reset(g);
+}
+
+// Runs len (1..kChunk) solve steps for (u, b) on stream s, through a captured graph when
+// enabled (one per chunk length), re-captured when the arrays or the stream change.
+dmg_status run_step(dmg_hier* h, int kind, int len, double* u, const double* b, hipStream_t s) {
   auto step = [&]() -> dmg_status {
-    for (int k = 0; k < kChunk; ++k)
+    for (int k = 0; k < len; ++k)
       DMG_CHECK(kind == 0 ? step_fp64(h, u, b, s) : step_ir(h, u, b, s));
     return DMG_OK;
   };
   // the legacy default stream cannot be captured: run eagerly there
   if (!h->opts.use_graph || s == nullptr) return step();
-  Graph& g = h->graph;
+  Graph& g = h->graph[len - 1];
   if (!(g.exec && g.key_u == u && g.key_b == b && g.stream == s && g.kind == kind)) {
     graph_reset(g);
     DMG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
@@ -857,7 +861,7 @@ dmg_status grid_vcycle(dmg_hier* h, double* u, const double* b, bool u_zero, con
 }  // namespace dmg
 
 dmg_hier::~dmg_hier() {
-  dmg::graph_reset(graph);
+  for (auto& g : graph) dmg::graph_reset(g);
   dmg::graph_reset(setup_graph);
   if (host) (void)hipHostFree(host);
 }
@@ -1095,7 +1099,7 @@ dmg_status dmg_autotune(dmg_hier* h, double* u, const double* b, int32_t flags, 
   clear_error();
   if (!h || !u || !b) return fail(DMG_ERR_INVALID_ARG, "null pointer argument");
   if (reps < 1 || reps > 1000) return fail(DMG_ERR_INVALID_ARG, "reps must be in [1,1000]");
-  graph_reset(h->graph);
+  reset_solve_graphs(h);
   graph_reset(h->setup_graph);  // its dense-operator runs carry the colour orders
   h->last_refresh_S = nullptr;
   if (flags & 1) {
@@ -1129,7 +1133,7 @@ dmg_status dmg_autotune(dmg_hier* h, double* u, const double* b, int32_t flags, 
         h->opts.pre_order[k] = cand[c][k];
         h->opts.post_order[k] = cand[c][3 - k];
       }
-      graph_reset(h->graph);
+      reset_solve_graphs(h);
       DMG_CHECK(compute_basis(h, stream));
       DMG_CHECK(compute_gemv_basis(h, stream));
       float total = 0.f;
@@ -1158,7 +1162,7 @@ dmg_status dmg_autotune(dmg_hier* h, double* u, const double* b, int32_t flags, 
         h->opts.pre_order[k] = cand[best][k];
         h->opts.post_order[k] = cand[best][3 - k];
       }
-    graph_reset(h->graph);
+    reset_solve_graphs(h);
     clear_error();
     DMG_CHECK(compute_basis(h, stream));  // for the order kept
     DMG_CHECK(compute_gemv_basis(h, stream));
@@ -1174,7 +1178,7 @@ dmg_status dmg_autotune(dmg_hier* h, double* u, const double* b, int32_t flags, 
     dmg_status st = DMG_OK;
     for (int m = 1; m <= 4 && st == DMG_OK; ++m) {
       h->opts.inner_cycles = m;
-      graph_reset(h->graph);
+      reset_solve_graphs(h);
       float total = 0.f;
       for (int r = 0; r < 3 && st == DMG_OK; ++r) {  // the first captures the graph: untimed
         st = launch_fill<double>(u, 0.0, h->L[0].n(), stream);
@@ -1196,7 +1200,7 @@ dmg_status dmg_autotune(dmg_hier* h, double* u, const double* b, int32_t flags, 
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     h->opts.inner_cycles = best;
-    graph_reset(h->graph);
+    reset_solve_graphs(h);
     if (st != DMG_OK) return st;
   }
   return DMG_OK;
@@ -1234,12 +1238,29 @@ dmg_status dmg_solve(dmg_hier* h, double* u, const double* b, double rtol, int32
                                h->flag + 4, rtol, max_iters, u, L0.n(), stream));
   int* hs = reinterpret_cast<int*>(h->host + 8);  // device flags [0..8): pivot, -, -, -, stop, steps
   double* hsc = h->host;  // scalars [0..7]
+  // Chunks of kChunk steps, except that once two synchronisations give the rate per step, a
+  // chunk is cut to the steps the rate predicts are left (a step beyond convergence still
+  // costs its launches, and the device stopping test makes any chunk length exact).
+  int len = kChunk, prev_k = -1;
+  double prev_rn = 0.0;
   for (;;) {
-    DMG_CHECK(run_step(h, ir ? 1 : 0, u, b, stream));
+    DMG_CHECK(run_step(h, ir ? 1 : 0, len, u, b, stream));
     DMG_HIP(hipMemcpyAsync(hs, h->flag, 8 * sizeof(int), hipMemcpyDeviceToHost, stream));
     DMG_HIP(hipMemcpyAsync(hsc, h->scalars, 8 * sizeof(double), hipMemcpyDeviceToHost, stream));
     DMG_HIP(hipStreamSynchronize(stream));
     if (hs[4] || hs[0]) break;
+    const int k_now = hs[5];
+    const double rn = hsc[slot + 1], target = std::sqrt(std::max(hsc[6], 0.0));
+    len = kChunk;
+    if (prev_k >= 0 && k_now > prev_k && prev_rn > 0.0 && rn > 0.0 && target > 0.0) {
+      const double rate = std::pow(rn / prev_rn, 1.0 / double(k_now - prev_k));
+      if (rate > 0.0 && rate < 0.95) {
+        const double left = std::ceil(std::log(target / rn) / std::log(rate) - 1e-9);
+        if (left >= 1.0 && left < double(kChunk)) len = int(left);
+      }
+    }
+    prev_k = k_now;
+    prev_rn = rn;
   }
   // a refresh does not wait for its setup: its coarsest factorisation is checked here
   if (hs[0]) return fail(DMG_ERR_NOT_SPD, "coarsest-level Cholesky met a non-positive pivot");

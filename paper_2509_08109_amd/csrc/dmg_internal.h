@@ -143,7 +143,7 @@ struct dmg_hier {
   double* gbasis = nullptr;
   float* gbasis32 = nullptr;
   double* gscratch = nullptr;
-  dmg::Graph graph;
+  dmg::Graph graph[dmg::kChunk];  // captured solve chunks of 1..kChunk steps
   // refresh: replayed as a captured graph from the second consecutive call with the same
   // stencil array and stream (the first of such a run goes eagerly: capture costs more than a
   // one-off setup)
