@@ -38,15 +38,18 @@ struct dmg_twolevel {
   int* flag = nullptr;  // [0] stop, [1] cycles done, [2] max cycles
   void* block = nullptr;
   double* host = nullptr;  // pinned: scalars [0..7], flags at [8..]
-  hipGraphExec_t exec = nullptr;
-  hipGraph_t graph = nullptr;
-  hipStream_t graph_stream = nullptr;
+  // captured chunks of 1..kChunk cycles
+  hipGraphExec_t exec[dmg::kChunk] = {};
+  hipGraph_t graph[dmg::kChunk] = {};
+  hipStream_t graph_stream[dmg::kChunk] = {};
   void reset_graph() {
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    exec = nullptr;
-    graph = nullptr;
-    graph_stream = nullptr;
+    for (int k = 0; k < dmg::kChunk; ++k) {
+      if (exec[k]) (void)hipGraphExecDestroy(exec[k]);
+      if (graph[k]) (void)hipGraphDestroy(graph[k]);
+      exec[k] = nullptr;
+      graph[k] = nullptr;
+      graph_stream[k] = nullptr;
+    }
   }
   ~dmg_twolevel() {
     reset_graph();
@@ -319,14 +322,19 @@ dmg_status step(dmg_twolevel* tl, hipStream_t s) {
                            kMaxHistory, s);
 }
 
-dmg_status run_chunk(dmg_twolevel* tl, hipStream_t s) {
+// len (1..kChunk) cycles, through the captured graph of that chunk length.
+dmg_status run_chunk(dmg_twolevel* tl, int len, hipStream_t s) {
   auto chunk = [&]() -> dmg_status {
-    for (int k = 0; k < kChunk; ++k) DMG_CHECK(step(tl, s));
+    for (int k = 0; k < len; ++k) DMG_CHECK(step(tl, s));
     return DMG_OK;
   };
   if (s == nullptr) return chunk();  // the legacy default stream cannot be captured
-  if (!(tl->exec && tl->graph_stream == s)) {
-    tl->reset_graph();
+  const int q = len - 1;
+  if (!(tl->exec[q] && tl->graph_stream[q] == s)) {
+    if (tl->exec[q]) (void)hipGraphExecDestroy(tl->exec[q]);
+    if (tl->graph[q]) (void)hipGraphDestroy(tl->graph[q]);
+    tl->exec[q] = nullptr;
+    tl->graph[q] = nullptr;
     DMG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     const dmg_status st = chunk();
     hipGraph_t g = nullptr;
@@ -336,15 +344,15 @@ dmg_status run_chunk(dmg_twolevel* tl, hipStream_t s) {
       return st;
     }
     if (e != hipSuccess) return fail(DMG_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
-    tl->graph = g;
-    e = hipGraphInstantiate(&tl->exec, g, nullptr, nullptr, 0);
+    tl->graph[q] = g;
+    e = hipGraphInstantiate(&tl->exec[q], g, nullptr, nullptr, 0);
     if (e != hipSuccess) {
       tl->reset_graph();
       return fail(DMG_ERR_HIP, "graph instantiate failed: %s", hipGetErrorString(e));
     }
-    tl->graph_stream = s;
+    tl->graph_stream[q] = s;
   }
-  DMG_HIP(hipGraphLaunch(tl->exec, s));
+  DMG_HIP(hipGraphLaunch(tl->exec[q], s));
   return DMG_OK;
 }
 
@@ -591,12 +599,28 @@ dmg_status dmg_twolevel_solve(dmg_twolevel* tl, double* u_p, const double* f_p, 
   DMG_CHECK(launch_check("two-level start"));
   int* hs = reinterpret_cast<int*>(tl->host + 8);
   double* hsc = tl->host;
+  // chunks of kChunk cycles; once two synchronisations give the rate per cycle, a chunk is cut
+  // to the cycles that rate predicts are left (the device test stops at the exact cycle anyway)
+  int len = kChunk, prev_k = -1;
+  double prev_rn = 0.0;
   for (;;) {
-    DMG_CHECK(run_chunk(tl, stream));
+    DMG_CHECK(run_chunk(tl, len, stream));
     DMG_HIP(hipMemcpyAsync(hs, tl->flag, 2 * sizeof(int), hipMemcpyDeviceToHost, stream));
     DMG_HIP(hipMemcpyAsync(hsc, tl->scal, 8 * sizeof(double), hipMemcpyDeviceToHost, stream));
     DMG_HIP(hipStreamSynchronize(stream));
     if (hs[0]) break;
+    const int k_now = hs[1];
+    const double rn = hsc[3], target = std::sqrt(std::max(hsc[6], 0.0));
+    len = kChunk;
+    if (prev_k >= 0 && k_now > prev_k && prev_rn > 0.0 && rn > 0.0 && target > 0.0) {
+      const double rate = std::pow(rn / prev_rn, 1.0 / double(k_now - prev_k));
+      if (rate > 0.0 && rate < 0.95) {
+        const double left = std::ceil(std::log(target / rn) / std::log(rate) - 1e-9);
+        if (left >= 1.0 && left < double(kChunk)) len = int(left);
+      }
+    }
+    prev_k = k_now;
+    prev_rn = rn;
   }
   k_tl_scatter<<<nb, 256, 0, stream>>>(tl->u, tl->t->perm, u_p, n);
   DMG_CHECK(launch_check("two-level scatter"));
