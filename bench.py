@@ -558,6 +558,17 @@ def main():
     calib_dst = torch.empty_like(calib)
     torch.mul(calib, 1.0, out=calib_dst)
     torch.cuda.synchronize()
+    # its rate, reported beside the roofline as context: what a plain streaming kernel sustains
+    # on this GPU (the roofline's peak stays the published figure)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(3):
+        torch.mul(calib, 1.0, out=calib_dst)
+    ev0.record(stream)
+    for _ in range(20):
+        torch.mul(calib, 1.0, out=calib_dst)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    stream_gbs = 2 * calib.numel() * 8 * 20 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
     del calib, calib_dst
 
     log(f"generating the {args.n}x{args.n} star workload")
@@ -595,6 +606,8 @@ def main():
                          "rel_err_vs_fp64_solution": err32,
                          "speedup_vs_fp64": round(i64["wall_s"] / i32["wall_s"], 3)},
         "roofline": roof,
+        "stream_reference": {"kernel": "torch.mul, float64, 512 MiB read + 512 MiB written",
+                             "gbs": round(stream_gbs, 1), "frac_of_peak": round(stream_gbs / HBM_PEAK_GBS, 4)},
     }
     del jac, K, b, u, u64, x32
     torch.cuda.empty_cache()

@@ -6,8 +6,9 @@
 //
 // Setup (host, once per mesh): A_p = sum_t K_t G_t with G_t the P1 element stiffness on the
 // physical triangle (Dirichlet rows and columns replaced by the identity); colours by a greedy
-// pass over the vertices in the caller's index order on the mesh graph (unknowns sharing a
-// triangle are neighbours; Dirichlet vertices have none); internal vertex order colour-major,
+// pass over the mesh graph (unknowns sharing a triangle are neighbours; Dirichlet vertices have
+// none) in smallest-last order, which needs fewer colours, and so fewer sequential passes per
+// sweep, than the caller's index order; internal vertex order colour-major,
 // each colour in the grid-cell order of the transfers, so one colour is one contiguous row range.
 // The transfers (C, C^T, M_p) are built in the same internal order.
 //
@@ -17,6 +18,7 @@
 // every kernel of the chunk is a no-op once it has stopped the solve.
 #include <algorithm>
 #include <cmath>
+#include <set>
 
 #include "mesh_internal.h"
 
@@ -414,23 +416,104 @@ void assemble_A(const Mesh& m, const double* K_t, Csr& off, std::vector<double>&
   });
 }
 
-// Greedy colours on the mesh graph, vertices in the caller's index order.
-std::vector<int> greedy_colours(const Mesh& m) {
-  std::vector<int> col(m.nv, -1);
-  std::vector<int> mark;  // mark[c] == v: colour c is taken by a neighbour of v
-  for (int v = 0; v < m.nv; ++v) {
-    if (!m.dof[v]) {
-      col[v] = 0;
-      continue;
+// The smallest member of a set of indices in [0, n): a three-level bit tree (insert, erase
+// and first in a few word operations).
+struct MinSet {
+  std::vector<uint64_t> w0, w1, w2;
+  int count = 0;
+  void init(int n) {
+    w0.assign((size_t(n) + 63) / 64, 0);
+    w1.assign((w0.size() + 63) / 64, 0);
+    w2.assign((w1.size() + 63) / 64, 0);
+  }
+  void insert(int v) {
+    const size_t i0 = size_t(v) >> 6, i1 = i0 >> 6;
+    if (!w0[i0]) {
+      if (!w1[i1]) w2[i1 >> 6] |= uint64_t(1) << (i1 & 63);
+      w1[i1] |= uint64_t(1) << (i0 & 63);
     }
-    for (int k = m.vt_ptr[v]; k < m.vt_ptr[v + 1]; ++k) {
-      const int* tv = m.tris + 3 * m.vt[k];
-      for (int b = 0; b < 3; ++b) {
-        const int w = tv[b];
-        if (w == v || !m.dof[w] || col[w] < 0) continue;
-        if (col[w] >= int(mark.size())) mark.resize(col[w] + 1, -1);
-        mark[col[w]] = v;
+    w0[i0] |= uint64_t(1) << (v & 63);
+    ++count;
+  }
+  void erase(int v) {
+    const size_t i0 = size_t(v) >> 6, i1 = i0 >> 6;
+    w0[i0] &= ~(uint64_t(1) << (v & 63));
+    if (!w0[i0]) {
+      w1[i1] &= ~(uint64_t(1) << (i0 & 63));
+      if (!w1[i1]) w2[i1 >> 6] &= ~(uint64_t(1) << (i1 & 63));
+    }
+    --count;
+  }
+  int first() const {
+    for (size_t k = 0; k < w2.size(); ++k)
+      if (w2[k]) {
+        const size_t i1 = k * 64 + size_t(__builtin_ctzll(w2[k]));
+        const size_t i0 = i1 * 64 + size_t(__builtin_ctzll(w1[i1]));
+        return int(i0 * 64 + size_t(__builtin_ctzll(w0[i0])));
       }
+    return -1;
+  }
+};
+
+// Greedy colours on the mesh graph in smallest-last order (Matula and Beck): the vertices are
+// taken out one at a time, each of least degree among those left (counting only neighbours
+// still left; the smallest index among equals), and coloured in the reverse order, each with
+// the smallest colour no coloured neighbour has.  A graph in which every subgraph has a vertex
+// of degree <= d gets at most d + 1 colours this way (6 for a planar mesh graph).  The graph is
+// the pattern of A_p's off-diagonal part (every coupling of unknowns sharing a triangle is
+// stored, even one that sums to zero); Dirichlet vertices are isolated and take colour 0.
+// Vertices wait in one index set per degree below kLowDeg, and in an ordered set of
+// (degree, index) above it.
+std::vector<int> greedy_colours(int nv, const Csr& g) {
+  constexpr int kLowDeg = 32;
+  std::vector<int> deg(nv);
+  std::vector<MinSet> bucket(kLowDeg);
+  std::set<int64_t> high;
+  auto put = [&](int v) {
+    if (deg[v] < kLowDeg) {
+      if (bucket[deg[v]].w0.empty()) bucket[deg[v]].init(nv);
+      bucket[deg[v]].insert(v);
+    } else {
+      high.insert((int64_t(deg[v]) << 32) | int64_t(v));
+    }
+  };
+  auto take = [&](int v) {
+    if (deg[v] < kLowDeg) bucket[deg[v]].erase(v);
+    else high.erase((int64_t(deg[v]) << 32) | int64_t(v));
+  };
+  for (int v = 0; v < nv; ++v) {
+    deg[v] = g.rp[v + 1] - g.rp[v];
+    put(v);
+  }
+  std::vector<char> gone(nv, 0);
+  std::vector<int> removed;
+  removed.reserve(nv);
+  int dmin = 0;  // no vertex left has a smaller degree
+  for (int step = 0; step < nv; ++step) {
+    while (dmin < kLowDeg && bucket[dmin].count == 0) ++dmin;
+    const int v = dmin < kLowDeg ? bucket[dmin].first() : int(*high.begin() & 0xffffffff);
+    take(v);
+    gone[v] = 1;
+    removed.push_back(v);
+    for (int k = g.rp[v]; k < g.rp[v + 1]; ++k) {
+      const int w = g.ci[k];
+      if (gone[w]) continue;
+      take(w);
+      --deg[w];
+      put(w);
+    }
+    // each neighbour left lost one; the least degree fell by at most one
+    dmin = std::max(0, std::min(dmin, kLowDeg) - 1);
+  }
+  std::vector<int> col(nv, -1);
+  std::vector<int> mark;  // mark[c] == v: colour c is taken by a neighbour of v
+  for (auto it = removed.rbegin(); it != removed.rend(); ++it) {
+    const int v = *it;
+    for (int k = g.rp[v]; k < g.rp[v + 1]; ++k) {
+      const int c = col[g.ci[k]];
+      if (c < 0) continue;
+      if (c >= int(mark.size())) mark.resize(c + 1, -1);
+      mark[c] = v;
     }
     int c = 0;
     while (c < int(mark.size()) && mark[c] == v) ++c;
@@ -472,7 +555,13 @@ dmg_status dmg_twolevel_create(int32_t nv, int32_t nt, const double* xy_c, const
   tl->nx = nx;
   tl->ny = ny;
   tl->mass = mass;
-  tl->colour = greedy_colours(m);
+  Csr off;
+  std::vector<double> diag;
+  assemble_A(m, K_t, off, diag);
+  for (int v = 0; v < nv; ++v)
+    if (!(diag[v] > 0.0) || !std::isfinite(diag[v]))
+      return fail(DMG_ERR_INVALID_ARG, "A_p has a non-positive diagonal at vertex %d", v);
+  tl->colour = greedy_colours(nv, off);
   const int ncol = 1 + *std::max_element(tl->colour.begin(), tl->colour.end());
   // internal order: colour-major, the transfers' grid-cell order within a colour (a stable
   // counting sort of the cell order by colour)
@@ -489,12 +578,6 @@ dmg_status dmg_twolevel_create(int32_t nv, int32_t nt, const double* xy_c, const
                            tl->t));
   std::vector<int> newidx(nv);
   for (int i = 0; i < nv; ++i) newidx[perm[i]] = i;
-  Csr off;
-  std::vector<double> diag;
-  assemble_A(m, K_t, off, diag);
-  for (int v = 0; v < nv; ++v)
-    if (!(diag[v] > 0.0) || !std::isfinite(diag[v]))
-      return fail(DMG_ERR_INVALID_ARG, "A_p has a non-positive diagonal at vertex %d", v);
   const Csr A = permute_rows(off, perm, &newidx);
   std::vector<double> d(nv), ml(nv, 0.0);
   for (int i = 0; i < nv; ++i) d[i] = diag[perm[i]];

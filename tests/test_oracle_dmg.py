@@ -5,6 +5,7 @@ does not grow with the problem size (Sec. 4.3's observation for the two-level me
 import os
 
 import numpy as np
+import pytest
 import scipy.sparse as spx
 import scipy.sparse.linalg as spl
 
@@ -60,13 +61,46 @@ def test_stiffness_properties_and_colouring():
     # every coupling of A_p is a mesh edge, and every mesh edge a coupling (no cancellation here)
     Gp = (abs(A) > 0).astype(float) - spx.eye(m.nv)
     assert abs((Gp != 0).astype(float) - (G != 0).astype(float)).max() == 0
-    assert col.max() + 1 <= 9                                     # max degree 8 on these meshes
+    # a planar graph always has a vertex of degree <= 5, so greedy colouring in smallest-last
+    # order needs at most 6 colours
+    assert col.max() + 1 <= 6
     assert np.all(col[~m.dof] == 0)                               # isolated Dirichlet vertices
-    # greedy: each vertex takes the smallest colour unused by its earlier neighbours
-    for v in range(0, m.nv, 7):
+    # the order: brute force over the removals, each of least degree among the vertices left
+    # (smallest index among equals); each vertex then takes the smallest colour unused by the
+    # neighbours coloured before it
+    order = dmg.smallest_last_order(G)
+    left = np.ones(m.nv, dtype=bool)
+    Gd = (G != 0).toarray()
+    for v in order[::-1]:
+        deg = (Gd & left[None, :]).sum(axis=1)
+        cand = np.nonzero(left)[0]
+        best = cand[deg[cand] == deg[cand].min()].min()
+        assert v == best
+        left[v] = False
+    pos = np.empty(m.nv, dtype=np.int64)
+    pos[order] = np.arange(m.nv)
+    for v in range(0, m.nv, 5):
         nb = G.indices[G.indptr[v]:G.indptr[v + 1]]
-        used = set(col[nb[nb < v]].tolist())
+        used = set(col[nb[pos[nb] < pos[v]]].tolist())
         assert col[v] == min(set(range(10)) - used)
+
+
+@pytest.mark.parametrize("edges, expected", [
+    # path 0-1-2: 0 leaves first, then 1, then 2; coloured 2, 1, 0
+    ([(0, 1), (1, 2)], [0, 1, 0]),
+    # triangle 0-1-2 with 3 hanging on 2: removals 3, 0, 1, 2; coloured 2, 1, 0, 3
+    ([(0, 1), (1, 2), (0, 2), (2, 3)], [2, 1, 0, 1]),
+    # wheel: hub 0 on the 5-cycle 1-2-3-4-5: removals 1, 2, 3, 0, 4, 5; coloured 5, 4, 0, 3, 2, 1
+    # (an odd wheel needs 4 colours)
+    ([(0, k) for k in range(1, 6)] + [(1, 2), (2, 3), (3, 4), (4, 5), (5, 1)], [2, 3, 1, 0, 1, 0]),
+])
+def test_smallest_last_colouring_by_hand(edges, expected):
+    n = len(expected)
+    r = [a for a, b in edges] + [b for a, b in edges]
+    c = [b for a, b in edges] + [a for a, b in edges]
+    G = spx.coo_matrix((np.ones(len(r)), (r, c)), shape=(n, n)).tocsr()
+    col = dmg.greedy_colouring(G, dmg.smallest_last_order(G))
+    assert col.tolist() == expected
 
 
 def test_lumped_mass_is_a_third_of_incident_area():
