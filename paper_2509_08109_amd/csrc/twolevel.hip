@@ -265,27 +265,31 @@ __global__ __launch_bounds__(256) void k_tl_start(const double* __restrict__ par
 
 inline int row_blocks(int rows) { return tblocks(rows, kMG); }
 
-dmg_status symmetric_sweep(dmg_twolevel* tl, const int* stop, hipStream_t s) {
+dmg_status sweep_colour(dmg_twolevel* tl, int c, const int* stop, hipStream_t s) {
+  const int r0 = tl->cs[c], r1 = tl->cs[c + 1];
+  if (r1 == r0) return DMG_OK;
+  k_tl_colour<<<row_blocks(r1 - r0), 256, 0, s>>>(tl->Arp, tl->Aci, tl->Av, tl->Ad, tl->f, tl->u,
+                                                  r0, r1, stop);
+  return launch_check("two-level colour sweep");
+}
+
+// Forward over colours first..C-1, then backward.  The backward sweep starts with the colour
+// just swept; sweeping it again would recompute the same values from the same inputs, so it
+// starts one colour lower.
+dmg_status symmetric_sweep(dmg_twolevel* tl, const int* stop, hipStream_t s, int first = 0) {
   const int nc = int(tl->cs.size()) - 1;
-  auto colour = [&](int c) -> dmg_status {
-    const int r0 = tl->cs[c], r1 = tl->cs[c + 1];
-    if (r1 == r0) return DMG_OK;
-    k_tl_colour<<<row_blocks(r1 - r0), 256, 0, s>>>(tl->Arp, tl->Aci, tl->Av, tl->Ad, tl->f,
-                                                    tl->u, r0, r1, stop);
-    return launch_check("two-level colour sweep");
-  };
-  for (int c = 0; c < nc; ++c) DMG_CHECK(colour(c));
-  // the backward sweep starts with the colour just swept; sweeping it again would recompute the
-  // same values from the same inputs, so it starts one colour lower
-  for (int c = nc - 2; c >= 0; --c) DMG_CHECK(colour(c));
+  for (int c = first; c < nc; ++c) DMG_CHECK(sweep_colour(tl, c, stop, s));
+  for (int c = nc - 2; c >= 0; --c) DMG_CHECK(sweep_colour(tl, c, stop, s));
   return DMG_OK;
 }
 
-// One two-level cycle on tl->u.
-dmg_status cycle(dmg_twolevel* tl, const int* stop, hipStream_t s) {
+// One two-level cycle on tl->u.  lead = false leaves out the pre-relaxation's first colour
+// pass: right after a post-relaxation (which ends with colour 0) and a residual norm, that pass
+// would reproduce the same values bit for bit.
+dmg_status cycle(dmg_twolevel* tl, const int* stop, hipStream_t s, bool lead = true) {
   dmg_transfer* t = tl->t.get();
   const int n = tl->nv, nb = row_blocks(n);
-  DMG_CHECK(symmetric_sweep(tl, stop, s));
+  DMG_CHECK(symmetric_sweep(tl, stop, s, lead ? 0 : 1));
   if (tl->mass == 0) {
     k_tl_resid<RMode::kLumped><<<nb, 256, 0, s>>>(tl->Arp, tl->Aci, tl->Av, tl->Ad, tl->f, tl->u,
                                                   tl->ML, t->dof, tl->w, n, nullptr, stop);
@@ -311,10 +315,12 @@ dmg_status cycle(dmg_twolevel* tl, const int* stop, hipStream_t s) {
   return symmetric_sweep(tl, stop, s);
 }
 
-// The repeated step of a solve: one cycle, the residual norm, the convergence test.
+// The repeated step of a solve: one cycle, the residual norm, the convergence test.  The solve
+// sweeps colour 0 once before its first step, so every step starts its pre-relaxation at
+// colour 1 (the previous step ended with colour 0 and left u unchanged since).
 dmg_status step(dmg_twolevel* tl, hipStream_t s) {
   const int* stop = tl->flag;
-  DMG_CHECK(cycle(tl, stop, s));
+  DMG_CHECK(cycle(tl, stop, s, false));
   const int nb = row_blocks(tl->nv);
   k_tl_resid<RMode::kNorm><<<nb, 256, 0, s>>>(tl->Arp, tl->Aci, tl->Av, tl->Ad, tl->f, tl->u,
                                               tl->ML, tl->t->dof, nullptr, tl->nv, tl->partials,
@@ -680,6 +686,7 @@ dmg_status dmg_twolevel_solve(dmg_twolevel* tl, double* u_p, const double* f_p, 
   DMG_CHECK(launch_check("two-level initial residual"));
   k_tl_start<<<1, 256, 0, stream>>>(tl->partials, nb, tl->scal, tl->flag, rtol, max_iters);
   DMG_CHECK(launch_check("two-level start"));
+  DMG_CHECK(sweep_colour(tl, 0, tl->flag, stream));  // the first step's leading colour pass
   int* hs = reinterpret_cast<int*>(tl->host + 8);
   double* hsc = tl->host;
   // chunks of kChunk cycles; once two synchronisations give the rate per cycle, a chunk is cut
