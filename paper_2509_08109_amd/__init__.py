@@ -426,20 +426,53 @@ def _interior(x: torch.Tensor) -> torch.Tensor:
     return y
 
 
+class _DiffSolver:
+    """The hierarchy and solve buffers that DiffSolve reuses for one (device, grid, options):
+    each solve refreshes the hierarchy from the new stencil (so it is recomputed, never kept
+    from an earlier call) and solves in the same two buffers, whose captured solve graphs are
+    then replayed instead of captured anew."""
+
+    _cache: dict = {}
+
+    def __init__(self, S: torch.Tensor, opts: Options | None):
+        self.h = Hierarchy(S, opts)
+        shp = (self.h.ny, self.h.nx)
+        self.u = torch.empty(shp, dtype=torch.float64, device=S.device)
+        self.b = torch.empty(shp, dtype=torch.float64, device=S.device)
+
+    @classmethod
+    def solve(cls, S: torch.Tensor, rhs: torch.Tensor, opts: Options | None, rtol: float,
+              max_iters: int):
+        o = opts if opts is not None else default_options()
+        if rhs.shape != S.shape[1:] or rhs.dtype != torch.float64 or rhs.device != S.device:
+            raise ValueError(f"right-hand side must be float64 {tuple(S.shape[1:])} on {S.device}")
+        key = (S.device, S.shape[1], S.shape[2], bytes(o))
+        ent = cls._cache.get(key)
+        if ent is None:
+            ent = cls._cache[key] = cls(S, o)
+        else:
+            ent.h.refresh(S)
+        ent.b.copy_(rhs)
+        ent.u.zero_()
+        _, its, rr, _ = ent.h.solve(ent.b, u=ent.u, rtol=rtol, max_iters=max_iters,
+                                    raise_on_fail=False)
+        return ent.u.clone(), its, rr
+
+
 class DiffSolve(torch.autograd.Function):
     """u = A(K)^{-1} b with A the mapped Q1 operator; gradients w.r.t. K (per cell) and b.
 
     Forward saves only (K, b, u); backward recomputes the stencil and hierarchy, solves the
     adjoint system A lam = du (A is symmetric, so the same V-cycle serves), and returns
-    dK = -lam_e^T G_e u_e and db = lam.
+    dK = -lam_e^T G_e u_e and db = lam.  Calls on one device share one hierarchy and its
+    buffers per grid size and options (DiffSolve.clear_cache() frees them), so they must not
+    run concurrently on different streams.
     """
 
     @staticmethod
     def forward(ctx, K, b, jac, rtol=1e-12, max_iters=200, opts=None):
         S = assemble_stencil(jac, K.detach().contiguous())
-        h = Hierarchy(S, opts)
-        u, its, rr, _ = h.solve(b.detach().contiguous(), rtol=rtol, max_iters=max_iters, raise_on_fail=False)
-        h.close()
+        u, its, rr = _DiffSolver.solve(S, b.detach(), opts, rtol, max_iters)
         ctx.save_for_backward(K, b, u)
         ctx.jac, ctx.rtol, ctx.max_iters, ctx.opts = jac, rtol, max_iters, opts
         ctx.iters, ctx.relres = its, rr
@@ -449,10 +482,14 @@ class DiffSolve(torch.autograd.Function):
     def backward(ctx, gu):
         K, b, u = ctx.saved_tensors
         S = assemble_stencil(ctx.jac, K.detach().contiguous())
-        h = Hierarchy(S, ctx.opts)
-        lam, _, _, _ = h.solve(_interior(gu.contiguous().to(torch.float64)), rtol=ctx.rtol,
-                               max_iters=ctx.max_iters, raise_on_fail=False)
-        h.close()
+        lam, _, _ = _DiffSolver.solve(S, _interior(gu.contiguous().to(torch.float64)), ctx.opts,
+                                      ctx.rtol, ctx.max_iters)
         dK = grad_K(ctx.jac, lam, u) if ctx.needs_input_grad[0] else None
         db = lam if ctx.needs_input_grad[1] else None
         return dK, db, None, None, None, None
+
+    @staticmethod
+    def clear_cache() -> None:
+        for ent in _DiffSolver._cache.values():
+            ent.h.close()
+        _DiffSolver._cache.clear()

@@ -361,6 +361,31 @@ def test_grad_K_matches_oracle(dmg):
     assert relerr(host(g), go) <= TOL
 
 
+def test_diffsolve_reuses_one_hierarchy_exactly(dmg):
+    """Repeated DiffSolve calls share one cached hierarchy, refreshed from each new stencil: every
+    call returns bit for bit what a fresh hierarchy's solve from zero returns."""
+    n = 65
+    prob = pb.star(n, seed=6)
+    jac = dev(prob.jac)
+    dmg.DiffSolve.clear_cache()
+    st = torch.cuda.Stream()                      # a side stream: the solves replay graphs
+    st.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(st):
+        for scale in (1.0, 2.5, 0.3):
+            K = dev(prob.K * scale)
+            b = dev(prob.b * (1.0 + scale))
+            u = dmg.DiffSolve.apply(K, b, jac, 1e-11)
+            h = dmg.Hierarchy(dmg.assemble_stencil(jac, K))
+            ur, _, _, _ = h.solve(b, rtol=1e-11)
+            h.close()
+            st.synchronize()
+            assert torch.equal(u, ur)
+    torch.cuda.synchronize()
+    assert len(dmg._DiffSolver._cache) == 1
+    dmg.DiffSolve.clear_cache()
+    assert len(dmg._DiffSolver._cache) == 0
+
+
 def test_diffsolve_gradients(dmg):
     n = 33
     prob = pb.star(n, seed=4)
