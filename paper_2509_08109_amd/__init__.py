@@ -427,31 +427,32 @@ def _interior(x: torch.Tensor) -> torch.Tensor:
 
 
 class _DiffSolver:
-    """The hierarchy and solve buffers that DiffSolve reuses for one (device, grid, options):
-    each solve refreshes the hierarchy from the new stencil (so it is recomputed, never kept
-    from an earlier call) and solves in the same two buffers, whose captured solve graphs are
-    then replayed instead of captured anew."""
+    """The hierarchy and buffers that DiffSolve reuses for one (device, grid, options): each
+    solve assembles the stencil into the same array and refreshes the hierarchy from it (so the
+    hierarchy is recomputed, never kept from an earlier call; from the second refresh on, the
+    setup runs as a replayed graph), then solves in the same two buffers, whose captured solve
+    graphs are replayed instead of captured anew."""
 
     _cache: dict = {}
 
-    def __init__(self, S: torch.Tensor, opts: Options | None):
-        self.h = Hierarchy(S, opts)
-        shp = (self.h.ny, self.h.nx)
-        self.u = torch.empty(shp, dtype=torch.float64, device=S.device)
-        self.b = torch.empty(shp, dtype=torch.float64, device=S.device)
-
     @classmethod
-    def solve(cls, S: torch.Tensor, rhs: torch.Tensor, opts: Options | None, rtol: float,
-              max_iters: int):
+    def solve(cls, jac: torch.Tensor, K: torch.Tensor, rhs: torch.Tensor, opts: Options | None,
+              rtol: float, max_iters: int):
         o = opts if opts is not None else default_options()
-        if rhs.shape != S.shape[1:] or rhs.dtype != torch.float64 or rhs.device != S.device:
-            raise ValueError(f"right-hand side must be float64 {tuple(S.shape[1:])} on {S.device}")
-        key = (S.device, S.shape[1], S.shape[2], bytes(o))
+        shp = (K.shape[0] + 1, K.shape[1] + 1)
+        if tuple(rhs.shape) != shp or rhs.dtype != torch.float64 or rhs.device != K.device:
+            raise ValueError(f"right-hand side must be float64 {shp} on {K.device}")
+        key = (K.device, shp, bytes(o))
         ent = cls._cache.get(key)
         if ent is None:
-            ent = cls._cache[key] = cls(S, o)
+            ent = cls._cache[key] = cls()
+            ent.S = assemble_stencil(jac, K)
+            ent.h = Hierarchy(ent.S, o)
+            ent.u = torch.empty(shp, dtype=torch.float64, device=K.device)
+            ent.b = torch.empty(shp, dtype=torch.float64, device=K.device)
         else:
-            ent.h.refresh(S)
+            assemble_stencil(jac, K, out=ent.S)
+            ent.h.refresh(ent.S)
         ent.b.copy_(rhs)
         ent.u.zero_()
         _, its, rr, _ = ent.h.solve(ent.b, u=ent.u, rtol=rtol, max_iters=max_iters,
@@ -471,8 +472,8 @@ class DiffSolve(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, K, b, jac, rtol=1e-12, max_iters=200, opts=None):
-        S = assemble_stencil(jac, K.detach().contiguous())
-        u, its, rr = _DiffSolver.solve(S, b.detach(), opts, rtol, max_iters)
+        u, its, rr = _DiffSolver.solve(jac, K.detach().contiguous(), b.detach(), opts, rtol,
+                                       max_iters)
         ctx.save_for_backward(K, b, u)
         ctx.jac, ctx.rtol, ctx.max_iters, ctx.opts = jac, rtol, max_iters, opts
         ctx.iters, ctx.relres = its, rr
@@ -481,8 +482,8 @@ class DiffSolve(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gu):
         K, b, u = ctx.saved_tensors
-        S = assemble_stencil(ctx.jac, K.detach().contiguous())
-        lam, _, _ = _DiffSolver.solve(S, _interior(gu.contiguous().to(torch.float64)), ctx.opts,
+        lam, _, _ = _DiffSolver.solve(ctx.jac, K.detach().contiguous(),
+                                      _interior(gu.contiguous().to(torch.float64)), ctx.opts,
                                       ctx.rtol, ctx.max_iters)
         dK = grad_K(ctx.jac, lam, u) if ctx.needs_input_grad[0] else None
         db = lam if ctx.needs_input_grad[1] else None
