@@ -106,7 +106,7 @@ void dmg_default_options(dmg_options* opts);
 const char* dmg_last_error(void);
 const char* dmg_version(void);
 
-/* ---- a1: stencil assembly (Sec. 2, eq. weak_computational; Sec. 2.1 D_c) --------------------
+/* ---- stencil assembly (Sec. 2, eq. weak_computational; Sec. 2.1 D_c) --------------------
  * jac : [16][ny-1][nx-1] float64.  Plane 4*q+e is entry e of J = dX/d(xi,eta) of the inverse
  *       map X = T^{-1} (e = 0: dx/dxi, 1: dx/deta, 2: dy/dxi, 3: dy/deta) at the 2x2 Gauss point
  *       q = qx + 2 qy of each cell, local offsets 1/2 -+ 1/(2 sqrt 3) of the cell width.
@@ -118,7 +118,7 @@ const char* dmg_version(void);
 dmg_status dmg_assemble_stencil(const double* jac, const double* K, int32_t nx, int32_t ny,
                                 double* S, hipStream_t stream);
 
-/* ---- a2-a4: hierarchy setup (Sec. 2.2; coarsening by two, operator-induced interpolation,
+/* ---- hierarchy setup (Sec. 2.2; coarsening by two, operator-induced interpolation,
  * Galerkin P^T A P, dense Cholesky of the coarsest interior system) --------------------------
  * The hierarchy lives entirely in a caller-provided device workspace (>= *bytes, 256-byte
  * aligned) which must outlive the handle; the library does not allocate device memory for it.
@@ -154,7 +154,7 @@ dmg_status dmg_hier_level(const dmg_hier* h, int32_t level, int32_t* nx, int32_t
 dmg_status dmg_stats(const dmg_hier* h, int32_t* levels, double* grid_complexity,
                      double* op_complexity);
 
-/* ---- a5-a8: one V(nu_pre, nu_post) cycle on A u = b, in place on u (Sec. 2.2) -------------
+/* ---- one V(nu_pre, nu_post) cycle on A u = b, in place on u (Sec. 2.2) -------------
  * Four-colour Gauss-Seidel smoothing, r = b - A u, b_H = P^T r, zero coarse initial guess,
  * recursion, coarsest Cholesky solve, u += P e_H, post-smoothing.  float64 only. */
 dmg_status dmg_vcycle(dmg_hier* h, double* u, const double* b, hipStream_t stream);
@@ -200,7 +200,7 @@ dmg_status dmg_hier_sweep_config(const dmg_hier* h, int32_t level, int32_t kind,
 dmg_status dmg_residual_norm(dmg_hier* h, const double* u, const double* b, double* norm,
                              hipStream_t stream);
 
-/* ---- a9: solve (Sec. 4 stopping rule: ||b - A u||_2 <= rtol ||b||_2) ------------------------
+/* ---- solve (Sec. 4 stopping rule: ||b - A u||_2 <= rtol ||b||_2) ------------------------
  * u in: initial guess, out: solution.  precision DMG_FP64: repeated V-cycles.  DMG_FP32_IR:
  * r = b - A x in fp64, rounded once to r32 = fl32(r); inner_cycles fp32 V-cycles from e = 0
  * with fp32-rounded copies of the fp64 Galerkin stencils/weights (coarsest solve in fp64);
@@ -209,18 +209,19 @@ dmg_status dmg_residual_norm(dmg_hier* h, const double* u, const double* b, doub
  * nullable) return the count of cycles or refinement steps and the final relative residual;
  * history (host, nullable, >= max_iters doubles) receives the relative residual after each
  * step.  Returns DMG_ERR_NO_CONVERGENCE (u holds the last iterate) or DMG_ERR_NONFINITE.  The
- * convergence test runs on the device; the host synchronises `stream` once per 4 steps. */
+ * convergence test runs on the device; the host synchronises `stream` once per chunk of at
+ * most 4 steps (a chunk is cut short once the observed reduction per step predicts fewer). */
 dmg_status dmg_solve(dmg_hier* h, double* u, const double* b, double rtol, int32_t max_iters,
                      int32_t* iters, double* relres, double* history, hipStream_t stream);
 
-/* ---- a11: per-cell gradient of J through the solve ---------------------------------------
+/* ---- per-cell gradient of J through the solve ---------------------------------------
  * dK[e] = -lambda_e^T G_e u_e, G_e the cell's Q1 element matrix (recomputed from jac as in
  * dmg_assemble_stencil), lambda and u vertex arrays with zero boundary ring.  With lambda
  * solving A lambda = dJ/du this is dJ/dK_e (discrete adjoint; A is symmetric). */
 dmg_status dmg_grad_K(const double* jac, const double* lambda, const double* u, int32_t nx,
                       int32_t ny, double* dK, hipStream_t stream);
 
-/* ---- a12: grid <-> mesh transfers (Sec. 2.3; Sec. 2.3.1 coupled mass) -----------------------
+/* ---- grid <-> mesh transfers (Sec. 2.3; Sec. 2.3.1 coupled mass) -----------------------
  * Create from a P1 mesh given as HOST arrays: xy_c [nv][2] the images T(x_v) in (-1,1)^2,
  * xy_p [nv][2] physical coordinates, tris [nt][3] (int32, any orientation), dof [nv] (uint8,
  * 0 = Dirichlet vertex).  C is assembled by rasterising each mapped triangle over the grid
@@ -247,7 +248,7 @@ dmg_status dmg_transfer_to_grid(dmg_transfer* t, const double* r_p, double* r_c,
                                 hipStream_t stream);
 void dmg_transfer_destroy(dmg_transfer* t);
 
-/* ---- a10: batched solve of independent instances ----------------------------------------
+/* ---- batched solve of independent instances ----------------------------------------
  * count instances with dims nx[k], ny[k] (host arrays, any mix of sizes dmg_setup accepts) and fine stencils
  * S[k] (host array of device pointers).  One workspace holds every hierarchy plus the batch's
  * schedule.  dmg_batch_solve runs one batched V-cycle per step: each fused sweep is launched
@@ -281,9 +282,11 @@ void dmg_batch_destroy(dmg_batch* bt);
  * cycles: a symmetric multicolour Gauss-Seidel sweep, r_c = C^T M^{-1} (f_p - A_p u_p), one
  * float64 V-cycle of `grid` on A_c e_c = r_c from e_c = 0, u_p += M^{-1} C e_c, a second
  * symmetric sweep.  M^{-1} is mass = 0: the lumped mass (row sums of M_p), or mass = 2: two CG
- * iterations on M_p (Sec. 2.3).  Colours: greedy over the vertices in index order on the mesh
- * graph (unknowns sharing a triangle are neighbours; Dirichlet vertices have none, colour 0);
- * the symmetric sweep updates colours 0..C-1 then C-2..0.
+ * iterations on M_p (Sec. 2.3).  Colours: greedy on the mesh graph (unknowns sharing a
+ * triangle are neighbours; Dirichlet vertices have none, colour 0) with the vertices in
+ * smallest-last order (each removed in turn as one of least degree among those left, the
+ * smallest index among equals; coloured in reverse removal order); the symmetric sweep updates
+ * colours 0..C-1 then C-2..0.
  * Create: mesh arrays on the HOST, nq and flags as for dmg_transfer_create (nq = 0, the exact overlap
  * integral, keeps the coarse correction's energy matched to A_p as the mesh is refined; low
  * quadrature orders let it drift); K_t [nt] host coefficient per
@@ -297,8 +300,9 @@ void dmg_batch_destroy(dmg_batch* bt);
  * cycle: one cycle on u_p [nv] (device, in/out) for f_p [nv] (device).
  * solve: cycles from u_p until ||f - A u|| <= rtol ||f - A u_0|| or max_iters; a zero initial
  * residual returns at once with iters = 0 and relres = 0.  history (host, nullable,
- * >= max_iters entries) receives ||f - A u_k|| / ||f - A u_0||.  Chunks of four cycles run in
- * one captured hipGraph (when `stream` is not the legacy default stream).  Returns
+ * >= max_iters entries) receives ||f - A u_k|| / ||f - A u_0||.  Chunks of at most four cycles
+ * (cut short once the observed reduction per cycle predicts fewer) run in one captured hipGraph
+ * each (when `stream` is not the legacy default stream).  Returns
  * DMG_ERR_NO_CONVERGENCE or DMG_ERR_NONFINITE with u_p holding the last iterate. */
 dmg_status dmg_twolevel_create(int32_t nv, int32_t nt, const double* xy_c, const double* xy_p,
                                const int32_t* tris, const uint8_t* dof, const double* K_t,
