@@ -562,20 +562,46 @@ void graph_reset(Graph& g) {
 
 void reset_solve_graphs(dmg_hier* h) {
   for (auto& g : h->graph) graph_reset(g);
+  graph_reset(h->first_graph);
 }
 
-// Runs len (1..kChunk) solve steps for (u, b) on stream s, through a captured graph when
-// enabled (one per chunk length), re-captured when the arrays or the stream change.
-dmg_status run_step(dmg_hier* h, int kind, int len, double* u, const double* b, hipStream_t s) {
+// The solve's start on the device: ||b|| and the initial residual's norm, the target and the
+// solve state (no host synchronisation; a solve that is done at the start runs its first
+// chunk of steps as skipped kernels).
+dmg_status solve_start(dmg_hier* h, int kind, double* u, const double* b, double rtol,
+                       int max_iters, hipStream_t s) {
+  const Level& L0 = h->L[0];
+  const int slot = kind ? 4 : 2;
+  double* pb = h->partials + kMaxPartials;
+  DMG_CHECK(launch_sq_partials(b, L0.n(), L0.nx, L0.ny, pb, s));
+  int nr = kReduceBlocks;
+  if (kind) {
+    DMG_CHECK(launch_ir_residual(L0.Sp, u, b, L0.b32, L0.nx, L0.ny, h->partials, s));
+    nr = ir_residual_blocks(L0.nx, L0.ny);
+  } else {
+    DMG_CHECK(launch_resid_sq_partials(L0.S, u, b, L0.nx, L0.ny, h->partials, s));
+  }
+  return launch_solve_start(pb, kReduceBlocks, h->partials, nr, h->scalars, h->scalars + slot,
+                            h->flag + 4, rtol, max_iters, u, L0.n(), s);
+}
+
+// Runs len (1..kChunk) solve steps for (u, b) on stream s, preceded by the solve's start when
+// `start` is set (then len = kChunk), through a captured graph when enabled (one per chunk
+// length, and one for the start with the first chunk), re-captured when the arrays, the stream
+// or the start's arguments change.
+dmg_status run_step(dmg_hier* h, int kind, int len, double* u, const double* b, hipStream_t s,
+                    bool start = false, double rtol = 0.0, int max_iters = 0) {
   auto step = [&]() -> dmg_status {
+    if (start) DMG_CHECK(solve_start(h, kind, u, b, rtol, max_iters, s));
     for (int k = 0; k < len; ++k)
       DMG_CHECK(kind == 0 ? step_fp64(h, u, b, s) : step_ir(h, u, b, s));
     return DMG_OK;
   };
   // the legacy default stream cannot be captured: run eagerly there
   if (!h->opts.use_graph || s == nullptr) return step();
-  Graph& g = h->graph[len - 1];
-  if (!(g.exec && g.key_u == u && g.key_b == b && g.stream == s && g.kind == kind)) {
+  Graph& g = start ? h->first_graph : h->graph[len - 1];
+  if (!(g.exec && g.key_u == u && g.key_b == b && g.stream == s && g.kind == kind &&
+        (!start || (g.rtol == rtol && g.max_iters == max_iters)))) {
     graph_reset(g);
     DMG_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
     dmg_status st = step();
@@ -596,6 +622,8 @@ dmg_status run_step(dmg_hier* h, int kind, int len, double* u, const double* b, 
     g.key_b = b;
     g.stream = s;
     g.kind = kind;
+    g.rtol = rtol;
+    g.max_iters = max_iters;
   }
   DMG_HIP(hipGraphLaunch(g.exec, s));
   return DMG_OK;
@@ -862,6 +890,7 @@ dmg_status grid_vcycle(dmg_hier* h, double* u, const double* b, bool u_zero, con
 
 dmg_hier::~dmg_hier() {
   for (auto& g : graph) dmg::graph_reset(g);
+  dmg::graph_reset(first_graph);
   dmg::graph_reset(setup_graph);
   if (host) (void)hipHostFree(host);
 }
@@ -1222,20 +1251,6 @@ dmg_status dmg_solve(dmg_hier* h, double* u, const double* b, double rtol, int32
   if (iters) *iters = 0;
   const bool ir = h->opts.precision == DMG_FP32_IR;
   const int slot = ir ? 4 : 2;
-  const Level& L0 = h->L[0];
-  // starting norms and the solve state on the device: no host synchronisation before the first
-  // chunk of steps (a solve that is done at the start runs one chunk of skipped kernels)
-  double* pb = h->partials + kMaxPartials;
-  DMG_CHECK(launch_sq_partials(b, L0.n(), L0.nx, L0.ny, pb, stream));
-  int nr = kReduceBlocks;
-  if (ir) {
-    DMG_CHECK(launch_ir_residual(L0.Sp, u, b, L0.b32, L0.nx, L0.ny, h->partials, stream));
-    nr = ir_residual_blocks(L0.nx, L0.ny);
-  } else {
-    DMG_CHECK(launch_resid_sq_partials(L0.S, u, b, L0.nx, L0.ny, h->partials, stream));
-  }
-  DMG_CHECK(launch_solve_start(pb, kReduceBlocks, h->partials, nr, h->scalars, h->scalars + slot,
-                               h->flag + 4, rtol, max_iters, u, L0.n(), stream));
   int* hs = reinterpret_cast<int*>(h->host + 8);  // device flags [0..8): pivot, -, -, -, stop, steps
   double* hsc = h->host;  // scalars [0..7]
   // Chunks of kChunk steps, except that once two synchronisations give the rate per step, a
@@ -1243,8 +1258,9 @@ dmg_status dmg_solve(dmg_hier* h, double* u, const double* b, double rtol, int32
   // costs its launches, and the device stopping test makes any chunk length exact).
   int len = kChunk, prev_k = -1;
   double prev_rn = 0.0;
-  for (;;) {
-    DMG_CHECK(run_step(h, ir ? 1 : 0, len, u, b, stream));
+  // the start and the first chunk run as one graph
+  for (bool first = true;; first = false) {
+    DMG_CHECK(run_step(h, ir ? 1 : 0, len, u, b, stream, first, rtol, max_iters));
     DMG_HIP(hipMemcpyAsync(hs, h->flag, 8 * sizeof(int), hipMemcpyDeviceToHost, stream));
     DMG_HIP(hipMemcpyAsync(hsc, h->scalars, 8 * sizeof(double), hipMemcpyDeviceToHost, stream));
     DMG_HIP(hipStreamSynchronize(stream));

@@ -103,6 +103,8 @@ struct Graph {
   const void* key_b = nullptr;
   hipStream_t stream = nullptr;
   int kind = -1;
+  double rtol = -1.0;  // the solve start's arguments, for a graph that holds the start
+  int max_iters = -1;
 };
 
 }  // namespace dmg
@@ -144,6 +146,7 @@ struct dmg_hier {
   float* gbasis32 = nullptr;
   double* gscratch = nullptr;
   dmg::Graph graph[dmg::kChunk];  // captured solve chunks of 1..kChunk steps
+  dmg::Graph first_graph;         // the solve's start followed by its first kChunk steps
   // refresh: replayed as a captured graph from the second consecutive call with the same
   // stencil array and stream (the first of such a run goes eagerly: capture costs more than a
   // one-off setup)
