@@ -139,7 +139,7 @@ DISCONTINUOUS = ("circle", "checker", "layer")
 
 
 def unit_square_K(kind: str, x, y) -> np.ndarray:
-    """The discontinuous diffusivities of Sec. 4.2's variable-coefficient problems on the unit
+    """The discontinuous diffusivities of Sec. 4.1's variable-coefficient problems on the unit
     square, at physical points (x, y):
       circle : 100 inside the circle of radius 3/5 about the origin, 1 elsewhere;
       checker: 100 where floor(4x) + floor(4y) is even, 1 elsewhere (a 4 x 4 checkerboard);
