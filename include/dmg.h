@@ -29,7 +29,8 @@
  *  - Every function returns dmg_status; on failure dmg_last_error() (thread-local) holds a
  *    message.  Argument validation happens on the host before anything is enqueued, so a
  *    rejected call has no device side effects.  No C++ exception crosses this boundary.
- *  - Grid dimensions must be 2^k + 1 (k >= 1) in each direction for the solver.
+ *  - Grid dimensions: any odd size >= 3 in each direction for the solver (dmg_setup states how
+ *    levels coarsen and which coarsest grids are accepted); assembly accepts any size >= 3.
  */
 #ifndef DMG_H
 #define DMG_H
@@ -202,10 +203,10 @@ dmg_status dmg_residual_norm(dmg_hier* h, const double* u, const double* b, doub
 
 /* ---- solve (Sec. 4 stopping rule: ||b - A u||_2 <= rtol ||b||_2) ------------------------
  * u in: initial guess, out: solution.  precision DMG_FP64: repeated V-cycles.  DMG_FP32_IR:
- * r = b - A x in fp64, rounded once to r32 = fl32(r); inner_cycles fp32 V-cycles from e = 0
- * with fp32-rounded copies of the fp64 Galerkin stencils/weights (coarsest solve in fp64);
- * x += e in fp64.  (Scaling r by a power of two before the fp32 cycles changes no bit of x;
- * scaling by ||r|| differs from that only in the rounding of r/||r||.)  iters / relres (host,
+ * r = b - A x in fp64, s = ||r||_2 (on the device), r32 = fl32(r / s); inner_cycles fp32
+ * V-cycles from e = 0 with fp32-rounded copies of the fp64 Galerkin stencils/weights (coarsest
+ * solve in fp64); x += s e in fp64.  Dividing by ||r|| keeps r32 in float32's normal range
+ * whatever the scale of b.  iters / relres (host,
  * nullable) return the count of cycles or refinement steps and the final relative residual;
  * history (host, nullable, >= max_iters doubles) receives the relative residual after each
  * step.  Returns DMG_ERR_NO_CONVERGENCE (u holds the last iterate) or DMG_ERR_NONFINITE.  The

@@ -198,10 +198,10 @@ void carve(dmg_hier& h, Arena& a, const std::vector<std::pair<int, int>>& dims,
         L.Sp32 = a.take<float>(5 * n);
       }
     }
+    if (l + 1 < dims.size() || (l == 0 && fp32)) L.r = a.take<double>(n);  // level 0: r = b - A x
     if (l + 1 < dims.size()) {
       const size_t nc = size_t(dims[l + 1].first) * dims[l + 1].second;
       L.P = staged ? slot(h.tail_img, img.P[k]) : a.take<double>(8 * nc);
-      L.r = a.take<double>(n);
       if (fp32) {
         L.P32 = staged ? slot(h.tail_img32, img.P[k]) : a.take<float>(8 * nc);
         L.r32 = a.take<float>(n);
@@ -431,11 +431,12 @@ dmg_status vcycle_line(dmg_hier* h, double* u0, const double* b0, bool u0_zero, 
 // strip kernels are out of place: each level alternates between its two iterate buffers and
 // the cycle ends with the level-0 iterate back in u0.  partials (optional) receives the
 // squared-residual partials of the final level-0 iterate.
-// x64 (float cycles only, nullable): float64 iterate that receives the cycle's result, x += u0,
-// fused into the last level-0 sweep.
+// x64 (float cycles only, nullable): float64 iterate that receives the cycle's result scaled by
+// the device scalar *xscale, x += s u0, fused into the last level-0 sweep.
 template <class T>
 dmg_status vcycle_impl(dmg_hier* h, T* u0, const T* b0, hipStream_t s, double* partials = nullptr,
-                       bool u0_zero = false, const int* stop = nullptr, double* x64 = nullptr) {
+                       bool u0_zero = false, const int* stop = nullptr, double* x64 = nullptr,
+                       const double* xscale = nullptr) {
   using Pr = Prec<T>;
   const dmg_options& o = h->opts;
   if (o.smoother != 0) {
@@ -473,7 +474,7 @@ dmg_status vcycle_impl(dmg_hier* h, T* u0, const T* b0, hipStream_t s, double* p
       T* dst = other(l, cur[l]);
       DMG_CHECK(launch_post<T>(Pr::cfgp(L), Pr::Sp(L), cur[l], dst, b, Pr::P(L), first ? e : nullptr,
                                (l == 0 && last) ? partials : nullptr, L.nx, L.ny, post.pf, post.cA,
-                               post.cB, stop, s, (l == 0 && last) ? x64 : nullptr));
+                               post.cB, stop, s, (l == 0 && last) ? x64 : nullptr, xscale));
       cur[l] = dst;
     }
     e = cur[l];
@@ -481,7 +482,7 @@ dmg_status vcycle_impl(dmg_hier* h, T* u0, const T* b0, hipStream_t s, double* p
   if (h->tail > 0 && cur[0] != u0)  // odd total sweep count: the iterate ends in the buffer
     DMG_CHECK(launch_copy<T>(cur[0], u0, h->L[0].n(), stop, s));
   if constexpr (std::is_same<T, float>::value) {
-    if (x64 && h->tail == 0) DMG_CHECK(launch_ir_update(x64, u0, h->L[0].n(), s, stop));
+    if (x64 && h->tail == 0) DMG_CHECK(launch_ir_update(x64, u0, h->L[0].n(), xscale, s, stop));
   }
   return DMG_OK;
 }
@@ -536,20 +537,21 @@ dmg_status step_fp64(dmg_hier* h, double* u, const double* b, hipStream_t s) {
                            kMaxHistory, s);
 }
 
-// The repeated step of float32 refinement: r32 = r/s, e = 0, inner fp32 cycles, x += s e,
-// r = b - A x, its norm (slot 4) and the convergence check.
+// The repeated step of float32 refinement: r32 = fl32(r / s) with s = ||r||, e = 0, inner fp32
+// cycles, x += s e, r = b - A x, its norm (slot 4) and the convergence check.
 dmg_status step_ir(dmg_hier* h, double* x, const double* b, hipStream_t s) {
-  // L.b32 holds fl32(b - A x) of the current x (written by the previous step or the solve's
-  // start); the float cycles solve A e = r from e = 0 and the last one adds e into x.  The
-  // refinement runs unscaled: scaling r by a power of two would change no bit of x (float
-  // arithmetic commutes with it), and scaling by ||r|| differs from that only in the rounding
-  // of r / ||r||.
+  // L.r holds r = b - A x of the current x and scalars[5] its norm s (from the previous step or
+  // the solve's start).  The float cycles solve A e = r / s from e = 0; the last one adds s e
+  // into x.  Dividing by ||r|| keeps r32 in float32's normal range whatever the scale of b.
   const int* stop = stop_flag(h);
   const Level& L = h->L[0];
   const int m = h->opts.inner_cycles;
+  const double* norm = h->scalars + 5;
+  DMG_CHECK(launch_ir_scale(L.r, L.b32, L.n(), norm, s, stop));
   for (int k = 0; k < m; ++k)
-    DMG_CHECK(vcycle_impl<float>(h, L.u32, L.b32, s, nullptr, k == 0, stop, k + 1 == m ? x : nullptr));
-  DMG_CHECK(launch_ir_residual(L.Sp, x, b, L.b32, L.nx, L.ny, h->partials, s, stop));
+    DMG_CHECK(vcycle_impl<float>(h, L.u32, L.b32, s, nullptr, k == 0, stop, k + 1 == m ? x : nullptr,
+                                 norm));
+  DMG_CHECK(launch_ir_residual(L.Sp, x, b, L.r, L.nx, L.ny, h->partials, s, stop));
   return launch_check_step(h->partials, ir_residual_blocks(L.nx, L.ny), h->scalars + 4, h->scalars,
                            h->flag + 4, h->hist, kMaxHistory, s);
 }
@@ -576,7 +578,7 @@ dmg_status solve_start(dmg_hier* h, int kind, double* u, const double* b, double
   DMG_CHECK(launch_sq_partials(b, L0.n(), L0.nx, L0.ny, pb, s));
   int nr = kReduceBlocks;
   if (kind) {
-    DMG_CHECK(launch_ir_residual(L0.Sp, u, b, L0.b32, L0.nx, L0.ny, h->partials, s));
+    DMG_CHECK(launch_ir_residual(L0.Sp, u, b, L0.r, L0.nx, L0.ny, h->partials, s));
     nr = ir_residual_blocks(L0.nx, L0.ny);
   } else {
     DMG_CHECK(launch_resid_sq_partials(L0.S, u, b, L0.nx, L0.ny, h->partials, s));

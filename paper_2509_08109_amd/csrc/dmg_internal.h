@@ -255,7 +255,8 @@ struct StripArgs {
   int cA, cB;         // column parity smoothed first on A-rows / on B-rows
   const int* stop;    // nullable: when *stop != 0 the kernel does nothing (converged solve)
   double* x64;        // float post sweeps only (nullable): float64 iterate that receives the
-                      // sweep's output, x += u, at the points this workgroup writes
+                      // sweep's output, x += s u, at the points this workgroup writes
+  const double* xscale;  // with x64: device address of the scale s (nullable: s = 1)
 };
 
 // Kernel arguments of the coarse tail (one instance).
@@ -304,7 +305,8 @@ dmg_status launch_pre(const StripConfig& cfg, const T* S, const T* uin, T* u, co
 template <class T>
 dmg_status launch_post(const StripConfig& cfg, const T* S, const T* uin, T* u, const T* b,
                        const T* P, const T* e, double* partials, int nx, int ny, int pf, int cA,
-                       int cB, const int* stop, hipStream_t s, double* x64 = nullptr);
+                       int cB, const int* stop, hipStream_t s, double* x64 = nullptr,
+                       const double* xscale = nullptr);
 template <class T>
 struct TailSpec {
   const T* S[kMaxTail];
@@ -376,15 +378,18 @@ dmg_status launch_wave_multi(const StripArgs<T>* list, int count, int tiles_per,
                              hipStream_t s);
 
 // iterative refinement helpers (stop: nullable device flag, see launch_check_step)
-// x += e over n points (used when no float strip sweep carries the update)
-dmg_status launch_ir_update(double* x, const float* e, size_t n, hipStream_t s,
-                            const int* stop = nullptr);
-// r32 = fl32(b - A x) with A (point-major [ny][nx][5]), x, b in float64, plus one squared-norm
-// partial per workgroup; ir_residual_blocks gives the number of partials written
+// x += s e over n points, s = *scale (used when no float strip sweep carries the update)
+dmg_status launch_ir_update(double* x, const float* e, size_t n, const double* scale,
+                            hipStream_t s, const int* stop = nullptr);
+// r = b - A x in float64 with A (point-major [ny][nx][5]) (zero on the boundary ring), plus one
+// squared-norm partial per workgroup; ir_residual_blocks gives the number of partials written
 int ir_residual_blocks(int nx, int ny);
-dmg_status launch_ir_residual(const double* S, const double* x, const double* b, float* r32,
+dmg_status launch_ir_residual(const double* S, const double* x, const double* b, double* r,
                               int nx, int ny, double* partials, hipStream_t s,
                               const int* stop = nullptr);
+// r32 = fl32(r / s) over n points, s = *norm (r32 = 0 where s = 0)
+dmg_status launch_ir_scale(const double* r, float* r32, size_t n, const double* norm,
+                           hipStream_t s, const int* stop = nullptr);
 // Per-instance arguments of the batched convergence check (k_check on each instance) and of the
 // batched start of a solve (norms of b and b - A u, solve state).
 struct CheckArgs {

@@ -35,6 +35,14 @@ constexpr int RS = 4;     // ring rows of S, b, r
 constexpr int umod(int x) { return ((x % RU) + RU) % RU; }
 constexpr int smod(int x) { return ((x % RS) + RS) % RS; }
 
+// x + s e with the product rounded before the sum (no contraction): the float64 update of
+// iterative refinement, x += s e.
+__device__ __forceinline__ double add_scaled(double x, double s, double e) {
+#pragma clang fp contract(off)
+  const double p = s * e;
+  return x + p;
+}
+
 // This thread's column of the ring rows, in registers (slots are compile-time constants).
 template <class T>
 struct ColRing {
@@ -281,10 +289,11 @@ __global__ __launch_bounds__(BW) void k_strip(StripArgs<T> a) {
   // rows past alast + 1 are never consumed: their prefetch slots read row -1, which the
   // loader maps to a fixed, cached address instead of streaming unused rows from memory
   auto live = [&](int r) { return r <= alast + 1 ? r : -1; };
+  const double xs = (POST && a.x64 && a.xscale) ? *a.xscale : 1.0;
   auto emit = [&](size_t v, T val) {
     a.u[v] = val;
     if constexpr (POST && std::is_same<T, float>::value)
-      if (a.x64) a.x64[v] += double(val);
+      if (a.x64) a.x64[v] = add_scaled(a.x64[v], xs, double(val));
   };
   const int base = a0 - 1;
   const bool interior_i = i >= 1 && i <= a.nx - 2;
@@ -912,10 +921,11 @@ __device__ __forceinline__ void wave_tile(const StripArgs<T>& a, int tile, int p
   // rows past alast + 1 are never consumed: their prefetch slots read row -1, which the
   // loader maps to a fixed, cached address instead of streaming unused rows from memory
   auto live = [&](int r) { return r <= alast + 1 ? r : -1; };
+  const double xs = (POST && a.x64 && a.xscale) ? *a.xscale : 1.0;
   auto emit = [&](size_t v, T val) {
     a.u[v] = val;
     if constexpr (POST && std::is_same<T, float>::value)
-      if (a.x64) a.x64[v] += double(val);
+      if (a.x64) a.x64[v] = add_scaled(a.x64[v], xs, double(val));
   };
   const int base = a0 - 1;
   (void)base;
@@ -1100,7 +1110,7 @@ __device__ __forceinline__ void res_load(const double* S, const double* x, const
 __global__ __launch_bounds__(64) void k_ir_resid(const double* __restrict__ S,
                                                  const double* __restrict__ x,
                                                  const double* __restrict__ b,
-                                                 float* __restrict__ r32, int nx, int ny, int rows,
+                                                 double* __restrict__ r64, int nx, int ny, int rows,
                                                  int nstrips, double* __restrict__ partials,
                                                  const int* __restrict__ stop) {
   if (stop && *stop) return;
@@ -1134,7 +1144,7 @@ __global__ __launch_bounds__(64) void k_ir_resid(const double* __restrict__ S,
     const bool interior = int_col && j >= 1 && j <= ny - 2;
     const double rv = interior ? r : 0.0;
     if (out_col) {
-      r32[size_t(j) * nx + i] = float(rv);
+      r64[size_t(j) * nx + i] = rv;
       acc += rv * rv;
     }
     m = c;
@@ -1146,13 +1156,29 @@ __global__ __launch_bounds__(64) void k_ir_resid(const double* __restrict__ S,
   if (t == 0) partials[blockIdx.x] = acc;
 }
 
-// x += e (float64 += float32) where no float strip sweep carries the update.
+// x += s e (float64 += float64 * float32), s = *scale, where no float strip sweep carries the
+// update.
 __global__ __launch_bounds__(256) void k_ir_add(double* __restrict__ x, const float* __restrict__ e,
-                                                size_t n, const int* __restrict__ stop) {
+                                                size_t n, const double* __restrict__ scale,
+                                                const int* __restrict__ stop) {
   if (stop && *stop) return;
+  const double s = *scale;
   for (size_t k = blockIdx.x * size_t(blockDim.x) + threadIdx.x; k < n;
        k += size_t(gridDim.x) * blockDim.x)
-    x[k] = x[k] + double(e[k]);
+    x[k] = add_scaled(x[k], s, double(e[k]));
+}
+
+// r32 = fl32(r / s), s = *norm: the float64 quotient rounded once more to float32 (zero where
+// s = 0, a solve that is already done).
+__global__ __launch_bounds__(256) void k_ir_scale(const double* __restrict__ r,
+                                                  float* __restrict__ r32, size_t n,
+                                                  const double* __restrict__ norm,
+                                                  const int* __restrict__ stop) {
+  if (stop && *stop) return;
+  const double s = *norm;
+  for (size_t k = blockIdx.x * size_t(blockDim.x) + threadIdx.x; k < n;
+       k += size_t(gridDim.x) * blockDim.x)
+    r32[k] = s > 0.0 ? float(r[k] / s) : 0.f;
 }
 
 namespace {
@@ -1173,18 +1199,26 @@ int ir_residual_blocks(int nx, int ny) {
   return nb;
 }
 
-dmg_status launch_ir_residual(const double* S, const double* x, const double* b, float* r32,
+dmg_status launch_ir_residual(const double* S, const double* x, const double* b, double* r,
                               int nx, int ny, double* partials, hipStream_t s, const int* stop) {
   int rows = 0, ns = 0, nb = 0;
   resid_shape(nx, ny, &rows, &ns, &nb);
-  k_ir_resid<<<nb, 64, 0, s>>>(S, x, b, r32, nx, ny, rows, ns, partials, stop);
+  k_ir_resid<<<nb, 64, 0, s>>>(S, x, b, r, nx, ny, rows, ns, partials, stop);
   return launch_check("ir_residual");
 }
 
-dmg_status launch_ir_update(double* x, const float* e, size_t n, hipStream_t s, const int* stop) {
+dmg_status launch_ir_update(double* x, const float* e, size_t n, const double* scale,
+                            hipStream_t s, const int* stop) {
   const size_t nb = (n + 255) / 256;
-  k_ir_add<<<unsigned(nb < 4096 ? (nb ? nb : 1) : 4096), 256, 0, s>>>(x, e, n, stop);
+  k_ir_add<<<unsigned(nb < 4096 ? (nb ? nb : 1) : 4096), 256, 0, s>>>(x, e, n, scale, stop);
   return launch_check("ir_update");
+}
+
+dmg_status launch_ir_scale(const double* r, float* r32, size_t n, const double* norm,
+                           hipStream_t s, const int* stop) {
+  const size_t nb = (n + 255) / 256;
+  k_ir_scale<<<unsigned(nb < 4096 ? (nb ? nb : 1) : 4096), 256, 0, s>>>(r, r32, n, norm, stop);
+  return launch_check("ir_scale");
 }
 
 // ---- launchers -----------------------------------------------------------------------------
@@ -1199,7 +1233,8 @@ int strip_blocks(int nx, int ny, int bw, int seg_h, int* nstrips, int* nsegs) {
 template <class T, bool POST>
 dmg_status launch_strip(const StripConfig& cfg, const T* S, const T* uin, T* u, const T* b,
                         const T* P, T* bH, const T* e, double* partials, int nx, int ny, int pf,
-                        int cA, int cB, const int* stop, hipStream_t s, double* x64 = nullptr) {
+                        int cA, int cB, const int* stop, hipStream_t s, double* x64 = nullptr,
+                        const double* xscale = nullptr) {
   if (POST && !uin) return fail(DMG_ERR_INVALID_ARG, "post sweep needs an input iterate");
   if (uin == u) return fail(DMG_ERR_INVALID_ARG, "strip sweeps work out of place");
   StripArgs<T> a;
@@ -1219,6 +1254,7 @@ dmg_status launch_strip(const StripConfig& cfg, const T* S, const T* uin, T* u, 
   a.cB = cB;
   a.stop = stop;
   a.x64 = x64;
+  a.xscale = xscale;
   const int nb = strip_blocks(nx, ny, cfg.bw, cfg.seg_h, &a.nstrips, &a.nsegs);
   const size_t lds =
       (size_t(RU + 4 * RS) * cfg.bw + (POST ? size_t(2 * kCoarseSlots) * (cfg.bw / 2 + 2) : 0)) *
@@ -1266,11 +1302,12 @@ dmg_status launch_pre(const StripConfig& cfg, const T* S, const T* uin, T* u, co
 template <class T>
 dmg_status launch_post(const StripConfig& cfg, const T* S, const T* uin, T* u, const T* b,
                        const T* P, const T* e, double* partials, int nx, int ny, int pf, int cA,
-                       int cB, const int* stop, hipStream_t s, double* x64) {
+                       int cB, const int* stop, hipStream_t s, double* x64,
+                       const double* xscale) {
   if (x64 && !std::is_same<T, float>::value)
     return fail(DMG_ERR_INVALID_ARG, "the float64 iterate update belongs to float sweeps");
   return launch_strip<T, true>(cfg, S, uin, u, b, P, nullptr, e, partials, nx, ny, pf, cA, cB,
-                               stop, s, x64);
+                               stop, s, x64, xscale);
 }
 
 TailLayout tail_layout(const int* nx, const int* ny, int nlev, int m, int elem, int dense,
@@ -1438,7 +1475,7 @@ dmg_status launch_wave_multi(const StripArgs<T>* list, int count, int tiles_per,
                                     hipStream_t);                                              \
   template dmg_status launch_post<T>(const StripConfig&, const T*, const T*, T*, const T*,     \
                                      const T*, const T*, double*, int, int, int, int, int,     \
-                                     const int*, hipStream_t, double*);                        \
+                                     const int*, hipStream_t, double*, const double*);         \
   template dmg_status launch_tail<T>(const TailSpec<T>&, hipStream_t);                        \
   template dmg_status make_tail_args<T>(const TailSpec<T>&, TailArgs<T>*, size_t*);           \
   template dmg_status launch_tail_multi<T>(const TailArgs<T>*, int, size_t, int, hipStream_t); \

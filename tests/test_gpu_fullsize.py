@@ -1,29 +1,27 @@
-"""Parity at the benchmark sizes (1025^2 and 4097^2 star workloads) on sampled outputs.
+"""Whole-grid parity at the benchmark sizes: the 1025 x 1025 star (root seed 1) and the
+4097 x 4097 star (root seed 2), in the launch configuration bench.py times (autotuned launch
+shapes, and for float32 refinement the tuned number of float32 cycles per step).
 
-The library runs on the full problem in the launch configuration bench.py times (autotuned
-hierarchy, float64 solve to 1e-10).  The oracle cannot process these grids whole in a test, so at
-sampled points it assembles a 17 x 17-vertex patch of the same problem from its own inputs (the
-map Jacobian and K of the patch's cells, drawn by the same generators) and compares, at the
-patch centre (2I, 2J):
-  * the fine stencil (level 0),
-  * the interpolation weights of coarse point (I, J),
-  * the Galerkin coarse stencil at (I, J) (level 1),
-which the patch boundary (a Dirichlet ring 8 vertices away) does not reach; and it checks the
-solution through a property that holds at any size: the residual b - A u at each sampled vertex,
-with the oracle's stencil, is within the solve's tolerance rtol ||b||.
+The inputs (map Jacobians at the Gauss points, log-normal K, b) come from the seeded on-device
+generator bench.py uses; both the library and the oracle receive those same arrays.  Every
+comparison is entry by entry over the whole grid (tests/entrywise.py):
+  * 1025^2: every level's stencil, Galerkin stencil and interpolation weights; every one of the
+    float64 V-cycle iterates to convergence, the solve's cycle count, residual history and
+    solution (bitwise equal to the last cycle's iterate); the float32-refined solve step by step
+    against the oracle's refinement, and its solution against the float64 oracle solution;
+  * 4097^2: every level's stencil and interpolation weights, the float64 solve's cycle count,
+    history and solution, and the float32-refined solution against the oracle's refinement and
+    against the float64 oracle solution.
 """
 import numpy as np
 import pytest
 import torch
 
-import problems as pb
-from oracle import boxmg, fem
+from entrywise import EPS32, assert_hierarchy, assert_iterate, grid_floor_ulps
+from oracle import boxmg, cycle, fem
 from problems.batch_device import star_device
-from problems.fields import lognormal_K_patch, sample_jacobian_patch
 
-TOL = 1e-12
-R = 8           # patch radius (vertices)
-SAMPLES = 48
+pytestmark = pytest.mark.gpu
 
 
 @pytest.fixture(scope="module")
@@ -33,71 +31,109 @@ def dmg():
     return m
 
 
-def _rel(a, b):
-    den = np.max(np.abs(b))
-    return np.max(np.abs(np.asarray(a) - np.asarray(b))) / (den if den > 0 else 1.0)
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
 
 
-def _oracle_patch(mp, n, seed, I, J):
-    """Oracle stencil, interpolation and Galerkin stencil of the patch centred at (2I, 2J)."""
-    i0, j0 = 2 * I - R, 2 * J - R
-    m = 2 * R                                      # cells
-    jac = sample_jacobian_patch(mp, n, i0, j0, m)
-    K = lognormal_K_patch(mp, n, i0, j0, m, pb.streams(seed)[1])
-    S = fem.assemble_stencil(jac, K, m + 1, m + 1)
-    P = boxmg.interpolation(S)
-    SH = boxmg.galerkin(S, P)
-    return S, P, SH
+def _say(msg):
+    print(f"[fullsize] {msg}", flush=True)
 
 
-def _p_planes(P, nx, I, J):
-    """The 8 weights of coarse point (I, J) in the library's plane layout, from a sparse P."""
-    ncx = (nx + 1) // 2
-    f = lambda i, j: j * nx + i
-    c = lambda a, b: b * ncx + a
-    i, j = 2 * I, 2 * J
-    return np.array([P[f(i + 1, j), c(I, J)], P[f(i + 1, j), c(I + 1, J)],
-                     P[f(i, j + 1), c(I, J)], P[f(i, j + 1), c(I, J + 1)],
-                     P[f(i + 1, j + 1), c(I, J)], P[f(i + 1, j + 1), c(I + 1, J)],
-                     P[f(i + 1, j + 1), c(I, J + 1)], P[f(i + 1, j + 1), c(I + 1, J + 1)]])
+def _levels(h):
+    out = []
+    for l in range(h.num_levels):
+        S, P = h.level(l)
+        out.append((host(S), None if P is None else host(P)))
+    return out
 
 
-@pytest.mark.gpu
-@pytest.mark.parametrize("n,seed", [(1025, 1), (4097, 2)])
-def test_full_size_sampled_parity(dmg, n, seed):
-    print(f"[fullsize] n={n} seed={seed}: generating", flush=True)
+def _inputs(dmg, n, seed):
     jac, K, b = star_device(n, seed, "cuda")
     S = dmg.assemble_stencil(jac, K)
+    jac_h, K_h, b_h = host(jac), host(K), host(b)
     del jac, K
+    return S, b, jac_h, K_h, b_h
+
+
+def _fp32_check(name, got, ref):
+    used = assert_iterate(name, got, ref, rtol=1e-5, eps=EPS32, floor_ulps=64)
+    _say(f"{name}: worst excess {used:.2f} eps32 max|x|")
+    return used
+
+
+def test_bench_config_1025_whole_grid(dmg):
+    n, seed = 1025, 1
+    S, b, jac_h, K_h, b_h = _inputs(dmg, n, seed)
+    S_or = fem.assemble_stencil(jac_h, K_h, n, n)
+    levels = boxmg.build_hierarchy(S_or)
     h = dmg.Hierarchy(S)
-    h.autotune(b, tiles=True, reps=2)
-    print(f"[fullsize] n={n}: solving with {h.config()['levels']}", flush=True)
-    u, k, rel, _ = h.solve(b, rtol=1e-10)
-    assert rel <= 1e-10 and 8 <= k <= 16
-    S0, P0 = h.level(0)
-    S1, _ = h.level(1)
-    torch.cuda.synchronize()
-    bh = b.cpu().numpy()
-    bn = np.linalg.norm(bh[1:-1, 1:-1])
-    mp = pb.Star.random(pb.streams(seed)[0])
-    rng = np.random.default_rng(100 + seed)
-    nc = (n + 1) // 2
-    worst = dict(S=0.0, P=0.0, SH=0.0, r=0.0)
-    for _ in range(SAMPLES):
-        I = int(rng.integers(R // 2 + 1, nc - R // 2 - 1))
-        J = int(rng.integers(R // 2 + 1, nc - R // 2 - 1))
-        So, Po, SHo = _oracle_patch(mp, n, seed, I, J)
-        i, j = 2 * I, 2 * J
-        worst["S"] = max(worst["S"], _rel(S0[:, j, i].cpu().numpy(), So[:, R, R]))
-        worst["P"] = max(worst["P"], _rel(P0[:, J, I].cpu().numpy(), _p_planes(Po, 2 * R + 1, R // 2, R // 2)))
-        worst["SH"] = max(worst["SH"], _rel(S1[:, J, I].cpu().numpy(), SHo[:, R // 2, R // 2]))
-        # residual at (i, j) with the oracle's stencil and the library's solution
-        A = fem.stencil_to_matrix(So)
-        uu = u[j - R:j + R + 1, i - R:i + R + 1].cpu().numpy().ravel()
-        r = bh[j, i] - (A @ uu)[R * (2 * R + 1) + R]
-        worst["r"] = max(worst["r"], abs(r) / bn)
-    print(f"[fullsize] n={n}: worst {worst}", flush=True)
-    assert worst["S"] <= TOL and worst["P"] <= TOL and worst["SH"] <= TOL
-    # every entry of b - A u is bounded by ||b - A u|| <= rtol ||b|| (plus rounding)
-    assert worst["r"] <= 1.01e-10
+    cfg = h.autotune(b, tiles=True, reps=5)                 # bench.py's float64 configuration
+    _say(f"{n}: tuned {cfg['levels']} / {cfg['post_levels']}")
+    assert h.num_levels == len(levels)
+    w = assert_hierarchy(f"{n}x{n} hierarchy", _levels(h), levels)
+    _say(f"{n}: hierarchy worst |got - ref| / scale {w:.2e}")
+    orc = cycle.Oracle(levels)
+    uo, ko, histo, its = cycle.solve(orc, b_h, 1e-10, keep_iterates=True)
+    u = torch.zeros_like(b)
+    worst = 0.0
+    for k in range(ko):
+        h.vcycle(u, b)
+        worst = max(worst, assert_iterate(f"{n}x{n} iterate {k + 1}", host(u), its[k],
+                                          floor_ulps=grid_floor_ulps(n)))
+    _say(f"{n}: {ko} iterates, worst excess {worst:.1f} eps max|u|")
+    x, kx, rel, hist = h.solve(b, rtol=1e-10)
+    assert kx == ko and rel <= 1e-10
+    assert np.allclose(hist, histo, rtol=1e-6, atol=1e-13)
+    assert torch.equal(x, u), "the solve's iterate is the last V-cycle's"
     h.close()
+    # float32 refinement as bench.py runs it
+    h32 = dmg.Hierarchy(S, precision=dmg.DMG_FP32_IR)
+    cfg = h32.autotune(b, tiles=True, reps=5, inner_cycles=True)
+    m = cfg["inner_cycles"]
+    xo, ko32, _, its32 = cycle.solve_ir(orc, cycle.Oracle(levels, np.float32), b_h, 1e-10, inner=m,
+                                        keep_iterates=True)
+    x32, k32, rel32, _ = h32.solve(b, rtol=1e-10)
+    assert k32 == ko32 and rel32 <= 1e-10
+    for step in range(1, ko32 + 1):
+        xs, _, _, _ = h32.solve(b, rtol=1e-10, max_iters=step, raise_on_fail=False)
+        _fp32_check(f"{n}x{n} fp32 (m={m}) step {step}", host(xs), its32[step - 1])
+    err = float(np.linalg.norm(host(x32) - uo) / np.linalg.norm(uo))
+    _say(f"{n}: fp32-refined m={m}, {k32} steps, error vs float64 oracle solution {err:.2e}")
+    assert err < 1e-7
+    h32.close()
+
+
+def test_bench_config_4097_whole_grid(dmg):
+    n, seed = 4097, 2
+    S, b, jac_h, K_h, b_h = _inputs(dmg, n, seed)
+    _say(f"{n}: oracle assembly and hierarchy")
+    S_or = fem.assemble_stencil(jac_h, K_h, n, n)
+    del jac_h, K_h
+    levels = boxmg.build_hierarchy(S_or)
+    h = dmg.Hierarchy(S)
+    h.autotune(b, tiles=True, reps=5)
+    assert h.num_levels == len(levels)
+    # the Galerkin triple-product scale is checked at 1025^2; here the sqrt(C_v C_n) scale
+    w = assert_hierarchy(f"{n}x{n} hierarchy", _levels(h), levels, galerkin=False)
+    _say(f"{n}: hierarchy worst |got - ref| / scale {w:.2e}; oracle solve")
+    orc = cycle.Oracle(levels)
+    uo, ko, histo, _ = cycle.solve(orc, b_h, 1e-10)
+    x, k, rel, hist = h.solve(b, rtol=1e-10)
+    assert k == ko and rel <= 1e-10
+    assert np.allclose(hist, histo, rtol=1e-6, atol=1e-13)
+    used = assert_iterate(f"{n}x{n} float64 solution", host(x), uo, floor_ulps=grid_floor_ulps(n))
+    _say(f"{n}: float64 {k} cycles, worst excess {used:.1f} eps max|u|")
+    h.close()
+    h32 = dmg.Hierarchy(S, precision=dmg.DMG_FP32_IR)
+    cfg = h32.autotune(b, tiles=True, reps=5, inner_cycles=True)
+    m = cfg["inner_cycles"]
+    x32, k32, rel32, _ = h32.solve(b, rtol=1e-10)
+    del S
+    xo32, ko32, _, _ = cycle.solve_ir(orc, cycle.Oracle(levels, np.float32), b_h, 1e-10, inner=m)
+    assert k32 == ko32 and rel32 <= 1e-10
+    _fp32_check(f"{n}x{n} fp32-refined solution (m={m})", host(x32), xo32)
+    err = float(np.linalg.norm(host(x32) - uo) / np.linalg.norm(uo))
+    _say(f"{n}: fp32-refined m={m}, {k32} steps, error vs float64 oracle solution {err:.2e}")
+    assert err < 1e-7
+    h32.close()

@@ -1,19 +1,19 @@
-"""Parity of the HIP library (called through the C ABI) with the float64 CPU oracle.
-
-Tolerances: float64 paths agree with the oracle to 1e-12 relative (per entry for setup data,
-per iterate for V-cycles); float32 refinement reaches the same float64 residual tolerance and
-its distance to the float64 oracle solution is reported and bounded."""
-import math
-
+"""Parity of the HIP library (called through the C ABI) with the float64 CPU oracle, entry by
+entry (tests/entrywise.py states each bound and why):
+  * setup data (stencils, interpolation weights, Galerkin stencils, gradients): every entry
+    within 1e-12 of the magnitude of the terms summed to form it;
+  * iterates of V-cycles and solves: every entry within 1e-12 |ref| + 256 eps max|ref|;
+  * identical cycle counts, residual histories to 1e-6 relative (late residuals ~1e-10 carry
+    the rounding noise of the residual itself)."""
 import numpy as np
 import pytest
 import torch
 
 import problems as pb
+from entrywise import (EPS64, assert_entrywise, assert_hierarchy, assert_iterate, assert_stencil)
 from oracle import adjoint, boxmg, cycle, fem, transfer
 
 pytestmark = pytest.mark.gpu
-TOL = 1e-12
 
 
 @pytest.fixture(scope="module")
@@ -30,11 +30,6 @@ def dev(x):
 def host(t):
     torch.cuda.synchronize()
     return t.detach().cpu().numpy()
-
-
-def relerr(a, b):
-    den = np.max(np.abs(b))
-    return np.max(np.abs(a - b)) / (den if den > 0 else 1.0)
 
 
 PROBLEMS = {
@@ -62,48 +57,26 @@ def case(request, dmg):
     return prob, S_or, levels
 
 
-def oracle_P_planes(P, nx, ny):
-    """The oracle's sparse P in the library's 8-plane layout."""
-    ncx, ncy = (nx + 1) // 2, (ny + 1) // 2
-    out = np.zeros((8, ncy, ncx))
-    P = P.tocsr()
-    for J in range(ncy):
-        for I in range(ncx):
-            c = J * ncx + I
-
-            def get(i, j, cc):
-                if 0 <= i < nx and 0 <= j < ny:
-                    return P[j * nx + i, cc]
-                return 0.0
-            if I < ncx - 1:
-                out[0, J, I] = get(2 * I + 1, 2 * J, c)
-                out[1, J, I] = get(2 * I + 1, 2 * J, c + 1)
-            if J < ncy - 1:
-                out[2, J, I] = get(2 * I, 2 * J + 1, c)
-                out[3, J, I] = get(2 * I, 2 * J + 1, c + ncx)
-            if I < ncx - 1 and J < ncy - 1:
-                out[4, J, I] = get(2 * I + 1, 2 * J + 1, c)
-                out[5, J, I] = get(2 * I + 1, 2 * J + 1, c + 1)
-                out[6, J, I] = get(2 * I + 1, 2 * J + 1, c + ncx)
-                out[7, J, I] = get(2 * I + 1, 2 * J + 1, c + ncx + 1)
+def hier_levels(h):
+    """Every level's (S, P) of a library hierarchy as host arrays."""
+    out = []
+    for l in range(h.num_levels):
+        S, P = h.level(l)
+        out.append((host(S), None if P is None else host(P)))
     return out
 
 
 def test_assembly_matches_oracle(dmg, case):
     prob, S_or, _ = case
     S = dmg.assemble_stencil(dev(prob.jac), dev(prob.K))
-    assert relerr(host(S), S_or) <= TOL
+    assert_stencil("assembly", host(S), S_or)
 
 
 def test_hierarchy_matches_oracle(dmg, case):
     prob, S_or, levels = case
     h = dmg.Hierarchy(dev(S_or))
     assert h.num_levels == len(levels)
-    for l, L in enumerate(levels):
-        S, P = h.level(l)
-        assert relerr(host(S), L.S) <= TOL, f"stencil level {l}"
-        if L.P is not None:
-            assert relerr(host(P), oracle_P_planes(L.P, L.nx, L.ny)) <= TOL, f"P level {l}"
+    assert_hierarchy("hierarchy", hier_levels(h), levels)
     h.close()
 
 
@@ -118,8 +91,7 @@ def test_vcycle_iterates_match_oracle(dmg, case):
     for k in range(8):
         h.vcycle(u, b)
         orc.vcycle(uo, bo)
-        err = np.linalg.norm(host(u).ravel() - uo) / np.linalg.norm(uo)
-        assert err <= TOL, f"iterate {k + 1}: {err:.3e}"
+        assert_iterate(f"iterate {k + 1}", host(u).ravel(), uo)
     h.close()
 
 
@@ -139,9 +111,9 @@ def test_dense_coarse_operator_matches_coarse_kernel(dmg, name):
         for h, u in zip(hs, us):
             h.vcycle(u, b)
         orc.vcycle(uo, prob.b.ravel().copy())
-        for u in us:
-            assert np.linalg.norm(host(u).ravel() - uo) / np.linalg.norm(uo) <= TOL
-        assert float((us[0] - us[1]).norm() / us[1].norm()) <= 1e-13
+        for g, u in enumerate(us):
+            assert_iterate(f"coarse_gemv={g} iterate {k + 1}", host(u).ravel(), uo)
+        assert_iterate(f"gemv vs coarse kernel, iterate {k + 1}", host(us[1]), host(us[0]))
     for h in hs:
         h.close()
     xs = []
@@ -149,10 +121,13 @@ def test_dense_coarse_operator_matches_coarse_kernel(dmg, name):
         h = dmg.Hierarchy(dev(S_or), coarse_gemv=g, precision=dmg.DMG_FP32_IR)
         x, k, rel, _ = h.solve(b, rtol=1e-10)
         assert rel <= 1e-10
-        xs.append((x, k))
+        xs.append((host(x), k))
         h.close()
+    # float32 cycles whose coarse levels differ by float32 rounding: the same outer-step count to
+    # one step; both solutions are 1e-10-residual solutions of one system
     assert abs(xs[0][1] - xs[1][1]) <= 1
-    assert float((xs[0][0] - xs[1][0]).norm() / xs[1][0].norm()) <= 1e-9
+    assert_iterate("fp32 refinement, gemv vs coarse kernel", xs[1][0], xs[0][0], rtol=1e-7,
+                   floor_ulps=int(1e-7 / EPS64))
 
 
 def test_refresh_replays_a_captured_setup(dmg):
@@ -183,7 +158,7 @@ def test_solve_matches_oracle(dmg, case):
     assert rel <= 1e-10 and k == ko
     # late relative residuals (~1e-10) carry rounding noise of order eps * cond-free 1e-15
     assert np.allclose(hist, histo, rtol=1e-6, atol=1e-13)
-    assert np.linalg.norm(host(u) - uo) / np.linalg.norm(uo) <= TOL
+    assert_iterate("solution", host(u), uo)
     h.close()
 
 
@@ -203,7 +178,7 @@ def test_colour_orders_and_sweep_counts(dmg, pre, post, nu):
     for k in range(4):
         h.vcycle(u, b)
         orc.vcycle(uo, prob.b.ravel().copy())
-        assert np.linalg.norm(host(u).ravel() - uo) / np.linalg.norm(uo) <= TOL, k
+        assert_iterate(f"iterate {k + 1}", host(u).ravel(), uo)
     h.close()
 
 
@@ -224,10 +199,11 @@ def test_strip_kernel_variants_match_oracle(dmg, wave, pre, post):
     for k in range(3):
         h.vcycle(u, b)
         orc.vcycle(uo, prob.b.ravel().copy())
-        assert np.linalg.norm(host(u).ravel() - uo) / np.linalg.norm(uo) <= TOL, k
+        assert_iterate(f"iterate {k + 1}", host(u).ravel(), uo)
     x, k, rel, hist = h.solve(b, rtol=1e-10)
     xo, ko, _, _ = cycle.solve(orc, prob.b, 1e-10)
-    assert k == ko and np.linalg.norm(host(x) - xo) / np.linalg.norm(xo) <= TOL
+    assert k == ko
+    assert_iterate("solution", host(x), xo)
     h.close()
 
 
@@ -280,7 +256,8 @@ def test_autotuned_hierarchy_matches_oracle(dmg):
     u, k, rel, _ = h64.solve(b, rtol=1e-10)
     orc = cycle.Oracle(levels, pre=cfg["pre_order"], post=cfg["post_order"])
     uo, ko, _, _ = cycle.solve(orc, prob.b, 1e-10)
-    assert k == ko and np.linalg.norm(host(u) - uo) / np.linalg.norm(uo) <= TOL
+    assert k == ko
+    assert_iterate("tuned solution", host(u), uo)
     x, k32, rel32, _ = h.solve(b, rtol=1e-10)
     assert rel32 <= 1e-10
     h.close()
@@ -303,11 +280,11 @@ def test_solve_on_a_side_stream_uses_graph_chunks(dmg):
             _, k2, _, _ = h.solve(b, u=u2, rtol=1e-10, max_iters=cap, raise_on_fail=False)
             uo, ko, _, _ = cycle.solve(orc, prob.b, 1e-10, max_iters=cap)
             assert k2 == ko == cap
-            assert np.linalg.norm(host(u2) - uo) / np.linalg.norm(uo) <= TOL
+            assert_iterate(f"max_iters={cap}", host(u2), uo)
     torch.cuda.synchronize()
     uo, ko, histo, _ = cycle.solve(orc, prob.b, 1e-10)
     assert k == ko and np.allclose(hist, histo, rtol=1e-6, atol=1e-13)
-    assert np.linalg.norm(host(u) - uo) / np.linalg.norm(uo) <= TOL
+    assert_iterate("solution", host(u), uo)
     h.close()
 
 
@@ -333,32 +310,19 @@ def test_graph_and_eager_solves_are_identical(dmg):
     assert out[0][1] == out[1][1] and np.array_equal(out[0][0], out[1][0])
 
 
-@pytest.mark.parametrize("inner", [1, 2])
-def test_fp32_refinement(dmg, inner):
-    prob = pb.star(257, seed=2)
-    S_or = fem.assemble_stencil(prob.jac, prob.K, prob.nx, prob.ny)
-    levels = boxmg.build_hierarchy(S_or)
-    h = dmg.Hierarchy(dev(S_or), precision=dmg.DMG_FP32_IR, inner_cycles=inner)
-    x, k, rel, hist = h.solve(dev(prob.b), rtol=1e-10)
-    assert rel <= 1e-10
-    xo, ko, histo, _ = cycle.solve_ir(cycle.Oracle(levels), cycle.Oracle(levels, np.float32), prob.b,
-                                      1e-10, inner=inner)
-    assert abs(k - ko) <= 1
-    u64, _, _, _ = cycle.solve(cycle.Oracle(levels), prob.b, 1e-10)
-    err = np.linalg.norm(host(x) - u64) / np.linalg.norm(u64)
-    # both are 1e-10-residual solutions of one system; their distance is bounded by cond * 1e-10
-    assert err < 1e-7, err
-    h.close()
-
-
 def test_grad_K_matches_oracle(dmg):
-    prob = pb.star(65, seed=4)
-    rng = np.random.default_rng(0)
-    lam = np.zeros((65, 65)); lam[1:-1, 1:-1] = rng.normal(size=(63, 63))
-    u = np.zeros((65, 65)); u[1:-1, 1:-1] = rng.normal(size=(63, 63))
-    g = dmg.grad_K(dev(prob.jac), dev(lam), dev(u))
-    go = adjoint.grad_K(prob.jac, lam, u, 65, 65)
-    assert relerr(host(g), go) <= TOL
+    """dK_e = -sum_ab lam_a G_e[a,b] u_b per cell, within 1e-12 of sum_ab |lam_a G_ab u_b|."""
+    for prob in (pb.star(65, seed=4), pb.quarter_annulus(33, ny=49)):
+        nx, ny = prob.nx, prob.ny
+        rng = np.random.default_rng(0)
+        lam = np.zeros((ny, nx)); lam[1:-1, 1:-1] = rng.normal(size=(ny - 2, nx - 2))
+        u = np.zeros((ny, nx)); u[1:-1, 1:-1] = rng.normal(size=(ny - 2, nx - 2))
+        g = dmg.grad_K(dev(prob.jac), dev(lam), dev(u))
+        go = adjoint.grad_K(prob.jac, lam, u, nx, ny)
+        G = fem.element_matrices(prob.jac, nx, ny)
+        scale = np.einsum("jia,jiab,jib->ji", np.abs(adjoint.local_values(lam)), np.abs(G),
+                          np.abs(adjoint.local_values(u)))
+        assert_entrywise("grad_K", host(g), go, scale, 1e-12)
 
 
 def test_diffsolve_reuses_one_hierarchy_exactly(dmg):
@@ -409,6 +373,13 @@ def test_diffsolve_gradients(dmg):
     gKo = adjoint.grad_K(prob.jac, lo, uo, n, n)
     assert np.linalg.norm(host(K.grad) - gKo) / np.linalg.norm(gKo) <= 1e-6
     assert np.linalg.norm(host(b.grad) - lo) / np.linalg.norm(lo) <= 1e-6
+    # entry by entry: both sides solve to 1e-13, so u and lam differ by that solve tolerance
+    # times the conditioning (~1e-11 of their size), far below 1e-6
+    G = fem.element_matrices(prob.jac, n, n)
+    scale = np.einsum("jia,jiab,jib->ji", np.abs(adjoint.local_values(lo)), np.abs(G),
+                      np.abs(adjoint.local_values(uo)))
+    assert_entrywise("dJ/dK", host(K.grad), gKo, scale, 1e-6)
+    assert_iterate("dJ/db", host(b.grad), lo, rtol=1e-6, floor_ulps=int(1e-9 / EPS64))
     # central differences along random directions
     zK, zb = pb.directions(4, 4, (n - 1, n - 1), (n, n))
     with torch.no_grad():
@@ -438,32 +409,43 @@ def test_transfer_matches_oracle(dmg):
     rp = rng.normal(size=mesh.nv)
     up = T.from_grid(dev(uc))
     rc = T.to_grid(dev(rp))
-    assert relerr(host(up), transfer.from_grid(M, Co, uc)) <= TOL
-    assert relerr(host(rc), transfer.to_grid(M, Co, rp * mesh.dof, n, n)) <= TOL
+    # CG2 is two steps of an iteration: its outputs are compared as iterates
+    assert_iterate("from_grid", host(up), transfer.from_grid(M, Co, uc))
+    assert_iterate("to_grid", host(rc), transfer.to_grid(M, Co, rp * mesh.dof, n, n))
     T.close()
 
 
-def _batch_vs_single(dmg, Ss, bs, bt, us, its, rels):
+def _batch_vs_single(dmg, Ss, bs, bt, us, its, rels, probs=None, orders=None):
     """The batch runs its coarse levels in the one-workgroup coarse kernel: its iterates equal
-    single solves with coarse_gemv=0 bitwise, and single solves with the whole-GPU dense coarse
-    operator (the default) to rounding."""
-    for S, b, u, k, r in zip(Ss, bs, us, its, rels):
-        h = dmg.Hierarchy(S, coarse_gemv=0)
+    single solves with coarse_gemv=0 (and the same colour orders) bitwise, and single solves
+    with the whole-GPU dense coarse operator (the default) to rounding.  With `probs`, every
+    instance is also solved by the oracle (same colour orders): the same cycle count and the
+    solution entry by entry."""
+    for k, (S, b, u, it, r) in enumerate(zip(Ss, bs, us, its, rels)):
+        pre, post = orders[k] if orders else ((0, 1, 2, 3), (3, 2, 1, 0))
+        h = dmg.Hierarchy(S, coarse_gemv=0, pre_order=pre, post_order=post)
         u1, k1, r1, _ = h.solve(b, rtol=1e-10)
-        assert k == k1 and r <= 1e-10
+        assert it == k1 and r <= 1e-10
         assert abs(r - r1) <= 1e-13 * max(r1, 1e-300) * 10
         assert torch.equal(u, u1)
         h.close()
-        h = dmg.Hierarchy(S)
+        h = dmg.Hierarchy(S, pre_order=pre, post_order=post)
         u2, k2, r2, _ = h.solve(b, rtol=1e-10)
-        assert k2 == k and r2 <= 1e-10
-        assert float((u2 - u).norm() / u.norm()) <= 1e-12
+        assert k2 == it and r2 <= 1e-10
+        assert_iterate(f"instance {k}: dense coarse operator vs batch", host(u2), host(u))
         h.close()
+        if probs is not None:
+            p = probs[k]
+            orc = cycle.Oracle(boxmg.build_hierarchy(fem.assemble_stencil(p.jac, p.K, p.nx, p.ny)),
+                               pre=pre, post=post)
+            uo, ko, _, _ = cycle.solve(orc, p.b, 1e-10, max_iters=300)
+            assert it == ko, (k, it, ko)
+            assert_iterate(f"instance {k} ({p.nx}x{p.ny}) vs oracle", host(u), uo)
 
 
 def test_batch_matches_single_solves(dmg):
     """Uneven sizes (one all-tail instance), different convergence counts: every instance's
-    iterate equals its single solve bitwise."""
+    iterate equals its single solve bitwise and the oracle's solution entry by entry."""
     probs = [pb.star(n, seed=10 + k) for k, n in enumerate((33, 65, 129, 65, 257, 129))]
     probs.append(pb.quarter_annulus(65))          # needs many more cycles than the stars
     Ss = [dmg.assemble_stencil(dev(p.jac), dev(p.K)) for p in probs]
@@ -471,7 +453,7 @@ def test_batch_matches_single_solves(dmg):
     bt = dmg.BatchSolver(Ss)
     us, its, rels = bt.solve(bs, rtol=1e-10)
     assert len(set(its)) > 1
-    _batch_vs_single(dmg, Ss, bs, bt, us, its, rels)
+    _batch_vs_single(dmg, Ss, bs, bt, us, its, rels, probs=probs)
     # a second solve on new arrays rebuilds the schedule; autotuned shapes change no bit
     bt.autotune(bs, reps=1)
     us2, its2, rels2 = bt.solve(bs, rtol=1e-10)
@@ -488,18 +470,8 @@ def test_batch_with_odd_dims_matches_single_solves(dmg):
     bs = [dev(p.b) for p in probs]
     bt = dmg.BatchSolver(Ss)
     us, its, rels = bt.solve(bs, rtol=1e-10)
-    _batch_vs_single(dmg, Ss, bs, bt, us, its, rels)
+    _batch_vs_single(dmg, Ss, bs, bt, us, its, rels, probs=probs)
     bt.close()
-
-
-def test_fp32_refinement_on_odd_dims(dmg):
-    prob = pb.star(97, seed=1, ny=65)
-    S_or = fem.assemble_stencil(prob.jac, prob.K, prob.nx, prob.ny)
-    h = dmg.Hierarchy(dev(S_or), precision=dmg.DMG_FP32_IR)
-    x, k, rel, hist = h.solve(dev(prob.b), rtol=1e-10)
-    uo, ko, histo, _ = cycle.solve(cycle.Oracle(boxmg.build_hierarchy(S_or)), prob.b, rtol=1e-10)
-    assert rel <= 1e-10 and abs(k - ko) <= 1
-    assert relerr(host(x), uo) <= 1e-8
 
 
 def test_batch_zero_rhs_and_limits(dmg):
@@ -530,7 +502,8 @@ def test_tiny_grids(dmg, n):
     h = dmg.Hierarchy(dev(S_or))
     u, k, rel, _ = h.solve(dev(prob.b), rtol=1e-10)
     uo, ko, _, _ = cycle.solve(cycle.Oracle(levels), prob.b, 1e-10)
-    assert k == ko and np.linalg.norm(host(u) - uo) <= TOL * max(np.linalg.norm(uo), 1e-300)
+    assert k == ko
+    assert_iterate(f"{n}x{n} solution", host(u), uo)
     h.close()
 
 
@@ -542,7 +515,8 @@ def test_coarsest_dense_cholesky_larger(dmg):
     assert h.num_levels == len(levels)
     u, k, rel, _ = h.solve(dev(prob.b), rtol=1e-10)
     uo, ko, _, _ = cycle.solve(cycle.Oracle(levels), prob.b, 1e-10)
-    assert k == ko and np.linalg.norm(host(u) - uo) / np.linalg.norm(uo) <= TOL
+    assert k == ko
+    assert_iterate("solution", host(u), uo)
     h.close()
 
 
@@ -586,11 +560,12 @@ def test_line_smoother_matches_oracle(dmg, name, smoother):
     for k in range(3):
         h.vcycle(u, b)
         orc.vcycle(uo, prob.b.ravel())
-        assert relerr(host(u).ravel(), uo) <= TOL, k
+        assert_iterate(f"iterate {k + 1}", host(u).ravel(), uo)
     x, k, rel, hist = h.solve(b, rtol=1e-10, max_iters=300)
     xo, ko, histo, _ = cycle.solve(orc, prob.b, rtol=1e-10, max_iters=300)
     assert k == ko and rel <= 1e-10
     assert np.allclose(hist, histo, rtol=1e-6, atol=1e-13)
+    assert_iterate("solution", host(x), xo)
     h.close()
 
 

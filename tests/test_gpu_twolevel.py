@@ -1,17 +1,17 @@
 """Parity of the two-level cycle on the physical mesh (HIP library through the C ABI) with the
 float64 oracle (oracle/dmg.py) on star-domain meshes: the relaxation colours bit for bit, every
-iterate to 1e-12 relative for both mass modes, whole solves (cycle counts, residual histories,
-solutions), the zero-residual start, the iteration cap, and the captured-graph path against the
-eager one."""
+iterate entry by entry (1e-12 |ref| + 256 eps max|ref|, tests/entrywise.py) for both mass modes
+and both coupled-mass rules, whole solves (cycle counts, residual histories, solutions), the
+zero-residual start, the iteration cap, and the captured-graph path against the eager one."""
 import numpy as np
 import pytest
 import torch
 
 import problems as pb
+from entrywise import assert_iterate
 from oracle import boxmg, cycle, dmg, fem, transfer
 
 pytestmark = pytest.mark.gpu
-TOL = 1e-12
 
 
 @pytest.fixture(scope="module")
@@ -28,11 +28,6 @@ def dev(x):
 def host(t):
     torch.cuda.synchronize()
     return t.detach().cpu().numpy()
-
-
-def relerr(a, b):
-    den = np.max(np.abs(b))
-    return np.max(np.abs(a - b)) / (den if den > 0 else 1.0)
 
 
 _CACHE = {}
@@ -67,10 +62,15 @@ def test_colouring_and_operator_size(lib):
 
 
 @pytest.mark.parametrize("n,mass,nq", [(17, "lumped", 0), (33, "lumped", 0), (17, "cg2", 0),
-                                       (33, "cg2", 0), (33, "lumped", 8), (65, "lumped", 0)])
+                                       (33, "cg2", 0), (33, "lumped", 8), (65, "lumped", 0),
+                                       (33, "cg2", 4)])
 def test_cycles_match_oracle(lib, n, mass, nq):
     """65 x 65 is the smallest grid whose finest level runs in the strip kernels (smaller grids
-    run whole in the one-workgroup coarse kernel)."""
+    run whole in the one-workgroup coarse kernel).  (cg2, nq = 4) is the paper's own
+    configuration: two CG iterations on M_p and the rasterised coupled mass.  On larger star
+    meshes that cycle diverges (its coarse correction over-corrects modes whose generalized
+    eigenvalue of (P^T A_p P, A_c) exceeds 2), and a divergent iteration multiplies the rounding
+    difference of two implementations every cycle, so it is compared here at 33^2 only."""
     P, orc, tl = pair(lib, n, mass=mass, nq=nq)
     g = np.random.Generator(np.random.PCG64(11))
     u0 = np.where(P.mesh.dof, g.uniform(-1, 1, P.mesh.nv), 0.0)
@@ -80,8 +80,8 @@ def test_cycles_match_oracle(lib, n, mass, nq):
     for k in range(3):
         orc.cycle(uo, P.f)
         tl.cycle(ug, fg)
-        e = relerr(host(ug), uo)
-        assert e <= TOL, f"cycle {k + 1}: {e:.3e}"
+        used = assert_iterate(f"cycle {k + 1}", host(ug), uo)
+        print(f"[twolevel] n={n} {mass} nq={nq} cycle {k + 1}: worst excess {used:.1f} eps max|u|")
 
 
 @pytest.mark.parametrize("n", [17, 33])
@@ -91,7 +91,7 @@ def test_solve_matches_oracle(lib, n):
     uo, ko, histo, _ = dmg.solve(orc, P.f, rtol=1e-10)
     assert k == ko and rel <= 1e-10
     assert np.allclose(hist, histo, rtol=1e-6, atol=1e-13)
-    assert relerr(host(u), uo) <= 1e-11
+    assert_iterate("solution", host(u), uo)
 
 
 def test_solve_from_random_guess_with_zero_rhs(lib):
@@ -116,7 +116,7 @@ def test_zero_initial_residual_and_iteration_cap(lib):
     u, k, rel, hist = tl.solve(dev(P.f), rtol=1e-30, max_iters=3, raise_on_fail=False)
     uo, ko, histo, _ = dmg.solve(orc, P.f, rtol=1e-30, max_iters=3)
     assert k == ko == 3 and np.allclose(hist, histo, rtol=1e-6, atol=1e-13)
-    assert relerr(host(u), uo) <= TOL
+    assert_iterate("capped solve", host(u), uo)
     with pytest.raises(lib.DmgError):
         tl.solve(dev(P.f), rtol=1e-30, max_iters=2)
 
@@ -163,7 +163,7 @@ def test_scaled_cycles_match_oracle(lib, n, mass):
         for k in range(3):
             orc.cycle(uo, P.f)
             tl.cycle(ug, fg)
-            assert relerr(host(ug), uo) <= TOL, k
+            assert_iterate(f"scaled cycle {k + 1}", host(ug), uo)
     finally:
         orc.gamma = 1.0
         tl.set_scaling(1.0)
@@ -206,4 +206,4 @@ def test_discontinuous_cycles_match_oracle(lib, kind):
     for k in range(2):
         orc.cycle(uo, P.f)
         tl.cycle(ug, fg)
-        assert relerr(host(ug), uo) <= TOL, k
+        assert_iterate(f"{kind} cycle {k + 1}", host(ug), uo)
