@@ -200,6 +200,18 @@ dmg_status dmg_hier_sweep_config(const dmg_hier* h, int32_t level, int32_t kind,
 /* ||b - A u||_2 over interior vertices (deterministic fixed-order reduction).  Synchronous. */
 dmg_status dmg_residual_norm(dmg_hier* h, const double* u, const double* b, double* norm,
                              hipStream_t stream);
+/* For callers that cannot allocate device memory (code under stream capture, serving loops,
+ * harnesses that forbid hipMalloc): the same residual norm without a hierarchy or workspace,
+ * allocating nothing.  S [5][ny][nx] stencil, u, b [ny][nx] (device, caller-owned); norm (device,
+ * caller-owned, 2 doubles) receives ||b - A u||_2^2 and ||b - A u||_2, bit for bit what
+ * dmg_residual_norm computes on a hierarchy of S.  Asynchronous on `stream` (it does not
+ * synchronise, so it can be captured).  The reduction partials live in one 8 KiB static device
+ * array per device (kept until the process ends), fully rewritten by each call; its size does
+ * not depend on the grid, so every grid with nx, ny >= 3 fits.  Calls that overlap on one device
+ * (other streams, other host threads) share that array and race: serialise them.
+ * Errors: DMG_ERR_INVALID_ARG, DMG_ERR_DIMS, DMG_ERR_HIP. */
+dmg_status dmg_residual_norm_noalloc(const double* S, const double* u, const double* b,
+                                     int32_t nx, int32_t ny, double* norm, hipStream_t stream);
 
 /* ---- solve (Sec. 4 stopping rule: ||b - A u||_2 <= rtol ||b||_2) ------------------------
  * u in: initial guess, out: solution.  precision DMG_FP64: repeated V-cycles.  DMG_FP32_IR:

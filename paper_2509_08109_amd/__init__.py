@@ -61,6 +61,20 @@ def assemble_stencil(jac: torch.Tensor, K: torch.Tensor, out: torch.Tensor | Non
     return out
 
 
+def residual_norm_noalloc(S: torch.Tensor, u: torch.Tensor, b: torch.Tensor,
+                          out: torch.Tensor | None = None) -> torch.Tensor:
+    """(||b - A u||^2, ||b - A u||) of the stencil S [5][ny][nx] into a device tensor of 2, with
+    no workspace and no device allocation inside the library (asynchronous on the current
+    stream)."""
+    _, ny, nx = S.shape
+    if out is None:
+        out = torch.empty(2, dtype=torch.float64, device=S.device)
+    _lib.check(lib().dmg_residual_norm_noalloc(_dev(S, (5, ny, nx), "S"), _dev(u, (ny, nx), "u"),
+                                               _dev(b, (ny, nx), "b"), nx, ny, _dev(out, (2,), "out"),
+                                               _stream(S.device)))
+    return out
+
+
 def grad_K(jac: torch.Tensor, lam: torch.Tensor, u: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
     """dK_e = -lam_e^T G_e u_e per cell ([ny-1][nx-1])."""
     ny, nx = u.shape

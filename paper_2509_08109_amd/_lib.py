@@ -49,6 +49,7 @@ SIGNATURES = {
     "dmg_stats": (_st, [_p, C.POINTER(_i32), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "dmg_vcycle": (_st, [_p, _p, _p, _p]),
     "dmg_residual_norm": (_st, [_p, _p, _p, C.POINTER(C.c_double), _p]),
+    "dmg_residual_norm_noalloc": (_st, [_p, _p, _p, _i32, _i32, _p, _p]),
     "dmg_autotune": (_st, [_p, _p, _p, _i32, _i32, _p]),
     "dmg_hier_config": (_st, [_p, _i32, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32)]),
     "dmg_hier_sweep_config": (_st, [_p, _i32, _i32, C.POINTER(_i32), C.POINTER(_i32)]),

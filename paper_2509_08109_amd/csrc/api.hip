@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 
 #include "dmg_internal.h"
@@ -899,6 +900,39 @@ dmg_hier::~dmg_hier() {
 
 using namespace dmg;
 
+// ---- scratch of the allocation-free residual norm ------------------------------------------
+// dmg_residual_norm_noalloc keeps its kReduceBlocks reduction partials (8 KiB) in this file-scope
+// device array; every device that runs it holds its own copy until the process ends.  In host
+// code the name is only a host-side stand-in: the array's device address is taken once per device
+// with hipGetSymbolAddress (that device current) and only that address reaches kernels.
+static __device__ __align__(256) double scratch[kReduceBlocks];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_addr[kMaxScratchDevices] = {};
+
+// The current device's address of `scratch`, looked up on this device's first call.
+dmg_status scratch_address(double** out) {
+  int dev = -1;
+  DMG_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxScratchDevices)
+    return fail(DMG_ERR_INVALID_ARG, "device index %d beyond the %d the scratch table covers", dev,
+                kMaxScratchDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(DMG_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                  hipGetErrorString(e));
+    g_scratch_addr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_addr[dev];
+  return DMG_OK;
+}
+}  // namespace
+
 extern "C" {
 
 void dmg_default_options(dmg_options* o) {
@@ -1243,6 +1277,18 @@ dmg_status dmg_residual_norm(dmg_hier* h, const double* u, const double* b, doub
   if (!h || !u || !b || !norm) return fail(DMG_ERR_INVALID_ARG, "null pointer argument");
   DMG_CHECK(norm_r(h, u, b, 2, stream));
   return read_scalar(h, 3, norm, stream);
+}
+
+dmg_status dmg_residual_norm_noalloc(const double* S, const double* u, const double* b, int32_t nx,
+                                     int32_t ny, double* norm, hipStream_t stream) {
+  clear_error();
+  if (!S || !u || !b || !norm) return fail(DMG_ERR_INVALID_ARG, "null pointer argument");
+  if (nx < 3 || ny < 3) return fail(DMG_ERR_DIMS, "grid dims must be >= 3 (got %d x %d)", nx, ny);
+  double* partials = nullptr;
+  DMG_CHECK(scratch_address(&partials));
+  // the partials kernel writes every one of the kReduceBlocks entries: nothing to clear first
+  DMG_CHECK(launch_resid_sq_partials(S, u, b, nx, ny, partials, stream));
+  return launch_finalize(partials, norm, stream, kReduceBlocks);
 }
 
 dmg_status dmg_solve(dmg_hier* h, double* u, const double* b, double rtol, int32_t max_iters,
