@@ -1,23 +1,28 @@
 #!/usr/bin/env python3
 """Throughput of the mapped structured multigrid solve on one MI355X.
 
-Workload (default): a 1025 x 1025 logical grid of a star-shaped domain (conformal square->disk
-map composed with a radial star deformation, boundary radius 1 + sum_{k<=8} a_k cos(k theta +
-phi_k)), log-normal K (sigma 1, correlation length 0.1), b ~ U(-1,1), homogeneous Dirichlet,
-float64 V(1,1) cycles from u = 0 to ||b - A u|| <= 1e-10 ||b||.  All inputs are synthetic and
-seeded; they are generated and copied to the GPU before timing.
+Headline workload: a 4097 x 4097 logical grid (16.8M unknowns) of a star-shaped domain
+(conformal square->disk map composed with a radial star deformation, boundary radius
+1 + sum_{k<=8} a_k cos(k theta + phi_k)), log-normal K (sigma 1, correlation length 0.1),
+b ~ U(-1,1), homogeneous Dirichlet, solved from u = 0 to ||b - A u|| <= 1e-10 ||b|| in float64
+(V(1,1) cycles) and with float32 V-cycles inside float64 iterative refinement.  All inputs are
+synthetic and seeded; they are generated on the GPU before timing.
 
 One step = the whole hot path on that input: stencil assembly from the map Jacobians,
 hierarchy setup (operator-induced interpolation, Galerkin levels, coarsest factor), and the
-solve.  value = interior DoF x steps / wall time.
+solve.  value = interior DoF x steps / wall time of the float64 steps; the float32-refined steps
+are timed the same way beside them.  roofline = the dominant float64 level-0 kernel (HIP events
+on the library's stream).  cpu_baseline = one whole step of the same workload by the float64
+oracle on one host thread, run in a subprocess during the GPU legs; its solution gives both GPU
+results' error against the float64 oracle.
 
-Extra legs (same JSON line): the float32-refined solve at the same size, the 4097 x 4097 size
-in float64 and float32-refined form, the batch of 256 uneven instances, the differentiable solve
-on 2049 x 2049 with its finite-difference check, the grid <-> mesh transfers, the roofline of the
-dominant kernel (timed with HIP events on the library's stream), and the float64 CPU oracle
-timed on the host (cpu_baseline).
+Extra legs (same JSON line): the same pair at 1025 x 1025, the batch of 256 uneven instances,
+the differentiable solve on 2049 x 2049 with its finite-difference check, the grid <-> mesh
+transfers, the two-level cycle on star meshes (and the paper's own configuration of it), the
+quarter annulus with point and line smoothing, the discontinuous-coefficient problems.
 
-    python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--n 1025] [--no-c3] [--no-c4] [--no-c5] [--no-transfer] [--no-cpu]
+    python bench.py [--gpus 1] [--steps 5] [--warmup 2] [--n 4097] [--no-c2] [--no-c4] [--no-c5]
+                    [--no-transfer] [--no-twolevel] [--no-annulus] [--no-disc] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -381,6 +386,16 @@ def run_twolevel_leg(dmg, dev, sizes=(129, 257, 513), seed: int = 1, reps: int =
         tl.set_scaling(gamma)
         _, k_g, rel_g, _ = tl.solve(fd, rtol=1e-10, raise_on_fail=False)
         tl.set_scaling(1.0)
+        # the paper's own configuration on the same mesh: two CG iterations on M_p and the
+        # rasterised coupled mass (4 x 4 Gauss points per grid cell)
+        tlp = dmg.TwoLevel(H, mesh.xy_c, mesh.xy_p, mesh.tris, mesh.dof, K_t=K_t, nq=4, mass="cg2")
+        try:
+            _, k_p, rel_p, hist_p = tlp.solve(fd, rtol=1e-10, max_iters=100, raise_on_fail=False)
+            paper = {"cycles": k_p, "relres": rel_p, "converged": bool(rel_p <= 1e-10),
+                     "rate_last_5": round((hist_p[-1] / hist_p[-6]) ** 0.2, 4) if len(hist_p) > 5 else None}
+        except dmg.DmgError as e:          # non-finite residual: the cycle diverged
+            paper = {"cycles": None, "relres": None, "converged": False, "diverged": str(e)}
+        tlp.close()
         free = int(mesh.dof.sum())
         rows.append({"grid": n, "mesh_vertices": int(mesh.nv), "unknowns": free,
                      "triangles": int(mesh.tris.shape[0]), "colours": ncol, "nnz_A": nnz_A,
@@ -390,8 +405,10 @@ def run_twolevel_leg(dmg, dev, sizes=(129, 257, 513), seed: int = 1, reps: int =
                      "unknowns_per_s": round(free / wall, 1),
                      "gen_s": round(t_gen, 2), "create_s": round(t_create, 2),
                      "scaling": {"gamma": round(gamma, 4), "estimate_s": round(t_gamma, 3),
-                                 "cycles_with_gamma": k_g, "relres_with_gamma": rel_g}})
-        log(f"two-level {n}: {k} cycles, {1e3 * wall:.2f} ms, create {t_create:.1f} s")
+                                 "cycles_with_gamma": k_g, "relres_with_gamma": rel_g},
+                     "paper_configuration_cg2_nq4": paper})
+        log(f"two-level {n}: {k} cycles, {1e3 * wall:.2f} ms, create {t_create:.1f} s; "
+            f"paper configuration (CG2, nq = 4): {paper}")
         tl.close()
         H.close()
     return {"workload": "star meshes, physical P1 system, lumped mass, exact coupled mass, FP64 grid V(1,1), "
@@ -486,39 +503,112 @@ CPU_SNIPPET = r"""
 import json, sys, time
 sys.path.insert(0, {root!r})
 import numpy as np
-import problems as pb
 from oracle import boxmg, cycle, fem
-prob = pb.star({n}, seed={seed})
-reps, t_total, iters = 0, 0.0, 0
-while reps < {max_reps} and (reps == 0 or t_total < {budget}):
+for job in {jobs!r}:
+    d = np.load(job["inputs"])
+    jac, K, b = d["jac"], d["K"], d["b"]
+    ny, nx = b.shape
     t0 = time.perf_counter()
-    S = fem.assemble_stencil(prob.jac, prob.K, prob.nx, prob.ny)
+    S = fem.assemble_stencil(jac, K, nx, ny)
+    t1 = time.perf_counter()
     orc = cycle.Oracle(boxmg.build_hierarchy(S))
-    u, k, hist, _ = cycle.solve(orc, prob.b, 1e-10)
-    t_total += time.perf_counter() - t0
-    reps += 1
-    iters = k
-print(json.dumps(dict(reps=reps, seconds=t_total, iters=iters, relres=hist[-1],
-                      dof=(prob.nx - 2) * (prob.ny - 2))))
+    t2 = time.perf_counter()
+    u, k, hist, _ = cycle.solve(orc, b, 1e-10)
+    t3 = time.perf_counter()
+    np.save(job["out"], u)
+    print(json.dumps(dict(n=nx, assemble_s=t1 - t0, setup_s=t2 - t1, solve_s=t3 - t2, seconds=t3 - t0,
+                          iters=k, relres=hist[-1], dof=(nx - 2) * (ny - 2))), flush=True)
+    del d, jac, K, b, S, orc, u
 """
 
 
-def cpu_baseline(n: int, seed: int, budget: float = 15.0):
-    """The float64 oracle, single-threaded, on the same workload (whole steps until ~budget s)."""
-    env = dict(os.environ)
-    for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
-        env[k] = "1"
-    env["CUDA_VISIBLE_DEVICES"] = ""
-    env["HIP_VISIBLE_DEVICES"] = ""
-    code = CPU_SNIPPET.format(root=ROOT, n=n, seed=seed, max_reps=5, budget=budget)
-    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
-    if r.returncode != 0:
-        raise RuntimeError(r.stderr[-2000:])
-    d = json.loads(r.stdout.strip().splitlines()[-1])
-    return dict(value=d["dof"] * d["reps"] / d["seconds"], unit="DoF/s", cores=1, kind="oracle",
-                sample=f"{d['reps']} whole step(s) (assemble + setup + solve to 1e-10, {d['iters']} V-cycles) "
-                       f"of the {n}x{n} workload, float64 NumPy/SciPy, one thread",
-                seconds=round(d["seconds"], 2), host_cpus=os.cpu_count())
+class OracleBaseline:
+    """The float64 oracle on the host, one thread, one whole step (assemble + setup + solve to
+    1e-10) of each given workload, run in a subprocess that starts before the GPU legs so that its
+    CPU time overlaps them.  Its inputs are the arrays the GPU legs use (written to a temporary
+    directory); its solutions come back so that every GPU result can state its error against the
+    float64 oracle."""
+
+    def __init__(self, workloads):
+        import tempfile
+
+        import numpy as np
+        self.dir = tempfile.mkdtemp(prefix="dmg_oracle_")
+        jobs = []
+        for name, jac, K, b in workloads:
+            path = os.path.join(self.dir, f"{name}_inputs.npz")
+            np.savez(path, jac=jac, K=K, b=b)
+            jobs.append(dict(name=name, inputs=path, out=os.path.join(self.dir, f"{name}_u.npy")))
+        self.jobs = jobs
+        env = dict(os.environ)
+        for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "NUMEXPR_NUM_THREADS"):
+            env[k] = "1"
+        env["CUDA_VISIBLE_DEVICES"] = ""
+        env["HIP_VISIBLE_DEVICES"] = ""
+        self.t0 = time.perf_counter()
+        self.proc = subprocess.Popen([sys.executable, "-c", CPU_SNIPPET.format(root=ROOT, jobs=jobs)],
+                                     stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, env=env)
+
+    def results(self, timeout: float = 900.0):
+        """{name: (stats dict, solution [ny][nx])} once the subprocess has finished."""
+        import shutil
+
+        import numpy as np
+        out, err = self.proc.communicate(timeout=timeout)
+        if self.proc.returncode != 0:
+            raise RuntimeError(err[-2000:])
+        stats = [json.loads(line) for line in out.strip().splitlines() if line.startswith("{")]
+        res = {job["name"]: (st, np.load(job["out"])) for job, st in zip(self.jobs, stats)}
+        shutil.rmtree(self.dir, ignore_errors=True)
+        return res
+
+
+def oracle_error(x, u_or):
+    """||x - u_or|| / ||u_or|| and max |x - u_or| / max |u_or| of a GPU solution x (tensor)."""
+    import numpy as np
+    xh = x.detach().cpu().numpy()
+    d = xh - u_or
+    return {"rel_l2": float(np.linalg.norm(d) / np.linalg.norm(u_or)),
+            "max_abs_over_max": float(np.abs(d).max() / np.abs(u_or).max())}
+
+
+def device_inputs(n: int, seed: int, dev):
+    """The star workload's map Jacobians at the Gauss points, log-normal K and b, generated on the
+    device from the seeded streams of ``problems.star(n, seed)``."""
+    from problems.batch_device import star_device
+    return star_device(n, seed, dev)
+
+
+def precision_legs(dmg, jac, K, b, steps: int, warmup: int, workload: str):
+    """float64 and float32-refined legs of one workload: whole steps timed, solve-only rates, the
+    roofline of the dominant float64 level-0 kernel."""
+    n_y, n_x = b.shape
+    dof = (n_x - 2) * (n_y - 2)
+    h, u, i64 = run_leg(dmg, jac, K, b, steps, warmup, dmg.DMG_FP64)
+    levels, gc, oc = h.stats()
+    log(f"{workload} fp64: {i64['iters']} cycles, {1e3 * i64['wall_s'] / steps:.2f} ms/step")
+    roof = kernel_roofline(dmg, h, b, workload)
+    log(f"{workload} roofline: {roof['kernel']} {roof['avg_us']} us, {roof['achieved']} GB/s")
+    u64 = u.clone()
+    h.close()
+    h32, x32, i32 = run_leg(dmg, jac, K, b, steps, warmup, dmg.DMG_FP32_IR)
+    log(f"{workload} fp32-refined: {i32['iters']} steps of {i32['tuned']['inner_cycles']} float32 cycles, "
+        f"{1e3 * i32['wall_s'] / steps:.2f} ms/step")
+    x32 = x32.clone()
+    h32.close()
+    fp64 = {"value": round(dof * steps / i64["wall_s"], 1), "unit": "DoF/s",
+            "ms_per_step": round(1e3 * i64["wall_s"] / steps, 3),
+            "solve_only_dof_per_s": round(dof * steps / i64["solve_wall_s"], 1),
+            "iters": i64["iters"], "relres": i64["relres"]}
+    fp32 = {"value": round(dof * steps / i32["wall_s"], 1), "unit": "DoF/s",
+            "ms_per_step": round(1e3 * i32["wall_s"] / steps, 3),
+            "solve_only_dof_per_s": round(dof * steps / i32["solve_wall_s"], 1),
+            "outer_steps": i32["iters"], "inner_cycles": i32["tuned"]["inner_cycles"],
+            "relres": i32["relres"],
+            "speedup_vs_fp64": round(i64["wall_s"] / i32["wall_s"], 3),
+            "solve_only_speedup_vs_fp64": round(i64["solve_wall_s"] / i32["solve_wall_s"], 3)}
+    info = {"levels": levels, "grid_complexity": round(gc, 4), "operator_complexity": round(oc, 4)}
+    return fp64, fp32, roof, info, u64, x32
 
 
 def main():
@@ -526,9 +616,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n", type=int, default=1025)
-    ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--no-c3", action="store_true", help="skip the 4097 x 4097 legs")
+    ap.add_argument("--n", type=int, default=4097, help="grid of the headline workload")
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--no-c2", action="store_true", help="skip the 1025 x 1025 legs")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-c4", action="store_true", help="skip the 256-instance batch leg")
     ap.add_argument("--no-c5", action="store_true", help="skip the 2049 x 2049 gradient leg")
@@ -571,69 +661,53 @@ def main():
     stream_gbs = 2 * calib.numel() * 8 * 20 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
     del calib, calib_dst
 
-    log(f"generating the {args.n}x{args.n} star workload")
-    prob, jac, K, b = make_inputs(args.n, args.seed, dev)
-    dof = (args.n - 2) ** 2
-    log("fp64 leg")
-    h, u, i64 = run_leg(dmg, jac, K, b, args.steps, args.warmup, dmg.DMG_FP64)
-    levels, gc, oc = h.stats()
-    log(f"fp64: {i64['iters']} cycles, {1e3 * i64['wall_s'] / args.steps:.2f} ms/step")
-    roof = kernel_roofline(dmg, h, b, f"{args.n}x{args.n}")
-    log(f"roofline: {roof['kernel']} {roof['avg_us']} us, {roof['achieved']} GB/s")
-    u64 = u.clone()
-    h.close()
-    log("fp32-refined leg")
-    h32, x32, i32 = run_leg(dmg, jac, K, b, args.steps, args.warmup, dmg.DMG_FP32_IR)
-    err32 = float(torch.linalg.norm(x32 - u64) / torch.linalg.norm(u64))
-    h32.close()
-    value = dof * args.steps / i64["wall_s"]
+    n, n2 = args.n, 1025
+    log(f"generating the {n}x{n} star workload (root seed {args.seed}) on the device")
+    jac, K, b = device_inputs(n, args.seed, dev)
+    c2 = None if args.no_c2 else device_inputs(n2, 1, dev)
+    oracle = None
+    if not args.no_cpu:
+        host = lambda t: t.detach().cpu().numpy()
+        work = [("headline", host(jac), host(K), host(b))]
+        if c2 is not None:
+            work.append(("c2", *(host(t) for t in c2)))
+        oracle = OracleBaseline(work)
+        del work
+        log("oracle baseline started (one thread, in the background)")
+    dof = (n - 2) ** 2
+    workload = f"{n}x{n}"
+    fp64, fp32, roof, info, u64, x32 = precision_legs(dmg, jac, K, b, args.steps, args.warmup, workload)
+    del jac, K
+    torch.cuda.empty_cache()
     res = {
-        "metric": METRIC, "value": round(value, 1), "unit": "DoF/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(1e3 * i64["wall_s"] / args.steps, 3),
+        "metric": METRIC, "value": fp64["value"], "unit": "DoF/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": fp64["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic (seeded star-domain map Jacobians, log-normal K, uniform RHS)",
-        "config": {"workload": f"{args.n}x{args.n} star domain, log-normal K, FP64 V(1,1) to 1e-10 rel. residual; "
-                               "step = assemble + setup + solve", "grid": [args.n, args.n],
-                   "dof": dof, "levels": levels, "grid_complexity": round(gc, 4),
-                   "operator_complexity": round(oc, 4), "seed": args.seed},
-        "iters": i64["iters"], "relres": i64["relres"],
-        "solve_only_dof_per_s": round(dof * args.steps / i64["solve_wall_s"], 1),
-        "fp32_refined": {"value": round(dof * args.steps / i32["wall_s"], 1), "unit": "DoF/s",
-                         "outer_steps": i32["iters"], "inner_cycles": i32["tuned"]["inner_cycles"],
-                         "relres": i32["relres"],
-                         "solve_only_dof_per_s": round(dof * args.steps / i32["solve_wall_s"], 1),
-                         "rel_err_vs_fp64_solution": err32,
-                         "speedup_vs_fp64": round(i64["wall_s"] / i32["wall_s"], 3)},
+        "config": {"workload": f"{n}x{n} star domain (root seed {args.seed}), log-normal K, "
+                               "FP64 V(1,1) and FP32-refined solves to 1e-10 rel. residual; "
+                               "step = assemble + setup + solve; value = FP64",
+                   "grid": [n, n], "dof": dof, **info, "seed": args.seed},
+        "iters": fp64["iters"], "relres": fp64["relres"],
+        "solve_only_dof_per_s": fp64["solve_only_dof_per_s"],
+        "fp64": fp64,
+        "fp32_refined": fp32,
         "roofline": roof,
         "stream_reference": {"kernel": "torch.mul, float64, 512 MiB read + 512 MiB written",
                              "gbs": round(stream_gbs, 1), "frac_of_peak": round(stream_gbs / HBM_PEAK_GBS, 4)},
     }
-    del jac, K, b, u, u64, x32
-    torch.cuda.empty_cache()
-    if not args.no_c3:
-        n3 = 4097
-        log(f"generating the {n3}x{n3} star workload")
-        prob3, jac3, K3, b3 = make_inputs(n3, 2, dev)
-        dof3 = (n3 - 2) ** 2
-        st3 = max(2, args.steps // 2)
-        h3, u3, j64 = run_leg(dmg, jac3, K3, b3, st3, 1, dmg.DMG_FP64)
-        roof3 = kernel_roofline(dmg, h3, b3, f"{n3}x{n3}", reps=10)
-        u3_64 = u3.clone()
-        h3.close()
-        h3b, x3, j32 = run_leg(dmg, jac3, K3, b3, st3, 1, dmg.DMG_FP32_IR)
-        h3b.close()
-        res["c3_4097"] = {
-            "fp64": {"value": round(dof3 * st3 / j64["wall_s"], 1), "solve_only_dof_per_s":
-                     round(dof3 * st3 / j64["solve_wall_s"], 1), "iters": j64["iters"], "relres": j64["relres"]},
-            "fp32_refined": {"value": round(dof3 * st3 / j32["wall_s"], 1), "solve_only_dof_per_s":
-                             round(dof3 * st3 / j32["solve_wall_s"], 1), "outer_steps": j32["iters"],
-                             "inner_cycles": j32["tuned"]["inner_cycles"], "relres": j32["relres"],
-                             "rel_err_vs_fp64_solution": float(torch.linalg.norm(x3 - u3_64) / torch.linalg.norm(u3_64))},
-            "solve_speedup_fp32_refined": round(j64["solve_wall_s"] / j32["solve_wall_s"], 3),
-            "roofline": roof3, "steps": st3,
-        }
-        del jac3, K3, b3, u3, x3, u3_64
+    solutions = {"headline": (u64, x32)}
+    del b
+    if c2 is not None:
+        jac2, K2, b2 = c2
+        fp64_2, fp32_2, roof2, info2, u64_2, x32_2 = precision_legs(dmg, jac2, K2, b2, args.steps,
+                                                                    args.warmup, f"{n2}x{n2}")
+        res["c2_1025"] = {"workload": f"{n2}x{n2} star domain (root seed 1); fits in the 256 MB "
+                                      "last-level cache, not an HBM roofline claim",
+                          "fp64": fp64_2, "fp32_refined": fp32_2, "roofline": roof2, **info2}
+        solutions["c2"] = (u64_2, x32_2)
+        del jac2, K2, b2, c2
+        torch.cuda.empty_cache()
     if not args.no_c4:
         log("batch leg: 256 star instances")
         res["c4_batch"] = run_batch_leg(dmg, dev, max(1, args.steps // 2))
@@ -652,9 +726,27 @@ def main():
     if not args.no_disc:
         log("discontinuous-coefficient leg: 513x513 unit square")
         res["discontinuous"] = run_discontinuous_leg(dmg, dev)
-    if not args.no_cpu:
-        log("cpu baseline (oracle)")
-        res["cpu_baseline"] = cpu_baseline(args.n, args.seed)
+    if oracle is not None:
+        log("waiting for the oracle baseline")
+        got = oracle.results()
+        st, u_or = got["headline"]
+        res["cpu_baseline"] = dict(
+            value=st["dof"] / st["seconds"], unit="DoF/s", cores=1, kind="oracle",
+            sample=f"one whole step (assemble + setup + solve to 1e-10, {st['iters']} V-cycles) of the "
+                   f"{n}x{n} workload, float64 NumPy/SciPy, one thread",
+            seconds=round(st["seconds"], 2), assemble_s=round(st["assemble_s"], 2),
+            setup_s=round(st["setup_s"], 2), solve_s=round(st["solve_s"], 2),
+            solve_only_dof_per_s=round(st["dof"] / st["solve_s"], 1), iters=st["iters"],
+            host_cpus=os.cpu_count())
+        res["fp64"]["error_vs_fp64_oracle"] = oracle_error(solutions["headline"][0], u_or)
+        res["fp32_refined"]["error_vs_fp64_oracle"] = oracle_error(solutions["headline"][1], u_or)
+        res["fp64"]["oracle_iters"] = st["iters"]
+        if "c2" in got:
+            st2, u_or2 = got["c2"]
+            res["c2_1025"]["fp64"]["error_vs_fp64_oracle"] = oracle_error(solutions["c2"][0], u_or2)
+            res["c2_1025"]["fp32_refined"]["error_vs_fp64_oracle"] = oracle_error(solutions["c2"][1], u_or2)
+            res["c2_1025"]["cpu_oracle"] = dict(value=st2["dof"] / st2["seconds"], unit="DoF/s", cores=1,
+                                                seconds=round(st2["seconds"], 2), iters=st2["iters"])
     print(json.dumps(res), flush=True)
 
 
