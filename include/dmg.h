@@ -58,7 +58,7 @@ typedef enum dmg_status {
 
 enum { DMG_FP64 = 0, DMG_FP32_IR = 1 };
 
-/* Mesh setup flags (dmg_transfer_create, dmg_twolevel_create). */
+/* Mesh setup flags (dmg_transfer_create_mesh, dmg_twolevel_create). */
 enum { DMG_MESH_HOST_SETUP = 1 /* assemble C and C^T on the host instead of the device */ };
 
 /* Solver options.  Fill with dmg_default_options() and change what is needed. */
@@ -234,8 +234,28 @@ dmg_status dmg_solve(dmg_hier* h, double* u, const double* b, double rtol, int32
 dmg_status dmg_grad_K(const double* jac, const double* lambda, const double* u, int32_t nx,
                       int32_t ny, double* dK, hipStream_t stream);
 
-/* ---- grid <-> mesh transfers (Sec. 2.3; Sec. 2.3.1 coupled mass) -----------------------
- * Create from a P1 mesh given as HOST arrays: xy_c [nv][2] the images T(x_v) in (-1,1)^2,
+/* ---- grid <-> mesh transfers (Sec. 2.3 interpolation P = M_p^{-1} C, restriction P^T;
+ * Sec. 2.3.1 coupled mass C) --------------------------------------------------------------
+ * Two ways to create a transfer; the apply calls below work on either.
+ *
+ * From the caller's matrices (no allocation): C (Np x Nc) and M_p (Np x Np) as DEVICE CSR arrays,
+ * int32 row pointers [Np + 1] starting at 0, int32 column indices and float64 values, borrowed:
+ * they must stay valid and unchanged while the handle is used.  Columns of C index the grid
+ * vector (vertex (i, j) of an nx x ny grid is column j nx + i, Nc = nx ny); Dirichlet treatment
+ * (empty rows of C, identity rows of M_p) is the caller's.  The workspace (device, 256-byte
+ * aligned, >= dmg_transfer_workspace_bytes for the same Np, Nc and nnz(C), owned by the caller
+ * and outliving the handle) receives C^T, formed here on the device (rows in ascending mesh
+ * order), and the CG vectors.  Create checks the CSR structure on the device (row pointers
+ * non-decreasing, columns in range; DMG_ERR_INVALID_ARG otherwise) and synchronises `stream`.
+ * Then from_grid = CG2(M_p, C u_c) and to_grid = C^T CG2(M_p, r_p) exactly as defined, with u_c
+ * and r_c vectors of Nc entries and the mesh vectors in the caller's row order.
+ * Errors: DMG_ERR_INVALID_ARG, DMG_ERR_WORKSPACE, DMG_ERR_HIP. */
+dmg_status dmg_transfer_workspace_bytes(int32_t Np, int32_t Nc, int64_t nnz_C, size_t* bytes);
+dmg_status dmg_transfer_create(int32_t Np, int32_t Nc, const int32_t* C_rowptr,
+                               const int32_t* C_col, const double* C_val, const int32_t* M_rowptr,
+                               const int32_t* M_col, const double* M_val, void* workspace,
+                               size_t ws_bytes, hipStream_t stream, dmg_transfer** out);
+/* From a P1 mesh given as HOST arrays (C and M_p assembled here): xy_c [nv][2] the images T(x_v) in (-1,1)^2,
  * xy_p [nv][2] physical coordinates, tris [nt][3] (int32, any orientation), dof [nv] (uint8,
  * 0 = Dirichlet vertex).  C is assembled by rasterising each mapped triangle over the grid
  * cells it overlaps with an nq x nq Gauss rule per cell, nq in [1, 32] (points outside the
@@ -248,9 +268,10 @@ dmg_status dmg_grad_K(const double* jac, const double* lambda, const double* u, 
  * from_grid: u_p = CG2(M_p, C u_c)      u_c [ny][nx] -> u_p [nv]
  * to_grid:   r_c = C^T CG2(M_p, r_p)    r_p [nv]     -> r_c [ny][nx]
  * CG2 = two iterations of unpreconditioned CG from 0.  Dirichlet entries are ignored/zero. */
-dmg_status dmg_transfer_create(int32_t nv, int32_t nt, const double* xy_c, const double* xy_p,
-                               const int32_t* tris, const uint8_t* dof, int32_t nx, int32_t ny,
-                               int32_t nq, int32_t flags, hipStream_t stream, dmg_transfer** out);
+dmg_status dmg_transfer_create_mesh(int32_t nv, int32_t nt, const double* xy_c,
+                                    const double* xy_p, const int32_t* tris, const uint8_t* dof,
+                                    int32_t nx, int32_t ny, int32_t nq, int32_t flags,
+                                    hipStream_t stream, dmg_transfer** out);
 dmg_status dmg_transfer_info(const dmg_transfer* t, int64_t* nnz_C, int64_t* nnz_M);
 /* C as a host CSR with rows in the caller's vertex order: rp [nv + 1], ci and v [nnz_C] (from
  * dmg_transfer_info), columns ascending within a row.  Synchronous. */
@@ -282,11 +303,18 @@ dmg_status dmg_batch_setup(int32_t count, const int32_t* nx, const int32_t* ny,
 dmg_status dmg_batch_solve(dmg_batch* bt, double* const* u, const double* const* b,
                            double rtol, int32_t max_iters, int32_t* iters, double* relres,
                            hipStream_t stream);
-/* Picks the wave-strip segment height of each level size and the coarse-tail workgroup size by
- * timing batched steps on (u, b) -- numerically neutral.  u is scratch (overwritten).
- * Synchronous. */
+/* Batch autotuner, synchronous; u is scratch (overwritten), b the right-hand sides.
+ * flags bit 0: the wave-strip segment height of each level size and the coarse-tail workgroup
+ * size, by timing `reps` batched steps each -- numerically neutral.
+ * flags bit 1: the colour-order pair (the same four row-separable pairs as dmg_autotune, post
+ * order the reverse of the pre order), by timing whole batched solves to 1e-10 from zero; one
+ * pair serves every instance, and each instance's dense coarse operators are rebuilt for it.
+ * This changes the iterates: read the choice back with dmg_batch_config.  Bit 1 runs first. */
 dmg_status dmg_batch_autotune(dmg_batch* bt, double* const* u, const double* const* b,
-                              int32_t reps, hipStream_t stream);
+                              int32_t flags, int32_t reps, hipStream_t stream);
+/* The colour orders (host arrays of 4, nullable) and coarse-tail workgroup size in use. */
+dmg_status dmg_batch_config(const dmg_batch* bt, int32_t* pre_order, int32_t* post_order,
+                            int32_t* tail_threads);
 void dmg_batch_destroy(dmg_batch* bt);
 
 /* ---- the two-level cycle on the physical mesh (Sec. 2.2, solution phase) -----------------
@@ -300,7 +328,7 @@ void dmg_batch_destroy(dmg_batch* bt);
  * smallest-last order (each removed in turn as one of least degree among those left, the
  * smallest index among equals; coloured in reverse removal order); the symmetric sweep updates
  * colours 0..C-1 then C-2..0.
- * Create: mesh arrays on the HOST, nq and flags as for dmg_transfer_create (nq = 0, the exact overlap
+ * Create: mesh arrays on the HOST, nq and flags as for dmg_transfer_create_mesh (nq = 0, the exact overlap
  * integral, keeps the coarse correction's energy matched to A_p as the mesh is refined; low
  * quadrature orders let it drift); K_t [nt] host coefficient per
  * triangle (null: 1); grid: a hierarchy built on the nx x ny grid that C maps to (its level-0

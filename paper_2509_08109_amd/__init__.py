@@ -240,11 +240,41 @@ class Transfer:
         self.device = torch.device(device)
         h = C.c_void_p()
         with torch.cuda.device(self.device):
-            _lib.check(lib().dmg_transfer_create(self.nv, self.nt, self.xy_c.ctypes.data, self.xy_p.ctypes.data,
-                                                 self.tris.ctypes.data, self.dof.ctypes.data, nx, ny, nq,
-                                                 DMG_MESH_HOST_SETUP if host_setup else 0,
-                                                 _stream(self.device), C.byref(h)))
+            _lib.check(lib().dmg_transfer_create_mesh(self.nv, self.nt, self.xy_c.ctypes.data,
+                                                      self.xy_p.ctypes.data, self.tris.ctypes.data,
+                                                      self.dof.ctypes.data, nx, ny, nq,
+                                                      DMG_MESH_HOST_SETUP if host_setup else 0,
+                                                      _stream(self.device), C.byref(h)))
         self._h = h
+
+    @classmethod
+    def from_csr(cls, C_mat, M_mat, nx: int, ny: int, device="cuda"):
+        """A transfer over the caller's coupled mass C (Np x nx*ny) and mass matrix M_p (Np x Np),
+        given as scipy CSR matrices (copied to the device and kept alive by the object, as is the
+        workspace)."""
+        self = cls.__new__(cls)
+        self.device = torch.device(device)
+        self.nx, self.ny = nx, ny
+        C_mat, M_mat = C_mat.tocsr(), M_mat.tocsr()
+        np_, nc = C_mat.shape
+        if nc != nx * ny or M_mat.shape != (np_, np_):
+            raise ValueError("C must be Np x nx*ny and M_p Np x Np")
+        self.nv = np_
+        as_dev = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=self.device)
+        self._csr = [as_dev(C_mat.indptr, torch.int32), as_dev(C_mat.indices, torch.int32),
+                     as_dev(C_mat.data, torch.float64), as_dev(M_mat.indptr, torch.int32),
+                     as_dev(M_mat.indices, torch.int32), as_dev(M_mat.data, torch.float64)]
+        nbytes = C.c_size_t()
+        _lib.check(lib().dmg_transfer_workspace_bytes(np_, nc, int(C_mat.nnz), C.byref(nbytes)))
+        self.workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        ws = base + (-base) % 256
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _lib.check(lib().dmg_transfer_create(np_, nc, *(t.data_ptr() for t in self._csr), ws,
+                                                 int(nbytes.value), _stream(self.device), C.byref(h)))
+        self._h = h
+        return self
 
     def copy_C(self):
         """C as (rp, ci, v) host arrays, rows in the caller's vertex order."""
@@ -401,11 +431,21 @@ class BatchSolver:
     def _ptrs(self, arrays, name):
         return (C.c_void_p * self.count)(*[_dev(a, (ny, nx), name) for a, (nx, ny) in zip(arrays, self.dims)])
 
-    def autotune(self, bs, reps: int = 3) -> None:
-        """Pick per-size launch shapes and the tail workgroup size by timing batched steps."""
+    def autotune(self, bs, reps: int = 3, tiles: bool = True, colour_order: bool = False):
+        """Pick per-size launch shapes and the tail workgroup size by timing batched steps (tiles),
+        and/or the colour-order pair by timing whole batched solves (colour_order, which changes
+        the iterates); returns config()."""
         us = [torch.zeros((ny, nx), dtype=torch.float64, device=self.device) for nx, ny in self.dims]
-        _lib.check(lib().dmg_batch_autotune(self._h, self._ptrs(us, "u"), self._ptrs(bs, "b"), int(reps),
-                                            _stream(self.device)))
+        flags = (1 if tiles else 0) | (2 if colour_order else 0)
+        _lib.check(lib().dmg_batch_autotune(self._h, self._ptrs(us, "u"), self._ptrs(bs, "b"), flags,
+                                            int(reps), _stream(self.device)))
+        return self.config()
+
+    def config(self):
+        """{'pre_order': [...], 'post_order': [...], 'tail_threads': n}"""
+        pre, post, tt = (C.c_int32 * 4)(), (C.c_int32 * 4)(), C.c_int32()
+        _lib.check(lib().dmg_batch_config(self._h, pre, post, C.byref(tt)))
+        return {"pre_order": list(pre), "post_order": list(post), "tail_threads": int(tt.value)}
 
     def solve(self, bs, us=None, rtol: float = 1e-10, max_iters: int = 200, raise_on_fail: bool = True):
         if us is None:

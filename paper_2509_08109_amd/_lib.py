@@ -57,7 +57,9 @@ SIGNATURES = {
     "dmg_solve": (_st, [_p, _p, _p, C.c_double, _i32, C.POINTER(_i32), C.POINTER(C.c_double),
                         C.POINTER(C.c_double), _p]),
     "dmg_grad_K": (_st, [_p, _p, _p, _i32, _i32, _p, _p]),
-    "dmg_transfer_create": (_st, [_i32, _i32, _p, _p, _p, _p, _i32, _i32, _i32, _i32, _p, C.POINTER(_p)]),
+    "dmg_transfer_create_mesh": (_st, [_i32, _i32, _p, _p, _p, _p, _i32, _i32, _i32, _i32, _p, C.POINTER(_p)]),
+    "dmg_transfer_workspace_bytes": (_st, [_i32, _i32, C.c_int64, C.POINTER(C.c_size_t)]),
+    "dmg_transfer_create": (_st, [_i32, _i32, _p, _p, _p, _p, _p, _p, _p, C.c_size_t, _p, C.POINTER(_p)]),
     "dmg_transfer_info": (_st, [_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "dmg_transfer_copy_C": (_st, [_p, _p, _p, _p]),
     "dmg_transfer_from_grid": (_st, [_p, _p, _p, _p]),
@@ -73,7 +75,8 @@ SIGNATURES = {
     "dmg_batch_workspace_bytes": (_st, [_i32, _p, _p, C.POINTER(Options), C.POINTER(C.c_size_t)]),
     "dmg_batch_setup": (_st, [_i32, _p, _p, _p, C.POINTER(Options), _p, C.c_size_t, _p, C.POINTER(_p)]),
     "dmg_batch_solve": (_st, [_p, _p, _p, C.c_double, _i32, _p, _p, _p]),
-    "dmg_batch_autotune": (_st, [_p, _p, _p, _i32, _p]),
+    "dmg_batch_autotune": (_st, [_p, _p, _p, _i32, _i32, _p]),
+    "dmg_batch_config": (_st, [_p, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32)]),
     "dmg_batch_destroy": (None, [_p]),
 }
 

@@ -22,6 +22,7 @@ struct dmg_transfer {
   void* block = nullptr;   // M_p, vectors, scalars
   void* cblock = nullptr;  // C and C^T
   bool device_C = false;   // C was assembled on the device
+  bool borrowed = false;   // C and M_p are the caller's device CSR arrays (created from CSR)
   ~dmg_transfer() {
     if (block) (void)hipFree(block);
     if (cblock) (void)hipFree(cblock);
@@ -236,6 +237,19 @@ struct DeviceCsrPair {
 // device merge holds; the caller then assembles on the host.
 dmg_status device_assemble_C(const Mesh& m, int nx, int ny, int nq,
                              const std::vector<int>& perm, hipStream_t s, DeviceCsrPair& out);
+
+// C^T of a device CSR (nr rows, nc columns, nnz entries) into caller buffers trp [nc + 1], tci and
+// tv [nnz], each transposed row in ascending source-row order (deterministic).  Scratch: cnt
+// [nc + 1], pos [nc], sums [transpose_sums(nc)] ints.  Asynchronous on s.
+int transpose_sums(int nc);
+dmg_status device_transpose(const int* rp, const int* ci, const double* v, int nr, int nc,
+                            int* trp, int* tci, double* tv, int* cnt, int* pos, int* sums,
+                            hipStream_t s);
+// Structure check of a device CSR with nr rows, nc columns and nnz entries: rp[0] = 0, rp
+// non-decreasing and at most nnz (checked first, reading rp only), then every column in [0, nc).
+// *ok receives the verdict; flag is one device int of scratch.  Synchronises s.
+dmg_status device_check_csr(const int* rp, const int* ci, int nr, int nc, int nnz, int* flag,
+                            bool* ok, hipStream_t s);
 
 // Row products run on groups of G consecutive lanes (G divides 64): lane l of a group reads
 // entries rp[r] + l, rp[r] + l + G, ... (coalesced), and the group sums its lanes with xor

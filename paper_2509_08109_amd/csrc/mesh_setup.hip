@@ -320,7 +320,64 @@ dmg_status scan(const int* in, int* out, int n, int* sums, hipStream_t s) {
   return launch_check("scan add");
 }
 
+// Row pointers only: rp[0] = 0 and 0 <= rp[i] <= rp[i + 1] <= nnz.
+__global__ __launch_bounds__(256) void k_check_rowptr(const int* __restrict__ rp, int nr, int nnz,
+                                                      int* __restrict__ flag) {
+  for (int i = int(blockIdx.x) * 256 + int(threadIdx.x); i < nr; i += int(gridDim.x) * 256) {
+    const int b = rp[i], e = rp[i + 1];
+    if ((i == 0 && b != 0) || b < 0 || e < b || e > nnz) atomicOr(flag, 1);
+  }
+}
+
+// Column indices of rows whose pointers were checked: every column in [0, nc).
+__global__ __launch_bounds__(256) void k_check_cols(const int* __restrict__ rp,
+                                                    const int* __restrict__ ci, int nr, int nc,
+                                                    int* __restrict__ flag) {
+  for (int i = int(blockIdx.x) * 256 + int(threadIdx.x); i < nr; i += int(gridDim.x) * 256) {
+    bool bad = false;
+    for (int k = rp[i]; k < rp[i + 1] && !bad; ++k) bad = ci[k] < 0 || ci[k] >= nc;
+    if (bad) atomicOr(flag, 1);
+  }
+}
+
 }  // namespace
+
+int transpose_sums(int nc) { return (nc + 1 + 1023) / 1024 + 2; }
+
+dmg_status device_transpose(const int* rp, const int* ci, const double* v, int nr, int nc,
+                            int* trp, int* tci, double* tv, int* cnt, int* pos, int* sums,
+                            hipStream_t s) {
+  k_fill_int<<<grid_for(size_t(nc) + 1), 256, 0, s>>>(cnt, 0, size_t(nc) + 1);
+  DMG_CHECK(launch_check("fill"));
+  k_cs_colcount<<<grid_for(size_t(nr)), 256, 0, s>>>(rp, ci, nr, cnt);
+  DMG_CHECK(launch_check("column counts"));
+  DMG_CHECK(scan(cnt, trp, nc + 1, sums, s));
+  k_fill_int<<<grid_for(size_t(nc)), 256, 0, s>>>(pos, 0, size_t(nc));
+  DMG_CHECK(launch_check("fill"));
+  k_cs_tfill<<<grid_for(size_t(nr)), 256, 0, s>>>(rp, ci, v, nr, trp, pos, tci, tv);
+  DMG_CHECK(launch_check("transpose"));
+  k_cs_tsort<<<grid_for(size_t(nc)), 256, 0, s>>>(trp, tci, tv, nc);
+  return launch_check("transpose order");
+}
+
+dmg_status device_check_csr(const int* rp, const int* ci, int nr, int nc, int nnz, int* flag,
+                            bool* ok, hipStream_t s) {
+  int bad = 0;
+  k_fill_int<<<1, 256, 0, s>>>(flag, 0, 1);
+  DMG_CHECK(launch_check("fill"));
+  k_check_rowptr<<<grid_for(size_t(nr)), 256, 0, s>>>(rp, nr, nnz, flag);
+  DMG_CHECK(launch_check("row pointer check"));
+  DMG_HIP(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  DMG_HIP(hipStreamSynchronize(s));
+  if (!bad) {  // the pointers bound every column read below
+    k_check_cols<<<grid_for(size_t(nr)), 256, 0, s>>>(rp, ci, nr, nc, flag);
+    DMG_CHECK(launch_check("column check"));
+    DMG_HIP(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    DMG_HIP(hipStreamSynchronize(s));
+  }
+  *ok = !bad;
+  return DMG_OK;
+}
 
 dmg_status device_assemble_C(const Mesh& m, int nx, int ny, int nq,
                              const std::vector<int>& perm, hipStream_t s, DeviceCsrPair& out) {

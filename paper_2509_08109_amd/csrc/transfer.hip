@@ -175,7 +175,8 @@ Csr transpose(const Csr& a, int ncols) {
 // stop (nullable): the kernel does nothing once the device flag is set.
 __device__ __forceinline__ bool stopped(const int* stop) { return stop && *stop; }
 
-// from_grid start: r0 = dof * (C u_c) (mesh rows in the internal order); partials of r0.r0
+// from_grid start: r0 = dof * (C u_c) (mesh rows in the internal order; dof nullable: all ones);
+// partials of r0.r0
 __global__ __launch_bounds__(256) void k_t_init_from(const int* __restrict__ rp,
                                                      const int* __restrict__ ci,
                                                      const double* __restrict__ v,
@@ -190,7 +191,7 @@ __global__ __launch_bounds__(256) void k_t_init_from(const int* __restrict__ rp,
   double acc = 0.0;
   for (int r = g0; r < n; r += ng) {
     const double y = row_dot<kMG>(rp, ci, v, r, lane, [&](int c) { return u_c[c]; });
-    const double val = dof[r] ? y : 0.0;
+    const double val = (!dof || dof[r]) ? y : 0.0;
     if (lane == 0) {
       r0[r] = val;
       acc += val * val;
@@ -200,7 +201,8 @@ __global__ __launch_bounds__(256) void k_t_init_from(const int* __restrict__ rp,
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
-// to_grid start: r0 = dof * r_p taken into the internal order; partials of r0.r0
+// to_grid start: r0 = dof * r_p taken into the internal order (dof, perm nullable: all ones, the
+// identity); partials of r0.r0
 __global__ __launch_bounds__(256) void k_t_init_to(const double* __restrict__ r_p,
                                                    const int* __restrict__ perm,
                                                    const unsigned char* __restrict__ dof,
@@ -208,7 +210,7 @@ __global__ __launch_bounds__(256) void k_t_init_to(const double* __restrict__ r_
                                                    double* __restrict__ partials) {
   double acc = 0.0;
   for (int r = blockIdx.x * 256 + threadIdx.x; r < n; r += gridDim.x * 256) {
-    const double val = dof[r] ? r_p[perm[r]] : 0.0;
+    const double val = (!dof || dof[r]) ? r_p[perm ? perm[r] : r] : 0.0;
     r0[r] = val;
     acc += val * val;
   }
@@ -498,15 +500,107 @@ dmg_status transfer_build(const Mesh& m, int nx, int ny, int nq, const std::vect
   return DMG_OK;
 }
 
+// Workspace of a transfer created from caller CSR matrices: C^T, the CG vectors, partials and
+// scalars, and the transpose's integer scratch.
+void csr_transfer_layout(Arena& a, dmg_transfer* t, int np, int nc, int64_t nnz, int** cnt,
+                         int** pos, int** sums, int** flag) {
+  t->CTrp = a.take<int>(size_t(nc) + 1);
+  t->CTci = a.take<int>(size_t(nnz) + 1);
+  t->CTv = a.take<double>(size_t(nnz) + 1);
+  t->x = a.take<double>(np);
+  t->r = a.take<double>(np);
+  t->p = a.take<double>(np);
+  t->q = a.take<double>(np);
+  t->partials = a.take<double>(kTBlocks);
+  t->scal = a.take<double>(16);
+  *cnt = a.take<int>(size_t(nc) + 1);
+  *pos = a.take<int>(size_t(nc));
+  *sums = a.take<int>(size_t(transpose_sums(nc)));
+  *flag = a.take<int>(1);
+}
+
 }  // namespace dmg
 
 using namespace dmg;
 
 extern "C" {
 
-dmg_status dmg_transfer_create(int32_t nv, int32_t nt, const double* xy_c, const double* xy_p,
-                               const int32_t* tris, const uint8_t* dof, int32_t nx, int32_t ny,
-                               int32_t nq, int32_t flags, hipStream_t stream, dmg_transfer** out) {
+dmg_status dmg_transfer_workspace_bytes(int32_t np, int32_t nc, int64_t nnz_C, size_t* bytes) {
+  clear_error();
+  if (!bytes) return fail(DMG_ERR_INVALID_ARG, "null output");
+  if (np <= 0 || nc <= 0 || nnz_C < 0 || nnz_C >= (int64_t(1) << 31))
+    return fail(DMG_ERR_INVALID_ARG, "bad sizes (Np=%d, Nc=%d, nnz_C=%lld)", np, nc,
+                (long long)nnz_C);
+  dmg_transfer t;
+  Arena sz;
+  int *cnt, *pos, *sums, *flag;
+  csr_transfer_layout(sz, &t, np, nc, nnz_C, &cnt, &pos, &sums, &flag);
+  *bytes = sz.used;
+  return DMG_OK;
+}
+
+dmg_status dmg_transfer_create(int32_t np, int32_t nc, const int32_t* C_rowptr,
+                               const int32_t* C_col, const double* C_val, const int32_t* M_rowptr,
+                               const int32_t* M_col, const double* M_val, void* workspace,
+                               size_t ws_bytes, hipStream_t stream, dmg_transfer** out) {
+  clear_error();
+  if (!out) return fail(DMG_ERR_INVALID_ARG, "null output handle");
+  *out = nullptr;
+  if (np <= 0 || nc <= 0) return fail(DMG_ERR_INVALID_ARG, "bad sizes (Np=%d, Nc=%d)", np, nc);
+  if (!C_rowptr || !C_col || !C_val || !M_rowptr || !M_col || !M_val)
+    return fail(DMG_ERR_INVALID_ARG, "null CSR array");
+  if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 255))
+    return fail(DMG_ERR_WORKSPACE, "workspace missing or not 256-byte aligned");
+  // the entry counts sit on the device: read them (this call synchronises `stream`)
+  int ends[4] = {0, 0, 0, 0};
+  DMG_HIP(hipMemcpyAsync(&ends[0], C_rowptr, sizeof(int), hipMemcpyDeviceToHost, stream));
+  DMG_HIP(hipMemcpyAsync(&ends[1], C_rowptr + np, sizeof(int), hipMemcpyDeviceToHost, stream));
+  DMG_HIP(hipMemcpyAsync(&ends[2], M_rowptr, sizeof(int), hipMemcpyDeviceToHost, stream));
+  DMG_HIP(hipMemcpyAsync(&ends[3], M_rowptr + np, sizeof(int), hipMemcpyDeviceToHost, stream));
+  DMG_HIP(hipStreamSynchronize(stream));
+  if (ends[0] != 0 || ends[2] != 0 || ends[1] < 0 || ends[3] < 0)
+    return fail(DMG_ERR_INVALID_ARG, "row pointers must start at 0 and end at the entry count");
+  std::unique_ptr<dmg_transfer> t(new dmg_transfer);
+  Arena sz;
+  int *cnt, *pos, *sums, *flag;
+  csr_transfer_layout(sz, t.get(), np, nc, ends[1], &cnt, &pos, &sums, &flag);
+  if (ws_bytes < sz.used)
+    return fail(DMG_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, sz.used);
+  Arena a;
+  a.base = static_cast<char*>(workspace);
+  a.cap = ws_bytes;
+  csr_transfer_layout(a, t.get(), np, nc, ends[1], &cnt, &pos, &sums, &flag);
+  // structure of both matrices (M_p square), checked on the device before C^T is formed
+  bool okC = false, okM = false;
+  DMG_CHECK(device_check_csr(C_rowptr, C_col, np, nc, ends[1], flag, &okC, stream));
+  DMG_CHECK(device_check_csr(M_rowptr, M_col, np, np, ends[3], flag, &okM, stream));
+  if (!okC || !okM)
+    return fail(DMG_ERR_INVALID_ARG, "CSR structure of %s: row pointers not non-decreasing from 0 "
+                "to the entry count, or a column index out of range", okC ? "M_p" : "C");
+  t->nv = np;
+  t->nx = nc;
+  t->ny = 1;
+  t->nnzC = ends[1];
+  t->nnzM = ends[3];
+  t->Crp = const_cast<int*>(C_rowptr);
+  t->Cci = const_cast<int*>(C_col);
+  t->Cv = const_cast<double*>(C_val);
+  t->Mrp = const_cast<int*>(M_rowptr);
+  t->Mci = const_cast<int*>(M_col);
+  t->Mv = const_cast<double*>(M_val);
+  t->dof = nullptr;
+  t->perm = nullptr;
+  t->borrowed = true;
+  DMG_CHECK(device_transpose(C_rowptr, C_col, C_val, np, nc, t->CTrp, t->CTci, t->CTv, cnt, pos,
+                             sums, stream));
+  *out = t.release();
+  return DMG_OK;
+}
+
+dmg_status dmg_transfer_create_mesh(int32_t nv, int32_t nt, const double* xy_c,
+                                    const double* xy_p, const int32_t* tris, const uint8_t* dof,
+                                    int32_t nx, int32_t ny, int32_t nq, int32_t flags,
+                                    hipStream_t stream, dmg_transfer** out) {
   clear_error();
   if (!out) return fail(DMG_ERR_INVALID_ARG, "null output handle");
   *out = nullptr;
@@ -542,7 +636,11 @@ dmg_status dmg_transfer_copy_C(const dmg_transfer* t, int32_t* rp, int32_t* ci, 
   std::vector<int> irp(n + 1), perm(n), ici(size_t(t->nnzC));
   std::vector<double> iv(size_t(t->nnzC));
   DMG_HIP(hipMemcpy(irp.data(), t->Crp, (n + 1) * sizeof(int), hipMemcpyDeviceToHost));
-  DMG_HIP(hipMemcpy(perm.data(), t->perm, n * sizeof(int), hipMemcpyDeviceToHost));
+  if (t->perm) {
+    DMG_HIP(hipMemcpy(perm.data(), t->perm, n * sizeof(int), hipMemcpyDeviceToHost));
+  } else {
+    for (int i = 0; i < n; ++i) perm[i] = i;
+  }
   if (t->nnzC > 0) {
     DMG_HIP(hipMemcpy(ici.data(), t->Cci, ici.size() * sizeof(int), hipMemcpyDeviceToHost));
     DMG_HIP(hipMemcpy(iv.data(), t->Cv, iv.size() * sizeof(double), hipMemcpyDeviceToHost));
@@ -567,7 +665,7 @@ dmg_status dmg_transfer_from_grid(dmg_transfer* t, const double* u_c, double* u_
   clear_error();
   if (!t || !u_c || !u_p) return fail(DMG_ERR_INVALID_ARG, "null pointer argument");
   DMG_CHECK(launch_from_start(t, u_c, nullptr, stream));
-  return cg2_tail(t, u_p, X2Mode::kScatter, nullptr, stream);
+  return cg2_tail(t, u_p, t->perm ? X2Mode::kScatter : X2Mode::kStore, nullptr, stream);
 }
 
 dmg_status dmg_transfer_to_grid(dmg_transfer* t, const double* r_p, double* r_c,

@@ -128,12 +128,32 @@ def test_transfer_validation_on_host(dmg):
     xy = np.zeros((3, 2))
     tris = np.array([[0, 1, 5]], dtype=np.int32)       # index out of range
     dof = np.ones(3, dtype=np.uint8)
-    st = lib.dmg_transfer_create(3, 1, xy.ctypes.data, xy.ctypes.data, tris.ctypes.data, dof.ctypes.data,
+    st = lib.dmg_transfer_create_mesh(3, 1, xy.ctypes.data, xy.ctypes.data, tris.ctypes.data, dof.ctypes.data,
                                  9, 9, 4, 0, None, C.byref(h))
     assert st == 1 and "out of range" in lib.dmg_last_error().decode()
-    assert lib.dmg_transfer_create(3, 1, xy.ctypes.data, xy.ctypes.data, tris.ctypes.data, dof.ctypes.data,
+    assert lib.dmg_transfer_create_mesh(3, 1, xy.ctypes.data, xy.ctypes.data, tris.ctypes.data, dof.ctypes.data,
                                    9, 9, -1, 0, None, C.byref(h)) == 1
     assert "nq" in lib.dmg_last_error().decode()
+
+
+def test_transfer_csr_validation_on_host(dmg):
+    """The CSR form's size query and the checks made before any device access."""
+    lib = dmg.lib()
+    nb = C.c_size_t()
+    assert lib.dmg_transfer_workspace_bytes(100, 81, 900, C.byref(nb)) == 0
+    # C^T (82 row pointers, 900 entries), four CG vectors, partials and scalars, transpose scratch
+    assert nb.value >= 4 * 82 + 12 * 900 + 4 * 8 * 100
+    assert lib.dmg_transfer_workspace_bytes(0, 81, 900, C.byref(nb)) == 1
+    assert lib.dmg_transfer_workspace_bytes(100, 81, -1, C.byref(nb)) == 1
+    h = C.c_void_p()
+    fake = C.c_void_p(0x1000)
+    assert lib.dmg_transfer_create(0, 81, fake, fake, fake, fake, fake, fake, fake, 1 << 20, None,
+                                   C.byref(h)) == 1
+    assert lib.dmg_transfer_create(100, 81, None, fake, fake, fake, fake, fake, fake, 1 << 20, None,
+                                   C.byref(h)) == 1
+    assert lib.dmg_transfer_create(100, 81, fake, fake, fake, fake, fake, fake, C.c_void_p(0x1008),
+                                   1 << 20, None, C.byref(h)) == 3
+    assert "aligned" in lib.dmg_last_error().decode()
 
 
 def test_twolevel_validation_on_host(dmg):
