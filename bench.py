@@ -188,7 +188,7 @@ def run_batch_leg(dmg, dev, steps: int, count: int = 256):
     bt = dmg.BatchSolver(Ss)
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
-    bt.autotune(bs, reps=2)
+    tuned = bt.autotune(bs, reps=2, tiles=True, colour_order=True)
     us = [torch.zeros_like(b) for b in bs]
     _, its, rels = bt.solve(bs, us=us, rtol=1e-10)          # warm-up (schedule, graph capture)
     wall = 0.0
@@ -207,6 +207,7 @@ def run_batch_leg(dmg, dev, steps: int, count: int = 256):
     return {"value": round(dof * steps / wall, 1), "unit": "DoF/s", "instances": count,
             "dof": dof, "sizes": {str(n): sizes.count(n) for n in sorted(set(sizes))},
             "cycles_min": min(its), "cycles_max": max(its), "max_relres": max(rels),
+            "tuned_colour_order": [tuned["pre_order"], tuned["post_order"]],
             "ms_per_batch_solve": round(1e3 * wall / steps, 2), "steps": steps,
             "generate_and_assemble_s": round(t_gen, 2), "setup_s": round(t_setup, 2)}
 

@@ -884,6 +884,20 @@ dmg_status setup_impl(dmg_hier* h, const double* S, hipStream_t s, bool first) {
 
 }  // namespace
 
+// New colour orders for a hierarchy: the dense coarse operators carry the orders, so they are
+// rebuilt, and graphs captured with the old ones are dropped.
+dmg_status set_colour_orders(dmg_hier* h, const int32_t* pre, const int32_t* post, hipStream_t s) {
+  for (int k = 0; k < 4; ++k) {
+    h->opts.pre_order[k] = pre[k];
+    h->opts.post_order[k] = post[k];
+  }
+  reset_solve_graphs(h);
+  graph_reset(h->setup_graph);
+  h->last_refresh_S = nullptr;
+  DMG_CHECK(compute_basis(h, s));
+  return compute_gemv_basis(h, s);
+}
+
 dmg_status grid_vcycle(dmg_hier* h, double* u, const double* b, bool u_zero, const int* stop,
                        hipStream_t s) {
   return vcycle_impl<double>(h, u, b, s, nullptr, u_zero, stop);

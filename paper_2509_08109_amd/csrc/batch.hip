@@ -555,10 +555,14 @@ dmg_status dmg_batch_solve(dmg_batch* bt, double* const* u, const double* const*
 }
 
 dmg_status dmg_batch_autotune(dmg_batch* bt, double* const* u, const double* const* b,
-                              int32_t reps, hipStream_t stream) {
+                              int32_t flags, int32_t reps, hipStream_t stream) {
   clear_error();
   if (!bt || !u || !b) return fail(DMG_ERR_INVALID_ARG, "null pointer argument");
   if (reps < 1 || reps > 1000) return fail(DMG_ERR_INVALID_ARG, "reps must be in [1,1000]");
+  if (flags & ~3) return fail(DMG_ERR_INVALID_ARG, "unknown autotune flags 0x%x", flags);
+  const int count = int(bt->inst.size());
+  for (int k = 0; k < count; ++k)
+    if (!u[k] || !b[k]) return fail(DMG_ERR_INVALID_ARG, "instance %d: null array", k);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   DMG_HIP(hipEventCreate(&e0));
   DMG_HIP(hipEventCreate(&e1));
@@ -578,7 +582,61 @@ dmg_status dmg_batch_autotune(dmg_batch* bt, double* const* u, const double* con
     return DMG_OK;
   };
   dmg_status st = DMG_OK;
+  if (flags & 2) {
+    // colour orders: the row-separable pairs whose post order reverses the pre order (the
+    // V-cycle stays symmetric); each is timed as whole batched solves to 1e-10 from zero, which
+    // counts the cycles it saves or costs.  One pair serves every instance.
+    static const int32_t cand[4][4] = {{0, 1, 2, 3}, {1, 0, 3, 2}, {2, 3, 0, 1}, {3, 2, 1, 0}};
+    float best_ms = 1e30f;
+    int best = -1;
+    for (int c = 0; c < 4 && st == DMG_OK; ++c) {
+      int32_t post[4];
+      for (int k = 0; k < 4; ++k) post[k] = cand[c][3 - k];
+      for (int k = 0; k < 4; ++k) {
+        bt->opts.pre_order[k] = cand[c][k];
+        bt->opts.post_order[k] = post[k];
+      }
+      for (auto* h : bt->inst)
+        if (st == DMG_OK) st = set_colour_orders(h, cand[c], post, stream);
+      bt->built = false;
+      bt->reset_graph();
+      float total = 0.f;
+      for (int r = 0; r <= std::max(1, reps / 4) && st == DMG_OK; ++r) {
+        for (int k = 0; k < count && st == DMG_OK; ++k)
+          st = launch_fill<double>(u[k], 0.0, bt->inst[k]->L[0].n(), stream);
+        if (st != DMG_OK) break;
+        DMG_HIP(hipEventRecord(e0, stream));
+        st = dmg_batch_solve(bt, u, b, 1e-10, 500, nullptr, nullptr, stream);
+        DMG_HIP(hipEventRecord(e1, stream));
+        DMG_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        DMG_HIP(hipEventElapsedTime(&ms, e0, e1));
+        if (r > 0) total += ms;  // the first solve builds the schedule and captures the graph
+      }
+      if (st == DMG_ERR_NO_CONVERGENCE) {  // this order does not reach the tolerance in 500 steps
+        st = DMG_OK;
+        clear_error();
+        continue;
+      }
+      if (st == DMG_OK && total < best_ms) {
+        best_ms = total;
+        best = c;
+      }
+    }
+    if (st == DMG_OK) {
+      const int c = best >= 0 ? best : 0;
+      int32_t post[4];
+      for (int k = 0; k < 4; ++k) post[k] = cand[c][3 - k];
+      for (int k = 0; k < 4; ++k) {
+        bt->opts.pre_order[k] = cand[c][k];
+        bt->opts.post_order[k] = post[k];
+      }
+      for (auto* h : bt->inst)
+        if (st == DMG_OK) st = set_colour_orders(h, cand[c], post, stream);
+    }
+  }
   for (auto& [d, h] : bt->seg_h) {
+    if (!(flags & 1) || st != DMG_OK) break;
     int best = h;
     float best_ms = 1e30f;
     for (int c = 2; c <= 128 && st == DMG_OK; c *= 2) {
@@ -594,7 +652,7 @@ dmg_status dmg_batch_autotune(dmg_batch* bt, double* const* u, const double* con
     }
     h = best;
   }
-  if (st == DMG_OK) {
+  if (st == DMG_OK && (flags & 1)) {
     int best = bt->tail_threads;
     float best_ms = 1e30f;
     for (int t : {256, 512, 1024}) {
@@ -614,6 +672,18 @@ dmg_status dmg_batch_autotune(dmg_batch* bt, double* const* u, const double* con
   bt->built = false;
   bt->reset_graph();
   return st;
+}
+
+dmg_status dmg_batch_config(const dmg_batch* bt, int32_t* pre_order, int32_t* post_order,
+                            int32_t* tail_threads) {
+  clear_error();
+  if (!bt) return fail(DMG_ERR_INVALID_ARG, "null batch");
+  for (int k = 0; k < 4; ++k) {
+    if (pre_order) pre_order[k] = bt->opts.pre_order[k];
+    if (post_order) post_order[k] = bt->opts.post_order[k];
+  }
+  if (tail_threads) *tail_threads = bt->tail_threads;
+  return DMG_OK;
 }
 
 void dmg_batch_destroy(dmg_batch* bt) { delete bt; }

@@ -377,6 +377,10 @@ template <class T>
 dmg_status launch_wave_multi(const StripArgs<T>* list, int count, int tiles_per, int mode, int pf,
                              hipStream_t s);
 
+// Sets a hierarchy's pre/post colour orders (4 colours each) and rebuilds what depends on them
+// (the dense coarse operators); captured solve graphs are dropped.  Asynchronous on s.
+dmg_status set_colour_orders(dmg_hier* h, const int32_t* pre, const int32_t* post, hipStream_t s);
+
 // iterative refinement helpers (stop: nullable device flag, see launch_check_step)
 // x += s e over n points, s = *scale (used when no float strip sweep carries the update)
 dmg_status launch_ir_update(double* x, const float* e, size_t n, const double* scale,

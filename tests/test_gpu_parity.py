@@ -415,6 +415,42 @@ def test_transfer_matches_oracle(dmg):
     T.close()
 
 
+@pytest.mark.parametrize("nq", [4, 0])
+def test_transfer_from_caller_csr_matches_oracle(dmg, nq):
+    """The transfer created from the caller's C and M_p (device CSR, caller workspace, C^T formed
+    on the device): from_grid = CG2(M_p, C u_c) and to_grid = C^T CG2(M_p, r_p) against the
+    oracle's, entry by entry, for the rasterised (nq = 4) and exact (nq = 0) coupled mass; and
+    against the transfer the library assembles from the same mesh."""
+    mp = pb.Star.random(pb.streams(2)[0])
+    n = 33
+    mesh = pb.lattice_mesh(mp, 45, np.random.default_rng(8))
+    M = transfer.p1_mass(mesh.xy_p, mesh.tris, mesh.dof)
+    Co = transfer.coupled_mass(mesh.xy_c, mesh.xy_p, mesh.tris, mesh.dof, n, n, nq=nq).tocsr()
+    T = dmg.Transfer.from_csr(Co, M, n, n)
+    assert T.nnz() == (Co.nnz, M.nnz)
+    rp, ci, v = T.copy_C()
+    assert np.array_equal(rp, Co.indptr) and np.array_equal(ci, Co.indices) and np.array_equal(v, Co.data)
+    Tm = dmg.Transfer(mesh.xy_c, mesh.xy_p, mesh.tris, mesh.dof, n, n, nq=nq)
+    rng = np.random.default_rng(4)
+    for _ in range(2):
+        uc = np.zeros((n, n)); uc[1:-1, 1:-1] = rng.normal(size=(n - 2, n - 2))
+        rpv = rng.normal(size=mesh.nv) * mesh.dof
+        up = host(T.from_grid(dev(uc)))
+        rc = host(T.to_grid(dev(rpv)))
+        assert_iterate("from_grid (CSR)", up, transfer.from_grid(M, Co, uc))
+        assert_iterate("to_grid (CSR)", rc, transfer.to_grid(M, Co, rpv, n, n))
+        assert_iterate("from_grid, CSR vs mesh form", up, host(Tm.from_grid(dev(uc))))
+        assert_iterate("to_grid, CSR vs mesh form", rc, host(Tm.to_grid(dev(rpv))))
+    T.close()
+    Tm.close()
+    # a column index beyond the grid is rejected by the device check before C^T is formed
+    bad = Co.copy()
+    bad.indices[bad.indptr[5]] = n * n + 3
+    with pytest.raises(dmg.DmgError) as ei:
+        dmg.Transfer.from_csr(bad, M, n, n)
+    assert ei.value.code == 1 and "out of range" in str(ei.value)
+
+
 def _batch_vs_single(dmg, Ss, bs, bt, us, its, rels, probs=None, orders=None):
     """The batch runs its coarse levels in the one-workgroup coarse kernel: its iterates equal
     single solves with coarse_gemv=0 (and the same colour orders) bitwise, and single solves
@@ -455,9 +491,29 @@ def test_batch_matches_single_solves(dmg):
     assert len(set(its)) > 1
     _batch_vs_single(dmg, Ss, bs, bt, us, its, rels, probs=probs)
     # a second solve on new arrays rebuilds the schedule; autotuned shapes change no bit
-    bt.autotune(bs, reps=1)
+    bt.autotune(bs, reps=1, tiles=True)
     us2, its2, rels2 = bt.solve(bs, rtol=1e-10)
     assert its2 == its and all(torch.equal(a, c) for a, c in zip(us, us2))
+    bt.close()
+
+
+def test_batch_tuned_colour_order_matches_oracle(dmg):
+    """The batch tuner picks the colour-order pair by timing whole batched solves; the batch
+    then runs it on every instance: each instance equals its single solve with that order bit
+    for bit and the oracle's solve with that order entry by entry (same cycle counts)."""
+    sizes = (129, 65, 257, 129, 65, 33, 257)
+    probs = [pb.star(n, seed=40 + k) for k, n in enumerate(sizes)]
+    probs.append(pb.quarter_annulus(65))
+    Ss = [dmg.assemble_stencil(dev(p.jac), dev(p.K)) for p in probs]
+    bs = [dev(p.b) for p in probs]
+    bt = dmg.BatchSolver(Ss)
+    cfg = bt.autotune(bs, reps=4, tiles=True, colour_order=True)
+    pre, post = tuple(cfg["pre_order"]), tuple(cfg["post_order"])
+    print(f"[batch] tuned colour order {pre} / {post}, tail threads {cfg['tail_threads']}")
+    assert post == pre[::-1] and sorted(pre) == [0, 1, 2, 3]
+    us, its, rels = bt.solve(bs, rtol=1e-10)
+    assert max(rels) <= 1e-10
+    _batch_vs_single(dmg, Ss, bs, bt, us, its, rels, probs=probs, orders=[(pre, post)] * len(probs))
     bt.close()
 
 
