@@ -366,8 +366,8 @@ dmg_status dmg_twolevel_solve(dmg_twolevel* tl, double* u_p, const double* f_p, 
  * (beta_j <= 1e-13 |alpha_j|).  gamma (host) receives the estimate, steps (nullable) the steps
  * taken m, T (host, nullable, [k][k]) the m x m tridiagonal in its leading block, zeros
  * elsewhere.  The estimate does not change the handle's gamma.  Lumped mass only
- * (DMG_ERR_UNSUPPORTED for CG2, whose P is not linear).  Synchronous; allocates and frees
- * scratch for six grid vectors. */
+ * (DMG_ERR_UNSUPPORTED for CG2, whose P is not linear).  Synchronous; allocates nothing (its
+ * six grid vectors of scratch are part of a lumped-mass handle from creation). */
 dmg_status dmg_twolevel_set_scaling(dmg_twolevel* tl, double gamma);
 dmg_status dmg_twolevel_scaling(dmg_twolevel* tl, const double* v0, int32_t k, double* gamma,
                                 double* T, int32_t* steps, hipStream_t stream);

@@ -515,6 +515,7 @@ class _DiffSolver:
 
 
 class DiffSolve(torch.autograd.Function):
+    last = None
     """u = A(K)^{-1} b with A the mapped Q1 operator; gradients w.r.t. K (per cell) and b.
 
     Forward saves only (K, b, u); backward recomputes the stencil and hierarchy, solves the
@@ -525,23 +526,35 @@ class DiffSolve(torch.autograd.Function):
     """
 
     @staticmethod
-    def forward(ctx, K, b, jac, rtol=1e-12, max_iters=200, opts=None):
+    def _check(which: str, its: int, rr: float, rtol: float, strict: bool) -> None:
+        if strict and not rr <= rtol:
+            raise DmgError(6, f"{which} solve stopped at relative residual {rr:.3e} after {its} "
+                              f"cycles, above rtol {rtol:.1e} (pass strict=False to accept it)")
+
+    @staticmethod
+    def forward(ctx, K, b, jac, rtol=1e-12, max_iters=200, opts=None, strict=True):
+        """strict (default): raise DmgError (DMG_ERR_NO_CONVERGENCE) when the forward solve, or
+        later the adjoint solve, ends above rtol; strict=False returns the last iterate (its
+        cycles and relative residual are in DiffSolve.last)."""
         u, its, rr = _DiffSolver.solve(jac, K.detach().contiguous(), b.detach(), opts, rtol,
                                        max_iters)
+        DiffSolve.last = {"forward": (its, rr)}
+        DiffSolve._check("forward", its, rr, rtol, strict)
         ctx.save_for_backward(K, b, u)
-        ctx.jac, ctx.rtol, ctx.max_iters, ctx.opts = jac, rtol, max_iters, opts
-        ctx.iters, ctx.relres = its, rr
+        ctx.jac, ctx.rtol, ctx.max_iters, ctx.opts, ctx.strict = jac, rtol, max_iters, opts, strict
         return u
 
     @staticmethod
     def backward(ctx, gu):
         K, b, u = ctx.saved_tensors
-        lam, _, _ = _DiffSolver.solve(ctx.jac, K.detach().contiguous(),
-                                      _interior(gu.contiguous().to(torch.float64)), ctx.opts,
-                                      ctx.rtol, ctx.max_iters)
+        lam, its, rr = _DiffSolver.solve(ctx.jac, K.detach().contiguous(),
+                                         _interior(gu.contiguous().to(torch.float64)), ctx.opts,
+                                         ctx.rtol, ctx.max_iters)
+        DiffSolve.last = dict(DiffSolve.last or {}, adjoint=(its, rr))
+        DiffSolve._check("adjoint", its, rr, ctx.rtol, ctx.strict)
         dK = grad_K(ctx.jac, lam, u) if ctx.needs_input_grad[0] else None
         db = lam if ctx.needs_input_grad[1] else None
-        return dK, db, None, None, None, None
+        return dK, db, None, None, None, None, None
 
     @staticmethod
     def clear_cache() -> None:

@@ -40,6 +40,8 @@ struct dmg_twolevel {
   int* flag = nullptr;  // [0] stop, [1] cycles done, [2] max cycles
   void* block = nullptr;
   double* host = nullptr;  // pinned: scalars [0..7], flags at [8..]
+  double* lz = nullptr;    // lumped mass only: the scaling estimate's six grid vectors, dot
+                           // partials and scalars (part of block)
   // captured chunks of 1..kChunk cycles
   hipGraphExec_t exec[dmg::kChunk] = {};
   hipGraph_t graph[dmg::kChunk] = {};
@@ -621,6 +623,7 @@ dmg_status dmg_twolevel_create(int32_t nv, int32_t nt, const double* xy_c, const
     tl->scal = a.take<double>(16);
     tl->hist = a.take<double>(kMaxHistory);
     tl->flag = a.take<int>(4);
+    tl->lz = mass == 0 ? a.take<double>(6 * ng + kLzBlocks + 4) : nullptr;
   };
   layout(sz);
   DMG_HIP(hipMalloc(&tl->block, sz.used));
@@ -754,22 +757,11 @@ dmg_status dmg_twolevel_scaling(dmg_twolevel* tl, const double* v0, int32_t k, d
   dmg_hier* h = tl->grid;
   const int nx = tl->nx, ny = tl->ny, n = tl->nv, nb = row_blocks(n);
   const size_t ng = size_t(nx) * ny;
-  // scratch for this call only: six grid vectors, dot partials, one device scalar
-  Arena sz;
-  double *vec[6], *partials, *dscal;
-  auto layout = [&](Arena& a) {
-    for (auto& p : vec) p = a.take<double>(ng);
-    partials = a.take<double>(kLzBlocks);
-    dscal = a.take<double>(4);
-  };
-  layout(sz);
-  void* block = nullptr;
-  DMG_HIP(hipMalloc(&block, sz.used));
-  std::unique_ptr<void, void (*)(void*)> guard(block, [](void* p) { (void)hipFree(p); });
-  Arena a;
-  a.base = static_cast<char*>(block);
-  a.cap = sz.used;
-  layout(a);
+  // scratch kept in the handle since creation: six grid vectors, dot partials, device scalars
+  double* vec[6];
+  for (int q = 0; q < 6; ++q) vec[q] = tl->lz + size_t(q) * ng;
+  double* partials = tl->lz + 6 * ng;
+  double* dscal = partials + kLzBlocks;
   double *v = vec[0], *Av = vec[1], *vp = vec[2], *Avp = vec[3], *w = vec[4], *g = vec[5];
   const unsigned gb = unsigned(std::min<size_t>((ng + 255) / 256, 4096));
   auto dot = [&](const double* x, const double* y, double* out) -> dmg_status {

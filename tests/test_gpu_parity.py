@@ -395,6 +395,45 @@ def test_diffsolve_gradients(dmg):
             assert abs(fdb - adb) <= 1e-6 * max(abs(adb), 1e-12)
 
 
+def test_diffsolve_reports_non_convergence(dmg):
+    """A forward or adjoint solve that stops above rtol raises (unless strict=False, which
+    returns the last iterate and reports its residual)."""
+    n = 33
+    prob = pb.star(n, seed=5)
+    jac = dev(prob.jac)
+    K = dev(prob.K).requires_grad_(True)
+    b = dev(prob.b)
+    with pytest.raises(dmg.DmgError) as ei:
+        dmg.DiffSolve.apply(K, b, jac, 1e-10, 1)
+    assert ei.value.code == 6 and "forward" in str(ei.value)
+    u = dmg.DiffSolve.apply(K, b, jac, 1e-10, 1, None, False)
+    its, rr = dmg.DiffSolve.last["forward"]
+    assert its == 1 and rr > 1e-10
+    # b = 0 solves exactly (u = 0, relative residual 0); the adjoint of a loss with a nonzero
+    # target cannot reach 1e-16 in three cycles: backward raises
+    t = dev(prob.target)
+    u = dmg.DiffSolve.apply(K, torch.zeros_like(b), jac, 1e-16, 3)
+    assert float(u.abs().max()) == 0.0
+    with pytest.raises(dmg.DmgError) as ei:
+        ((u - t) ** 2).sum().backward()
+    assert "adjoint" in str(ei.value)
+    dmg.DiffSolve.clear_cache()
+
+
+def test_stats_match_oracle_complexities(dmg):
+    """Levels, grid complexity and operator complexity (Sec. 4 definitions) against the
+    oracle's hierarchy."""
+    for prob in (pb.star(129, seed=1), pb.quarter_annulus(33, ny=49), pb.star(45, seed=1, ny=67)):
+        S_or = fem.assemble_stencil(prob.jac, prob.K, prob.nx, prob.ny)
+        levels = boxmg.build_hierarchy(S_or)
+        gc, oc = boxmg.complexities(levels)
+        h = dmg.Hierarchy(dev(S_or))
+        lv, hgc, hoc = h.stats()
+        h.close()
+        assert lv == len(levels)
+        assert abs(hgc - gc) <= 1e-14 * gc and abs(hoc - oc) <= 1e-14 * oc, (hgc, gc, hoc, oc)
+
+
 def test_transfer_matches_oracle(dmg):
     mp = pb.Star.random(pb.streams(1)[0])
     n = 33
