@@ -1248,14 +1248,16 @@ dmg_status dmg_autotune(dmg_hier* h, double* u, const double* b, int32_t flags, 
   }
   if ((flags & 4) && h->opts.precision == DMG_FP32_IR) {
     // float32 cycles per refinement step: more cycles per float64 residual trade cheap float
-    // work against the float64 residual pass; keep the count with the fastest solve
+    // work against the float64 residual pass; keep the count with the fastest solve (float32
+    // rounding caps what one step can reach at ~1e-7, so 1e-10 needs at least two steps and
+    // counts beyond 8 only add cycles)
     hipEvent_t e0 = nullptr, e1 = nullptr;
     DMG_HIP(hipEventCreate(&e0));
     DMG_HIP(hipEventCreate(&e1));
     float best_ms = 1e30f;
     int best = h->opts.inner_cycles;
     dmg_status st = DMG_OK;
-    for (int m = 1; m <= 4 && st == DMG_OK; ++m) {
+    for (int m = 1; m <= 8 && st == DMG_OK; ++m) {
       h->opts.inner_cycles = m;
       reset_solve_graphs(h);
       float total = 0.f;

@@ -114,6 +114,23 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ par
   }
 }
 
+constexpr int kCheckThreads = 1024;
+
+// Sum over a kCheckThreads workgroup in a fixed order (wavefront trees, then the wavefront sums
+// in index order); the total is returned to thread 0.
+__device__ __forceinline__ double block_sum_check(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  __shared__ double ws[kCheckThreads / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) ws[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < kCheckThreads / 64; ++w) t += ws[w];
+  return t;
+}
+
 // Convergence bookkeeping of a solve step, on the device: sums the partials into out[0..1]
 // (||r||^2, ||r||), appends ||r||/||b|| to the history and raises *stop when
 // ||r||^2 <= target^2, the step budget is spent, or the norm is not finite.
@@ -126,9 +143,18 @@ __device__ __forceinline__ void check_body(const double* __restrict__ partials, 
   // nothing is written once the solve has stopped
   const int stopped = st[0], steps = st[1], max_steps = st[2];
   const double bnorm = sc[1], target = sc[6];
-  double acc = 0.0;
-  for (int k = threadIdx.x; k < count; k += 256) acc += partials[k];
-  const double t = block_sum(acc);
+  // thread k sums partials k, k + 1024, ... in four interleaved running sums, so that four loads
+  // are in flight at a time; then the fixed-order tree over the workgroup
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int k = threadIdx.x;
+  for (; k + 3 * kCheckThreads < count; k += 4 * kCheckThreads) {
+    a0 += partials[k];
+    a1 += partials[k + kCheckThreads];
+    a2 += partials[k + 2 * kCheckThreads];
+    a3 += partials[k + 3 * kCheckThreads];
+  }
+  for (; k < count; k += kCheckThreads) a0 += partials[k];
+  const double t = block_sum_check((a0 + a1) + (a2 + a3));
   if (stopped) return;
   if (threadIdx.x == 0) {
     out[0] = t;
@@ -140,7 +166,7 @@ __device__ __forceinline__ void check_body(const double* __restrict__ partials, 
   }
 }
 
-__global__ __launch_bounds__(256) void k_check(const double* __restrict__ partials, int count,
+__global__ __launch_bounds__(kCheckThreads) void k_check(const double* __restrict__ partials, int count,
                                                double* __restrict__ out,
                                                const double* __restrict__ sc,
                                                int* __restrict__ st, double* __restrict__ hist,
@@ -149,7 +175,7 @@ __global__ __launch_bounds__(256) void k_check(const double* __restrict__ partia
 }
 
 // One workgroup per instance.
-__global__ __launch_bounds__(256) void k_check_multi(const CheckArgs* __restrict__ list) {
+__global__ __launch_bounds__(kCheckThreads) void k_check_multi(const CheckArgs* __restrict__ list) {
   const CheckArgs& c = list[blockIdx.x];
   check_body(c.partials, c.count, c.out, c.sc, c.st, c.hist, c.hist_cap);
 }
@@ -442,7 +468,7 @@ dmg_status launch_solve_start(const double* pb, int nb, const double* pr, int nr
 
 dmg_status launch_check_multi(const CheckArgs* list, int count, hipStream_t s) {
   if (count < 1) return DMG_OK;
-  k_check_multi<<<count, 256, 0, s>>>(list);
+  k_check_multi<<<count, kCheckThreads, 0, s>>>(list);
   return launch_check("check_multi");
 }
 
@@ -470,7 +496,7 @@ dmg_status launch_gather_multi(const CheckArgs* list, int count, double* rel, in
 
 dmg_status launch_check_step(const double* partials, int count, double* out, const double* sc,
                              int* st, double* hist, int hist_cap, hipStream_t s) {
-  k_check<<<1, 256, 0, s>>>(partials, count, out, sc, st, hist, hist_cap);
+  k_check<<<1, kCheckThreads, 0, s>>>(partials, count, out, sc, st, hist, hist_cap);
   return launch_check("check");
 }
 
