@@ -289,9 +289,11 @@ def run_diff_leg(dmg, dev, steps: int, n: int = 2049, n_dirs: int = 64):
 
 def run_transfer_leg(dmg, dev, n: int = 1025, seed: int = 1, reps: int = 20):
     """Grid <-> mesh transfers on the n x n grid of the star (root seed `seed`): a jittered P1
-    lattice with about n^2 / 0.28 vertices mapped through the same star map; C and M_p are
-    assembled on the host at creation; from_grid = CG2(M_p, C u_c) and to_grid = C^T CG2(M_p, r_p)
-    are timed with HIP events (mean of `reps` back-to-back applies)."""
+    lattice with about n^2 / 0.28 vertices mapped through the same star map, the rasterised
+    coupled mass (nq = 4).  Two forms: C and C^T assembled at creation (CSR products per apply),
+    and matrix-free (the overlap sets stored, the integrals recomputed per apply).
+    from_grid = CG2(M_p, C u_c) and to_grid = C^T CG2(M_p, r_p) are timed with HIP events (mean
+    of `reps` back-to-back applies); the device bytes that hold C are reported for both."""
     import numpy as np
     import torch
 
@@ -301,41 +303,59 @@ def run_transfer_leg(dmg, dev, n: int = 1025, seed: int = 1, reps: int = 20):
     t0 = time.perf_counter()
     mesh = pb.lattice_mesh(mp, m, np.random.default_rng(seed))
     t_mesh = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    T = dmg.Transfer(mesh.xy_c, mesh.xy_p, mesh.tris, mesh.dof, n, n, nq=4, device=dev)
-    torch.cuda.synchronize()
-    t_create = time.perf_counter() - t0
-    nnzC, nnzM = T.nnz()
     uc = torch.zeros((n, n), dtype=torch.float64, device=dev)
     uc[1:-1, 1:-1] = 1.0
     rp = torch.ones(mesh.nv, dtype=torch.float64, device=dev)
     up = torch.empty(mesh.nv, dtype=torch.float64, device=dev)
     rc = torch.empty((n, n), dtype=torch.float64, device=dev)
-    out = {}
-    for name, fn in (("from_grid", lambda: T.from_grid(uc, out=up)), ("to_grid", lambda: T.to_grid(rp, out=rc))):
-        for _ in range(3):
-            fn()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        torch.cuda._sleep(20_000_000)
-        e0.record()
-        for _ in range(reps):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        out[name + "_us"] = round(1e3 * e0.elapsed_time(e1) / reps, 1)
+
+    def timed(T):
+        out = {}
+        for name, fn in (("from_grid", lambda: T.from_grid(uc, out=up)),
+                         ("to_grid", lambda: T.to_grid(rp, out=rc))):
+            for _ in range(3):
+                fn()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            torch.cuda._sleep(20_000_000)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            out[name + "_us"] = round(1e3 * e0.elapsed_time(e1) / reps, 1)
+        return out
+
+    t0 = time.perf_counter()
+    T = dmg.Transfer(mesh.xy_c, mesh.xy_p, mesh.tris, mesh.dof, n, n, nq=4, device=dev)
+    torch.cuda.synchronize()
+    t_create = time.perf_counter() - t0
+    nnzC, nnzM = T.nnz()
+    c_bytes = T.memory()[0]
+    out = timed(T)
+    T.close()
     # algorithmic bytes of one apply: C (or C^T) once and M_p twice at 12 B per nonzero (value +
     # column index) plus 4 B row pointers, the CG2 vectors (r0 written; r0, q0 for q0 = M r0;
     # r1 from r0, q0; r0, r1 for p1; r0, r1 and the result for x2: 11 passes of nv float64 plus
     # the int32 permutation) and the grid vector (read or written once)
     bytes_apply = (12.0 * (nnzC + 2 * nnzM) + 4.0 * 3 * mesh.nv + 8.0 * 11 * mesh.nv + 4.0 * mesh.nv
                    + 8.0 * n * n)
-    T.close()
+    t0 = time.perf_counter()
+    Tf = dmg.Transfer(mesh.xy_c, mesh.xy_p, mesh.tris, mesh.dof, n, n, nq=4, device=dev,
+                      matrix_free=True)
+    torch.cuda.synchronize()
+    t_create_mf = time.perf_counter() - t0
+    mf_bytes, pairs = Tf.memory()
+    mf = timed(Tf)
+    Tf.close()
     return {"grid": [n, n], "mesh_vertices": int(mesh.nv), "mesh_triangles": int(mesh.tris.shape[0]),
             "nnz_C": nnzC, "nnz_M": nnzM, "mesh_s": round(t_mesh, 2), "create_s": round(t_create, 2),
             **out, "apply_bytes": bytes_apply,
             "from_grid_gbs": round(bytes_apply / (out["from_grid_us"] * 1e-6) / 1e9, 1),
-            "to_grid_gbs": round(bytes_apply / (out["to_grid_us"] * 1e-6) / 1e9, 1)}
+            "to_grid_gbs": round(bytes_apply / (out["to_grid_us"] * 1e-6) / 1e9, 1),
+            "C_device_bytes": c_bytes,
+            "matrix_free": {"create_s": round(t_create_mf, 2), "overlap_pairs": pairs,
+                            "C_device_bytes": mf_bytes, **mf}}
 
 
 def run_twolevel_leg(dmg, dev, sizes=(129, 257, 513), seed: int = 1, reps: int = 3):

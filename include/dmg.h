@@ -59,7 +59,10 @@ typedef enum dmg_status {
 enum { DMG_FP64 = 0, DMG_FP32_IR = 1 };
 
 /* Mesh setup flags (dmg_transfer_create_mesh, dmg_twolevel_create). */
-enum { DMG_MESH_HOST_SETUP = 1 /* assemble C and C^T on the host instead of the device */ };
+enum {
+  DMG_MESH_HOST_SETUP = 1, /* assemble C and C^T on the host instead of the device */
+  DMG_MESH_MATRIX_FREE = 2 /* store no C: recompute its action from the overlap sets each apply */
+};
 
 /* Solver options.  Fill with dmg_default_options() and change what is needed. */
 typedef struct dmg_options {
@@ -181,7 +184,7 @@ dmg_status dmg_sweep(dmg_hier* h, int32_t level, int32_t kind, double* u, const 
  * lowest measured solve time among the row-separable orders whose post order is the reverse of
  * the pre order (0123/3210, 1032/2301, 2301/1032, 3210/0123) -- this changes the iterates, so
  * read the choice back with dmg_hier_config.  flags bit 2 (DMG_FP32_IR): pick inner_cycles in
- * 1..4 with the lowest measured solve time to 1e-10 -- this changes the iterates (read it back
+ * 1..8 with the lowest measured solve time to 1e-10 -- this changes the iterates (read it back
  * with dmg_hier_inner_cycles).  u is scratch (overwritten), b a right-hand side of the level-0
  * shape.  Synchronous.  Invalidates captured graphs. */
 dmg_status dmg_autotune(dmg_hier* h, double* u, const double* b, int32_t flags, int32_t reps,
@@ -265,6 +268,15 @@ dmg_status dmg_transfer_create(int32_t Np, int32_t Nc, const int32_t* C_rowptr,
  * allocate nothing.  C and C^T are assembled on the device unless flags has
  * DMG_MESH_HOST_SETUP (or a row of C holds more than 64 grid columns, when the host assembly
  * takes over); both give the same bits.  M_p is assembled on the host (threads).
+ * DMG_MESH_MATRIX_FREE (Sec. 2.3.1, closing remark; takes precedence over DMG_MESH_HOST_SETUP):
+ * no C or C^T is stored.  Setup keeps the overlap sets -- per triangle its vertex images,
+ * Jacobian factor and box of grid cells, per grid cell the triangles whose box holds it -- and
+ * every apply recomputes the same triangle-cell integrals as the assembly (same nq rule), C u
+ * by a gather per triangle then per mesh row, C^T y by a gather per grid cell then per grid
+ * vertex, in fixed orders (deterministic; equal to the assembled form's results to rounding).
+ * Device memory drops from two CSR copies of C to 16 B per vertex + ~20 B per triangle + 4 B per
+ * triangle-cell pair + a buffer of max(3 nt, 4 cells) float64; each apply costs the integrals
+ * once more.  dmg_transfer_copy_C then returns DMG_ERR_UNSUPPORTED and nnz_C reads 0.
  * from_grid: u_p = CG2(M_p, C u_c)      u_c [ny][nx] -> u_p [nv]
  * to_grid:   r_c = C^T CG2(M_p, r_p)    r_p [nv]     -> r_c [ny][nx]
  * CG2 = two iterations of unpreconditioned CG from 0.  Dirichlet entries are ignored/zero. */
@@ -273,6 +285,9 @@ dmg_status dmg_transfer_create_mesh(int32_t nv, int32_t nt, const double* xy_c,
                                     int32_t nx, int32_t ny, int32_t nq, int32_t flags,
                                     hipStream_t stream, dmg_transfer** out);
 dmg_status dmg_transfer_info(const dmg_transfer* t, int64_t* nnz_C, int64_t* nnz_M);
+/* Device bytes that hold C (its CSR and C^T's, or the matrix-free overlap sets with their buffer)
+ * and the triangle-cell pairs of the overlap sets (0 unless matrix-free); nullable outputs. */
+dmg_status dmg_transfer_memory(const dmg_transfer* t, size_t* bytes_C, int64_t* overlap_pairs);
 /* C as a host CSR with rows in the caller's vertex order: rp [nv + 1], ci and v [nnz_C] (from
  * dmg_transfer_info), columns ascending within a row.  Synchronous. */
 dmg_status dmg_transfer_copy_C(const dmg_transfer* t, int32_t* rp, int32_t* ci, double* v);

@@ -16,7 +16,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import DMG_FP32_IR, DMG_FP64, DMG_MESH_HOST_SETUP, DmgError, Options, default_options
+from ._lib import DMG_FP32_IR, DMG_FP64, DMG_MESH_HOST_SETUP, DMG_MESH_MATRIX_FREE, DmgError, Options, default_options
 
 __all__ = ["Hierarchy", "assemble_stencil", "grad_K", "Transfer", "TwoLevel", "BatchSolver", "DiffSolve",
            "default_options", "Options", "DmgError", "DMG_FP64", "DMG_FP32_IR", "lib", "version"]
@@ -223,11 +223,17 @@ class Hierarchy:
             pass
 
 
+def _mesh_flags(host_setup: bool, matrix_free: bool) -> int:
+    return (DMG_MESH_HOST_SETUP if host_setup else 0) | (DMG_MESH_MATRIX_FREE if matrix_free else 0)
+
+
 class Transfer:
-    """L2-projection transfers between a P1 mesh and the grid (host mesh arrays)."""
+    """L2-projection transfers between a P1 mesh and the grid (host mesh arrays).  host_setup:
+    assemble C on the host; matrix_free: store no C, recompute its action from the overlap sets
+    on every apply."""
 
     def __init__(self, xy_c, xy_p, tris, dof, nx: int, ny: int, nq: int = 4, device="cuda",
-                 host_setup: bool = False):
+                 host_setup: bool = False, matrix_free: bool = False):
         self.xy_c = np.ascontiguousarray(xy_c, dtype=np.float64)
         self.xy_p = np.ascontiguousarray(xy_p, dtype=np.float64)
         self.tris = np.ascontiguousarray(tris, dtype=np.int32)
@@ -243,7 +249,7 @@ class Transfer:
             _lib.check(lib().dmg_transfer_create_mesh(self.nv, self.nt, self.xy_c.ctypes.data,
                                                       self.xy_p.ctypes.data, self.tris.ctypes.data,
                                                       self.dof.ctypes.data, nx, ny, nq,
-                                                      DMG_MESH_HOST_SETUP if host_setup else 0,
+                                                      _mesh_flags(host_setup, matrix_free),
                                                       _stream(self.device), C.byref(h)))
         self._h = h
 
@@ -290,6 +296,12 @@ class Transfer:
         _lib.check(lib().dmg_transfer_info(self._h, C.byref(a), C.byref(b)))
         return int(a.value), int(b.value)
 
+    def memory(self):
+        """(device bytes holding C, triangle-cell pairs of the overlap sets or 0)."""
+        a, b = C.c_size_t(), C.c_int64()
+        _lib.check(lib().dmg_transfer_memory(self._h, C.byref(a), C.byref(b)))
+        return int(a.value), int(b.value)
+
     def from_grid(self, u_c: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
         if out is None:
             out = torch.empty(self.nv, dtype=torch.float64, device=self.device)
@@ -320,10 +332,11 @@ class TwoLevel:
     """The two-level cycle on a physical P1 mesh (host mesh arrays) over the grid hierarchy
     ``grid`` (a Hierarchy on the grid that the mesh maps to; it must outlive this object).
     nq: 0 for the exact coupled mass (default) or the order of the rasterised rule;
-    mass: "lumped" or "cg2"; host_setup: assemble C on the host (the default is the device)."""
+    mass: "lumped" or "cg2"; host_setup: assemble C on the host (the default is the device);
+    matrix_free: store no C (as for Transfer)."""
 
     def __init__(self, grid: Hierarchy, xy_c, xy_p, tris, dof, K_t=None, nq: int = 0, mass: str = "lumped",
-                 host_setup: bool = False):
+                 host_setup: bool = False, matrix_free: bool = False):
         if mass not in ("lumped", "cg2"):
             raise ValueError("mass must be 'lumped' or 'cg2'")
         self.grid = grid
@@ -347,7 +360,7 @@ class TwoLevel:
                                                  tris.ctypes.data, dof.ctypes.data,
                                                  None if kt is None else kt.ctypes.data, grid._h, nq,
                                                  0 if mass == "lumped" else 2,
-                                                 DMG_MESH_HOST_SETUP if host_setup else 0,
+                                                 _mesh_flags(host_setup, matrix_free),
                                                  _stream(self.device), C.byref(h)))
         self._h = h
 

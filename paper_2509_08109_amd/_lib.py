@@ -12,7 +12,7 @@ STATUS_NAMES = {0: "DMG_OK", 1: "DMG_ERR_INVALID_ARG", 2: "DMG_ERR_DIMS", 3: "DM
                 4: "DMG_ERR_NOT_SPD", 5: "DMG_ERR_NONFINITE", 6: "DMG_ERR_NO_CONVERGENCE",
                 7: "DMG_ERR_HIP", 8: "DMG_ERR_UNSUPPORTED"}
 DMG_FP64, DMG_FP32_IR = 0, 1
-DMG_MESH_HOST_SETUP = 1
+DMG_MESH_HOST_SETUP, DMG_MESH_MATRIX_FREE = 1, 2
 
 
 class DmgError(RuntimeError):
@@ -61,6 +61,7 @@ SIGNATURES = {
     "dmg_transfer_workspace_bytes": (_st, [_i32, _i32, C.c_int64, C.POINTER(C.c_size_t)]),
     "dmg_transfer_create": (_st, [_i32, _i32, _p, _p, _p, _p, _p, _p, _p, C.c_size_t, _p, C.POINTER(_p)]),
     "dmg_transfer_info": (_st, [_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "dmg_transfer_memory": (_st, [_p, C.POINTER(C.c_size_t), C.POINTER(C.c_int64)]),
     "dmg_transfer_copy_C": (_st, [_p, _p, _p, _p]),
     "dmg_transfer_from_grid": (_st, [_p, _p, _p, _p]),
     "dmg_transfer_to_grid": (_st, [_p, _p, _p, _p]),

@@ -27,7 +27,8 @@ FLAGS = [
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
     "-I" + os.path.join(ROOT, "include"),
 ]
-SOURCES = ["setup_kernels.hip", "cycle_kernels.hip", "fused_kernels.hip", "transfer.hip", "mesh_setup.hip",
+SOURCES = ["setup_kernels.hip", "cycle_kernels.hip", "fused_kernels.hip", "transfer.hip", "transfer_mf.hip",
+           "mesh_setup.hip",
            "twolevel.hip", "line_smoother.hip", "batch.hip", "api.hip"]
 
 

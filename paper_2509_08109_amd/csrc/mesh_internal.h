@@ -23,9 +23,25 @@ struct dmg_transfer {
   void* cblock = nullptr;  // C and C^T
   bool device_C = false;   // C was assembled on the device
   bool borrowed = false;   // C and M_p are the caller's device CSR arrays (created from CSR)
+  // matrix-free C (DMG_MESH_MATRIX_FREE): the overlap sets in mfblock, no stored C or C^T
+  bool mf = false;
+  int nt = 0, nq = 0;
+  double* mf_xy = nullptr;      // [nv][2] vertex images T(x_v), internal order
+  double* mf_jac = nullptr;     // [nt] Jacobian factor area(tau_p) / area(mapped tau), 0: skipped
+  double* mf_q = nullptr;       // Gauss nodes [nq] then weights [nq] on [0, 1]
+  double* mf_buf = nullptr;     // [max(3 nt, 4 cells)]: per-triangle or per-cell partial sums
+  int* mf_tv = nullptr;         // [nt][3] internal vertex indices
+  int* mf_vt_ptr = nullptr;     // [nv + 1]: mesh row -> entries 3 t + slot, ascending t
+  int* mf_vt = nullptr;
+  int* mf_ct_ptr = nullptr;     // [(nx - 1)(ny - 1) + 1]: cell -> triangles whose box holds it
+  int* mf_ct = nullptr;         // ascending t
+  int64_t mf_pairs = 0;         // triangle-cell pairs of the boxes
+  size_t mf_bytes = 0;          // device bytes of mfblock
+  void* mfblock = nullptr;
   ~dmg_transfer() {
     if (block) (void)hipFree(block);
     if (cblock) (void)hipFree(cblock);
+    if (mfblock) (void)hipFree(mfblock);
   }
 };
 
@@ -103,11 +119,17 @@ std::vector<int> locality_order(const Mesh& m, int nx, int ny);
 // Rows of a in the order perm (new row i = old row perm[i]); columns through colmap when given.
 Csr permute_rows(const Csr& a, const std::vector<int>& perm, const std::vector<int>* colmap);
 
+// How a transfer holds C: assembled on the device (the host assembly takes over when a row is
+// too long for the device merge), assembled on the host, or matrix-free over the overlap sets.
+enum class CForm { kDevice, kHost, kMatrixFree };
+inline CForm c_form(int flags) {
+  return (flags & DMG_MESH_MATRIX_FREE) ? CForm::kMatrixFree
+         : (flags & DMG_MESH_HOST_SETUP) ? CForm::kHost : CForm::kDevice;
+}
+
 // Transfer operators of mesh m on the nx x ny grid with internal row i = caller vertex perm[i].
-// device_C: assemble C and C^T on the device (the host assembly is used when false, or when a
-// row is too long for the device merge).
 dmg_status transfer_build(const Mesh& m, int nx, int ny, int nq, const std::vector<int>& perm,
-                          bool device_C, hipStream_t s, std::unique_ptr<dmg_transfer>& out);
+                          CForm form, hipStream_t s, std::unique_ptr<dmg_transfer>& out);
 
 // ---- the coupled-mass integrals of one mapped triangle over one grid cell -------------------
 // Shared by the host and the device assembly, with contraction off, so both give the same bits.
@@ -250,6 +272,16 @@ dmg_status device_transpose(const int* rp, const int* ci, const double* v, int n
 // *ok receives the verdict; flag is one device int of scratch.  Synchronises s.
 dmg_status device_check_csr(const int* rp, const int* ci, int nr, int nc, int nnz, int* flag,
                             bool* ok, hipStream_t s);
+
+// Matrix-free C over the overlap sets W_i (transfer_mf.hip): builds t's lists from the mesh
+// (internal vertex order perm); the apply kernels replace the CSR products of C and C^T.
+dmg_status mf_build(const Mesh& m, int nx, int ny, int nq, const std::vector<int>& perm,
+                    hipStream_t s, dmg_transfer* t);
+// t->r = dof * (C u_c) and its squared-norm partials (tblocks(nv, kMG) of them)
+dmg_status mf_launch_from(dmg_transfer* t, const double* u_c, const int* stop, hipStream_t s);
+// r_c = C^T x (x in the internal order)
+dmg_status mf_launch_ct(dmg_transfer* t, const double* x, double* r_c, const int* stop,
+                        hipStream_t s);
 
 // Row products run on groups of G consecutive lanes (G divides 64): lane l of a group reads
 // entries rp[r] + l, rp[r] + l + G, ... (coalesced), and the group sums its lanes with xor

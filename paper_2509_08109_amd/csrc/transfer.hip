@@ -324,6 +324,7 @@ __global__ __launch_bounds__(256) void k_t_ct(const int* __restrict__ rp, const 
 }  // namespace
 
 dmg_status launch_from_start(dmg_transfer* t, const double* u_c, const int* stop, hipStream_t s) {
+  if (t->mf) return mf_launch_from(t, u_c, stop, s);
   k_t_init_from<<<tblocks(t->nv, kMG), 256, 0, s>>>(t->Crp, t->Cci, t->Cv, u_c, t->dof, t->r,
                                                      t->nv, t->partials, stop);
   return launch_check("transfer C u");
@@ -358,6 +359,7 @@ dmg_status cg2_tail(dmg_transfer* t, double* out, X2Mode mode, const int* stop, 
 }
 
 dmg_status launch_ct(dmg_transfer* t, const double* x, double* r_c, const int* stop, hipStream_t s) {
+  if (t->mf) return mf_launch_ct(t, x, r_c, stop, s);
   const int ng = t->nx * t->ny;
   k_t_ct<<<tblocks(ng, kCG), 256, 0, s>>>(t->CTrp, t->CTci, t->CTv, x, r_c, ng, stop);
   return launch_check("transfer C^T x");
@@ -402,7 +404,7 @@ Csr permute_rows(const Csr& a, const std::vector<int>& perm, const std::vector<i
 }
 
 dmg_status transfer_build(const Mesh& m, int nx, int ny, int nq, const std::vector<int>& perm,
-                          bool device_C, hipStream_t stream, std::unique_ptr<dmg_transfer>& out) {
+                          CForm form, hipStream_t stream, std::unique_ptr<dmg_transfer>& out) {
   const int nv = m.nv;
   const size_t ng = size_t(nx) * ny;
   std::unique_ptr<dmg_transfer> t(new dmg_transfer);
@@ -413,9 +415,13 @@ dmg_status transfer_build(const Mesh& m, int nx, int ny, int nq, const std::vect
     if (bytes) DMG_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, stream));
     return DMG_OK;
   };
-  // C and C^T: on the device, else (or when a row is too long for the device merge) on the host
+  // C and C^T: on the device, else (or when a row is too long for the device merge) on the host;
+  // or neither, the overlap sets instead
   bool have_C = false;
-  if (device_C) {
+  if (form == CForm::kMatrixFree) {
+    DMG_CHECK(mf_build(m, nx, ny, nq, perm, stream, t.get()));
+    have_C = true;
+  } else if (form == CForm::kDevice) {
     DeviceCsrPair d;
     const dmg_status st = device_assemble_C(m, nx, ny, nq, perm, stream, d);
     if (st == DMG_OK) {
@@ -614,8 +620,7 @@ dmg_status dmg_transfer_create_mesh(int32_t nv, int32_t nt, const double* xy_c,
   Mesh m{nv, nt, xy_c, xy_p, tris, dof, {}, {}};
   build_adjacency(m);
   std::unique_ptr<dmg_transfer> t;
-  DMG_CHECK(transfer_build(m, nx, ny, nq, locality_order(m, nx, ny),
-                           (flags & DMG_MESH_HOST_SETUP) == 0, stream, t));
+  DMG_CHECK(transfer_build(m, nx, ny, nq, locality_order(m, nx, ny), c_form(flags), stream, t));
   *out = t.release();
   return DMG_OK;
 }
@@ -628,10 +633,24 @@ dmg_status dmg_transfer_info(const dmg_transfer* t, int64_t* nnz_C, int64_t* nnz
   return DMG_OK;
 }
 
+dmg_status dmg_transfer_memory(const dmg_transfer* t, size_t* bytes_C, int64_t* overlap_pairs) {
+  clear_error();
+  if (!t) return fail(DMG_ERR_INVALID_ARG, "null transfer");
+  if (bytes_C) {
+    const size_t nc = size_t(t->nx) * t->ny;
+    *bytes_C = t->mf ? t->mf_bytes
+                     : (size_t(t->nv) + 1 + nc + 1) * sizeof(int) +
+                           2 * size_t(t->nnzC) * (sizeof(int) + sizeof(double));
+  }
+  if (overlap_pairs) *overlap_pairs = t->mf ? t->mf_pairs : 0;
+  return DMG_OK;
+}
+
 dmg_status dmg_transfer_copy_C(const dmg_transfer* t, int32_t* rp, int32_t* ci, double* v) {
   clear_error();
   if (!t || !rp || (t->nnzC > 0 && (!ci || !v)))
     return fail(DMG_ERR_INVALID_ARG, "null pointer argument");
+  if (t->mf) return fail(DMG_ERR_UNSUPPORTED, "a matrix-free transfer stores no C");
   const int n = t->nv;
   std::vector<int> irp(n + 1), perm(n), ici(size_t(t->nnzC));
   std::vector<double> iv(size_t(t->nnzC));

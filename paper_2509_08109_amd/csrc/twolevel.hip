@@ -145,6 +145,24 @@ __global__ __launch_bounds__(256) void k_tl_prolong(const int* __restrict__ rp,
   }
 }
 
+// The same two operations from C v formed beforehand (cx = dof * (C v), a matrix-free transfer):
+// u += gamma cx / ML on the free rows, or x = cx / ML stored (zero on Dirichlet rows).
+template <bool ADD>
+__global__ __launch_bounds__(256) void k_tl_lumped(const double* __restrict__ cx,
+                                                   const double* __restrict__ ML,
+                                                   const unsigned char* __restrict__ dof,
+                                                   double* __restrict__ out, int n, double gamma,
+                                                   const int* __restrict__ stop) {
+  if (halted(stop)) return;
+  for (int r = int(blockIdx.x) * 256 + int(threadIdx.x); r < n; r += int(gridDim.x) * 256) {
+    if constexpr (ADD) {
+      if (dof[r]) out[r] += gamma * (cx[r] / ML[r]);
+    } else {
+      out[r] = dof[r] ? cx[r] / ML[r] : 0.0;
+    }
+  }
+}
+
 // ---- the scaling estimate (generalized Lanczos on grid vectors) ----------------------------
 // x = P v = dof * (C v) / ML on the mesh (lumped interpolation, stored).
 __global__ __launch_bounds__(256) void k_tl_interp(const int* __restrict__ rp,
@@ -306,7 +324,11 @@ dmg_status cycle(dmg_twolevel* tl, const int* stop, hipStream_t s, bool lead = t
     DMG_CHECK(launch_ct(t, tl->w, tl->rc, stop, s));
   }
   DMG_CHECK(grid_vcycle(tl->grid, tl->ec, tl->rc, true, stop, s));
-  if (tl->mass == 0) {
+  if (tl->mass == 0 && t->mf) {
+    DMG_CHECK(launch_from_start(t, tl->ec, stop, s));
+    k_tl_lumped<true><<<nb, 256, 0, s>>>(t->r, tl->ML, t->dof, tl->u, n, tl->gamma, stop);
+    DMG_CHECK(launch_check("two-level interpolation"));
+  } else if (tl->mass == 0) {
     k_tl_prolong<<<nb, 256, 0, s>>>(t->Crp, t->Cci, t->Cv, tl->ec, tl->ML, t->dof, tl->u, n,
                                     tl->gamma, stop);
     DMG_CHECK(launch_check("two-level interpolation"));
@@ -582,8 +604,7 @@ dmg_status dmg_twolevel_create(int32_t nv, int32_t nt, const double* xy_c, const
     std::vector<int> pos(tl->cs.begin(), tl->cs.end() - 1);
     for (int v : cell) perm[pos[tl->colour[v]]++] = v;
   }
-  DMG_CHECK(transfer_build(m, nx, ny, nq, perm, (flags & DMG_MESH_HOST_SETUP) == 0, stream,
-                           tl->t));
+  DMG_CHECK(transfer_build(m, nx, ny, nq, perm, c_form(flags), stream, tl->t));
   std::vector<int> newidx(nv);
   for (int i = 0; i < nv; ++i) newidx[perm[i]] = i;
   const Csr A = permute_rows(off, perm, &newidx);
@@ -778,7 +799,12 @@ dmg_status dmg_twolevel_scaling(dmg_twolevel* tl, const double* v0, int32_t k, d
   };
   // G x = R A_p P x on grid vectors, R = C^T ML^{-1}
   auto applyG = [&](const double* x, double* out) -> dmg_status {
-    k_tl_interp<<<nb, 256, 0, stream>>>(t->Crp, t->Cci, t->Cv, x, tl->ML, t->dof, tl->w, n);
+    if (t->mf) {
+      DMG_CHECK(launch_from_start(t, x, nullptr, stream));
+      k_tl_lumped<false><<<nb, 256, 0, stream>>>(t->r, tl->ML, t->dof, tl->w, n, 0.0, nullptr);
+    } else {
+      k_tl_interp<<<nb, 256, 0, stream>>>(t->Crp, t->Cci, t->Cv, x, tl->ML, t->dof, tl->w, n);
+    }
     DMG_CHECK(launch_check("lanczos P"));
     k_tl_apply_scaled<<<nb, 256, 0, stream>>>(tl->Arp, tl->Aci, tl->Av, tl->Ad, tl->w, tl->ML,
                                               t->dof, t->x, n);

@@ -2,7 +2,8 @@
 float64 oracle (oracle/dmg.py) on star-domain meshes: the relaxation colours bit for bit, every
 iterate entry by entry (1e-12 |ref| + 256 eps max|ref|, tests/entrywise.py) for both mass modes
 and both coupled-mass rules, whole solves (cycle counts, residual histories, solutions), the
-zero-residual start, the iteration cap, and the captured-graph path against the eager one."""
+zero-residual start, the iteration cap, the captured-graph path against the eager one, and the
+cycle over the matrix-free coupled mass."""
 import numpy as np
 import pytest
 import torch
@@ -33,11 +34,11 @@ def host(t):
 _CACHE = {}
 
 
-def pair(lib, n, seed=1, mass="lumped", nq=0, kind=None):
+def pair(lib, n, seed=1, mass="lumped", nq=0, kind=None, matrix_free=False):
     """(problem, oracle two-level, GPU two-level) on the star mesh of grid size n (or on the unit
     square with the discontinuous diffusivity ``kind``); nq = 0 is the exact coupled mass, nq > 0
-    the rasterised rule of that order."""
-    key = (n, seed, mass, nq, kind)
+    the rasterised rule of that order; matrix_free: the library stores no C."""
+    key = (n, seed, mass, nq, kind, matrix_free)
     if key not in _CACHE:
         P = pb.star_dmg(n, seed=seed) if kind is None else pb.discontinuous_dmg(kind, n)
         m = P.mesh
@@ -48,7 +49,8 @@ def pair(lib, n, seed=1, mass="lumped", nq=0, kind=None):
         orc = dmg.TwoLevel(A, M, Cm, grid, n, n, dmg.mesh_colouring(m.tris, m.dof),
                            mass="lumped" if mass == "lumped" else 2)
         H = lib.Hierarchy(lib.assemble_stencil(dev(P.grid.jac), dev(P.grid.K)))
-        tl = lib.TwoLevel(H, m.xy_c, m.xy_p, m.tris, m.dof, K_t=P.K_t, nq=nq, mass=mass)
+        tl = lib.TwoLevel(H, m.xy_c, m.xy_p, m.tris, m.dof, K_t=P.K_t, nq=nq, mass=mass,
+                          matrix_free=matrix_free)
         _CACHE[key] = (P, orc, tl)
     return _CACHE[key]
 
@@ -82,6 +84,40 @@ def test_cycles_match_oracle(lib, n, mass, nq):
         tl.cycle(ug, fg)
         used = assert_iterate(f"cycle {k + 1}", host(ug), uo)
         print(f"[twolevel] n={n} {mass} nq={nq} cycle {k + 1}: worst excess {used:.1f} eps max|u|")
+
+
+@pytest.mark.parametrize("n,mass,nq", [(33, "lumped", 0), (65, "lumped", 0), (33, "cg2", 4),
+                                       (33, "lumped", 8)])
+def test_matrix_free_cycles_match_oracle(lib, n, mass, nq):
+    """The two-level cycle over the matrix-free coupled mass (no C stored; its action recomputed
+    from the overlap sets on every interpolation and restriction) against the oracle's cycle with
+    the assembled C, entry by entry, and its solve's cycle count and history."""
+    P, orc, tl = pair(lib, n, mass=mass, nq=nq, matrix_free=True)
+    g = np.random.Generator(np.random.PCG64(13))
+    u0 = np.where(P.mesh.dof, g.uniform(-1, 1, P.mesh.nv), 0.0)
+    uo, ug, fg = u0.copy(), dev(u0), dev(P.f)
+    for k in range(3):
+        orc.cycle(uo, P.f)
+        tl.cycle(ug, fg)
+        used = assert_iterate(f"matrix-free cycle {k + 1}", host(ug), uo)
+        print(f"[twolevel] matrix-free n={n} {mass} nq={nq} cycle {k + 1}: worst excess {used:.1f} eps max|u|")
+    if mass == "lumped":
+        u, k, rel, hist = tl.solve(fg, rtol=1e-10)
+        uo, ko, histo, _ = dmg.solve(orc, P.f, rtol=1e-10)
+        assert k == ko and rel <= 1e-10
+        assert np.allclose(hist, histo, rtol=1e-6, atol=1e-13)
+        assert_iterate("matrix-free solution", host(u), uo)
+
+
+def test_matrix_free_scaling_estimate_matches_oracle(lib):
+    """Sec. 2.4's estimate runs P and R through the matrix-free coupled mass."""
+    n = 33
+    P, orc, tl = pair(lib, n, matrix_free=True)
+    v0 = np.random.Generator(np.random.PCG64(9)).uniform(-1, 1, (n, n))
+    go, To = dmg.coarse_scaling(orc, v0, 12)
+    gg, Tg = tl.estimate_scaling(dev(v0), 12)
+    assert abs(gg - go) <= 1e-9 * abs(go), (gg, go)
+    assert np.allclose(Tg, To, rtol=1e-8, atol=1e-10)
 
 
 @pytest.mark.parametrize("n", [17, 33])
