@@ -89,8 +89,10 @@ typedef struct dmg_options {
                             interior line of one parity, even lines first, is solved exactly
                             with the other lines held; the post sweep runs in reverse (the
                             V-cycle stays symmetric).  Line smoothing runs unfused level by
-                            level, float64 only (DMG_FP32_IR and the batch solve return
-                            DMG_ERR_UNSUPPORTED); nu_pre / nu_post count whole line sweeps. */
+                            level: in float64, in the float32 inner cycles of DMG_FP32_IR
+                            (float32 stencils, weights and Thomas factors), and in the batch
+                            solve (each line step launched once per level size over all
+                            instances); nu_pre / nu_post count whole line sweeps.         */
   int32_t coarse_gemv;   /* 1 (default): when the coarse kernel's top level is a coarse level
                             with at most 1024 interior unknowns (33 x 33), apply the cycle from
                             there down as its dense matrix (built at setup) with one
@@ -308,8 +310,11 @@ void dmg_transfer_destroy(dmg_transfer* t);
  * or max_iters; a converged instance's work stops at once.  The iterates equal those of
  * dmg_solve on each instance.  u (in: initial guess, out: solution) and b are host arrays of
  * device pointers; iters / relres (host, [count], nullable) receive per-instance counts and
- * final relative residuals.  float64 only (DMG_ERR_UNSUPPORTED otherwise); nu_pre + nu_post
- * must be even.  Returns DMG_ERR_NO_CONVERGENCE if any instance did not converge. */
+ * final relative residuals.  float64 only (DMG_ERR_UNSUPPORTED otherwise); with point smoothing
+ * nu_pre + nu_post must be even.  With line relaxation (opts.smoother 1-3) each level size runs
+ * its unfused line steps (coarse start, sweeps, residual, restriction, interpolation) as one
+ * launch each over its instances, and the iterates equal dmg_solve's with coarse_gemv = 0.
+ * Returns DMG_ERR_NO_CONVERGENCE if any instance did not converge. */
 dmg_status dmg_batch_workspace_bytes(int32_t count, const int32_t* nx, const int32_t* ny,
                                      const dmg_options* opts, size_t* bytes);
 dmg_status dmg_batch_setup(int32_t count, const int32_t* nx, const int32_t* ny,
@@ -321,7 +326,8 @@ dmg_status dmg_batch_solve(dmg_batch* bt, double* const* u, const double* const*
 /* Batch autotuner, synchronous; u is scratch (overwritten), b the right-hand sides.
  * flags bit 0: the wave-strip segment height of each level size and the coarse-tail workgroup
  * size, by timing `reps` batched steps each -- numerically neutral.
- * flags bit 1: the colour-order pair (the same four row-separable pairs as dmg_autotune, post
+ * flags bit 1 (point smoothing only; ignored with line relaxation, which visits no colours):
+ * the colour-order pair (the same four row-separable pairs as dmg_autotune, post
  * order the reverse of the pre order), by timing whole batched solves to 1e-10 from zero; one
  * pair serves every instance, and each instance's dense coarse operators are rebuilt for it.
  * This changes the iterates: read the choice back with dmg_batch_config.  Bit 1 runs first. */

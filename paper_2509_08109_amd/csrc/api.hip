@@ -55,8 +55,6 @@ dmg_status check_options(const dmg_options* o) {
     return fail(DMG_ERR_INVALID_ARG, "strip_kernel must be 0 or 1");
   if (o->smoother < 0 || o->smoother > 3)
     return fail(DMG_ERR_INVALID_ARG, "smoother must be 0 (point), 1 (x-lines), 2 (y-lines) or 3");
-  if (o->smoother != 0 && o->precision != DMG_FP64)
-    return fail(DMG_ERR_UNSUPPORTED, "line relaxation runs in float64 only");
   if (o->coarse_gemv != 0 && o->coarse_gemv != 1)
     return fail(DMG_ERR_INVALID_ARG, "coarse_gemv must be 0 or 1");
   return DMG_OK;
@@ -212,9 +210,13 @@ void carve(dmg_hier& h, Arena& a, const std::vector<std::pair<int, int>>& dims,
       L.u = a.take<double>(n);
       L.b = in_img ? slot(h.tail_img, img.b[k]) : a.take<double>(n);
     }
-    if (o.smoother != 0 && int(l) < h.tail) L.lf = a.take<double>(4 * n);
+    if (o.smoother != 0 && int(l) < h.tail) {
+      L.lf = a.take<double>(4 * n);
+      if (fp32) L.lf32 = a.take<float>(4 * n);
+    }
     if (fp32) {
-      if (int(l) >= h.tail) L.S32 = staged ? slot(h.tail_img32, img.S[k]) : a.take<float>(5 * n);
+      if (int(l) >= h.tail || o.smoother != 0)
+        L.S32 = staged ? slot(h.tail_img32, img.S[k]) : a.take<float>(5 * n);
       L.u32 = a.take<float>(n);
       L.b32 = in_img ? slot(h.tail_img32, img.b[k]) : a.take<float>(n);
     }
@@ -400,28 +402,34 @@ dmg_status coarse_launch(dmg_hier* h, T* u_top, const T* b_top, hipStream_t s, b
   return tail_launch<T>(h, u_top, b_top, s, u0_zero, stop);
 }
 
-// One float64 V-cycle with zebra line relaxation: unfused kernels on the levels above the coarse
-// tail (coarse levels start from u = 0; u0_zero says the same of level 0), the tail levels with
-// their line sweeps and the coarsest solve in the one-workgroup coarse kernel.
-dmg_status vcycle_line(dmg_hier* h, double* u0, const double* b0, bool u0_zero, const int* stop,
-                       hipStream_t s) {
+// One V-cycle in precision T with zebra line relaxation: unfused kernels on the levels above the
+// coarse tail (coarse levels start from u = 0; u0_zero says the same of level 0), the tail levels
+// with their line sweeps and the coarsest solve in the one-workgroup coarse kernel (or the dense
+// coarse operator).  x64 (float cycles, nullable): x += *xscale u0 once the cycle is done.
+template <class Tp>
+dmg_status vcycle_line(dmg_hier* h, Tp* u0, const Tp* b0, bool u0_zero, const int* stop,
+                       hipStream_t s, double* x64 = nullptr, const double* xscale = nullptr) {
+  using Pr = Prec<Tp>;
   const dmg_options& o = h->opts;
   const int T = h->tail;
-  auto U = [&](int l) { return l == 0 ? u0 : h->L[l].u; };
-  auto B = [&](int l) { return l == 0 ? b0 : static_cast<const double*>(h->L[l].b); };
+  auto U = [&](int l) { return l == 0 ? u0 : Pr::u(h->L[l]); };
+  auto B = [&](int l) { return l == 0 ? b0 : static_cast<const Tp*>(Pr::b(h->L[l])); };
   for (int l = 0; l < T; ++l) {
     const Level& L = h->L[l];
-    if (l > 0 || u0_zero) DMG_CHECK(launch_fill<double>(U(l), 0.0, L.n(), s));
+    if (l > 0 || u0_zero) DMG_CHECK(launch_fill<Tp>(U(l), Tp(0), L.n(), s));
     for (int k = 0; k < o.nu_pre; ++k)
-      DMG_CHECK(line_sweep(L, U(l), B(l), o.smoother, true, stop, s));
-    DMG_CHECK(line_resid_restrict(L, h->L[l + 1], U(l), B(l), stop, s));
+      DMG_CHECK(line_sweep<Tp>(L, U(l), B(l), o.smoother, true, stop, s));
+    DMG_CHECK(line_resid_restrict<Tp>(L, h->L[l + 1], U(l), B(l), stop, s));
   }
-  DMG_CHECK(coarse_launch<double>(h, U(T), B(T), s, T == 0 && u0_zero, stop));
+  DMG_CHECK(coarse_launch<Tp>(h, U(T), B(T), s, T == 0 && u0_zero, stop));
   for (int l = T - 1; l >= 0; --l) {
     const Level& L = h->L[l];
-    DMG_CHECK(line_prolong(L, U(l + 1), U(l), stop, s));
+    DMG_CHECK(line_prolong<Tp>(L, U(l + 1), U(l), stop, s));
     for (int k = 0; k < o.nu_post; ++k)
-      DMG_CHECK(line_sweep(L, U(l), B(l), o.smoother, false, stop, s));
+      DMG_CHECK(line_sweep<Tp>(L, U(l), B(l), o.smoother, false, stop, s));
+  }
+  if constexpr (std::is_same<Tp, float>::value) {
+    if (x64) DMG_CHECK(launch_ir_update(x64, u0, h->L[0].n(), xscale, s, stop));
   }
   return DMG_OK;
 }
@@ -440,10 +448,7 @@ dmg_status vcycle_impl(dmg_hier* h, T* u0, const T* b0, hipStream_t s, double* p
                        const double* xscale = nullptr) {
   using Pr = Prec<T>;
   const dmg_options& o = h->opts;
-  if (o.smoother != 0) {
-    if constexpr (std::is_same<T, double>::value) return vcycle_line(h, u0, b0, u0_zero, stop, s);
-    return fail(DMG_ERR_UNSUPPORTED, "line relaxation runs in float64 only");
-  }
+  if (o.smoother != 0) return vcycle_line<T>(h, u0, b0, u0_zero, stop, s, x64, xscale);
   const OrderParams pre = order_params(o.pre_order), post = order_params(o.post_order);
   T* cur[kMaxLevels];
   auto other = [&](int l, const T* x) -> T* {
@@ -871,7 +876,10 @@ dmg_status setup_impl(dmg_hier* h, const double* S, hipStream_t s, bool first) {
     DMG_CHECK(launch_f32_batch(fb, s));
   }
   if (h->opts.smoother != 0)
-    for (int l = 0; l < h->tail; ++l) DMG_CHECK(line_factors(h->L[l], s));
+    for (int l = 0; l < h->tail; ++l) {
+      DMG_CHECK(line_factors<double>(h->L[l], s));
+      if (h->opts.precision == DMG_FP32_IR) DMG_CHECK(line_factors<float>(h->L[l], s));
+    }
   DMG_CHECK(compute_basis(h, s));
   DMG_CHECK(compute_gemv_basis(h, s));
   if (!first) return DMG_OK;

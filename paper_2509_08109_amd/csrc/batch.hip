@@ -7,7 +7,10 @@
 // every instance has stopped; each instance has its own stop flag, so the tiles of converged
 // instances exit at once.  Results equal bitwise those of dmg_solve on each instance alone with
 // one-wavefront sweeps and coarse_gemv = 0 (the wave sweeps, the tail and the check do the same
-// arithmetic, and segment heights change no bit).
+// arithmetic, and segment heights change no bit).  With line relaxation the levels above the
+// tails run the unfused line steps instead, each launched once per level size over its
+// instances (one argument list per level size serves every step: the sweeps are in place),
+// and the residual norms come from a per-instance norm kernel.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -25,12 +28,14 @@ constexpr int kNormBlocks = 64;     // workgroups per instance for the starting 
 constexpr size_t kArgAlign = 256;   // alignment of each argument list in the argument buffer
 
 struct Launch {
-  enum Kind { WAVE, TAIL, DENSE, RESID, CHECK } kind;
+  enum Kind { WAVE, TAIL, DENSE, RESID, CHECK, LINE } kind;
   int mode = 0;        // WAVE: 1 pre, 2 post with prolongation, 3 post
   int count = 0;       // instances (list length)
   int tiles_per = 0;   // WAVE: tiles per instance; DENSE: largest interior unknown count
   size_t off = 0;      // byte offset of the list in the device argument buffer
   size_t lds = 0;      // TAIL: LDS bytes
+  dmg::LineStep step = dmg::LineStep::kSweep;  // LINE: which step, on which lines, at which size
+  int dir = 0, parity = 0, nx = 0, ny = 0;
 };
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -89,10 +94,29 @@ namespace {
 
 size_t args_capacity(int count, const dmg_options& o) {
   const size_t sweeps = size_t(o.nu_pre + o.nu_post);
-  const size_t per_inst = size_t(kMaxLevels) * sweeps * sizeof(StripArgs<double>) +
-                          sizeof(TailArgs<double>) + sizeof(CheckArgs) + 2 * sizeof(NormArgs);
-  const size_t lists = size_t(count) * kMaxLevels * sweeps + 8;
+  size_t per_inst = size_t(kMaxLevels) * sweeps * sizeof(StripArgs<double>) +
+                    sizeof(TailArgs<double>) + sizeof(CheckArgs) + 2 * sizeof(NormArgs);
+  size_t lists = size_t(count) * kMaxLevels * sweeps + 8;
+  if (o.smoother != 0) {  // line cycles: per level size one list for every step, one for u = 0
+    per_inst += 2 * size_t(kMaxLevels) * sizeof(LineArgs<double>);
+    lists += 2 * size_t(count) * kMaxLevels;
+  }
   return size_t(count) * per_inst + lists * kArgAlign;
+}
+
+// The line sweeps of one pre-smoothing pass as (direction, parity), even lines first; the post
+// pass runs them in reverse.
+int line_seq(int smoother, int dir[4], int par[4]) {
+  int n = 0;
+  if (smoother == 1 || smoother == 3) {
+    dir[n] = 0, par[n++] = 0;
+    dir[n] = 0, par[n++] = 1;
+  }
+  if (smoother == 2 || smoother == 3) {
+    dir[n] = 1, par[n++] = 0;
+    dir[n] = 1, par[n++] = 1;
+  }
+  return n;
 }
 
 size_t batch_extra_bytes(int count, const dmg_options& o) {
@@ -152,9 +176,10 @@ dmg_status build_schedule(dmg_batch* bt, double* const* u, const double* const* 
     const double* e;
     double* partials;
   };
+  const bool line = o.smoother != 0;
   // per instance and strip level: the buffers of each pre and post sweep (as in one V-cycle)
   std::vector<std::vector<std::vector<Sweep>>> pre_sw(count), post_sw(count);
-  for (int k = 0; k < count; ++k) {
+  for (int k = 0; k < count && !line; ++k) {
     dmg_hier* h = bt->inst[k];
     const int T = h->tail;
     double* u0 = u[k];
@@ -232,14 +257,70 @@ dmg_status build_schedule(dmg_batch* bt, double* const* u, const double* const* 
     out->tiles_per = tiles_per;
     return put(list.data(), list.size() * sizeof(list[0]), &out->off);
   };
+  // line cycles: every step of a level size reads one argument list (the sweeps are in place)
+  std::map<std::tuple<long, int, int>, std::pair<size_t, size_t>> line_lists;  // (all, l > 0)
+  std::map<std::tuple<long, int, int>, int> zero_count;
+  if (line) {
+    for (auto& [key, mem] : groups) {
+      std::vector<LineArgs<double>> all, coarse;
+      for (auto [k, l] : mem) {
+        dmg_hier* h = bt->inst[k];
+        const Level& L = h->L[l];
+        LineArgs<double> a{};
+        a.S = L.S;
+        a.lf = L.lf;
+        a.P = L.P;
+        a.u = l == 0 ? u[k] : L.u;
+        a.b = l == 0 ? b[k] : L.b;
+        a.r = L.r;
+        a.bH = h->L[l + 1].b;
+        a.e = h->L[l + 1].u;
+        a.nx = L.nx;
+        a.ny = L.ny;
+        a.stop = bt->state + 4 * k;
+        all.push_back(a);
+        if (l > 0) coarse.push_back(a);
+      }
+      size_t off_all = 0, off_coarse = 0;
+      DMG_CHECK(put(all.data(), all.size() * sizeof(all[0]), &off_all));
+      if (!coarse.empty()) DMG_CHECK(put(coarse.data(), coarse.size() * sizeof(coarse[0]), &off_coarse));
+      line_lists[key] = {off_all, off_coarse};
+      zero_count[key] = int(coarse.size());
+    }
+  }
+  int ldir[4], lpar[4];
+  const int nls = line ? line_seq(o.smoother, ldir, lpar) : 0;
+  auto line_launch = [&](const std::tuple<long, int, int>& key, LineStep step, int dir, int par,
+                         bool coarse_only) {
+    Launch L;
+    L.kind = Launch::LINE;
+    L.step = step;
+    L.dir = dir;
+    L.parity = par;
+    L.nx = std::get<1>(key);
+    L.ny = std::get<2>(key);
+    L.count = coarse_only ? zero_count[key] : int(groups[key].size());
+    L.off = coarse_only ? line_lists[key].second : line_lists[key].first;
+    return L;
+  };
   std::vector<Launch> seq;
-  for (auto& [key, mem] : groups)
+  for (auto& [key, mem] : groups) {
+    if (line) {  // coarse levels start from 0; pre sweeps; residual; restriction
+      if (zero_count[key] > 0) seq.push_back(line_launch(key, LineStep::kZero, 0, 0, true));
+      for (int s = 0; s < o.nu_pre; ++s)
+        for (int q = 0; q < nls; ++q)
+          seq.push_back(line_launch(key, LineStep::kSweep, ldir[q], lpar[q], false));
+      seq.push_back(line_launch(key, LineStep::kResidual, 0, 0, false));
+      seq.push_back(line_launch(key, LineStep::kRestrict, 0, 0, false));
+      continue;
+    }
     for (int s = 0; s < o.nu_pre; ++s) {
       Launch L;
       DMG_CHECK(wave_list(mem, true, s, &L));
       L.mode = 1;
       seq.push_back(L);
     }
+  }
   {  // coarse tails: the one-workgroup tail kernel, or the dense operator of the tail's top
     std::vector<TailArgs<double>> list;
     std::vector<DenseArgs<double>> dense;
@@ -280,13 +361,21 @@ dmg_status build_schedule(dmg_batch* bt, double* const* u, const double* const* 
       seq.push_back(L);
     }
   }
-  for (auto it = groups.rbegin(); it != groups.rend(); ++it)
+  for (auto it = groups.rbegin(); it != groups.rend(); ++it) {
+    if (line) {  // interpolation, then the post sweeps in reverse
+      seq.push_back(line_launch(it->first, LineStep::kProlong, 0, 0, false));
+      for (int s = 0; s < o.nu_post; ++s)
+        for (int q = nls - 1; q >= 0; --q)
+          seq.push_back(line_launch(it->first, LineStep::kSweep, ldir[q], lpar[q], false));
+      continue;
+    }
     for (int s = 0; s < o.nu_post; ++s) {
       Launch L;
       DMG_CHECK(wave_list(it->second, false, s, &L));
       L.mode = s == 0 ? 2 : 3;
       seq.push_back(L);
     }
+  }
   // per-instance norm arguments (starting norms; residual partials of all-tail instances)
   std::vector<NormArgs> norms(count), tail_only;
   for (int k = 0; k < count; ++k) {
@@ -294,7 +383,7 @@ dmg_status build_schedule(dmg_batch* bt, double* const* u, const double* const* 
     const Level& L0 = h->L[0];
     norms[k] = NormArgs{L0.S, u[k], b[k], L0.nx, L0.ny, h->scalars, bt->state + 4 * k, rtol,
                         max_iters, h->partials};
-    if (h->tail == 0) tail_only.push_back(norms[k]);
+    if (h->tail == 0 || line) tail_only.push_back(norms[k]);  // no fused sweep gives partials
   }
   if (!tail_only.empty()) {
     Launch L;
@@ -307,7 +396,7 @@ dmg_status build_schedule(dmg_batch* bt, double* const* u, const double* const* 
     std::vector<CheckArgs> list(count);
     for (int k = 0; k < count; ++k) {
       dmg_hier* h = bt->inst[k];
-      list[k] = CheckArgs{h->partials, h->tail > 0 ? level0_tiles[k] : kNormBlocks,
+      list[k] = CheckArgs{h->partials, (h->tail > 0 && !line) ? level0_tiles[k] : kNormBlocks,
                           h->scalars + 2, h->scalars, bt->state + 4 * k, h->hist, kMaxHistory};
     }
     Launch L;
@@ -348,6 +437,10 @@ dmg_status run_step(dmg_batch* bt, hipStream_t s) {
         break;
       case Launch::CHECK:
         DMG_CHECK(launch_check_multi(reinterpret_cast<const CheckArgs*>(p), L.count, s));
+        break;
+      case Launch::LINE:
+        DMG_CHECK(launch_line_multi(L.step, reinterpret_cast<const LineArgs<double>*>(p), L.count,
+                                    L.nx, L.ny, L.dir, L.parity, s));
         break;
     }
   }
@@ -441,7 +534,6 @@ dmg_status dmg_batch_workspace_bytes(int32_t count, const int32_t* nx, const int
   dmg_default_options(&o);
   if (opts) o = *opts;
   o.coarse_gemv = 0;  // the batch runs its coarse levels in the one-workgroup coarse kernel
-  if (o.smoother != 0) return fail(DMG_ERR_UNSUPPORTED, "the batch solve uses point smoothing");
   size_t total = 0;
   for (int k = 0; k < count; ++k) {
     size_t b = 0;
@@ -463,7 +555,6 @@ dmg_status dmg_batch_setup(int32_t count, const int32_t* nx, const int32_t* ny,
   dmg_default_options(&o);
   if (opts) o = *opts;
   o.coarse_gemv = 0;  // the batch runs its coarse levels in the one-workgroup coarse kernel
-  if (o.smoother != 0) return fail(DMG_ERR_UNSUPPORTED, "the batch solve uses point smoothing");
   if (o.precision != DMG_FP64)
     return fail(DMG_ERR_UNSUPPORTED, "batched solves run in float64 (precision DMG_FP64)");
   size_t need = 0;
@@ -504,9 +595,9 @@ dmg_status dmg_batch_setup(int32_t count, const int32_t* nx, const int32_t* ny,
   DMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&bt->h_rel), size_t(count) * sizeof(double)));
   DMG_HIP(hipHostMalloc(reinterpret_cast<void**>(&bt->h_steps), size_t(count) * sizeof(int)));
   // launch shapes: one per level size, shared by every instance that has that size
-  std::map<std::pair<int, int>, int> members;
+  std::map<std::pair<int, int>, int> members;  // (line cycles launch no strip kernels)
   for (auto* h : bt->inst)
-    for (int l = 0; l < h->tail; ++l) ++members[{h->L[l].nx, h->L[l].ny}];
+    for (int l = 0; l < h->tail && o.smoother == 0; ++l) ++members[{h->L[l].nx, h->L[l].ny}];
   for (auto& [d, m] : members) bt->seg_h[d] = default_seg_h(d.first, d.second, m);
   *out = bt.release();
   return DMG_OK;
@@ -582,7 +673,7 @@ dmg_status dmg_batch_autotune(dmg_batch* bt, double* const* u, const double* con
     return DMG_OK;
   };
   dmg_status st = DMG_OK;
-  if (flags & 2) {
+  if ((flags & 2) && bt->opts.smoother == 0) {  // (line relaxation visits no colours)
     // colour orders: the row-separable pairs whose post order reverses the pre order (the
     // V-cycle stays symmetric); each is timed as whole batched solves to 1e-10 from zero, which
     // counts the cycles it saves or costs.  One pair serves every instance.

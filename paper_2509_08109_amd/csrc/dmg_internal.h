@@ -75,7 +75,9 @@ struct Level {
   double* r = nullptr;    // residual scratch
   double* lf = nullptr;   // line relaxation (levels above the tail): [4][ny][nx] Thomas factors
                           // of the x-lines (super-diagonal, reciprocal pivot), then the y-lines
-  float* S32 = nullptr;   // fp32 copies for DMG_FP32_IR (S32: tail levels only)
+  float* lf32 = nullptr;  // its float32 counterpart (line relaxation with DMG_FP32_IR)
+  float* S32 = nullptr;   // fp32 copies for DMG_FP32_IR (S32: tail levels, and every level
+                          // with line relaxation)
   float* P32 = nullptr;
   float* u32 = nullptr;
   float* t32 = nullptr;
@@ -438,19 +440,46 @@ dmg_status launch_check_step(const double* partials, int count, double* out, con
 dmg_status launch_stencil_apply(const double* S, const double* x, double* y, int nx, int ny,
                                 hipStream_t s);
 
-// Zebra line relaxation on the levels above the coarse tail (line_smoother.hip), float64.
+// Zebra line relaxation on the levels above the coarse tail (line_smoother.hip), in T = double
+// (S, P, lf, r, b of the level) or T = float (their float32 copies S32, P32, lf32, r32, b32).
 // Every kernel is a no-op once *stop (nullable) is set.
 // The line sweeps of smoother 1-3 on level L (pre order, or reversed for the post sweep).
-dmg_status line_sweep(const Level& L, double* u, const double* b, int smoother, bool pre,
-                      const int* stop, hipStream_t s);
-// The Thomas factors of every x-line and y-line of level L into L.lf (at setup).
+template <class T>
+dmg_status line_sweep(const Level& L, T* u, const T* b, int smoother, bool pre, const int* stop,
+                      hipStream_t s);
+// The Thomas factors of every x-line and y-line of level L into L.lf / L.lf32 (at setup).
+template <class T>
 dmg_status line_factors(const Level& L, hipStream_t s);
-// L.r = b - A u, then Lc.b = P^T L.r.
-dmg_status line_resid_restrict(const Level& L, const Level& Lc, const double* u, const double* b,
+// r = b - A u into the level's residual scratch, then the coarse right-hand side P^T r.
+template <class T>
+dmg_status line_resid_restrict(const Level& L, const Level& Lc, const T* u, const T* b,
                                const int* stop, hipStream_t s);
 // u += P e.
-dmg_status line_prolong(const Level& L, const double* e, double* u, const int* stop,
-                        hipStream_t s);
+template <class T>
+dmg_status line_prolong(const Level& L, const T* e, T* u, const int* stop, hipStream_t s);
+
+// One instance's arrays at one level for the batched line cycle (line_smoother.hip): planar
+// stencil, line factors, weights to the next coarser level, iterate (in place), right-hand side,
+// residual / sweep scratch, the coarse right-hand side written by the restriction, the coarse
+// correction read by the interpolation, dims, and the instance's stop flag.
+template <class T>
+struct LineArgs {
+  const T* S;
+  const T* lf;
+  const T* P;
+  T* u;
+  const T* b;
+  T* r;
+  T* bH;
+  const T* e;
+  int nx, ny;
+  const int* stop;
+};
+enum class LineStep { kZero, kSweep, kResidual, kRestrict, kProlong };
+// One step over `count` instances of one level size nx x ny (list in device memory); kSweep
+// sweeps the lines of direction dir (0: x-lines, 1: y-lines) and the given parity.
+dmg_status launch_line_multi(LineStep step, const LineArgs<double>* list, int count, int nx,
+                             int ny, int dir, int parity, hipStream_t s);
 
 // One float64 V-cycle of hierarchy h on level-0 arrays (u, b); u_zero: start from u = 0
 // without reading u.  Every kernel is a no-op once *stop (nullable) is set.

@@ -1,4 +1,6 @@
-// V-cycles with zebra line relaxation, the smoother for anisotropic operators (float64).
+// V-cycles with zebra line relaxation, the smoother for anisotropic operators, in float64 or (the
+// inner cycles of float32 refinement) float32: every kernel is a template on the arithmetic type,
+// reading that precision's copies of the stencil, weights and line factors.
 //
 // A line sweep solves, for every interior line of one parity, the line's own equations exactly
 // with the unknowns of the other lines held: the tridiagonal system of the couplings along the
@@ -23,8 +25,9 @@ __device__ __forceinline__ bool halted(const int* stop) { return stop && *stop; 
 
 // 2x2 matrix t <- t / 2^e with 2^e the power of two at or above its largest entry: an exact
 // rescaling, which leaves the ratio p / q it produces unchanged and keeps long products finite.
-__device__ __forceinline__ void rescale(double t[4]) {
-  const double mx = fmax(fmax(fabs(t[0]), fabs(t[1])), fmax(fabs(t[2]), fabs(t[3])));
+template <class T>
+__device__ __forceinline__ void rescale(T t[4]) {
+  const T mx = fmax(fmax(fabs(t[0]), fabs(t[1])), fmax(fabs(t[2]), fabs(t[3])));
   if (!(mx > 0.0) || !isfinite(mx)) return;
   int ex = 0;
   (void)frexp(mx, &ex);
@@ -40,10 +43,9 @@ __device__ __forceinline__ void rescale(double t[4]) {
 // Lane p multiplies the matrices of its chunk of consecutive points (as in the sweeps), a scan
 // over the lanes gives each chunk its incoming cp, and the lane then runs the recurrence itself
 // over its points (lane 0 exactly as the sequential recurrence).
-template <int DIR>
-__global__ __launch_bounds__(256) void k_line_factor_scan(const double* __restrict__ S,
-                                                          double* __restrict__ lf, int nx,
-                                                          int ny) {
+template <int DIR, class T>
+__global__ __launch_bounds__(256) void k_line_factor_scan(const T* __restrict__ S,
+                                                          T* __restrict__ lf, int nx, int ny) {
   const size_t N = size_t(nx) * ny;
   const int lane = int(threadIdx.x) & 63;
   const int line = 1 + int(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
@@ -54,38 +56,38 @@ __global__ __launch_bounds__(256) void k_line_factor_scan(const double* __restri
   const int k0 = 1 + lane * L, k1 = min(1 + (lane + 1) * L, n + 1);
   const size_t step = DIR == 0 ? 1 : size_t(nx);
   const size_t v0 = DIR == 0 ? size_t(line) * nx : size_t(line);
-  const double* C = S;
-  const double* a = S + (DIR == 0 ? N : 2 * N);
-  double* cpo = lf + (DIR == 0 ? 0 : 2 * N);
-  double* imo = lf + (DIR == 0 ? N : 3 * N);
-  double t[4] = {1.0, 0.0, 0.0, 1.0};  // [[t0, t1], [t2, t3]] on (p, q)
+  const T* C = S;
+  const T* a = S + (DIR == 0 ? N : 2 * N);
+  T* cpo = lf + (DIR == 0 ? 0 : 2 * N);
+  T* imo = lf + (DIR == 0 ? N : 3 * N);
+  T t[4] = {T(1), T(0), T(0), T(1)};  // [[t0, t1], [t2, t3]] on (p, q)
   for (int k = k0; k < k1; ++k) {
     const size_t v = v0 + size_t(k) * step;
-    const double e = a[v + step], c = C[v], w = a[v];
-    const double n0 = e * t[2], n1 = e * t[3];
-    const double n2 = c * t[2] - w * t[0], n3 = c * t[3] - w * t[1];
+    const T e = a[v + step], c = C[v], w = a[v];
+    const T n0 = e * t[2], n1 = e * t[3];
+    const T n2 = c * t[2] - w * t[0], n3 = c * t[3] - w * t[1];
     t[0] = n0, t[1] = n1, t[2] = n2, t[3] = n3;
     rescale(t);
   }
   // inclusive scan: lane p holds the product of chunks 0..p (later chunks on the left)
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
-    double q[4];
+    T q[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) q[k] = __shfl_up(t[k], d, 64);
     if (lane >= d) {
-      const double n0 = t[0] * q[0] + t[1] * q[2], n1 = t[0] * q[1] + t[1] * q[3];
-      const double n2 = t[2] * q[0] + t[3] * q[2], n3 = t[2] * q[1] + t[3] * q[3];
+      const T n0 = t[0] * q[0] + t[1] * q[2], n1 = t[0] * q[1] + t[1] * q[3];
+      const T n2 = t[2] * q[0] + t[3] * q[2], n3 = t[2] * q[1] + t[3] * q[3];
       t[0] = n0, t[1] = n1, t[2] = n2, t[3] = n3;
       rescale(t);
     }
   }
   // incoming (p, q): the product of the earlier chunks applied to (0, 1)
-  const double p_in = __shfl_up(t[1], 1, 64), q_in = __shfl_up(t[3], 1, 64);
-  double pc = lane == 0 ? 0.0 : p_in / q_in;
+  const T p_in = __shfl_up(t[1], 1, 64), q_in = __shfl_up(t[3], 1, 64);
+  T pc = lane == 0 ? T(0) : p_in / q_in;
   for (int k = k0; k < k1; ++k) {
     const size_t v = v0 + size_t(k) * step;
-    const double im = 1.0 / (C[v] - a[v] * pc);
+    const T im = T(1) / (C[v] - a[v] * pc);
     pc = a[v + step] * im;
     cpo[v] = pc;
     imo[v] = im;
@@ -104,19 +106,16 @@ __global__ __launch_bounds__(256) void k_line_factor_scan(const double* __restri
 // over its points.  Lane 0's points round exactly as the sequential recurrence; a later lane's
 // starting value comes from the composed maps, whose rounding differs at the level of a few ulps.
 // dp (scratch) holds x, then pd.  u is read (neighbouring lines) and written (this line).
-template <int DIR>
-__global__ __launch_bounds__(256) void k_line_scan(const double* __restrict__ S,
-                                                   const double* uin,
-                                                   const double* __restrict__ b,
-                                                   const double* __restrict__ lf,
-                                                   double* __restrict__ dp, int nx, int ny,
-                                                   int parity, const int* __restrict__ stop,
-                                                   double* u) {
-  if (halted(stop)) return;
+// (blk: the workgroup's index among the sweep's workgroups)
+template <int DIR, class T>
+__device__ __forceinline__ void line_scan_body(const T* __restrict__ S, const T* uin,
+                                               const T* __restrict__ b, const T* __restrict__ lf,
+                                               T* __restrict__ dp, int nx, int ny, int parity,
+                                               T* u, unsigned blk) {
   const size_t N = size_t(nx) * ny;
   const int lane = int(threadIdx.x) & 63;
   const int first = parity == 0 ? 2 : 1;
-  const int line = first + 2 * int(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6));
+  const int line = first + 2 * int(blk * (blockDim.x >> 6) + (threadIdx.x >> 6));
   const int len = DIR == 0 ? nx : ny;     // points along a line, boundary included
   const int count = DIR == 0 ? ny : nx;   // lines
   if (line > count - 2) return;           // the whole wavefront
@@ -125,17 +124,17 @@ __global__ __launch_bounds__(256) void k_line_scan(const double* __restrict__ S,
   const int k0 = 1 + lane * L, k1 = min(1 + (lane + 1) * L, n + 1);  // may be empty
   const size_t step = DIR == 0 ? 1 : size_t(nx);
   const size_t v0 = DIR == 0 ? size_t(line) * nx : size_t(line);  // point k = 0 of the line
-  const double *W = S + N, *So = S + 2 * N, *SW = S + 3 * N, *SE = S + 4 * N;
-  const double* a = DIR == 0 ? W : So;  // coupling to the previous point of the line
-  const double* cp = lf + (DIR == 0 ? 0 : 2 * N);
-  const double* im = lf + (DIR == 0 ? N : 3 * N);
+  const T *W = S + N, *So = S + 2 * N, *SW = S + 3 * N, *SE = S + 4 * N;
+  const T* a = DIR == 0 ? W : So;  // coupling to the previous point of the line
+  const T* cp = lf + (DIR == 0 ? 0 : 2 * N);
+  const T* im = lf + (DIR == 0 ? N : 3 * N);
   // forward: x into dp; this lane's map pd_out = fa + fb pd_in
-  double fa = 0.0, fb = 1.0;
+  T fa = T(0), fb = T(1);
   // (the unrolled loops keep the loads of several points in flight ahead of the recurrence)
 #pragma unroll 4
   for (int k = k0; k < k1; ++k) {
     const size_t v = v0 + size_t(k) * step;
-    double off;
+    T off;
     if (DIR == 0)
       off = ((((So[v] * uin[v - nx] + So[v + nx] * uin[v + nx]) + SW[v] * uin[v - nx - 1]) +
               SE[v] * uin[v - nx + 1]) +
@@ -146,23 +145,23 @@ __global__ __launch_bounds__(256) void k_line_scan(const double* __restrict__ S,
               SE[v] * uin[v - nx + 1]) +
              SE[v + nx - 1] * uin[v + nx - 1]) +
             SW[v + nx + 1] * uin[v + nx + 1];
-    const double x = b[v] - off;
+    const T x = b[v] - off;
     dp[v] = x;
-    const double av = a[v], m = im[v];
+    const T av = a[v], m = im[v];
     fa = (x - av * fa) * m;
     fb = -(av * fb) * m;
   }
   // inclusive scan of the maps over the lanes (lane p after lane p - 1), then the incoming value
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
-    const double pa = __shfl_up(fa, d, 64), pb = __shfl_up(fb, d, 64);
+    const T pa = __shfl_up(fa, d, 64), pb = __shfl_up(fb, d, 64);
     if (lane >= d) {
       fa = fa + fb * pa;
       fb = fb * pb;
     }
   }
-  double pd = __shfl_up(fa, 1, 64);
-  if (lane == 0) pd = 0.0;
+  T pd = __shfl_up(fa, 1, 64);
+  if (lane == 0) pd = T(0);
 #pragma unroll 4
   for (int k = k0; k < k1; ++k) {
     const size_t v = v0 + size_t(k) * step;
@@ -170,45 +169,62 @@ __global__ __launch_bounds__(256) void k_line_scan(const double* __restrict__ S,
     dp[v] = pd;
   }
   // backward: this lane's map u_{k0} = ba + bb u_{k1} (cp of the last point taken as 0)
-  double ba = 0.0, bb = 1.0;
+  T ba = T(0), bb = T(1);
 #pragma unroll 4
   for (int k = k1 - 1; k >= k0; --k) {
     const size_t v = v0 + size_t(k) * step;
-    const double c = k == n ? 0.0 : cp[v];
+    const T c = k == n ? T(0) : cp[v];
     ba = dp[v] - c * ba;
     bb = -(c * bb);
   }
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
-    const double na = __shfl_down(ba, d, 64), nb = __shfl_down(bb, d, 64);
+    const T na = __shfl_down(ba, d, 64), nb = __shfl_down(bb, d, 64);
     if (lane + d < 64) {
       ba = ba + bb * na;
       bb = bb * nb;
     }
   }
-  double x = __shfl_down(ba, 1, 64);
-  if (lane == 63) x = 0.0;
+  T x = __shfl_down(ba, 1, 64);
+  if (lane == 63) x = T(0);
 #pragma unroll 4
   for (int k = k1 - 1; k >= k0; --k) {
     const size_t v = v0 + size_t(k) * step;
-    const double c = k == n ? 0.0 : cp[v];
+    const T c = k == n ? T(0) : cp[v];
     x = dp[v] - c * x;
     u[v] = x;
   }
 }
 
-// r = b - A u on interior points, 0 on the boundary ring.
-__global__ __launch_bounds__(256) void k_line_resid(const double* __restrict__ S,
-                                                    const double* __restrict__ u,
-                                                    const double* __restrict__ b,
-                                                    double* __restrict__ r, int nx, int ny,
-                                                    const int* __restrict__ stop) {
+template <int DIR, class T>
+__global__ __launch_bounds__(256) void k_line_scan(const T* __restrict__ S, const T* uin,
+                                                   const T* __restrict__ b,
+                                                   const T* __restrict__ lf, T* __restrict__ dp,
+                                                   int nx, int ny, int parity,
+                                                   const int* __restrict__ stop, T* u) {
   if (halted(stop)) return;
+  line_scan_body<DIR, T>(S, uin, b, lf, dp, nx, ny, parity, u, blockIdx.x);
+}
+
+// The same sweep over the instances of a batch that share one level size: instance blockIdx.y.
+template <int DIR, class T>
+__global__ __launch_bounds__(256) void k_line_scan_multi(const LineArgs<T>* __restrict__ list,
+                                                         int parity) {
+  const LineArgs<T> a = list[blockIdx.y];
+  if (halted(a.stop)) return;
+  line_scan_body<DIR, T>(a.S, a.u, a.b, a.lf, a.r, a.nx, a.ny, parity, a.u, blockIdx.x);
+}
+
+// r = b - A u on interior points, 0 on the boundary ring (blk of nblk workgroups, grid-stride).
+template <class T>
+__device__ __forceinline__ void line_resid_body(const T* __restrict__ S, const T* __restrict__ u,
+                                                const T* __restrict__ b, T* __restrict__ r,
+                                                int nx, int ny, unsigned blk, unsigned nblk) {
   const size_t N = size_t(nx) * ny;
-  for (size_t v = blockIdx.x * 256u + threadIdx.x; v < N; v += size_t(gridDim.x) * 256u) {
+  for (size_t v = blk * 256u + threadIdx.x; v < N; v += size_t(nblk) * 256u) {
     const int j = int(v / nx), i = int(v % nx);
     if (i > 0 && i < nx - 1 && j > 0 && j < ny - 1) {
-      const double off = ((((((S[3 * N + v] * u[v - nx - 1] + S[2 * N + v] * u[v - nx]) +
+      const T off = ((((((S[3 * N + v] * u[v - nx - 1] + S[2 * N + v] * u[v - nx]) +
                               S[4 * N + v] * u[v - nx + 1]) +
                              S[N + v] * u[v - 1]) +
                             S[N + v + 1] * u[v + 1]) +
@@ -217,31 +233,40 @@ __global__ __launch_bounds__(256) void k_line_resid(const double* __restrict__ S
                          S[3 * N + v + nx + 1] * u[v + nx + 1];
       r[v] = b[v] - (off + S[v] * u[v]);
     } else {
-      r[v] = 0.0;
+      r[v] = T(0);
     }
   }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_line_resid(const T* __restrict__ S,
+                                                    const T* __restrict__ u,
+                                                    const T* __restrict__ b, T* __restrict__ r,
+                                                    int nx, int ny,
+                                                    const int* __restrict__ stop) {
+  if (halted(stop)) return;
+  line_resid_body<T>(S, u, b, r, nx, ny, blockIdx.x, gridDim.x);
 }
 
 // b_H = P^T r on interior coarse points (boundary 0).  P per coarse cell c = J ncx + I: planes
 // 0-1 the x-line weights of fine (2I+1, 2J) on coarse (I, J), (I+1, J); 2-3 the y-line weights
 // of (2I, 2J+1) on (I, J), (I, J+1); 4-7 the centre weights of (2I+1, 2J+1) on (I, J), (I+1, J),
 // (I, J+1), (I+1, J+1).
-__global__ __launch_bounds__(256) void k_line_restrict(const double* __restrict__ P,
-                                                       const double* __restrict__ r,
-                                                       double* __restrict__ bH, int nx, int ny,
-                                                       const int* __restrict__ stop) {
-  if (halted(stop)) return;
+template <class T>
+__device__ __forceinline__ void line_restrict_body(const T* __restrict__ P,
+                                                   const T* __restrict__ r, T* __restrict__ bH,
+                                                   int nx, int ny, unsigned blk, unsigned nblk) {
   const int ncx = (nx + 1) / 2, ncy = (ny + 1) / 2;
   const size_t NC = size_t(ncx) * ncy;
-  for (size_t k = blockIdx.x * 256u + threadIdx.x; k < NC; k += size_t(gridDim.x) * 256u) {
+  for (size_t k = blk * 256u + threadIdx.x; k < NC; k += size_t(nblk) * 256u) {
     const int J = int(k / ncx), I = int(k % ncx);
     if (I == 0 || I == ncx - 1 || J == 0 || J == ncy - 1) {
-      bH[k] = 0.0;
+      bH[k] = T(0);
       continue;
     }
     const size_t f = size_t(2 * J) * nx + 2 * I;  // fine (2I, 2J)
     const size_t c = k, cw = k - 1, cs = k - ncx, csw = k - ncx - 1;
-    double acc = r[f];
+    T acc = r[f];
     acc += P[c] * r[f + 1] + P[NC + cw] * r[f - 1];
     acc += P[2 * NC + c] * r[f + nx] + P[3 * NC + cs] * r[f - nx];
     acc += P[4 * NC + c] * r[f + nx + 1] + P[5 * NC + cw] * r[f + nx - 1];
@@ -250,19 +275,27 @@ __global__ __launch_bounds__(256) void k_line_restrict(const double* __restrict_
   }
 }
 
-// u += P e on interior fine points.
-__global__ __launch_bounds__(256) void k_line_prolong(const double* __restrict__ P,
-                                                      const double* __restrict__ e,
-                                                      double* __restrict__ u, int nx, int ny,
-                                                      const int* __restrict__ stop) {
+template <class T>
+__global__ __launch_bounds__(256) void k_line_restrict(const T* __restrict__ P,
+                                                       const T* __restrict__ r,
+                                                       T* __restrict__ bH, int nx, int ny,
+                                                       const int* __restrict__ stop) {
   if (halted(stop)) return;
+  line_restrict_body<T>(P, r, bH, nx, ny, blockIdx.x, gridDim.x);
+}
+
+// u += P e on interior fine points.
+template <class T>
+__device__ __forceinline__ void line_prolong_body(const T* __restrict__ P,
+                                                  const T* __restrict__ e, T* __restrict__ u,
+                                                  int nx, int ny, unsigned blk, unsigned nblk) {
   const int ncx = (nx + 1) / 2, ncy = (ny + 1) / 2;
   const size_t NC = size_t(ncx) * ncy, N = size_t(nx) * ny;
-  for (size_t v = blockIdx.x * 256u + threadIdx.x; v < N; v += size_t(gridDim.x) * 256u) {
+  for (size_t v = blk * 256u + threadIdx.x; v < N; v += size_t(nblk) * 256u) {
     const int j = int(v / nx), i = int(v % nx);
     if (i == 0 || i == nx - 1 || j == 0 || j == ny - 1) continue;
     const size_t c = size_t(j >> 1) * ncx + (i >> 1);
-    double x;
+    T x;
     if (!(i & 1) && !(j & 1))
       x = e[c];
     else if ((i & 1) && !(j & 1))
@@ -274,6 +307,44 @@ __global__ __launch_bounds__(256) void k_line_prolong(const double* __restrict__
           P[7 * NC + c] * e[c + ncx + 1];
     u[v] += x;
   }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_line_prolong(const T* __restrict__ P,
+                                                      const T* __restrict__ e, T* __restrict__ u,
+                                                      int nx, int ny,
+                                                      const int* __restrict__ stop) {
+  if (halted(stop)) return;
+  line_prolong_body<T>(P, e, u, nx, ny, blockIdx.x, gridDim.x);
+}
+
+// The unfused steps of a batched line V-cycle over the instances of one level size (instance
+// blockIdx.y): u = 0 (a coarse level's start), r = b - A u then b_H = P^T r, u += P e.
+template <class T>
+__global__ __launch_bounds__(256) void k_line_zero_multi(const LineArgs<T>* __restrict__ list) {
+  const LineArgs<T> a = list[blockIdx.y];
+  if (halted(a.stop)) return;
+  const size_t N = size_t(a.nx) * a.ny;
+  for (size_t v = blockIdx.x * 256u + threadIdx.x; v < N; v += size_t(gridDim.x) * 256u)
+    a.u[v] = T(0);
+}
+template <class T>
+__global__ __launch_bounds__(256) void k_line_resid_multi(const LineArgs<T>* __restrict__ list) {
+  const LineArgs<T> a = list[blockIdx.y];
+  if (halted(a.stop)) return;
+  line_resid_body<T>(a.S, a.u, a.b, a.r, a.nx, a.ny, blockIdx.x, gridDim.x);
+}
+template <class T>
+__global__ __launch_bounds__(256) void k_line_restrict_multi(const LineArgs<T>* __restrict__ list) {
+  const LineArgs<T> a = list[blockIdx.y];
+  if (halted(a.stop)) return;
+  line_restrict_body<T>(a.P, a.r, a.bH, a.nx, a.ny, blockIdx.x, gridDim.x);
+}
+template <class T>
+__global__ __launch_bounds__(256) void k_line_prolong_multi(const LineArgs<T>* __restrict__ list) {
+  const LineArgs<T> a = list[blockIdx.y];
+  if (halted(a.stop)) return;
+  line_prolong_body<T>(a.P, a.e, a.u, a.nx, a.ny, blockIdx.x, gridDim.x);
 }
 
 unsigned grid_blocks(size_t n) {
@@ -294,10 +365,29 @@ int line_sweeps(int smoother, int dir[4], int par[4]) {
   return n;
 }
 
+// The arrays of level L in precision T: stencil (planar), weights, line factors, residual
+// scratch, right-hand side.
+template <class T>
+struct LineArrays;
+template <>
+struct LineArrays<double> {
+  const double *S, *P, *lf;
+  double *r, *b;
+  explicit LineArrays(const Level& L) : S(L.S), P(L.P), lf(L.lf), r(L.r), b(L.b) {}
+};
+template <>
+struct LineArrays<float> {
+  const float *S, *P, *lf;
+  float *r, *b;
+  explicit LineArrays(const Level& L) : S(L.S32), P(L.P32), lf(L.lf32), r(L.r32), b(L.b32) {}
+};
+
 }  // namespace
 
-dmg_status line_sweep(const Level& L, double* u, const double* b, int smoother, bool pre,
-                      const int* stop, hipStream_t s) {
+template <class T>
+dmg_status line_sweep(const Level& L, T* u, const T* b, int smoother, bool pre, const int* stop,
+                      hipStream_t s) {
+  const LineArrays<T> A(L);
   int dir[4], par[4];
   const int n = line_sweeps(smoother, dir, par);
   for (int k = 0; k < n; ++k) {
@@ -305,37 +395,88 @@ dmg_status line_sweep(const Level& L, double* u, const double* b, int smoother, 
     // dp scratch: r (free during the sweeps); one wavefront per line, four per workgroup
     if (dir[q] == 0) {
       const int lines = (L.ny - 2 + 1) / 2;
-      k_line_scan<0><<<(lines + 3) / 4, 256, 0, s>>>(L.S, u, b, L.lf, L.r, L.nx, L.ny, par[q],
-                                                     stop, u);
+      k_line_scan<0, T><<<(lines + 3) / 4, 256, 0, s>>>(A.S, u, b, A.lf, A.r, L.nx, L.ny, par[q],
+                                                        stop, u);
     } else {
       const int lines = (L.nx - 2 + 1) / 2;
-      k_line_scan<1><<<(lines + 3) / 4, 256, 0, s>>>(L.S, u, b, L.lf, L.r, L.nx, L.ny, par[q],
-                                                     stop, u);
+      k_line_scan<1, T><<<(lines + 3) / 4, 256, 0, s>>>(A.S, u, b, A.lf, A.r, L.nx, L.ny, par[q],
+                                                        stop, u);
     }
     DMG_CHECK(launch_check("line sweep"));
   }
   return DMG_OK;
 }
 
+template <class T>
 dmg_status line_factors(const Level& L, hipStream_t s) {
-  k_line_factor_scan<0><<<(L.ny - 2 + 3) / 4, 256, 0, s>>>(L.S, L.lf, L.nx, L.ny);
+  const LineArrays<T> A(L);
+  T* lf = const_cast<T*>(A.lf);
+  k_line_factor_scan<0, T><<<(L.ny - 2 + 3) / 4, 256, 0, s>>>(A.S, lf, L.nx, L.ny);
   DMG_CHECK(launch_check("line factors x"));
-  k_line_factor_scan<1><<<(L.nx - 2 + 3) / 4, 256, 0, s>>>(L.S, L.lf, L.nx, L.ny);
+  k_line_factor_scan<1, T><<<(L.nx - 2 + 3) / 4, 256, 0, s>>>(A.S, lf, L.nx, L.ny);
   return launch_check("line factors y");
 }
 
-dmg_status line_resid_restrict(const Level& L, const Level& Lc, const double* u, const double* b,
+template <class T>
+dmg_status line_resid_restrict(const Level& L, const Level& Lc, const T* u, const T* b,
                                const int* stop, hipStream_t s) {
-  k_line_resid<<<grid_blocks(L.n()), 256, 0, s>>>(L.S, u, b, L.r, L.nx, L.ny, stop);
+  const LineArrays<T> A(L);
+  T* bc = LineArrays<T>(Lc).b;
+  k_line_resid<T><<<grid_blocks(L.n()), 256, 0, s>>>(A.S, u, b, A.r, L.nx, L.ny, stop);
   DMG_CHECK(launch_check("line residual"));
-  k_line_restrict<<<grid_blocks(Lc.n()), 256, 0, s>>>(L.P, L.r, Lc.b, L.nx, L.ny, stop);
+  k_line_restrict<T><<<grid_blocks(Lc.n()), 256, 0, s>>>(A.P, A.r, bc, L.nx, L.ny, stop);
   return launch_check("line restriction");
 }
 
-dmg_status line_prolong(const Level& L, const double* e, double* u, const int* stop,
-                        hipStream_t s) {
-  k_line_prolong<<<grid_blocks(L.n()), 256, 0, s>>>(L.P, e, u, L.nx, L.ny, stop);
+template <class T>
+dmg_status line_prolong(const Level& L, const T* e, T* u, const int* stop, hipStream_t s) {
+  const LineArrays<T> A(L);
+  k_line_prolong<T><<<grid_blocks(L.n()), 256, 0, s>>>(A.P, e, u, L.nx, L.ny, stop);
   return launch_check("line interpolation");
 }
+
+dmg_status launch_line_multi(LineStep step, const LineArgs<double>* list, int count, int nx,
+                             int ny, int dir, int parity, hipStream_t s) {
+  if (count <= 0) return DMG_OK;
+  const size_t n = size_t(nx) * ny;
+  // grid-stride steps: enough workgroups per instance that the launch fills the GPU
+  const unsigned per = std::max(1u, std::min(grid_blocks(n), unsigned(4096 / count + 1)));
+  switch (step) {
+    case LineStep::kSweep: {
+      const int lines = dir == 0 ? (ny - 2 + 1) / 2 : (nx - 2 + 1) / 2;
+      const dim3 grid(unsigned((lines + 3) / 4), unsigned(count));
+      if (dir == 0) k_line_scan_multi<0, double><<<grid, 256, 0, s>>>(list, parity);
+      else k_line_scan_multi<1, double><<<grid, 256, 0, s>>>(list, parity);
+      return launch_check("batched line sweep");
+    }
+    case LineStep::kZero:
+      k_line_zero_multi<double><<<dim3(per, unsigned(count)), 256, 0, s>>>(list);
+      return launch_check("batched coarse start");
+    case LineStep::kResidual:
+      k_line_resid_multi<double><<<dim3(per, unsigned(count)), 256, 0, s>>>(list);
+      return launch_check("batched line residual");
+    case LineStep::kRestrict: {
+      const size_t nc = size_t((nx + 1) / 2) * ((ny + 1) / 2);
+      const unsigned pc = std::max(1u, std::min(grid_blocks(nc), unsigned(4096 / count + 1)));
+      k_line_restrict_multi<double><<<dim3(pc, unsigned(count)), 256, 0, s>>>(list);
+      return launch_check("batched line restriction");
+    }
+    case LineStep::kProlong:
+      k_line_prolong_multi<double><<<dim3(per, unsigned(count)), 256, 0, s>>>(list);
+      return launch_check("batched line interpolation");
+  }
+  return fail(DMG_ERR_INVALID_ARG, "unknown batched line step");
+}
+
+#define DMG_LINE_INST(T)                                                                       \
+  template dmg_status line_sweep<T>(const Level&, T*, const T*, int, bool, const int*,         \
+                                    hipStream_t);                                              \
+  template dmg_status line_factors<T>(const Level&, hipStream_t);                              \
+  template dmg_status line_resid_restrict<T>(const Level&, const Level&, const T*, const T*,   \
+                                             const int*, hipStream_t);                         \
+  template dmg_status line_prolong<T>(const Level&, const T*, T*, const int*, hipStream_t);
+DMG_LINE_INST(double)
+DMG_LINE_INST(float)
+#undef DMG_LINE_INST
 
 }  // namespace dmg

@@ -7,7 +7,8 @@ Bounds (entry by entry, tests/entrywise.py): one float32 cycle agrees with the o
 cycle to 1e-5 |ref| + FP32_FLOOR eps32 max|ref| (the two sum in different orders in float32,
 and the library applies the levels below 33 x 33 as their float64 dense operator rounded to
 float32); every refined iterate agrees with the oracle's to the same bound; the outer step
-counts are equal."""
+counts are equal.  The same holds with zebra line relaxation, whose float32 line solves (Thomas
+recurrences here, LU in the oracle) differ by rounding."""
 import numpy as np
 import pytest
 import torch
@@ -36,10 +37,15 @@ def host(t):
     return t.detach().cpu().numpy()
 
 
-def _setup(prob):
+LINE = {1: "xline", 2: "yline", 3: "alt"}
+
+
+def _setup(prob, smoother=0):
     S_or = fem.assemble_stencil(prob.jac, prob.K, prob.nx, prob.ny)
     levels = boxmg.build_hierarchy(S_or)
-    return S_or, levels, cycle.Oracle(levels), cycle.Oracle(levels, np.float32)
+    sm = LINE.get(smoother, "point")
+    return (S_or, levels, cycle.Oracle(levels, smoother=sm),
+            cycle.Oracle(levels, np.float32, smoother=sm))
 
 
 def _check_fp32(name, got, ref):
@@ -114,4 +120,36 @@ def test_fp32_refinement_is_scale_invariant(dmg):
     # the oracle's refinement on the scaled system takes the same steps
     _, ko, _, _ = cycle.solve_ir(o64, o32, prob.b * 1e-30, 1e-10)
     assert ko == k
+    h.close()
+
+
+@pytest.mark.parametrize("name,smoother", [("annulus65", 1), ("annulus65", 2), ("annulus65", 3),
+                                           ("annulus129x97", 1), ("annulus129x97", 3),
+                                           ("star97x65", 2), ("star97x65", 3)])
+def test_fp32_refinement_with_line_relaxation_matches_oracle(dmg, name, smoother):
+    """Float32 inner cycles with zebra line relaxation (x-lines, y-lines, alternating) inside
+    float64 refinement: every outer step's x against the oracle's refinement with the same
+    smoother in float32, the same step count, and the solution against the float64 line-smoothed
+    oracle solution."""
+    prob = {"annulus65": lambda: pb.quarter_annulus(65),
+            "annulus129x97": lambda: pb.quarter_annulus(129, ny=97),
+            "star97x65": lambda: pb.star(97, seed=1, ny=65)}[name]()
+    S_or, levels, o64, o32 = _setup(prob, smoother)
+    xo, ko, histo, its = cycle.solve_ir(o64, o32, prob.b, 1e-10, inner=1, keep_iterates=True)
+    h = dmg.Hierarchy(dev(S_or), precision=dmg.DMG_FP32_IR, smoother=smoother, inner_cycles=1)
+    b = dev(prob.b)
+    x, k, rel, hist = h.solve(b, rtol=1e-10, max_iters=300)
+    assert rel <= 1e-10 and k == ko, (k, ko)
+    assert np.allclose(hist, histo, rtol=1e-3)
+    worst = 0.0
+    for step in range(1, min(ko, 6) + 1):
+        xs, ks, _, _ = h.solve(b, rtol=1e-10, max_iters=step, raise_on_fail=False)
+        assert ks == step
+        worst = max(worst, _check_fp32(f"{name} smoother={smoother} outer step {step}", host(xs),
+                                       its[step - 1]))
+    u64, k64, _, _ = cycle.solve(o64, prob.b, 1e-10, max_iters=300)
+    err = float(np.linalg.norm(host(x) - u64) / np.linalg.norm(u64))
+    print(f"[fp32] {name} line smoother {smoother}: {k} steps (float64 line solve {k64} cycles), "
+          f"error vs float64 oracle solution {err:.2e}")
+    assert err < 1e-7
     h.close()

@@ -603,6 +603,38 @@ def test_batch_with_odd_dims_matches_single_solves(dmg):
     bt.close()
 
 
+@pytest.mark.parametrize("smoother", [1, 3])
+def test_batch_line_relaxation_matches_single_solves(dmg, smoother):
+    """Zebra line relaxation in the batch (x-lines, alternating): the line steps of one level size
+    run as one launch over every instance that has it.  Each instance's solution equals its
+    single line-smoothed solve (coarse_gemv = 0) bit for bit with the same cycle count, and the
+    oracle's line-smoothed solve entry by entry; autotuning changes nothing."""
+    probs = [pb.quarter_annulus(65), pb.quarter_annulus(129, ny=97), pb.star(65, seed=51),
+             pb.quarter_annulus(33, ny=49), pb.star(97, seed=52, ny=65), pb.quarter_annulus(65, seed=3)]
+    Ss = [dmg.assemble_stencil(dev(p.jac), dev(p.K)) for p in probs]
+    bs = [dev(p.b) for p in probs]
+    bt = dmg.BatchSolver(Ss, smoother=smoother)
+    us, its, rels = bt.solve(bs, rtol=1e-10, max_iters=300)
+    assert max(rels) <= 1e-10
+    for k, (S, b, u, it, r, p) in enumerate(zip(Ss, bs, us, its, rels, probs)):
+        h = dmg.Hierarchy(S, coarse_gemv=0, smoother=smoother)
+        u1, k1, r1, _ = h.solve(b, rtol=1e-10, max_iters=300)
+        h.close()
+        assert it == k1, (k, it, k1)
+        assert abs(r - r1) <= 1e-12 * r1, (k, r, r1)    # the norms' partial sums differ
+        assert torch.equal(u, u1), k
+        orc = cycle.Oracle(boxmg.build_hierarchy(fem.assemble_stencil(p.jac, p.K, p.nx, p.ny)),
+                           smoother=LINE[smoother])
+        uo, ko, _, _ = cycle.solve(orc, p.b, 1e-10, max_iters=300)
+        assert it == ko, (k, it, ko)
+        assert_iterate(f"instance {k} ({p.nx}x{p.ny}) line batch vs oracle", host(u), uo)
+    cfg = bt.autotune(bs, reps=1, tiles=True, colour_order=True)
+    assert cfg["pre_order"] == [0, 1, 2, 3]              # line relaxation visits no colours
+    us2, its2, _ = bt.solve(bs, rtol=1e-10, max_iters=300)
+    assert its2 == its and all(torch.equal(a, c) for a, c in zip(us, us2))
+    bt.close()
+
+
 def test_batch_zero_rhs_and_limits(dmg):
     probs = [pb.star(n, seed=20 + k) for k, n in enumerate((129, 65, 257))]
     Ss = [dmg.assemble_stencil(dev(p.jac), dev(p.K)) for p in probs]
@@ -721,7 +753,3 @@ def test_line_smoother_graph_and_limits(dmg):
     assert k_2 == k_e
     assert float((2.0 * x_2 - x_e).abs().max()) <= 1e-13 * float(x_e.abs().max())
     h.close()
-    with pytest.raises(dmg.DmgError):
-        dmg.Hierarchy(S, smoother=3, precision=dmg.DMG_FP32_IR)
-    with pytest.raises(dmg.DmgError):
-        dmg.BatchSolver([S], smoother=1)
