@@ -7,8 +7,8 @@
 //         box and the interior grid corners g, times its Jacobian factor, into y[3 t + a]; one
 //         thread per mesh row then adds the y entries of its incident triangles (ascending
 //         triangle order) and forms the squared-norm partials CG2 starts from.
-//   C^T y (to_grid's end): one thread per grid cell sums, over the triangles of its list, the
-//         four corner values J sum_a w[a][g] y[v_a] (Dirichlet vertices count as zero); one
+//   C^T y (to_grid's end): a group of lanes per grid cell sums, over the triangles of its list,
+//         the four corner values J sum_a w[a][g] y[v_a] (Dirichlet vertices count as zero); one
 //         thread per interior grid vertex adds the matching corners of its four cells.
 //
 // Every sum runs in a fixed order and nothing is scattered, so results do not depend on the
@@ -165,7 +165,11 @@ __global__ __launch_bounds__(256) void k_mf_rows(const int* __restrict__ vt_ptr,
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
-// z[4 c + g] = sum over the triangles t of cell c's list of J_t sum_a w[a][g] y[v_a]
+// z[4 c + g] = sum over the triangles t of cell c's list of J_t sum_a w[a][g] y[v_a].  A cell's
+// list (~20 triangles on a mesh finer than the grid) is split over kCellLanes consecutive lanes
+// (lane l takes entries l, l + kCellLanes, ...), whose sums are combined by xor shuffles in a
+// fixed order.
+constexpr int kCellLanes = 4;
 template <bool EXACT>
 __global__ __launch_bounds__(256) void k_mf_cells(const double* __restrict__ xy,
                                                   const int* __restrict__ tv,
@@ -180,10 +184,13 @@ __global__ __launch_bounds__(256) void k_mf_cells(const double* __restrict__ xy,
                                                   const int* __restrict__ stop) {
   if (mf_stopped(stop)) return;
   const int ncx = nx - 1, ncell = ncx * (ny - 1);
-  for (int c = int(blockIdx.x) * 256 + int(threadIdx.x); c < ncell; c += int(gridDim.x) * 256) {
+  const int lane = int(threadIdx.x) & (kCellLanes - 1);
+  const int c0 = int((blockIdx.x * 256u + threadIdx.x) / kCellLanes);
+  const int cstep = int(gridDim.x * 256u / kCellLanes);
+  for (int c = c0; c < ncell; c += cstep) {  // uniform over the lanes of a cell's group
     const int ci = c % ncx, cj = c / ncx;
     double zc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int k = ct_ptr[c]; k < ct_ptr[c + 1]; ++k) {
+    for (int k = ct_ptr[c] + lane; k < ct_ptr[c + 1]; k += kCellLanes) {
       const int t = ct[k];
       double tri[3][2];
       int v[3];
@@ -198,7 +205,13 @@ __global__ __launch_bounds__(256) void k_mf_cells(const double* __restrict__ xy,
         zc[g] = __builtin_fma(J, s, zc[g]);
       }
     }
-    for (int g = 0; g < 4; ++g) z[4 * size_t(c) + g] = zc[g];
+    for (int g = 0; g < 4; ++g) {
+#pragma unroll
+      for (int off = kCellLanes / 2; off > 0; off >>= 1)
+        zc[g] += __shfl_xor(zc[g], off, kCellLanes);
+    }
+    if (lane == 0)
+      for (int g = 0; g < 4; ++g) z[4 * size_t(c) + g] = zc[g];
   }
 }
 
@@ -373,7 +386,7 @@ dmg_status mf_launch_ct(dmg_transfer* t, const double* x, double* r_c, const int
   const double hx = 2.0 / (t->nx - 1), hy = 2.0 / (t->ny - 1);
   const size_t ncell = size_t(t->nx - 1) * (t->ny - 1);
   auto k = t->nq == 0 ? k_mf_cells<true> : k_mf_cells<false>;
-  k<<<mf_grid(ncell), 256, 0, s>>>(t->mf_xy, t->mf_tv, t->mf_jac, t->mf_ct_ptr, t->mf_ct, t->nx,
+  k<<<mf_grid(ncell * kCellLanes), 256, 0, s>>>(t->mf_xy, t->mf_tv, t->mf_jac, t->mf_ct_ptr, t->mf_ct, t->nx,
                                    t->ny, hx, hy, t->nq, t->mf_q, x, t->dof, t->mf_buf, stop);
   DMG_CHECK(launch_check("matrix-free C^T x (cells)"));
   k_mf_verts<<<mf_grid(size_t(t->nx) * t->ny), 256, 0, s>>>(t->mf_buf, t->nx, t->ny, r_c, stop);
