@@ -435,18 +435,29 @@ k_setup_small(SmallSetup a) {
   coarse_factor_body(a.S[l], a.nx[l], a.ny[l], a.m, a.idx, a.chol, a.flag);
 }
 
-// Level 0: the caller's planar stencil copied into the hierarchy, planar and point-major.
+// Level 0: the caller's planar stencil copied into the hierarchy, planar and point-major.  Each
+// workgroup takes 256 consecutive points: the five planes are read and copied coalesced, the
+// point-major block goes through LDS so that it is written as one contiguous run.
 __global__ __launch_bounds__(256) void k_copy_pack(const double* __restrict__ S,
                                                    double* __restrict__ Sd,
                                                    double* __restrict__ Sp, size_t n) {
-  for (size_t v = blockIdx.x * size_t(blockDim.x) + threadIdx.x; v < n;
-       v += size_t(gridDim.x) * blockDim.x) {
+  __shared__ double tile[5 * 256];
+  const int t = int(threadIdx.x);
+  for (size_t base = size_t(blockIdx.x) * 256; base < n; base += size_t(gridDim.x) * 256) {
+    const size_t v = base + t;
+    const int cnt = int(n - base < 256 ? n - base : 256);
+    double x[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) x[k] = v < n ? S[k * n + v] : 0.0;
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      const double x = S[k * n + v];
-      Sd[k * n + v] = x;
-      if (Sp) Sp[5 * v + k] = x;
+      if (v < n) Sd[k * n + v] = x[k];
+      tile[5 * t + k] = x[k];
     }
+    __syncthreads();
+    if (Sp)
+      for (int q = t; q < 5 * cnt; q += 256) Sp[5 * base + q] = tile[q];
+    __syncthreads();  // the tile is rewritten by the next chunk
   }
 }
 
@@ -475,14 +486,22 @@ __global__ __launch_bounds__(256) void k_f32_batch(F32Batch a) {
   if (k >= a.count) return;
   const F32Seg g = a.seg[k];
   const size_t step = size_t(g.blocks) * blockDim.x;
-  for (size_t v = size_t(b) * blockDim.x + threadIdx.x; v < g.n; v += step) {
-    if (g.pack) {
+  if (g.pack) {  // point-major: 256 points per chunk, staged in LDS, written as one run
+    __shared__ float tile[5 * 256];
+    const int t = int(threadIdx.x);
+    for (size_t base = size_t(b) * 256; base < g.n; base += step) {
+      const size_t v = base + t;
+      const int cnt = int(g.n - base < 256 ? g.n - base : 256);
 #pragma unroll
-      for (int c = 0; c < 5; ++c) g.dst[5 * v + c] = float(g.src[c * g.n + v]);
-    } else {
-      g.dst[v] = float(g.src[v]);
+      for (int c = 0; c < 5; ++c) tile[5 * t + c] = v < g.n ? float(g.src[c * g.n + v]) : 0.f;
+      __syncthreads();
+      for (int q = t; q < 5 * cnt; q += 256) g.dst[5 * base + q] = tile[q];
+      __syncthreads();
     }
+    return;
   }
+  for (size_t v = size_t(b) * blockDim.x + threadIdx.x; v < g.n; v += step)
+    g.dst[v] = float(g.src[v]);
 }
 
 dim3 grid2(int nx, int ny) { return dim3((nx + kBX - 1) / kBX, (ny + kBY - 1) / kBY); }
