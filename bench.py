@@ -66,8 +66,8 @@ def run_leg(dmg, jac, K, b, steps: int, warmup: int, precision: int, inner: int 
     u = torch.zeros_like(b)
 
     def step():
-        dmg.assemble_stencil(jac, K, out=S)
-        h.refresh(S)
+        # the fine stencil assembled straight into the hierarchy, then its coarse levels
+        h.refresh_assembled(jac, K)
         u.zero_()
         _, k, rel, _ = h.solve(b, u=u, rtol=1e-10)
         info["iters"], info["relres"] = k, rel

@@ -147,6 +147,15 @@ void dmg_destroy(dmg_hier* h);
  * on h.  From the second consecutive call with the same S pointer and stream (use_graph), the
  * setup is captured once into a hipGraph and replayed; it reads S's current contents. */
 dmg_status dmg_refresh(dmg_hier* h, const double* S, hipStream_t stream);
+/* dmg_assemble_stencil from (jac, K) followed by dmg_refresh, without the caller's stencil array:
+ * the fine stencil is assembled straight into the hierarchy's level 0 (its planar and
+ * point-major copies), then the coarse levels are recomputed.  The result equals that of
+ * dmg_assemble_stencil into S followed by dmg_refresh(h, S) bit for bit (jac, K as
+ * dmg_assemble_stencil takes them, for h's grid dims; they must stay valid until the work has
+ * run).  Asynchronous like dmg_refresh; the graph is captured from the second consecutive call
+ * with the same jac, K and stream. */
+dmg_status dmg_refresh_assembled(dmg_hier* h, const double* jac, const double* K,
+                                 hipStream_t stream);
 
 /* Inspection of level l (0 = finest): dims and device pointers to its float64 stencil
  * [5][ny][nx] and (l < levels-1) interpolation weights [8][ny_c][nx_c] where entry (I,J) of

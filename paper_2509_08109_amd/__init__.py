@@ -140,6 +140,13 @@ class Hierarchy:
         solve)."""
         _lib.check(lib().dmg_refresh(self._h, _dev(S, (5, self.ny, self.nx), "S"), _stream(self.device)))
 
+    def refresh_assembled(self, jac: torch.Tensor, K: torch.Tensor) -> None:
+        """assemble_stencil(jac, K) followed by refresh(), with the fine stencil assembled straight
+        into the hierarchy (no stencil array of the caller's); the same bits."""
+        pj = _dev(jac, (16, self.ny - 1, self.nx - 1), "jac")
+        pk = _dev(K, (self.ny - 1, self.nx - 1), "K")
+        _lib.check(lib().dmg_refresh_assembled(self._h, pj, pk, _stream(self.device)))
+
     @property
     def strip_levels(self) -> int:
         """Levels handled by the fused strip kernels (the rest run in the coarse-tail kernel)."""

@@ -44,6 +44,7 @@ SIGNATURES = {
     "dmg_setup": (_st, [_p, _i32, _i32, C.POINTER(Options), _p, C.c_size_t, _p, C.POINTER(_p)]),
     "dmg_destroy": (None, [_p]),
     "dmg_refresh": (_st, [_p, _p, _p]),
+    "dmg_refresh_assembled": (_st, [_p, _p, _p, _p]),
     "dmg_sweep": (_st, [_p, _i32, _i32, _p, _p, _p]),
     "dmg_hier_level": (_st, [_p, _i32, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_p), C.POINTER(_p)]),
     "dmg_stats": (_st, [_p, C.POINTER(_i32), C.POINTER(C.c_double), C.POINTER(C.c_double)]),

@@ -828,8 +828,10 @@ dmg_status tune_tail(dmg_hier* h, T* u_top, const T* b_top, int reps, hipStream_
 
 // first: the hierarchy's initial setup, which zeroes the tail image, waits for the setup and
 // reports a non-positive coarsest pivot; otherwise a refresh, only enqueued (the next solve
-// reports the pivot).
-dmg_status setup_impl(dmg_hier* h, const double* S, hipStream_t s, bool first) {
+// reports the pivot).  jac and K (with S null): the fine stencil is assembled from them straight
+// into level 0, planar and point-major, in place of the copy of a caller's S.
+dmg_status setup_impl(dmg_hier* h, const double* S, hipStream_t s, bool first,
+                      const double* jac = nullptr, const double* K = nullptr) {
   const int nl = int(h->L.size());
   // levels from first_small down run their whole setup in one single-workgroup kernel
   int first_small = nl - 1;
@@ -840,7 +842,10 @@ dmg_status setup_impl(dmg_hier* h, const double* S, hipStream_t s, bool first) {
   // on (nothing writes them; a refresh rewrites only the S, P and dense-operator slots)
   if (first && h->tail_img) DMG_CHECK(launch_fill<double>(h->tail_img, 0.0, size_t(h->tail_img_n), s));
   if (first && h->tail_img32) DMG_CHECK(launch_fill<float>(h->tail_img32, 0.f, size_t(h->tail_img_n), s));
-  DMG_CHECK(launch_copy_pack(S, h->L[0].S, h->L[0].Sp, h->L[0].n(), s));
+  if (jac)
+    DMG_CHECK(launch_assemble(jac, K, h->L[0].nx, h->L[0].ny, h->L[0].S, s, h->L[0].Sp));
+  else
+    DMG_CHECK(launch_copy_pack(S, h->L[0].S, h->L[0].Sp, h->L[0].n(), s));
   for (int l = 0; l < first_small; ++l) {
     const Level& L = h->L[l];
     DMG_CHECK(launch_interp_weights(L.S, L.nx, L.ny, L.P, s));
@@ -902,6 +907,7 @@ dmg_status set_colour_orders(dmg_hier* h, const int32_t* pre, const int32_t* pos
   reset_solve_graphs(h);
   graph_reset(h->setup_graph);
   h->last_refresh_S = nullptr;
+  h->last_refresh_K = nullptr;
   DMG_CHECK(compute_basis(h, s));
   return compute_gemv_basis(h, s);
 }
@@ -1047,25 +1053,33 @@ dmg_status dmg_setup(const double* S, int32_t nx, int32_t ny, const dmg_options*
 
 void dmg_destroy(dmg_hier* h) { delete h; }
 
-dmg_status dmg_refresh(dmg_hier* h, const double* S, hipStream_t stream) {
-  clear_error();
-  if (!h || !S) return fail(DMG_ERR_INVALID_ARG, "null pointer argument");
+}  // extern "C"
+
+namespace {
+
+// A refresh from the stencil S, or (S null) from the coefficients (jac, K).  From the second
+// consecutive refresh from the same arrays on the same stream, the setup is captured once and
+// replayed (its ~25 small launches are otherwise paced by the host).
+dmg_status refresh_impl(dmg_hier* h, const double* S, const double* jac, const double* K,
+                        hipStream_t stream) {
+  const void* key = S ? static_cast<const void*>(S) : static_cast<const void*>(jac);
+  const void* key2 = S ? nullptr : static_cast<const void*>(K);
   // the legacy default stream cannot be captured
-  if (!h->opts.use_graph || stream == nullptr) return setup_impl(h, S, stream, false);
+  if (!h->opts.use_graph || stream == nullptr) return setup_impl(h, S, stream, false, jac, K);
   Graph& g = h->setup_graph;
-  if (g.exec && g.key_u == S && g.stream == stream) {
+  if (g.exec && g.key_u == key && g.key_b == key2 && g.stream == stream) {
     DMG_HIP(hipGraphLaunch(g.exec, stream));
     return DMG_OK;
   }
-  const bool again = h->last_refresh_S == S && h->last_refresh_stream == stream;
-  h->last_refresh_S = S;
+  const bool again = h->last_refresh_S == key && h->last_refresh_K == key2 &&
+                     h->last_refresh_stream == stream;
+  h->last_refresh_S = key;
+  h->last_refresh_K = key2;
   h->last_refresh_stream = stream;
   graph_reset(g);
-  if (!again) return setup_impl(h, S, stream, false);
-  // a second refresh from the same array: capture the setup (its ~25 small launches are
-  // otherwise paced by the host) and replay it from now on
+  if (!again) return setup_impl(h, S, stream, false, jac, K);
   DMG_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
-  const dmg_status st = setup_impl(h, S, stream, false);
+  const dmg_status st = setup_impl(h, S, stream, false, jac, K);
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamEndCapture(stream, &graph);
   if (st != DMG_OK) {
@@ -1079,10 +1093,28 @@ dmg_status dmg_refresh(dmg_hier* h, const double* S, hipStream_t stream) {
     graph_reset(g);
     return fail(DMG_ERR_HIP, "setup graph instantiate failed: %s", hipGetErrorString(e));
   }
-  g.key_u = S;
+  g.key_u = key;
+  g.key_b = key2;
   g.stream = stream;
   DMG_HIP(hipGraphLaunch(g.exec, stream));
   return DMG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dmg_status dmg_refresh(dmg_hier* h, const double* S, hipStream_t stream) {
+  clear_error();
+  if (!h || !S) return fail(DMG_ERR_INVALID_ARG, "null pointer argument");
+  return refresh_impl(h, S, nullptr, nullptr, stream);
+}
+
+dmg_status dmg_refresh_assembled(dmg_hier* h, const double* jac, const double* K,
+                                 hipStream_t stream) {
+  clear_error();
+  if (!h || !jac || !K) return fail(DMG_ERR_INVALID_ARG, "null pointer argument");
+  return refresh_impl(h, nullptr, jac, K, stream);
 }
 
 dmg_status dmg_sweep(dmg_hier* h, int32_t level, int32_t kind, double* u, const double* b,
@@ -1189,6 +1221,7 @@ dmg_status dmg_autotune(dmg_hier* h, double* u, const double* b, int32_t flags, 
   reset_solve_graphs(h);
   graph_reset(h->setup_graph);  // its dense-operator runs carry the colour orders
   h->last_refresh_S = nullptr;
+  h->last_refresh_K = nullptr;
   if (flags & 1) {
     DMG_CHECK(tune_levels<double>(h, reps, stream));
     Level& T0 = h->L[h->tail];

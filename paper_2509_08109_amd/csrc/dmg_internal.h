@@ -154,6 +154,7 @@ struct dmg_hier {
   // one-off setup)
   dmg::Graph setup_graph;
   const void* last_refresh_S = nullptr;
+  const void* last_refresh_K = nullptr;  // refreshes from coefficients: (jac, K)
   hipStream_t last_refresh_stream = nullptr;
   ~dmg_hier();
 };
@@ -161,8 +162,9 @@ struct dmg_hier {
 namespace dmg {
 
 // ---- kernels (launchers return DMG_OK or DMG_ERR_HIP) --------------------------------------
+// S planar [5][ny][nx]; Sp (nullable) the same point-major [ny][nx][5]
 dmg_status launch_assemble(const double* jac, const double* K, int nx, int ny, double* S,
-                           hipStream_t s);
+                           hipStream_t s, double* Sp = nullptr);
 dmg_status launch_interp_weights(const double* S, int nx, int ny, double* P, hipStream_t s);
 // SHp (nullable): also write the coarse stencil point-major [nyc][nxc][5]
 dmg_status launch_rap(const double* S, const double* P, int nx, int ny, double* SH,

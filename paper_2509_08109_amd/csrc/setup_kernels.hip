@@ -72,9 +72,11 @@ __device__ __forceinline__ void element_rows(const double* __restrict__ jac, siz
 // cell for its NE vertex, row 2 for the NW, row 1 for the SE, row 0 for the SW); each vertex
 // then sums the rows of its four cells in the order SW cell, SE cell, NW cell, NE cell.
 constexpr int kTileCX = kBX + 1, kTileCY = kBY + 1, kTileCells = kTileCX * kTileCY;
+// Sp (nullable): the same stencil point-major as well, each tile row staged in LDS and stored as
+// one contiguous run (the hierarchy's level 0, assembled in place).
 __global__ __launch_bounds__(256) void k_assemble(const double* __restrict__ jac,
                                                   const double* __restrict__ K, int nx, int ny,
-                                                  double* __restrict__ S) {
+                                                  double* __restrict__ S, double* __restrict__ Sp) {
   // g[e][c]: e = 0..3 row 3 (C, W, S, SW), 4..6 row 2 (C, S, SE), 7..8 row 1 (C, W), 9 row 0 (C)
   __shared__ double g[10][kTileCells];
   const int i0 = blockIdx.x * kBX, j0 = blockIdx.y * kBY;
@@ -102,11 +104,11 @@ __global__ __launch_bounds__(256) void k_assemble(const double* __restrict__ jac
   }
   __syncthreads();
   const int i = i0 + threadIdx.x, j = j0 + threadIdx.y;
-  if (i >= nx || j >= ny) return;
+  const bool in = i < nx && j < ny;
   const size_t N = size_t(nx) * ny;
   const size_t v = size_t(j) * nx + i;
   double C = 0, W = 0, So = 0, SW = 0, SE = 0;
-  if (i > 0 && i < nx - 1 && j > 0 && j < ny - 1) {
+  if (in && i > 0 && i < nx - 1 && j > 0 && j < ny - 1) {
     const int qsw = threadIdx.y * kTileCX + threadIdx.x;  // cell (i-1, j-1): v is its NE node
     const int qse = qsw + 1;                              // cell (i, j-1): v is its NW node
     const int qnw = qsw + kTileCX;                        // cell (i-1, j): v is its SE node
@@ -122,11 +124,24 @@ __global__ __launch_bounds__(256) void k_assemble(const double* __restrict__ jac
     if (i - 1 > 0) W += g[8][qnw];
     C += g[9][qne];
   }
-  S[0 * N + v] = C;
-  S[1 * N + v] = W;
-  S[2 * N + v] = So;
-  S[3 * N + v] = SW;
-  S[4 * N + v] = SE;
+  if (in) {
+    S[0 * N + v] = C;
+    S[1 * N + v] = W;
+    S[2 * N + v] = So;
+    S[3 * N + v] = SW;
+    S[4 * N + v] = SE;
+  }
+  if (!Sp) return;  // uniform over the workgroup
+  __shared__ double sp[kBY][5 * kBX];
+  const double vals[5] = {C, W, So, SW, SE};
+#pragma unroll
+  for (int k = 0; k < 5; ++k) sp[threadIdx.y][5 * threadIdx.x + k] = vals[k];
+  __syncthreads();
+  const int cnt = 5 * (nx - i0 < kBX ? nx - i0 : kBX);  // values of one tile row
+  for (int q = tid; q < kBY * 5 * kBX; q += kBX * kBY) {
+    const int r = q / (5 * kBX), k = q % (5 * kBX);
+    if (k < cnt && j0 + r < ny) Sp[5 * (size_t(j0 + r) * nx + i0) + k] = sp[r][k];
+  }
 }
 
 __global__ __launch_bounds__(256) void k_grad_K(const double* __restrict__ jac,
@@ -530,8 +545,8 @@ dmg_status launch_f32_batch(const F32Batch& a, hipStream_t s) {
 }
 
 dmg_status launch_assemble(const double* jac, const double* K, int nx, int ny, double* S,
-                           hipStream_t s) {
-  k_assemble<<<grid2(nx, ny), dim3(kBX, kBY), 0, s>>>(jac, K, nx, ny, S);
+                           hipStream_t s, double* Sp) {
+  k_assemble<<<grid2(nx, ny), dim3(kBX, kBY), 0, s>>>(jac, K, nx, ny, S, Sp);
   return launch_check("assemble");
 }
 

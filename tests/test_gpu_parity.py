@@ -529,6 +529,41 @@ def test_matrix_free_transfer_matches_oracle(dmg, nq, nx, ny, m):
     Ta.close()
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_refresh_assembled_equals_assemble_then_refresh(dmg, precision):
+    """dmg_refresh_assembled (the fine stencil assembled straight into the hierarchy, planar and
+    point-major) against dmg_assemble_stencil + dmg_refresh: every level's stencil and weights bit
+    for bit, and the same solve bit for bit; called three times so that the captured setup graph
+    is replayed (on a side stream), with new coefficients in between."""
+    p1, p2 = pb.star(257, seed=61, ny=193), pb.star(257, seed=62, ny=193)
+    jac, K = dev(p1.jac), dev(p1.K)
+    b = dev(p1.b)
+    S = dmg.assemble_stencil(jac, K)
+    ha = dmg.Hierarchy(S, precision=precision)
+    hb = dmg.Hierarchy(S, precision=precision)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        for rep in range(3):
+            if rep == 2:                                  # new coefficients in the same arrays
+                jac.copy_(dev(p2.jac))
+                K.copy_(dev(p2.K))
+            dmg.assemble_stencil(jac, K, out=S)
+            ha.refresh(S)
+            hb.refresh_assembled(jac, K)
+            for l in range(ha.num_levels):
+                Sa, Pa = ha.level(l)
+                Sb, Pb = hb.level(l)
+                assert torch.equal(Sa, Sb), (rep, l)
+                assert (Pa is None) == (Pb is None) and (Pa is None or torch.equal(Pa, Pb)), (rep, l)
+            xa, ka, _, _ = ha.solve(b, rtol=1e-10)
+            xb, kb, _, _ = hb.solve(b, rtol=1e-10)
+            assert ka == kb and torch.equal(xa, xb), rep
+    torch.cuda.synchronize()
+    ha.close()
+    hb.close()
+
+
 def _batch_vs_single(dmg, Ss, bs, bt, us, its, rels, probs=None, orders=None):
     """The batch runs its coarse levels in the one-workgroup coarse kernel: its iterates equal
     single solves with coarse_gemv=0 (and the same colour orders) bitwise, and single solves
