@@ -502,10 +502,11 @@ def _interior(x: torch.Tensor) -> torch.Tensor:
 
 class _DiffSolver:
     """The hierarchy and buffers that DiffSolve reuses for one (device, grid, options): each
-    solve assembles the stencil into the same array and refreshes the hierarchy from it (so the
-    hierarchy is recomputed, never kept from an earlier call; from the second refresh on, the
-    setup runs as a replayed graph), then solves in the same two buffers, whose captured solve
-    graphs are replayed instead of captured anew."""
+    solve copies K into the same array and refreshes the hierarchy from (jac, K), the stencil
+    assembled straight into it (so the hierarchy is recomputed, never kept from an earlier call;
+    from the second refresh with the same jac on, the setup runs as a replayed graph), then
+    solves in the same two buffers, whose captured solve graphs are replayed instead of captured
+    anew."""
 
     _cache: dict = {}
 
@@ -520,13 +521,13 @@ class _DiffSolver:
         ent = cls._cache.get(key)
         if ent is None:
             ent = cls._cache[key] = cls()
-            ent.S = assemble_stencil(jac, K)
-            ent.h = Hierarchy(ent.S, o)
+            ent.h = Hierarchy(assemble_stencil(jac, K), o)
+            ent.K = K.detach().to(torch.float64).contiguous().clone()
             ent.u = torch.empty(shp, dtype=torch.float64, device=K.device)
             ent.b = torch.empty(shp, dtype=torch.float64, device=K.device)
         else:
-            assemble_stencil(jac, K, out=ent.S)
-            ent.h.refresh(ent.S)
+            ent.K.copy_(K)
+            ent.h.refresh_assembled(jac, ent.K)
         ent.b.copy_(rhs)
         ent.u.zero_()
         _, its, rr, _ = ent.h.solve(ent.b, u=ent.u, rtol=rtol, max_iters=max_iters,
