@@ -557,6 +557,8 @@ dmg_status dmg_batch_setup(int32_t count, const int32_t* nx, const int32_t* ny,
   o.coarse_gemv = 0;  // the batch runs its coarse levels in the one-workgroup coarse kernel
   if (o.precision != DMG_FP64)
     return fail(DMG_ERR_UNSUPPORTED, "batched solves run in float64 (precision DMG_FP64)");
+  if (o.smoother != 0 && count > 65535)  // the line steps index instances by blockIdx.y
+    return fail(DMG_ERR_UNSUPPORTED, "batched line relaxation takes at most 65535 instances");
   size_t need = 0;
   DMG_CHECK(dmg_batch_workspace_bytes(count, nx, ny, &o, &need));
   if (!workspace || ws_bytes < need)

@@ -248,6 +248,8 @@ dmg_status mf_build(const Mesh& m, int nx, int ny, int nq, const std::vector<int
   const int nv = m.nv, nt = m.nt;
   const size_t ncell = size_t(nx - 1) * (ny - 1);
   if (ncell >= (size_t(1) << 31)) return fail(DMG_ERR_DIMS, "grid too large for the cell lists");
+  if (nt > (INT32_MAX - 3) / 3)  // the incidence entries 3 t + slot are int32
+    return fail(DMG_ERR_INVALID_ARG, "too many triangles for the matrix-free form (%d)", nt);
   const double hx = 2.0 / (nx - 1), hy = 2.0 / (ny - 1);
   std::vector<int> newidx(nv);
   for (int i = 0; i < nv; ++i) newidx[perm[i]] = i;
