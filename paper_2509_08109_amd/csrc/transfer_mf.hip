@@ -116,7 +116,8 @@ __global__ __launch_bounds__(256) void k_mf_tri(const double* __restrict__ xy,
                                                 double* __restrict__ y,
                                                 const int* __restrict__ stop) {
   if (mf_stopped(stop)) return;
-  for (int t = int(blockIdx.x) * 256 + int(threadIdx.x); t < nt; t += int(gridDim.x) * 256) {
+  for (int64_t tt = int64_t(blockIdx.x) * 256 + threadIdx.x; tt < nt; tt += int64_t(gridDim.x) * 256) {
+    const int t = int(tt);
     const double J = jac[t];
     double acc[3] = {0.0, 0.0, 0.0};
     if (J != 0.0) {
@@ -154,7 +155,8 @@ __global__ __launch_bounds__(256) void k_mf_rows(const int* __restrict__ vt_ptr,
                                                  const int* __restrict__ stop) {
   if (mf_stopped(stop)) return;
   double acc = 0.0;
-  for (int r = int(blockIdx.x) * 256 + int(threadIdx.x); r < n; r += int(gridDim.x) * 256) {
+  for (int64_t rr = int64_t(blockIdx.x) * 256 + threadIdx.x; rr < n; rr += int64_t(gridDim.x) * 256) {
+    const int r = int(rr);
     double s = 0.0;
     for (int k = vt_ptr[r]; k < vt_ptr[r + 1]; ++k) s += y[vt[k]];
     const double val = dof[r] ? s : 0.0;
@@ -183,12 +185,13 @@ __global__ __launch_bounds__(256) void k_mf_cells(const double* __restrict__ xy,
                                                   double* __restrict__ z,
                                                   const int* __restrict__ stop) {
   if (mf_stopped(stop)) return;
-  const int ncx = nx - 1, ncell = ncx * (ny - 1);
+  const int ncx = nx - 1;
+  const int64_t ncell = int64_t(ncx) * (ny - 1);
   const int lane = int(threadIdx.x) & (kCellLanes - 1);
-  const int c0 = int((blockIdx.x * 256u + threadIdx.x) / kCellLanes);
-  const int cstep = int(gridDim.x * 256u / kCellLanes);
-  for (int c = c0; c < ncell; c += cstep) {  // uniform over the lanes of a cell's group
-    const int ci = c % ncx, cj = c / ncx;
+  const int64_t c0 = (blockIdx.x * 256u + threadIdx.x) / kCellLanes;
+  const int64_t cstep = gridDim.x * 256u / kCellLanes;
+  for (int64_t c = c0; c < ncell; c += cstep) {  // uniform over the lanes of a cell's group
+    const int ci = int(c % ncx), cj = int(c / ncx);
     double zc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int k = ct_ptr[c] + lane; k < ct_ptr[c + 1]; k += kCellLanes) {
       const int t = ct[k];
@@ -221,9 +224,10 @@ __global__ __launch_bounds__(256) void k_mf_verts(const double* __restrict__ z, 
                                                   double* __restrict__ out,
                                                   const int* __restrict__ stop) {
   if (mf_stopped(stop)) return;
-  const int ng = nx * ny, ncx = nx - 1;
-  for (int p = int(blockIdx.x) * 256 + int(threadIdx.x); p < ng; p += int(gridDim.x) * 256) {
-    const int i = p % nx, j = p / nx;
+  const int64_t ng = int64_t(nx) * ny;
+  const int ncx = nx - 1;
+  for (int64_t p = int64_t(blockIdx.x) * 256 + threadIdx.x; p < ng; p += int64_t(gridDim.x) * 256) {
+    const int i = int(p % nx), j = int(p / nx);
     double s = 0.0;
     if (i > 0 && i < nx - 1 && j > 0 && j < ny - 1) {
       const size_t c00 = size_t(j - 1) * ncx + (i - 1), c01 = c00 + ncx;
