@@ -5,8 +5,9 @@
 //
 //   C x   (from_grid's start): one thread per triangle sums w[a][g] x[g] over the cells of its
 //         box and the interior grid corners g, times its Jacobian factor, into y[3 t + a]; one
-//         thread per mesh row then adds the y entries of its incident triangles (ascending
-//         triangle order) and forms the squared-norm partials CG2 starts from.
+//         group of lanes per mesh row then adds the y entries of its incident triangles (ascending
+//         triangle order, lane l taking entries l, l + 4, ...) and forms the squared-norm partials CG2
+//         starts from.
 //   C^T y (to_grid's end): a group of lanes per grid cell sums, over the triangles of its list,
 //         the four corner values J sum_a w[a][g] y[v_a] (Dirichlet vertices count as zero); one
 //         thread per interior grid vertex adds the matching corners of its four cells.
@@ -145,7 +146,8 @@ __global__ __launch_bounds__(256) void k_mf_tri(const double* __restrict__ xy,
   }
 }
 
-// r0[r] = dof[r] * (sum of y over r's incidence list); partials of r0.r0 (one per workgroup)
+// r0[r] = dof[r] * (sum of y over r's incidence list); partials of r0.r0 (one per workgroup,
+// tblocks(n, kMG) workgroups as the CG2 tail expects)
 __global__ __launch_bounds__(256) void k_mf_rows(const int* __restrict__ vt_ptr,
                                                  const int* __restrict__ vt,
                                                  const double* __restrict__ y,
@@ -154,14 +156,21 @@ __global__ __launch_bounds__(256) void k_mf_rows(const int* __restrict__ vt_ptr,
                                                  double* __restrict__ partials,
                                                  const int* __restrict__ stop) {
   if (mf_stopped(stop)) return;
+  // kMG lanes per row: lane l adds entries l, l + kMG, ...; the group sums by xor shuffles
+  const int lane = int(threadIdx.x) & (kMG - 1);
+  const int64_t g0 = (blockIdx.x * 256u + threadIdx.x) / kMG, gstep = gridDim.x * 256u / kMG;
   double acc = 0.0;
-  for (int64_t rr = int64_t(blockIdx.x) * 256 + threadIdx.x; rr < n; rr += int64_t(gridDim.x) * 256) {
+  for (int64_t rr = g0; rr < n; rr += gstep) {  // uniform over a row's lanes
     const int r = int(rr);
     double s = 0.0;
-    for (int k = vt_ptr[r]; k < vt_ptr[r + 1]; ++k) s += y[vt[k]];
-    const double val = dof[r] ? s : 0.0;
-    r0[r] = val;
-    acc += val * val;
+    for (int k = vt_ptr[r] + lane; k < vt_ptr[r + 1]; k += kMG) s += y[vt[k]];
+#pragma unroll
+    for (int off = kMG / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kMG);
+    if (lane == 0) {
+      const double val = dof[r] ? s : 0.0;
+      r0[r] = val;
+      acc += val * val;
+    }
   }
   const double t = mesh_block_sum(acc);
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
