@@ -134,6 +134,21 @@ def test_transfer_validation_on_host(dmg):
     assert lib.dmg_transfer_create_mesh(3, 1, xy.ctypes.data, xy.ctypes.data, tris.ctypes.data, dof.ctypes.data,
                                    9, 9, -1, 0, None, C.byref(h)) == 1
     assert "nq" in lib.dmg_last_error().decode()
+    # the matrix-free flag goes through the same checks before any device work
+    assert lib.dmg_transfer_create_mesh(3, 1, xy.ctypes.data, xy.ctypes.data, tris.ctypes.data, dof.ctypes.data,
+                                   9, 9, 4, dmg.DMG_MESH_MATRIX_FREE, None, C.byref(h)) == 1
+    assert "out of range" in lib.dmg_last_error().decode()
+    nb, pairs = C.c_size_t(), C.c_int64()
+    assert lib.dmg_transfer_memory(None, C.byref(nb), C.byref(pairs)) == 1
+
+
+def test_refresh_assembled_validation_on_host(dmg):
+    lib = dmg.lib()
+    fake = C.c_void_p(0x1000)
+    assert lib.dmg_refresh_assembled(None, fake, fake, None) == 1
+    assert lib.dmg_refresh_assembled(fake, None, fake, None) == 1
+    assert lib.dmg_refresh_assembled(fake, fake, None, None) == 1
+    assert "null" in lib.dmg_last_error().decode()
 
 
 def test_transfer_csr_validation_on_host(dmg):
