@@ -529,13 +529,15 @@ def test_matrix_free_transfer_matches_oracle(dmg, nq, nx, ny, m):
     Ta.close()
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_refresh_assembled_equals_assemble_then_refresh(dmg, precision):
+@pytest.mark.parametrize("precision,n,ny", [(0, 257, 193), (1, 257, 193), (0, 33, 33), (1, 45, 67),
+                                            (0, 65, 17)])
+def test_refresh_assembled_equals_assemble_then_refresh(dmg, precision, n, ny):
     """dmg_refresh_assembled (the fine stencil assembled straight into the hierarchy, planar and
     point-major) against dmg_assemble_stencil + dmg_refresh: every level's stencil and weights bit
     for bit, and the same solve bit for bit; called three times so that the captured setup graph
-    is replayed (on a side stream), with new coefficients in between."""
-    p1, p2 = pb.star(257, seed=61, ny=193), pb.star(257, seed=62, ny=193)
+    is replayed (on a side stream), with new coefficients in between.  Small grids run whole in
+    the coarse kernel; widths below and not a multiple of the 64-column assembly tile."""
+    p1, p2 = pb.star(n, seed=61, ny=ny), pb.star(n, seed=62, ny=ny)
     jac, K = dev(p1.jac), dev(p1.K)
     b = dev(p1.b)
     S = dmg.assemble_stencil(jac, K)
