@@ -5,6 +5,8 @@ through properties that hold at any size.
   on the triangles incident to its vertex, so the oracle computes sampled rows exactly from those
   triangles alone and they are compared entry by entry (same columns; values to the rounding
   bound eps / h^2 of the barycentric evaluations).
+* The matrix-free coupled mass at the transfer leg's size (1025^2 grid, 3.76M-vertex mesh): whole
+  from_grid and to_grid vectors against the stored form, entry by entry.
 * The two-level solve at a 513^2 grid (0.94M vertices, the bench's largest two-level size):
   the residual of the returned solution, recomputed on the host with A_p assembled here by
   vectorised NumPy (independently of the library), meets the tolerance.
@@ -80,6 +82,30 @@ def _p1_stiffness_vectorised(xy, tris, dof, K_t):
     A = spx.coo_matrix((G.ravel(), (rows, cols)), shape=(xy.shape[0],) * 2).tocsr()
     d = spx.diags(dof.astype(np.float64))
     return (d @ A @ d + spx.diags((~dof).astype(np.float64))).tocsr()
+
+
+def test_matrix_free_transfer_at_1025(lib):
+    """The bench's transfer workload (1025^2 grid, the 3.76M-vertex lattice mesh, rasterised C with
+    nq = 4): the matrix-free form against the stored form, whole vectors entry by entry.  The two
+    evaluate the same triangle-cell integrals (the same points counted) and sum them in different
+    orders, so they agree to rounding; the stored form is itself checked against the oracle on
+    sampled rows (above) and whole at small sizes."""
+    from entrywise import assert_iterate
+    n = 1025
+    mp = pb.Star.random(pb.streams(1)[0])
+    mesh = pb.lattice_mesh(mp, pb.mesh_points_for_grid(n), np.random.default_rng(1))
+    T = lib.Transfer(mesh.xy_c, mesh.xy_p, mesh.tris, mesh.dof, n, n, nq=4)
+    Tf = lib.Transfer(mesh.xy_c, mesh.xy_p, mesh.tris, mesh.dof, n, n, nq=4, matrix_free=True)
+    rng = np.random.default_rng(21)
+    uc = dev(rng.normal(size=(n, n)))
+    rp = dev(rng.normal(size=mesh.nv))
+    for name, a, b in (("from_grid", T.from_grid(uc), Tf.from_grid(uc)),
+                       ("to_grid", T.to_grid(rp), Tf.to_grid(rp))):
+        torch.cuda.synchronize()
+        used = assert_iterate(f"{name} at {n}^2, matrix-free vs stored", b.cpu().numpy(), a.cpu().numpy())
+        print(f"[fullsize-mesh] {name}: worst excess {used:.1f} eps max|ref|")
+    T.close()
+    Tf.close()
 
 
 def test_twolevel_residual_at_513(lib):
