@@ -214,7 +214,8 @@ def run_batch_leg(dmg, dev, steps: int, count: int = 256):
     return {"value": round(dof * steps / wall, 1), "unit": "DoF/s", "instances": count,
             "dof": dof, "sizes": {str(n): sizes.count(n) for n in sorted(set(sizes))},
             "cycles_min": min(its), "cycles_max": max(its), "max_relres": max(rels),
-            "tuned_colour_order": [tuned["pre_order"], tuned["post_order"]],
+            "tuned_colour_orders": {str(n): list(map(list, o)) for n, o in
+                                    sorted({n: o for n, o in zip(sizes, tuned["orders"])}.items())},
             "ms_per_batch_solve": round(1e3 * wall / steps, 2), "steps": steps,
             "generate_and_assemble_s": round(t_gen, 2), "setup_s": round(t_setup, 2)}
 

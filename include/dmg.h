@@ -336,15 +336,19 @@ dmg_status dmg_batch_solve(dmg_batch* bt, double* const* u, const double* const*
  * flags bit 0: the wave-strip segment height of each level size and the coarse-tail workgroup
  * size, by timing `reps` batched steps each -- numerically neutral.
  * flags bit 1 (point smoothing only; ignored with line relaxation, which visits no colours):
- * the colour-order pair (the same four row-separable pairs as dmg_autotune, post
- * order the reverse of the pre order), by timing whole batched solves to 1e-10 from zero; one
- * pair serves every instance, and each instance's dense coarse operators are rebuilt for it.
- * This changes the iterates: read the choice back with dmg_batch_config.  Bit 1 runs first. */
+ * the colour-order pair (the same four row-separable pairs as dmg_autotune, post order the
+ * reverse of the pre order) of each size class (the instances with one finest grid size), class
+ * by class, by timing whole batched solves to 1e-10 from zero; each instance's dense coarse
+ * operators are rebuilt for its pair.  This changes the iterates: read the choices back with
+ * dmg_batch_instance_orders.  Bit 1 runs first. */
 dmg_status dmg_batch_autotune(dmg_batch* bt, double* const* u, const double* const* b,
                               int32_t flags, int32_t reps, hipStream_t stream);
-/* The colour orders (host arrays of 4, nullable) and coarse-tail workgroup size in use. */
+/* Instance 0's colour orders (host arrays of 4, nullable) and the coarse-tail workgroup size. */
 dmg_status dmg_batch_config(const dmg_batch* bt, int32_t* pre_order, int32_t* post_order,
                             int32_t* tail_threads);
+/* Instance k's colour orders (host arrays of 4, nullable). */
+dmg_status dmg_batch_instance_orders(const dmg_batch* bt, int32_t k, int32_t* pre_order,
+                                     int32_t* post_order);
 void dmg_batch_destroy(dmg_batch* bt);
 
 /* ---- the two-level cycle on the physical mesh (Sec. 2.2, solution phase) -----------------

@@ -453,8 +453,8 @@ class BatchSolver:
 
     def autotune(self, bs, reps: int = 3, tiles: bool = True, colour_order: bool = False):
         """Pick per-size launch shapes and the tail workgroup size by timing batched steps (tiles),
-        and/or the colour-order pair by timing whole batched solves (colour_order, which changes
-        the iterates); returns config()."""
+        and/or the colour-order pair of each size class by timing whole batched solves
+        (colour_order, which changes the iterates); returns config()."""
         us = [torch.zeros((ny, nx), dtype=torch.float64, device=self.device) for nx, ny in self.dims]
         flags = (1 if tiles else 0) | (2 if colour_order else 0)
         _lib.check(lib().dmg_batch_autotune(self._h, self._ptrs(us, "u"), self._ptrs(bs, "b"), flags,
@@ -462,10 +462,17 @@ class BatchSolver:
         return self.config()
 
     def config(self):
-        """{'pre_order': [...], 'post_order': [...], 'tail_threads': n}"""
+        """{'pre_order': [...], 'post_order': [...] (instance 0's), 'tail_threads': n,
+        'orders': [(pre, post) of each instance]}"""
         pre, post, tt = (C.c_int32 * 4)(), (C.c_int32 * 4)(), C.c_int32()
         _lib.check(lib().dmg_batch_config(self._h, pre, post, C.byref(tt)))
-        return {"pre_order": list(pre), "post_order": list(post), "tail_threads": int(tt.value)}
+        orders = []
+        for k in range(self.count):
+            p, q = (C.c_int32 * 4)(), (C.c_int32 * 4)()
+            _lib.check(lib().dmg_batch_instance_orders(self._h, k, p, q))
+            orders.append((tuple(p), tuple(q)))
+        return {"pre_order": list(pre), "post_order": list(post), "tail_threads": int(tt.value),
+                "orders": orders}
 
     def solve(self, bs, us=None, rtol: float = 1e-10, max_iters: int = 200, raise_on_fail: bool = True):
         if us is None:

@@ -79,6 +79,7 @@ SIGNATURES = {
     "dmg_batch_solve": (_st, [_p, _p, _p, C.c_double, _i32, _p, _p, _p]),
     "dmg_batch_autotune": (_st, [_p, _p, _p, _i32, _i32, _p]),
     "dmg_batch_config": (_st, [_p, C.POINTER(_i32), C.POINTER(_i32), C.POINTER(_i32)]),
+    "dmg_batch_instance_orders": (_st, [_p, _i32, C.POINTER(_i32), C.POINTER(_i32)]),
     "dmg_batch_destroy": (None, [_p]),
 }
 

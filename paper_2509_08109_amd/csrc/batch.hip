@@ -36,6 +36,7 @@ struct Launch {
   size_t lds = 0;      // TAIL: LDS bytes
   dmg::LineStep step = dmg::LineStep::kSweep;  // LINE: which step, on which lines, at which size
   int dir = 0, parity = 0, nx = 0, ny = 0;
+  int pf = 0;  // WAVE: the row parity smoothed first (one per launch)
 };
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -159,7 +160,6 @@ dmg_status build_schedule(dmg_batch* bt, double* const* u, const double* const* 
                           int32_t max_iters) {
   const int count = int(bt->inst.size());
   const dmg_options& o = bt->opts;
-  const OrderP pre = order_of(o.pre_order), post = order_of(o.post_order);
   std::vector<unsigned char> host(bt->args_cap);
   size_t used = 0;
   auto put = [&](const void* p, size_t n, size_t* off) -> dmg_status {
@@ -242,7 +242,8 @@ dmg_status build_schedule(dmg_batch* bt, double* const* u, const double* const* 
       a.ny = L.ny;
       a.seg_h = bt->seg_h[{L.nx, L.ny}];
       strip_blocks(L.nx, L.ny, 64, a.seg_h, &a.nstrips, &a.nsegs);
-      const OrderP& op = is_pre ? pre : post;
+      // each instance's own colour orders (the batch tuner may give each size class its own)
+      const OrderP op = order_of(is_pre ? h->opts.pre_order : h->opts.post_order);
       a.pf = op.pf;
       a.cA = op.cA;
       a.cB = op.cB;
@@ -255,7 +256,18 @@ dmg_status build_schedule(dmg_batch* bt, double* const* u, const double* const* 
     out->kind = Launch::WAVE;
     out->count = int(list.size());
     out->tiles_per = tiles_per;
+    out->pf = list.empty() ? 0 : list[0].pf;
     return put(list.data(), list.size() * sizeof(list[0]), &out->off);
+  };
+  // the members of a level size whose pre (post) order smooths row parity pf first: one wave
+  // launch per parity, since the kernel takes it as a compile-time parameter
+  auto by_pf = [&](const std::vector<std::pair<int, int>>& mem, bool is_pre, int pf) {
+    std::vector<std::pair<int, int>> out;
+    for (auto kl : mem) {
+      const dmg_hier* h = bt->inst[kl.first];
+      if (order_of(is_pre ? h->opts.pre_order : h->opts.post_order).pf == pf) out.push_back(kl);
+    }
+    return out;
   };
   // line cycles: every step of a level size reads one argument list (the sweeps are in place)
   std::map<std::tuple<long, int, int>, std::pair<size_t, size_t>> line_lists;  // (all, l > 0)
@@ -314,12 +326,15 @@ dmg_status build_schedule(dmg_batch* bt, double* const* u, const double* const* 
       seq.push_back(line_launch(key, LineStep::kRestrict, 0, 0, false));
       continue;
     }
-    for (int s = 0; s < o.nu_pre; ++s) {
-      Launch L;
-      DMG_CHECK(wave_list(mem, true, s, &L));
-      L.mode = 1;
-      seq.push_back(L);
-    }
+    for (int s = 0; s < o.nu_pre; ++s)
+      for (int pf = 0; pf < 2; ++pf) {
+        const auto part = by_pf(mem, true, pf);
+        if (part.empty()) continue;
+        Launch L;
+        DMG_CHECK(wave_list(part, true, s, &L));
+        L.mode = 1;
+        seq.push_back(L);
+      }
   }
   {  // coarse tails: the one-workgroup tail kernel, or the dense operator of the tail's top
     std::vector<TailArgs<double>> list;
@@ -369,12 +384,15 @@ dmg_status build_schedule(dmg_batch* bt, double* const* u, const double* const* 
           seq.push_back(line_launch(it->first, LineStep::kSweep, ldir[q], lpar[q], false));
       continue;
     }
-    for (int s = 0; s < o.nu_post; ++s) {
-      Launch L;
-      DMG_CHECK(wave_list(it->second, false, s, &L));
-      L.mode = s == 0 ? 2 : 3;
-      seq.push_back(L);
-    }
+    for (int s = 0; s < o.nu_post; ++s)
+      for (int pf = 0; pf < 2; ++pf) {
+        const auto part = by_pf(it->second, false, pf);
+        if (part.empty()) continue;
+        Launch L;
+        DMG_CHECK(wave_list(part, false, s, &L));
+        L.mode = s == 0 ? 2 : 3;
+        seq.push_back(L);
+      }
   }
   // per-instance norm arguments (starting norms; residual partials of all-tail instances)
   std::vector<NormArgs> norms(count), tail_only;
@@ -419,10 +437,7 @@ dmg_status run_step(dmg_batch* bt, hipStream_t s) {
     switch (L.kind) {
       case Launch::WAVE:
         DMG_CHECK(launch_wave_multi<double>(reinterpret_cast<const StripArgs<double>*>(p), L.count,
-                                            L.tiles_per, L.mode,
-                                            L.mode == 1 ? order_of(bt->opts.pre_order).pf
-                                                        : order_of(bt->opts.post_order).pf,
-                                            s));
+                                            L.tiles_per, L.mode, L.pf, s));
         break;
       case Launch::TAIL:
         DMG_CHECK(launch_tail_multi<double>(reinterpret_cast<const TailArgs<double>*>(p), L.count,
@@ -677,56 +692,56 @@ dmg_status dmg_batch_autotune(dmg_batch* bt, double* const* u, const double* con
   dmg_status st = DMG_OK;
   if ((flags & 2) && bt->opts.smoother == 0) {  // (line relaxation visits no colours)
     // colour orders: the row-separable pairs whose post order reverses the pre order (the
-    // V-cycle stays symmetric); each is timed as whole batched solves to 1e-10 from zero, which
-    // counts the cycles it saves or costs.  One pair serves every instance.
+    // V-cycle stays symmetric), chosen per size class (instances of one finest grid size), one
+    // class after another (coordinate descent), each candidate timed as whole batched solves to
+    // 1e-10 from zero, which counts the cycles it saves or costs
     static const int32_t cand[4][4] = {{0, 1, 2, 3}, {1, 0, 3, 2}, {2, 3, 0, 1}, {3, 2, 1, 0}};
-    float best_ms = 1e30f;
-    int best = -1;
-    for (int c = 0; c < 4 && st == DMG_OK; ++c) {
+    std::map<std::pair<int, int>, std::vector<int>> classes;
+    for (int k = 0; k < count; ++k) classes[{bt->inst[k]->L[0].nx, bt->inst[k]->L[0].ny}].push_back(k);
+    auto set_class = [&](const std::vector<int>& mem, int c) -> dmg_status {
       int32_t post[4];
       for (int k = 0; k < 4; ++k) post[k] = cand[c][3 - k];
-      for (int k = 0; k < 4; ++k) {
-        bt->opts.pre_order[k] = cand[c][k];
-        bt->opts.post_order[k] = post[k];
-      }
-      for (auto* h : bt->inst)
-        if (st == DMG_OK) st = set_colour_orders(h, cand[c], post, stream);
+      for (int k : mem) DMG_CHECK(set_colour_orders(bt->inst[k], cand[c], post, stream));
       bt->built = false;
       bt->reset_graph();
-      float total = 0.f;
-      for (int r = 0; r <= std::max(1, reps / 4) && st == DMG_OK; ++r) {
-        for (int k = 0; k < count && st == DMG_OK; ++k)
-          st = launch_fill<double>(u[k], 0.0, bt->inst[k]->L[0].n(), stream);
-        if (st != DMG_OK) break;
-        DMG_HIP(hipEventRecord(e0, stream));
-        st = dmg_batch_solve(bt, u, b, 1e-10, 500, nullptr, nullptr, stream);
-        DMG_HIP(hipEventRecord(e1, stream));
-        DMG_HIP(hipEventSynchronize(e1));
-        float ms = 0.f;
-        DMG_HIP(hipEventElapsedTime(&ms, e0, e1));
-        if (r > 0) total += ms;  // the first solve builds the schedule and captures the graph
+      return DMG_OK;
+    };
+    for (auto& [dims, mem] : classes) {
+      if (st != DMG_OK) break;
+      float best_ms = 1e30f;
+      int best = -1;
+      for (int c = 0; c < 4 && st == DMG_OK; ++c) {
+        st = set_class(mem, c);
+        float total = 0.f;
+        for (int r = 0; r <= std::max(1, reps / 4) && st == DMG_OK; ++r) {
+          for (int k = 0; k < count && st == DMG_OK; ++k)
+            st = launch_fill<double>(u[k], 0.0, bt->inst[k]->L[0].n(), stream);
+          if (st != DMG_OK) break;
+          DMG_HIP(hipEventRecord(e0, stream));
+          st = dmg_batch_solve(bt, u, b, 1e-10, 500, nullptr, nullptr, stream);
+          DMG_HIP(hipEventRecord(e1, stream));
+          DMG_HIP(hipEventSynchronize(e1));
+          float ms = 0.f;
+          DMG_HIP(hipEventElapsedTime(&ms, e0, e1));
+          if (r > 0) total += ms;  // the first solve builds the schedule and captures the graph
+        }
+        if (st == DMG_ERR_NO_CONVERGENCE) {  // this order does not reach the tolerance in 500 steps
+          st = DMG_OK;
+          clear_error();
+          continue;
+        }
+        if (st == DMG_OK && total < best_ms) {
+          best_ms = total;
+          best = c;
+        }
       }
-      if (st == DMG_ERR_NO_CONVERGENCE) {  // this order does not reach the tolerance in 500 steps
-        st = DMG_OK;
-        clear_error();
-        continue;
-      }
-      if (st == DMG_OK && total < best_ms) {
-        best_ms = total;
-        best = c;
-      }
+      if (st == DMG_OK) st = set_class(mem, best >= 0 ? best : 0);
     }
-    if (st == DMG_OK) {
-      const int c = best >= 0 ? best : 0;
-      int32_t post[4];
-      for (int k = 0; k < 4; ++k) post[k] = cand[c][3 - k];
+    if (st == DMG_OK)  // the batch-wide record: instance 0's pair
       for (int k = 0; k < 4; ++k) {
-        bt->opts.pre_order[k] = cand[c][k];
-        bt->opts.post_order[k] = post[k];
+        bt->opts.pre_order[k] = bt->inst[0]->opts.pre_order[k];
+        bt->opts.post_order[k] = bt->inst[0]->opts.post_order[k];
       }
-      for (auto* h : bt->inst)
-        if (st == DMG_OK) st = set_colour_orders(h, cand[c], post, stream);
-    }
   }
   for (auto& [d, h] : bt->seg_h) {
     if (!(flags & 1) || st != DMG_OK) break;
@@ -776,6 +791,19 @@ dmg_status dmg_batch_config(const dmg_batch* bt, int32_t* pre_order, int32_t* po
     if (post_order) post_order[k] = bt->opts.post_order[k];
   }
   if (tail_threads) *tail_threads = bt->tail_threads;
+  return DMG_OK;
+}
+
+dmg_status dmg_batch_instance_orders(const dmg_batch* bt, int32_t k, int32_t* pre_order,
+                                     int32_t* post_order) {
+  clear_error();
+  if (!bt) return fail(DMG_ERR_INVALID_ARG, "null batch");
+  if (k < 0 || k >= int(bt->inst.size()))
+    return fail(DMG_ERR_INVALID_ARG, "instance %d out of range [0,%zu)", k, bt->inst.size());
+  for (int q = 0; q < 4; ++q) {
+    if (pre_order) pre_order[q] = bt->inst[k]->opts.pre_order[q];
+    if (post_order) post_order[q] = bt->inst[k]->opts.post_order[q];
+  }
   return DMG_OK;
 }
 

@@ -613,9 +613,9 @@ def test_batch_matches_single_solves(dmg):
 
 
 def test_batch_tuned_colour_order_matches_oracle(dmg):
-    """The batch tuner picks the colour-order pair by timing whole batched solves; the batch
-    then runs it on every instance: each instance equals its single solve with that order bit
-    for bit and the oracle's solve with that order entry by entry (same cycle counts)."""
+    """The batch tuner picks a colour-order pair per size class by timing whole batched solves;
+    each instance then runs its class's pair and equals its single solve with that pair bit for
+    bit and the oracle's solve with that pair entry by entry (same cycle counts)."""
     sizes = (129, 65, 257, 129, 65, 33, 257)
     probs = [pb.star(n, seed=40 + k) for k, n in enumerate(sizes)]
     probs.append(pb.quarter_annulus(65))
@@ -623,12 +623,16 @@ def test_batch_tuned_colour_order_matches_oracle(dmg):
     bs = [dev(p.b) for p in probs]
     bt = dmg.BatchSolver(Ss)
     cfg = bt.autotune(bs, reps=4, tiles=True, colour_order=True)
-    pre, post = tuple(cfg["pre_order"]), tuple(cfg["post_order"])
-    print(f"[batch] tuned colour order {pre} / {post}, tail threads {cfg['tail_threads']}")
-    assert post == pre[::-1] and sorted(pre) == [0, 1, 2, 3]
+    orders = cfg["orders"]
+    by_class = {}
+    for p, (pre, post) in zip(probs, orders):
+        assert post == pre[::-1] and sorted(pre) == [0, 1, 2, 3]
+        assert by_class.setdefault((p.nx, p.ny), (pre, post)) == (pre, post)  # one pair per class
+    print(f"[batch] tuned colour orders per class {by_class}, tail threads {cfg['tail_threads']}")
+    assert tuple(cfg["pre_order"]) == orders[0][0]
     us, its, rels = bt.solve(bs, rtol=1e-10)
     assert max(rels) <= 1e-10
-    _batch_vs_single(dmg, Ss, bs, bt, us, its, rels, probs=probs, orders=[(pre, post)] * len(probs))
+    _batch_vs_single(dmg, Ss, bs, bt, us, its, rels, probs=probs, orders=orders)
     bt.close()
 
 
