@@ -688,8 +688,11 @@ dmg_status time_level(dmg_hier* h, int l, const StripConfig& c, int reps, hipStr
   T* u = l == 0 ? Pr::r(L) : Pr::u(L);
   T* t = Pr::t(L);
   const T* b = l == 0 ? Pr::Sp(L) : Pr::b(L);
+  // the pre sweep in the form the cycle runs it: from the iterate on level 0, from zero on the
+  // coarser levels (that kernel reads no iterate, and its best shape can differ)
+  const T* uin = l == 0 ? u : nullptr;
   DMG_CHECK(time_runs([&]() {
-    return launch_pre<T>(c, Pr::Sp(L), u, t, b, Pr::P(L), Pr::b(h->L[l + 1]), L.nx, L.ny, pre.pf,
+    return launch_pre<T>(c, Pr::Sp(L), uin, t, b, Pr::P(L), Pr::b(h->L[l + 1]), L.nx, L.ny, pre.pf,
                          pre.cA, pre.cB, nullptr, s);
   }, reps, s, e0, e1, ms_pre));
   return time_runs([&]() {
