@@ -225,7 +225,8 @@ void carve(dmg_hier& h, Arena& a, const std::vector<std::pair<int, int>>& dims,
   h.m_coarse = (c.first - 2) * (c.second - 2);
   h.coarse_idx = a.take<int>(size_t(h.m_coarse));
   h.chol = a.take<double>(size_t(h.m_coarse) * h.m_coarse);
-  h.partials = a.take<double>(kMaxPartials + kReduceBlocks);  // + the b-norm partials of a solve start
+  // + the b-norm partials of a solve start and its counts of nonzero initial-iterate entries
+  h.partials = a.take<double>(kMaxPartials + 2 * kReduceBlocks);
   for (size_t l = 0; l < dims.size(); ++l) {
     h.L[l].cfg = default_strip_config(dims[l].first, dims[l].second, o);
     h.L[l].cfg32 = h.L[l].cfgp = h.L[l].cfgp32 = h.L[l].cfg;
@@ -524,6 +525,8 @@ dmg_status norm_r(dmg_hier* h, const double* u, const double* b, int slot, hipSt
 // Device solve state: flag[4] = stop, flag[5] = steps done, flag[6] = max steps;
 // scalars[6] = (rtol ||b||)^2.
 int* stop_flag(dmg_hier* h) { return h->flag + 4; }
+// flag[8]: set by a solve's start when the initial iterate is zero
+int* zero_flag(dmg_hier* h) { return h->flag + 8; }
 
 // The repeated step of a float64 solve: one V-cycle, then the residual norm of the new iterate
 // (slot 2) and the convergence check.  When the finest level runs in the strip kernels, the
@@ -575,19 +578,22 @@ void reset_solve_graphs(dmg_hier* h) {
 
 // The solve's start on the device: ||b|| and the initial residual's norm, the target and the
 // solve state (no host synchronisation; a solve that is done at the start runs its first
-// chunk of steps as skipped kernels).
+// chunk of steps as skipped kernels).  The pass over b also tests whether u is zero; then the
+// initial residual is b, and its pass reads neither the stencil nor u (same partials, same bits).
 dmg_status solve_start(dmg_hier* h, int kind, double* u, const double* b, double rtol,
                        int max_iters, hipStream_t s) {
   const Level& L0 = h->L[0];
   const int slot = kind ? 4 : 2;
   double* pb = h->partials + kMaxPartials;
-  DMG_CHECK(launch_sq_partials(b, L0.n(), L0.nx, L0.ny, pb, s));
+  double* nonzero = pb + kReduceBlocks;
+  int* zero = zero_flag(h);
+  DMG_CHECK(launch_start_norms(b, u, L0.nx, L0.ny, pb, nonzero, zero, s));
   int nr = kReduceBlocks;
   if (kind) {
-    DMG_CHECK(launch_ir_residual(L0.Sp, u, b, L0.r, L0.nx, L0.ny, h->partials, s));
+    DMG_CHECK(launch_ir_residual(L0.Sp, u, b, L0.r, L0.nx, L0.ny, h->partials, s, nullptr, zero));
     nr = ir_residual_blocks(L0.nx, L0.ny);
   } else {
-    DMG_CHECK(launch_resid_sq_partials(L0.S, u, b, L0.nx, L0.ny, h->partials, s));
+    DMG_CHECK(launch_resid_sq_partials(L0.S, u, b, L0.nx, L0.ny, h->partials, s, nullptr, zero, pb));
   }
   return launch_solve_start(pb, kReduceBlocks, h->partials, nr, h->scalars, h->scalars + slot,
                             h->flag + 4, rtol, max_iters, u, L0.n(), s);

@@ -67,13 +67,21 @@ __device__ __forceinline__ double block_sum(double v) {
   return t;
 }
 
-// partials[blk] = sum over interior rows assigned to blk of (b - A u)^2
+// partials[blk] = sum over interior rows assigned to blk of (b - A u)^2.  When *zero is set
+// (u is zero everywhere) the residual is b: the block copies its b-norm partial pb[blk] (k_sq's,
+// which sums the same terms in the same order) instead of reading S and u.
 __global__ __launch_bounds__(256) void k_resid_sq(const double* __restrict__ S,
                                                   const double* __restrict__ u,
                                                   const double* __restrict__ b, int nx, int ny,
                                                   double* __restrict__ partials,
-                                                  const int* __restrict__ stop) {
+                                                  const int* __restrict__ stop,
+                                                  const int* __restrict__ zero,
+                                                  const double* __restrict__ pb) {
   if (stop && *stop) return;
+  if (zero && *zero) {
+    if (threadIdx.x == 0) partials[blockIdx.x] = pb[blockIdx.x];
+    return;
+  }
   const size_t N = size_t(nx) * ny;
   const size_t m = size_t(nx - 2) * (ny - 2);
   double acc = 0.0;
@@ -88,8 +96,13 @@ __global__ __launch_bounds__(256) void k_resid_sq(const double* __restrict__ S,
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
+// partials[blk] = sum of x^2 over the interior points assigned to blk; with u, also
+// nonzero[blk] = number of the entries of u (every point, boundary included) assigned to blk
+// that are not zero (NaN counts as not zero).
 __global__ __launch_bounds__(256) void k_sq(const double* __restrict__ x, int nx, int ny,
-                                            double* __restrict__ partials) {
+                                            double* __restrict__ partials,
+                                            const double* __restrict__ u,
+                                            double* __restrict__ nonzero) {
   const size_t m = size_t(nx - 2) * (ny - 2);
   double acc = 0.0;
   for (size_t k = blockIdx.x * size_t(blockDim.x) + threadIdx.x; k < m;
@@ -100,6 +113,23 @@ __global__ __launch_bounds__(256) void k_sq(const double* __restrict__ x, int nx
   }
   const double t = block_sum(acc);
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
+  if (!u) return;
+  const size_t n = size_t(nx) * ny;
+  double cnt = 0.0;
+  for (size_t k = blockIdx.x * size_t(blockDim.x) + threadIdx.x; k < n;
+       k += size_t(gridDim.x) * blockDim.x)
+    cnt += u[k] == 0.0 ? 0.0 : 1.0;
+  const double c = block_sum(cnt);
+  if (threadIdx.x == 0) nonzero[blockIdx.x] = c;
+}
+
+// *zero = 1 when the nonzero counts of k_sq sum to zero, else 0
+__global__ __launch_bounds__(256) void k_zero_flag(const double* __restrict__ nonzero, int count,
+                                                   int* __restrict__ zero) {
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < count; k += 256) acc += nonzero[k];
+  const double t = block_sum(acc);
+  if (threadIdx.x == 0) *zero = t == 0.0 ? 1 : 0;
 }
 
 // out[0] = sum of the partials (fixed order), out[1] = sqrt(out[0])
@@ -435,15 +465,25 @@ DMG_INST(float)
 #undef DMG_INST
 
 dmg_status launch_resid_sq_partials(const double* S, const double* u, const double* b, int nx,
-                                    int ny, double* partials, hipStream_t s, const int* stop) {
-  k_resid_sq<<<kReduceBlocks, 256, 0, s>>>(S, u, b, nx, ny, partials, stop);
+                                    int ny, double* partials, hipStream_t s, const int* stop,
+                                    const int* zero, const double* pb) {
+  if (zero && !pb) return fail(DMG_ERR_INVALID_ARG, "a zero-iterate residual needs the b partials");
+  k_resid_sq<<<kReduceBlocks, 256, 0, s>>>(S, u, b, nx, ny, partials, stop, zero, pb);
   return launch_check("resid_sq");
 }
 
 dmg_status launch_sq_partials(const double* x, size_t, int nx, int ny, double* partials,
                               hipStream_t s) {
-  k_sq<<<kReduceBlocks, 256, 0, s>>>(x, nx, ny, partials);
+  k_sq<<<kReduceBlocks, 256, 0, s>>>(x, nx, ny, partials, nullptr, nullptr);
   return launch_check("sq");
+}
+
+dmg_status launch_start_norms(const double* b, const double* u, int nx, int ny, double* pb,
+                              double* nonzero, int* zero, hipStream_t s) {
+  k_sq<<<kReduceBlocks, 256, 0, s>>>(b, nx, ny, pb, u, nonzero);
+  DMG_CHECK(launch_check("sq"));
+  k_zero_flag<<<1, 256, 0, s>>>(nonzero, kReduceBlocks, zero);
+  return launch_check("zero_flag");
 }
 
 dmg_status launch_stencil_apply(const double* S, const double* x, double* y, int nx, int ny,

@@ -122,7 +122,8 @@ struct dmg_hier {
   double* chol = nullptr;     // [m][m] Cholesky factor (lower), float64
   double* partials = nullptr; // [kReduceBlocks] reduction partials
   double* scalars = nullptr;  // [16] device scalars (norms, IR scale)
-  int* flag = nullptr;        // device ints: [0] pivot flag, [4..6] solve state (stop, steps, max)
+  int* flag = nullptr;        // device ints: [0] pivot flag, [4..6] solve state (stop, steps, max),
+                              // [8] initial iterate is zero
   double* hist = nullptr;     // device history of relative residuals [kMaxHistory]
   double* host = nullptr;     // pinned host scalars [16]
   // With a coarse tail below level 0: its levels' S, P and right-hand sides stored in one block
@@ -233,11 +234,20 @@ dmg_status launch_copy(const T* x, T* y, size_t n, const int* stop, hipStream_t 
 
 // ||b - A u||^2 partials (fixed block count) and sum(x^2) partials; finalize sums the
 // partials in a fixed order into out[0] (and sqrt into out[1]).
+// zero (nullable, with pb): device flag; when set, u is taken as zero and the partials are
+// copied from the b-norm partials pb of launch_sq_partials / launch_start_norms (bitwise the
+// partials the residual pass would form from u = 0).
 dmg_status launch_resid_sq_partials(const double* S, const double* u, const double* b, int nx,
                                     int ny, double* partials, hipStream_t s,
-                                    const int* stop = nullptr);
+                                    const int* stop = nullptr, const int* zero = nullptr,
+                                    const double* pb = nullptr);
 dmg_status launch_sq_partials(const double* x, size_t n, int nx, int ny, double* partials,
                               hipStream_t s);
+// The b-norm partials of launch_sq_partials (pb, bitwise the same) and, from one read of u,
+// *zero = 1 when every entry of u (boundary included) is zero, else 0; nonzero receives
+// kReduceBlocks per-block counts.
+dmg_status launch_start_norms(const double* b, const double* u, int nx, int ny, double* pb,
+                              double* nonzero, int* zero, hipStream_t s);
 dmg_status launch_finalize(const double* partials, double* out, hipStream_t s,
                            int count = kReduceBlocks);
 
@@ -392,9 +402,11 @@ dmg_status launch_ir_update(double* x, const float* e, size_t n, const double* s
 // r = b - A x in float64 with A (point-major [ny][nx][5]) (zero on the boundary ring), plus one
 // squared-norm partial per workgroup; ir_residual_blocks gives the number of partials written
 int ir_residual_blocks(int nx, int ny);
+// zero (nullable): device flag; when set, x is taken as zero and r = b is written without
+// reading S or x (bitwise what the full pass gives for x = 0).
 dmg_status launch_ir_residual(const double* S, const double* x, const double* b, double* r,
                               int nx, int ny, double* partials, hipStream_t s,
-                              const int* stop = nullptr);
+                              const int* stop = nullptr, const int* zero = nullptr);
 // r32 = fl32(r / s) over n points, s = *norm (r32 = 0 where s = 0)
 dmg_status launch_ir_scale(const double* r, float* r32, size_t n, const double* norm,
                            hipStream_t s, const int* stop = nullptr);

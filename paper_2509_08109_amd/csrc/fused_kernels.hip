@@ -1112,7 +1112,8 @@ __global__ __launch_bounds__(64) void k_ir_resid(const double* __restrict__ S,
                                                  const double* __restrict__ b,
                                                  double* __restrict__ r64, int nx, int ny, int rows,
                                                  int nstrips, double* __restrict__ partials,
-                                                 const int* __restrict__ stop) {
+                                                 const int* __restrict__ stop,
+                                                 const int* __restrict__ zero) {
   if (stop && *stop) return;
   const int strip = int(blockIdx.x) % nstrips, seg = int(blockIdx.x) / nstrips;
   const int t = threadIdx.x;
@@ -1120,6 +1121,23 @@ __global__ __launch_bounds__(64) void k_ir_resid(const double* __restrict__ S,
   const int j0 = seg * rows, j1 = min(j0 + rows, ny);
   const bool out_col = t >= 1 && t <= kResidOut && i < nx;
   const bool int_col = i >= 1 && i <= nx - 2;
+  if (zero && *zero) {
+    // x = 0: A x vanishes and r = b; the same points are summed in the same order
+    double acc = 0.0;
+    for (int j = j0; j < j1; ++j) {
+      const bool interior = int_col && j >= 1 && j <= ny - 2;
+      if (out_col) {
+        const size_t v = size_t(j) * nx + i;
+        const double rv = interior ? b[v] : 0.0;
+        r64[v] = rv;
+        acc += rv * rv;
+      }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+    if (t == 0) partials[blockIdx.x] = acc;
+    return;
+  }
   ResRow m, c, n, nn;  // rows j - 1, j, j + 1 and the prefetched j + 2
   res_load(S, x, b, nx, ny, i, j0 - 1, m);
   res_load(S, x, b, nx, ny, i, j0, c);
@@ -1200,10 +1218,11 @@ int ir_residual_blocks(int nx, int ny) {
 }
 
 dmg_status launch_ir_residual(const double* S, const double* x, const double* b, double* r,
-                              int nx, int ny, double* partials, hipStream_t s, const int* stop) {
+                              int nx, int ny, double* partials, hipStream_t s, const int* stop,
+                              const int* zero) {
   int rows = 0, ns = 0, nb = 0;
   resid_shape(nx, ny, &rows, &ns, &nb);
-  k_ir_resid<<<nb, 64, 0, s>>>(S, x, b, r, nx, ny, rows, ns, partials, stop);
+  k_ir_resid<<<nb, 64, 0, s>>>(S, x, b, r, nx, ny, rows, ns, partials, stop, zero);
   return launch_check("ir_residual");
 }
 

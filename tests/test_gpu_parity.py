@@ -310,6 +310,56 @@ def test_graph_and_eager_solves_are_identical(dmg):
     assert out[0][1] == out[1][1] and np.array_equal(out[0][0], out[1][0])
 
 
+def test_solve_start_tests_the_initial_iterate(dmg):
+    """A solve's start tests the initial iterate on the device.  From zero, the first residual
+    is b and its pass reads neither the stencil nor u.  From anything else it is formed in full.
+    The same captured start (same arrays, so graph replays) is run with a zero guess, a random
+    interior guess, a guess that is nonzero only on the boundary ring (a zero residual change, but
+    not a zero iterate) and zero again.  Each gives the oracle's step count, history and iterate.
+    Float32 refinement from zero gives the same bits before and after a nonzero-guess solve on the
+    same arrays."""
+    prob = pb.star(257, seed=5)
+    S_or = fem.assemble_stencil(prob.jac, prob.K, prob.nx, prob.ny)
+    levels = boxmg.build_hierarchy(S_or)
+    orc = cycle.Oracle(levels)
+    rng = np.random.default_rng(3)
+    g_int = np.zeros((prob.ny, prob.nx))
+    g_int[1:-1, 1:-1] = rng.uniform(-1.0, 1.0, (prob.ny - 2, prob.nx - 2))
+    g_bnd = np.zeros((prob.ny, prob.nx))
+    g_bnd[0, :] = 1.0
+    g_bnd[:, -1] = -2.0
+    zero = np.zeros((prob.ny, prob.nx))
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        h = dmg.Hierarchy(dev(S_or))
+        b = dev(prob.b)
+        u = torch.zeros_like(b)
+        for name, g in (("zero", zero), ("interior guess", g_int), ("boundary-only guess", g_bnd),
+                        ("zero again", zero)):
+            u.copy_(dev(g))
+            x, k, rel, hist = h.solve(b, u=u, rtol=1e-10)
+            uo, ko, histo, _ = cycle.solve(orc, prob.b, 1e-10, u0=g.copy())
+            assert k == ko, (name, k, ko)
+            assert np.allclose(hist, histo, rtol=1e-6, atol=1e-13), name
+            # the library writes boundary entries of a solution as 0; the oracle keeps u0's
+            assert_iterate(name, host(x)[1:-1, 1:-1].ravel(), np.asarray(uo)[1:-1, 1:-1].ravel())
+        h.close()
+        h32 = dmg.Hierarchy(dev(S_or), precision=dmg.DMG_FP32_IR, inner_cycles=2)
+        x32 = torch.zeros_like(b)
+        runs = []
+        for g in (zero, g_int, zero):
+            x32.copy_(dev(g))
+            x, k, rel, _ = h32.solve(b, u=x32, rtol=1e-10)
+            assert rel <= 1e-10
+            runs.append((x.clone(), k))
+        assert torch.equal(runs[0][0], runs[2][0]) and runs[0][1] == runs[2][1]
+        u64, _, _, _ = cycle.solve(orc, prob.b, 1e-10)
+        err = float(np.linalg.norm(host(runs[1][0]) - u64) / np.linalg.norm(u64))
+        assert err < 1e-7, err
+        h32.close()
+    torch.cuda.synchronize()
+
+
 def test_grad_K_matches_oracle(dmg):
     """dK_e = -sum_ab lam_a G_e[a,b] u_b per cell, within 1e-12 of sum_ab |lam_a G_ab u_b|."""
     for prob in (pb.star(65, seed=4), pb.quarter_annulus(33, ny=49)):
