@@ -244,7 +244,7 @@ def run_diff_leg(dmg, dev, steps: int, n: int = 2049, n_dirs: int = 64):
 
     K = K0.clone().requires_grad_(True)
     b = b0.clone().requires_grad_(True)
-    for _ in range(1):                                   # warm-up
+    for _ in range(2):                                   # warm-up (graph captures)
         J_of(K, b, 1e-10).backward()
     K.grad = None
     b.grad = None
@@ -765,7 +765,7 @@ def main():
         res["c4_batch"] = run_batch_leg(dmg, dev, max(1, args.steps // 2))
     if not args.no_c5:
         log("gradient leg: 2049x2049 star")
-        res["c5_gradient"] = run_diff_leg(dmg, dev, max(1, args.steps // 2))
+        res["c5_gradient"] = run_diff_leg(dmg, dev, max(4, args.steps))
     if not args.no_transfer:
         log("transfer leg: 1025x1025 grid, ~3.8M-vertex mesh")
         res["transfer"] = run_transfer_leg(dmg, dev)
