@@ -792,6 +792,14 @@ def test_zero_rhs_and_failures(dmg):
     with pytest.raises(dmg.DmgError) as ei:
         h.solve(bad)
     assert ei.value.code == 5
+    # a NaN in the initial guess, inside or on the boundary ring, is not a zero iterate: the
+    # start forms the residual in full and reports it
+    for where in ((7, 9), (0, 3)):
+        u_nan = torch.zeros((33, 33), dtype=torch.float64, device="cuda")
+        u_nan[where] = float("nan")
+        with pytest.raises(dmg.DmgError) as ei:
+            h.solve(dev(prob.b), u=u_nan)
+        assert ei.value.code == 5, where
     h.close()
     Sneg = -S
     with pytest.raises(dmg.DmgError) as ei:
