@@ -269,7 +269,7 @@ dmg_status device_transpose(const int* rp, const int* ci, const double* v, int n
                             hipStream_t s);
 // Structure check of a device CSR with nr rows, nc columns and nnz entries: rp[0] = 0, rp
 // non-decreasing and at most nnz (checked first, reading rp only), then every column in [0, nc).
-// *ok receives the verdict; flag is one device int of scratch.  Synchronises s.
+// *ok receives the result of the check; flag is one device int of scratch.  Synchronises s.
 dmg_status device_check_csr(const int* rp, const int* ci, int nr, int nc, int nnz, int* flag,
                             bool* ok, hipStream_t s);
 
