@@ -11,7 +11,9 @@ comparison is entry by entry over the whole grid (tests/entrywise.py):
     against the oracle's refinement, and its solution against the float64 oracle solution;
   * 4097^2: every level's stencil and interpolation weights, the float64 solve's cycle count,
     history and solution, and the float32-refined solution against the oracle's refinement and
-    against the float64 oracle solution.
+    against the float64 oracle solution;
+  * the 256-instance batch (sizes 129^2 to 1025^2, root seed 3): every instance against its single
+    solve bit for bit, and one instance of each size against the oracle.
 """
 import numpy as np
 import pytest
@@ -137,3 +139,45 @@ def test_bench_config_4097_whole_grid(dmg):
     _say(f"{n}: fp32-refined m={m}, {k32} steps, error vs float64 oracle solution {err:.2e}")
     assert err < 1e-7
     h32.close()
+
+
+def test_batch_bench_config(dmg):
+    """The batch workload bench.py times: 256 star instances, sizes uniform over
+    {129, 257, 513, 1025}^2 (root seed 3), tuned as bench.py tunes them (segment heights, tail
+    workgroup size, one colour-order pair per size class).  Every instance converges and equals its
+    single solve (coarse kernel, the same colour orders) bit for bit; the first instance of each
+    size class equals the oracle's solve of the same arrays (cycle count, and the solution entry by
+    entry)."""
+    from problems.batch_device import star_batch_device
+
+    Ss, bs, sizes, first = [], [], [], {}
+    for k, (n, jac, K, b) in enumerate(star_batch_device(256, device="cuda")):
+        Ss.append(dmg.assemble_stencil(jac, K))
+        bs.append(b)
+        sizes.append(n)
+        if n not in first:
+            first[n] = (k, host(jac), host(K), host(b))
+        del jac, K
+    _say(f"batch: {len(Ss)} instances, sizes {sorted(set(sizes))}")
+    bt = dmg.BatchSolver(Ss)
+    cfg = bt.autotune(bs, reps=2, tiles=True, colour_order=True)
+    orders = cfg["orders"]
+    us, its, rels = bt.solve(bs, rtol=1e-10)
+    assert max(rels) <= 1e-10
+    _say(f"batch: cycles {min(its)}..{max(its)}, max relres {max(rels):.2e}")
+    for k, (S, b) in enumerate(zip(Ss, bs)):
+        pre, post = orders[k]
+        h = dmg.Hierarchy(S, coarse_gemv=0, pre_order=pre, post_order=post)
+        u1, k1, _, _ = h.solve(b, rtol=1e-10)
+        assert k1 == its[k] and torch.equal(us[k], u1), (k, sizes[k])
+        h.close()
+    for n, (k, jac_h, K_h, b_h) in sorted(first.items()):
+        pre, post = orders[k]
+        orc = cycle.Oracle(boxmg.build_hierarchy(fem.assemble_stencil(jac_h, K_h, n, n)),
+                           pre=pre, post=post)
+        uo, ko, _, _ = cycle.solve(orc, b_h, 1e-10, max_iters=300)
+        assert its[k] == ko, (k, n, its[k], ko)
+        used = assert_iterate(f"batch instance {k} ({n}x{n}) vs oracle", host(us[k]), uo,
+                              floor_ulps=grid_floor_ulps(n))
+        _say(f"batch instance {k} ({n}x{n}): {ko} cycles, worst excess {used:.1f} eps max|u|")
+    bt.close()
