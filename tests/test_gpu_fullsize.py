@@ -13,14 +13,16 @@ comparison is entry by entry over the whole grid (tests/entrywise.py):
     history and solution, and the float32-refined solution against the oracle's refinement and
     against the float64 oracle solution;
   * the 256-instance batch (sizes 129^2 to 1025^2, root seed 3): every instance against its single
-    solve bit for bit, and one instance of each size against the oracle.
+    solve bit for bit, and one instance of each size against the oracle;
+  * the differentiable solve on the 2049^2 star (root seed 4): dJ/dK per cell and dJ/db against
+    the oracle's adjoint gradient of the same arrays.
 """
 import numpy as np
 import pytest
 import torch
 
-from entrywise import EPS32, assert_hierarchy, assert_iterate, grid_floor_ulps
-from oracle import boxmg, cycle, fem
+from entrywise import EPS32, EPS64, assert_entrywise, assert_hierarchy, assert_iterate, grid_floor_ulps
+from oracle import adjoint, boxmg, cycle, fem
 from problems.batch_device import star_device
 
 pytestmark = pytest.mark.gpu
@@ -181,3 +183,42 @@ def test_batch_bench_config(dmg):
                               floor_ulps=grid_floor_ulps(n))
         _say(f"batch instance {k} ({n}x{n}): {ko} cycles, worst excess {used:.1f} eps max|u|")
     bt.close()
+
+
+def test_gradient_bench_config_2049(dmg):
+    """The differentiable solve bench.py times: the 2049^2 star (root seed 4), J(u) = 1/2 ||u - u_t||^2
+    over the interior, with bench.py's tolerance (1e-10) for the forward and the adjoint solve.  Both
+    sides take the same cycle counts, so u and lambda are the same iterates (parity to rounding, not
+    to the solve tolerance).  DiffSolve's dJ/dK (per cell) is compared with the oracle's adjoint
+    gradient of the same arrays within 1e-9 of sum_ab |lam_a G_e[a,b] u_b|, and dJ/db (= lambda)
+    entry by entry within 1e-9."""
+    import problems as pb
+
+    n = 2049
+    prob = pb.star(n, seed=4, device="cuda")
+    as_dev = lambda x: torch.as_tensor(x, dtype=torch.float64, device="cuda").contiguous()
+    jac = as_dev(prob.jac)
+    K = as_dev(prob.K).requires_grad_(True)
+    b = as_dev(prob.b).requires_grad_(True)
+    t = as_dev(prob.target)
+    u = dmg.DiffSolve.apply(K, b, jac, 1e-10)
+    d = (u - t)[1:-1, 1:-1]
+    (0.5 * (d * d).sum()).backward()
+    gK, gb = host(K.grad), host(b.grad)
+    kf, ka = dmg.DiffSolve.last["forward"][0], dmg.DiffSolve.last["adjoint"][0]
+    dmg.DiffSolve.clear_cache()
+    del jac, K, b, t, u, d
+    torch.cuda.empty_cache()
+    S_or = fem.assemble_stencil(prob.jac, prob.K, n, n)
+    orc = cycle.Oracle(boxmg.build_hierarchy(S_or))
+    uo, ko, _, _ = cycle.solve(orc, prob.b, 1e-10)
+    lo, kl, _, _ = cycle.solve(orc, adjoint.objective_grad_u(uo, prob.target), 1e-10)
+    assert (kf, ka) == (ko, kl), ((kf, ka), (ko, kl))
+    gKo = adjoint.grad_K(prob.jac, lo, uo, n, n)
+    G = fem.element_matrices(prob.jac, n, n)
+    scale = np.einsum("jia,jiab,jib->ji", np.abs(adjoint.local_values(lo)), np.abs(G),
+                      np.abs(adjoint.local_values(uo)))
+    assert_entrywise("2049x2049 dJ/dK", gK, gKo, scale, 1e-9)
+    assert_iterate("2049x2049 dJ/db", gb, lo, rtol=1e-9, floor_ulps=int(1e-12 / EPS64))
+    rel = float(np.linalg.norm(gK - gKo) / np.linalg.norm(gKo))
+    _say(f"gradient 2049: oracle {ko} + {kl} cycles; ||dK - dK_oracle|| / ||dK_oracle|| = {rel:.2e}")
