@@ -7,6 +7,9 @@ through properties that hold at any size.
   bound eps / h^2 of the barycentric evaluations).
 * The matrix-free coupled mass at the transfer leg's size (1025^2 grid, 3.76M-vertex mesh): whole
   from_grid and to_grid vectors against the stored form, entry by entry.
+* The stored transfer at the same size (rasterised C, nq = 4): sampled rows of C against the
+  oracle's rule, and whole from_grid / to_grid vectors against the oracle's CG2 applies made with
+  the library's C.
 * The two-level solve at a 513^2 grid (0.94M vertices, the bench's largest two-level size):
   the residual of the returned solution, recomputed on the host with A_p assembled here by
   vectorised NumPy (independently of the library), meets the tolerance.
@@ -147,3 +150,45 @@ def test_line_smoothed_annulus_residual_at_1025(lib):
     assert k <= 10 and rel <= 1e-10
     assert rel_host <= 1e-10 * (1 + 1e-6) and abs(rel_host - rel) <= 1e-6 * rel
     h.close()
+
+
+def test_transfer_applies_at_1025(lib):
+    """The bench's transfer workload in its stored form (1025^2 grid, the 3.76M-vertex lattice
+    mesh, rasterised C with nq = 4).  Sampled rows of C against the oracle's rasterised rule on
+    the vertex's incident triangles alone, entry by entry.  Then from_grid = CG2(M_p, C u_c) and
+    to_grid = C^T CG2(M_p, r_p), whole vectors, against the oracle's CG2 applies.  Those use the
+    oracle's M_p and the library's own C (downloaded), so the full-size check covers the device
+    products, the mass matrix and CG2, while the rows cover C."""
+    from entrywise import assert_iterate
+    n = 1025
+    mp = pb.Star.random(pb.streams(1)[0])
+    mesh = pb.lattice_mesh(mp, pb.mesh_points_for_grid(n), np.random.default_rng(1))
+    T = lib.Transfer(mesh.xy_c, mesh.xy_p, mesh.tris, mesh.dof, n, n, nq=4)
+    rpt, ci, v = T.copy_C()
+    rng = np.random.default_rng(22)
+    free = np.flatnonzero(mesh.dof)
+    for vtx in rng.choice(free, size=12, replace=False):
+        sub = _incident(mesh.tris, vtx)
+        verts = np.unique(sub)
+        local = np.searchsorted(verts, sub)
+        Co = transfer.coupled_mass(mesh.xy_c[verts], mesh.xy_p[verts], local, mesh.dof[verts], n, n,
+                                   nq=4).tocsr()
+        row = Co.getrow(int(np.searchsorted(verts, vtx)))
+        row.sort_indices()
+        cols, vals = ci[rpt[vtx]:rpt[vtx + 1]], v[rpt[vtx]:rpt[vtx + 1]]
+        assert np.array_equal(cols, row.indices), vtx
+        tol = 4 * np.finfo(float).eps / (2.0 / (n - 1)) ** 2
+        assert np.max(np.abs(vals - row.data)) <= tol * np.max(np.abs(row.data)), vtx
+    C = spx.csr_matrix((v, ci, rpt), shape=(mesh.nv, n * n))
+    M = transfer.p1_mass(mesh.xy_p, mesh.tris, mesh.dof)
+    uc = np.zeros((n, n))
+    uc[1:-1, 1:-1] = rng.normal(size=(n - 2, n - 2))
+    rp = rng.normal(size=mesh.nv)
+    up = T.from_grid(dev(uc))
+    rc = T.to_grid(dev(rp))
+    torch.cuda.synchronize()
+    for name, got, ref in (("from_grid", up.cpu().numpy(), transfer.from_grid(M, C, uc)),
+                           ("to_grid", rc.cpu().numpy(), transfer.to_grid(M, C, rp * mesh.dof, n, n))):
+        used = assert_iterate(f"{name} at {n}^2 vs oracle CG2", got, ref)
+        print(f"[fullsize-mesh] {name} vs oracle: worst excess {used:.1f} eps max|ref|")
+    T.close()
