@@ -236,8 +236,9 @@ dmg_status dmg_residual_norm_noalloc(const double* S, const double* u, const dou
  * nullable) return the count of cycles or refinement steps and the final relative residual;
  * history (host, nullable, >= max_iters doubles) receives the relative residual after each
  * step.  Returns DMG_ERR_NO_CONVERGENCE (u holds the last iterate) or DMG_ERR_NONFINITE.  The
- * convergence test runs on the device; the host synchronises `stream` once per chunk of at
- * most 4 steps (a chunk is cut short once the observed reduction per step predicts fewer).
+ * convergence test runs on the device; the host synchronises `stream` after the start and the
+ * first 4 steps, then after the steps the observed reduction per step predicts are left (at
+ * most 16, enqueued as graphs of at most 4 steps).
  * The start tests u on the device: when every entry (boundary included) is zero, the initial
  * residual is b and is formed without a pass over the stencil, with the same bits. */
 dmg_status dmg_solve(dmg_hier* h, double* u, const double* b, double rtol, int32_t max_iters,

@@ -1367,26 +1367,36 @@ dmg_status dmg_solve(dmg_hier* h, double* u, const double* b, double rtol, int32
   const int slot = ir ? 4 : 2;
   int* hs = reinterpret_cast<int*>(h->host + 8);  // device flags [0..8): pivot, -, -, -, stop, steps
   double* hsc = h->host;  // scalars [0..7]
-  // Chunks of kChunk steps, except that once two synchronisations give the rate per step, a
-  // chunk is cut to the steps the rate predicts are left (a step beyond convergence still
-  // costs its launches, and the device stopping test makes any chunk length exact).
-  int len = kChunk, prev_k = -1;
+  // The start and the first kChunk steps run as one graph, then the host synchronises.  From
+  // then on the rate per step (from the initial residual norm, then from the previous
+  // synchronisation) predicts the steps left: that many are enqueued as back-to-back chunk
+  // graphs (up to kAhead steps) before the next synchronisation.  A step beyond convergence
+  // still costs its launches, and the device stopping test makes any count exact.
+  constexpr int kAhead = 4 * kChunk;
+  int todo = kChunk, prev_k = -1;
   double prev_rn = 0.0;
-  // the start and the first chunk run as one graph
   for (bool first = true;; first = false) {
-    DMG_CHECK(run_step(h, ir ? 1 : 0, len, u, b, stream, first, rtol, max_iters));
+    for (int done = 0; done < todo;) {
+      const int len = first ? kChunk : std::min(kChunk, todo - done);
+      DMG_CHECK(run_step(h, ir ? 1 : 0, len, u, b, stream, first && done == 0, rtol, max_iters));
+      done += len;
+    }
     DMG_HIP(hipMemcpyAsync(hs, h->flag, 8 * sizeof(int), hipMemcpyDeviceToHost, stream));
     DMG_HIP(hipMemcpyAsync(hsc, h->scalars, 8 * sizeof(double), hipMemcpyDeviceToHost, stream));
     DMG_HIP(hipStreamSynchronize(stream));
     if (hs[4] || hs[0]) break;
     const int k_now = hs[5];
     const double rn = hsc[slot + 1], target = std::sqrt(std::max(hsc[6], 0.0));
-    len = kChunk;
-    if (prev_k >= 0 && k_now > prev_k && prev_rn > 0.0 && rn > 0.0 && target > 0.0) {
+    if (prev_k < 0) {  // first synchronisation: measure from the start's residual
+      prev_k = 0;
+      prev_rn = hsc[7];
+    }
+    todo = kChunk;
+    if (k_now > prev_k && prev_rn > 0.0 && rn > 0.0 && target > 0.0) {
       const double rate = std::pow(rn / prev_rn, 1.0 / double(k_now - prev_k));
       if (rate > 0.0 && rate < 0.95) {
         const double left = std::ceil(std::log(target / rn) / std::log(rate) - 1e-9);
-        if (left >= 1.0 && left < double(kChunk)) len = int(left);
+        if (left >= 1.0) todo = int(std::min(left, double(kAhead)));
       }
     }
     prev_k = k_now;

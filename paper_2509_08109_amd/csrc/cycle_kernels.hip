@@ -254,6 +254,7 @@ __global__ __launch_bounds__(256) void k_solve_start(const double* __restrict__ 
     sc_r[0] = tr;
     sc_r[1] = rn;
     sc_b[6] = target * target;
+    sc_b[7] = rn;  // the initial residual norm, kept for the host's step-count prediction
     st[0] = (bn == 0.0 || !(rn > target) || max_iters <= 0 || !isfinite(tb) || !isfinite(tr)) ? 1 : 0;
     st[1] = 0;
     st[2] = max_iters;

@@ -434,7 +434,8 @@ struct NormArgs {
 };
 dmg_status launch_check_multi(const CheckArgs* list, int count, hipStream_t s);
 // Start of a solve on the device: sums the b-norm and residual-norm partials (fixed order) into
-// sc_b[0..1] = ||b||^2, ||b|| and sc_r[0..1] = ||r||^2, ||r||, sets sc_b[6] = (rtol ||b||)^2 and
+// sc_b[0..1] = ||b||^2, ||b|| and sc_r[0..1] = ||r||^2, ||r||, sets sc_b[6] = (rtol ||b||)^2,
+// sc_b[7] = ||r|| (kept: later steps overwrite sc_r) and
 // the state st = {stop, steps = 0, max}: stop when ||r|| <= rtol ||b||, max_iters <= 0, b = 0 or
 // a norm is not finite.  When b = 0 it also zeroes u (n values).
 dmg_status launch_solve_start(const double* pb, int nb, const double* pr, int nr, double* sc_b,
