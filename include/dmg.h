@@ -379,8 +379,9 @@ void dmg_batch_destroy(dmg_batch* bt);
  * solve: cycles from u_p until ||f - A u|| <= rtol ||f - A u_0|| or max_iters; a zero initial
  * residual returns at once with iters = 0 and relres = 0.  history (host, nullable,
  * >= max_iters entries) receives ||f - A u_k|| / ||f - A u_0||.  Chunks of at most four cycles
- * (cut short once the observed reduction per cycle predicts fewer) run in one captured hipGraph
- * each (when `stream` is not the legacy default stream).  Returns
+ * run in one captured hipGraph each (when `stream` is not the legacy default stream); the host
+ * synchronises after the first chunk, then after the cycles the observed reduction per cycle
+ * predicts are left (at most 16, as back-to-back chunks).  Returns
  * DMG_ERR_NO_CONVERGENCE or DMG_ERR_NONFINITE with u_p holding the last iterate. */
 dmg_status dmg_twolevel_create(int32_t nv, int32_t nt, const double* xy_c, const double* xy_p,
                                const int32_t* tris, const uint8_t* dof, const double* K_t,

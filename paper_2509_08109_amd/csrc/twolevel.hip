@@ -713,24 +713,35 @@ dmg_status dmg_twolevel_solve(dmg_twolevel* tl, double* u_p, const double* f_p, 
   DMG_CHECK(sweep_colour(tl, 0, tl->flag, stream));  // the first step's leading colour pass
   int* hs = reinterpret_cast<int*>(tl->host + 8);
   double* hsc = tl->host;
-  // chunks of kChunk cycles; once two synchronisations give the rate per cycle, a chunk is cut
-  // to the cycles that rate predicts are left (the device test stops at the exact cycle anyway)
-  int len = kChunk, prev_k = -1;
+  // The first kChunk cycles, then a synchronisation.  From then on the rate per cycle (from r0
+  // over the first chunk, then between synchronisations) predicts the cycles left: that many
+  // are enqueued as back-to-back chunk graphs (up to kAhead cycles) before the next
+  // synchronisation.  The device test stops at the exact cycle anyway.
+  constexpr int kAhead = 4 * kChunk;
+  int todo = kChunk, prev_k = -1;
   double prev_rn = 0.0;
   for (;;) {
-    DMG_CHECK(run_chunk(tl, len, stream));
+    for (int done = 0; done < todo;) {
+      const int len = std::min(kChunk, todo - done);
+      DMG_CHECK(run_chunk(tl, len, stream));
+      done += len;
+    }
     DMG_HIP(hipMemcpyAsync(hs, tl->flag, 2 * sizeof(int), hipMemcpyDeviceToHost, stream));
     DMG_HIP(hipMemcpyAsync(hsc, tl->scal, 8 * sizeof(double), hipMemcpyDeviceToHost, stream));
     DMG_HIP(hipStreamSynchronize(stream));
     if (hs[0]) break;
     const int k_now = hs[1];
     const double rn = hsc[3], target = std::sqrt(std::max(hsc[6], 0.0));
-    len = kChunk;
-    if (prev_k >= 0 && k_now > prev_k && prev_rn > 0.0 && rn > 0.0 && target > 0.0) {
+    if (prev_k < 0) {  // first synchronisation: measure from the initial residual r0
+      prev_k = 0;
+      prev_rn = hsc[1];
+    }
+    todo = kChunk;
+    if (k_now > prev_k && prev_rn > 0.0 && rn > 0.0 && target > 0.0) {
       const double rate = std::pow(rn / prev_rn, 1.0 / double(k_now - prev_k));
       if (rate > 0.0 && rate < 0.95) {
         const double left = std::ceil(std::log(target / rn) / std::log(rate) - 1e-9);
-        if (left >= 1.0 && left < double(kChunk)) len = int(left);
+        if (left >= 1.0) todo = int(std::min(left, double(kAhead)));
       }
     }
     prev_k = k_now;
